@@ -1,0 +1,244 @@
+"""FP64 CPU oracle for the 3DGS render path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It never imports the GPU library and
+the GPU library never imports it; the two share only the seeded input
+generator, which holds none of the method's arithmetic.
+
+``gs_oracle.cpp`` (compiled to ``liboracle.so`` with g++, no fast-math)
+implements the forward definition: the per-Gaussian projection of Eq. 1,
+the SH colour, and the per-pixel compositing of Eqs. 2-3 by brute force in
+ascending (depth, index) order; plus the (tile, depth) key list and a
+library stable sort.  ``grad.py`` gives reference gradients by float64
+automatic differentiation of the same definition (Section 3.2: the
+formulation is differentiable).
+
+Pins (tests/test_oracle_*.py): closed forms for one isotropic Gaussian on
+and off the optical axis, two ordered Gaussians and n coincident Gaussians;
+covariance eigen-invariants; the SH basis against SciPy's complex
+harmonics and by quadrature; the sort against NumPy's stable argsort and a
+brute-force sort; front-to-back against back-to-front compositing; and the
+gradients against central finite differences of the C forward.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+# Reading of the constants the paper leaves open (see the header of
+# gs_oracle.cpp): 16x16 tiles, eps2d = 0.3 px^2, tau = 1/255,
+# alpha_max = 0.99, t_eps = 1e-4, J clamp 1.3x the half-FoV tangent,
+# black background.
+DEFAULT_SETTINGS = dict(tile_w=16, tile_h=16, eps2d=0.3, tau=1.0 / 255.0,
+                        alpha_max=0.99, t_eps=1e-4, clip=1.3,
+                        bg=(0.0, 0.0, 0.0))
+
+# record layout (must match the enums in gs_oracle.cpp)
+D_MX, D_MY, D_SA, D_SB, D_SC, D_CA, D_CB, D_CC, D_DEPTH = range(9)
+D_R, D_G, D_B, D_RR, D_RG, D_RB, D_OPAC, D_C3 = 9, 10, 11, 12, 13, 14, 15, 16
+D_QMAX, D_TZ = 22, 23
+I_CULL, I_PX0, I_PX1, I_PY0, I_PY1, I_TX0, I_TY0, I_TX1, I_TY1, I_TILES, I_AMBIG = range(11)
+C_VISIBLE, C_NEAR, C_INVALID, C_DET, C_OPACITY, C_OFFIMAGE = range(6)
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with g++ (OpenMP, -O2, IEEE semantics)."""
+    global _lib
+    with _lock:
+        stale = (not os.path.exists(_LIB)
+                 or os.path.getmtime(_LIB) < os.path.getmtime(_SRC))
+        if force or stale:
+            tmp = _LIB + ".tmp"
+            cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fno-fast-math",
+                   "-ffp-contract=off", "-shared", "-fPIC", _SRC, "-o", tmp]
+            subprocess.run(cmd, check=True)
+            os.replace(tmp, _LIB)
+            _lib = None
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.orc_preprocess.argtypes = [I64, P, P, P, P, P, ctypes.c_int, P, P, P, P, P]
+        lib.orc_preprocess_f64.argtypes = [I64, P, P, P, P, P, ctypes.c_int, P, P, P, P, P]
+        lib.orc_render_pixels.argtypes = [I64, P, P, P, P, I64, P, P, P, P, P, P]
+        lib.orc_keys.argtypes = [I64, P, P, ctypes.c_int, P, P]
+        lib.orc_count_instances.argtypes = [I64, P]
+        lib.orc_count_instances.restype = I64
+        lib.orc_pair_max_weight.argtypes = [I64, P, P, P, P, P, P]
+        lib.orc_stable_sort_pairs.argtypes = [I64, P, P]
+        lib.orc_sh_basis.argtypes = [ctypes.c_int, I64, P, P]
+        lib.orc_rec_layout.argtypes = [P]
+        lib.orc_num_threads.restype = ctypes.c_int
+        lay = np.zeros(2, np.int32)
+        lib.orc_rec_layout(lay.ctypes.data)
+        assert tuple(lay) == (24, 11), lay
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data if a is not None else None
+
+
+def cam_array(cam) -> np.ndarray:
+    v = np.asarray(cam.viewmat, np.float64).reshape(16)
+    return np.concatenate([v, [cam.fx, cam.fy, cam.cx, cam.cy, cam.width,
+                               cam.height, cam.znear]]).astype(np.float64)
+
+
+def set_array(settings=None) -> np.ndarray:
+    s = dict(DEFAULT_SETTINGS)
+    if settings:
+        s.update(settings)
+    return np.array([s["tile_w"], s["tile_h"], s["eps2d"], s["tau"],
+                     s["alpha_max"], s["t_eps"], s["clip"], *s["bg"]], np.float64)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+class Records:
+    """Per-Gaussian float64 records of one or more concatenated assets."""
+
+    def __init__(self, d: np.ndarray, i: np.ndarray):
+        self.d = np.ascontiguousarray(d, np.float64)
+        self.i = np.ascontiguousarray(i, np.int32)
+
+    @property
+    def n(self):
+        return self.d.shape[0]
+
+    @property
+    def visible(self):
+        return self.i[:, I_CULL] == C_VISIBLE
+
+    def concat(self, other: "Records") -> "Records":
+        return Records(np.concatenate([self.d, other.d]), np.concatenate([self.i, other.i]))
+
+
+def preprocess(scene, cam, settings=None, f64_inputs=False) -> Records:
+    """Eq. 1 + colour + culls for every Gaussian of ``scene`` (float64).
+
+    Inputs are read as float32 (the library's type) unless ``f64_inputs``,
+    which keeps them in float64 (for finite differences)."""
+    lib = _load()
+    n = scene.n
+    d = np.zeros((n, 24), np.float64)
+    iv = np.zeros((n, 11), np.int32)
+    dt = np.float64 if f64_inputs else np.float32
+    f = lambda a: np.ascontiguousarray(a, dt)
+    arrs = [f(scene.means), f(scene.log_scales), f(scene.quats),
+            f(scene.opacity_logits), f(scene.sh)]
+    model = None if scene.model is None else np.ascontiguousarray(scene.model, np.float64)
+    ca, sa = cam_array(cam), set_array(settings)
+    fn = lib.orc_preprocess_f64 if f64_inputs else lib.orc_preprocess
+    rc = fn(n, *[_p(a) for a in arrs], int(scene.sh_degree), _p(model),
+            _p(ca), _p(sa), _p(d), _p(iv))
+    if rc != 0:
+        raise ValueError("orc_preprocess rejected its arguments")
+    return Records(d, iv)
+
+
+def preprocess_many(scenes, cam, settings=None) -> Records:
+    """Records of several assets, concatenated in order (one global list)."""
+    recs = None
+    for s in scenes:
+        r = preprocess(s, cam, settings)
+        recs = r if recs is None else recs.concat(r)
+    return recs
+
+
+def render_pixels(recs: Records, cam, pix, settings=None):
+    """Eq. 3 by brute force at the given pixels (int array (P,2) of x, y).
+
+    Returns dict(rgba (P,4), T (P,), n_blend (P,), margin (P,), flags (P,))."""
+    lib = _load()
+    pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
+    P = pix.shape[0]
+    out = dict(rgba=np.zeros((P, 4)), T=np.zeros(P), n_blend=np.zeros(P, np.int32),
+               margin=np.zeros(P), flags=np.zeros(P, np.int32))
+    ca, sa = cam_array(cam), set_array(settings)
+    lib.orc_render_pixels(recs.n, _p(recs.d), _p(recs.i), _p(ca), _p(sa), P, _p(pix),
+                          _p(out["rgba"]), _p(out["T"]), _p(out["n_blend"]),
+                          _p(out["margin"]), _p(out["flags"]))
+    return out
+
+
+def all_pixels(cam) -> np.ndarray:
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    return np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
+
+
+def render_image(recs: Records, cam, settings=None):
+    """Full image (H,W,4) plus T, n_blend, margin, flags as (H,W) maps."""
+    o = render_pixels(recs, cam, all_pixels(cam), settings)
+    H, W = cam.height, cam.width
+    return dict(rgba=o["rgba"].reshape(H, W, 4), T=o["T"].reshape(H, W),
+                n_blend=o["n_blend"].reshape(H, W), margin=o["margin"].reshape(H, W),
+                flags=o["flags"].reshape(H, W))
+
+
+def tiles_xy(cam, settings=None):
+    s = dict(DEFAULT_SETTINGS)
+    if settings:
+        s.update(settings)
+    return ((cam.width + s["tile_w"] - 1) // s["tile_w"],
+            (cam.height + s["tile_h"] - 1) // s["tile_h"])
+
+
+def keys(recs: Records, cam, settings=None):
+    """(tile, depth) keys and Gaussian-index values, Gaussian-major order."""
+    lib = _load()
+    total = int(lib.orc_count_instances(recs.n, _p(recs.i)))
+    k = np.zeros(total, np.uint64)
+    v = np.zeros(total, np.uint32)
+    tx, _ = tiles_xy(cam, settings)
+    lib.orc_keys(recs.n, _p(recs.d), _p(recs.i), tx, _p(k), _p(v))
+    return k, v
+
+
+def stable_sort_pairs(keys_in, values_in):
+    """Library stable sort (std::stable_sort) of (key, value) by key."""
+    lib = _load()
+    k = np.ascontiguousarray(keys_in, np.uint64).copy()
+    v = np.ascontiguousarray(values_in, np.uint32).copy()
+    lib.orc_stable_sort_pairs(k.shape[0], _p(k), _p(v))
+    return k, v
+
+
+def pair_max_weight(recs: Records, cam, g, tile, settings=None):
+    """max over the pixel centres of ``tile`` of o*exp(-Q/2) for Gaussian g."""
+    lib = _load()
+    g = np.ascontiguousarray(g, np.uint32)
+    tile = np.ascontiguousarray(tile, np.uint32)
+    out = np.zeros(g.shape[0])
+    ca, sa = cam_array(cam), set_array(settings)
+    lib.orc_pair_max_weight(g.shape[0], _p(g), _p(tile), _p(recs.d), _p(ca), _p(sa), _p(out))
+    return out
+
+
+def sh_basis(degree, dirs):
+    """Real SH basis (n,16) at unit directions (n,3)."""
+    lib = _load()
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    out = np.zeros((dirs.shape[0], 16))
+    if lib.orc_sh_basis(int(degree), dirs.shape[0], _p(dirs), _p(out)) != 0:
+        raise ValueError("degree must be 0..3")
+    return out
