@@ -1,0 +1,221 @@
+"""Benchmark of the per-frame 3DGS render path on one MI355X.
+
+Default workload: the 1,000,000-Gaussian clustered scene (SH degree 3) at
+1920x1080, forward (preprocess -> keys + radix sort -> tile compositing),
+inputs resident in HBM.  A step is one whole frame.  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload medium|large|diff|tiny]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "frames/sec @1080p, 1M–6M Gaussians, fwd and fwd+bwd; sort Gkeys/s; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+# plain (non-packed) FP32 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x
+# 4 (a wave64 op every cycle per SIMD pair) ... expressed as lane-ops/s:
+# 256 CUs * 64 lanes/clk * 2.4 GHz = 39.3 T lane-ops/s; an FMA counts as 2
+# flops, so 78.6 TFLOP/s for unpacked FMA.
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+
+WORKLOADS = {
+    "tiny": "tiny: 4,096 Gaussians, SH degree 0, 256x256, forward",
+    "medium": "medium: 1,000,000 Gaussians (64 clusters in [-5,5]^3), SH degree 3, 1920x1080, forward",
+    "large": "large: 6,000,000 Gaussians (64 clusters in [-20,20]^3), SH degree 3, 1920x1080 eye inside, forward",
+    "diff": "diff: 500,000 Gaussians, SH degree 3, 800x800, forward+backward (L1)",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--radix-bits", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=2048)
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def make_workload(name):
+    from paper_2512_08478_amd import scenes as S
+    if name == "tiny":
+        return S.tiny_scene()
+    if name == "medium":
+        return S.medium_scene()
+    if name == "large":
+        return S.large_scene()
+    if name == "diff":
+        return S.diff_scene()
+    raise ValueError(name)
+
+
+def algorithmic_bytes(n, n_vis, inst, K, W, H, passes, tiles):
+    """Bytes each stage must move (reads + writes), per launch."""
+    return {
+        # means 12 + log-scales 12 + quats 16 + logit 4 read; 48 B record + 4 B count written;
+        # SH 12K bytes read for visible Gaussians only
+        "preprocess": n * (44 + 52) + n_vis * 12 * K,
+        # counts read + offsets written, in place
+        "scan": n * 8,
+        # offsets 4 + record tail 16 read per Gaussian; key 8 + value 4 written per instance
+        "keygen": n * 20 + inst * 12,
+        # per pass: key + value read and written
+        "radix_pass": inst * 24,
+        # sorted keys read, two u32 per tile written
+        "tile_ranges": inst * 8 + tiles * 8,
+        # value + 48 B record gathered per instance, RGBA + T + last written per pixel
+        "raster": inst * (4 + 48) + tiles * 8 + W * H * 24,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2512_08478_amd import _lib as L
+    from paper_2512_08478_amd.render import GaussianParams, Renderer
+
+    tw, th = map(int, args.tile.split("x"))
+    sc, cam = make_workload(args.workload)
+    R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=args.radix_bits))
+    p = GaussianParams.from_scene(sc)
+    backward = args.workload == "diff"
+    H, W = cam.height, cam.width
+    target = None
+    if backward:
+        from paper_2512_08478_amd import scenes as S
+        target = torch.from_numpy(S.random_target(4, H, W)).cuda()
+
+    # first frame: read the instance count once to size the sort buffers
+    fr = R.forward(p, cam)
+    torch.cuda.synchronize()
+    inst = fr.capacity
+    capacity = inst
+
+    def step():
+        f = R.forward(p, cam, capacity=capacity)
+        if backward:
+            # L1 loss gradient w.r.t. RGB (the caller's loss, not part of the method)
+            G = torch.zeros((H, W, 4), device="cuda")
+            G[..., :3] = torch.sign(f.image[..., :3] - target) / (3.0 * H * W)
+            R.backward(p, cam, f, G)
+        return f
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    flag = int(f.flag[0].item()) & 0xFFFFFFFF
+    if flag & 1:
+        raise RuntimeError("instance capacity exceeded during the timed steps")
+
+    # per-kernel durations, measured with HIP events recorded by libgs on the
+    # stream its kernels run on
+    L.trace_enable(True)
+    reps = max(5, min(20, args.steps))
+    acc = {}
+    cnt = {}
+    for _ in range(reps):
+        step()
+        for lab, ms in L.trace_read():
+            acc[lab] = acc.get(lab, 0.0) + ms
+            cnt[lab] = cnt.get(lab, 0) + 1
+    L.trace_enable(False)
+    kern_ms = {k: acc[k] / reps for k in acc}          # per frame (all passes)
+    kern_avg = {k: acc[k] / cnt[k] for k in acc}       # per launch
+
+    rec = f.splats[: sc.n * 48].cpu().numpy().view(np.uint16).reshape(sc.n, 24)
+    n_vis = int(np.count_nonzero(rec[:, 22] >= rec[:, 20]))
+    K = (sc.sh_degree + 1) ** 2
+    tiles = R.tiles(cam)
+    import ctypes
+    key_bits = L.load().gs_sort_key_bits(ctypes.byref(L.make_camera(cam)), ctypes.byref(R.settings))
+    passes = -(-key_bits // args.radix_bits)
+    ab = algorithmic_bytes(sc.n, n_vis, inst, K, W, H, passes, tiles)
+    stages = {}
+    for k, v in kern_avg.items():
+        e = {"ms_per_launch": round(v, 5), "ms_per_frame": round(kern_ms[k], 5)}
+        if k in ab:
+            gbs = ab[k] / (v * 1e-3) / 1e9
+            e.update(algo_bytes=int(ab[k]), gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+        stages[k] = e
+    sort_ms = sum(kern_ms.get(k, 0.0) for k in ("sort_init", "keygen", "radix_pass", "tile_ranges"))
+    # dominant HBM-bound kernel by time per frame
+    hbm_kernels = [k for k in ("preprocess", "radix_pass", "keygen", "scan", "tile_ranges") if k in kern_ms]
+    dom = max(hbm_kernels, key=lambda k: kern_ms[k])
+    dom_gbs = ab[dom] / (kern_avg[dom] * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "algo_bytes_per_launch": int(ab[dom])}
+
+    out = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms_per_step, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "n_gaussians": sc.n, "width": W,
+                   "height": H, "tile": args.tile, "radix_bits": args.radix_bits,
+                   "visible": n_vis, "instances": inst, "key_bits": key_bits, "passes": passes},
+        "sort_gkeys_per_s": round(inst / (sort_ms * 1e-3) / 1e9, 3) if sort_ms > 0 else None,
+        "sort_ms": round(sort_ms, 4),
+        "stages": stages,
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(sc, cam, n_pix):
+    """The FP64 oracle, as it stands, on a bounded sample of the same frame:
+    preprocess of every Gaussian + brute-force compositing of n_pix random
+    pixels, scaled to a whole frame."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    rec = oracle.preprocess(sc, cam)
+    t1 = time.perf_counter()
+    rng = np.random.default_rng(123)
+    pix = np.stack([rng.integers(0, cam.width, n_pix), rng.integers(0, cam.height, n_pix)], 1)
+    oracle.render_pixels(rec, cam, pix)
+    t2 = time.perf_counter()
+    frame_s = (t1 - t0) + (t2 - t1) * (cam.width * cam.height) / n_pix
+    return {"value": round(1.0 / frame_s, 8), "unit": "frames/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle: preprocess of all {sc.n} Gaussians ({t1 - t0:.2f} s) + "
+                      f"brute-force Eq. 3 at {n_pix} random pixels ({t2 - t1:.2f} s), "
+                      f"scaled to {cam.width}x{cam.height} pixels"}
+
+
+if __name__ == "__main__":
+    main()

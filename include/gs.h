@@ -1,0 +1,267 @@
+/*
+ * gs.h -- C ABI of libgs, a gfx950 (MI355X) implementation of the per-frame
+ * 3D Gaussian Splatting render path.
+ *
+ * The method follows "Visionary" (arXiv 2512.08478): the 3DGS definition of
+ * Section 3.2 (Eq. 1 projection, Eq. 2 pixel weight, Eq. 3 front-to-back
+ * compositing over depth-sorted Gaussians) and the per-frame GPU pipeline of
+ * Algorithm 1 / Section 3.4 (per-model preprocess with frustum and opacity
+ * culls, a GPU radix sort, then the splat draw).  This library sorts
+ * (tile, depth) keys and composites front to back per pixel in a compute
+ * kernel instead of drawing depth-sorted quads; the sum is the same Eq. 3.
+ *
+ * Conventions for every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller, row-major
+ *     and contiguous, float32 unless noted, with base addresses aligned to
+ *     16 bytes.  The library never allocates device memory and never
+ *     synchronises the stream, except where a function says so.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  All
+ *     work is enqueued on it, in order.
+ *   - Structs (gs_camera, gs_settings, model transforms) are HOST pointers,
+ *     read during the call.
+ *   - Every function returns a gs_status.  Argument checks run before any
+ *     HIP call, so a rejected call has no effect on the device.  On
+ *     GS_ERR_HIP the HIP error code is kept per thread (gs_last_hip_error).
+ *   - n == 0 (no Gaussians) is valid and renders the background.
+ *   - Calls that share a workspace must not overlap in time.
+ */
+#ifndef GS_H_
+#define GS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gs_status {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARGUMENT = 1, /* null pointer, negative size, bad struct field */
+  GS_ERR_UNSUPPORTED = 2,      /* SH degree > 3, tile shape, digit width */
+  GS_ERR_CAPACITY = 3,         /* more (Gaussian, tile) instances than capacity */
+  GS_ERR_HIP = 4,              /* a HIP runtime call failed; see gs_last_hip_error */
+  GS_ERR_MISALIGNED = 5,       /* a device pointer is not 16-byte aligned */
+  GS_ERR_WORKSPACE = 6         /* workspace smaller than gs_workspace_size() */
+} gs_status;
+
+/*
+ * Pinhole camera (Eq. 1's projection operator; Algorithm 1's (V, P)).
+ * viewmat: row-major 4x4 world->camera matrix, OpenCV axes (+x right,
+ * +y down, +z forward); its upper 3x3 must be a rotation.  A camera-space
+ * point t maps to pixel coordinates (fx*t.x/t.z + cx, fy*t.y/t.z + cy);
+ * pixel (i, j) samples the point (i + 1/2, j + 1/2).  Gaussians with
+ * camera-space depth <= znear are culled.
+ */
+typedef struct gs_camera {
+  float viewmat[16];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float znear;
+  float reserved;
+} gs_camera;
+
+/*
+ * Constants the paper leaves open, with the defaults gs_default_settings()
+ * fills in:
+ *   tile_w x tile_h   8x8, 16x8, 16x16 (default), 32x8 or 32x16 pixels
+ *   eps2d      0.3   px^2 added to the diagonal of the 2-D covariance S
+ *   alpha_min  1/255 opacity cull (Algorithm 1) and per-pixel skip
+ *   alpha_max  0.99  clamp of the pixel weight of Eq. 2
+ *   t_eps      1e-4  compositing blends a Gaussian, then stops once the
+ *                    transmittance is below t_eps
+ *   clip       1.3   x/z, y/z inside the Jacobian J are clamped to clip
+ *                    times the half-FoV tangent
+ *   bg         (0,0,0) background colour; output alpha is 1 - T_final
+ *   radix_bits 8     digit width of the radix sort (6, 7 or 8)
+ */
+typedef struct gs_settings {
+  int32_t tile_w, tile_h;
+  float eps2d;
+  float alpha_min;
+  float alpha_max;
+  float t_eps;
+  float clip;
+  float bg[3];
+  int32_t radix_bits;
+  int32_t reserved;
+} gs_settings;
+
+/*
+ * Projected splat: the per-Gaussian record written by gs_preprocess
+ * (Algorithm 1's `points2d` entry), 48 bytes.  The 2-D quadratic form of
+ * Eq. 2 is stored in a whitened form:
+ *     Q(dx, dy) = (dx, dy) S^-1 (dx, dy)^T = qa * (dx - qb*dy)^2 + qc * dy^2
+ * with S = [[a, b], [b, c]], qa = c/det S, qb = b/c, qc = 1/c.  Both terms
+ * are non-negative, so Q is evaluated without cancellation.
+ * Tile rect [tx0..tx1] x [ty0..ty1] is inclusive; a culled Gaussian has
+ * tx1 < tx0 and touches no tile.
+ */
+typedef struct gs_splat {
+  float mean_x, mean_y;
+  float qa, qb;
+  float qc, opacity;
+  float r, g, b;
+  float depth;
+  uint16_t tx0, ty0, tx1, ty1;
+} gs_splat;
+
+/* Workspace stages for gs_workspace_size. */
+typedef enum gs_stage {
+  GS_STAGE_PREPROCESS = 0,
+  GS_STAGE_SORT = 1,
+  GS_STAGE_SORT_PAIRS = 2,
+  GS_STAGE_BACKWARD = 3
+} gs_stage;
+
+const char* gs_version(void);
+const char* gs_status_string(int32_t status);
+/* hipError_t of the last GS_ERR_HIP on this thread (0 if none). */
+int32_t gs_last_hip_error(void);
+/* Fill *s with the defaults listed above. */
+void gs_default_settings(gs_settings* s);
+
+/*
+ * Opt-in kernel tracer (for profiling; not thread-safe).  gs_trace_enable(1)
+ * creates a pool of HIP events on first use and starts recording one event
+ * before each kernel the library launches and one after the last; 0 stops.
+ * gs_trace_read waits for the last recorded event, then writes up to
+ * max_entries (label, milliseconds) pairs -- labels are 32-byte
+ * NUL-terminated strings in `labels` -- sets *count and clears the record.
+ * Each interval runs from a kernel's launch point in the stream to the
+ * next, so it covers that kernel and any gap before the next one.
+ */
+int32_t gs_trace_enable(int32_t on);
+int32_t gs_trace_read(int32_t max_entries, char* labels, float* ms, int32_t* count);
+
+/*
+ * Bytes of workspace a stage needs.  `n` is the number of Gaussians,
+ * `capacity` the instance capacity (for the sort stages; for
+ * GS_STAGE_SORT_PAIRS the number of pairs).  Returns 0 on invalid input.
+ */
+size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity,
+                         const gs_camera* cam, const gs_settings* set);
+
+/*
+ * Significant key bits of gs_sort for this camera and settings: 32 depth
+ * bits plus ceil(log2(tiles)) tile bits.  The sort makes
+ * ceil(key_bits / radix_bits) passes.
+ */
+int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set);
+
+/*
+ * gs_preprocess -- per-Gaussian projection (Section 3.2, Eq. 1) and colour,
+ * with the culls of Algorithm 1's Preprocess procedure.
+ *
+ * Inputs (raw parameters, device, float32):
+ *   means[n*3], log_scales[n*3] (scale = exp), quats[n*4] as (w, x, y, z)
+ *   (normalised here; a zero quaternion is culled), opacity_logits[n]
+ *   (opacity = sigmoid), sh[n*K*3] with K = (sh_degree+1)^2, coefficient-
+ *   major with RGB innermost; sh_degree in 0..3.
+ *   model: host pointer to a 3x4 row-major similarity transform [s*R | t]
+ *   placing this asset in the world (Algorithm 1's per-model M_k), or NULL
+ *   for the identity.  Covariances become (sR) Sigma (sR)^T and the SH
+ *   view direction is taken in the asset's own frame (R^T d).
+ * Outputs (device):
+ *   splats[n]      one gs_splat per Gaussian.
+ *   offsets[n]     u32 exclusive prefix sum of the tiles each Gaussian
+ *                  touches (instance offsets in Gaussian-major order).
+ *   total[1]       u32 total number of (Gaussian, tile) instances.
+ * Culled (record with an empty rect, zero tiles): camera depth <= znear,
+ * opacity < alpha_min, non-finite values, zero quaternion, or a footprint
+ * whose opacity-aware bounding box (where o*exp(-Q/2) >= alpha_min)
+ * contains no pixel centre.
+ * Workspace: gs_workspace_size(GS_STAGE_PREPROCESS, n, 0, ...).
+ */
+int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales,
+                      const float* quats, const float* opacity_logits,
+                      const float* sh, int32_t sh_degree, const float* model,
+                      const gs_camera* cam, const gs_settings* set,
+                      gs_splat* splats, uint32_t* offsets, uint32_t* total,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * gs_sort -- key generation and the per-frame GPU radix sort (Algorithm 1,
+ * Radix Sort; Section 3.4).  For each visible Gaussian in index order and
+ * each tile of its rect in row-major order, key = tile_id << 32 |
+ * bits(float32 depth), value = Gaussian index; the pairs are then sorted by
+ * a stable LSD radix sort, so equal keys stay in Gaussian-index order and
+ * the permutation is unique.  Depth is camera-space z, which orders like
+ * the paper's NDC z for z > 0.
+ *
+ * Reads splats[n], offsets[n] and total (device, from gs_preprocess).
+ * Writes keys[capacity] (u64, sorted), values[capacity] (u32, sorted) and
+ * tile_ranges[2*tiles] (u32 [start, end) of each tile in the sorted list,
+ * tiles = ceil(W/tile_w) * ceil(H/tile_h), row-major).  Only the first
+ * `total` entries of keys/values are meaningful.
+ *
+ * The instance count is read on the device; there is no host sync.  When
+ * total > capacity, nothing past `capacity` is written, `status_flag[0]`
+ * (device u32, may be NULL) gets bit 0 set and the ranges cover only the
+ * first `capacity` instances: the caller checks the flag (after a sync)
+ * and retries with a larger capacity.
+ * Workspace: gs_workspace_size(GS_STAGE_SORT, n, capacity, cam, set).
+ */
+int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* offsets,
+                const uint32_t* total, const gs_camera* cam,
+                const gs_settings* set, int64_t capacity, uint64_t* keys,
+                uint32_t* values, uint32_t* tile_ranges, uint32_t* status_flag,
+                void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * gs_sort_pairs -- the stable LSD radix sort on its own: sorts n
+ * (key u64, value u32) pairs by the low `key_bits` bits of the key
+ * (1..64; higher bits must be zero).  keys_in/values_in are not modified;
+ * the result goes to keys_out/values_out (distinct buffers).
+ * Workspace: gs_workspace_size(GS_STAGE_SORT_PAIRS, 0, n, NULL, set).
+ */
+int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in,
+                      const uint32_t* values_in, int32_t key_bits,
+                      uint64_t* keys_out, uint32_t* values_out,
+                      const gs_settings* set, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/*
+ * gs_rasterize -- Eqs. 2-3 per pixel.  For each tile, its splats are
+ * visited in sorted (depth, index) order; per pixel
+ *   alpha = min(alpha_max, opacity * exp(-Q/2)); skip if alpha < alpha_min;
+ *   C += T * alpha * rgb; T *= (1 - alpha); stop once T < t_eps.
+ * Writes image[H*W*4] (RGB = C + T*bg, A = 1 - T), T_final[H*W] and
+ * last[H*W] (u32: one past the position, within the tile's sorted range,
+ * of the last splat blended into the pixel; used by the backward pass).
+ */
+int32_t gs_rasterize(const gs_splat* splats, const uint32_t* values,
+                     const uint32_t* tile_ranges, const gs_camera* cam,
+                     const gs_settings* set, float* image, float* T_final,
+                     uint32_t* last, void* stream);
+
+/*
+ * gs_rasterize_backward -- gradients of a loss L through Eqs. 1-3
+ * (Section 3.2: the formulation is differentiable) for the same inputs and
+ * forward outputs, given dL_dimage[H*W*4] (RGBA).
+ *
+ * The blend order is re-walked from the saved sort (values, tile_ranges)
+ * back to front, recovering each transmittance from T_final by division;
+ * no per-pixel lists are stored.  Writes d_means[n*3], d_log_scales[n*3],
+ * d_quats[n*4], d_opacity_logits[n], d_sh[n*K*3] (overwritten, or added
+ * to when `accumulate` is non-zero).  Gradients are zero where a clamp
+ * binds (alpha_max, the J clamp, colour at 0) and for culled Gaussians;
+ * depth (the sort key) is not differentiated.  Accumulation across pixels
+ * uses float atomics, so the last bits can vary from run to run.
+ * Workspace: gs_workspace_size(GS_STAGE_BACKWARD, n, 0, cam, set).
+ */
+int32_t gs_rasterize_backward(
+    int64_t n, const float* means, const float* log_scales, const float* quats,
+    const float* opacity_logits, const float* sh, int32_t sh_degree,
+    const float* model, const gs_camera* cam, const gs_settings* set,
+    const gs_splat* splats, const uint32_t* values,
+    const uint32_t* tile_ranges, const float* T_final, const uint32_t* last,
+    const float* dL_dimage, float* d_means, float* d_log_scales,
+    float* d_quats, float* d_opacity_logits, float* d_sh, int32_t accumulate,
+    void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H_ */

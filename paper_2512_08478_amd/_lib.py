@@ -1,0 +1,167 @@
+"""ctypes binding of libgs.so (argument marshalling only).
+
+Names and argument orders mirror include/gs.h.  Loading fails loudly when
+the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgs.so")
+
+GS_OK = 0
+GS_ERR_INVALID_ARGUMENT = 1
+GS_ERR_UNSUPPORTED = 2
+GS_ERR_CAPACITY = 3
+GS_ERR_HIP = 4
+GS_ERR_MISALIGNED = 5
+GS_ERR_WORKSPACE = 6
+
+GS_STAGE_PREPROCESS = 0
+GS_STAGE_SORT = 1
+GS_STAGE_SORT_PAIRS = 2
+GS_STAGE_BACKWARD = 3
+
+SPLAT_BYTES = 48
+
+EXPORTED = (
+    "gs_version", "gs_status_string", "gs_last_hip_error", "gs_default_settings",
+    "gs_workspace_size", "gs_sort_key_bits", "gs_preprocess", "gs_sort", "gs_sort_pairs",
+    "gs_rasterize", "gs_rasterize_backward", "gs_trace_enable", "gs_trace_read",
+)
+
+
+class GsLibraryMissing(RuntimeError):
+    pass
+
+
+class GsError(RuntimeError):
+    def __init__(self, status, what, hip_error=0):
+        self.status = status
+        self.hip_error = hip_error
+        msg = f"{what}: {status_string(status)} (status {status}"
+        if status == GS_ERR_HIP:
+            msg += f", hipError {hip_error}"
+        super().__init__(msg + ")")
+
+
+class GsCamera(ctypes.Structure):
+    _fields_ = [("viewmat", ctypes.c_float * 16), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("znear", ctypes.c_float), ("reserved", ctypes.c_float)]
+
+
+class GsSettings(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("eps2d", ctypes.c_float),
+                ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
+                ("t_eps", ctypes.c_float), ("clip", ctypes.c_float), ("bg", ctypes.c_float * 3),
+                ("radix_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libgs.so (built in-tree by paper_2512_08478_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GsLibraryMissing(
+            f"{LIB_PATH} is missing; build it with `python -m paper_2512_08478_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    CAM, SET = ctypes.POINTER(GsCamera), ctypes.POINTER(GsSettings)
+    lib.gs_version.restype = ctypes.c_char_p
+    lib.gs_version.argtypes = []
+    lib.gs_status_string.restype = ctypes.c_char_p
+    lib.gs_status_string.argtypes = [I32]
+    lib.gs_last_hip_error.restype = I32
+    lib.gs_last_hip_error.argtypes = []
+    lib.gs_default_settings.restype = None
+    lib.gs_default_settings.argtypes = [SET]
+    lib.gs_workspace_size.restype = SZ
+    lib.gs_workspace_size.argtypes = [I32, I64, I64, CAM, SET]
+    lib.gs_sort_key_bits.restype = I32
+    lib.gs_sort_key_bits.argtypes = [CAM, SET]
+    lib.gs_preprocess.restype = I32
+    lib.gs_preprocess.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, SZ, P]
+    lib.gs_sort.restype = I32
+    lib.gs_sort.argtypes = [I64, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ, P]
+    lib.gs_sort_pairs.restype = I32
+    lib.gs_sort_pairs.argtypes = [I64, P, P, I32, P, P, SET, P, SZ, P]
+    lib.gs_rasterize.restype = I32
+    lib.gs_rasterize.argtypes = [P, P, P, CAM, SET, P, P, P, P]
+    lib.gs_rasterize_backward.restype = I32
+    lib.gs_rasterize_backward.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, P, P,
+                                          P, P, P, P, P, I32, P, SZ, P]
+    lib.gs_trace_enable.restype = I32
+    lib.gs_trace_enable.argtypes = [I32]
+    lib.gs_trace_read.restype = I32
+    lib.gs_trace_read.argtypes = [I32, P, P, P]
+    _lib = lib
+    return lib
+
+
+def trace_enable(on: bool):
+    check(load().gs_trace_enable(1 if on else 0), "gs_trace_enable")
+
+
+def trace_read(max_entries: int = 512):
+    """[(label, ms)] recorded since the last read (waits for the GPU)."""
+    lib = load()
+    labels = ctypes.create_string_buffer(32 * max_entries)
+    ms = (ctypes.c_float * max_entries)()
+    cnt = ctypes.c_int32(0)
+    check(lib.gs_trace_read(max_entries, labels, ms, ctypes.byref(cnt)), "gs_trace_read")
+    raw = labels.raw
+    return [(raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode(), float(ms[i]))
+            for i in range(cnt.value)]
+
+
+def status_string(status: int) -> str:
+    return load().gs_status_string(int(status)).decode()
+
+
+def check(status: int, what: str):
+    if status != GS_OK:
+        raise GsError(status, what, load().gs_last_hip_error() if status == GS_ERR_HIP else 0)
+
+
+def default_settings(**overrides) -> GsSettings:
+    s = GsSettings()
+    load().gs_default_settings(ctypes.byref(s))
+    for k, v in overrides.items():
+        if k == "bg":
+            for i in range(3):
+                s.bg[i] = float(v[i])
+        else:
+            setattr(s, k, v)
+    return s
+
+
+def make_camera(cam) -> GsCamera:
+    """GsCamera from any object with viewmat (4x4), fx, fy, cx, cy, width,
+    height, znear."""
+    c = GsCamera()
+    vm = [float(x) for row in cam.viewmat for x in row] if hasattr(cam.viewmat[0], "__len__") \
+        else [float(x) for x in cam.viewmat]
+    for i in range(16):
+        c.viewmat[i] = vm[i]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.znear = float(getattr(cam, "znear", 0.2))
+    return c
+
+
+def model_array(model):
+    """Host float[12] for a 3x4 model transform, or None."""
+    if model is None:
+        return None
+    flat = [float(x) for row in model for x in row] if hasattr(model[0], "__len__") \
+        else [float(x) for x in model]
+    if len(flat) != 12:
+        raise ValueError("model transform must be 3x4")
+    return (ctypes.c_float * 12)(*flat)

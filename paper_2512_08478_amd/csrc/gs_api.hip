@@ -1,0 +1,453 @@
+// C ABI of libgs: argument validation, workspace layout and launch order.
+// Every check runs before the first HIP call.
+#include <cmath>
+#include <cstring>
+
+#include "gs_internal.h"
+
+namespace gs {
+bool tile_shape_supported(int tw, int th);
+
+namespace {
+constexpr int kTraceMax = 512;
+struct Tracer {
+  bool on = false;
+  bool created = false;
+  int count = 0;
+  hipEvent_t ev[kTraceMax];
+  char label[kTraceMax][32];
+};
+Tracer g_trace;
+}  // namespace
+
+void trace_mark(hipStream_t st, const char* label) {
+  Tracer& t = g_trace;
+  if (!t.on || t.count >= kTraceMax) return;
+  if (hipEventRecord(t.ev[t.count], st) != hipSuccess) return;
+  std::strncpy(t.label[t.count], label ? label : "", 31);
+  t.label[t.count][31] = 0;
+  ++t.count;
+}
+}  // namespace gs
+
+namespace {
+
+thread_local int32_t g_last_hip_error = 0;
+
+constexpr int64_t kMaxN = (int64_t)1 << 31;           // Gaussians per call
+constexpr int64_t kMaxInstances = ((int64_t)1 << 30) - 1;  // look-back counters are 30 bits
+
+int32_t hip_fail(hipError_t e) {
+  g_last_hip_error = (int32_t)e;
+  return GS_ERR_HIP;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// 0 = fine, else a gs_status
+int32_t check_dev(const void* p, bool required = true) {
+  if (!p) return required ? GS_ERR_INVALID_ARGUMENT : GS_OK;
+  return aligned16(p) ? GS_OK : GS_ERR_MISALIGNED;
+}
+
+int32_t check_settings(const gs_settings* s) {
+  if (!s) return GS_ERR_INVALID_ARGUMENT;
+  if (!gs::tile_shape_supported(s->tile_w, s->tile_h)) return GS_ERR_UNSUPPORTED;
+  if (s->radix_bits < 6 || s->radix_bits > 8) return GS_ERR_UNSUPPORTED;
+  if (!(s->eps2d >= 0.f) || !std::isfinite(s->eps2d)) return GS_ERR_INVALID_ARGUMENT;
+  if (!(s->alpha_min > 0.f) || !(s->alpha_max > s->alpha_min) || !(s->alpha_max < 1.f))
+    return GS_ERR_INVALID_ARGUMENT;
+  if (!(s->t_eps >= 0.f) || !(s->t_eps < 1.f)) return GS_ERR_INVALID_ARGUMENT;
+  if (!(s->clip > 0.f)) return GS_ERR_INVALID_ARGUMENT;
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(s->bg[c])) return GS_ERR_INVALID_ARGUMENT;
+  return GS_OK;
+}
+
+int32_t check_camera(const gs_camera* c, const gs_settings* s) {
+  if (!c) return GS_ERR_INVALID_ARGUMENT;
+  if (c->width <= 0 || c->height <= 0 || c->width > 32768 || c->height > 32768)
+    return GS_ERR_INVALID_ARGUMENT;
+  if (!(c->fx > 0.f) || !(c->fy > 0.f) || !std::isfinite(c->fx) || !std::isfinite(c->fy) ||
+      !std::isfinite(c->cx) || !std::isfinite(c->cy) || !(c->znear > 0.f))
+    return GS_ERR_INVALID_ARGUMENT;
+  for (int k = 0; k < 16; ++k)
+    if (!std::isfinite(c->viewmat[k])) return GS_ERR_INVALID_ARGUMENT;
+  // upper 3x3 must be a rotation
+  double R[9];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) R[3 * r + k] = c->viewmat[4 * r + k];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double d = 0;
+      for (int k = 0; k < 3; ++k) d += R[3 * i + k] * R[3 * j + k];
+      if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-4) return GS_ERR_INVALID_ARGUMENT;
+    }
+  (void)s;
+  return GS_OK;
+}
+
+int tiles_x_of(const gs_camera* c, const gs_settings* s) { return (c->width + s->tile_w - 1) / s->tile_w; }
+int tiles_y_of(const gs_camera* c, const gs_settings* s) { return (c->height + s->tile_h - 1) / s->tile_h; }
+
+int key_bits_of(const gs_camera* c, const gs_settings* s) {
+  const int64_t tiles = (int64_t)tiles_x_of(c, s) * tiles_y_of(c, s);
+  int b = 0;
+  while (((int64_t)1 << b) < tiles) ++b;
+  return 32 + b;
+}
+
+gs::SetK make_setk(const gs_camera* c, const gs_settings* s) {
+  gs::SetK k;
+  k.tile_w = s->tile_w;
+  k.tile_h = s->tile_h;
+  k.tiles_x = tiles_x_of(c, s);
+  k.tiles_y = tiles_y_of(c, s);
+  k.eps2d = s->eps2d;
+  k.tau = s->alpha_min;
+  k.log2_tau = (float)std::log2((double)s->alpha_min);
+  k.amax = s->alpha_max;
+  k.t_eps = s->t_eps;
+  for (int i = 0; i < 3; ++i) k.bg[i] = s->bg[i];
+  return k;
+}
+
+// Camera (and optional similarity model transform) in the kernels' form.
+int32_t make_camk(const gs_camera* c, const gs_settings* s, const float* model, gs::CamK* k) {
+  std::memset(k, 0, sizeof(*k));
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 4; ++q) k->V[4 * r + q] = c->viewmat[4 * r + q];
+  double Vr[9], A[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, tvec[3] = {0, 0, 0};
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) Vr[3 * r + q] = c->viewmat[4 * r + q];
+  k->has_model = model ? 1 : 0;
+  double sk = 1.0;
+  if (model) {
+    for (int r = 0; r < 3; ++r) {
+      for (int q = 0; q < 3; ++q) A[3 * r + q] = model[4 * r + q];
+      tvec[r] = model[4 * r + 3];
+    }
+    for (int q = 0; q < 12; ++q)
+      if (!std::isfinite(model[q])) return GS_ERR_INVALID_ARGUMENT;
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(det > 0.0)) return GS_ERR_INVALID_ARGUMENT;
+    sk = std::cbrt(det);
+    // must be a similarity: A A^T = s^2 I
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double d = 0;
+        for (int q = 0; q < 3; ++q) d += A[3 * i + q] * A[3 * j + q];
+        if (std::fabs(d / (sk * sk) - (i == j ? 1.0 : 0.0)) > 1e-4) return GS_ERR_INVALID_ARGUMENT;
+      }
+  }
+  for (int r = 0; r < 3; ++r) {
+    for (int q = 0; q < 3; ++q) {
+      k->A[4 * r + q] = (float)A[3 * r + q];
+      k->Rk[3 * r + q] = (float)(A[3 * r + q] / sk);
+      double t3 = 0;
+      for (int m = 0; m < 3; ++m) t3 += Vr[3 * r + m] * A[3 * m + q];
+      k->T3[3 * r + q] = (float)t3;
+    }
+    k->A[4 * r + 3] = (float)tvec[r];
+  }
+  for (int q = 0; q < 3; ++q)
+    k->campos[q] = (float)(-(Vr[q] * c->viewmat[3] + Vr[3 + q] * c->viewmat[7] + Vr[6 + q] * c->viewmat[11]));
+  k->fx = c->fx; k->fy = c->fy; k->cx = c->cx; k->cy = c->cy;
+  k->limx = (float)(s->clip * 0.5 * c->width / c->fx);
+  k->limy = (float)(s->clip * 0.5 * c->height / c->fy);
+  k->znear = c->znear;
+  k->W = c->width;
+  k->H = c->height;
+  return GS_OK;
+}
+
+int32_t check_inputs(int64_t n, const float* means, const float* log_scales, const float* quats,
+                     const float* logits, const float* sh, int32_t deg) {
+  if (n < 0 || n >= kMaxN) return GS_ERR_INVALID_ARGUMENT;
+  if (deg < 0 || deg > 3) return GS_ERR_UNSUPPORTED;
+  if (n == 0) return GS_OK;
+  int32_t r;
+  if ((r = check_dev(means)) || (r = check_dev(log_scales)) || (r = check_dev(quats)) ||
+      (r = check_dev(logits)) || (r = check_dev(sh)))
+    return r;
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gs_version(void) { return "libgs 0.1.0 (gfx950)"; }
+
+const char* gs_status_string(int32_t status) {
+  switch (status) {
+    case GS_OK: return "ok";
+    case GS_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case GS_ERR_UNSUPPORTED: return "unsupported (SH degree, tile shape or digit width)";
+    case GS_ERR_CAPACITY: return "instance capacity exceeded";
+    case GS_ERR_HIP: return "HIP runtime error";
+    case GS_ERR_MISALIGNED: return "device pointer not 16-byte aligned";
+    case GS_ERR_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+int32_t gs_last_hip_error(void) { return g_last_hip_error; }
+
+int32_t gs_trace_enable(int32_t on) {
+  gs::Tracer& t = gs::g_trace;
+  if (on && !t.created) {
+    for (int i = 0; i < gs::kTraceMax; ++i) {
+      hipError_t e = hipEventCreate(&t.ev[i]);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+    t.created = true;
+  }
+  t.on = on != 0;
+  t.count = 0;
+  return GS_OK;
+}
+
+int32_t gs_trace_read(int32_t max_entries, char* labels, float* ms, int32_t* count) {
+  gs::Tracer& t = gs::g_trace;
+  if (!count || (max_entries > 0 && (!labels || !ms))) return GS_ERR_INVALID_ARGUMENT;
+  *count = 0;
+  if (!t.created || t.count == 0) return GS_OK;
+  hipError_t e = hipEventSynchronize(t.ev[t.count - 1]);
+  if (e != hipSuccess) return hip_fail(e);
+  int k = 0;
+  for (int i = 0; i + 1 < t.count && k < max_entries; ++i) {
+    if (t.label[i][0] == 0) continue;
+    float v = 0.f;
+    e = hipEventElapsedTime(&v, t.ev[i], t.ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(e);
+    std::memcpy(labels + 32 * k, t.label[i], 32);
+    ms[k] = v;
+    ++k;
+  }
+  *count = k;
+  t.count = 0;
+  return GS_OK;
+}
+
+void gs_default_settings(gs_settings* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof(*s));
+  s->tile_w = 16;
+  s->tile_h = 16;
+  s->eps2d = 0.3f;
+  s->alpha_min = 1.0f / 255.0f;
+  s->alpha_max = 0.99f;
+  s->t_eps = 1e-4f;
+  s->clip = 1.3f;
+  s->radix_bits = 8;
+}
+
+int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set) {
+  if (check_settings(set) || check_camera(cam, set)) return -1;
+  return key_bits_of(cam, set);
+}
+
+size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity, const gs_camera* cam,
+                         const gs_settings* set) {
+  if (n < 0 || capacity < 0) return 0;
+  switch (stage) {
+    case GS_STAGE_PREPROCESS:
+      return gs::scan_layout(n).bytes;
+    case GS_STAGE_SORT:
+      if (check_settings(set) || check_camera(cam, set) || capacity > kMaxInstances) return 0;
+      return gs::sort_layout(capacity, 0).bytes;
+    case GS_STAGE_SORT_PAIRS:
+      if (check_settings(set) || capacity > kMaxInstances) return 0;
+      return gs::sort_layout(capacity, 0).bytes;
+    case GS_STAGE_BACKWARD:
+      return gs::align_up((size_t)(n > 0 ? n : 1) * gs::kGrad2dStride * 4, 256);
+    default:
+      return 0;
+  }
+}
+
+int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales, const float* quats,
+                      const float* opacity_logits, const float* sh, int32_t sh_degree,
+                      const float* model, const gs_camera* cam, const gs_settings* set,
+                      gs_splat* splats, uint32_t* offsets, uint32_t* total, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  int32_t r;
+  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
+  if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
+  if ((r = check_dev(total))) return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(offsets)))) return r;
+  const gs::ScanLayout L = gs::scan_layout(n);
+  if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
+  gs::CamK ck;
+  if ((r = make_camk(cam, set, model, &ck))) return r;
+  const gs::SetK sk = make_setk(cam, set);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  gs::trace_mark(st, "preprocess");
+  hipError_t e = gs::launch_preprocess((int)n, means, log_scales, quats, opacity_logits, sh,
+                                       sh_degree, ck, sk, splats, offsets, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "scan");
+  e = gs::launch_scan((int)n, offsets, total, workspace, L, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
+int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* offsets, const uint32_t* total,
+                const gs_camera* cam, const gs_settings* set, int64_t capacity, uint64_t* keys,
+                uint32_t* values, uint32_t* tile_ranges, uint32_t* status_flag, void* workspace,
+                size_t workspace_bytes, void* stream) {
+  int32_t r;
+  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
+  if (n < 0 || n >= kMaxN || capacity < 0 || capacity > kMaxInstances) return GS_ERR_INVALID_ARGUMENT;
+  if ((r = check_dev(total)) || (r = check_dev(tile_ranges))) return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(offsets)))) return r;
+  if (capacity > 0 && ((r = check_dev(keys)) || (r = check_dev(values)))) return r;
+  if ((r = check_dev(status_flag, false))) return r;
+  const gs::SortLayout L = gs::sort_layout(capacity, 0);
+  if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
+  const int bits = set->radix_bits;
+  const int passes = (key_bits_of(cam, set) + bits - 1) / bits;
+  const int tiles_x = tiles_x_of(cam, set), tiles = tiles_x * tiles_y_of(cam, set);
+  char* ws = static_cast<char*>(workspace);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.total);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  gs::trace_mark(st, "sort_init");
+  hipError_t e = gs::launch_sort_init(L, ws, passes, 1 << bits, tile_ranges, tiles, status_flag,
+                                      total, capacity, st);
+  if (e != hipSuccess) return hip_fail(e);
+  if (capacity == 0) {
+    gs::trace_mark(st, "");
+    return GS_OK;
+  }
+  uint64_t* ktmp = reinterpret_cast<uint64_t*>(ws + L.keys_tmp);
+  uint32_t* vtmp = reinterpret_cast<uint32_t*>(ws + L.vals_tmp);
+  gs::trace_mark(st, "keygen");
+  e = gs::launch_keygen((int)n, splats, offsets, total, capacity, tiles_x, bits, passes, ktmp, vtmp,
+                        hist, count, st);
+  if (e != hipSuccess) return hip_fail(e);
+  e = gs::launch_radix_passes(capacity, count, bits, passes, ktmp, vtmp,
+                              reinterpret_cast<uint64_t*>(ws + L.keys_alt),
+                              reinterpret_cast<uint32_t*>(ws + L.vals_alt), keys, values, hist,
+                              reinterpret_cast<uint32_t*>(ws + L.tickets),
+                              reinterpret_cast<uint32_t*>(ws + L.lookback), st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "tile_ranges");
+  e = gs::launch_tile_ranges(capacity, count, keys, tile_ranges, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
+int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in, const uint32_t* values_in,
+                      int32_t key_bits, uint64_t* keys_out, uint32_t* values_out,
+                      const gs_settings* set, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+  int32_t r;
+  if ((r = check_settings(set))) return r;
+  if (n < 0 || n > kMaxInstances || key_bits < 1 || key_bits > 64) return GS_ERR_INVALID_ARGUMENT;
+  if (n > 0) {
+    if ((r = check_dev(keys_in)) || (r = check_dev(values_in)) || (r = check_dev(keys_out)) ||
+        (r = check_dev(values_out)))
+      return r;
+    if ((const void*)keys_in == (const void*)keys_out || (const void*)values_in == (const void*)values_out)
+      return GS_ERR_INVALID_ARGUMENT;
+  }
+  const gs::SortLayout L = gs::sort_layout(n, 0);
+  if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
+  if (n == 0) return GS_OK;
+  const int bits = set->radix_bits;
+  const int passes = (key_bits + bits - 1) / bits;
+  char* ws = static_cast<char*>(workspace);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.total);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  gs::trace_mark(st, "sort_init");
+  hipError_t e = gs::launch_sort_init(L, ws, passes, 1 << bits, nullptr, 0, nullptr, nullptr, n, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "histogram");
+  e = gs::launch_histogram(n, keys_in, bits, passes, hist, st);
+  if (e != hipSuccess) return hip_fail(e);
+  e = gs::launch_radix_passes(n, count, bits, passes, const_cast<uint64_t*>(keys_in),
+                              const_cast<uint32_t*>(values_in),
+                              reinterpret_cast<uint64_t*>(ws + L.keys_alt),
+                              reinterpret_cast<uint32_t*>(ws + L.vals_alt), keys_out, values_out,
+                              hist, reinterpret_cast<uint32_t*>(ws + L.tickets),
+                              reinterpret_cast<uint32_t*>(ws + L.lookback), st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
+int32_t gs_rasterize(const gs_splat* splats, const uint32_t* values, const uint32_t* tile_ranges,
+                     const gs_camera* cam, const gs_settings* set, float* image, float* T_final,
+                     uint32_t* last, void* stream) {
+  int32_t r;
+  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
+  if ((r = check_dev(splats, false)) || (r = check_dev(values, false)) ||
+      (r = check_dev(tile_ranges)) || (r = check_dev(image)) || (r = check_dev(T_final)) ||
+      (r = check_dev(last)))
+    return r;
+  const gs::SetK sk = make_setk(cam, set);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  gs::trace_mark(st, "raster");
+  hipError_t e = gs::launch_rasterize(splats, values, tile_ranges, sk, cam->width, cam->height,
+                                      image, T_final, last, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
+int32_t gs_rasterize_backward(int64_t n, const float* means, const float* log_scales,
+                              const float* quats, const float* opacity_logits, const float* sh,
+                              int32_t sh_degree, const float* model, const gs_camera* cam,
+                              const gs_settings* set, const gs_splat* splats,
+                              const uint32_t* values, const uint32_t* tile_ranges,
+                              const float* T_final, const uint32_t* last,
+                              const float* dL_dimage, float* d_means, float* d_log_scales,
+                              float* d_quats, float* d_opacity_logits, float* d_sh,
+                              int32_t accumulate, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+  int32_t r;
+  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
+  if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
+  if ((r = check_dev(tile_ranges)) || (r = check_dev(T_final)) || (r = check_dev(last)) ||
+      (r = check_dev(dL_dimage)) || (r = check_dev(values, false)))
+    return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(d_means)) ||
+                (r = check_dev(d_log_scales)) || (r = check_dev(d_quats)) ||
+                (r = check_dev(d_opacity_logits)) || (r = check_dev(d_sh))))
+    return r;
+  const size_t need = gs_workspace_size(GS_STAGE_BACKWARD, n, 0, cam, set);
+  if (workspace_bytes < need) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
+  gs::CamK ck;
+  if ((r = make_camk(cam, set, model, &ck))) return r;
+  const gs::SetK sk = make_setk(cam, set);
+  if (n == 0) return GS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* grad2d = static_cast<float*>(workspace);
+  gs::trace_mark(st, "bwd_clear");
+  hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u,
+                                     n * gs::kGrad2dStride, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "raster_bwd");
+  e = gs::launch_rasterize_backward(splats, values, tile_ranges, sk, cam->width, cam->height,
+                                    T_final, last, dL_dimage, grad2d, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "preprocess_bwd");
+  e = gs::launch_preprocess_backward((int)n, means, log_scales, quats, opacity_logits, sh,
+                                     sh_degree, ck, sk, splats, grad2d, d_means, d_log_scales,
+                                     d_quats, d_opacity_logits, d_sh, accumulate, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Device helpers for wave64 (gfx950): lane queries, ballots, wave scans and
+// agent-scope atomic loads/stores for cross-workgroup look-back.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// bits of lanes below this one
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+
+__device__ __forceinline__ float shfl_f32(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+// Inclusive scan of u32 over the 64 lanes.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t o = shfl_u32(v, l >= d ? l - d : l);
+    if (l >= d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += shfl_u32(v, l ^ d);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += shfl_f32(v, l ^ d);
+  return v;
+}
+
+// Lanes of the wave whose `d` (BITS wide) equals this lane's, among `active`.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
+  uint64_t m = active;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const uint64_t v = ballot((d >> b) & 1u);
+    m &= ((d >> b) & 1u) ? v : ~v;
+  }
+  return m;
+}
+
+// Agent-scope (all XCDs) relaxed atomics for look-back status words.  The
+// payload and its flag live in the same word, so no further ordering is
+// needed.
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// a*d - b*c with one rounding error (Kahan's fma method).
+__device__ __forceinline__ float det2(float a, float b, float c, float d) {
+  const float w = b * c;
+  const float e = fmaf(-b, c, w);
+  const float f = fmaf(a, d, -w);
+  return f + e;
+}
+
+}  // namespace gs

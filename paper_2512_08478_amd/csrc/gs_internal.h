@@ -1,0 +1,112 @@
+// Internal declarations shared by the libgs translation units (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gs.h"
+
+namespace gs {
+
+constexpr int kBlock = 256;          // threads per block for streaming kernels
+constexpr int kScanItems = 16;       // u32 per thread in the offsets scan
+constexpr int kScanPart = kBlock * kScanItems;
+constexpr int kSortItems = 16;       // keys per thread in a radix pass
+constexpr int kSortPart = kBlock * kSortItems;  // keys per partition (4096)
+constexpr int kMaxPasses = 11;       // 64 bits / 6-bit digits
+
+constexpr uint32_t kLbFlagAgg = 1u << 30;   // look-back: partition count published
+constexpr uint32_t kLbFlagInc = 2u << 30;   // look-back: inclusive prefix published
+constexpr uint32_t kLbValue = (1u << 30) - 1;
+
+// Camera and settings as kernels see them (by value, in kernarg memory).
+struct CamK {
+  float V[12];        // world->camera rows 0..2 (3x4)
+  float T3[9];        // (view rotation) x (model linear part): maps an
+                      // asset-local direction into camera space
+  float Rk[9];        // model rotation (model linear part / its scale)
+  float A[12];        // model transform [s R | t]
+  float campos[3];    // camera centre in world coordinates
+  float fx, fy, cx, cy;
+  float limx, limy;   // clip * half-FoV tangents
+  float znear;
+  int W, H;
+  int has_model;
+};
+
+struct SetK {
+  int tile_w, tile_h, tiles_x, tiles_y;
+  float eps2d, tau, log2_tau, amax, t_eps;
+  float bg[3];
+};
+
+// Workspace carve-up helpers.
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct SortLayout {
+  size_t keys_tmp, vals_tmp, keys_alt, vals_alt, hist, tickets, lookback, flags, total;
+  size_t bytes;
+  int parts;
+};
+SortLayout sort_layout(int64_t capacity, int passes);
+
+struct ScanLayout {
+  size_t status, ticket, bytes;
+  int parts;
+};
+ScanLayout scan_layout(int64_t n);
+
+struct BwdLayout {
+  size_t grad2d, bytes;
+};
+BwdLayout bwd_layout(int64_t n);
+
+// Launchers (enqueue only; return the first launch error).
+hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
+                             const float* quats, const float* logits, const float* sh,
+                             int degree, const CamK& cam, const SetK& set,
+                             gs_splat* splats, uint32_t* counts, hipStream_t st);
+hipError_t launch_scan(int n, uint32_t* data, uint32_t* total, void* ws, const ScanLayout& L,
+                       hipStream_t st);
+hipError_t launch_sort_init(const SortLayout& L, char* ws, int passes, int nbins,
+                            uint32_t* tile_ranges, int tiles, uint32_t* status_flag,
+                            const uint32_t* total_src, int64_t capacity, hipStream_t st);
+hipError_t launch_keygen(int n, const gs_splat* splats, const uint32_t* offsets,
+                         const uint32_t* total, int64_t capacity, int tiles_x,
+                         int bits, int passes, uint64_t* keys, uint32_t* vals,
+                         uint32_t* hist, uint32_t* count, hipStream_t st);
+hipError_t launch_histogram(int64_t n, const uint64_t* keys, int bits, int passes,
+                            uint32_t* hist, hipStream_t st);
+hipError_t launch_radix_passes(int64_t capacity, const uint32_t* count, int bits, int passes,
+                               uint64_t* keys_a, uint32_t* vals_a, uint64_t* keys_b,
+                               uint32_t* vals_b, uint64_t* keys_out, uint32_t* vals_out,
+                               const uint32_t* hist, uint32_t* tickets, uint32_t* lookback,
+                               hipStream_t st);
+hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint64_t* keys,
+                              uint32_t* ranges, hipStream_t st);
+hipError_t launch_rasterize(const gs_splat* splats, const uint32_t* values,
+                            const uint32_t* ranges, const SetK& set, int W, int H,
+                            float* image, float* T_final, uint32_t* last, hipStream_t st);
+hipError_t launch_rasterize_backward(const gs_splat* splats, const uint32_t* values,
+                                     const uint32_t* ranges, const SetK& set, int W, int H,
+                                     const float* T_final, const uint32_t* last,
+                                     const float* dL_dimage, float* grad2d, hipStream_t st);
+hipError_t launch_preprocess_backward(int n, const float* means, const float* log_scales,
+                                      const float* quats, const float* logits, const float* sh,
+                                      int degree, const CamK& cam, const SetK& set,
+                                      const gs_splat* splats, const float* grad2d,
+                                      float* d_means, float* d_log_scales, float* d_quats,
+                                      float* d_logits, float* d_sh, int accumulate,
+                                      hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
+
+// Opt-in kernel tracer: when enabled, trace_mark records a HIP event on the
+// stream; the interval from one mark to the next is attributed to the
+// first mark's label (an empty label closes the interval).
+void trace_mark(hipStream_t st, const char* label);
+
+// Per-Gaussian 2-D gradient record written by the raster backward:
+// d(mean_x, mean_y, qa, qb, qc, opacity, r, g, b), padded to 12 floats.
+constexpr int kGrad2dStride = 12;
+
+}  // namespace gs

@@ -1,0 +1,524 @@
+// Per-Gaussian preprocess (Section 3.2 Eq. 1, Algorithm 1's Preprocess
+// procedure): activations, covariance from scale and rotation, per-model
+// transform, camera transform, culls, EWA footprint, SH colour, tile rect.
+//
+// One thread per Gaussian, 256-thread blocks.  Every input attribute is an
+// array of its own (means, log-scales, quaternions, logits, SH), so each
+// wave reads contiguous spans; the SH rows are read only for Gaussians that
+// survive the culls.
+#include "gs_device.h"
+#include "gs_internal.h"
+
+namespace gs {
+namespace {
+
+// Real SH normalisation constants (degree <= 3), with the sign of the
+// Condon-Shortley phase folded in; each is the closed form noted beside it.
+constexpr float kC0 = 0.28209479177387814f;   // 1/2 sqrt(1/pi)
+constexpr float kC1 = 0.48860251190291992f;   // sqrt(3/(4 pi))
+constexpr float kC2a = 1.0925484305920792f;   // 1/2 sqrt(15/pi)
+constexpr float kC2b = 0.31539156525252005f;  // 1/4 sqrt(5/pi)
+constexpr float kC2c = 0.54627421529603959f;  // 1/4 sqrt(15/pi)
+constexpr float kC3a = 0.59004358992664352f;  // 1/4 sqrt(35/(2 pi))
+constexpr float kC3b = 2.8906114426405538f;   // 1/2 sqrt(105/pi)
+constexpr float kC3c = 0.45704579946446572f;  // 1/4 sqrt(21/(2 pi))
+constexpr float kC3d = 0.37317633259011540f;  // 1/4 sqrt(7/pi)
+constexpr float kC3e = 1.4453057213202769f;   // 1/4 sqrt(105/pi)
+
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
+  Y[0] = kC0;
+  if (DEG >= 1) {
+    Y[1] = -kC1 * y;
+    Y[2] = kC1 * z;
+    Y[3] = -kC1 * x;
+  }
+  if (DEG >= 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kC2a * x * y;
+    Y[5] = -kC2a * y * z;
+    Y[6] = kC2b * (2.f * zz - xx - yy);
+    Y[7] = -kC2a * x * z;
+    Y[8] = kC2c * (xx - yy);
+    if (DEG >= 3) {
+      Y[9] = -kC3a * y * (3.f * xx - yy);
+      Y[10] = kC3b * x * y * z;
+      Y[11] = -kC3c * y * (4.f * zz - xx - yy);
+      Y[12] = kC3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+      Y[13] = -kC3c * x * (4.f * zz - xx - yy);
+      Y[14] = kC3e * z * (xx - yy);
+      Y[15] = -kC3a * x * (xx - 3.f * yy);
+    }
+  }
+}
+
+// rgb = sum_k sh_k Y_k + 1/2 for Gaussian i (before the clamp at 0).
+template <int DEG>
+__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int i, const float* Y,
+                                          float* rgb) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  float acc[3] = {0.5f, 0.5f, 0.5f};
+  if constexpr (DEG == 1 || DEG == 3) {
+    // rows are 48 or 192 bytes: 16-byte aligned float4 loads
+    const float4* row = reinterpret_cast<const float4*>(sh + (size_t)i * K * 3);
+    float v[K * 3];
+#pragma unroll
+    for (int j = 0; j < K * 3 / 4; ++j) {
+      const float4 f = row[j];
+      v[4 * j] = f.x; v[4 * j + 1] = f.y; v[4 * j + 2] = f.z; v[4 * j + 3] = f.w;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[0] = fmaf(v[3 * k], Y[k], acc[0]);
+      acc[1] = fmaf(v[3 * k + 1], Y[k], acc[1]);
+      acc[2] = fmaf(v[3 * k + 2], Y[k], acc[2]);
+    }
+  } else {
+    const float* row = sh + (size_t)i * K * 3;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[0] = fmaf(row[3 * k], Y[k], acc[0]);
+      acc[1] = fmaf(row[3 * k + 1], Y[k], acc[1]);
+      acc[2] = fmaf(row[3 * k + 2], Y[k], acc[2]);
+    }
+  }
+  rgb[0] = acc[0]; rgb[1] = acc[1]; rgb[2] = acc[2];
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_preprocess(
+    int n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, CamK cam, SetK set, gs_splat* __restrict__ splats,
+    uint32_t* __restrict__ counts) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+
+  const float p0 = means[3 * i], p1 = means[3 * i + 1], p2 = means[3 * i + 2];
+  const float4 q = quats[i];
+  const float lg = logits[i];
+
+  // world-space mean (per-model transform, Algorithm 1's M_k)
+  float w0 = p0, w1 = p1, w2 = p2;
+  if (cam.has_model) {
+    w0 = fmaf(cam.A[0], p0, fmaf(cam.A[1], p1, fmaf(cam.A[2], p2, cam.A[3])));
+    w1 = fmaf(cam.A[4], p0, fmaf(cam.A[5], p1, fmaf(cam.A[6], p2, cam.A[7])));
+    w2 = fmaf(cam.A[8], p0, fmaf(cam.A[9], p1, fmaf(cam.A[10], p2, cam.A[11])));
+  }
+  // camera space (x_c = V x_w)
+  const float tx = fmaf(cam.V[0], w0, fmaf(cam.V[1], w1, fmaf(cam.V[2], w2, cam.V[3])));
+  const float ty = fmaf(cam.V[4], w0, fmaf(cam.V[5], w1, fmaf(cam.V[6], w2, cam.V[7])));
+  const float tz = fmaf(cam.V[8], w0, fmaf(cam.V[9], w1, fmaf(cam.V[10], w2, cam.V[11])));
+
+  const float o = 1.f / (1.f + expf(-lg));
+  const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+  uint32_t tiles = 0;
+  uint32_t rect_lo = 0x0000FFFFu, rect_hi = 0u;  // tx0=0xFFFF ty0=0 | tx1=0 ty1=0: empty
+
+  bool ok = (tz > cam.znear) && (o >= set.tau) && (qn2 > 0.f) &&
+            __builtin_isfinite(tx) && __builtin_isfinite(ty) && __builtin_isfinite(qn2);
+  if (ok) {
+    // Sigma = R diag(s^2) R^T; with N = T3 R diag(s), camera-space
+    // covariance is N N^T and S = J N N^T J^T + eps I = M M^T + eps I.
+    const float s0 = expf(log_scales[3 * i]), s1 = expf(log_scales[3 * i + 1]),
+                s2 = expf(log_scales[3 * i + 2]);
+    const float inv = 1.f / sqrtf(qn2);
+    const float qw = q.x * inv, qx = q.y * inv, qy = q.z * inv, qz = q.w * inv;
+    float R[9];
+    R[0] = 1.f - 2.f * (qy * qy + qz * qz); R[1] = 2.f * (qx * qy - qw * qz); R[2] = 2.f * (qx * qz + qw * qy);
+    R[3] = 2.f * (qx * qy + qw * qz); R[4] = 1.f - 2.f * (qx * qx + qz * qz); R[5] = 2.f * (qy * qz - qw * qx);
+    R[6] = 2.f * (qx * qz - qw * qy); R[7] = 2.f * (qy * qz + qw * qx); R[8] = 1.f - 2.f * (qx * qx + qy * qy);
+    float N[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        N[3 * r + c] = fmaf(cam.T3[3 * r], R[c], fmaf(cam.T3[3 * r + 1], R[3 + c], cam.T3[3 * r + 2] * R[6 + c]));
+    N[0] *= s0; N[3] *= s0; N[6] *= s0;
+    N[1] *= s1; N[4] *= s1; N[7] *= s1;
+    N[2] *= s2; N[5] *= s2; N[8] *= s2;
+    // Jacobian of the perspective division at t (x/z, y/z clamped)
+    const float iz = 1.f / tz;
+    const float xt = fminf(cam.limx, fmaxf(-cam.limx, tx * iz));
+    const float yt = fminf(cam.limy, fmaxf(-cam.limy, ty * iz));
+    const float j00 = cam.fx * iz, j02 = -cam.fx * xt * iz;
+    const float j11 = cam.fy * iz, j12 = -cam.fy * yt * iz;
+    float m0[3], m1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      m0[c] = fmaf(j00, N[c], j02 * N[6 + c]);
+      m1[c] = fmaf(j11, N[3 + c], j12 * N[6 + c]);
+    }
+    const float aa = fmaf(m0[0], m0[0], fmaf(m0[1], m0[1], m0[2] * m0[2]));
+    const float cc = fmaf(m1[0], m1[0], fmaf(m1[1], m1[1], m1[2] * m1[2]));
+    const float b = fmaf(m0[0], m1[0], fmaf(m0[1], m1[1], m0[2] * m1[2]));
+    const float a = aa + set.eps2d, c = cc + set.eps2d;
+    // det S = |m0 x m1|^2 + eps (|m0|^2 + |m1|^2) + eps^2 (Cauchy-Binet):
+    // a sum of non-negative terms, so no cancellation.
+    const float x0 = det2(m0[1], m0[2], m1[1], m1[2]);
+    const float x1 = det2(m0[2], m0[0], m1[2], m1[0]);
+    const float x2 = det2(m0[0], m0[1], m1[0], m1[1]);
+    const float D = fmaf(x0, x0, fmaf(x1, x1, x2 * x2)) +
+                    set.eps2d * (aa + cc) + set.eps2d * set.eps2d;
+    const float mx = fmaf(cam.fx, tx * iz, cam.cx);
+    const float my = fmaf(cam.fy, ty * iz, cam.cy);
+    ok = D > 0.f && c > 0.f && __builtin_isfinite(D) && __builtin_isfinite(a) &&
+         __builtin_isfinite(mx) && __builtin_isfinite(my);
+    if (ok) {
+      const float qa = c / D, qb = b / c, qc = 1.f / c;
+      // Opacity-aware bbox: o exp(-Q/2) >= tau inside the ellipse
+      // Q <= 2 ln(o/tau), whose bbox half-extents are sqrt(qmax a),
+      // sqrt(qmax c).  Inflated slightly so that rounding can only add
+      // tiles (an added tile holds no pixel with weight >= tau).
+      const float qmax = 2.f * (logf(o) - logf(set.tau));
+      const float rx = sqrtf(qmax * a) * (1.f + 1e-5f) + 1e-3f + 1e-6f * fabsf(mx);
+      const float ry = sqrtf(qmax * c) * (1.f + 1e-5f) + 1e-3f + 1e-6f * fabsf(my);
+      float fx0 = ceilf(mx - rx - 0.5f), fx1 = floorf(mx + rx - 0.5f);
+      float fy0 = ceilf(my - ry - 0.5f), fy1 = floorf(my + ry - 0.5f);
+      fx0 = fmaxf(fx0, 0.f); fy0 = fmaxf(fy0, 0.f);
+      fx1 = fminf(fx1, (float)(cam.W - 1)); fy1 = fminf(fy1, (float)(cam.H - 1));
+      if (fx0 <= fx1 && fy0 <= fy1) {
+        const int px0 = (int)fx0, px1 = (int)fx1, py0 = (int)fy0, py1 = (int)fy1;
+        const int tx0 = px0 / set.tile_w, tx1 = px1 / set.tile_w;
+        const int ty0 = py0 / set.tile_h, ty1 = py1 / set.tile_h;
+        tiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        rect_lo = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+        rect_hi = (uint32_t)tx1 | ((uint32_t)ty1 << 16);
+        // view direction for the colour, in the asset's frame
+        float d0 = w0 - cam.campos[0], d1 = w1 - cam.campos[1], d2 = w2 - cam.campos[2];
+        const float dn = 1.f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+        d0 *= dn; d1 *= dn; d2 *= dn;
+        if (cam.has_model) {
+          const float e0 = cam.Rk[0] * d0 + cam.Rk[3] * d1 + cam.Rk[6] * d2;
+          const float e1 = cam.Rk[1] * d0 + cam.Rk[4] * d1 + cam.Rk[7] * d2;
+          const float e2 = cam.Rk[2] * d0 + cam.Rk[5] * d1 + cam.Rk[8] * d2;
+          d0 = e0; d1 = e1; d2 = e2;
+        }
+        float Y[16];
+        sh_basis<DEG>(d0, d1, d2, Y);
+        float rgb[3];
+        sh_colour<DEG>(sh, i, Y, rgb);
+        r0 = make_float4(mx, my, qa, qb);
+        r1 = make_float4(qc, o, fmaxf(rgb[0], 0.f), fmaxf(rgb[1], 0.f));
+        r2.x = fmaxf(rgb[2], 0.f);
+      }
+    }
+  }
+  r2.y = tz;
+  r2.z = __uint_as_float(rect_lo);
+  r2.w = __uint_as_float(rect_hi);
+  float4* dst = reinterpret_cast<float4*>(splats + i);
+  dst[0] = r0;
+  dst[1] = r1;
+  dst[2] = r2;
+  counts[i] = tiles;
+}
+
+// dY/d(x, y, z) of the basis above, accumulated against per-basis weights
+// wk: returns sum_k wk[k] * grad Y_k.
+template <int DEG>
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const float* wk,
+                                              float* g) {
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  if (DEG >= 1) {
+    gy -= kC1 * wk[1];
+    gz += kC1 * wk[2];
+    gx -= kC1 * wk[3];
+  }
+  if (DEG >= 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    gx += kC2a * y * wk[4]; gy += kC2a * x * wk[4];
+    gy -= kC2a * z * wk[5]; gz -= kC2a * y * wk[5];
+    gx -= 2.f * kC2b * x * wk[6]; gy -= 2.f * kC2b * y * wk[6]; gz += 4.f * kC2b * z * wk[6];
+    gx -= kC2a * z * wk[7]; gz -= kC2a * x * wk[7];
+    gx += 2.f * kC2c * x * wk[8]; gy -= 2.f * kC2c * y * wk[8];
+    if (DEG >= 3) {
+      gx -= 6.f * kC3a * x * y * wk[9]; gy -= 3.f * kC3a * (xx - yy) * wk[9];
+      gx += kC3b * y * z * wk[10]; gy += kC3b * x * z * wk[10]; gz += kC3b * x * y * wk[10];
+      gx += 2.f * kC3c * x * y * wk[11]; gy -= kC3c * (4.f * zz - xx - 3.f * yy) * wk[11];
+      gz -= 8.f * kC3c * y * z * wk[11];
+      gx -= 6.f * kC3d * x * z * wk[12]; gy -= 6.f * kC3d * y * z * wk[12];
+      gz += kC3d * (6.f * zz - 3.f * xx - 3.f * yy) * wk[12];
+      gx -= kC3c * (4.f * zz - 3.f * xx - yy) * wk[13]; gy += 2.f * kC3c * x * y * wk[13];
+      gz -= 8.f * kC3c * x * z * wk[13];
+      gx += 2.f * kC3e * x * z * wk[14]; gy -= 2.f * kC3e * y * z * wk[14];
+      gz += kC3e * (xx - yy) * wk[14];
+      gx -= 3.f * kC3a * (xx - yy) * wk[15]; gy += 6.f * kC3a * x * y * wk[15];
+    }
+  }
+  g[0] = gx; g[1] = gy; g[2] = gz;
+}
+
+// Chain rule from the 2-D gradient record d(mean2d, qa, qb, qc, opacity,
+// rgb) back to the raw inputs, recomputing the forward quantities.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_preprocess_bwd(
+    int n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, CamK cam, SetK set, const gs_splat* __restrict__ splats,
+    const float* __restrict__ grad2d, float* __restrict__ d_means,
+    float* __restrict__ d_log_scales, float4* __restrict__ d_quats,
+    float* __restrict__ d_logits, float* __restrict__ d_sh, int accumulate) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float gp[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
+  float glogit = 0.f;
+  float gsh[K * 3];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.f;
+
+  const float4 r2 = reinterpret_cast<const float4*>(splats + i)[2];
+  const uint32_t rl = __float_as_uint(r2.z), rh = __float_as_uint(r2.w);
+  const bool visible = (rh & 0xFFFFu) >= (rl & 0xFFFFu);
+  if (visible) {
+    const float* G = grad2d + (size_t)i * kGrad2dStride;
+    const float gmx = G[0], gmy = G[1], gqa = G[2], gqb = G[3], gqc = G[4], gop = G[5];
+    const float grgb[3] = {G[6], G[7], G[8]};
+
+    // ---- recompute the forward quantities
+    const float p0 = means[3 * i], p1 = means[3 * i + 1], p2 = means[3 * i + 2];
+    const float4 q = quats[i];
+    const float lg = logits[i];
+    float w0 = p0, w1 = p1, w2 = p2;
+    if (cam.has_model) {
+      w0 = fmaf(cam.A[0], p0, fmaf(cam.A[1], p1, fmaf(cam.A[2], p2, cam.A[3])));
+      w1 = fmaf(cam.A[4], p0, fmaf(cam.A[5], p1, fmaf(cam.A[6], p2, cam.A[7])));
+      w2 = fmaf(cam.A[8], p0, fmaf(cam.A[9], p1, fmaf(cam.A[10], p2, cam.A[11])));
+    }
+    const float tx = fmaf(cam.V[0], w0, fmaf(cam.V[1], w1, fmaf(cam.V[2], w2, cam.V[3])));
+    const float ty = fmaf(cam.V[4], w0, fmaf(cam.V[5], w1, fmaf(cam.V[6], w2, cam.V[7])));
+    const float tz = fmaf(cam.V[8], w0, fmaf(cam.V[9], w1, fmaf(cam.V[10], w2, cam.V[11])));
+    const float o = 1.f / (1.f + expf(-lg));
+    const float s[3] = {expf(log_scales[3 * i]), expf(log_scales[3 * i + 1]),
+                        expf(log_scales[3 * i + 2])};
+    const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+    const float inv = 1.f / sqrtf(qn2);
+    const float qw = q.x * inv, qx = q.y * inv, qy = q.z * inv, qz = q.w * inv;
+    float R[9];
+    R[0] = 1.f - 2.f * (qy * qy + qz * qz); R[1] = 2.f * (qx * qy - qw * qz); R[2] = 2.f * (qx * qz + qw * qy);
+    R[3] = 2.f * (qx * qy + qw * qz); R[4] = 1.f - 2.f * (qx * qx + qz * qz); R[5] = 2.f * (qy * qz - qw * qx);
+    R[6] = 2.f * (qx * qz - qw * qy); R[7] = 2.f * (qy * qz + qw * qx); R[8] = 1.f - 2.f * (qx * qx + qy * qy);
+    float P[9];  // T3 R
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        P[3 * r + c] = fmaf(cam.T3[3 * r], R[c], fmaf(cam.T3[3 * r + 1], R[3 + c], cam.T3[3 * r + 2] * R[6 + c]));
+    float N[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) N[3 * r + c] = P[3 * r + c] * s[c];
+    const float iz = 1.f / tz;
+    const float xr = tx * iz, yr = ty * iz;
+    const bool xclamp = xr < -cam.limx || xr > cam.limx;
+    const bool yclamp = yr < -cam.limy || yr > cam.limy;
+    const float xt = fminf(cam.limx, fmaxf(-cam.limx, xr));
+    const float yt = fminf(cam.limy, fmaxf(-cam.limy, yr));
+    const float j00 = cam.fx * iz, j02 = -cam.fx * xt * iz;
+    const float j11 = cam.fy * iz, j12 = -cam.fy * yt * iz;
+    float m0[3], m1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      m0[c] = fmaf(j00, N[c], j02 * N[6 + c]);
+      m1[c] = fmaf(j11, N[3 + c], j12 * N[6 + c]);
+    }
+    const float aa = fmaf(m0[0], m0[0], fmaf(m0[1], m0[1], m0[2] * m0[2]));
+    const float cc = fmaf(m1[0], m1[0], fmaf(m1[1], m1[1], m1[2] * m1[2]));
+    const float b = fmaf(m0[0], m1[0], fmaf(m0[1], m1[1], m0[2] * m1[2]));
+    const float c = cc + set.eps2d;
+    const float x0 = det2(m0[1], m0[2], m1[1], m1[2]);
+    const float x1 = det2(m0[2], m0[0], m1[2], m1[0]);
+    const float x2 = det2(m0[0], m0[1], m1[0], m1[1]);
+    const float D = fmaf(x0, x0, fmaf(x1, x1, x2 * x2)) +
+                    set.eps2d * (aa + cc) + set.eps2d * set.eps2d;
+    const float qa = c / D, qb = b / c, qc = 1.f / c;
+
+    // ---- colour: rgb = max(0, sum_k sh_k Y_k(dl) + 1/2)
+    float v0 = w0 - cam.campos[0], v1 = w1 - cam.campos[1], v2 = w2 - cam.campos[2];
+    const float vn = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+    const float ivn = 1.f / vn;
+    const float d0 = v0 * ivn, d1 = v1 * ivn, d2 = v2 * ivn;
+    float e0 = d0, e1 = d1, e2 = d2;
+    if (cam.has_model) {
+      e0 = cam.Rk[0] * d0 + cam.Rk[3] * d1 + cam.Rk[6] * d2;
+      e1 = cam.Rk[1] * d0 + cam.Rk[4] * d1 + cam.Rk[7] * d2;
+      e2 = cam.Rk[2] * d0 + cam.Rk[5] * d1 + cam.Rk[8] * d2;
+    }
+    float Y[16];
+    sh_basis<DEG>(e0, e1, e2, Y);
+    float rgb[3];
+    sh_colour<DEG>(sh, i, Y, rgb);
+    float graw[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) graw[ch] = rgb[ch] > 0.f ? grgb[ch] : 0.f;
+    float wk[16];
+    const float* shrow = sh + (size_t)i * K * 3;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      gsh[3 * k] = graw[0] * Y[k];
+      gsh[3 * k + 1] = graw[1] * Y[k];
+      gsh[3 * k + 2] = graw[2] * Y[k];
+      wk[k] = graw[0] * shrow[3 * k] + graw[1] * shrow[3 * k + 1] + graw[2] * shrow[3 * k + 2];
+    }
+    float gdl[3];
+    sh_basis_grad<DEG>(e0, e1, e2, wk, gdl);
+    float gd0 = gdl[0], gd1 = gdl[1], gd2 = gdl[2];
+    if (cam.has_model) {  // dl = Rk^T d  ->  dL/dd = Rk dL/ddl
+      gd0 = cam.Rk[0] * gdl[0] + cam.Rk[1] * gdl[1] + cam.Rk[2] * gdl[2];
+      gd1 = cam.Rk[3] * gdl[0] + cam.Rk[4] * gdl[1] + cam.Rk[5] * gdl[2];
+      gd2 = cam.Rk[6] * gdl[0] + cam.Rk[7] * gdl[1] + cam.Rk[8] * gdl[2];
+    }
+    const float dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
+    float gw[3] = {(gd0 - dd * d0) * ivn, (gd1 - dd * d1) * ivn, (gd2 - dd * d2) * ivn};
+
+    // ---- opacity
+    glogit = gop * o * (1.f - o);
+
+    // ---- (qa, qb, qc) -> S = [[a, b], [b, c]]
+    const float ga = -gqa * qa * qa;
+    const float gb = 2.f * gqa * qa * qa * qb + gqb * qc;
+    const float gc = -gqa * qa * qa * qb * qb - gqb * qb * qc - gqc * qc * qc;
+    // ---- S = M M^T + eps I
+    float gm0[3], gm1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gm0[k] = 2.f * ga * m0[k] + gb * m1[k];
+      gm1[k] = gb * m0[k] + 2.f * gc * m1[k];
+    }
+    // ---- M = J N  (rows m0 = j00 N0 + j02 N2, m1 = j11 N1 + j12 N2)
+    float gj00 = 0.f, gj02 = 0.f, gj11 = 0.f, gj12 = 0.f;
+    float gN[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gj00 += gm0[k] * N[k];
+      gj02 += gm0[k] * N[6 + k];
+      gj11 += gm1[k] * N[3 + k];
+      gj12 += gm1[k] * N[6 + k];
+      gN[k] = j00 * gm0[k];
+      gN[3 + k] = j11 * gm1[k];
+      gN[6 + k] = j02 * gm0[k] + j12 * gm1[k];
+    }
+    // ---- N = P diag(s), P = T3 R
+    float gR[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float gs = gN[c] * P[c] + gN[3 + c] * P[3 + c] + gN[6 + c] * P[6 + c];
+      gls[c] = gs * s[c];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)  // dL/dR_rc = sum_i T3_ir gP_ic, gP_ic = gN_ic s_c
+        gR[3 * r + c] = (cam.T3[r] * gN[c] + cam.T3[3 + r] * gN[3 + c] + cam.T3[6 + r] * gN[6 + c]) * s[c];
+    // ---- R(q^) -> q^
+    const float gqw = 2.f * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+    const float gqx = 2.f * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.f * qx * gR[4] - qw * gR[5] +
+                             qz * gR[6] + qw * gR[7] - 2.f * qx * gR[8]);
+    const float gqy = 2.f * (-2.f * qy * gR[0] + qx * gR[1] + qw * gR[2] + qx * gR[3] + qz * gR[5] -
+                             qw * gR[6] + qz * gR[7] - 2.f * qy * gR[8]);
+    const float gqz = 2.f * (-2.f * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.f * qz * gR[4] +
+                             qy * gR[5] + qx * gR[6] + qy * gR[7]);
+    // ---- normalisation q^ = q/|q|
+    const float qd = gqw * qw + gqx * qx + gqy * qy + gqz * qz;
+    gq[0] = (gqw - qd * qw) * inv;
+    gq[1] = (gqx - qd * qx) * inv;
+    gq[2] = (gqy - qd * qy) * inv;
+    gq[3] = (gqz - qd * qz) * inv;
+    // ---- J and mean2d -> camera-space t
+    const float iz2 = iz * iz;
+    float gtx = gmx * cam.fx * iz, gty = gmy * cam.fy * iz;
+    float gtz = -(gmx * cam.fx * tx + gmy * cam.fy * ty) * iz2;
+    gtz += -gj00 * cam.fx * iz2 - gj11 * cam.fy * iz2;
+    if (xclamp) {
+      gtz += gj02 * cam.fx * xt * iz2;
+    } else {
+      gtx += -gj02 * cam.fx * iz2;
+      gtz += 2.f * gj02 * cam.fx * tx * iz2 * iz;
+    }
+    if (yclamp) {
+      gtz += gj12 * cam.fy * yt * iz2;
+    } else {
+      gty += -gj12 * cam.fy * iz2;
+      gtz += 2.f * gj12 * cam.fy * ty * iz2 * iz;
+    }
+    // ---- t = V w + v  ->  w; w = A p + t_k  ->  p
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gw[k] += cam.V[k] * gtx + cam.V[4 + k] * gty + cam.V[8 + k] * gtz;
+    if (cam.has_model) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gp[k] = cam.A[k] * gw[0] + cam.A[4 + k] * gw[1] + cam.A[8 + k] * gw[2];
+    } else {
+      gp[0] = gw[0]; gp[1] = gw[1]; gp[2] = gw[2];
+    }
+  }
+
+  if (accumulate) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      d_means[3 * i + k] += gp[k];
+      d_log_scales[3 * i + k] += gls[k];
+    }
+    float4 dq = d_quats[i];
+    dq.x += gq[0]; dq.y += gq[1]; dq.z += gq[2]; dq.w += gq[3];
+    d_quats[i] = dq;
+    d_logits[i] += glogit;
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) d_sh[(size_t)i * K * 3 + k] += gsh[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      d_means[3 * i + k] = gp[k];
+      d_log_scales[3 * i + k] = gls[k];
+    }
+    d_quats[i] = make_float4(gq[0], gq[1], gq[2], gq[3]);
+    d_logits[i] = glogit;
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) d_sh[(size_t)i * K * 3 + k] = gsh[k];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
+                             const float* quats, const float* logits, const float* sh,
+                             int degree, const CamK& cam, const SetK& set,
+                             gs_splat* splats, uint32_t* counts, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid((n + kBlock - 1) / kBlock), block(kBlock);
+  const float4* q4 = reinterpret_cast<const float4*>(quats);
+  switch (degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, block, 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, counts); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, block, 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, counts); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, block, 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, counts); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, grid, block, 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, counts); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_backward(int n, const float* means, const float* log_scales,
+                                      const float* quats, const float* logits, const float* sh,
+                                      int degree, const CamK& cam, const SetK& set,
+                                      const gs_splat* splats, const float* grad2d,
+                                      float* d_means, float* d_log_scales, float* d_quats,
+                                      float* d_logits, float* d_sh, int accumulate,
+                                      hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid((n + kBlock - 1) / kBlock), block(kBlock);
+  const float4* q4 = reinterpret_cast<const float4*>(quats);
+  float4* dq4 = reinterpret_cast<float4*>(d_quats);
+#define GS_PBWD(D) hipLaunchKernelGGL(k_preprocess_bwd<D>, grid, block, 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, grad2d, d_means, d_log_scales, dq4, d_logits, d_sh, accumulate)
+  switch (degree) {
+    case 0: GS_PBWD(0); break;
+    case 1: GS_PBWD(1); break;
+    case 2: GS_PBWD(2); break;
+    default: GS_PBWD(3); break;
+  }
+#undef GS_PBWD
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,186 @@
+"""Torch-facing wrapper of libgs: device buffers, streams and autograd.
+
+PyTorch supplies device memory (tensor data pointers) and the current HIP
+stream; every step of the render path runs in libgs's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+__all__ = ["GaussianParams", "Renderer", "Frame", "render", "GsRender"]
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class GaussianParams:
+    """Raw Gaussian parameters on the GPU (float32, contiguous)."""
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    opacity_logits: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+    model: object = None  # 3x4 similarity transform or None
+
+    @property
+    def n(self):
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_scene(scene, device="cuda", requires_grad=False):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous().requires_grad_(requires_grad)
+        return GaussianParams(f(scene.means), f(scene.log_scales), f(scene.quats),
+                              f(scene.opacity_logits), f(scene.sh), int(scene.sh_degree),
+                              None if scene.model is None else [list(map(float, r)) for r in scene.model])
+
+    def tensors(self):
+        return (self.means, self.log_scales, self.quats, self.opacity_logits, self.sh)
+
+
+@dataclass
+class Frame:
+    """Forward outputs plus the state the backward pass re-walks."""
+    image: torch.Tensor      # (H, W, 4)
+    T_final: torch.Tensor    # (H, W)
+    last: torch.Tensor       # (H, W) int32 (u32 on the device)
+    splats: torch.Tensor     # (n*48,) uint8
+    offsets: torch.Tensor    # (n,) int32 (u32)
+    total: torch.Tensor      # (1,) int32 (u32), device
+    keys: torch.Tensor       # (capacity,) int64 (u64)
+    values: torch.Tensor     # (capacity,) int32 (u32)
+    ranges: torch.Tensor     # (2*tiles,) int32 (u32)
+    flag: torch.Tensor       # (1,) int32: bit 0 = capacity exceeded
+    capacity: int
+
+
+class Renderer:
+    """Holds settings and reusable workspaces for one device."""
+
+    def __init__(self, settings=None, device="cuda"):
+        self.settings = L.default_settings(**(settings or {}))
+        self.device = torch.device(device)
+        self._bufs = {}
+        L.load()
+
+    # ------------------------------------------------------------ buffers
+    def _buf(self, name, nbytes, reuse=True):
+        nbytes = max(int(nbytes), 256)
+        if not reuse:
+            return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        b = self._bufs.get(name)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(int(nbytes * 1.25) + 256, dtype=torch.uint8, device=self.device)
+            self._bufs[name] = b
+        return b
+
+    def tiles(self, cam):
+        s = self.settings
+        return ((cam.width + s.tile_w - 1) // s.tile_w) * ((cam.height + s.tile_h - 1) // s.tile_h)
+
+    # ------------------------------------------------------------ stages
+    def preprocess(self, p: GaussianParams, cam, reuse=True):
+        lib = L.load()
+        c, s = L.make_camera(cam), self.settings
+        n = p.n
+        splats = self._buf("splats", n * L.SPLAT_BYTES, reuse)
+        offsets = self._buf("offsets", n * 4, reuse).view(torch.int32)
+        total = self._buf("total", 4, reuse).view(torch.int32)
+        ws_bytes = lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, n, 0, ctypes.byref(c), ctypes.byref(s))
+        ws = self._buf("ws_pre", ws_bytes)
+        st = lib.gs_preprocess(n, *[_p(t) for t in p.tensors()], p.sh_degree, L.model_array(p.model),
+                               ctypes.byref(c), ctypes.byref(s), _p(splats), _p(offsets), _p(total),
+                               _p(ws), ws.numel(), _stream())
+        L.check(st, "gs_preprocess")
+        return splats, offsets, total
+
+    def sort(self, n, splats, offsets, total, cam, capacity=None, reuse=True):
+        """capacity=None reads the instance total back (one sync)."""
+        lib = L.load()
+        c, s = L.make_camera(cam), self.settings
+        if capacity is None:
+            capacity = int(total[:1].item()) & 0xFFFFFFFF
+        capacity = int(capacity)
+        keys = self._buf("keys", capacity * 8, reuse).view(torch.int64)
+        values = self._buf("values", capacity * 4, reuse).view(torch.int32)
+        ranges = self._buf("ranges", self.tiles(cam) * 8, reuse).view(torch.int32)
+        flag = self._buf("flag", 4, reuse).view(torch.int32)
+        ws_bytes = lib.gs_workspace_size(L.GS_STAGE_SORT, n, capacity, ctypes.byref(c), ctypes.byref(s))
+        if ws_bytes == 0:
+            raise L.GsError(L.GS_ERR_INVALID_ARGUMENT, "gs_workspace_size(sort)")
+        ws = self._buf("ws_sort", ws_bytes)
+        st = lib.gs_sort(n, _p(splats), _p(offsets), _p(total), ctypes.byref(c), ctypes.byref(s),
+                         capacity, _p(keys), _p(values), _p(ranges), _p(flag), _p(ws), ws.numel(),
+                         _stream())
+        L.check(st, "gs_sort")
+        return keys, values, ranges, flag, capacity
+
+    def rasterize(self, splats, values, ranges, cam):
+        lib = L.load()
+        c, s = L.make_camera(cam), self.settings
+        H, W = cam.height, cam.width
+        image = torch.empty((H, W, 4), dtype=torch.float32, device=self.device)
+        T = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        last = torch.empty((H, W), dtype=torch.int32, device=self.device)
+        st = lib.gs_rasterize(_p(splats), _p(values), _p(ranges), ctypes.byref(c), ctypes.byref(s),
+                              _p(image), _p(T), _p(last), _stream())
+        L.check(st, "gs_rasterize")
+        return image, T, last
+
+    def forward(self, p: GaussianParams, cam, capacity=None, reuse=True) -> Frame:
+        splats, offsets, total = self.preprocess(p, cam, reuse)
+        keys, values, ranges, flag, cap = self.sort(p.n, splats, offsets, total, cam, capacity, reuse)
+        image, T, last = self.rasterize(splats, values, ranges, cam)
+        return Frame(image, T, last, splats, offsets, total, keys, values, ranges, flag, cap)
+
+    def backward(self, p: GaussianParams, cam, fr: Frame, dL_dimage, out=None, accumulate=False):
+        lib = L.load()
+        c, s = L.make_camera(cam), self.settings
+        n = p.n
+        if out is None:
+            out = tuple(torch.zeros_like(t) for t in p.tensors())
+        dL = dL_dimage.to(torch.float32).contiguous()
+        ws_bytes = lib.gs_workspace_size(L.GS_STAGE_BACKWARD, n, 0, ctypes.byref(c), ctypes.byref(s))
+        ws = self._buf("ws_bwd", ws_bytes)
+        st = lib.gs_rasterize_backward(
+            n, *[_p(t) for t in p.tensors()], p.sh_degree, L.model_array(p.model), ctypes.byref(c),
+            ctypes.byref(s), _p(fr.splats), _p(fr.values), _p(fr.ranges), _p(fr.T_final),
+            _p(fr.last), _p(dL), *[_p(t) for t in out], int(bool(accumulate)), _p(ws), ws.numel(),
+            _stream())
+        L.check(st, "gs_rasterize_backward")
+        return out
+
+
+class GsRender(torch.autograd.Function):
+    """image = render(params); backward through libgs's hand-written kernels."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, renderer, cam, sh_degree, model):
+        p = GaussianParams(means.detach(), log_scales.detach(), quats.detach(),
+                           opacity_logits.detach(), sh.detach(), sh_degree, model)
+        fr = renderer.forward(p, cam, reuse=False)
+        ctx.renderer, ctx.cam, ctx.p, ctx.frame = renderer, cam, p, fr
+        return fr.image
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        g = ctx.renderer.backward(ctx.p, ctx.cam, ctx.frame, grad_image)
+        return (*g, None, None, None, None)
+
+
+def render(params: GaussianParams, cam, renderer: Renderer = None):
+    """Differentiable render of ``params`` from ``cam``: (H, W, 4) RGBA."""
+    renderer = renderer or Renderer()
+    return GsRender.apply(params.means, params.log_scales, params.quats, params.opacity_logits,
+                          params.sh, renderer, cam, params.sh_degree, params.model)

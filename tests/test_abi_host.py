@@ -1,0 +1,171 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/gs.h declares, and rejects bad arguments before any HIP call (so
+these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2512_08478_amd import _lib as L
+from paper_2512_08478_amd import scenes as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2512_08478_amd import build
+        build.build()
+    return L.load()
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "gs.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 11
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert set(L.EXPORTED) <= set(names)
+
+
+def test_version_and_status_strings(lib):
+    assert b"gfx950" in lib.gs_version()
+    assert L.status_string(0) == "ok"
+    for s in range(1, 7):
+        assert L.status_string(s) != "unknown status"
+    assert L.status_string(99) == "unknown status"
+
+
+def test_default_settings(lib):
+    s = L.default_settings()
+    assert (s.tile_w, s.tile_h, s.radix_bits) == (16, 16, 8)
+    assert s.eps2d == pytest.approx(0.3)
+    assert s.alpha_min == pytest.approx(1 / 255)
+    assert s.alpha_max == pytest.approx(0.99)
+    assert s.t_eps == pytest.approx(1e-4)
+    assert s.clip == pytest.approx(1.3)
+    assert list(s.bg) == [0.0, 0.0, 0.0]
+
+
+def cam_1080():
+    return L.make_camera(S.orbit_camera(0, 8, 8.0, 1920, 1080))
+
+
+def test_key_bits_and_workspace_sizes(lib):
+    c, s = cam_1080(), L.default_settings()
+    # 120 x 68 = 8160 tiles -> 13 tile bits above the 32 depth bits
+    assert lib.gs_sort_key_bits(ctypes.byref(c), ctypes.byref(s)) == 45
+    s8 = L.default_settings(tile_w=8, tile_h=8)
+    assert lib.gs_sort_key_bits(ctypes.byref(c), ctypes.byref(s8)) == 32 + 15  # 240x135
+    tiny = L.make_camera(S.tiny_scene(n=4)[1])
+    assert lib.gs_sort_key_bits(ctypes.byref(tiny), ctypes.byref(s)) == 40  # 256 tiles
+    assert lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, 1_000_000, 0, ctypes.byref(c), ctypes.byref(s)) > 0
+    w1 = lib.gs_workspace_size(L.GS_STAGE_SORT, 1_000_000, 4_000_000, ctypes.byref(c), ctypes.byref(s))
+    assert w1 >= 4_000_000 * 24
+    assert lib.gs_workspace_size(L.GS_STAGE_BACKWARD, 10, 0, ctypes.byref(c), ctypes.byref(s)) >= 480
+    assert lib.gs_workspace_size(L.GS_STAGE_SORT, 10, -1, ctypes.byref(c), ctypes.byref(s)) == 0
+    assert lib.gs_workspace_size(L.GS_STAGE_SORT, 10, 1 << 31, ctypes.byref(c), ctypes.byref(s)) == 0
+    assert lib.gs_workspace_size(99, 10, 10, ctypes.byref(c), ctypes.byref(s)) == 0
+
+
+FAKE = 0x7F0000000000  # aligned, never dereferenced: every call below fails validation first
+
+
+def pre(lib, n=4, deg=0, cam=None, st=None, ptrs=None, ws_bytes=1 << 20, total=FAKE):
+    c = cam or cam_1080()
+    s = st or L.default_settings()
+    p = ptrs or [FAKE] * 5
+    return lib.gs_preprocess(n, *[ctypes.c_void_p(x) if x else None for x in p], deg, None,
+                             ctypes.byref(c), ctypes.byref(s), ctypes.c_void_p(FAKE),
+                             ctypes.c_void_p(FAKE), ctypes.c_void_p(total) if total else None,
+                             ctypes.c_void_p(FAKE), ws_bytes, None)
+
+
+def test_preprocess_argument_validation(lib):
+    assert pre(lib, n=-1) == L.GS_ERR_INVALID_ARGUMENT
+    assert pre(lib, n=1 << 31) == L.GS_ERR_INVALID_ARGUMENT
+    assert pre(lib, deg=4) == L.GS_ERR_UNSUPPORTED
+    assert pre(lib, deg=-1) == L.GS_ERR_UNSUPPORTED
+    assert pre(lib, ptrs=[FAKE, 0, FAKE, FAKE, FAKE]) == L.GS_ERR_INVALID_ARGUMENT
+    assert pre(lib, ptrs=[FAKE, FAKE + 4, FAKE, FAKE, FAKE]) == L.GS_ERR_MISALIGNED
+    assert pre(lib, total=0) == L.GS_ERR_INVALID_ARGUMENT
+    assert pre(lib, ws_bytes=0) == L.GS_ERR_WORKSPACE
+    assert pre(lib, st=L.default_settings(tile_w=12)) == L.GS_ERR_UNSUPPORTED
+    assert pre(lib, st=L.default_settings(radix_bits=9)) == L.GS_ERR_UNSUPPORTED
+    assert pre(lib, st=L.default_settings(alpha_max=1.0)) == L.GS_ERR_INVALID_ARGUMENT
+    assert pre(lib, st=L.default_settings(alpha_min=0.0)) == L.GS_ERR_INVALID_ARGUMENT
+    assert pre(lib, st=L.default_settings(eps2d=-1.0)) == L.GS_ERR_INVALID_ARGUMENT
+    bad = cam_1080()
+    bad.width = 0
+    assert pre(lib, cam=bad) == L.GS_ERR_INVALID_ARGUMENT
+    bad = cam_1080()
+    bad.viewmat[0] = 2.0  # not a rotation
+    assert pre(lib, cam=bad) == L.GS_ERR_INVALID_ARGUMENT
+    bad = cam_1080()
+    bad.fx = float("nan")
+    assert pre(lib, cam=bad) == L.GS_ERR_INVALID_ARGUMENT
+
+
+def test_model_transform_must_be_similarity(lib):
+    c, s = cam_1080(), L.default_settings()
+    shear = (ctypes.c_float * 12)(1, 0.5, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    r = lib.gs_preprocess(4, *[ctypes.c_void_p(FAKE)] * 5, 0, shear, ctypes.byref(c),
+                          ctypes.byref(s), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
+                          ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), 0, None)
+    # the workspace check comes first; give enough workspace to reach the model check
+    assert r == L.GS_ERR_WORKSPACE
+    r = lib.gs_preprocess(4, *[ctypes.c_void_p(FAKE)] * 5, 0, shear, ctypes.byref(c),
+                          ctypes.byref(s), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
+                          ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), 1 << 20, None)
+    assert r == L.GS_ERR_INVALID_ARGUMENT
+    mirror = (ctypes.c_float * 12)(-1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    r = lib.gs_preprocess(4, *[ctypes.c_void_p(FAKE)] * 5, 0, mirror, ctypes.byref(c),
+                          ctypes.byref(s), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
+                          ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), 1 << 20, None)
+    assert r == L.GS_ERR_INVALID_ARGUMENT
+
+
+def test_sort_argument_validation(lib):
+    c, s = cam_1080(), L.default_settings()
+    F = ctypes.c_void_p(FAKE)
+
+    def srt(n=4, cap=16, keys=F, ws=1 << 30, flag=None):
+        return lib.gs_sort(n, F, F, F, ctypes.byref(c), ctypes.byref(s), cap, keys, F, F, flag, F,
+                           ws, None)
+    assert srt(cap=-1) == L.GS_ERR_INVALID_ARGUMENT
+    assert srt(cap=1 << 30) == L.GS_ERR_INVALID_ARGUMENT
+    assert srt(keys=None) == L.GS_ERR_INVALID_ARGUMENT
+    assert srt(keys=ctypes.c_void_p(FAKE + 8)) == L.GS_ERR_MISALIGNED
+    assert srt(flag=ctypes.c_void_p(FAKE + 4)) == L.GS_ERR_MISALIGNED
+    assert srt(ws=16) == L.GS_ERR_WORKSPACE
+
+    def sp(n=8, kb=64, kin=F, kout=ctypes.c_void_p(FAKE + 4096), ws=1 << 30):
+        return lib.gs_sort_pairs(n, kin, F, kb, kout, ctypes.c_void_p(FAKE + 8192), ctypes.byref(s),
+                                 F, ws, None)
+    assert sp(kb=0) == L.GS_ERR_INVALID_ARGUMENT
+    assert sp(kb=65) == L.GS_ERR_INVALID_ARGUMENT
+    assert sp(n=-2) == L.GS_ERR_INVALID_ARGUMENT
+    assert sp(kout=F) == L.GS_ERR_INVALID_ARGUMENT  # in == out
+    assert sp(ws=0) == L.GS_ERR_WORKSPACE
+
+
+def test_raster_argument_validation(lib):
+    c, s = cam_1080(), L.default_settings()
+    F = ctypes.c_void_p(FAKE)
+    r = lib.gs_rasterize(F, F, F, ctypes.byref(c), ctypes.byref(s), None, F, F, None)
+    assert r == L.GS_ERR_INVALID_ARGUMENT
+    r = lib.gs_rasterize(F, F, ctypes.c_void_p(FAKE + 2), ctypes.byref(c), ctypes.byref(s), F, F, F, None)
+    assert r == L.GS_ERR_MISALIGNED
+    r = lib.gs_rasterize_backward(4, F, F, F, F, F, 7, None, ctypes.byref(c), ctypes.byref(s),
+                                  F, F, F, F, F, F, F, F, F, F, F, 0, F, 1 << 20, None)
+    assert r == L.GS_ERR_UNSUPPORTED
+    r = lib.gs_rasterize_backward(4, F, F, F, F, F, 3, None, ctypes.byref(c), ctypes.byref(s),
+                                  F, F, F, F, F, F, F, F, F, F, F, 0, F, 8, None)
+    assert r == L.GS_ERR_WORKSPACE

@@ -1,0 +1,338 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Preprocess records, the bit-exact sort, the tile key lists and the rendered
+images, at the tiny size (whole image, every Gaussian) and at the full
+1M / 6M sizes in the launch configuration the benchmark times (sampled
+pixels the oracle computes one by one).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2512_08478_amd import scenes as S
+from gpu_util import (SPLAT_DTYPE, conic_from_whitened, image_check, print_case, splats_np, u32,
+                      u64)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_08478_amd.render import Renderer
+    return Renderer()
+
+
+def gp(scene):
+    from paper_2512_08478_amd.render import GaussianParams
+    return GaussianParams.from_scene(scene)
+
+
+# ------------------------------------------------------------------ preprocess
+
+def compare_records(orc, rec, ref, cam):
+    """GPU per-Gaussian records vs oracle records (Eq. 1, colour, culls)."""
+    vis_o = ref.visible
+    vis_g = rec["tx1"] >= rec["tx0"]
+    amb = ref.i[:, orc.I_AMBIG] == 1
+    mismatch = (vis_o != vis_g) & ~amb
+    assert not mismatch.any(), np.nonzero(mismatch)[0][:10]
+    v = vis_o & vis_g
+    d = ref.d[v]
+    r = rec[v]
+    np.testing.assert_allclose(r["mx"], d[:, orc.D_MX], rtol=2e-6, atol=2e-3)
+    np.testing.assert_allclose(r["my"], d[:, orc.D_MY], rtol=2e-6, atol=2e-3)
+    np.testing.assert_allclose(r["depth"], d[:, orc.D_DEPTH], rtol=1e-6)
+    np.testing.assert_allclose(r["op"], d[:, orc.D_OPAC], rtol=2e-6)
+    np.testing.assert_allclose(np.stack([r["r"], r["g"], r["b"]], 1), d[:, orc.D_R:orc.D_B + 1], atol=2e-6)
+    con = conic_from_whitened(r)
+    ref_con = d[:, orc.D_CA:orc.D_CC + 1]
+    scale = np.abs(ref_con).max(1, keepdims=True)
+    np.testing.assert_allclose(con / scale, ref_con / scale, atol=2e-5)
+    # tile rects: the GPU's may only be larger, by tiles that hold no pixel
+    # with weight >= alpha_min
+    it = ref.i[v]
+    assert np.all(r["tx0"] <= it[:, orc.I_TX0]) and np.all(r["tx1"] >= it[:, orc.I_TX1])
+    assert np.all(r["ty0"] <= it[:, orc.I_TY0]) and np.all(r["ty1"] >= it[:, orc.I_TY1])
+    return v
+
+
+def extra_pairs_harmless(orc, ref, rec, cam, v):
+    tx_n = (cam.width + 15) // 16
+    gs, tiles = [], []
+    for g in np.nonzero(v)[0]:
+        a, b = rec[g], ref.i[g]
+        for ty in range(a["ty0"], a["ty1"] + 1):
+            for tx in range(a["tx0"], a["tx1"] + 1):
+                if not (b[orc.I_TX0] <= tx <= b[orc.I_TX1] and b[orc.I_TY0] <= ty <= b[orc.I_TY1]):
+                    gs.append(g)
+                    tiles.append(ty * tx_n + tx)
+    if gs:
+        w = orc.pair_max_weight(ref, cam, np.array(gs), np.array(tiles))
+        assert w.max() < (1.0 / 255.0) * (1 + 1e-5)
+    return len(gs)
+
+
+def test_preprocess_tiny(R, orc):
+    print_case("preprocess tiny 4096")
+    sc, cam = S.tiny_scene()
+    splats, offsets, total = R.preprocess(gp(sc), cam)
+    torch.cuda.synchronize()
+    rec = splats_np(splats, sc.n)
+    ref = orc.preprocess(sc, cam)
+    v = compare_records(orc, rec, ref, cam)
+    extra_pairs_harmless(orc, ref, rec, cam, v)
+    cnt = np.where(rec["tx1"] >= rec["tx0"],
+                   (rec["tx1"].astype(np.int64) - rec["tx0"] + 1) * (rec["ty1"].astype(np.int64) - rec["ty0"] + 1), 0)
+    offs = u32(offsets[:sc.n])
+    np.testing.assert_array_equal(offs, np.concatenate([[0], np.cumsum(cnt)[:-1]]).astype(np.uint32))
+    assert int(u32(total)[0]) == cnt.sum()
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2, 3])
+def test_preprocess_sh_degrees(R, orc, deg):
+    print_case(f"preprocess sh degree {deg}")
+    rng = np.random.default_rng(40 + deg)
+    sc, cam = S.tiny_scene(n=2000)
+    K = (deg + 1) ** 2
+    sh = np.zeros((sc.n, K, 3), np.float32)
+    sh[:, 0] = sc.sh[:, 0]
+    if K > 1:
+        sh[:, 1:] = rng.normal(0, 0.2, (sc.n, K - 1, 3))
+    sc = S.Scene(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sh, deg)
+    cam2 = S.pinhole_camera(S.look_at((1.5, 1.0, -2.5)), 200, 150, 50.0)
+    splats, _, _ = R.preprocess(gp(sc), cam2)
+    torch.cuda.synchronize()
+    compare_records(orc, splats_np(splats, sc.n), orc.preprocess(sc, cam2), cam2)
+
+
+def test_preprocess_model_transform(R, orc):
+    print_case("preprocess with model transform")
+    from scipy.spatial.transform import Rotation
+    sc, _ = S.medium_scene(n=20000)
+    A = 0.7 * Rotation.from_euler("xyz", [0.4, -1.0, 0.3]).as_matrix()
+    sc.model = np.concatenate([A, np.array([[1.0], [-0.5], [2.0]])], 1).astype(np.float32)
+    cam = S.pinhole_camera(S.look_at((2.0, 1.0, -9.0)), 640, 480, 60.0)
+    splats, _, _ = R.preprocess(gp(sc), cam)
+    torch.cuda.synchronize()
+    compare_records(orc, splats_np(splats, sc.n), orc.preprocess(sc, cam), cam)
+
+
+# ------------------------------------------------------------------ sort
+
+SIZES = [1, 2, 63, 64, 65, 4095, 4096, 4097, 3 * 4096 + 17, 100_003]
+
+
+def sort_pairs_gpu(keys, vals, key_bits, radix_bits=8):
+    from paper_2512_08478_amd import _lib as L
+    import ctypes
+    lib = L.load()
+    s = L.default_settings(radix_bits=radix_bits)
+    n = len(keys)
+    kin = torch.from_numpy(keys.view(np.int64)).cuda()
+    vin = torch.from_numpy(vals.view(np.int32)).cuda()
+    kout = torch.empty_like(kin)
+    vout = torch.empty_like(vin)
+    ws_b = lib.gs_workspace_size(L.GS_STAGE_SORT_PAIRS, 0, n, None, ctypes.byref(s))
+    ws = torch.empty(ws_b, dtype=torch.uint8, device="cuda")
+    st = lib.gs_sort_pairs(n, ctypes.c_void_p(kin.data_ptr()), ctypes.c_void_p(vin.data_ptr()),
+                           key_bits, ctypes.c_void_p(kout.data_ptr()), ctypes.c_void_p(vout.data_ptr()),
+                           ctypes.byref(s), ctypes.c_void_p(ws.data_ptr()), ws_b,
+                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    L.check(st, "gs_sort_pairs")
+    torch.cuda.synchronize()
+    # the input must be untouched
+    np.testing.assert_array_equal(u64(kin), keys)
+    return u64(kout), u32(vout)
+
+
+@pytest.mark.parametrize("kind", S.SORT_KEY_KINDS)
+def test_sort_pairs_bitexact(R, orc, kind):
+    for n in SIZES:
+        print_case(f"sort_pairs {kind} n={n}")
+        k, v = S.sort_keys(kind, n, seed=n)
+        kb = 45 if kind in ("random45",) else 64
+        ks, vs = sort_pairs_gpu(k, v, kb)
+        rk, rv = orc.stable_sort_pairs(k, v)
+        np.testing.assert_array_equal(ks, rk, err_msg=f"{kind} n={n}")
+        np.testing.assert_array_equal(vs, rv, err_msg=f"{kind} n={n}")
+
+
+@pytest.mark.parametrize("bits", [6, 7, 8])
+def test_sort_pairs_digit_widths(R, orc, bits):
+    for kind in ("random64", "depth_like", "tile_runs"):
+        print_case(f"sort_pairs bits={bits} {kind}")
+        k, v = S.sort_keys(kind, 50_001, seed=bits)
+        ks, vs = sort_pairs_gpu(k, v, 64, radix_bits=bits)
+        rk, rv = orc.stable_sort_pairs(k, v)
+        np.testing.assert_array_equal(ks, rk)
+        np.testing.assert_array_equal(vs, rv)
+
+
+def test_sort_pairs_large(R, orc):
+    print_case("sort_pairs depth_like 10M")
+    k, v = S.sort_keys("depth_like", 10_000_000, seed=3)
+    ks, vs = sort_pairs_gpu(k, v, 45)
+    perm = np.argsort(k, kind="stable")
+    np.testing.assert_array_equal(ks, k[perm])
+    np.testing.assert_array_equal(vs, v[perm])
+
+
+def test_sort_pairs_empty(R):
+    print_case("sort_pairs n=0")
+    ks, vs = sort_pairs_gpu(np.zeros(0, np.uint64), np.zeros(0, np.uint32), 64)
+    assert ks.size == 0 and vs.size == 0
+
+
+# ------------------------------------------------------------------ keys + image
+
+def expected_sorted_pairs(rec, tiles_x):
+    """The unique stable order of (tile, depth bits, index) over the GPU's
+    own (Gaussian, tile) pairs -- the property the sort must produce."""
+    keys, vals = [], []
+    for g in np.nonzero(rec["tx1"] >= rec["tx0"])[0]:
+        a = rec[g]
+        zb = np.uint64(np.float32(a["depth"]).view(np.uint32))
+        for ty in range(a["ty0"], a["ty1"] + 1):
+            for tx in range(a["tx0"], a["tx1"] + 1):
+                keys.append((np.uint64(ty * tiles_x + tx) << np.uint64(32)) | zb)
+                vals.append(g)
+    keys = np.array(keys, np.uint64)
+    vals = np.array(vals, np.uint32)
+    perm = np.argsort(keys, kind="stable")
+    return keys[perm], vals[perm]
+
+
+def test_sort_keys_tiny(R, orc):
+    print_case("gs_sort keys tiny")
+    sc, cam = S.tiny_scene()
+    fr = R.forward(gp(sc), cam)
+    torch.cuda.synchronize()
+    rec = splats_np(fr.splats, sc.n)
+    n = fr.capacity
+    ek, ev = expected_sorted_pairs(rec, 16)
+    np.testing.assert_array_equal(u64(fr.keys)[:n], ek)
+    np.testing.assert_array_equal(u32(fr.values)[:n], ev)
+    # tile ranges
+    rng = u32(fr.ranges).reshape(-1, 2)
+    tile = (ek >> np.uint64(32)).astype(np.int64)
+    for t in range(rng.shape[0]):
+        idx = np.nonzero(tile == t)[0]
+        if idx.size:
+            assert (rng[t, 0], rng[t, 1]) == (idx[0], idx[-1] + 1)
+        else:
+            assert rng[t, 0] == rng[t, 1]
+    # against the oracle's own FP64 key list: same pairs up to harmless ones
+    ref = orc.preprocess(sc, cam)
+    ok, ov = orc.keys(ref, cam)
+    gset = set(zip((ek >> np.uint64(32)).tolist(), ev.tolist()))
+    oset = set(zip((ok >> np.uint64(32)).tolist(), ov.tolist()))
+    assert oset - gset == set()
+    extra = gset - oset
+    if extra:
+        t, g = map(np.array, zip(*extra))
+        w = orc.pair_max_weight(ref, cam, g, t)
+        assert w.max() < (1 / 255) * (1 + 1e-5)
+
+
+def test_render_tiny_whole_image(R, orc):
+    print_case("render tiny 256x256 vs brute force")
+    sc, cam = S.tiny_scene()
+    fr = R.forward(gp(sc), cam)
+    img = fr.image.cpu().numpy().reshape(-1, 4)
+    T = fr.T_final.cpu().numpy().reshape(-1)
+    ref = orc.render_image(orc.preprocess(sc, cam), cam)
+    flat = {k: v.reshape(-1, 4) if k == "rgba" else v.reshape(-1) for k, v in ref.items()}
+    e, nflag = image_check(img, flat)
+    print(f"tiny max err {e:.2e}, flagged {nflag}")
+    np.testing.assert_allclose(T[flat["margin"] >= 1e-5], flat["T"][flat["margin"] >= 1e-5], atol=1e-4)
+
+
+def sampled_pixels(cam, n, seed):
+    rng = np.random.default_rng(seed)
+    pix = np.stack([rng.integers(0, cam.width, n), rng.integers(0, cam.height, n)], 1)
+    corners = np.array([[0, 0], [cam.width - 1, cam.height - 1], [cam.width // 2, cam.height // 2],
+                        [cam.width - 1, 0], [0, cam.height - 1]])
+    return np.concatenate([pix, corners]).astype(np.int32)
+
+
+def test_render_medium_1080p_sampled(R, orc):
+    print_case("render 1M 1920x1080 sampled pixels")
+    sc, cam = S.medium_scene()
+    fr = R.forward(gp(sc), cam)
+    img = fr.image.cpu().numpy()
+    pix = sampled_pixels(cam, 256, 11)
+    ref = orc.render_pixels(orc.preprocess(sc, cam), cam, pix)
+    e, nflag = image_check(img[pix[:, 1], pix[:, 0]], ref)
+    print(f"1M max err {e:.2e}, flagged {nflag}, instances {fr.capacity}")
+
+
+def test_render_large_6m_sampled(R, orc):
+    print_case("render 6M 1920x1080 sampled pixels")
+    sc, cam = S.large_scene()
+    fr = R.forward(gp(sc), cam)
+    img = fr.image.cpu().numpy()
+    rec = splats_np(fr.splats, sc.n)
+    culled = float(np.mean(rec["tx1"] < rec["tx0"]))
+    print(f"6M culled fraction {culled:.3f}, instances {fr.capacity}")
+    assert 0.30 <= culled <= 0.50
+    pix = sampled_pixels(cam, 64, 12)
+    ref = orc.render_pixels(orc.preprocess(sc, cam), cam, pix)
+    e, nflag = image_check(img[pix[:, 1], pix[:, 0]], ref)
+    print(f"6M max err {e:.2e}, flagged {nflag}")
+
+
+# ------------------------------------------------------------------ edge cases + invariances
+
+def test_empty_and_all_culled(R):
+    print_case("n=0 and all-culled")
+    from paper_2512_08478_amd.render import Renderer
+    sc, cam = S.tiny_scene(n=16)
+    r2 = Renderer(dict(bg=(0.2, 0.4, 0.6)))
+    empty = sc.subset(np.arange(0))
+    fr = r2.forward(gp(empty), cam)
+    img = fr.image.cpu().numpy()
+    assert np.all(img[..., :3] == np.float32([0.2, 0.4, 0.6])) and np.all(img[..., 3] == 0)
+    behind = sc.subset(np.arange(16))
+    behind.means[:, 2] = -10.0  # all behind the camera
+    fr = r2.forward(gp(behind), cam)
+    img = fr.image.cpu().numpy()
+    assert fr.capacity == 0
+    assert np.all(img[..., 3] == 0)
+
+
+def test_tile_shape_and_digit_width_invariance(R):
+    print_case("tile shapes / digit widths give bitwise-identical images")
+    from paper_2512_08478_amd.render import Renderer
+    sc, cam = S.tiny_scene()
+    cam = S.pinhole_camera(S.look_at((0.3, -0.2, -3.0)), 250, 190, 60.0)  # ragged edge tiles
+    base = R.forward(gp(sc), cam).image.cpu().numpy()
+    for tw, th, bits in [(8, 8, 8), (16, 8, 7), (32, 8, 6), (32, 16, 8), (16, 16, 6)]:
+        img = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits)).forward(gp(sc), cam).image.cpu().numpy()
+        np.testing.assert_array_equal(img, base, err_msg=f"{tw}x{th} bits {bits}")
+
+
+def test_shuffle_and_repeat_invariance(R):
+    print_case("input shuffle and repeated runs")
+    sc, cam = S.tiny_scene()
+    a = R.forward(gp(sc), cam).image.cpu().numpy()
+    b = R.forward(gp(sc), cam).image.cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    perm = np.random.default_rng(5).permutation(sc.n)
+    c = R.forward(gp(sc.subset(perm)), cam).image.cpu().numpy()
+    np.testing.assert_array_equal(a, c)
+
+
+def test_capacity_overflow_flag(R):
+    print_case("capacity overflow sets the flag")
+    sc, cam = S.tiny_scene()
+    p = gp(sc)
+    splats, offsets, total = R.preprocess(p, cam)
+    tot = int(u32(total)[0])
+    keys, values, ranges, flag, cap = R.sort(sc.n, splats, offsets, total, cam, capacity=tot // 2)
+    torch.cuda.synchronize()
+    assert int(u32(flag)[0]) & 1 == 1
+    keys, values, ranges, flag, cap = R.sort(sc.n, splats, offsets, total, cam, capacity=tot)
+    torch.cuda.synchronize()
+    assert int(u32(flag)[0]) == 0
