@@ -76,12 +76,13 @@ class Renderer:
 
     # ------------------------------------------------------------ buffers
     def _buf(self, name, nbytes, reuse=True):
-        nbytes = max(int(nbytes), 256)
+        nbytes = (max(int(nbytes), 256) + 255) // 256 * 256
         if not reuse:
             return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         b = self._bufs.get(name)
         if b is None or b.numel() < nbytes:
-            b = torch.empty(int(nbytes * 1.25) + 256, dtype=torch.uint8, device=self.device)
+            grown = (int(nbytes * 1.25) + 255) // 256 * 256
+            b = torch.empty(grown, dtype=torch.uint8, device=self.device)
             self._bufs[name] = b
         return b
 
@@ -94,9 +95,9 @@ class Renderer:
         lib = L.load()
         c, s = L.make_camera(cam), self.settings
         n = p.n
-        splats = self._buf("splats", n * L.SPLAT_BYTES, reuse)
-        offsets = self._buf("offsets", n * 4, reuse).view(torch.int32)
-        total = self._buf("total", 4, reuse).view(torch.int32)
+        splats = self._buf("splats", n * L.SPLAT_BYTES, reuse)[:n * L.SPLAT_BYTES]
+        offsets = self._buf("offsets", n * 4, reuse).view(torch.int32)[:n]
+        total = self._buf("total", 4, reuse).view(torch.int32)[:1]
         ws_bytes = lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, n, 0, ctypes.byref(c), ctypes.byref(s))
         ws = self._buf("ws_pre", ws_bytes)
         st = lib.gs_preprocess(n, *[_p(t) for t in p.tensors()], p.sh_degree, L.model_array(p.model),
@@ -112,10 +113,10 @@ class Renderer:
         if capacity is None:
             capacity = int(total[:1].item()) & 0xFFFFFFFF
         capacity = int(capacity)
-        keys = self._buf("keys", capacity * 8, reuse).view(torch.int64)
-        values = self._buf("values", capacity * 4, reuse).view(torch.int32)
-        ranges = self._buf("ranges", self.tiles(cam) * 8, reuse).view(torch.int32)
-        flag = self._buf("flag", 4, reuse).view(torch.int32)
+        keys = self._buf("keys", capacity * 8, reuse).view(torch.int64)[:capacity]
+        values = self._buf("values", capacity * 4, reuse).view(torch.int32)[:capacity]
+        ranges = self._buf("ranges", self.tiles(cam) * 8, reuse).view(torch.int32)[:2 * self.tiles(cam)]
+        flag = self._buf("flag", 4, reuse).view(torch.int32)[:1]
         ws_bytes = lib.gs_workspace_size(L.GS_STAGE_SORT, n, capacity, ctypes.byref(c), ctypes.byref(s))
         if ws_bytes == 0:
             raise L.GsError(L.GS_ERR_INVALID_ARGUMENT, "gs_workspace_size(sort)")

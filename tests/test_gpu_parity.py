@@ -276,7 +276,7 @@ def test_render_large_6m_sampled(R, orc):
     rec = splats_np(fr.splats, sc.n)
     culled = float(np.mean(rec["tx1"] < rec["tx0"]))
     print(f"6M culled fraction {culled:.3f}, instances {fr.capacity}")
-    assert 0.30 <= culled <= 0.50
+    assert 0.35 <= culled <= 0.45
     pix = sampled_pixels(cam, 64, 12)
     ref = orc.render_pixels(orc.preprocess(sc, cam), cam, pix)
     e, nflag = image_check(img[pix[:, 1], pix[:, 0]], ref)
