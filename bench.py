@@ -20,11 +20,11 @@ if ROOT not in sys.path:
 
 METRIC = "frames/sec @1080p, 1M–6M Gaussians, fwd and fwd+bwd; sort Gkeys/s; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# plain (non-packed) FP32 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x
-# 4 (a wave64 op every cycle per SIMD pair) ... expressed as lane-ops/s:
-# 256 CUs * 64 lanes/clk * 2.4 GHz = 39.3 T lane-ops/s; an FMA counts as 2
-# flops, so 78.6 TFLOP/s for unpacked FMA.
-VALU_LANE_OPS = 256 * 64 * 2.4e9
+
+SORT_KERNELS = ("sort_init", "depth_hist", "depth_pass", "keygen", "tile_hist", "tile_pass",
+                "tile_ranges")
+HBM_KERNELS = ("preprocess", "depth_pass", "keygen", "tile_pass", "tile_ranges", "depth_hist",
+               "tile_hist")
 
 WORKLOADS = {
     "tiny": "tiny: 4,096 Gaussians, SH degree 0, 256x256, forward",
@@ -61,20 +61,24 @@ def make_workload(name):
     raise ValueError(name)
 
 
-def algorithmic_bytes(n, n_vis, inst, K, W, H, passes, tiles):
-    """Bytes each stage must move (reads + writes), per launch."""
+def algorithmic_bytes(n, n_vis, inst, K, W, H, tiles):
+    """Bytes each kernel must move (reads + writes), per launch."""
     return {
-        # means 12 + log-scales 12 + quats 16 + logit 4 read; 48 B record + 4 B count written;
-        # SH 12K bytes read for visible Gaussians only
-        "preprocess": n * (44 + 52) + n_vis * 12 * K,
-        # counts read + offsets written, in place
-        "scan": n * 8,
-        # offsets 4 + record tail 16 read per Gaussian; key 8 + value 4 written per instance
-        "keygen": n * 20 + inst * 12,
-        # per pass: key + value read and written
-        "radix_pass": inst * 24,
-        # sorted keys read, two u32 per tile written
-        "tile_ranges": inst * 8 + tiles * 8,
+        # means 12 + log-scales 12 + quats 16 + logit 4 read, 48 B record written per
+        # Gaussian; SH 12K bytes read and (depth, index) 8 B written per visible one
+        "preprocess": n * (44 + 48) + n_vis * (12 * K + 8),
+        # depth keys read
+        "depth_hist": n_vis * 4,
+        # per depth pass: u32 key + u32 value read and written per visible Gaussian
+        "depth_pass": n_vis * 16,
+        # sorted index 4 + record tail 16 read per visible Gaussian; tile key 4 + value 4
+        # written per instance
+        "keygen": n_vis * 20 + inst * 8,
+        "tile_hist": inst * 4,
+        # per tile pass: u32 key + u32 value read and written per instance
+        "tile_pass": inst * 16,
+        # sorted tile keys read, two u32 per tile written
+        "tile_ranges": inst * 4 + tiles * 8,
         # value + 48 B record gathered per instance, RGBA + T + last written per pixel
         "raster": inst * (4 + 48) + tiles * 8 + W * H * 24,
     }
@@ -151,8 +155,8 @@ def main():
     tiles = R.tiles(cam)
     import ctypes
     key_bits = L.load().gs_sort_key_bits(ctypes.byref(L.make_camera(cam)), ctypes.byref(R.settings))
-    passes = -(-key_bits // args.radix_bits)
-    ab = algorithmic_bytes(sc.n, n_vis, inst, K, W, H, passes, tiles)
+    passes = [-(-32 // args.radix_bits), -(-(key_bits - 32) // args.radix_bits)]
+    ab = algorithmic_bytes(sc.n, n_vis, inst, K, W, H, tiles)
     stages = {}
     for k, v in kern_avg.items():
         e = {"ms_per_launch": round(v, 5), "ms_per_frame": round(kern_ms[k], 5)}
@@ -160,9 +164,9 @@ def main():
             gbs = ab[k] / (v * 1e-3) / 1e9
             e.update(algo_bytes=int(ab[k]), gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
         stages[k] = e
-    sort_ms = sum(kern_ms.get(k, 0.0) for k in ("sort_init", "keygen", "radix_pass", "tile_ranges"))
+    sort_ms = sum(kern_ms.get(k, 0.0) for k in SORT_KERNELS)
     # dominant HBM-bound kernel by time per frame
-    hbm_kernels = [k for k in ("preprocess", "radix_pass", "keygen", "scan", "tile_ranges") if k in kern_ms]
+    hbm_kernels = [k for k in HBM_KERNELS if k in kern_ms]
     dom = max(hbm_kernels, key=lambda k: kern_ms[k])
     dom_gbs = ab[dom] / (kern_avg[dom] * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
@@ -184,7 +188,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_gaussians": sc.n, "width": W,
                    "height": H, "tile": args.tile, "radix_bits": args.radix_bits,
-                   "visible": n_vis, "instances": inst, "key_bits": key_bits, "passes": passes},
+                   "visible": n_vis, "instances": inst, "key_bits": key_bits,
+                   "depth_passes": passes[0], "tile_passes": passes[1]},
         "sort_gkeys_per_s": round(inst / (sort_ms * 1e-3) / 1e9, 3) if sort_ms > 0 else None,
         "sort_ms": round(sort_ms, 4),
         "stages": stages,

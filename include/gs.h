@@ -145,7 +145,8 @@ size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity,
 /*
  * Significant key bits of gs_sort for this camera and settings: 32 depth
  * bits plus ceil(log2(tiles)) tile bits.  The sort makes
- * ceil(key_bits / radix_bits) passes.
+ * ceil(32 / radix_bits) depth passes and ceil(tile bits / radix_bits)
+ * tile passes.
  */
 int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set);
 
@@ -163,10 +164,16 @@ int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set);
  *   for the identity.  Covariances become (sR) Sigma (sR)^T and the SH
  *   view direction is taken in the asset's own frame (R^T d).
  * Outputs (device):
- *   splats[n]      one gs_splat per Gaussian.
- *   offsets[n]     u32 exclusive prefix sum of the tiles each Gaussian
- *                  touches (instance offsets in Gaussian-major order).
- *   total[1]       u32 total number of (Gaussian, tile) instances.
+ *   splats[n]       one gs_splat per Gaussian (culled ones have an empty rect).
+ *   depth_keys[n]   u32 float32 bits of the camera-space depth of each
+ *                   visible Gaussian, compacted in Gaussian-index order
+ *                   (Algorithm 1's `depths`; the first counts[1] entries are
+ *                   meaningful).
+ *   depth_index[n]  u32 Gaussian index of each compacted entry (`indices`).
+ *   counts[2]       u32: counts[0] = (Gaussian, tile) instances in total,
+ *                   counts[1] = visible Gaussians.
+ * The compaction replaces Algorithm 1's atomic append with an ordered
+ * (prefix-sum) one, so the later stable sort has one unique result.
  * Culled (record with an empty rect, zero tiles): camera depth <= znear,
  * opacity < alpha_min, non-finite values, zero quaternion, or a footprint
  * whose opacity-aware bounding box (where o*exp(-Q/2) >= alpha_min)
@@ -177,36 +184,42 @@ int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales,
                       const float* quats, const float* opacity_logits,
                       const float* sh, int32_t sh_degree, const float* model,
                       const gs_camera* cam, const gs_settings* set,
-                      gs_splat* splats, uint32_t* offsets, uint32_t* total,
-                      void* workspace, size_t workspace_bytes, void* stream);
+                      gs_splat* splats, uint32_t* depth_keys,
+                      uint32_t* depth_index, uint32_t* counts, void* workspace,
+                      size_t workspace_bytes, void* stream);
 
 /*
  * gs_sort -- key generation and the per-frame GPU radix sort (Algorithm 1,
- * Radix Sort; Section 3.4).  For each visible Gaussian in index order and
- * each tile of its rect in row-major order, key = tile_id << 32 |
- * bits(float32 depth), value = Gaussian index; the pairs are then sorted by
- * a stable LSD radix sort, so equal keys stay in Gaussian-index order and
- * the permutation is unique.  Depth is camera-space z, which orders like
- * the paper's NDC z for z > 0.
+ * Radix Sort; Section 3.4).  The sort order is that of the 64-bit keys
+ *     key = tile_id << 32 | bits(float32 depth)
+ * taken for each visible Gaussian in index order and each tile of its rect
+ * in row-major order, sorted by a stable LSD radix sort: equal keys stay in
+ * Gaussian-index order, so the permutation is unique.  Depth is camera-space
+ * z, which orders like the paper's NDC z for z > 0.  The LSD passes over the
+ * 32 depth bits run on the compacted visible Gaussians before they are
+ * expanded into (Gaussian, tile) instances (every instance of a Gaussian
+ * has the same depth, so the order is the same); the passes over the tile
+ * bits run on the instances.
  *
- * Reads splats[n], offsets[n] and total (device, from gs_preprocess).
- * Writes keys[capacity] (u64, sorted), values[capacity] (u32, sorted) and
- * tile_ranges[2*tiles] (u32 [start, end) of each tile in the sorted list,
- * tiles = ceil(W/tile_w) * ceil(H/tile_h), row-major).  Only the first
- * `total` entries of keys/values are meaningful.
+ * Reads splats[n], depth_keys/depth_index and counts (device, from
+ * gs_preprocess).  Writes values[capacity] (u32 Gaussian index per sorted
+ * instance), tile_ranges[2*tiles] (u32 [start, end) of each tile in the
+ * sorted list, tiles = ceil(W/tile_w) * ceil(H/tile_h), row-major) and, if
+ * `keys` is not NULL, keys[capacity] (the sorted u64 keys above).  Only the
+ * first counts[0] entries are meaningful.
  *
- * The instance count is read on the device; there is no host sync.  When
- * total > capacity, nothing past `capacity` is written, `status_flag[0]`
- * (device u32, may be NULL) gets bit 0 set and the ranges cover only the
- * first `capacity` instances: the caller checks the flag (after a sync)
- * and retries with a larger capacity.
+ * Counts are read on the device; there is no host sync.  When counts[0] >
+ * capacity, only the first `capacity` instances in depth order are kept,
+ * `status_flag[0]` (device u32, may be NULL) gets bit 0 set, and the caller
+ * retries with a larger capacity after checking the flag.
  * Workspace: gs_workspace_size(GS_STAGE_SORT, n, capacity, cam, set).
  */
-int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* offsets,
-                const uint32_t* total, const gs_camera* cam,
-                const gs_settings* set, int64_t capacity, uint64_t* keys,
-                uint32_t* values, uint32_t* tile_ranges, uint32_t* status_flag,
-                void* workspace, size_t workspace_bytes, void* stream);
+int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
+                const uint32_t* depth_index, const uint32_t* counts,
+                const gs_camera* cam, const gs_settings* set, int64_t capacity,
+                uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
+                uint32_t* status_flag, void* workspace, size_t workspace_bytes,
+                void* stream);
 
 /*
  * gs_sort_pairs -- the stable LSD radix sort on its own: sorts n

@@ -254,13 +254,15 @@ size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity, const gs_ca
   if (n < 0 || capacity < 0) return 0;
   switch (stage) {
     case GS_STAGE_PREPROCESS:
-      return gs::scan_layout(n).bytes;
+      if (n >= kMaxN) return 0;
+      return gs::pre_layout(n).bytes;
     case GS_STAGE_SORT:
-      if (check_settings(set) || check_camera(cam, set) || capacity > kMaxInstances) return 0;
-      return gs::sort_layout(capacity, 0).bytes;
+      if (check_settings(set) || check_camera(cam, set) || capacity > kMaxInstances || n >= kMaxN)
+        return 0;
+      return gs::sort_layout(n, capacity).bytes;
     case GS_STAGE_SORT_PAIRS:
       if (check_settings(set) || capacity > kMaxInstances) return 0;
-      return gs::sort_layout(capacity, 0).bytes;
+      return gs::pairs_layout(capacity).bytes;
     case GS_STAGE_BACKWARD:
       return gs::align_up((size_t)(n > 0 ? n : 1) * gs::kGrad2dStride * 4, 256);
     default:
@@ -271,75 +273,93 @@ size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity, const gs_ca
 int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales, const float* quats,
                       const float* opacity_logits, const float* sh, int32_t sh_degree,
                       const float* model, const gs_camera* cam, const gs_settings* set,
-                      gs_splat* splats, uint32_t* offsets, uint32_t* total, void* workspace,
-                      size_t workspace_bytes, void* stream) {
+                      gs_splat* splats, uint32_t* depth_keys, uint32_t* depth_index,
+                      uint32_t* counts, void* workspace, size_t workspace_bytes, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
-  if ((r = check_dev(total))) return r;
-  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(offsets)))) return r;
-  const gs::ScanLayout L = gs::scan_layout(n);
+  if ((r = check_dev(counts))) return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)) || (r = check_dev(depth_index))))
+    return r;
+  const gs::PreLayout L = gs::pre_layout(n);
   if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
   if ((r = check_dev(workspace))) return r;
   gs::CamK ck;
   if ((r = make_camk(cam, set, model, &ck))) return r;
   const gs::SetK sk = make_setk(cam, set);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  gs::trace_mark(st, "preprocess");
+  gs::trace_mark(st, "preprocess_init");
   hipError_t e = gs::launch_preprocess((int)n, means, log_scales, quats, opacity_logits, sh,
-                                       sh_degree, ck, sk, splats, offsets, st);
-  if (e != hipSuccess) return hip_fail(e);
-  gs::trace_mark(st, "scan");
-  e = gs::launch_scan((int)n, offsets, total, workspace, L, st);
+                                       sh_degree, ck, sk, splats, depth_keys, depth_index, counts,
+                                       workspace, L, st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;
 }
 
-int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* offsets, const uint32_t* total,
-                const gs_camera* cam, const gs_settings* set, int64_t capacity, uint64_t* keys,
-                uint32_t* values, uint32_t* tile_ranges, uint32_t* status_flag, void* workspace,
+int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
+                const uint32_t* depth_index, const uint32_t* counts, const gs_camera* cam,
+                const gs_settings* set, int64_t capacity, uint64_t* keys, uint32_t* values,
+                uint32_t* tile_ranges, uint32_t* status_flag, void* workspace,
                 size_t workspace_bytes, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if (n < 0 || n >= kMaxN || capacity < 0 || capacity > kMaxInstances) return GS_ERR_INVALID_ARGUMENT;
-  if ((r = check_dev(total)) || (r = check_dev(tile_ranges))) return r;
-  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(offsets)))) return r;
-  if (capacity > 0 && ((r = check_dev(keys)) || (r = check_dev(values)))) return r;
-  if ((r = check_dev(status_flag, false))) return r;
-  const gs::SortLayout L = gs::sort_layout(capacity, 0);
+  if ((r = check_dev(counts)) || (r = check_dev(tile_ranges))) return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)) || (r = check_dev(depth_index))))
+    return r;
+  if (capacity > 0 && (r = check_dev(values))) return r;
+  if ((r = check_dev(keys, false)) || (r = check_dev(status_flag, false))) return r;
+  const gs::SortLayout L = gs::sort_layout(n, capacity);
   if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
   if ((r = check_dev(workspace))) return r;
   const int bits = set->radix_bits;
-  const int passes = (key_bits_of(cam, set) + bits - 1) / bits;
+  const int tile_bits = key_bits_of(cam, set) - 32;
+  const int pd = (32 + bits - 1) / bits;
+  const int pt = tile_bits > 0 ? (tile_bits + bits - 1) / bits : 1;
   const int tiles_x = tiles_x_of(cam, set), tiles = tiles_x * tiles_y_of(cam, set);
   char* ws = static_cast<char*>(workspace);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.total);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
+  uint32_t* count = U(L.count);
+  uint32_t* hist = U(L.hist);
+  uint32_t* tickets = U(L.tickets);
+  uint32_t* lookback = U(L.lookback);
   gs::trace_mark(st, "sort_init");
-  hipError_t e = gs::launch_sort_init(L, ws, passes, 1 << bits, tile_ranges, tiles, status_flag,
-                                      total, capacity, st);
+  hipError_t e = gs::launch_sort_init(L, ws, tile_ranges, tiles, status_flag, counts, capacity, st);
   if (e != hipSuccess) return hip_fail(e);
-  if (capacity == 0) {
+  if (n == 0 || capacity == 0) {
     gs::trace_mark(st, "");
     return GS_OK;
   }
-  uint64_t* ktmp = reinterpret_cast<uint64_t*>(ws + L.keys_tmp);
-  uint32_t* vtmp = reinterpret_cast<uint32_t*>(ws + L.vals_tmp);
-  gs::trace_mark(st, "keygen");
-  e = gs::launch_keygen((int)n, splats, offsets, total, capacity, tiles_x, bits, passes, ktmp, vtmp,
-                        hist, count, st);
+  // depth passes over the visible Gaussians (count = counts[1])
+  gs::trace_mark(st, "depth_hist");
+  e = gs::launch_histogram<uint32_t>(depth_keys, counts + 1, n, bits, pd, hist, st);
   if (e != hipSuccess) return hip_fail(e);
-  e = gs::launch_radix_passes(capacity, count, bits, passes, ktmp, vtmp,
-                              reinterpret_cast<uint64_t*>(ws + L.keys_alt),
-                              reinterpret_cast<uint32_t*>(ws + L.vals_alt), keys, values, hist,
-                              reinterpret_cast<uint32_t*>(ws + L.tickets),
-                              reinterpret_cast<uint32_t*>(ws + L.lookback), st);
+  e = gs::launch_radix_passes<uint32_t>(n, counts + 1, bits, pd, 0, depth_keys, depth_index,
+                                        U(L.dk[1]), U(L.dv[1]), U(L.dk[0]), U(L.dv[0]), false,
+                                        hist, tickets, lookback, L.parts, "depth_pass", st);
+  if (e != hipSuccess) return hip_fail(e);
+  // instances in depth order, then the tile passes
+  gs::trace_mark(st, "keygen");
+  e = gs::launch_keygen(n, U(L.dv[0]), counts + 1, splats, tiles_x, count, U(L.tk[0]), U(L.tv[0]),
+                        reinterpret_cast<uint64_t*>(ws + L.kg_status), tickets + pd + pt, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "tile_hist");
+  e = gs::launch_histogram<uint32_t>(U(L.tk[0]), count, capacity, bits, pt, hist + pd * 256, st);
+  if (e != hipSuccess) return hip_fail(e);
+  e = gs::launch_radix_passes<uint32_t>(capacity, count, bits, pt, pd, U(L.tk[0]), U(L.tv[0]),
+                                        U(L.tk[1]), U(L.tv[1]), U(L.tkf), values, true,
+                                        hist + pd * 256, tickets, lookback, L.parts, "tile_pass", st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "tile_ranges");
-  e = gs::launch_tile_ranges(capacity, count, keys, tile_ranges, st);
+  e = gs::launch_tile_ranges(capacity, count, U(L.tkf), tile_ranges, st);
   if (e != hipSuccess) return hip_fail(e);
+  if (keys) {
+    gs::trace_mark(st, "compose_keys");
+    e = gs::launch_compose_keys(capacity, count, U(L.tkf), values, splats, keys, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
   gs::trace_mark(st, "");
   return GS_OK;
 }
@@ -358,7 +378,7 @@ int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in, const uint32_t* values
     if ((const void*)keys_in == (const void*)keys_out || (const void*)values_in == (const void*)values_out)
       return GS_ERR_INVALID_ARGUMENT;
   }
-  const gs::SortLayout L = gs::sort_layout(n, 0);
+  const gs::SortLayout L = gs::pairs_layout(n);
   if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
   if ((r = check_dev(workspace))) return r;
   if (n == 0) return GS_OK;
@@ -366,20 +386,20 @@ int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in, const uint32_t* values
   const int passes = (key_bits + bits - 1) / bits;
   char* ws = static_cast<char*>(workspace);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t* count = reinterpret_cast<uint32_t*>(ws + L.total);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
   gs::trace_mark(st, "sort_init");
-  hipError_t e = gs::launch_sort_init(L, ws, passes, 1 << bits, nullptr, 0, nullptr, nullptr, n, st);
+  hipError_t e = gs::launch_sort_init(L, ws, nullptr, 0, nullptr, nullptr, n, st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "histogram");
-  e = gs::launch_histogram(n, keys_in, bits, passes, hist, st);
+  e = gs::launch_histogram<uint64_t>(keys_in, nullptr, n, bits, passes, hist, st);
   if (e != hipSuccess) return hip_fail(e);
-  e = gs::launch_radix_passes(n, count, bits, passes, const_cast<uint64_t*>(keys_in),
-                              const_cast<uint32_t*>(values_in),
-                              reinterpret_cast<uint64_t*>(ws + L.keys_alt),
-                              reinterpret_cast<uint32_t*>(ws + L.vals_alt), keys_out, values_out,
-                              hist, reinterpret_cast<uint32_t*>(ws + L.tickets),
-                              reinterpret_cast<uint32_t*>(ws + L.lookback), st);
+  e = gs::launch_radix_passes<uint64_t>(n, nullptr, bits, passes, 0, keys_in, values_in,
+                                        reinterpret_cast<uint64_t*>(ws + L.dk[0]),
+                                        reinterpret_cast<uint32_t*>(ws + L.dv[0]), keys_out,
+                                        values_out, true, hist,
+                                        reinterpret_cast<uint32_t*>(ws + L.tickets),
+                                        reinterpret_cast<uint32_t*>(ws + L.lookback), L.parts,
+                                        "radix_pass", st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;

@@ -9,11 +9,9 @@
 namespace gs {
 
 constexpr int kBlock = 256;          // threads per block for streaming kernels
-constexpr int kScanItems = 16;       // u32 per thread in the offsets scan
-constexpr int kScanPart = kBlock * kScanItems;
 constexpr int kSortItems = 16;       // keys per thread in a radix pass
 constexpr int kSortPart = kBlock * kSortItems;  // keys per partition (4096)
-constexpr int kMaxPasses = 11;       // 64 bits / 6-bit digits
+constexpr int kMaxPassTotal = 32;    // radix passes per call (depth + tile, or 64-bit)
 
 constexpr uint32_t kLbFlagAgg = 1u << 30;   // look-back: partition count published
 constexpr uint32_t kLbFlagInc = 2u << 30;   // look-back: inclusive prefix published
@@ -43,47 +41,51 @@ struct SetK {
 // Workspace carve-up helpers.
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// gs_sort workspace: depth ping-pong (u32 keys/values, n each), tile
+// ping-pong and final tile keys (u32, capacity each), histograms, tickets,
+// look-back words (two buffers), keygen status words, instance count.
 struct SortLayout {
-  size_t keys_tmp, vals_tmp, keys_alt, vals_alt, hist, tickets, lookback, flags, total;
+  size_t dk[2], dv[2], tk[2], tv[2], tkf, hist, tickets, lookback, kg_status, count;
   size_t bytes;
-  int parts;
+  int parts;     // look-back partitions per buffer
+  int kg_parts;  // keygen partitions
 };
-SortLayout sort_layout(int64_t capacity, int passes);
+SortLayout sort_layout(int64_t n, int64_t capacity);
+SortLayout pairs_layout(int64_t n);  // gs_sort_pairs: dk[0]/dv[0] are the u64/u32 alternates
 
-struct ScanLayout {
+struct PreLayout {
   size_t status, ticket, bytes;
   int parts;
 };
-ScanLayout scan_layout(int64_t n);
-
-struct BwdLayout {
-  size_t grad2d, bytes;
-};
-BwdLayout bwd_layout(int64_t n);
+PreLayout pre_layout(int64_t n);
 
 // Launchers (enqueue only; return the first launch error).
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
-                             gs_splat* splats, uint32_t* counts, hipStream_t st);
-hipError_t launch_scan(int n, uint32_t* data, uint32_t* total, void* ws, const ScanLayout& L,
-                       hipStream_t st);
-hipError_t launch_sort_init(const SortLayout& L, char* ws, int passes, int nbins,
-                            uint32_t* tile_ranges, int tiles, uint32_t* status_flag,
-                            const uint32_t* total_src, int64_t capacity, hipStream_t st);
-hipError_t launch_keygen(int n, const gs_splat* splats, const uint32_t* offsets,
-                         const uint32_t* total, int64_t capacity, int tiles_x,
-                         int bits, int passes, uint64_t* keys, uint32_t* vals,
-                         uint32_t* hist, uint32_t* count, hipStream_t st);
-hipError_t launch_histogram(int64_t n, const uint64_t* keys, int bits, int passes,
-                            uint32_t* hist, hipStream_t st);
-hipError_t launch_radix_passes(int64_t capacity, const uint32_t* count, int bits, int passes,
-                               uint64_t* keys_a, uint32_t* vals_a, uint64_t* keys_b,
-                               uint32_t* vals_b, uint64_t* keys_out, uint32_t* vals_out,
-                               const uint32_t* hist, uint32_t* tickets, uint32_t* lookback,
-                               hipStream_t st);
-hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint64_t* keys,
+                             gs_splat* splats, uint32_t* depth_keys, uint32_t* depth_index,
+                             uint32_t* counts, void* ws, const PreLayout& L, hipStream_t st);
+hipError_t launch_sort_init(const SortLayout& L, char* ws, uint32_t* tile_ranges, int tiles,
+                            uint32_t* status_flag, const uint32_t* total_src, int64_t capacity,
+                            hipStream_t st);
+template <typename KeyT>
+hipError_t launch_histogram(const KeyT* keys, const uint32_t* count, int64_t n_grid, int bits,
+                            int passes, uint32_t* hist, hipStream_t st);
+template <typename KeyT>
+hipError_t launch_radix_passes(int64_t n_grid, const uint32_t* count, int bits, int passes,
+                               int pass_base, const KeyT* kin, const uint32_t* vin, KeyT* k_alt,
+                               uint32_t* v_alt, KeyT* k_out, uint32_t* v_out, bool last_keys,
+                               uint32_t* hist, uint32_t* tickets, uint32_t* lookback, int lb_parts,
+                               const char* label, hipStream_t st);
+hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* vis_count,
+                         const gs_splat* splats, int tiles_x, const uint32_t* inst_count,
+                         uint32_t* tkeys, uint32_t* tvals, uint64_t* status, uint32_t* ticket,
+                         hipStream_t st);
+hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
                               uint32_t* ranges, hipStream_t st);
+hipError_t launch_compose_keys(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
+                               const uint32_t* values, const gs_splat* splats, uint64_t* keys,
+                               hipStream_t st);
 hipError_t launch_rasterize(const gs_splat* splats, const uint32_t* values,
                             const uint32_t* ranges, const SetK& set, int W, int H,
                             float* image, float* T_final, uint32_t* last, hipStream_t st);

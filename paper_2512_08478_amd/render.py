@@ -56,9 +56,10 @@ class Frame:
     T_final: torch.Tensor    # (H, W)
     last: torch.Tensor       # (H, W) int32 (u32 on the device)
     splats: torch.Tensor     # (n*48,) uint8
-    offsets: torch.Tensor    # (n,) int32 (u32)
-    total: torch.Tensor      # (1,) int32 (u32), device
-    keys: torch.Tensor       # (capacity,) int64 (u64)
+    depth_keys: torch.Tensor  # (n,) int32 (u32): compacted visible depth bits
+    depth_index: torch.Tensor  # (n,) int32 (u32): their Gaussian indices
+    counts: torch.Tensor     # (2,) int32 (u32), device: instances, visible
+    keys: torch.Tensor       # (capacity,) int64 (u64) or None
     values: torch.Tensor     # (capacity,) int32 (u32)
     ranges: torch.Tensor     # (2*tiles,) int32 (u32)
     flag: torch.Tensor       # (1,) int32: bit 0 = capacity exceeded
@@ -96,24 +97,25 @@ class Renderer:
         c, s = L.make_camera(cam), self.settings
         n = p.n
         splats = self._buf("splats", n * L.SPLAT_BYTES, reuse)[:n * L.SPLAT_BYTES]
-        offsets = self._buf("offsets", n * 4, reuse).view(torch.int32)[:n]
-        total = self._buf("total", 4, reuse).view(torch.int32)[:1]
+        dkeys = self._buf("depth_keys", n * 4, reuse).view(torch.int32)[:n]
+        didx = self._buf("depth_index", n * 4, reuse).view(torch.int32)[:n]
+        counts = self._buf("counts", 8, reuse).view(torch.int32)[:2]
         ws_bytes = lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, n, 0, ctypes.byref(c), ctypes.byref(s))
         ws = self._buf("ws_pre", ws_bytes)
         st = lib.gs_preprocess(n, *[_p(t) for t in p.tensors()], p.sh_degree, L.model_array(p.model),
-                               ctypes.byref(c), ctypes.byref(s), _p(splats), _p(offsets), _p(total),
-                               _p(ws), ws.numel(), _stream())
+                               ctypes.byref(c), ctypes.byref(s), _p(splats), _p(dkeys), _p(didx),
+                               _p(counts), _p(ws), ws.numel(), _stream())
         L.check(st, "gs_preprocess")
-        return splats, offsets, total
+        return splats, dkeys, didx, counts
 
-    def sort(self, n, splats, offsets, total, cam, capacity=None, reuse=True):
-        """capacity=None reads the instance total back (one sync)."""
+    def sort(self, n, splats, dkeys, didx, counts, cam, capacity=None, reuse=True, want_keys=False):
+        """capacity=None reads the instance count back (one sync)."""
         lib = L.load()
         c, s = L.make_camera(cam), self.settings
         if capacity is None:
-            capacity = int(total[:1].item()) & 0xFFFFFFFF
+            capacity = int(counts[:1].item()) & 0xFFFFFFFF
         capacity = int(capacity)
-        keys = self._buf("keys", capacity * 8, reuse).view(torch.int64)[:capacity]
+        keys = self._buf("keys", capacity * 8, reuse).view(torch.int64)[:capacity] if want_keys else None
         values = self._buf("values", capacity * 4, reuse).view(torch.int32)[:capacity]
         ranges = self._buf("ranges", self.tiles(cam) * 8, reuse).view(torch.int32)[:2 * self.tiles(cam)]
         flag = self._buf("flag", 4, reuse).view(torch.int32)[:1]
@@ -121,9 +123,9 @@ class Renderer:
         if ws_bytes == 0:
             raise L.GsError(L.GS_ERR_INVALID_ARGUMENT, "gs_workspace_size(sort)")
         ws = self._buf("ws_sort", ws_bytes)
-        st = lib.gs_sort(n, _p(splats), _p(offsets), _p(total), ctypes.byref(c), ctypes.byref(s),
-                         capacity, _p(keys), _p(values), _p(ranges), _p(flag), _p(ws), ws.numel(),
-                         _stream())
+        st = lib.gs_sort(n, _p(splats), _p(dkeys), _p(didx), _p(counts), ctypes.byref(c),
+                         ctypes.byref(s), capacity, _p(keys), _p(values), _p(ranges), _p(flag),
+                         _p(ws), ws.numel(), _stream())
         L.check(st, "gs_sort")
         return keys, values, ranges, flag, capacity
 
@@ -139,11 +141,12 @@ class Renderer:
         L.check(st, "gs_rasterize")
         return image, T, last
 
-    def forward(self, p: GaussianParams, cam, capacity=None, reuse=True) -> Frame:
-        splats, offsets, total = self.preprocess(p, cam, reuse)
-        keys, values, ranges, flag, cap = self.sort(p.n, splats, offsets, total, cam, capacity, reuse)
+    def forward(self, p: GaussianParams, cam, capacity=None, reuse=True, want_keys=False) -> Frame:
+        splats, dkeys, didx, counts = self.preprocess(p, cam, reuse)
+        keys, values, ranges, flag, cap = self.sort(p.n, splats, dkeys, didx, counts, cam, capacity,
+                                                    reuse, want_keys)
         image, T, last = self.rasterize(splats, values, ranges, cam)
-        return Frame(image, T, last, splats, offsets, total, keys, values, ranges, flag, cap)
+        return Frame(image, T, last, splats, dkeys, didx, counts, keys, values, ranges, flag, cap)
 
     def backward(self, p: GaussianParams, cam, fr: Frame, dL_dimage, out=None, accumulate=False):
         lib = L.load()

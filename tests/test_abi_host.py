@@ -84,7 +84,8 @@ def pre(lib, n=4, deg=0, cam=None, st=None, ptrs=None, ws_bytes=1 << 20, total=F
     p = ptrs or [FAKE] * 5
     return lib.gs_preprocess(n, *[ctypes.c_void_p(x) if x else None for x in p], deg, None,
                              ctypes.byref(c), ctypes.byref(s), ctypes.c_void_p(FAKE),
-                             ctypes.c_void_p(FAKE), ctypes.c_void_p(total) if total else None,
+                             ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
+                             ctypes.c_void_p(total) if total else None,
                              ctypes.c_void_p(FAKE), ws_bytes, None)
 
 
@@ -115,20 +116,18 @@ def test_preprocess_argument_validation(lib):
 
 def test_model_transform_must_be_similarity(lib):
     c, s = cam_1080(), L.default_settings()
+    F = ctypes.c_void_p(FAKE)
     shear = (ctypes.c_float * 12)(1, 0.5, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
-    r = lib.gs_preprocess(4, *[ctypes.c_void_p(FAKE)] * 5, 0, shear, ctypes.byref(c),
-                          ctypes.byref(s), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
-                          ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), 0, None)
+    r = lib.gs_preprocess(4, *[F] * 5, 0, shear, ctypes.byref(c), ctypes.byref(s), F, F, F, F, F,
+                          0, None)
     # the workspace check comes first; give enough workspace to reach the model check
     assert r == L.GS_ERR_WORKSPACE
-    r = lib.gs_preprocess(4, *[ctypes.c_void_p(FAKE)] * 5, 0, shear, ctypes.byref(c),
-                          ctypes.byref(s), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
-                          ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), 1 << 20, None)
+    r = lib.gs_preprocess(4, *[F] * 5, 0, shear, ctypes.byref(c), ctypes.byref(s), F, F, F, F, F,
+                          1 << 20, None)
     assert r == L.GS_ERR_INVALID_ARGUMENT
     mirror = (ctypes.c_float * 12)(-1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
-    r = lib.gs_preprocess(4, *[ctypes.c_void_p(FAKE)] * 5, 0, mirror, ctypes.byref(c),
-                          ctypes.byref(s), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
-                          ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), 1 << 20, None)
+    r = lib.gs_preprocess(4, *[F] * 5, 0, mirror, ctypes.byref(c), ctypes.byref(s), F, F, F, F, F,
+                          1 << 20, None)
     assert r == L.GS_ERR_INVALID_ARGUMENT
 
 
@@ -136,12 +135,12 @@ def test_sort_argument_validation(lib):
     c, s = cam_1080(), L.default_settings()
     F = ctypes.c_void_p(FAKE)
 
-    def srt(n=4, cap=16, keys=F, ws=1 << 30, flag=None):
-        return lib.gs_sort(n, F, F, F, ctypes.byref(c), ctypes.byref(s), cap, keys, F, F, flag, F,
-                           ws, None)
+    def srt(n=4, cap=16, keys=F, values=F, ws=1 << 30, flag=None):
+        return lib.gs_sort(n, F, F, F, F, ctypes.byref(c), ctypes.byref(s), cap, keys, values, F,
+                           flag, F, ws, None)
     assert srt(cap=-1) == L.GS_ERR_INVALID_ARGUMENT
     assert srt(cap=1 << 30) == L.GS_ERR_INVALID_ARGUMENT
-    assert srt(keys=None) == L.GS_ERR_INVALID_ARGUMENT
+    assert srt(values=None) == L.GS_ERR_INVALID_ARGUMENT
     assert srt(keys=ctypes.c_void_p(FAKE + 8)) == L.GS_ERR_MISALIGNED
     assert srt(flag=ctypes.c_void_p(FAKE + 4)) == L.GS_ERR_MISALIGNED
     assert srt(ws=16) == L.GS_ERR_WORKSPACE

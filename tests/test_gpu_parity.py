@@ -77,17 +77,20 @@ def extra_pairs_harmless(orc, ref, rec, cam, v):
 def test_preprocess_tiny(R, orc):
     print_case("preprocess tiny 4096")
     sc, cam = S.tiny_scene()
-    splats, offsets, total = R.preprocess(gp(sc), cam)
+    splats, dkeys, didx, counts = R.preprocess(gp(sc), cam)
     torch.cuda.synchronize()
     rec = splats_np(splats, sc.n)
     ref = orc.preprocess(sc, cam)
     v = compare_records(orc, rec, ref, cam)
     extra_pairs_harmless(orc, ref, rec, cam, v)
-    cnt = np.where(rec["tx1"] >= rec["tx0"],
-                   (rec["tx1"].astype(np.int64) - rec["tx0"] + 1) * (rec["ty1"].astype(np.int64) - rec["ty0"] + 1), 0)
-    offs = u32(offsets[:sc.n])
-    np.testing.assert_array_equal(offs, np.concatenate([[0], np.cumsum(cnt)[:-1]]).astype(np.uint32))
-    assert int(u32(total)[0]) == cnt.sum()
+    vis = rec["tx1"] >= rec["tx0"]
+    cnt = np.where(vis, (rec["tx1"].astype(np.int64) - rec["tx0"] + 1) * (rec["ty1"].astype(np.int64) - rec["ty0"] + 1), 0)
+    c = u32(counts)
+    assert int(c[0]) == cnt.sum() and int(c[1]) == vis.sum()
+    # ordered compaction: visible Gaussians in index order with their depth bits
+    nv = int(c[1])
+    np.testing.assert_array_equal(u32(didx)[:nv], np.nonzero(vis)[0].astype(np.uint32))
+    np.testing.assert_array_equal(u32(dkeys)[:nv], rec["depth"][vis].view(np.uint32))
 
 
 @pytest.mark.parametrize("deg", [0, 1, 2, 3])
@@ -207,7 +210,7 @@ def expected_sorted_pairs(rec, tiles_x):
 def test_sort_keys_tiny(R, orc):
     print_case("gs_sort keys tiny")
     sc, cam = S.tiny_scene()
-    fr = R.forward(gp(sc), cam)
+    fr = R.forward(gp(sc), cam, want_keys=True)
     torch.cuda.synchronize()
     rec = splats_np(fr.splats, sc.n)
     n = fr.capacity
@@ -328,11 +331,14 @@ def test_capacity_overflow_flag(R):
     print_case("capacity overflow sets the flag")
     sc, cam = S.tiny_scene()
     p = gp(sc)
-    splats, offsets, total = R.preprocess(p, cam)
-    tot = int(u32(total)[0])
-    keys, values, ranges, flag, cap = R.sort(sc.n, splats, offsets, total, cam, capacity=tot // 2)
+    pre = R.preprocess(p, cam)
+    tot = int(u32(pre[3])[0])
+    keys, values, ranges, flag, cap = R.sort(sc.n, *pre, cam, capacity=tot // 2)
     torch.cuda.synchronize()
     assert int(u32(flag)[0]) & 1 == 1
-    keys, values, ranges, flag, cap = R.sort(sc.n, splats, offsets, total, cam, capacity=tot)
+    # the kept half is the front of the depth order: every range lies inside it
+    rng = u32(ranges).reshape(-1, 2)
+    assert rng[:, 1].max() <= tot // 2
+    keys, values, ranges, flag, cap = R.sort(sc.n, *pre, cam, capacity=tot)
     torch.cuda.synchronize()
     assert int(u32(flag)[0]) == 0
