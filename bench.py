@@ -21,10 +21,9 @@ if ROOT not in sys.path:
 METRIC = "frames/sec @1080p, 1M–6M Gaussians, fwd and fwd+bwd; sort Gkeys/s; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 
-SORT_KERNELS = ("sort_init", "depth_hist", "depth_pass", "keygen", "tile_hist", "tile_pass",
-                "tile_ranges")
-HBM_KERNELS = ("preprocess", "depth_pass", "keygen", "tile_pass", "tile_ranges", "depth_hist",
-               "tile_hist")
+SORT_KERNELS = ("sort_init", "radix_hist", "depth_pass", "kg_count", "kg_scan", "keygen",
+                "tile_pass", "tile_ranges")
+HBM_KERNELS = ("preprocess", "depth_pass", "keygen", "kg_count", "tile_pass", "tile_ranges")
 
 WORKLOADS = {
     "tiny": "tiny: 4,096 Gaussians, SH degree 0, 256x256, forward",
@@ -42,6 +41,7 @@ def parse():
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--radix-bits", type=int, default=8)
+    ap.add_argument("--sort-mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=2048)
     ap.add_argument("--verbose", action="store_true")
@@ -64,17 +64,16 @@ def make_workload(name):
 def algorithmic_bytes(n, n_vis, inst, K, W, H, tiles):
     """Bytes each kernel must move (reads + writes), per launch."""
     return {
-        # means 12 + log-scales 12 + quats 16 + logit 4 read, 48 B record written per
-        # Gaussian; SH 12K bytes read and (depth, index) 8 B written per visible one
-        "preprocess": n * (44 + 48) + n_vis * (12 * K + 8),
-        # depth keys read
-        "depth_hist": n_vis * 4,
-        # per depth pass: u32 key + u32 value read and written per visible Gaussian
-        "depth_pass": n_vis * 16,
-        # sorted index 4 + record tail 16 read per visible Gaussian; tile key 4 + value 4
-        # written per instance
+        # means 12 + log-scales 12 + quats 16 + logit 4 read, 48 B record + 4 B depth key
+        # written per Gaussian; SH 12K bytes read per visible one
+        "preprocess": n * (44 + 52) + n_vis * 12 * K,
+        # per depth pass: u32 key + u32 value read and written per Gaussian (upsweep,
+        # scan and downsweep together)
+        "depth_pass": n * 16,
+        # sorted index 4 + record tail 16 read per visible Gaussian
+        "kg_count": n_vis * 20,
+        # the same reads again; tile key 4 + value 4 written per instance
         "keygen": n_vis * 20 + inst * 8,
-        "tile_hist": inst * 4,
         # per tile pass: u32 key + u32 value read and written per instance
         "tile_pass": inst * 16,
         # sorted tile keys read, two u32 per tile written
@@ -97,7 +96,7 @@ def main():
 
     tw, th = map(int, args.tile.split("x"))
     sc, cam = make_workload(args.workload)
-    R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=args.radix_bits))
+    R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=args.radix_bits, sort_mode=args.sort_mode))
     p = GaussianParams.from_scene(sc)
     backward = args.workload == "diff"
     H, W = cam.height, cam.width

@@ -74,6 +74,10 @@ typedef struct gs_camera {
  *                    times the half-FoV tangent
  *   bg         (0,0,0) background colour; output alpha is 1 - T_final
  *   radix_bits 8     digit width of the radix sort (6, 7 or 8)
+ *   sort_mode  0     0: reduce-then-scan radix passes (count, scan, scatter
+ *                    kernels; no workgroup waits on another); 1: onesweep
+ *                    passes with decoupled look-back between workgroups.
+ *                    Both give the same (unique) stable result.
  */
 typedef struct gs_settings {
   int32_t tile_w, tile_h;
@@ -84,7 +88,7 @@ typedef struct gs_settings {
   float clip;
   float bg[3];
   int32_t radix_bits;
-  int32_t reserved;
+  int32_t sort_mode;
 } gs_settings;
 
 /*
@@ -137,7 +141,8 @@ int32_t gs_trace_read(int32_t max_entries, char* labels, float* ms, int32_t* cou
 /*
  * Bytes of workspace a stage needs.  `n` is the number of Gaussians,
  * `capacity` the instance capacity (for the sort stages; for
- * GS_STAGE_SORT_PAIRS the number of pairs).  Returns 0 on invalid input.
+ * GS_STAGE_SORT_PAIRS the number of pairs).  Returns 0 on invalid input
+ * and for GS_STAGE_PREPROCESS, which needs none.
  */
 size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity,
                          const gs_camera* cam, const gs_settings* set);
@@ -165,28 +170,22 @@ int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set);
  *   view direction is taken in the asset's own frame (R^T d).
  * Outputs (device):
  *   splats[n]       one gs_splat per Gaussian (culled ones have an empty rect).
- *   depth_keys[n]   u32 float32 bits of the camera-space depth of each
- *                   visible Gaussian, compacted in Gaussian-index order
- *                   (Algorithm 1's `depths`; the first counts[1] entries are
- *                   meaningful).
- *   depth_index[n]  u32 Gaussian index of each compacted entry (`indices`).
+ *   depth_keys[n]   u32 depth sort key per Gaussian: the float32 bits of its
+ *                   camera-space depth (Algorithm 1's `depths`), or
+ *                   0xFFFFFFFF when culled, so culled Gaussians sort last.
  *   counts[2]       u32: counts[0] = (Gaussian, tile) instances in total,
  *                   counts[1] = visible Gaussians.
- * The compaction replaces Algorithm 1's atomic append with an ordered
- * (prefix-sum) one, so the later stable sort has one unique result.
  * Culled (record with an empty rect, zero tiles): camera depth <= znear,
  * opacity < alpha_min, non-finite values, zero quaternion, or a footprint
  * whose opacity-aware bounding box (where o*exp(-Q/2) >= alpha_min)
- * contains no pixel centre.
- * Workspace: gs_workspace_size(GS_STAGE_PREPROCESS, n, 0, ...).
+ * contains no pixel centre.  No workspace is needed.
  */
 int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales,
                       const float* quats, const float* opacity_logits,
                       const float* sh, int32_t sh_degree, const float* model,
                       const gs_camera* cam, const gs_settings* set,
-                      gs_splat* splats, uint32_t* depth_keys,
-                      uint32_t* depth_index, uint32_t* counts, void* workspace,
-                      size_t workspace_bytes, void* stream);
+                      gs_splat* splats, uint32_t* depth_keys, uint32_t* counts,
+                      void* stream);
 
 /*
  * gs_sort -- key generation and the per-frame GPU radix sort (Algorithm 1,
@@ -196,13 +195,13 @@ int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales,
  * in row-major order, sorted by a stable LSD radix sort: equal keys stay in
  * Gaussian-index order, so the permutation is unique.  Depth is camera-space
  * z, which orders like the paper's NDC z for z > 0.  The LSD passes over the
- * 32 depth bits run on the compacted visible Gaussians before they are
- * expanded into (Gaussian, tile) instances (every instance of a Gaussian
- * has the same depth, so the order is the same); the passes over the tile
- * bits run on the instances.
+ * 32 depth bits run on the Gaussians before they are expanded into
+ * (Gaussian, tile) instances (every instance of a Gaussian has the same
+ * depth, so the order is the same); the passes over the tile bits run on
+ * the instances.  Sorting all n depth keys keeps equal depths in index
+ * order, which replaces Algorithm 1's nondeterministic atomic append.
  *
- * Reads splats[n], depth_keys/depth_index and counts (device, from
- * gs_preprocess).  Writes values[capacity] (u32 Gaussian index per sorted
+ * Reads splats[n], depth_keys[n] and counts (device, from gs_preprocess).  Writes values[capacity] (u32 Gaussian index per sorted
  * instance), tile_ranges[2*tiles] (u32 [start, end) of each tile in the
  * sorted list, tiles = ceil(W/tile_w) * ceil(H/tile_h), row-major) and, if
  * `keys` is not NULL, keys[capacity] (the sorted u64 keys above).  Only the
@@ -215,8 +214,8 @@ int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales,
  * Workspace: gs_workspace_size(GS_STAGE_SORT, n, capacity, cam, set).
  */
 int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
-                const uint32_t* depth_index, const uint32_t* counts,
-                const gs_camera* cam, const gs_settings* set, int64_t capacity,
+                const uint32_t* counts, const gs_camera* cam,
+                const gs_settings* set, int64_t capacity,
                 uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
                 uint32_t* status_flag, void* workspace, size_t workspace_bytes,
                 void* stream);

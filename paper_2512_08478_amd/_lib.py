@@ -57,7 +57,7 @@ class GsSettings(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("eps2d", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_eps", ctypes.c_float), ("clip", ctypes.c_float), ("bg", ctypes.c_float * 3),
-                ("radix_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("radix_bits", ctypes.c_int32), ("sort_mode", ctypes.c_int32)]
 
 
 _lib = None
@@ -87,9 +87,9 @@ def load():
     lib.gs_sort_key_bits.restype = I32
     lib.gs_sort_key_bits.argtypes = [CAM, SET]
     lib.gs_preprocess.restype = I32
-    lib.gs_preprocess.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, P, SZ, P]
+    lib.gs_preprocess.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P]
     lib.gs_sort.restype = I32
-    lib.gs_sort.argtypes = [I64, P, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ, P]
+    lib.gs_sort.argtypes = [I64, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ, P]
     lib.gs_sort_pairs.restype = I32
     lib.gs_sort_pairs.argtypes = [I64, P, P, I32, P, P, SET, P, SZ, P]
     lib.gs_rasterize.restype = I32

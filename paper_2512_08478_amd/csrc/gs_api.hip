@@ -54,6 +54,7 @@ int32_t check_settings(const gs_settings* s) {
   if (!s) return GS_ERR_INVALID_ARGUMENT;
   if (!gs::tile_shape_supported(s->tile_w, s->tile_h)) return GS_ERR_UNSUPPORTED;
   if (s->radix_bits < 6 || s->radix_bits > 8) return GS_ERR_UNSUPPORTED;
+  if (s->sort_mode != 0 && s->sort_mode != 1) return GS_ERR_UNSUPPORTED;
   if (!(s->eps2d >= 0.f) || !std::isfinite(s->eps2d)) return GS_ERR_INVALID_ARGUMENT;
   if (!(s->alpha_min > 0.f) || !(s->alpha_max > s->alpha_min) || !(s->alpha_max < 1.f))
     return GS_ERR_INVALID_ARGUMENT;
@@ -242,6 +243,7 @@ void gs_default_settings(gs_settings* s) {
   s->t_eps = 1e-4f;
   s->clip = 1.3f;
   s->radix_bits = 8;
+  s->sort_mode = 0;
 }
 
 int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set) {
@@ -254,8 +256,7 @@ size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity, const gs_ca
   if (n < 0 || capacity < 0) return 0;
   switch (stage) {
     case GS_STAGE_PREPROCESS:
-      if (n >= kMaxN) return 0;
-      return gs::pre_layout(n).bytes;
+      return 0;
     case GS_STAGE_SORT:
       if (check_settings(set) || check_camera(cam, set) || capacity > kMaxInstances || n >= kMaxN)
         return 0;
@@ -273,47 +274,39 @@ size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity, const gs_ca
 int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales, const float* quats,
                       const float* opacity_logits, const float* sh, int32_t sh_degree,
                       const float* model, const gs_camera* cam, const gs_settings* set,
-                      gs_splat* splats, uint32_t* depth_keys, uint32_t* depth_index,
-                      uint32_t* counts, void* workspace, size_t workspace_bytes, void* stream) {
+                      gs_splat* splats, uint32_t* depth_keys, uint32_t* counts, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
   if ((r = check_dev(counts))) return r;
-  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)) || (r = check_dev(depth_index))))
-    return r;
-  const gs::PreLayout L = gs::pre_layout(n);
-  if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
-  if ((r = check_dev(workspace))) return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)))) return r;
   gs::CamK ck;
   if ((r = make_camk(cam, set, model, &ck))) return r;
   const gs::SetK sk = make_setk(cam, set);
   hipStream_t st = static_cast<hipStream_t>(stream);
   gs::trace_mark(st, "preprocess_init");
   hipError_t e = gs::launch_preprocess((int)n, means, log_scales, quats, opacity_logits, sh,
-                                       sh_degree, ck, sk, splats, depth_keys, depth_index, counts,
-                                       workspace, L, st);
+                                       sh_degree, ck, sk, splats, depth_keys, counts, st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;
 }
 
 int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
-                const uint32_t* depth_index, const uint32_t* counts, const gs_camera* cam,
-                const gs_settings* set, int64_t capacity, uint64_t* keys, uint32_t* values,
-                uint32_t* tile_ranges, uint32_t* status_flag, void* workspace,
-                size_t workspace_bytes, void* stream) {
+                const uint32_t* counts, const gs_camera* cam, const gs_settings* set,
+                int64_t capacity, uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
+                uint32_t* status_flag, void* workspace, size_t workspace_bytes, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if (n < 0 || n >= kMaxN || capacity < 0 || capacity > kMaxInstances) return GS_ERR_INVALID_ARGUMENT;
   if ((r = check_dev(counts)) || (r = check_dev(tile_ranges))) return r;
-  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)) || (r = check_dev(depth_index))))
-    return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)))) return r;
   if (capacity > 0 && (r = check_dev(values))) return r;
   if ((r = check_dev(keys, false)) || (r = check_dev(status_flag, false))) return r;
   const gs::SortLayout L = gs::sort_layout(n, capacity);
   if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
   if ((r = check_dev(workspace))) return r;
-  const int bits = set->radix_bits;
+  const int bits = set->radix_bits, mode = set->sort_mode;
   const int tile_bits = key_bits_of(cam, set) - 32;
   const int pd = (32 + bits - 1) / bits;
   const int pt = tile_bits > 0 ? (tile_bits + bits - 1) / bits : 1;
@@ -322,35 +315,40 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   hipStream_t st = static_cast<hipStream_t>(stream);
   auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
   uint32_t* count = U(L.count);
-  uint32_t* hist = U(L.hist);
-  uint32_t* tickets = U(L.tickets);
-  uint32_t* lookback = U(L.lookback);
   gs::trace_mark(st, "sort_init");
-  hipError_t e = gs::launch_sort_init(L, ws, tile_ranges, tiles, status_flag, counts, capacity, st);
+  hipError_t e = gs::launch_sort_init(L, ws, mode, tile_ranges, tiles, status_flag, counts,
+                                      capacity, st);
   if (e != hipSuccess) return hip_fail(e);
   if (n == 0 || capacity == 0) {
     gs::trace_mark(st, "");
     return GS_OK;
   }
-  // depth passes over the visible Gaussians (count = counts[1])
-  gs::trace_mark(st, "depth_hist");
-  e = gs::launch_histogram<uint32_t>(depth_keys, counts + 1, n, bits, pd, hist, st);
+  // depth digits over all n Gaussians (culled ones carry the largest key)
+  gs::RadixArgs<uint32_t> d{};
+  d.mode = mode;
+  d.n_grid = n;
+  d.count = nullptr;
+  d.kin = depth_keys;
+  d.vin = nullptr;
+  d.k_alt = U(L.dk[1]); d.v_alt = U(L.dv[1]);
+  d.k_out = U(L.dk[0]); d.v_out = U(L.dv[0]);
+  d.table = U(L.table); d.totals = U(L.totals);
+  d.hist = U(L.hist); d.tickets = U(L.tickets); d.lookback = U(L.lookback); d.lb_parts = L.parts;
+  e = gs::launch_radix_sort<uint32_t>(d, bits, pd, 0, false, "depth_pass", st);
   if (e != hipSuccess) return hip_fail(e);
-  e = gs::launch_radix_passes<uint32_t>(n, counts + 1, bits, pd, 0, depth_keys, depth_index,
-                                        U(L.dk[1]), U(L.dv[1]), U(L.dk[0]), U(L.dv[0]), false,
-                                        hist, tickets, lookback, L.parts, "depth_pass", st);
+  // instances of the visible Gaussians in depth order, then the tile digits
+  e = gs::launch_keygen(n, U(L.dv[0]), counts + 1, splats, tiles_x, count, U(L.kg_counts),
+                        U(L.totals), U(L.tk[0]), U(L.tv[0]), st);
   if (e != hipSuccess) return hip_fail(e);
-  // instances in depth order, then the tile passes
-  gs::trace_mark(st, "keygen");
-  e = gs::launch_keygen(n, U(L.dv[0]), counts + 1, splats, tiles_x, count, U(L.tk[0]), U(L.tv[0]),
-                        reinterpret_cast<uint64_t*>(ws + L.kg_status), tickets + pd + pt, st);
-  if (e != hipSuccess) return hip_fail(e);
-  gs::trace_mark(st, "tile_hist");
-  e = gs::launch_histogram<uint32_t>(U(L.tk[0]), count, capacity, bits, pt, hist + pd * 256, st);
-  if (e != hipSuccess) return hip_fail(e);
-  e = gs::launch_radix_passes<uint32_t>(capacity, count, bits, pt, pd, U(L.tk[0]), U(L.tv[0]),
-                                        U(L.tk[1]), U(L.tv[1]), U(L.tkf), values, true,
-                                        hist + pd * 256, tickets, lookback, L.parts, "tile_pass", st);
+  gs::RadixArgs<uint32_t> t = d;
+  t.n_grid = capacity;
+  t.count = count;
+  t.kin = U(L.tk[0]);
+  t.vin = U(L.tv[0]);
+  t.k_alt = U(L.tk[1]); t.v_alt = U(L.tv[1]);
+  t.k_out = U(L.tkf); t.v_out = values;
+  t.hist = U(L.hist) + pd * 256;
+  e = gs::launch_radix_sort<uint32_t>(t, bits, pt, pd, true, "tile_pass", st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "tile_ranges");
   e = gs::launch_tile_ranges(capacity, count, U(L.tkf), tile_ranges, st);
@@ -386,20 +384,23 @@ int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in, const uint32_t* values
   const int passes = (key_bits + bits - 1) / bits;
   char* ws = static_cast<char*>(workspace);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
   gs::trace_mark(st, "sort_init");
-  hipError_t e = gs::launch_sort_init(L, ws, nullptr, 0, nullptr, nullptr, n, st);
+  hipError_t e = gs::launch_sort_init(L, ws, set->sort_mode, nullptr, 0, nullptr, nullptr, n, st);
   if (e != hipSuccess) return hip_fail(e);
-  gs::trace_mark(st, "histogram");
-  e = gs::launch_histogram<uint64_t>(keys_in, nullptr, n, bits, passes, hist, st);
-  if (e != hipSuccess) return hip_fail(e);
-  e = gs::launch_radix_passes<uint64_t>(n, nullptr, bits, passes, 0, keys_in, values_in,
-                                        reinterpret_cast<uint64_t*>(ws + L.dk[0]),
-                                        reinterpret_cast<uint32_t*>(ws + L.dv[0]), keys_out,
-                                        values_out, true, hist,
-                                        reinterpret_cast<uint32_t*>(ws + L.tickets),
-                                        reinterpret_cast<uint32_t*>(ws + L.lookback), L.parts,
-                                        "radix_pass", st);
+  gs::RadixArgs<uint64_t> a{};
+  a.mode = set->sort_mode;
+  a.n_grid = n;
+  a.count = nullptr;
+  a.kin = keys_in;
+  a.vin = values_in;
+  a.k_alt = reinterpret_cast<uint64_t*>(ws + L.dk[0]);
+  a.v_alt = U(L.dv[0]);
+  a.k_out = keys_out;
+  a.v_out = values_out;
+  a.table = U(L.table); a.totals = U(L.totals);
+  a.hist = U(L.hist); a.tickets = U(L.tickets); a.lookback = U(L.lookback); a.lb_parts = L.parts;
+  e = gs::launch_radix_sort<uint64_t>(a, bits, passes, 0, true, "radix_pass", st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;

@@ -89,46 +89,3 @@ __device__ __forceinline__ float det2(float a, float b, float c, float d) {
 }
 
 }  // namespace gs
-
-namespace gs {
-
-// Decoupled look-back over 64-bit status words (flag in bits 32..33, value
-// in bits 0..31), for one partition, executed by one whole wave.  Publishes
-// `agg` for `part`, walks back over earlier partitions 64 at a time until it
-// meets one whose inclusive prefix is published, publishes its own
-// inclusive prefix and returns the exclusive prefix (the sum of the
-// aggregates of partitions 0..part-1).  Every earlier partition must already
-// be running (partition indices come from an atomic ticket) and publishes
-// its aggregate without waiting, so the walk always ends.
-constexpr uint64_t kStatAgg = 1ull << 32;
-constexpr uint64_t kStatInc = 2ull << 32;
-
-__device__ __forceinline__ uint32_t wave_lookback(uint64_t* status, int part, uint32_t agg) {
-  const int lane = lane_id();
-  if (part == 0) {
-    if (lane == 0) st_agent64(&status[0], kStatInc | agg);
-    return 0u;
-  }
-  if (lane == 0) st_agent64(&status[part], kStatAgg | agg);
-  uint32_t excl = 0;
-  int j = part - 1;
-  while (true) {
-    const int idx = j - lane;
-    uint64_t s = idx >= 0 ? ld_agent64(&status[idx]) : kStatInc;
-    while (ballot((s >> 32) == 0) != 0ull) {
-      if ((s >> 32) == 0) s = ld_agent64(&status[idx]);
-    }
-    const uint64_t inc = ballot((s >> 32) == 2);
-    if (inc) {
-      const int first = __builtin_ctzll(inc);
-      excl += wave_sum_u32(lane <= first ? (uint32_t)s : 0u);
-      break;
-    }
-    excl += wave_sum_u32((uint32_t)s);
-    j -= 64;
-  }
-  if (lane == 0) st_agent64(&status[part], kStatInc | (uint64_t)(excl + agg));
-  return excl;
-}
-
-}  // namespace gs

@@ -42,44 +42,53 @@ struct SetK {
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // gs_sort workspace: depth ping-pong (u32 keys/values, n each), tile
-// ping-pong and final tile keys (u32, capacity each), histograms, tickets,
-// look-back words (two buffers), keygen status words, instance count.
+// ping-pong and final tile keys (u32, capacity each), onesweep histograms,
+// tickets and look-back words (two buffers), the reduce-then-scan count
+// table and digit totals, keygen slice counts, the kept instance count.
 struct SortLayout {
-  size_t dk[2], dv[2], tk[2], tv[2], tkf, hist, tickets, lookback, kg_status, count;
+  size_t dk[2], dv[2], tk[2], tv[2], tkf, hist, tickets, lookback, table, totals, kg_counts, count;
   size_t bytes;
-  int parts;     // look-back partitions per buffer
-  int kg_parts;  // keygen partitions
+  int parts;     // 4096-key partitions of the largest sort
+  int kg_parts;  // keygen slices
 };
 SortLayout sort_layout(int64_t n, int64_t capacity);
 SortLayout pairs_layout(int64_t n);  // gs_sort_pairs: dk[0]/dv[0] are the u64/u32 alternates
 
-struct PreLayout {
-  size_t status, ticket, bytes;
-  int parts;
+// One stable LSD radix sort of (key, value) pairs.
+template <typename KeyT>
+struct RadixArgs {
+  int mode;                 // 0 reduce-then-scan, 1 onesweep (decoupled look-back)
+  int64_t n_grid;           // upper bound of n: sizes the grids
+  const uint32_t* count;    // device n (NULL: n = n_grid)
+  const KeyT* kin;          // input keys (not modified)
+  const uint32_t* vin;      // input values (NULL: value = position)
+  KeyT* k_alt;              // ping-pong buffers
+  uint32_t* v_alt;
+  KeyT* k_out;              // the result
+  uint32_t* v_out;
+  uint32_t* table;          // mode 0: 256 x partitions counts
+  uint32_t* totals;         // mode 0: 256 digit totals
+  uint32_t* hist;           // mode 1: 256 bins per pass
+  uint32_t* tickets;        // mode 1: one per pass
+  uint32_t* lookback;       // mode 1: two buffers of lb_parts x 256 words
+  int lb_parts;
 };
-PreLayout pre_layout(int64_t n);
 
 // Launchers (enqueue only; return the first launch error).
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
-                             gs_splat* splats, uint32_t* depth_keys, uint32_t* depth_index,
-                             uint32_t* counts, void* ws, const PreLayout& L, hipStream_t st);
-hipError_t launch_sort_init(const SortLayout& L, char* ws, uint32_t* tile_ranges, int tiles,
-                            uint32_t* status_flag, const uint32_t* total_src, int64_t capacity,
-                            hipStream_t st);
+                             gs_splat* splats, uint32_t* depth_keys, uint32_t* counts,
+                             hipStream_t st);
+hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
+                            int tiles, uint32_t* status_flag, const uint32_t* total_src,
+                            int64_t capacity, hipStream_t st);
 template <typename KeyT>
-hipError_t launch_histogram(const KeyT* keys, const uint32_t* count, int64_t n_grid, int bits,
-                            int passes, uint32_t* hist, hipStream_t st);
-template <typename KeyT>
-hipError_t launch_radix_passes(int64_t n_grid, const uint32_t* count, int bits, int passes,
-                               int pass_base, const KeyT* kin, const uint32_t* vin, KeyT* k_alt,
-                               uint32_t* v_alt, KeyT* k_out, uint32_t* v_out, bool last_keys,
-                               uint32_t* hist, uint32_t* tickets, uint32_t* lookback, int lb_parts,
-                               const char* label, hipStream_t st);
+hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int pass_base,
+                             bool last_keys, const char* label, hipStream_t st);
 hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* vis_count,
                          const gs_splat* splats, int tiles_x, const uint32_t* inst_count,
-                         uint32_t* tkeys, uint32_t* tvals, uint64_t* status, uint32_t* ticket,
+                         uint32_t* kg_counts, uint32_t* kg_total, uint32_t* tkeys, uint32_t* tvals,
                          hipStream_t st);
 hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
                               uint32_t* ranges, hipStream_t st);

@@ -216,68 +216,45 @@ __device__ __forceinline__ uint32_t project_one(
   return tiles;
 }
 
-__global__ __launch_bounds__(kBlock) void k_preprocess_init(uint64_t* status, int parts,
-                                                            uint32_t* ticket, uint32_t* counts) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < parts) status[i] = 0;
-  if (i == 0) {
-    *ticket = 0;
-    counts[0] = 0;
-    counts[1] = 0;
-  }
+__global__ __launch_bounds__(64) void k_preprocess_init(uint32_t* counts) {
+  if (threadIdx.x < 2) counts[threadIdx.x] = 0;
 }
 
-// Per-Gaussian record, plus the ordered compaction of the visible Gaussians
-// that replaces Algorithm 1's atomic append: each workgroup (256 Gaussians,
-// taken in ticket order) ranks its visible Gaussians with a ballot, gets the
-// count of visible Gaussians before it by decoupled look-back, and writes
-// (float32 depth bits, index) at its position.  Visible Gaussians therefore
-// appear in index order, which keeps the later stable sort's result unique.
+// Record of Gaussian i, its depth sort key (float32 bits of the camera-space
+// depth; the largest key when culled, so culled Gaussians sort last) and,
+// per workgroup, two integer atomics for the instance and visible counts
+// (sums, so their order does not matter).
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_preprocess(
     int n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float4* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, CamK cam, SetK set, gs_splat* __restrict__ splats,
-    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ depth_index,
-    uint32_t* __restrict__ counts, uint64_t* __restrict__ status, uint32_t* __restrict__ ticket) {
-  __shared__ uint32_t s_part, s_prefix;
+    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ counts) {
   __shared__ uint32_t s_vis[kBlock / 64], s_til[kBlock / 64];
-  if (threadIdx.x == 0) s_part = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const int part = (int)s_part;
-  const int i = part * kBlock + threadIdx.x;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
   uint32_t tiles = 0;
-  float tz = 0.f;
-  if (i < n) tiles = project_one<DEG>(i, means, log_scales, quats, logits, sh, cam, set, splats, &tz);
-  const bool visible = tiles > 0;
+  if (i < n) {
+    float tz = 0.f;
+    tiles = project_one<DEG>(i, means, log_scales, quats, logits, sh, cam, set, splats, &tz);
+    depth_keys[i] = tiles ? __float_as_uint(tz) : 0xFFFFFFFFu;
+  }
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const uint64_t vm = ballot(visible);
-  const uint32_t wsum_tiles = wave_sum_u32(tiles);
+  const uint32_t wv = (uint32_t)__builtin_popcountll(ballot(tiles > 0));
+  const uint32_t wt = wave_sum_u32(tiles);
   if (lane == 0) {
-    s_vis[wave] = (uint32_t)__builtin_popcountll(vm);
-    s_til[wave] = wsum_tiles;
+    s_vis[wave] = wv;
+    s_til[wave] = wt;
   }
   __syncthreads();
-  uint32_t woff = 0, bvis = 0, btiles = 0;
+  if (threadIdx.x == 0) {
+    uint32_t bv = 0, bt = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) {
-    woff += w < wave ? s_vis[w] : 0u;
-    bvis += s_vis[w];
-    btiles += s_til[w];
-  }
-  if (wave == 0) {
-    const uint32_t pre = wave_lookback(status, part, bvis);
-    if (lane == 0) {
-      s_prefix = pre;
-      if (btiles) atomicAdd(&counts[0], btiles);
-      if (bvis) atomicAdd(&counts[1], bvis);
+    for (int w = 0; w < kBlock / 64; ++w) {
+      bv += s_vis[w];
+      bt += s_til[w];
     }
-  }
-  __syncthreads();
-  if (visible) {
-    const uint32_t pos = s_prefix + woff + (uint32_t)__builtin_popcountll(vm & lanemask_lt());
-    depth_keys[pos] = __float_as_uint(tz);
-    depth_index[pos] = (uint32_t)i;
+    if (bt) atomicAdd(&counts[0], bt);
+    if (bv) atomicAdd(&counts[1], bv);
   }
 }
 
@@ -548,31 +525,17 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(
 
 }  // namespace
 
-PreLayout pre_layout(int64_t n) {
-  PreLayout L;
-  L.parts = (int)((n + kBlock - 1) / kBlock);
-  L.status = 0;
-  L.ticket = align_up((size_t)(L.parts > 0 ? L.parts : 1) * 8, 256);
-  L.bytes = L.ticket + 256;
-  return L;
-}
-
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
-                             gs_splat* splats, uint32_t* depth_keys, uint32_t* depth_index,
-                             uint32_t* counts, void* ws, const PreLayout& L, hipStream_t st) {
-  char* w = static_cast<char*>(ws);
-  uint64_t* status = reinterpret_cast<uint64_t*>(w + L.status);
-  uint32_t* ticket = reinterpret_cast<uint32_t*>(w + L.ticket);
-  const int init_blocks = L.parts > 0 ? (L.parts + kBlock - 1) / kBlock : 1;
-  hipLaunchKernelGGL(k_preprocess_init, dim3(init_blocks), dim3(kBlock), 0, st, status, L.parts,
-                     ticket, counts);
+                             gs_splat* splats, uint32_t* depth_keys, uint32_t* counts,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_preprocess_init, dim3(1), dim3(64), 0, st, counts);
   if (n == 0) return hipGetLastError();
   trace_mark(st, "preprocess");
-  const dim3 grid(L.parts), block(kBlock);
+  const dim3 grid((n + kBlock - 1) / kBlock), block(kBlock);
   const float4* q4 = reinterpret_cast<const float4*>(quats);
-#define GS_PRE(D) hipLaunchKernelGGL(k_preprocess<D>, grid, block, 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, depth_keys, depth_index, counts, status, ticket)
+#define GS_PRE(D) hipLaunchKernelGGL(k_preprocess<D>, grid, block, 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, depth_keys, counts)
   switch (degree) {
     case 0: GS_PRE(0); break;
     case 1: GS_PRE(1); break;

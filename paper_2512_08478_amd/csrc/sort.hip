@@ -6,21 +6,27 @@
 // digits and its last passes on the tile digits.  Every (Gaussian, tile)
 // instance of one Gaussian carries the same depth, so the depth passes give
 // the same order whether they run before or after a Gaussian is expanded
-// into its tiles: they run on the visible Gaussians (u32 depth keys), the
-// instances are generated in that depth order (u32 tile keys), and the tile
-// passes finish the sort.  The permutation is identical to sorting the
-// 64-bit keys of the Gaussian-major instance list, with far fewer bytes.
+// into its tiles: they run on the Gaussians (u32 depth keys; culled ones
+// carry the largest key and sort last), the instances are generated in that
+// depth order (u32 tile keys), and the tile passes finish the sort.  The
+// permutation is identical to sorting the 64-bit keys of the Gaussian-major
+// instance list, with far fewer bytes moved.
 //
-// Each radix pass is onesweep-style: one digit histogram up front, then one
-// kernel per digit in which a workgroup
-//   1. takes a 4096-key partition by atomic ticket (every partition it waits
-//      on has already started),
-//   2. ranks the keys of each wave with ballot-based digit matching (one
-//      ballot per digit bit; equal digits keep index order: stable),
-//   3. publishes its per-digit counts and looks back over earlier
-//      partitions, eight status words in flight per digit,
-//   4. stages keys in LDS in sorted order and writes them out, so that
-//      consecutive threads write consecutive addresses of one digit run.
+// A radix pass ranks the keys of each 4096-key partition in LDS: every wave
+// ranks 64 keys at a time by ballot-based digit matching (one ballot per
+// digit bit; equal digits keep index order, so the sort is stable), waves
+// are stacked by per-wave digit counts, and the keys are staged in LDS in
+// sorted order so that consecutive threads write consecutive addresses of
+// one digit run.  The partition's global offsets per digit come from one of
+// two schemes (gs_settings.sort_mode):
+//   0  reduce-then-scan: an upsweep kernel writes every partition's digit
+//      counts, a scan kernel turns them into per-partition offsets, and the
+//      downsweep scatters.  No workgroup waits on another.
+//   1  onesweep: one histogram up front, then a single kernel per digit that
+//      publishes its counts and looks back over earlier partitions (eight
+//      status words in flight per digit) with agent-scope atomics.  On an
+//      8-XCD part every look-back round trip leaves the XCD's L2, so the
+//      inclusive-prefix frontier advances one window per round trip.
 // Counts are read from device memory, so no host round trip is needed.
 #include "gs_device.h"
 #include "gs_internal.h"
@@ -30,11 +36,12 @@ namespace {
 
 constexpr int kHistMax = 2048;     // LDS histogram bins (passes x 2^bits)
 constexpr int kLbWindow = 8;       // look-back status words in flight per digit
+constexpr int kKgItems = 4;        // sorted Gaussians per thread in the keygen
+constexpr int kKgPart = kBlock * kKgItems;
 
 __global__ __launch_bounds__(kBlock) void k_sort_init(uint32_t* hist, int hist_len,
                                                       uint32_t* tickets, int ntickets,
                                                       uint32_t* lookback, int lb_len,
-                                                      uint64_t* kg_status, int kg_len,
                                                       uint32_t* ranges, int ranges_len,
                                                       uint32_t* count, const uint32_t* total_src,
                                                       uint32_t host_total, int64_t capacity,
@@ -43,7 +50,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_init(uint32_t* hist, int hist_l
   const int i0 = blockIdx.x * kBlock + threadIdx.x;
   for (int i = i0; i < lb_len; i += stride) lookback[i] = 0;
   for (int i = i0; i < ranges_len; i += stride) ranges[i] = 0;
-  for (int i = i0; i < kg_len; i += stride) kg_status[i] = 0;
   for (int i = i0; i < hist_len; i += stride) hist[i] = 0;
   if (i0 < ntickets) tickets[i0] = 0;
   if (i0 == 0) {
@@ -69,8 +75,91 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t d, bool vali
   if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__builtin_popcountll(peers));
 }
 
-// Digit histograms of `passes` digits of keys[0, n); global layout is 256
-// bins per pass.  n comes from *count when count != NULL.
+__device__ __forceinline__ uint32_t read_n(const uint32_t* count, int64_t n_host) {
+  return count ? *count : (uint32_t)n_host;
+}
+
+// Block-wide exclusive scan of one u32 per thread (256 threads).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan(v);
+  if (lane == 63) s_tmp[wave] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    off += w < wave ? s_tmp[w] : 0u;
+    tot += s_tmp[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - v;
+}
+
+// ---------------------------------------------------------------- counting
+
+// Digit counts of one 4096-key partition per workgroup, written digit-major
+// into table[d * P + partition] (zeros past the end).
+template <typename KeyT, int BITS>
+__global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ kin,
+                                                       const uint32_t* __restrict__ count,
+                                                       int64_t n_host, int shift,
+                                                       uint32_t* __restrict__ table, int P) {
+  constexpr int NB = 1 << BITS;
+  __shared__ uint32_t s_h[NB];
+  const int t = threadIdx.x;
+  for (int d = t; d < NB; d += kBlock) s_h[d] = 0;
+  __syncthreads();
+  const uint32_t n = read_n(count, n_host);
+  const uint32_t base = blockIdx.x * kSortPart;
+  if (base < n) {
+    KeyT k[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const uint32_t idx = base + i * kBlock + t;
+      k[i] = idx < n ? kin[idx] : KeyT(0);
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+      wave_hist_add<BITS>(s_h, digit_of<KeyT, BITS>(k[i], shift), base + i * kBlock + t < n);
+  }
+  __syncthreads();
+  for (int d = t; d < NB; d += kBlock) table[(size_t)d * P + blockIdx.x] = s_h[d];
+}
+
+// Exclusive scan of each row of a rows x P table in place (one workgroup
+// per row); the row sums go to totals[row].
+__global__ __launch_bounds__(kBlock) void k_row_scan(uint32_t* __restrict__ table, int P,
+                                                     uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_tmp[kBlock / 64];
+  constexpr int IT = 16;
+  uint32_t* row = table + (size_t)blockIdx.x * P;
+  const int t = threadIdx.x;
+  uint32_t carry = 0;
+  for (int base = 0; base < P; base += kBlock * IT) {
+    uint32_t v[IT];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const int idx = base + t * IT + j;
+      v[j] = idx < P ? row[idx] : 0u;
+      s += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = carry + block_excl_scan(s, s_tmp, &tot);
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const int idx = base + t * IT + j;
+      if (idx < P) row[idx] = run;
+      run += v[j];
+    }
+    carry += tot;
+  }
+  if (t == 0) totals[blockIdx.x] = carry;
+}
+
+// Digit histograms of `passes` digits of keys[0, n) for the onesweep mode;
+// global layout is 256 bins per pass.
 template <typename KeyT, int BITS>
 __global__ __launch_bounds__(kBlock) void k_histogram(const KeyT* __restrict__ keys,
                                                       const uint32_t* __restrict__ count,
@@ -78,38 +167,47 @@ __global__ __launch_bounds__(kBlock) void k_histogram(const KeyT* __restrict__ k
                                                       uint32_t* __restrict__ hist) {
   constexpr int NB = 1 << BITS;
   __shared__ uint32_t s_hist[kHistMax];
-  for (int b = threadIdx.x; b < passes * NB; b += kBlock) s_hist[b] = 0;
+  const int t = threadIdx.x;
+  for (int b = t; b < passes * NB; b += kBlock) s_hist[b] = 0;
   __syncthreads();
-  const int64_t n = count ? (int64_t)*count : n_host;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    const bool valid = i < n;
-    const KeyT key = valid ? keys[i] : KeyT(0);
-    for (int p = 0; p < passes; ++p)
-      wave_hist_add<BITS>(s_hist + p * NB, digit_of<KeyT, BITS>(key, p * BITS), valid);
+  const uint32_t n = read_n(count, n_host);
+  for (uint32_t base = blockIdx.x * kSortPart; base < n; base += gridDim.x * kSortPart) {
+    KeyT k[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const uint32_t idx = base + i * kBlock + t;
+      k[i] = idx < n ? keys[idx] : KeyT(0);
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const bool valid = base + i * kBlock + t < n;
+      for (int p = 0; p < passes; ++p)
+        wave_hist_add<BITS>(s_hist + p * NB, digit_of<KeyT, BITS>(k[i], p * BITS), valid);
+    }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < passes * NB; b += kBlock) {
+  for (int b = t; b < passes * NB; b += kBlock) {
     const uint32_t v = s_hist[b];
     if (v) atomicAdd(&hist[(b / NB) * 256 + (b % NB)], v);
   }
 }
 
-// One radix pass.  kin/vin hold n pairs (n = *count); pairs are scattered to
-// kout/vout by the digit at `shift`.  WRITE_KEYS = false skips the key
-// stores of a last pass whose keys nobody reads.
-template <typename KeyT, int BITS, bool WRITE_KEYS>
-__global__ __launch_bounds__(kBlock) void k_onesweep(const KeyT* __restrict__ kin,
-                                                     const uint32_t* __restrict__ vin,
-                                                     KeyT* __restrict__ kout,
-                                                     uint32_t* __restrict__ vout,
-                                                     const uint32_t* __restrict__ count,
-                                                     int64_t n_host, int shift,
-                                                     const uint32_t* __restrict__ hist,
-                                                     uint32_t* __restrict__ ticket,
-                                                     uint32_t* __restrict__ lb,
-                                                     uint32_t* __restrict__ lb_next) {
+// ---------------------------------------------------------------- scatter
+
+// One radix pass.  kin/vin hold n pairs (vin == NULL: value = position);
+// pairs are scattered to kout/vout by the digit at `shift`.
+// LOOKBACK = false: partition = workgroup, offsets from the scanned table
+//   (table[d * P + part]) and the per-digit totals.
+// LOOKBACK = true: partition by ticket, `totals` is this pass's global digit
+//   histogram, offsets by decoupled look-back over lb.
+// WRITE_KEYS = false skips the key stores of a last pass whose keys nobody
+// reads.
+template <typename KeyT, int BITS, bool WRITE_KEYS, bool LOOKBACK>
+__global__ __launch_bounds__(kBlock) void k_radix_pass(
+    const KeyT* __restrict__ kin, const uint32_t* __restrict__ vin, KeyT* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ count, int64_t n_host, int shift,
+    const uint32_t* __restrict__ table, int P, const uint32_t* __restrict__ totals,
+    uint32_t* __restrict__ ticket, uint32_t* __restrict__ lb, uint32_t* __restrict__ lb_next) {
   constexpr int NB = 1 << BITS;
   constexpr int NW = kBlock / 64;
   __shared__ uint32_t s_whist[NW][NB];
@@ -121,14 +219,15 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const KeyT* __restrict__ ki
   __shared__ uint32_t s_part;
 
   const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-  if (t == 0) s_part = atomicAdd(ticket, 1u);
+  if (LOOKBACK && t == 0) s_part = atomicAdd(ticket, 1u);
   for (int b = t; b < NW * NB; b += kBlock) (&s_whist[0][0])[b] = 0;
   __syncthreads();
-  const uint32_t part = s_part;
-  const uint32_t n = count ? *count : (uint32_t)n_host;
+  const uint32_t part = LOOKBACK ? s_part : blockIdx.x;
+  const uint32_t n = read_n(count, n_host);
   const uint32_t base = part * kSortPart;
   if (base >= n) return;
-  for (int b = t; b < NB; b += kBlock) lb_next[part * NB + b] = 0;
+  if (LOOKBACK)
+    for (int b = t; b < NB; b += kBlock) lb_next[part * NB + b] = 0;
 
   // warp-striped load: wave w owns keys [w*64*ITEMS, (w+1)*64*ITEMS)
   KeyT k[kSortItems];
@@ -161,8 +260,8 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const KeyT* __restrict__ ki
       run += x;
     }
     tot = run;
-    gcount = hist[t];
-    st_agent(&lb[part * NB + t], (part == 0 ? kLbFlagInc : kLbFlagAgg) | tot);
+    gcount = totals[t];
+    if (LOOKBACK) st_agent(&lb[part * NB + t], (part == 0 ? kLbFlagInc : kLbFlagAgg) | tot);
   }
   const uint32_t inc_tot = wave_incl_scan(tot);
   const uint32_t inc_g = wave_incl_scan(gcount);
@@ -180,7 +279,9 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const KeyT* __restrict__ ki
     const uint32_t local = off_tot + inc_tot - tot;
     const uint32_t gstart = off_g + inc_g - gcount;
     uint32_t prefix = 0;
-    if (part > 0) {
+    if (!LOOKBACK) {
+      prefix = table[(size_t)t * P + part];
+    } else if (part > 0) {
       int j = (int)part - 1;
       while (true) {
         uint32_t s[kLbWindow];
@@ -228,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const KeyT* __restrict__ ki
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
     const uint32_t idx = wbase + i * 64;
-    s_vals[pos[i]] = idx < n ? vin[idx] : 0u;
+    s_vals[pos[i]] = idx < n ? (vin ? vin[idx] : idx) : 0u;
   }
   __syncthreads();
   for (int j = t; j < kSortPart; j += kBlock) {
@@ -237,63 +338,87 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const KeyT* __restrict__ ki
   }
 }
 
-// Instances in depth order.  Workgroup `part` (ticket order) takes 256
-// Gaussians of the depth-sorted visible list, counts their tiles, gets the
-// number of instances before it by decoupled look-back, and writes
-// (tile id, Gaussian index) for each tile of each rect in row-major order;
-// the expansion is spread over the workgroup with a binary search over the
-// local offsets, so a large splat does not serialise one thread.
-__global__ __launch_bounds__(kBlock) void k_keygen(const uint32_t* __restrict__ sorted_idx,
-                                                   const uint32_t* __restrict__ vis_count,
-                                                   const gs_splat* __restrict__ splats, int tiles_x,
-                                                   const uint32_t* __restrict__ inst_count,
-                                                   uint32_t* __restrict__ tkeys,
-                                                   uint32_t* __restrict__ tvals,
-                                                   uint64_t* __restrict__ status,
-                                                   uint32_t* __restrict__ ticket) {
-  __shared__ uint32_t s_part, s_prefix;
-  __shared__ uint32_t s_off[kBlock + 1];
-  __shared__ uint32_t s_lo[kBlock], s_hi[kBlock], s_g[kBlock];
-  __shared__ uint32_t s_wave[kBlock / 64];
-  const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-  if (t == 0) s_part = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const uint32_t part = s_part, nvis = *vis_count, cap = *inst_count;
-  const uint32_t base = part * kBlock;
-  if (base >= nvis) return;
-  const uint32_t j = base + t;
-  uint32_t cnt = 0, g = 0, lo = 0, hi = 0;
-  if (j < nvis) {
-    g = sorted_idx[j];
-    const float4 r2 = reinterpret_cast<const float4*>(splats + g)[2];
-    lo = __float_as_uint(r2.z);
-    hi = __float_as_uint(r2.w);
-    cnt = ((hi & 0xFFFFu) - (lo & 0xFFFFu) + 1) * ((hi >> 16) - (lo >> 16) + 1);
-  }
-  s_g[t] = g;
-  s_lo[t] = lo;
-  s_hi[t] = hi;
-  const uint32_t incl = wave_incl_scan(cnt);
-  if (lane == 63) s_wave[wave] = incl;
-  __syncthreads();
-  uint32_t woff = 0, btot = 0;
+// ---------------------------------------------------------------- keygen
+
+__device__ __forceinline__ uint32_t rect_tiles(uint32_t lo, uint32_t hi) {
+  return ((hi & 0xFFFFu) - (lo & 0xFFFFu) + 1) * ((hi >> 16) - (lo >> 16) + 1);
+}
+
+// Tiles touched by each 1024-Gaussian slice of the depth-sorted visible list.
+__global__ __launch_bounds__(kBlock) void k_kg_count(const uint32_t* __restrict__ sorted_idx,
+                                                     const uint32_t* __restrict__ vis_count,
+                                                     const gs_splat* __restrict__ splats,
+                                                     uint32_t* __restrict__ kg_counts) {
+  __shared__ uint32_t s_tmp[kBlock / 64];
+  const uint32_t nvis = *vis_count;
+  const uint32_t base = blockIdx.x * kKgPart;
+  uint32_t sum = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) {
-    woff += w < wave ? s_wave[w] : 0u;
-    btot += s_wave[w];
+  for (int j = 0; j < kKgItems; ++j) {
+    const uint32_t p = base + j * kBlock + threadIdx.x;
+    if (p < nvis) {
+      const float4 r2 = reinterpret_cast<const float4*>(splats + sorted_idx[p])[2];
+      sum += rect_tiles(__float_as_uint(r2.z), __float_as_uint(r2.w));
+    }
   }
-  s_off[t] = woff + incl - cnt;
-  if (t == kBlock - 1) s_off[kBlock] = btot;
-  if (wave == 0) {
-    const uint32_t pre = wave_lookback(status, (int)part, btot);
-    if (lane == 0) s_prefix = pre;
+  uint32_t tot;
+  block_excl_scan(sum, s_tmp, &tot);
+  if (threadIdx.x == 0) kg_counts[blockIdx.x] = tot;
+}
+
+// Instances in depth order: slice p of the depth-sorted visible list starts
+// at kg_prefix[p] (scanned slice counts) and writes (tile id, Gaussian
+// index) for each tile of each rect in row-major order.  The expansion is
+// spread over the workgroup with a binary search over local offsets, so a
+// large splat does not serialise one thread.
+__global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict__ sorted_idx,
+                                                     const uint32_t* __restrict__ vis_count,
+                                                     const gs_splat* __restrict__ splats,
+                                                     int tiles_x,
+                                                     const uint32_t* __restrict__ inst_count,
+                                                     const uint32_t* __restrict__ kg_prefix,
+                                                     uint32_t* __restrict__ tkeys,
+                                                     uint32_t* __restrict__ tvals) {
+  __shared__ uint32_t s_off[kKgPart + 1];
+  __shared__ uint32_t s_lo[kKgPart], s_hi[kKgPart], s_g[kKgPart];
+  __shared__ uint32_t s_tmp[kBlock / 64];
+  const int t = threadIdx.x;
+  const uint32_t nvis = *vis_count, cap = *inst_count;
+  const uint32_t base = blockIdx.x * kKgPart;
+  if (base >= nvis) return;
+  uint32_t cnt[kKgItems], sum = 0;
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j) {
+    const int li = t * kKgItems + j;
+    const uint32_t p = base + li;
+    uint32_t g = 0, lo = 0, hi = 0, c = 0;
+    if (p < nvis) {
+      g = sorted_idx[p];
+      const float4 r2 = reinterpret_cast<const float4*>(splats + g)[2];
+      lo = __float_as_uint(r2.z);
+      hi = __float_as_uint(r2.w);
+      c = rect_tiles(lo, hi);
+    }
+    s_g[li] = g;
+    s_lo[li] = lo;
+    s_hi[li] = hi;
+    cnt[j] = c;
+    sum += c;
   }
+  uint32_t btot;
+  uint32_t run = block_excl_scan(sum, s_tmp, &btot);
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j) {
+    s_off[t * kKgItems + j] = run;
+    run += cnt[j];
+  }
+  if (t == 0) s_off[kKgPart] = btot;
   __syncthreads();
-  const uint32_t prefix = s_prefix;
+  const uint32_t prefix = kg_prefix[blockIdx.x];
   for (uint32_t kk = 0; kk < btot; kk += kBlock) {
     const uint32_t k = kk + t;
     if (k < btot) {
-      int a = 0, b = kBlock - 1;
+      int a = 0, b = kKgPart - 1;
       while (a < b) {
         const int mid = (a + b + 1) >> 1;
         if (s_off[mid] <= k) a = mid; else b = mid - 1;
@@ -349,23 +474,42 @@ int stream_grid(int64_t items, int cap = 2048) {
 }
 
 template <typename KeyT, int BITS>
-void histogram_t(const KeyT* keys, const uint32_t* count, int64_t n_grid, int passes,
-                 uint32_t* hist, hipStream_t st) {
-  hipLaunchKernelGGL((k_histogram<KeyT, BITS>), dim3(stream_grid(n_grid, 256)), dim3(kBlock), 0,
-                     st, keys, count, n_grid, passes, hist);
+void pass_t(const RadixArgs<KeyT>& a, int p, int q, const KeyT* ki, const uint32_t* vi, KeyT* kd,
+            uint32_t* vd, bool write_keys, hipStream_t st) {
+  const int parts = (int)((a.n_grid + kSortPart - 1) / kSortPart);
+  const int shift = p * BITS;
+  if (a.mode == 1) {
+    uint32_t* lb = a.lookback + (size_t)(q & 1) * a.lb_parts * 256;
+    uint32_t* lb_next = a.lookback + (size_t)((q + 1) & 1) * a.lb_parts * 256;
+    const uint32_t* h = a.hist + p * 256;
+    if (write_keys)
+      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, true, true>), dim3(parts), dim3(kBlock), 0, st,
+                         ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0, h, a.tickets + q, lb,
+                         lb_next);
+    else
+      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, false, true>), dim3(parts), dim3(kBlock), 0, st,
+                         ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0, h, a.tickets + q, lb,
+                         lb_next);
+  } else {
+    hipLaunchKernelGGL((k_rs_upsweep<KeyT, BITS>), dim3(parts), dim3(kBlock), 0, st, ki, a.count,
+                       a.n_grid, shift, a.table, parts);
+    hipLaunchKernelGGL(k_row_scan, dim3(1 << BITS), dim3(kBlock), 0, st, a.table, parts, a.totals);
+    if (write_keys)
+      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, true, false>), dim3(parts), dim3(kBlock), 0, st,
+                         ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
+                         nullptr, nullptr, nullptr);
+    else
+      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, false, false>), dim3(parts), dim3(kBlock), 0, st,
+                         ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
+                         nullptr, nullptr, nullptr);
+  }
 }
 
 template <typename KeyT, int BITS>
-void onesweep_t(bool write_keys, int parts, const KeyT* kin, const uint32_t* vin, KeyT* kout,
-                uint32_t* vout, const uint32_t* count, int64_t n_host, int shift,
-                const uint32_t* hist, uint32_t* ticket, uint32_t* lb, uint32_t* lb_next,
-                hipStream_t st) {
-  if (write_keys)
-    hipLaunchKernelGGL((k_onesweep<KeyT, BITS, true>), dim3(parts), dim3(kBlock), 0, st, kin, vin,
-                       kout, vout, count, n_host, shift, hist, ticket, lb, lb_next);
-  else
-    hipLaunchKernelGGL((k_onesweep<KeyT, BITS, false>), dim3(parts), dim3(kBlock), 0, st, kin,
-                       vin, kout, vout, count, n_host, shift, hist, ticket, lb, lb_next);
+void hist_t(const RadixArgs<KeyT>& a, int passes, hipStream_t st) {
+  const int parts = (int)((a.n_grid + kSortPart - 1) / kSortPart);
+  hipLaunchKernelGGL((k_histogram<KeyT, BITS>), dim3(parts < 512 ? parts : 512), dim3(kBlock), 0,
+                     st, a.kin, a.count, a.n_grid, passes, a.hist);
 }
 
 }  // namespace
@@ -375,7 +519,7 @@ SortLayout sort_layout(int64_t n, int64_t capacity) {
   const int64_t nn = n > 0 ? n : 1, cap = capacity > 0 ? capacity : 1;
   const int64_t big = nn > cap ? nn : cap;
   L.parts = (int)((big + kSortPart - 1) / kSortPart);
-  L.kg_parts = (int)((nn + kBlock - 1) / kBlock);
+  L.kg_parts = (int)((nn + kKgPart - 1) / kKgPart);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -390,7 +534,9 @@ SortLayout sort_layout(int64_t n, int64_t capacity) {
   L.hist = take((size_t)kMaxPassTotal * 256 * 4);
   L.tickets = take((size_t)kMaxPassTotal * 4);
   L.lookback = take((size_t)2 * L.parts * 256 * 4);
-  L.kg_status = take((size_t)L.kg_parts * 8);
+  L.table = take((size_t)L.parts * 256 * 4);
+  L.totals = take(256 * 4);
+  L.kg_counts = take((size_t)L.kg_parts * 4);
   L.count = take(4);
   L.bytes = o;
   return L;
@@ -413,93 +559,79 @@ SortLayout pairs_layout(int64_t n) {
   L.hist = take((size_t)kMaxPassTotal * 256 * 4);
   L.tickets = take((size_t)kMaxPassTotal * 4);
   L.lookback = take((size_t)2 * L.parts * 256 * 4);
-  L.kg_status = 0;
+  L.table = take((size_t)L.parts * 256 * 4);
+  L.totals = take(256 * 4);
+  L.kg_counts = 0;
   L.count = take(4);
   L.bytes = o;
   return L;
 }
 
-hipError_t launch_sort_init(const SortLayout& L, char* ws, uint32_t* tile_ranges, int tiles,
-                            uint32_t* status_flag, const uint32_t* total_src, int64_t capacity,
-                            hipStream_t st) {
-  const int lb_len = 2 * L.parts * 256;
+hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
+                            int tiles, uint32_t* status_flag, const uint32_t* total_src,
+                            int64_t capacity, hipStream_t st) {
+  const int lb_len = mode == 1 ? 2 * L.parts * 256 : 0;
   const int ranges_len = tile_ranges ? 2 * tiles : 0;
-  int64_t most = lb_len > ranges_len ? lb_len : ranges_len;
-  if (L.kg_parts > most) most = L.kg_parts;
+  const int64_t most = lb_len > ranges_len ? lb_len : ranges_len;
   hipLaunchKernelGGL(k_sort_init, dim3(stream_grid(most, 1024)), dim3(kBlock), 0, st,
-                     reinterpret_cast<uint32_t*>(ws + L.hist), kMaxPassTotal * 256,
+                     reinterpret_cast<uint32_t*>(ws + L.hist), mode == 1 ? kMaxPassTotal * 256 : 0,
                      reinterpret_cast<uint32_t*>(ws + L.tickets), kMaxPassTotal,
-                     reinterpret_cast<uint32_t*>(ws + L.lookback), lb_len,
-                     reinterpret_cast<uint64_t*>(ws + L.kg_status), L.kg_parts, tile_ranges,
-                     ranges_len, reinterpret_cast<uint32_t*>(ws + L.count), total_src,
-                     (uint32_t)capacity, capacity, status_flag);
+                     reinterpret_cast<uint32_t*>(ws + L.lookback), lb_len, tile_ranges, ranges_len,
+                     reinterpret_cast<uint32_t*>(ws + L.count), total_src, (uint32_t)capacity,
+                     capacity, status_flag);
   return hipGetLastError();
 }
 
 template <typename KeyT>
-hipError_t launch_histogram(const KeyT* keys, const uint32_t* count, int64_t n_grid, int bits,
-                            int passes, uint32_t* hist, hipStream_t st) {
-  if (n_grid == 0 || passes == 0) return hipSuccess;
-  switch (bits) {
-    case 6: histogram_t<KeyT, 6>(keys, count, n_grid, passes, hist, st); break;
-    case 7: histogram_t<KeyT, 7>(keys, count, n_grid, passes, hist, st); break;
-    default: histogram_t<KeyT, 8>(keys, count, n_grid, passes, hist, st); break;
+hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int pass_base,
+                             bool last_keys, const char* label, hipStream_t st) {
+  if (a.n_grid == 0 || passes == 0) return hipSuccess;
+  if (a.mode == 1) {
+    trace_mark(st, "radix_hist");
+    switch (bits) {
+      case 6: hist_t<KeyT, 6>(a, passes, st); break;
+      case 7: hist_t<KeyT, 7>(a, passes, st); break;
+      default: hist_t<KeyT, 8>(a, passes, st); break;
+    }
   }
-  return hipGetLastError();
-}
-template hipError_t launch_histogram<uint32_t>(const uint32_t*, const uint32_t*, int64_t, int, int,
-                                               uint32_t*, hipStream_t);
-template hipError_t launch_histogram<uint64_t>(const uint64_t*, const uint32_t*, int64_t, int, int,
-                                               uint32_t*, hipStream_t);
-
-template <typename KeyT>
-hipError_t launch_radix_passes(int64_t n_grid, const uint32_t* count, int bits, int passes,
-                               int pass_base, const KeyT* kin, const uint32_t* vin, KeyT* k_alt,
-                               uint32_t* v_alt, KeyT* k_out, uint32_t* v_out, bool last_keys,
-                               uint32_t* hist, uint32_t* tickets, uint32_t* lookback, int lb_parts,
-                               const char* label, hipStream_t st) {
-  const int parts = (int)((n_grid + kSortPart - 1) / kSortPart);
-  if (parts == 0 || passes == 0) return hipSuccess;
-  const KeyT* ki = kin;
-  const uint32_t* vi = vin;
+  const KeyT* ki = a.kin;
+  const uint32_t* vi = a.vin;
   for (int p = 0; p < passes; ++p) {
-    const int q = pass_base + p;  // global pass index: look-back buffer parity and ticket
+    const int q = pass_base + p;  // global pass index: ticket and look-back buffer parity
     const bool to_out = ((passes - 1 - p) % 2) == 0;
-    KeyT* kd = to_out ? k_out : k_alt;
-    uint32_t* vd = to_out ? v_out : v_alt;
-    uint32_t* lb = lookback + (size_t)(q & 1) * lb_parts * 256;
-    uint32_t* lb_next = lookback + (size_t)((q + 1) & 1) * lb_parts * 256;
+    KeyT* kd = to_out ? a.k_out : a.k_alt;
+    uint32_t* vd = to_out ? a.v_out : a.v_alt;
     const bool wk = (p + 1 < passes) || last_keys;
     trace_mark(st, label);
     switch (bits) {
-      case 6: onesweep_t<KeyT, 6>(wk, parts, ki, vi, kd, vd, count, n_grid, p * bits, hist + p * 256, tickets + q, lb, lb_next, st); break;
-      case 7: onesweep_t<KeyT, 7>(wk, parts, ki, vi, kd, vd, count, n_grid, p * bits, hist + p * 256, tickets + q, lb, lb_next, st); break;
-      default: onesweep_t<KeyT, 8>(wk, parts, ki, vi, kd, vd, count, n_grid, p * bits, hist + p * 256, tickets + q, lb, lb_next, st); break;
+      case 6: pass_t<KeyT, 6>(a, p, q, ki, vi, kd, vd, wk, st); break;
+      case 7: pass_t<KeyT, 7>(a, p, q, ki, vi, kd, vd, wk, st); break;
+      default: pass_t<KeyT, 8>(a, p, q, ki, vi, kd, vd, wk, st); break;
     }
     ki = kd;
     vi = vd;
   }
   return hipGetLastError();
 }
-template hipError_t launch_radix_passes<uint32_t>(int64_t, const uint32_t*, int, int, int,
-                                                  const uint32_t*, const uint32_t*, uint32_t*,
-                                                  uint32_t*, uint32_t*, uint32_t*, bool, uint32_t*,
-                                                  uint32_t*, uint32_t*, int, const char*,
-                                                  hipStream_t);
-template hipError_t launch_radix_passes<uint64_t>(int64_t, const uint32_t*, int, int, int,
-                                                  const uint64_t*, const uint32_t*, uint64_t*,
-                                                  uint32_t*, uint64_t*, uint32_t*, bool, uint32_t*,
-                                                  uint32_t*, uint32_t*, int, const char*,
-                                                  hipStream_t);
+template hipError_t launch_radix_sort<uint32_t>(const RadixArgs<uint32_t>&, int, int, int, bool,
+                                                const char*, hipStream_t);
+template hipError_t launch_radix_sort<uint64_t>(const RadixArgs<uint64_t>&, int, int, int, bool,
+                                                const char*, hipStream_t);
 
 hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* vis_count,
                          const gs_splat* splats, int tiles_x, const uint32_t* inst_count,
-                         uint32_t* tkeys, uint32_t* tvals, uint64_t* status, uint32_t* ticket,
+                         uint32_t* kg_counts, uint32_t* kg_total, uint32_t* tkeys, uint32_t* tvals,
                          hipStream_t st) {
-  const int parts = (int)((n + kBlock - 1) / kBlock);
+  const int parts = (int)((n + kKgPart - 1) / kKgPart);
   if (parts == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_keygen, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count, splats,
-                     tiles_x, inst_count, tkeys, tvals, status, ticket);
+  trace_mark(st, "kg_count");
+  hipLaunchKernelGGL(k_kg_count, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count, splats,
+                     kg_counts);
+  trace_mark(st, "kg_scan");
+  hipLaunchKernelGGL(k_row_scan, dim3(1), dim3(kBlock), 0, st, kg_counts, parts, kg_total);
+  trace_mark(st, "keygen");
+  hipLaunchKernelGGL(k_kg_write, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count, splats,
+                     tiles_x, inst_count, kg_counts, tkeys, tvals);
   return hipGetLastError();
 }
 

@@ -77,7 +77,7 @@ def extra_pairs_harmless(orc, ref, rec, cam, v):
 def test_preprocess_tiny(R, orc):
     print_case("preprocess tiny 4096")
     sc, cam = S.tiny_scene()
-    splats, dkeys, didx, counts = R.preprocess(gp(sc), cam)
+    splats, dkeys, counts = R.preprocess(gp(sc), cam)
     torch.cuda.synchronize()
     rec = splats_np(splats, sc.n)
     ref = orc.preprocess(sc, cam)
@@ -87,10 +87,9 @@ def test_preprocess_tiny(R, orc):
     cnt = np.where(vis, (rec["tx1"].astype(np.int64) - rec["tx0"] + 1) * (rec["ty1"].astype(np.int64) - rec["ty0"] + 1), 0)
     c = u32(counts)
     assert int(c[0]) == cnt.sum() and int(c[1]) == vis.sum()
-    # ordered compaction: visible Gaussians in index order with their depth bits
-    nv = int(c[1])
-    np.testing.assert_array_equal(u32(didx)[:nv], np.nonzero(vis)[0].astype(np.uint32))
-    np.testing.assert_array_equal(u32(dkeys)[:nv], rec["depth"][vis].view(np.uint32))
+    # depth sort keys: float32 depth bits, the largest key when culled
+    expect = np.where(vis, rec["depth"].view(np.uint32), np.uint32(0xFFFFFFFF))
+    np.testing.assert_array_equal(u32(dkeys), expect)
 
 
 @pytest.mark.parametrize("deg", [0, 1, 2, 3])
@@ -105,7 +104,7 @@ def test_preprocess_sh_degrees(R, orc, deg):
         sh[:, 1:] = rng.normal(0, 0.2, (sc.n, K - 1, 3))
     sc = S.Scene(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sh, deg)
     cam2 = S.pinhole_camera(S.look_at((1.5, 1.0, -2.5)), 200, 150, 50.0)
-    splats, _, _ = R.preprocess(gp(sc), cam2)
+    splats = R.preprocess(gp(sc), cam2)[0]
     torch.cuda.synchronize()
     compare_records(orc, splats_np(splats, sc.n), orc.preprocess(sc, cam2), cam2)
 
@@ -117,7 +116,7 @@ def test_preprocess_model_transform(R, orc):
     A = 0.7 * Rotation.from_euler("xyz", [0.4, -1.0, 0.3]).as_matrix()
     sc.model = np.concatenate([A, np.array([[1.0], [-0.5], [2.0]])], 1).astype(np.float32)
     cam = S.pinhole_camera(S.look_at((2.0, 1.0, -9.0)), 640, 480, 60.0)
-    splats, _, _ = R.preprocess(gp(sc), cam)
+    splats = R.preprocess(gp(sc), cam)[0]
     torch.cuda.synchronize()
     compare_records(orc, splats_np(splats, sc.n), orc.preprocess(sc, cam), cam)
 
@@ -127,11 +126,11 @@ def test_preprocess_model_transform(R, orc):
 SIZES = [1, 2, 63, 64, 65, 4095, 4096, 4097, 3 * 4096 + 17, 100_003]
 
 
-def sort_pairs_gpu(keys, vals, key_bits, radix_bits=8):
+def sort_pairs_gpu(keys, vals, key_bits, radix_bits=8, sort_mode=0):
     from paper_2512_08478_amd import _lib as L
     import ctypes
     lib = L.load()
-    s = L.default_settings(radix_bits=radix_bits)
+    s = L.default_settings(radix_bits=radix_bits, sort_mode=sort_mode)
     n = len(keys)
     kin = torch.from_numpy(keys.view(np.int64)).cuda()
     vin = torch.from_numpy(vals.view(np.int32)).cuda()
@@ -150,24 +149,26 @@ def sort_pairs_gpu(keys, vals, key_bits, radix_bits=8):
     return u64(kout), u32(vout)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("kind", S.SORT_KEY_KINDS)
-def test_sort_pairs_bitexact(R, orc, kind):
+def test_sort_pairs_bitexact(R, orc, kind, mode):
     for n in SIZES:
-        print_case(f"sort_pairs {kind} n={n}")
+        print_case(f"sort_pairs {kind} n={n} mode={mode}")
         k, v = S.sort_keys(kind, n, seed=n)
         kb = 45 if kind in ("random45",) else 64
-        ks, vs = sort_pairs_gpu(k, v, kb)
+        ks, vs = sort_pairs_gpu(k, v, kb, sort_mode=mode)
         rk, rv = orc.stable_sort_pairs(k, v)
         np.testing.assert_array_equal(ks, rk, err_msg=f"{kind} n={n}")
         np.testing.assert_array_equal(vs, rv, err_msg=f"{kind} n={n}")
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("bits", [6, 7, 8])
-def test_sort_pairs_digit_widths(R, orc, bits):
+def test_sort_pairs_digit_widths(R, orc, bits, mode):
     for kind in ("random64", "depth_like", "tile_runs"):
-        print_case(f"sort_pairs bits={bits} {kind}")
+        print_case(f"sort_pairs bits={bits} {kind} mode={mode}")
         k, v = S.sort_keys(kind, 50_001, seed=bits)
-        ks, vs = sort_pairs_gpu(k, v, 64, radix_bits=bits)
+        ks, vs = sort_pairs_gpu(k, v, 64, radix_bits=bits, sort_mode=mode)
         rk, rv = orc.stable_sort_pairs(k, v)
         np.testing.assert_array_equal(ks, rk)
         np.testing.assert_array_equal(vs, rv)
@@ -311,9 +312,11 @@ def test_tile_shape_and_digit_width_invariance(R):
     sc, cam = S.tiny_scene()
     cam = S.pinhole_camera(S.look_at((0.3, -0.2, -3.0)), 250, 190, 60.0)  # ragged edge tiles
     base = R.forward(gp(sc), cam).image.cpu().numpy()
-    for tw, th, bits in [(8, 8, 8), (16, 8, 7), (32, 8, 6), (32, 16, 8), (16, 16, 6)]:
-        img = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits)).forward(gp(sc), cam).image.cpu().numpy()
-        np.testing.assert_array_equal(img, base, err_msg=f"{tw}x{th} bits {bits}")
+    for tw, th, bits, mode in [(8, 8, 8, 0), (16, 8, 7, 1), (32, 8, 6, 0), (32, 16, 8, 1),
+                               (16, 16, 6, 1), (16, 16, 7, 0)]:
+        img = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=mode)).forward(
+            gp(sc), cam).image.cpu().numpy()
+        np.testing.assert_array_equal(img, base, err_msg=f"{tw}x{th} bits {bits} mode {mode}")
 
 
 def test_shuffle_and_repeat_invariance(R):
@@ -332,7 +335,7 @@ def test_capacity_overflow_flag(R):
     sc, cam = S.tiny_scene()
     p = gp(sc)
     pre = R.preprocess(p, cam)
-    tot = int(u32(pre[3])[0])
+    tot = int(u32(pre[2])[0])
     keys, values, ranges, flag, cap = R.sort(sc.n, *pre, cam, capacity=tot // 2)
     torch.cuda.synchronize()
     assert int(u32(flag)[0]) & 1 == 1
