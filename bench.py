@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--sort-mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=2048)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (counter calibration)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -94,6 +96,12 @@ def main():
     from paper_2512_08478_amd import _lib as L
     from paper_2512_08478_amd.render import GaussianParams, Renderer
 
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib * 2**20 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tw, th = map(int, args.tile.split("x"))
     sc, cam = make_workload(args.workload)
     R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=args.radix_bits, sort_mode=args.sort_mode))

@@ -141,8 +141,7 @@ int32_t gs_trace_read(int32_t max_entries, char* labels, float* ms, int32_t* cou
 /*
  * Bytes of workspace a stage needs.  `n` is the number of Gaussians,
  * `capacity` the instance capacity (for the sort stages; for
- * GS_STAGE_SORT_PAIRS the number of pairs).  Returns 0 on invalid input
- * and for GS_STAGE_PREPROCESS, which needs none.
+ * GS_STAGE_SORT_PAIRS the number of pairs).  Returns 0 on invalid input.
  */
 size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity,
                          const gs_camera* cam, const gs_settings* set);
@@ -178,14 +177,16 @@ int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set);
  * Culled (record with an empty rect, zero tiles): camera depth <= znear,
  * opacity < alpha_min, non-finite values, zero quaternion, or a footprint
  * whose opacity-aware bounding box (where o*exp(-Q/2) >= alpha_min)
- * contains no pixel centre.  No workspace is needed.
+ * contains no pixel centre.
+ * Workspace: gs_workspace_size(GS_STAGE_PREPROCESS, n, 0, ...) bytes
+ * (per-workgroup partial counts).
  */
 int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales,
                       const float* quats, const float* opacity_logits,
                       const float* sh, int32_t sh_degree, const float* model,
                       const gs_camera* cam, const gs_settings* set,
                       gs_splat* splats, uint32_t* depth_keys, uint32_t* counts,
-                      void* stream);
+                      void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * gs_sort -- key generation and the per-frame GPU radix sort (Algorithm 1,

@@ -87,7 +87,7 @@ def load():
     lib.gs_sort_key_bits.restype = I32
     lib.gs_sort_key_bits.argtypes = [CAM, SET]
     lib.gs_preprocess.restype = I32
-    lib.gs_preprocess.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P]
+    lib.gs_preprocess.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, SZ, P]
     lib.gs_sort.restype = I32
     lib.gs_sort.argtypes = [I64, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ, P]
     lib.gs_sort_pairs.restype = I32

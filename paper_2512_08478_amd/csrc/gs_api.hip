@@ -256,7 +256,8 @@ size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity, const gs_ca
   if (n < 0 || capacity < 0) return 0;
   switch (stage) {
     case GS_STAGE_PREPROCESS:
-      return 0;
+      if (n >= kMaxN) return 0;
+      return gs::preprocess_ws_bytes(n);
     case GS_STAGE_SORT:
       if (check_settings(set) || check_camera(cam, set) || capacity > kMaxInstances || n >= kMaxN)
         return 0;
@@ -274,19 +275,22 @@ size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity, const gs_ca
 int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales, const float* quats,
                       const float* opacity_logits, const float* sh, int32_t sh_degree,
                       const float* model, const gs_camera* cam, const gs_settings* set,
-                      gs_splat* splats, uint32_t* depth_keys, uint32_t* counts, void* stream) {
+                      gs_splat* splats, uint32_t* depth_keys, uint32_t* counts, void* workspace,
+                      size_t workspace_bytes, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
   if ((r = check_dev(counts))) return r;
   if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)))) return r;
+  if (workspace_bytes < gs::preprocess_ws_bytes(n)) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
   gs::CamK ck;
   if ((r = make_camk(cam, set, model, &ck))) return r;
   const gs::SetK sk = make_setk(cam, set);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  gs::trace_mark(st, "preprocess_init");
   hipError_t e = gs::launch_preprocess((int)n, means, log_scales, quats, opacity_logits, sh,
-                                       sh_degree, ck, sk, splats, depth_keys, counts, st);
+                                       sh_degree, ck, sk, splats, depth_keys, counts, workspace,
+                                       st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;

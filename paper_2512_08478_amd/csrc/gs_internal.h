@@ -75,11 +75,12 @@ struct RadixArgs {
 };
 
 // Launchers (enqueue only; return the first launch error).
+size_t preprocess_ws_bytes(int64_t n);
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
                              gs_splat* splats, uint32_t* depth_keys, uint32_t* counts,
-                             hipStream_t st);
+                             void* ws, hipStream_t st);
 hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
                             int tiles, uint32_t* status_flag, const uint32_t* total_src,
                             int64_t capacity, hipStream_t st);

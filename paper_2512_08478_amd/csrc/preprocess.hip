@@ -216,20 +216,16 @@ __device__ __forceinline__ uint32_t project_one(
   return tiles;
 }
 
-__global__ __launch_bounds__(64) void k_preprocess_init(uint32_t* counts) {
-  if (threadIdx.x < 2) counts[threadIdx.x] = 0;
-}
-
-// Record of Gaussian i, its depth sort key (float32 bits of the camera-space
-// depth; the largest key when culled, so culled Gaussians sort last) and,
-// per workgroup, two integer atomics for the instance and visible counts
-// (sums, so their order does not matter).
+// Record of Gaussian i and its depth sort key (float32 bits of the
+// camera-space depth; the largest key when culled, so culled Gaussians sort
+// last).  Each workgroup writes its tile and visible counts to its own
+// slot of `partial`; k_count_finalize sums the slots.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_preprocess(
     int n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float4* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, CamK cam, SetK set, gs_splat* __restrict__ splats,
-    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ counts) {
+    uint32_t* __restrict__ depth_keys, uint2* __restrict__ partial) {
   __shared__ uint32_t s_vis[kBlock / 64], s_til[kBlock / 64];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   uint32_t tiles = 0;
@@ -253,8 +249,37 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
       bv += s_vis[w];
       bt += s_til[w];
     }
-    if (bt) atomicAdd(&counts[0], bt);
-    if (bv) atomicAdd(&counts[1], bv);
+    partial[blockIdx.x] = make_uint2(bt, bv);
+  }
+}
+
+// counts[0] = total instances, counts[1] = visible Gaussians.
+__global__ __launch_bounds__(kBlock) void k_count_finalize(const uint2* __restrict__ partial,
+                                                           int blocks, uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_a[kBlock / 64], s_b[kBlock / 64];
+  uint32_t a = 0, b = 0;
+  for (int i = threadIdx.x; i < blocks; i += kBlock) {
+    const uint2 v = partial[i];
+    a += v.x;
+    b += v.y;
+  }
+  a = wave_sum_u32(a);
+  b = wave_sum_u32(b);
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_a[wave] = a;
+    s_b[wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ta = 0, tb = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      ta += s_a[w];
+      tb += s_b[w];
+    }
+    counts[0] = ta;
+    counts[1] = tb;
   }
 }
 
@@ -525,24 +550,32 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(
 
 }  // namespace
 
+size_t preprocess_ws_bytes(int64_t n) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  return align_up((size_t)(blocks > 0 ? blocks : 1) * 8, 256);
+}
+
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
                              gs_splat* splats, uint32_t* depth_keys, uint32_t* counts,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(k_preprocess_init, dim3(1), dim3(64), 0, st, counts);
-  if (n == 0) return hipGetLastError();
-  trace_mark(st, "preprocess");
-  const dim3 grid((n + kBlock - 1) / kBlock), block(kBlock);
-  const float4* q4 = reinterpret_cast<const float4*>(quats);
-#define GS_PRE(D) hipLaunchKernelGGL(k_preprocess<D>, grid, block, 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, depth_keys, counts)
-  switch (degree) {
-    case 0: GS_PRE(0); break;
-    case 1: GS_PRE(1); break;
-    case 2: GS_PRE(2); break;
-    default: GS_PRE(3); break;
-  }
+                             void* ws, hipStream_t st) {
+  const int blocks = (n + kBlock - 1) / kBlock;
+  uint2* partial = static_cast<uint2*>(ws);
+  if (n > 0) {
+    trace_mark(st, "preprocess");
+    const float4* q4 = reinterpret_cast<const float4*>(quats);
+#define GS_PRE(D) hipLaunchKernelGGL(k_preprocess<D>, dim3(blocks), dim3(kBlock), 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, depth_keys, partial)
+    switch (degree) {
+      case 0: GS_PRE(0); break;
+      case 1: GS_PRE(1); break;
+      case 2: GS_PRE(2); break;
+      default: GS_PRE(3); break;
+    }
 #undef GS_PRE
+  }
+  trace_mark(st, "count_finalize");
+  hipLaunchKernelGGL(k_count_finalize, dim3(1), dim3(kBlock), 0, st, partial, blocks, counts);
   return hipGetLastError();
 }
 

@@ -98,9 +98,11 @@ class Renderer:
         splats = self._buf("splats", n * L.SPLAT_BYTES, reuse)[:n * L.SPLAT_BYTES]
         dkeys = self._buf("depth_keys", n * 4, reuse).view(torch.int32)[:n]
         counts = self._buf("counts", 8, reuse).view(torch.int32)[:2]
+        ws_bytes = lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, n, 0, ctypes.byref(c), ctypes.byref(s))
+        ws = self._buf("ws_pre", ws_bytes, reuse)
         st = lib.gs_preprocess(n, *[_p(t) for t in p.tensors()], p.sh_degree, L.model_array(p.model),
                                ctypes.byref(c), ctypes.byref(s), _p(splats), _p(dkeys), _p(counts),
-                               _stream())
+                               _p(ws), ws.numel(), _stream())
         L.check(st, "gs_preprocess")
         return splats, dkeys, counts
 

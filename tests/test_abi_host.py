@@ -66,7 +66,7 @@ def test_key_bits_and_workspace_sizes(lib):
     assert lib.gs_sort_key_bits(ctypes.byref(c), ctypes.byref(s8)) == 32 + 15  # 240x135
     tiny = L.make_camera(S.tiny_scene(n=4)[1])
     assert lib.gs_sort_key_bits(ctypes.byref(tiny), ctypes.byref(s)) == 40  # 256 tiles
-    assert lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, 1_000_000, 0, ctypes.byref(c), ctypes.byref(s)) == 0
+    assert lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, 1_000_000, 0, ctypes.byref(c), ctypes.byref(s)) >= 3907 * 8
     w1 = lib.gs_workspace_size(L.GS_STAGE_SORT, 1_000_000, 4_000_000, ctypes.byref(c), ctypes.byref(s))
     assert w1 >= 4_000_000 * 24
     assert lib.gs_workspace_size(L.GS_STAGE_BACKWARD, 10, 0, ctypes.byref(c), ctypes.byref(s)) >= 480
@@ -78,13 +78,14 @@ def test_key_bits_and_workspace_sizes(lib):
 FAKE = 0x7F0000000000  # aligned, never dereferenced: every call below fails validation first
 
 
-def pre(lib, n=4, deg=0, cam=None, st=None, ptrs=None, total=FAKE):
+def pre(lib, n=4, deg=0, cam=None, st=None, ptrs=None, total=FAKE, ws_bytes=1 << 20):
     c = cam or cam_1080()
     s = st or L.default_settings()
     p = ptrs or [FAKE] * 5
     return lib.gs_preprocess(n, *[ctypes.c_void_p(x) if x else None for x in p], deg, None,
                              ctypes.byref(c), ctypes.byref(s), ctypes.c_void_p(FAKE),
-                             ctypes.c_void_p(FAKE), ctypes.c_void_p(total) if total else None, None)
+                             ctypes.c_void_p(FAKE), ctypes.c_void_p(total) if total else None,
+                             ctypes.c_void_p(FAKE), ws_bytes, None)
 
 
 def test_preprocess_argument_validation(lib):
@@ -96,6 +97,7 @@ def test_preprocess_argument_validation(lib):
     assert pre(lib, ptrs=[FAKE, FAKE + 4, FAKE, FAKE, FAKE]) == L.GS_ERR_MISALIGNED
     assert pre(lib, total=0) == L.GS_ERR_INVALID_ARGUMENT
     assert pre(lib, st=L.default_settings(sort_mode=2)) == L.GS_ERR_UNSUPPORTED
+    assert pre(lib, ws_bytes=0) == L.GS_ERR_WORKSPACE
     assert pre(lib, st=L.default_settings(tile_w=12)) == L.GS_ERR_UNSUPPORTED
     assert pre(lib, st=L.default_settings(radix_bits=9)) == L.GS_ERR_UNSUPPORTED
     assert pre(lib, st=L.default_settings(alpha_max=1.0)) == L.GS_ERR_INVALID_ARGUMENT
@@ -116,10 +118,12 @@ def test_model_transform_must_be_similarity(lib):
     c, s = cam_1080(), L.default_settings()
     F = ctypes.c_void_p(FAKE)
     shear = (ctypes.c_float * 12)(1, 0.5, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
-    r = lib.gs_preprocess(4, *[F] * 5, 0, shear, ctypes.byref(c), ctypes.byref(s), F, F, F, None)
+    r = lib.gs_preprocess(4, *[F] * 5, 0, shear, ctypes.byref(c), ctypes.byref(s), F, F, F, F,
+                          1 << 20, None)
     assert r == L.GS_ERR_INVALID_ARGUMENT
     mirror = (ctypes.c_float * 12)(-1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
-    r = lib.gs_preprocess(4, *[F] * 5, 0, mirror, ctypes.byref(c), ctypes.byref(s), F, F, F, None)
+    r = lib.gs_preprocess(4, *[F] * 5, 0, mirror, ctypes.byref(c), ctypes.byref(s), F, F, F, F,
+                          1 << 20, None)
     assert r == L.GS_ERR_INVALID_ARGUMENT
 
 
