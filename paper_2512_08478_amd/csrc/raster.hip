@@ -1,11 +1,27 @@
 // Tile compositing (Section 3.2 Eqs. 2-3) forward and backward.
 //
-// One workgroup per tile, one thread per pixel.  The tile's splats (already
-// in (depth, index) order) are staged through LDS in batches of one record
-// per thread; every pixel walks the batch front to back.  A pixel stops
-// after the blend that takes its transmittance below t_eps; a wave whose
-// 64 pixels have all stopped skips the batch loop, and the workgroup leaves
-// once every pixel has stopped.
+// One workgroup per tile; each wave owns one 8x8 pixel quadrant of the tile
+// and each lane one pixel.  The tile's splats (already in (depth, index)
+// order) are staged through LDS in batches.  While staging, every splat
+// gets
+//   * a quadrant mask: the quadrants its opacity-aware footprint (where
+//     o exp(-Q/2) >= alpha_min) can reach, from the ellipse's exact extents
+//     with a small outward margin, so that a wave skips a splat with a
+//     scalar test and no vector work;
+//   * per-row terms of the log2 weight
+//       e = log2(o) - (log2e/2) Q = rowterm[r] - qa' (ubase[r][g] + lx)^2,
+//     with Q = qa (dx - qb dy)^2 + qc dy^2, qa' = qa log2e/2, and
+//     ubase[r][g] the value of dx - qb dy at column 0 of the 8-pixel column
+//     group g of row r.  A pixel then costs an add, a multiply and an fma.
+//     The terms depend only on the pixel's row and 8-aligned column group,
+//     never on the tile shape, so every tile shape gives bitwise-identical
+//     images; the backward kernel stages them identically, so its
+//     skip decisions match the forward pass exactly.
+// Per pixel, front to back: skip when e < log2(alpha_min); otherwise
+// alpha = min(alpha_max, 2^e), C += T alpha rgb, T *= 1 - alpha, and stop
+// right after the blend that takes T below t_eps.  A wave whose pixels have
+// all stopped skips the batch loop; the workgroup leaves once every pixel
+// has stopped.
 //
 // Tiles are assigned XCD-major: the hardware deals consecutive workgroups
 // round-robin to the 8 XCDs, so workgroup b works on tile
@@ -18,6 +34,7 @@ namespace gs {
 namespace {
 
 constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
+constexpr float kLn2 = 0.69314718055994531f;
 constexpr int kXcds = 8;
 
 __device__ __forceinline__ int xcd_tile(int b, int tiles) {
@@ -27,6 +44,66 @@ __device__ __forceinline__ int xcd_tile(int b, int tiles) {
 
 inline int xcd_grid(int tiles) { return ((tiles + kXcds - 1) / kXcds) * kXcds; }
 
+// LDS staging shared by the forward and backward kernels.
+template <int TW, int TH>
+struct Stage {
+  static constexpr int NT = TW * TH;
+  static constexpr int QX = TW / 8;          // quadrant columns (= 8-column groups)
+  static constexpr int NQ = NT / 64;         // quadrants = waves
+  static constexpr int BATCH = NT < 128 ? NT : 128;
+  static constexpr int TPS = NT / BATCH;     // threads per splat while staging
+  static constexpr int RPT = TH / TPS;       // rows each staging thread fills
+  float4 hdr[BATCH];          // qa', r, g, b
+  float4 aux[BATCH];          // qb, qc', my, opacity
+  float rt[BATCH][TH];        // log2(o) - qc' dy^2 per tile row
+  float ub[BATCH][TH][QX];    // dx - qb dy at column 0 of each 8-column group
+  uint32_t mask[BATCH];       // quadrants the footprint reaches
+  uint32_t gid[BATCH];        // Gaussian index
+};
+
+// Stage splat `j` of the batch (this thread's share of its rows).
+template <int TW, int TH>
+__device__ __forceinline__ void stage_splat(Stage<TW, TH>& S, int j, int part,
+                                            const gs_splat* __restrict__ splats, uint32_t g,
+                                            int tx0, int ty0, float log2_tau) {
+  using St = Stage<TW, TH>;
+  const float4* rec = reinterpret_cast<const float4*>(splats + g);
+  const float4 a = rec[0], b = rec[1];
+  const float c = rec[2].x;
+  const float mx = a.x, my = a.y, qb = a.w;
+  const float qa_ = a.z * kHalfLog2e, qc_ = b.x * kHalfLog2e;
+  const float lo = log2f(b.y);
+  if (part == 0) {
+    // footprint e >= log2(alpha_min) <=> Q' <= qm; its extents are
+    // |dy| <= sqrt(qm / qc') and |dx| <= sqrt(qm (qb^2 / qc' + 1 / qa')).
+    const float qm = fmaxf(lo - log2_tau, 0.f);
+    float ry = sqrtf(qm / qc_);
+    float rx = sqrtf(qm * (qb * qb / qc_ + 1.f / qa_));
+    ry = ry * (1.f + 1e-4f) + 1e-3f;
+    rx = rx * (1.f + 1e-4f) + 1e-3f;
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < St::NQ; ++q) {
+      const float x0 = tx0 + 8 * (q % St::QX) + 0.5f, y0 = ty0 + 8 * (q / St::QX) + 0.5f;
+      const bool hit = (mx + rx >= x0) && (mx - rx <= x0 + 7.f) && (my + ry >= y0) &&
+                       (my - ry <= y0 + 7.f);
+      m |= hit ? (1u << q) : 0u;
+    }
+    S.hdr[j] = make_float4(qa_, b.z, b.w, c);
+    S.aux[j] = make_float4(qb, qc_, my, b.y);
+    S.mask[j] = m;
+    S.gid[j] = g;
+  }
+#pragma unroll
+  for (int rr = 0; rr < St::RPT; ++rr) {
+    const int r = part * St::RPT + rr;
+    const float dy = (ty0 + r + 0.5f) - my;
+    S.rt[j][r] = fmaf(-qc_, dy * dy, lo);
+#pragma unroll
+    for (int q = 0; q < St::QX; ++q) S.ub[j][r][q] = fmaf(-qb, dy, (tx0 + 8 * q + 0.5f) - mx);
+  }
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ splats,
                                                    const uint32_t* __restrict__ values,
@@ -35,53 +112,45 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
                                                    float* __restrict__ image,
                                                    float* __restrict__ T_final,
                                                    uint32_t* __restrict__ last) {
-  constexpr int NT = TW * TH;
-  __shared__ float4 s_a[NT];  // mean_x, mean_y, qa*log2e/2, qb
-  __shared__ float4 s_b[NT];  // qc*log2e/2, log2(opacity), r, g
-  __shared__ float s_c[NT];   // b
+  using St = Stage<TW, TH>;
+  __shared__ St S;
   const int tiles = set.tiles_x * set.tiles_y;
   const int tile = xcd_tile(blockIdx.x, tiles);
   if (tile >= tiles) return;
-  const int tid = threadIdx.x;
-  const int px = (tile % set.tiles_x) * TW + tid % TW;
-  const int py = (tile / set.tiles_x) * TH + tid / TW;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int qx = wave % St::QX, qy = wave / St::QX;
+  const int tx0 = (tile % set.tiles_x) * TW, ty0 = (tile / set.tiles_x) * TH;
+  const int lx = lane & 7, row = qy * 8 + (lane >> 3);
+  const int px = tx0 + qx * 8 + lx, py = ty0 + row;
   const bool inside = px < W && py < H;
-  const float fx = px + 0.5f, fy = py + 0.5f;
+  const float lxf = (float)lx;
+  const uint32_t qbit = 1u << wave;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  const float log2_tau = set.log2_tau;
 
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t lastc = 0;
   bool done = !inside;
-  for (uint32_t bs = start; bs < end; bs += NT) {
-    if (__syncthreads_count(done) == NT) break;
-    const uint32_t idx = bs + tid;
-    if (idx < end) {
-      const float4* rec = reinterpret_cast<const float4*>(splats + values[idx]);
-      float4 a = rec[0], b = rec[1];
-      const float c = rec[2].x;
-      a.z *= kHalfLog2e;
-      b.x *= kHalfLog2e;
-      b.y = log2f(b.y);
-      s_a[tid] = a;
-      s_b[tid] = b;
-      s_c[tid] = c;
+  for (uint32_t bs = start; bs < end; bs += St::BATCH) {
+    if (__syncthreads_count(done) == St::NT) break;
+    {
+      const int j = tid / St::TPS, part = tid % St::TPS;
+      if (bs + j < end) stage_splat<TW, TH>(S, j, part, splats, values[bs + j], tx0, ty0, log2_tau);
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, end - bs);
+    const int cnt = (int)min((uint32_t)St::BATCH, end - bs);
     if (!done) {
       for (int j = 0; j < cnt; ++j) {
-        const float4 a = s_a[j];
-        const float4 b = s_b[j];
-        const float dx = fx - a.x, dy = fy - a.y;
-        const float u = fmaf(-a.w, dy, dx);
-        // log2 of o*exp(-Q/2), Q = qa u^2 + qc dy^2
-        const float e = b.y - fmaf(a.z, u * u, b.x * (dy * dy));
-        if (e < set.log2_tau) continue;  // weight below alpha_min: skipped
+        if (!(__builtin_amdgcn_readfirstlane(S.mask[j]) & qbit)) continue;
+        const float u = S.ub[j][row][qx] + lxf;
+        const float4 h = S.hdr[j];
+        const float e = fmaf(-h.x, u * u, S.rt[j][row]);
+        if (e < log2_tau) continue;  // weight below alpha_min: skipped
         const float alpha = fminf(set.amax, exp2f(e));
         const float w = alpha * T;
-        C0 = fmaf(w, b.z, C0);
-        C1 = fmaf(w, b.w, C1);
-        C2 = fmaf(w, s_c[j], C2);
+        C0 = fmaf(w, h.y, C0);
+        C1 = fmaf(w, h.z, C1);
+        C2 = fmaf(w, h.w, C2);
         T = T * (1.f - alpha);
         lastc = bs + j + 1 - start;
         if (T < set.t_eps) {
@@ -105,8 +174,8 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
 //   S_i = colour composited behind i (normalised by T_{i+1}),
 //   B_i = T_final / T_{i+1},
 // dC/dalpha_i = T_i (c_i - S_i - B_i bg) and dA/dalpha_i = T_i B_i.
-// Per splat the 9 partial derivatives are summed over the wave first and
-// added to the Gaussian's 2-D gradient record with one atomic per value.
+// Per splat the 9 partial derivatives are summed over the wave and added
+// to the Gaussian's 2-D gradient record with one atomic per value.
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restrict__ splats,
                                                        const uint32_t* __restrict__ values,
@@ -116,23 +185,22 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
                                                        const uint32_t* __restrict__ last,
                                                        const float* __restrict__ dL_dimage,
                                                        float* __restrict__ grad2d) {
-  constexpr int NT = TW * TH;
-  // staged exactly as in the forward kernel, so that every skip decision
-  // (log2 weight < log2 alpha_min) is taken on identical arithmetic
-  __shared__ float4 s_a[NT];  // mean_x, mean_y, qa*log2e/2, qb
-  __shared__ float4 s_b[NT];  // qc*log2e/2, log2(opacity), r, g
-  __shared__ float2 s_c[NT];  // b, opacity
-  __shared__ uint32_t s_g[NT];
+  using St = Stage<TW, TH>;
+  __shared__ St S;
   __shared__ uint32_t s_maxlast;
   const int tiles = set.tiles_x * set.tiles_y;
   const int tile = xcd_tile(blockIdx.x, tiles);
   if (tile >= tiles) return;
-  const int tid = threadIdx.x;
-  const int px = (tile % set.tiles_x) * TW + tid % TW;
-  const int py = (tile / set.tiles_x) * TH + tid / TW;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int qx = wave % St::QX, qy = wave / St::QX;
+  const int tx0 = (tile % set.tiles_x) * TW, ty0 = (tile / set.tiles_x) * TH;
+  const int lx = lane & 7, row = qy * 8 + (lane >> 3);
+  const int px = tx0 + qx * 8 + lx, py = ty0 + row;
   const bool inside = px < W && py < H;
-  const float fx = px + 0.5f, fy = py + 0.5f;
+  const float lxf = (float)lx, fy = py + 0.5f;
+  const uint32_t qbit = 1u << wave;
   const uint32_t start = ranges[2 * tile];
+  const float log2_tau = set.log2_tau;
 
   float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, dA = 0.f;
   uint32_t mylast = 0;
@@ -150,48 +218,36 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
   const uint32_t nlast = s_maxlast;
   const float bgdot = dC0 * set.bg[0] + dC1 * set.bg[1] + dC2 * set.bg[2];
   float S0 = 0.f, S1 = 0.f, S2 = 0.f, B = 1.f;
-  constexpr float kLn2 = 0.69314718055994531f;
 
   // batches cover positions [0, nlast) of the tile's range, last batch first
-  const int nb = (int)((nlast + NT - 1) / NT);
+  const int nb = (int)((nlast + St::BATCH - 1) / St::BATCH);
   for (int bi = nb - 1; bi >= 0; --bi) {
-    const uint32_t bs = (uint32_t)bi * NT;
+    const uint32_t bs = (uint32_t)bi * St::BATCH;
     __syncthreads();
-    const uint32_t pos = bs + tid;
-    if (pos < nlast) {
-      const uint32_t g = values[start + pos];
-      const float4* rec = reinterpret_cast<const float4*>(splats + g);
-      float4 a = rec[0], b = rec[1];
-      const float c = rec[2].x;
-      const float o = b.y;
-      a.z *= kHalfLog2e;
-      b.x *= kHalfLog2e;
-      b.y = log2f(b.y);
-      s_a[tid] = a;
-      s_b[tid] = b;
-      s_c[tid] = make_float2(c, o);
-      s_g[tid] = g;
+    {
+      const int j = tid / St::TPS, part = tid % St::TPS;
+      if (bs + j < nlast)
+        stage_splat<TW, TH>(S, j, part, splats, values[start + bs + j], tx0, ty0, log2_tau);
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, nlast - bs);
+    const int cnt = (int)min((uint32_t)St::BATCH, nlast - bs);
     for (int j = cnt - 1; j >= 0; --j) {
-      const float4 a = s_a[j];
-      const float4 b = s_b[j];
+      if (!(__builtin_amdgcn_readfirstlane(S.mask[j]) & qbit)) continue;
       float gmx = 0.f, gmy = 0.f, gqa = 0.f, gqb = 0.f, gqc = 0.f, gop = 0.f;
       float gr = 0.f, gg = 0.f, gb = 0.f;
       bool contrib = false;
       if (bs + j < mylast) {
-        const float dx = fx - a.x, dy = fy - a.y;
-        const float u = fmaf(-a.w, dy, dx);
-        const float e = b.y - fmaf(a.z, u * u, b.x * (dy * dy));
-        if (e >= set.log2_tau) {
+        const float u = S.ub[j][row][qx] + lxf;
+        const float4 h = S.hdr[j];
+        const float e = fmaf(-h.x, u * u, S.rt[j][row]);
+        if (e >= log2_tau) {
           contrib = true;
-          const float2 c2 = s_c[j];
+          const float4 x = S.aux[j];  // qb, qc', my, opacity
           const float gw = exp2f(e);
           const float alpha = fminf(set.amax, gw);
           const float om = 1.f - alpha;
           const float Ti = T / om;
-          const float cr = b.z, cg = b.w, cb = c2.x;
+          const float cr = h.y, cg = h.z, cb = h.w;
           const float w = alpha * Ti;
           gr = dC0 * w; gg = dC1 * w; gb = dC2 * w;
           const float dalpha = Ti * (dC0 * (cr - S0) + dC1 * (cg - S1) + dC2 * (cb - S2) -
@@ -202,15 +258,17 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
           B *= om;
           T = Ti;
           if (gw < set.amax) {
-            // weight g = 2^e with e = log2(o) - Q', Q' = (log2e/2) Q
-            gop = dalpha * gw / c2.y;
+            // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
+            // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y
+            const float dy = fy - x.z;
+            gop = dalpha * gw / x.w;
             const float dQ = -kLn2 * gw * dalpha;  // dL/dQ'
-            const float qau = a.z * u;
+            const float qau = h.x * u;
             gqa = dQ * kHalfLog2e * (u * u);
             gqb = -2.f * dQ * qau * dy;
             gqc = dQ * kHalfLog2e * (dy * dy);
             gmx = -2.f * dQ * qau;
-            gmy = 2.f * dQ * (qau * a.w - b.x * dy);
+            gmy = 2.f * dQ * (qau * x.x - x.y * dy);
           }
         }
       }
@@ -219,8 +277,8 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
         gqa = wave_sum_f32(gqa); gqb = wave_sum_f32(gqb); gqc = wave_sum_f32(gqc);
         gop = wave_sum_f32(gop);
         gr = wave_sum_f32(gr); gg = wave_sum_f32(gg); gb = wave_sum_f32(gb);
-        if (lane_id() == 0) {
-          float* dst = grad2d + (size_t)s_g[j] * kGrad2dStride;
+        if (lane == 0) {
+          float* dst = grad2d + (size_t)S.gid[j] * kGrad2dStride;
           atomicAdd(dst + 0, gmx); atomicAdd(dst + 1, gmy);
           atomicAdd(dst + 2, gqa); atomicAdd(dst + 3, gqb); atomicAdd(dst + 4, gqc);
           atomicAdd(dst + 5, gop);

@@ -366,11 +366,37 @@ __global__ __launch_bounds__(kBlock) void k_kg_count(const uint32_t* __restrict_
   if (threadIdx.x == 0) kg_counts[blockIdx.x] = tot;
 }
 
+// Block-wide exclusive max-scan of one u32 per thread (256 threads): the
+// largest value held by any lower thread, 0 for thread 0.
+__device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* s_tmp) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = shfl_u32(incl, lane >= d ? lane - d : lane);
+    if (lane >= d) incl = max(incl, o);
+  }
+  uint32_t excl = shfl_u32(incl, lane > 0 ? lane - 1 : 0);
+  if (lane == 0) excl = 0;
+  if (lane == 63) s_tmp[wave] = incl;
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w)
+    if (w < wave) excl = max(excl, s_tmp[w]);
+  __syncthreads();
+  return excl;
+}
+
+constexpr int kKgWin = 2048;              // instances expanded per window
+constexpr int kKgWinItems = kKgWin / kBlock;
+
 // Instances in depth order: slice p of the depth-sorted visible list starts
 // at kg_prefix[p] (scanned slice counts) and writes (tile id, Gaussian
 // index) for each tile of each rect in row-major order.  The expansion is
-// spread over the workgroup with a binary search over local offsets, so a
-// large splat does not serialise one thread.
+// spread evenly over the workgroup: per window of 2048 instances, each
+// Gaussian marks the position where its run starts (its local index + 1)
+// and a block-wide max-scan hands every position its Gaussian, so large
+// splats do not serialise a thread.
 __global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict__ sorted_idx,
                                                      const uint32_t* __restrict__ vis_count,
                                                      const gs_splat* __restrict__ splats,
@@ -379,14 +405,15 @@ __global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ kg_prefix,
                                                      uint32_t* __restrict__ tkeys,
                                                      uint32_t* __restrict__ tvals) {
-  __shared__ uint32_t s_off[kKgPart + 1];
+  __shared__ uint32_t s_off[kKgPart];
   __shared__ uint32_t s_lo[kKgPart], s_hi[kKgPart], s_g[kKgPart];
+  __shared__ uint32_t s_own[kKgWin];
   __shared__ uint32_t s_tmp[kBlock / 64];
   const int t = threadIdx.x;
   const uint32_t nvis = *vis_count, cap = *inst_count;
   const uint32_t base = blockIdx.x * kKgPart;
   if (base >= nvis) return;
-  uint32_t cnt[kKgItems], sum = 0;
+  uint32_t cnt[kKgItems], off[kKgItems], sum = 0;
 #pragma unroll
   for (int j = 0; j < kKgItems; ++j) {
     const int li = t * kKgItems + j;
@@ -409,31 +436,53 @@ __global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict_
   uint32_t run = block_excl_scan(sum, s_tmp, &btot);
 #pragma unroll
   for (int j = 0; j < kKgItems; ++j) {
+    off[j] = run;
     s_off[t * kKgItems + j] = run;
     run += cnt[j];
   }
-  if (t == 0) s_off[kKgPart] = btot;
-  __syncthreads();
   const uint32_t prefix = kg_prefix[blockIdx.x];
-  for (uint32_t kk = 0; kk < btot; kk += kBlock) {
-    const uint32_t k = kk + t;
-    if (k < btot) {
-      int a = 0, b = kKgPart - 1;
-      while (a < b) {
-        const int mid = (a + b + 1) >> 1;
-        if (s_off[mid] <= k) a = mid; else b = mid - 1;
-      }
-      const uint32_t local = k - s_off[a];
-      const uint32_t rl = s_lo[a], rh = s_hi[a];
-      const uint32_t tx0 = rl & 0xFFFFu, ty0 = rl >> 16, tx1 = rh & 0xFFFFu;
-      const uint32_t w = tx1 - tx0 + 1;
-      const uint32_t ry = local / w;
-      const uint32_t gp = prefix + k;
-      if (gp < cap) {
-        tkeys[gp] = (ty0 + ry) * (uint32_t)tiles_x + tx0 + (local - ry * w);
-        tvals[gp] = s_g[a];
+  for (uint32_t w0 = 0; w0 < btot; w0 += kKgWin) {
+#pragma unroll
+    for (int k = 0; k < kKgWinItems; ++k) s_own[t * kKgWinItems + k] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kKgItems; ++j) {
+      if (cnt[j] && off[j] < w0 + kKgWin && off[j] + cnt[j] > w0)
+        s_own[(off[j] > w0 ? off[j] : w0) - w0] = (uint32_t)(t * kKgItems + j) + 1;
+    }
+    __syncthreads();
+    uint32_t v[kKgWinItems], m = 0;
+#pragma unroll
+    for (int k = 0; k < kKgWinItems; ++k) {
+      v[k] = s_own[t * kKgWinItems + k];
+      m = max(m, v[k]);
+    }
+    uint32_t carry = block_excl_max(m, s_tmp);
+#pragma unroll
+    for (int k = 0; k < kKgWinItems; ++k) {
+      carry = max(carry, v[k]);
+      s_own[t * kKgWinItems + k] = carry;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kKgWinItems; ++k) {
+      const uint32_t q = (uint32_t)(k * kBlock + t);
+      const uint32_t kk = w0 + q;
+      if (kk < btot) {
+        const uint32_t li = s_own[q] - 1;
+        const uint32_t local = kk - s_off[li];
+        const uint32_t rl = s_lo[li], rh = s_hi[li];
+        const uint32_t tx0 = rl & 0xFFFFu, ty0 = rl >> 16, tx1 = rh & 0xFFFFu;
+        const uint32_t w = tx1 - tx0 + 1;
+        const uint32_t ry = local / w;
+        const uint32_t gp = prefix + kk;
+        if (gp < cap) {
+          tkeys[gp] = (ty0 + ry) * (uint32_t)tiles_x + tx0 + (local - ry * w);
+          tvals[gp] = s_g[li];
+        }
       }
     }
+    __syncthreads();
   }
 }
 
