@@ -37,6 +37,12 @@ constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr int kXcds = 8;
 
+// 2^e on the hardware exponential unit.  Only exponents at or above
+// log2(alpha_min) reach it, far from the denormal range, so the library's
+// range reduction is unnecessary; forward and backward share it, so both
+// see the same alpha.
+__device__ __forceinline__ float hw_exp2(float e) { return __builtin_amdgcn_exp2f(e); }
+
 __device__ __forceinline__ int xcd_tile(int b, int tiles) {
   const int chunk = (tiles + kXcds - 1) / kXcds;
   return (b % kXcds) * chunk + b / kXcds;
@@ -44,28 +50,31 @@ __device__ __forceinline__ int xcd_tile(int b, int tiles) {
 
 inline int xcd_grid(int tiles) { return ((tiles + kXcds - 1) / kXcds) * kXcds; }
 
-// LDS staging shared by the forward and backward kernels.
+// LDS staging shared by the forward and backward kernels.  Row terms are
+// stored row-contiguous per splat ([splat][group][row]), so that the writes
+// (consecutive threads on consecutive rows) and a wave's reads (its 8 rows
+// of one splat) both touch consecutive words.
 template <int TW, int TH>
 struct Stage {
   static constexpr int NT = TW * TH;
   static constexpr int QX = TW / 8;          // quadrant columns (= 8-column groups)
   static constexpr int NQ = NT / 64;         // quadrants = waves
   static constexpr int BATCH = NT < 128 ? NT : 128;
-  static constexpr int TPS = NT / BATCH;     // threads per splat while staging
-  static constexpr int RPT = TH / TPS;       // rows each staging thread fills
+  static constexpr int NCH = (BATCH + 63) / 64;  // 64-slot chunks per batch
   float4 hdr[BATCH];          // qa', r, g, b
   float4 aux[BATCH];          // qb, qc', my, opacity
+  float2 ml[BATCH];           // mx, log2(opacity)
   float rt[BATCH][TH];        // log2(o) - qc' dy^2 per tile row
-  float ub[BATCH][TH][QX];    // dx - qb dy at column 0 of each 8-column group
+  float ub[BATCH][QX][TH];    // dx - qb dy at column 0 of each 8-column group
   uint32_t mask[BATCH];       // quadrants the footprint reaches
   uint32_t gid[BATCH];        // Gaussian index
 };
 
-// Stage splat `j` of the batch (this thread's share of its rows).
+// Phase 1 of staging: splat j's parameters, footprint mask and index.
 template <int TW, int TH>
-__device__ __forceinline__ void stage_splat(Stage<TW, TH>& S, int j, int part,
-                                            const gs_splat* __restrict__ splats, uint32_t g,
-                                            int tx0, int ty0, float log2_tau) {
+__device__ __forceinline__ void stage_params(Stage<TW, TH>& S, int j,
+                                             const gs_splat* __restrict__ splats, uint32_t g,
+                                             int tx0, int ty0, float log2_tau) {
   using St = Stage<TW, TH>;
   const float4* rec = reinterpret_cast<const float4*>(splats + g);
   const float4 a = rec[0], b = rec[1];
@@ -73,34 +82,54 @@ __device__ __forceinline__ void stage_splat(Stage<TW, TH>& S, int j, int part,
   const float mx = a.x, my = a.y, qb = a.w;
   const float qa_ = a.z * kHalfLog2e, qc_ = b.x * kHalfLog2e;
   const float lo = log2f(b.y);
-  if (part == 0) {
-    // footprint e >= log2(alpha_min) <=> Q' <= qm; its extents are
-    // |dy| <= sqrt(qm / qc') and |dx| <= sqrt(qm (qb^2 / qc' + 1 / qa')).
-    const float qm = fmaxf(lo - log2_tau, 0.f);
-    float ry = sqrtf(qm / qc_);
-    float rx = sqrtf(qm * (qb * qb / qc_ + 1.f / qa_));
-    ry = ry * (1.f + 1e-4f) + 1e-3f;
-    rx = rx * (1.f + 1e-4f) + 1e-3f;
-    uint32_t m = 0;
+  // footprint e >= log2(alpha_min) <=> Q' <= qm; its extents are
+  // |dy| <= sqrt(qm / qc') and |dx| <= sqrt(qm (qb^2 / qc' + 1 / qa')).
+  const float qm = fmaxf(lo - log2_tau, 0.f);
+  float ry = sqrtf(qm / qc_);
+  float rx = sqrtf(qm * (qb * qb / qc_ + 1.f / qa_));
+  ry = ry * (1.f + 1e-4f) + 1e-3f;
+  rx = rx * (1.f + 1e-4f) + 1e-3f;
+  uint32_t m = 0;
 #pragma unroll
-    for (int q = 0; q < St::NQ; ++q) {
-      const float x0 = tx0 + 8 * (q % St::QX) + 0.5f, y0 = ty0 + 8 * (q / St::QX) + 0.5f;
-      const bool hit = (mx + rx >= x0) && (mx - rx <= x0 + 7.f) && (my + ry >= y0) &&
-                       (my - ry <= y0 + 7.f);
-      m |= hit ? (1u << q) : 0u;
-    }
-    S.hdr[j] = make_float4(qa_, b.z, b.w, c);
-    S.aux[j] = make_float4(qb, qc_, my, b.y);
-    S.mask[j] = m;
-    S.gid[j] = g;
+  for (int q = 0; q < St::NQ; ++q) {
+    const float x0 = tx0 + 8 * (q % St::QX) + 0.5f, y0 = ty0 + 8 * (q / St::QX) + 0.5f;
+    const bool hit = (mx + rx >= x0) && (mx - rx <= x0 + 7.f) && (my + ry >= y0) &&
+                     (my - ry <= y0 + 7.f);
+    m |= hit ? (1u << q) : 0u;
   }
+  S.hdr[j] = make_float4(qa_, b.z, b.w, c);
+  S.aux[j] = make_float4(qb, qc_, my, b.y);
+  S.ml[j] = make_float2(mx, lo);
+  S.mask[j] = m;
+  S.gid[j] = g;
+}
+
+// Phase 2 of staging: the row terms of every staged splat, one (splat, row)
+// pair per thread and step.
+template <int TW, int TH>
+__device__ __forceinline__ void stage_rows(Stage<TW, TH>& S, int cnt, int tx0, int ty0) {
+  using St = Stage<TW, TH>;
+  for (int item = threadIdx.x; item < cnt * TH; item += St::NT) {
+    const int j = item / TH, r = item % TH;
+    const float4 x = S.aux[j];   // qb, qc', my, opacity
+    const float2 ml = S.ml[j];   // mx, log2(opacity)
+    const float dy = (ty0 + r + 0.5f) - x.z;
+    S.rt[j][r] = fmaf(-x.y, dy * dy, ml.y);
 #pragma unroll
-  for (int rr = 0; rr < St::RPT; ++rr) {
-    const int r = part * St::RPT + rr;
-    const float dy = (ty0 + r + 0.5f) - my;
-    S.rt[j][r] = fmaf(-qc_, dy * dy, lo);
+    for (int q = 0; q < St::QX; ++q) S.ub[j][q][r] = fmaf(-x.x, dy, (tx0 + 8 * q + 0.5f) - ml.x);
+  }
+}
+
+// The staged splats whose footprint reaches this wave's quadrant, as one
+// 64-bit mask per 64 batch slots (every lane of the wave must take part).
+template <int TW, int TH>
+__device__ __forceinline__ void quadrant_hits(const Stage<TW, TH>& S, int cnt, int lane,
+                                              uint32_t qbit,
+                                              uint64_t (&hm)[Stage<TW, TH>::NCH]) {
 #pragma unroll
-    for (int q = 0; q < St::QX; ++q) S.ub[j][r][q] = fmaf(-qb, dy, (tx0 + 8 * q + 0.5f) - mx);
+  for (int c = 0; c < Stage<TW, TH>::NCH; ++c) {
+    const int j = c * 64 + lane;
+    hm[c] = ballot(j < cnt && (S.mask[j < cnt ? j : 0] & qbit) != 0u);
   }
 }
 
@@ -133,30 +162,37 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
   bool done = !inside;
   for (uint32_t bs = start; bs < end; bs += St::BATCH) {
     if (__syncthreads_count(done) == St::NT) break;
-    {
-      const int j = tid / St::TPS, part = tid % St::TPS;
-      if (bs + j < end) stage_splat<TW, TH>(S, j, part, splats, values[bs + j], tx0, ty0, log2_tau);
-    }
-    __syncthreads();
     const int cnt = (int)min((uint32_t)St::BATCH, end - bs);
+    if (tid < cnt) stage_params<TW, TH>(S, tid, splats, values[bs + tid], tx0, ty0, log2_tau);
+    __syncthreads();
+    stage_rows<TW, TH>(S, cnt, tx0, ty0);
+    __syncthreads();
+    uint64_t hm[St::NCH];
+    quadrant_hits<TW, TH>(S, cnt, lane, qbit, hm);
     if (!done) {
-      for (int j = 0; j < cnt; ++j) {
-        if (!(__builtin_amdgcn_readfirstlane(S.mask[j]) & qbit)) continue;
-        const float u = S.ub[j][row][qx] + lxf;
-        const float4 h = S.hdr[j];
-        const float e = fmaf(-h.x, u * u, S.rt[j][row]);
-        if (e < log2_tau) continue;  // weight below alpha_min: skipped
-        const float alpha = fminf(set.amax, exp2f(e));
-        const float w = alpha * T;
-        C0 = fmaf(w, h.y, C0);
-        C1 = fmaf(w, h.z, C1);
-        C2 = fmaf(w, h.w, C2);
-        T = T * (1.f - alpha);
-        lastc = bs + j + 1 - start;
-        if (T < set.t_eps) {
-          done = true;
-          break;
+#pragma unroll
+      for (int c = 0; c < St::NCH; ++c) {
+        uint64_t m = hm[c];
+        while (m) {
+          const int j = c * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          const float u = S.ub[j][qx][row] + lxf;
+          const float4 h = S.hdr[j];
+          const float e = fmaf(-h.x, u * u, S.rt[j][row]);
+          if (e < log2_tau) continue;  // weight below alpha_min: skipped
+          const float alpha = fminf(set.amax, hw_exp2(e));
+          const float w = alpha * T;
+          C0 = fmaf(w, h.y, C0);
+          C1 = fmaf(w, h.z, C1);
+          C2 = fmaf(w, h.w, C2);
+          T = T * (1.f - alpha);
+          lastc = bs + j + 1 - start;
+          if (T < set.t_eps) {
+            done = true;
+            break;
+          }
         }
+        if (done) break;
       }
     }
   }
@@ -224,65 +260,70 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
   for (int bi = nb - 1; bi >= 0; --bi) {
     const uint32_t bs = (uint32_t)bi * St::BATCH;
     __syncthreads();
-    {
-      const int j = tid / St::TPS, part = tid % St::TPS;
-      if (bs + j < nlast)
-        stage_splat<TW, TH>(S, j, part, splats, values[start + bs + j], tx0, ty0, log2_tau);
-    }
-    __syncthreads();
     const int cnt = (int)min((uint32_t)St::BATCH, nlast - bs);
-    for (int j = cnt - 1; j >= 0; --j) {
-      if (!(__builtin_amdgcn_readfirstlane(S.mask[j]) & qbit)) continue;
-      float gmx = 0.f, gmy = 0.f, gqa = 0.f, gqb = 0.f, gqc = 0.f, gop = 0.f;
-      float gr = 0.f, gg = 0.f, gb = 0.f;
-      bool contrib = false;
-      if (bs + j < mylast) {
-        const float u = S.ub[j][row][qx] + lxf;
-        const float4 h = S.hdr[j];
-        const float e = fmaf(-h.x, u * u, S.rt[j][row]);
-        if (e >= log2_tau) {
-          contrib = true;
-          const float4 x = S.aux[j];  // qb, qc', my, opacity
-          const float gw = exp2f(e);
-          const float alpha = fminf(set.amax, gw);
-          const float om = 1.f - alpha;
-          const float Ti = T / om;
-          const float cr = h.y, cg = h.z, cb = h.w;
-          const float w = alpha * Ti;
-          gr = dC0 * w; gg = dC1 * w; gb = dC2 * w;
-          const float dalpha = Ti * (dC0 * (cr - S0) + dC1 * (cg - S1) + dC2 * (cb - S2) -
-                                     B * bgdot + dA * B);
-          S0 = fmaf(alpha, cr - S0, S0);
-          S1 = fmaf(alpha, cg - S1, S1);
-          S2 = fmaf(alpha, cb - S2, S2);
-          B *= om;
-          T = Ti;
-          if (gw < set.amax) {
-            // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
-            // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y
-            const float dy = fy - x.z;
-            gop = dalpha * gw / x.w;
-            const float dQ = -kLn2 * gw * dalpha;  // dL/dQ'
-            const float qau = h.x * u;
-            gqa = dQ * kHalfLog2e * (u * u);
-            gqb = -2.f * dQ * qau * dy;
-            gqc = dQ * kHalfLog2e * (dy * dy);
-            gmx = -2.f * dQ * qau;
-            gmy = 2.f * dQ * (qau * x.x - x.y * dy);
+    if (tid < cnt) stage_params<TW, TH>(S, tid, splats, values[start + bs + tid], tx0, ty0, log2_tau);
+    __syncthreads();
+    stage_rows<TW, TH>(S, cnt, tx0, ty0);
+    __syncthreads();
+    uint64_t hm[St::NCH];
+    quadrant_hits<TW, TH>(S, cnt, lane, qbit, hm);
+#pragma unroll
+    for (int c = St::NCH - 1; c >= 0; --c) {
+      uint64_t m = hm[c];
+      while (m) {
+        const int j = c * 64 + 63 - __builtin_clzll(m);
+        m &= ~(1ull << (j - c * 64));
+        float gmx = 0.f, gmy = 0.f, gqa = 0.f, gqb = 0.f, gqc = 0.f, gop = 0.f;
+        float gr = 0.f, gg = 0.f, gb = 0.f;
+        bool contrib = false;
+        if (bs + j < mylast) {
+          const float u = S.ub[j][qx][row] + lxf;
+          const float4 h = S.hdr[j];
+          const float e = fmaf(-h.x, u * u, S.rt[j][row]);
+          if (e >= log2_tau) {
+            contrib = true;
+            const float4 x = S.aux[j];  // qb, qc', my, opacity
+            const float gw = hw_exp2(e);
+            const float alpha = fminf(set.amax, gw);
+            const float om = 1.f - alpha;
+            const float Ti = T / om;
+            const float cr = h.y, cg = h.z, cb = h.w;
+            const float w = alpha * Ti;
+            gr = dC0 * w; gg = dC1 * w; gb = dC2 * w;
+            const float dalpha = Ti * (dC0 * (cr - S0) + dC1 * (cg - S1) + dC2 * (cb - S2) -
+                                       B * bgdot + dA * B);
+            S0 = fmaf(alpha, cr - S0, S0);
+            S1 = fmaf(alpha, cg - S1, S1);
+            S2 = fmaf(alpha, cb - S2, S2);
+            B *= om;
+            T = Ti;
+            if (gw < set.amax) {
+              // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
+              // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y
+              const float dy = fy - x.z;
+              gop = dalpha * gw / x.w;
+              const float dQ = -kLn2 * gw * dalpha;  // dL/dQ'
+              const float qau = h.x * u;
+              gqa = dQ * kHalfLog2e * (u * u);
+              gqb = -2.f * dQ * qau * dy;
+              gqc = dQ * kHalfLog2e * (dy * dy);
+              gmx = -2.f * dQ * qau;
+              gmy = 2.f * dQ * (qau * x.x - x.y * dy);
+            }
           }
         }
-      }
-      if (ballot(contrib)) {
-        gmx = wave_sum_f32(gmx); gmy = wave_sum_f32(gmy);
-        gqa = wave_sum_f32(gqa); gqb = wave_sum_f32(gqb); gqc = wave_sum_f32(gqc);
-        gop = wave_sum_f32(gop);
-        gr = wave_sum_f32(gr); gg = wave_sum_f32(gg); gb = wave_sum_f32(gb);
-        if (lane == 0) {
-          float* dst = grad2d + (size_t)S.gid[j] * kGrad2dStride;
-          atomicAdd(dst + 0, gmx); atomicAdd(dst + 1, gmy);
-          atomicAdd(dst + 2, gqa); atomicAdd(dst + 3, gqb); atomicAdd(dst + 4, gqc);
-          atomicAdd(dst + 5, gop);
-          atomicAdd(dst + 6, gr); atomicAdd(dst + 7, gg); atomicAdd(dst + 8, gb);
+        if (ballot(contrib)) {
+          gmx = wave_sum_f32(gmx); gmy = wave_sum_f32(gmy);
+          gqa = wave_sum_f32(gqa); gqb = wave_sum_f32(gqb); gqc = wave_sum_f32(gqc);
+          gop = wave_sum_f32(gop);
+          gr = wave_sum_f32(gr); gg = wave_sum_f32(gg); gb = wave_sum_f32(gb);
+          if (lane == 0) {
+            float* dst = grad2d + (size_t)S.gid[j] * kGrad2dStride;
+            atomicAdd(dst + 0, gmx); atomicAdd(dst + 1, gmy);
+            atomicAdd(dst + 2, gqa); atomicAdd(dst + 3, gqb); atomicAdd(dst + 4, gqc);
+            atomicAdd(dst + 5, gop);
+            atomicAdd(dst + 6, gr); atomicAdd(dst + 7, gg); atomicAdd(dst + 8, gb);
+          }
         }
       }
     }
