@@ -21,9 +21,17 @@ if ROOT not in sys.path:
 METRIC = "frames/sec @1080p, 1M–6M Gaussians, fwd and fwd+bwd; sort Gkeys/s; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# FP32 operations Eqs. 2-3 need per composited (pixel, Gaussian) pair:
+# offset 2, quadratic form with the conic 7, o*exp(-Q/2) 3, clamp + skip
+# test 2, T*alpha and the three colour FMAs 7, T *= 1 - alpha 2, stop test 1.
+FLOPS_PER_BLEND = 24
+
 SORT_KERNELS = ("sort_init", "radix_hist", "depth_pass", "kg_count", "kg_scan", "keygen",
                 "tile_pass", "tile_ranges")
-HBM_KERNELS = ("preprocess", "depth_pass", "keygen", "kg_count", "tile_pass", "tile_ranges")
+HBM_KERNELS = ("preprocess", "depth_pass", "keygen", "kg_count", "tile_pass", "tile_ranges",
+               "preprocess_bwd")
+ALU_KERNELS = ("raster", "raster_bwd")
 
 WORKLOADS = {
     "tiny": "tiny: 4,096 Gaussians, SH degree 0, 256x256, forward",
@@ -82,7 +90,29 @@ def algorithmic_bytes(n, n_vis, inst, K, W, H, tiles):
         "tile_ranges": inst * 4 + tiles * 8,
         # value + 48 B record gathered per instance, RGBA + T + last written per pixel
         "raster": inst * (4 + 48) + tiles * 8 + W * H * 24,
+        # parameters (44 B) + SH (12K) + 2-D gradient record (48) read and all
+        # parameter gradients (44 + 12K) written per visible Gaussian
+        "preprocess_bwd": n_vis * (44 + 12 * K + 48 + 44 + 12 * K),
     }
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE + WRITE_SIZE passes (copy-calibrated), or None when there are
+    none for this workload or the kernel's sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        rec = json.load(open(path))[workload][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_2512_08478_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return int(rec["bytes_per_launch"])
 
 
 def main():
@@ -156,6 +186,12 @@ def main():
     kern_ms = {k: acc[k] / reps for k in acc}          # per frame (all passes)
     kern_avg = {k: acc[k] / cnt[k] for k in acc}       # per launch
 
+    # composited (pixel, Gaussian) pairs of this frame, for the compositing roofline
+    nbl = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    R.rasterize(f.splats, f.values, f.ranges, cam, n_blend=nbl)
+    blends = int(nbl.sum(dtype=torch.int64).item())
+    del nbl
+
     rec = f.splats[: sc.n * 48].cpu().numpy().view(np.uint16).reshape(sc.n, 24)
     n_vis = int(np.count_nonzero(rec[:, 22] >= rec[:, 20]))
     K = (sc.sh_degree + 1) ** 2
@@ -171,14 +207,30 @@ def main():
             gbs = ab[k] / (v * 1e-3) / 1e9
             e.update(algo_bytes=int(ab[k]), gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
         stages[k] = e
+    # compositing: blended pairs x FLOPS_PER_BLEND (the backward revisits
+    # every blended pair once more, with roughly twice the arithmetic)
+    flops = {"raster": blends * FLOPS_PER_BLEND, "raster_bwd": blends * 2 * FLOPS_PER_BLEND}
+    for k in ALU_KERNELS:
+        if k in stages:
+            tf = flops[k] / (kern_avg[k] * 1e-3) / 1e12
+            stages[k].update(algo_flops=int(flops[k]), tflops=round(tf, 3),
+                             alu_frac=round(tf / FP32_VECTOR_PEAK_TFLOPS, 4))
     sort_ms = sum(kern_ms.get(k, 0.0) for k in SORT_KERNELS)
-    # dominant HBM-bound kernel by time per frame
-    hbm_kernels = [k for k in HBM_KERNELS if k in kern_ms]
-    dom = max(hbm_kernels, key=lambda k: kern_ms[k])
-    dom_gbs = ab[dom] / (kern_avg[dom] * 1e-3) / 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "algo_bytes_per_launch": int(ab[dom])}
+    # roofline of the kernel that takes the most time per frame
+    dom = max(kern_ms, key=lambda k: kern_ms[k])
+    if dom in ALU_KERNELS:
+        tf = flops[dom] / (kern_avg[dom] * 1e-3) / 1e12
+        roofline = {"kernel": dom, "bound": "alu", "achieved": round(tf, 3),
+                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                    "algo_flops_per_launch": int(flops[dom]), "blended_pairs": blends}
+    else:
+        dom_gbs = ab[dom] / (kern_avg[dom] * 1e-3) / 1e9
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dom_gbs, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+                    "traffic": None, "algo_bytes_per_launch": int(ab[dom])}
+    roofline["ms_per_launch"] = round(kern_avg[dom], 5)
+    roofline["traffic"] = measured_traffic(args.workload, dom)
 
     out = {
         "metric": METRIC,

@@ -242,11 +242,14 @@ int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in,
  * Writes image[H*W*4] (RGB = C + T*bg, A = 1 - T), T_final[H*W] and
  * last[H*W] (u32: one past the position, within the tile's sorted range,
  * of the last splat blended into the pixel; used by the backward pass).
+ * n_blend[H*W] (u32, optional: NULL skips it) receives the number of
+ * splats blended into each pixel, i.e. the count of (pixel, Gaussian)
+ * pairs Eq. 3 actually composites.
  */
 int32_t gs_rasterize(const gs_splat* splats, const uint32_t* values,
                      const uint32_t* tile_ranges, const gs_camera* cam,
                      const gs_settings* set, float* image, float* T_final,
-                     uint32_t* last, void* stream);
+                     uint32_t* last, uint32_t* n_blend, void* stream);
 
 /*
  * gs_rasterize_backward -- gradients of a loss L through Eqs. 1-3

@@ -93,7 +93,7 @@ def load():
     lib.gs_sort_pairs.restype = I32
     lib.gs_sort_pairs.argtypes = [I64, P, P, I32, P, P, SET, P, SZ, P]
     lib.gs_rasterize.restype = I32
-    lib.gs_rasterize.argtypes = [P, P, P, CAM, SET, P, P, P, P]
+    lib.gs_rasterize.argtypes = [P, P, P, CAM, SET, P, P, P, P, P]
     lib.gs_rasterize_backward.restype = I32
     lib.gs_rasterize_backward.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, P, P,
                                           P, P, P, P, P, I32, P, SZ, P]

@@ -412,18 +412,18 @@ int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in, const uint32_t* values
 
 int32_t gs_rasterize(const gs_splat* splats, const uint32_t* values, const uint32_t* tile_ranges,
                      const gs_camera* cam, const gs_settings* set, float* image, float* T_final,
-                     uint32_t* last, void* stream) {
+                     uint32_t* last, uint32_t* n_blend, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if ((r = check_dev(splats, false)) || (r = check_dev(values, false)) ||
       (r = check_dev(tile_ranges)) || (r = check_dev(image)) || (r = check_dev(T_final)) ||
-      (r = check_dev(last)))
+      (r = check_dev(last)) || (n_blend && (r = check_dev(n_blend))))
     return r;
   const gs::SetK sk = make_setk(cam, set);
   hipStream_t st = static_cast<hipStream_t>(stream);
   gs::trace_mark(st, "raster");
   hipError_t e = gs::launch_rasterize(splats, values, tile_ranges, sk, cam->width, cam->height,
-                                      image, T_final, last, st);
+                                      image, T_final, last, n_blend, st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;

@@ -98,7 +98,8 @@ hipError_t launch_compose_keys(int64_t capacity, const uint32_t* count, const ui
                                hipStream_t st);
 hipError_t launch_rasterize(const gs_splat* splats, const uint32_t* values,
                             const uint32_t* ranges, const SetK& set, int W, int H,
-                            float* image, float* T_final, uint32_t* last, hipStream_t st);
+                            float* image, float* T_final, uint32_t* last, uint32_t* n_blend,
+                            hipStream_t st);
 hipError_t launch_rasterize_backward(const gs_splat* splats, const uint32_t* values,
                                      const uint32_t* ranges, const SetK& set, int W, int H,
                                      const float* T_final, const uint32_t* last,

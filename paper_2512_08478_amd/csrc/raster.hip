@@ -140,7 +140,8 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
                                                    SetK set, int W, int H,
                                                    float* __restrict__ image,
                                                    float* __restrict__ T_final,
-                                                   uint32_t* __restrict__ last) {
+                                                   uint32_t* __restrict__ last,
+                                                   uint32_t* __restrict__ n_blend) {
   using St = Stage<TW, TH>;
   __shared__ St S;
   const int tiles = set.tiles_x * set.tiles_y;
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
   const float log2_tau = set.log2_tau;
 
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  uint32_t lastc = 0;
+  uint32_t lastc = 0, nb = 0;
   bool done = !inside;
   for (uint32_t bs = start; bs < end; bs += St::BATCH) {
     if (__syncthreads_count(done) == St::NT) break;
@@ -187,6 +188,7 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
           C2 = fmaf(w, h.w, C2);
           T = T * (1.f - alpha);
           lastc = bs + j + 1 - start;
+          ++nb;
           if (T < set.t_eps) {
             done = true;
             break;
@@ -202,6 +204,7 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
         make_float4(fmaf(T, set.bg[0], C0), fmaf(T, set.bg[1], C1), fmaf(T, set.bg[2], C2), 1.f - T);
     T_final[p] = T;
     last[p] = lastc;
+    if (n_blend) n_blend[p] = nb;
   }
 }
 
@@ -333,10 +336,10 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
 template <int TW, int TH>
 void raster_fwd(const gs_splat* splats, const uint32_t* values, const uint32_t* ranges,
                 const SetK& set, int W, int H, float* image, float* T_final, uint32_t* last,
-                hipStream_t st) {
+                uint32_t* n_blend, hipStream_t st) {
   const int tiles = set.tiles_x * set.tiles_y;
   hipLaunchKernelGGL((k_raster<TW, TH>), dim3(xcd_grid(tiles)), dim3(TW * TH), 0, st, splats,
-                     values, ranges, set, W, H, image, T_final, last);
+                     values, ranges, set, W, H, image, T_final, last, n_blend);
 }
 
 template <int TW, int TH>
@@ -357,13 +360,14 @@ bool tile_shape_supported(int tw, int th) {
 
 hipError_t launch_rasterize(const gs_splat* splats, const uint32_t* values,
                             const uint32_t* ranges, const SetK& set, int W, int H,
-                            float* image, float* T_final, uint32_t* last, hipStream_t st) {
+                            float* image, float* T_final, uint32_t* last, uint32_t* n_blend,
+                            hipStream_t st) {
   const int tw = set.tile_w, th = set.tile_h;
-  if (tw == 8 && th == 8) raster_fwd<8, 8>(splats, values, ranges, set, W, H, image, T_final, last, st);
-  else if (tw == 16 && th == 8) raster_fwd<16, 8>(splats, values, ranges, set, W, H, image, T_final, last, st);
-  else if (tw == 16 && th == 16) raster_fwd<16, 16>(splats, values, ranges, set, W, H, image, T_final, last, st);
-  else if (tw == 32 && th == 8) raster_fwd<32, 8>(splats, values, ranges, set, W, H, image, T_final, last, st);
-  else raster_fwd<32, 16>(splats, values, ranges, set, W, H, image, T_final, last, st);
+  if (tw == 8 && th == 8) raster_fwd<8, 8>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
+  else if (tw == 16 && th == 8) raster_fwd<16, 8>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
+  else if (tw == 16 && th == 16) raster_fwd<16, 16>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
+  else if (tw == 32 && th == 8) raster_fwd<32, 8>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
+  else raster_fwd<32, 16>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
   return hipGetLastError();
 }
 

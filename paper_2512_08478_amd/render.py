@@ -127,15 +127,20 @@ class Renderer:
         L.check(st, "gs_sort")
         return keys, values, ranges, flag, capacity
 
-    def rasterize(self, splats, values, ranges, cam):
+    def rasterize(self, splats, values, ranges, cam, n_blend=None):
+        """Eqs. 2-3.  `n_blend`, if given, is an int32 (H, W) tensor that
+        receives the number of splats blended into each pixel."""
         lib = L.load()
         c, s = L.make_camera(cam), self.settings
         H, W = cam.height, cam.width
         image = torch.empty((H, W, 4), dtype=torch.float32, device=self.device)
         T = torch.empty((H, W), dtype=torch.float32, device=self.device)
         last = torch.empty((H, W), dtype=torch.int32, device=self.device)
+        if n_blend is not None:
+            assert n_blend.shape == (H, W) and n_blend.dtype == torch.int32 and n_blend.is_contiguous()
         st = lib.gs_rasterize(_p(splats), _p(values), _p(ranges), ctypes.byref(c), ctypes.byref(s),
-                              _p(image), _p(T), _p(last), _stream())
+                              _p(image), _p(T), _p(last), _p(n_blend) if n_blend is not None else None,
+                              _stream())
         L.check(st, "gs_rasterize")
         return image, T, last
 

@@ -154,9 +154,13 @@ def test_sort_argument_validation(lib):
 def test_raster_argument_validation(lib):
     c, s = cam_1080(), L.default_settings()
     F = ctypes.c_void_p(FAKE)
-    r = lib.gs_rasterize(F, F, F, ctypes.byref(c), ctypes.byref(s), None, F, F, None)
+    r = lib.gs_rasterize(F, F, F, ctypes.byref(c), ctypes.byref(s), None, F, F, None, None)
     assert r == L.GS_ERR_INVALID_ARGUMENT
-    r = lib.gs_rasterize(F, F, ctypes.c_void_p(FAKE + 2), ctypes.byref(c), ctypes.byref(s), F, F, F, None)
+    r = lib.gs_rasterize(F, F, ctypes.c_void_p(FAKE + 2), ctypes.byref(c), ctypes.byref(s), F, F, F,
+                         None, None)
+    assert r == L.GS_ERR_MISALIGNED
+    r = lib.gs_rasterize(F, F, F, ctypes.byref(c), ctypes.byref(s), F, F, F,
+                         ctypes.c_void_p(FAKE + 2), None)
     assert r == L.GS_ERR_MISALIGNED
     r = lib.gs_rasterize_backward(4, F, F, F, F, F, 7, None, ctypes.byref(c), ctypes.byref(s),
                                   F, F, F, F, F, F, F, F, F, F, F, 0, F, 1 << 20, None)

@@ -99,5 +99,11 @@ def test_backward_accumulate(R):
     g1 = R.backward(p, cam, fr, G)
     g1 = [t.clone() for t in g1]
     g2 = R.backward(p, cam, fr, G, out=[t.clone() for t in g1], accumulate=True)
-    for a, b in zip(g1, g2):
-        np.testing.assert_allclose(b.cpu().numpy(), 2 * a.cpu().numpy(), rtol=1e-5, atol=1e-8)
+    # the second pass adds a fresh backward whose float atomics may sum in
+    # another order, so compare against the magnitude of each gradient
+    for name, a, b in zip(("means", "log_scales", "quats", "opacity", "sh"), g1, g2):
+        a, b = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+        scale = max(np.abs(a).max(), 1e-30)
+        d = np.abs(b - 2 * a).max() / scale
+        print(f"{name}: max |g2 - 2 g1| / max |g1| = {d:.2e}")
+        assert d <= 1e-5, (name, d)

@@ -253,6 +253,30 @@ def test_render_tiny_whole_image(R, orc):
     np.testing.assert_allclose(T[flat["margin"] >= 1e-5], flat["T"][flat["margin"] >= 1e-5], atol=1e-4)
 
 
+def test_blend_counts_match_oracle(R, orc):
+    """The optional per-pixel blend count equals the oracle's count of
+    composited Gaussians wherever no decision is within rounding of a
+    threshold, and requesting it leaves the image bitwise unchanged."""
+    print_case("n_blend tiny 256x256 + 1M sampled")
+    for sc, cam, pix in ((*S.tiny_scene(), None), (*S.medium_scene(), "sample")):
+        fr = R.forward(gp(sc), cam)
+        nb = torch.empty((cam.height, cam.width), dtype=torch.int32, device="cuda")
+        img2, T2, last2 = R.rasterize(fr.splats, fr.values, fr.ranges, cam, n_blend=nb)
+        assert torch.equal(img2, fr.image) and torch.equal(last2, fr.last)
+        if pix is None:
+            pix = orc.all_pixels(cam)
+        else:
+            pix = sampled_pixels(cam, 256, 21)
+        ref = orc.render_pixels(orc.preprocess(sc, cam), cam, pix)
+        got = nb.cpu().numpy()[pix[:, 1], pix[:, 0]]
+        ok = (ref["margin"] >= 1e-5) & (ref["flags"] == 0)
+        assert ok.mean() > 0.9
+        np.testing.assert_array_equal(got[ok], ref["n_blend"][ok])
+        last = fr.last.cpu().numpy()[pix[:, 1], pix[:, 0]]
+        assert (got <= last).all()
+        print(f"n_blend mean {got.mean():.1f}, checked {int(ok.sum())} px")
+
+
 def sampled_pixels(cam, n, seed):
     rng = np.random.default_rng(seed)
     pix = np.stack([rng.integers(0, cam.width, n), rng.integers(0, cam.height, n)], 1)
