@@ -189,6 +189,37 @@ int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales,
                       void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * One asset of a multi-asset scene (Algorithm 1 loops over models, each with
+ * its own model matrix M_k, and feeds all of them to one global sort).  The
+ * assets' Gaussians are concatenated in the parameter arrays: asset a owns
+ * indices [offset, offset + count).  model: HOST pointer to the asset's 3x4
+ * row-major similarity transform, or NULL for the identity.
+ */
+typedef struct gs_asset {
+  int64_t offset;
+  int64_t count;
+  const float* model;
+} gs_asset;
+
+/*
+ * gs_preprocess_assets -- gs_preprocess over n_assets assets (1 to 64) whose
+ * Gaussians are concatenated (assets[0].offset = 0, each asset starts where
+ * the previous one ends, the counts sum to n; otherwise
+ * GS_ERR_INVALID_ARGUMENT).  Record i, depth_keys[i] and the sort values
+ * refer to the global index i, so one gs_sort / gs_rasterize call renders
+ * every asset with a single global depth order.  counts[] sums over all
+ * assets.  Same workspace as gs_preprocess for n Gaussians.  Each asset is
+ * one kernel launch; assets with count 0 launch nothing.
+ */
+int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n,
+                             const float* means, const float* log_scales,
+                             const float* quats, const float* opacity_logits,
+                             const float* sh, int32_t sh_degree, const gs_camera* cam,
+                             const gs_settings* set, gs_splat* splats,
+                             uint32_t* depth_keys, uint32_t* counts, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/*
  * gs_sort -- key generation and the per-frame GPU radix sort (Algorithm 1,
  * Radix Sort; Section 3.4).  The sort order is that of the 64-bit keys
  *     key = tile_id << 32 | bits(float32 depth)
@@ -275,6 +306,23 @@ int32_t gs_rasterize_backward(
     const float* dL_dimage, float* d_means, float* d_log_scales,
     float* d_quats, float* d_opacity_logits, float* d_sh, int32_t accumulate,
     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * gs_rasterize_backward_assets -- gs_rasterize_backward for a frame made by
+ * gs_preprocess_assets with the same asset table: the compositing backward
+ * runs once over the global records, then each asset's chain rule uses its
+ * own model transform.  Gradient arrays are indexed like the inputs
+ * (concatenated assets).
+ */
+int32_t gs_rasterize_backward_assets(
+    int32_t n_assets, const gs_asset* assets, int64_t n, const float* means,
+    const float* log_scales, const float* quats, const float* opacity_logits,
+    const float* sh, int32_t sh_degree, const gs_camera* cam, const gs_settings* set,
+    const gs_splat* splats, const uint32_t* values, const uint32_t* tile_ranges,
+    const float* T_final, const uint32_t* last, const float* dL_dimage,
+    float* d_means, float* d_log_scales, float* d_quats, float* d_opacity_logits,
+    float* d_sh, int32_t accumulate, void* workspace, size_t workspace_bytes,
+    void* stream);
 
 #ifdef __cplusplus
 }

@@ -156,11 +156,11 @@ def preprocess(scene, cam, settings=None, f64_inputs=False) -> Records:
     return Records(d, iv)
 
 
-def preprocess_many(scenes, cam, settings=None) -> Records:
+def preprocess_many(scenes, cam, settings=None, f64_inputs=False) -> Records:
     """Records of several assets, concatenated in order (one global list)."""
     recs = None
     for s in scenes:
-        r = preprocess(s, cam, settings)
+        r = preprocess(s, cam, settings, f64_inputs)
         recs = r if recs is None else recs.concat(r)
     return recs
 

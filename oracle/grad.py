@@ -148,12 +148,24 @@ def render_and_grad(scene, cam, pix, dL_drgba, settings=None, chunk=64):
 
     Returns (rgba numpy (P,4), dict of float64 numpy gradients with keys
     means, log_scales, quats, opacity_logits, sh)."""
+    rgba, grads = render_and_grad_assets([scene], cam, pix, dL_drgba, settings, chunk)
+    return rgba, grads[0]
+
+
+def render_and_grad_assets(scenes, cam, pix, dL_drgba, settings=None, chunk=64):
+    """As render_and_grad for several assets rendered together: every asset
+    is projected with its own model transform and all visible Gaussians are
+    composited in one global (depth, global index) order, the global index
+    running over the assets in list order (Algorithm 1's single sort over
+    all models).  Returns (rgba (P,4), [gradient dict per asset])."""
     st = _settings(settings)
     pix = np.asarray(pix, np.int64).reshape(-1, 2)
     G = torch.as_tensor(np.asarray(dL_drgba, np.float64).reshape(-1, 4), dtype=_F)
-    params = scene_tensors(scene)
+    params = [scene_tensors(sc) for sc in scenes]
+    offs = np.cumsum([0] + [sc.n for sc in scenes])
     with torch.no_grad():
-        p = project(*params, scene.sh_degree, scene.model, cam, st)
+        ps = [project(*params[a], sc.sh_degree, sc.model, cam, st) for a, sc in enumerate(scenes)]
+        p = {k: torch.cat([q[k] for q in ps]) for k in ps[0]}
         vis = torch.nonzero(p["ok"]).flatten().numpy()
         depth = p["depth"].numpy()
         order = vis[np.lexsort((vis, depth[vis]))]
@@ -167,9 +179,25 @@ def render_and_grad(scene, cam, pix, dL_drgba, settings=None, chunk=64):
             used |= m.any(0).numpy()
         cols = np.nonzero(used)[0]
         mask = torch.cat(masks, 0)[:, torch.as_tensor(cols)] if len(cols) else torch.zeros((len(pix), 0), dtype=torch.bool)
-    sel = torch.as_tensor(order[cols], dtype=torch.int64)
-    sub = [t.index_select(0, sel) for t in params]
-    q = project(*sub, scene.sh_degree, scene.model, cam, st)
+    gsel = order[cols]  # global indices of the blending Gaussians, in blend order
+    parts = []
+    for a, sc in enumerate(scenes):
+        loc = gsel[(gsel >= offs[a]) & (gsel < offs[a + 1])] - offs[a]
+        if len(loc) == 0:
+            continue
+        sel = torch.as_tensor(loc, dtype=torch.int64)
+        sub = [t.index_select(0, sel) for t in params[a]]
+        parts.append((offs[a] + loc, project(*sub, sc.sh_degree, sc.model, cam, st)))
+    if parts:
+        # back to blend order
+        gidx = np.concatenate([g for g, _ in parts])
+        q = {k: torch.cat([d[k] for _, d in parts]) for k in ("mean2d", "conic", "opacity", "rgb")}
+        where = {int(g): i for i, g in enumerate(gidx)}
+        perm = torch.as_tensor([where[int(g)] for g in gsel], dtype=torch.int64)
+        q = {k: v.index_select(0, perm) for k, v in q.items()}
+    else:
+        q = {"mean2d": torch.zeros((0, 2), dtype=_F), "conic": torch.zeros((0, 3), dtype=_F),
+             "opacity": torch.zeros(0, dtype=_F), "rgb": torch.zeros((0, 3), dtype=_F)}
     pp = torch.as_tensor(pix + 0.5, dtype=_F)
     a = torch.clamp(_weights(q, pp[:, 0], pp[:, 1]), max=st["alpha_max"]) * mask
     one_m = 1.0 - a
@@ -179,9 +207,14 @@ def render_and_grad(scene, cam, pix, dL_drgba, settings=None, chunk=64):
     bg = torch.as_tensor(np.asarray(st["bg"], np.float64), dtype=_F)
     rgba = torch.cat([C + Tf[:, None] * bg[None], (1.0 - Tf)[:, None]], 1)
     L = (G * rgba).sum()
-    grads = torch.autograd.grad(L, params, allow_unused=True)
+    flat = [t for ts in params for t in ts]
+    grads = torch.autograd.grad(L, flat, allow_unused=True) if L.requires_grad else [None] * len(flat)
     names = ["means", "log_scales", "quats", "opacity_logits", "sh"]
-    out = {}
-    for nm, g, t in zip(names, grads, params):
-        out[nm] = np.zeros(t.shape) if g is None else g.detach().numpy()
+    out = []
+    for a in range(len(scenes)):
+        d = {}
+        for k, nm in enumerate(names):
+            g, t = grads[5 * a + k], params[a][k]
+            d[nm] = np.zeros(t.shape) if g is None else g.detach().numpy()
+        out.append(d)
     return rgba.detach().numpy(), out

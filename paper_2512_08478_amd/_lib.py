@@ -30,7 +30,9 @@ EXPORTED = (
     "gs_version", "gs_status_string", "gs_last_hip_error", "gs_default_settings",
     "gs_workspace_size", "gs_sort_key_bits", "gs_preprocess", "gs_sort", "gs_sort_pairs",
     "gs_rasterize", "gs_rasterize_backward", "gs_trace_enable", "gs_trace_read",
+    "gs_preprocess_assets", "gs_rasterize_backward_assets",
 )
+MAX_ASSETS = 64
 
 
 class GsLibraryMissing(RuntimeError):
@@ -58,6 +60,26 @@ class GsSettings(ctypes.Structure):
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_eps", ctypes.c_float), ("clip", ctypes.c_float), ("bg", ctypes.c_float * 3),
                 ("radix_bits", ctypes.c_int32), ("sort_mode", ctypes.c_int32)]
+
+
+class GsAsset(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("count", ctypes.c_int64),
+                ("model", ctypes.POINTER(ctypes.c_float))]
+
+
+def asset_table(assets):
+    """ctypes array of GsAsset from [(offset, count, model 3x4 or None)].
+    Returns (array, keep-alive list of model buffers)."""
+    arr = (GsAsset * max(1, len(assets)))()
+    keep = []
+    for a, (off, cnt, model) in enumerate(assets):
+        arr[a].offset = int(off)
+        arr[a].count = int(cnt)
+        if model is not None:
+            m = model_array(model)
+            keep.append(m)
+            arr[a].model = ctypes.cast(m, ctypes.POINTER(ctypes.c_float))
+    return arr, keep
 
 
 _lib = None
@@ -97,6 +119,13 @@ def load():
     lib.gs_rasterize_backward.restype = I32
     lib.gs_rasterize_backward.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, P, P,
                                           P, P, P, P, P, I32, P, SZ, P]
+    AS = ctypes.POINTER(GsAsset)
+    lib.gs_preprocess_assets.restype = I32
+    lib.gs_preprocess_assets.argtypes = [I32, AS, I64, P, P, P, P, P, I32, CAM, SET, P, P, P, P,
+                                         SZ, P]
+    lib.gs_rasterize_backward_assets.restype = I32
+    lib.gs_rasterize_backward_assets.argtypes = [I32, AS, I64, P, P, P, P, P, I32, CAM, SET, P, P,
+                                                 P, P, P, P, P, P, P, P, P, I32, P, SZ, P]
     lib.gs_trace_enable.restype = I32
     lib.gs_trace_enable.argtypes = [I32]
     lib.gs_trace_read.restype = I32

@@ -1,0 +1,180 @@
+"""Batched multi-view, multi-asset forward + backward in one HIP graph.
+
+Every view renders all assets of the scene with one global depth order
+(Algorithm 1 feeds every model's Gaussians to one sort), then runs the
+hand-written backward; gradients of all views add up in one set of
+parameter-gradient buffers.  `BatchRenderer.capture()` records the whole
+batch -- every view's preprocess, sort, compositing, loss gradient and
+backward -- into one HIP graph (through torch's graph capture, on the
+library's stream), so a step is a single graph launch with no host
+synchronisation.  Instance capacities are planned beforehand from one
+counting pass; a view that exceeds its capacity raises its overflow flag,
+which `replay()` checks.
+
+`autotune()` picks the tile shape and the radix digit width (and sort mode)
+by timing whole batches.  Images do not depend on these choices (every tile
+shape composites the same pairs in the same order with the same
+arithmetic), so tuning never changes results.
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from .render import GaussianParams, Renderer
+
+TILE_SHAPES = ((16, 16), (16, 8), (32, 8), (8, 8), (32, 16))
+RADIX_BITS = (8, 7, 6)
+SORT_MODES = (0, 1)
+
+
+def l1_grad(image, target):
+    """dL/dRGBA of L = mean |RGB - target| over (H, W, 3); alpha gets none."""
+    H, W = target.shape[:2]
+    g = torch.zeros((H, W, 4), dtype=torch.float32, device=image.device)
+    g[..., :3] = torch.sign(image[..., :3] - target) / (3.0 * H * W)
+    return g
+
+
+class BatchRenderer:
+    """Views x assets forward + backward with fixed per-view capacities."""
+
+    def __init__(self, params: GaussianParams, cams, targets, settings=None, headroom=1.10,
+                 device="cuda"):
+        if len(cams) != len(targets):
+            raise ValueError("one target image per view")
+        self.p = params
+        self.cams = list(cams)
+        self.targets = [t.to(device=device, dtype=torch.float32).contiguous() for t in targets]
+        self.R = Renderer(settings, device)
+        self.headroom = headroom
+        self.capacity = None
+        self.graph = None
+        self.images = None
+        self.grads = tuple(torch.zeros_like(t) for t in params.tensors())
+        self.flags = torch.zeros(len(self.cams), dtype=torch.int32, device=device)
+
+    @property
+    def settings(self):
+        s = self.R.settings
+        return dict(tile_w=s.tile_w, tile_h=s.tile_h, radix_bits=s.radix_bits,
+                    sort_mode=s.sort_mode)
+
+    def plan(self):
+        """Per-view instance capacities from one counting pass (syncs once per view)."""
+        caps = []
+        for cam in self.cams:
+            _, _, counts = self.R.preprocess(self.p, cam)
+            caps.append(int(counts[:1].item()) & 0xFFFFFFFF)
+        self.capacity = [max(256, int(c * self.headroom)) for c in caps]
+        return list(caps)
+
+    def _enqueue(self):
+        """All views' forward + backward on the current stream; no host sync."""
+        images = []
+        for v, cam in enumerate(self.cams):
+            fr = self.R.forward(self.p, cam, capacity=self.capacity[v])
+            self.flags[v:v + 1].copy_(fr.flag)
+            g = l1_grad(fr.image, self.targets[v])
+            self.R.backward(self.p, cam, fr, g, out=self.grads, accumulate=v > 0)
+            images.append(fr.image)
+        return images
+
+    def run_eager(self):
+        """One batch without a graph (sizes every reusable buffer)."""
+        if self.capacity is None:
+            self.plan()
+        self.images = self._enqueue()
+        return self.images
+
+    def capture(self):
+        """Record the whole batch into one HIP graph."""
+        if self.capacity is None:
+            self.plan()
+        # an eager pass first: grows every reusable buffer to its final size,
+        # so nothing is reallocated while capturing
+        self.run_eager()
+        torch.cuda.synchronize()
+        self._check_flags()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.images = self._enqueue()
+        self.graph = g
+        return g
+
+    def replay(self, check=True):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+        if check:
+            torch.cuda.synchronize()
+            self._check_flags()
+        return self.images
+
+    def _check_flags(self):
+        bad = torch.nonzero(self.flags & 1).flatten().tolist()
+        if bad:
+            raise RuntimeError(f"instance capacity exceeded in views {bad}; plan() again "
+                               f"with more headroom")
+
+
+def plain_views(params: GaussianParams, cams, targets, settings=None, renderer=None):
+    """The plain path: view by view, each reading its instance count back
+    (one sync) before sorting, gradients accumulated over views."""
+    R = renderer or Renderer(settings)
+    grads = tuple(torch.zeros_like(t) for t in params.tensors())
+    images = []
+    for v, cam in enumerate(cams):
+        fr = R.forward(params, cam)
+        g = l1_grad(fr.image, targets[v].to(device=fr.image.device, dtype=torch.float32))
+        R.backward(params, cam, fr, g, out=grads, accumulate=v > 0)
+        images.append(fr.image.clone())
+    return images, grads
+
+
+def _time_batch(br: BatchRenderer, reps: int):
+    br.run_eager()
+    torch.cuda.synchronize()
+    br._check_flags()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        br.run_eager()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
+             tiles=TILE_SHAPES, bits=RADIX_BITS, modes=SORT_MODES, log=None):
+    """Coordinate search: tile shape (at 8-bit digits, mode 0), then digit
+    width, then sort mode, each by the wall time of whole eager batches.
+    Returns (settings dict, [(settings, seconds)])."""
+    base = dict(base_settings or {})
+    table = []
+
+    def measure(over):
+        s = dict(base, **over)
+        br = BatchRenderer(params, cams, targets, s)
+        br.plan()
+        t = _time_batch(br, reps)
+        table.append((dict(over), t))
+        if log:
+            log(f"autotune {over}: {t * 1e3:.2f} ms per batch")
+        del br
+        return t
+
+    best = dict(tile_w=tiles[0][0], tile_h=tiles[0][1], radix_bits=bits[0], sort_mode=modes[0])
+    best_t = None
+    for tw, th in tiles:
+        t = measure(dict(best, tile_w=tw, tile_h=th))
+        if best_t is None or t < best_t:
+            best_t, best = t, dict(best, tile_w=tw, tile_h=th)
+    for b in bits[1:]:
+        t = measure(dict(best, radix_bits=b))
+        if t < best_t:
+            best_t, best = t, dict(best, radix_bits=b)
+    for m in modes[1:]:
+        t = measure(dict(best, sort_mode=m))
+        if t < best_t:
+            best_t, best = t, dict(best, sort_mode=m)
+    return dict(base, **best), table

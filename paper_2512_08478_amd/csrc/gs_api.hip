@@ -9,7 +9,7 @@ namespace gs {
 bool tile_shape_supported(int tw, int th);
 
 namespace {
-constexpr int kTraceMax = 512;
+constexpr int kTraceMax = 4096;
 struct Tracer {
   bool on = false;
   bool created = false;
@@ -175,6 +175,17 @@ int32_t check_inputs(int64_t n, const float* means, const float* log_scales, con
   return GS_OK;
 }
 
+// assets must tile [0, n) in order: offset_0 = 0, offset_{a+1} = offset_a + count_a
+int32_t check_assets(int32_t n_assets, const gs_asset* assets, int64_t n) {
+  if (n_assets < 1 || n_assets > gs::kMaxAssets || !assets) return GS_ERR_INVALID_ARGUMENT;
+  int64_t next = 0;
+  for (int a = 0; a < n_assets; ++a) {
+    if (assets[a].offset != next || assets[a].count < 0) return GS_ERR_INVALID_ARGUMENT;
+    next += assets[a].count;
+  }
+  return next == n ? GS_OK : GS_ERR_INVALID_ARGUMENT;
+}
+
 }  // namespace
 
 extern "C" {
@@ -272,28 +283,53 @@ size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity, const gs_ca
   }
 }
 
+int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n,
+                             const float* means, const float* log_scales, const float* quats,
+                             const float* opacity_logits, const float* sh, int32_t sh_degree,
+                             const gs_camera* cam, const gs_settings* set, gs_splat* splats,
+                             uint32_t* depth_keys, uint32_t* counts, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+  int32_t r;
+  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
+  if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
+  if ((r = check_assets(n_assets, assets, n))) return r;
+  if ((r = check_dev(counts))) return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)))) return r;
+  if (workspace_bytes < gs::preprocess_ws_bytes(n)) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
+  gs::CamK ck[gs::kMaxAssets];
+  for (int a = 0; a < n_assets; ++a)
+    if ((r = make_camk(cam, set, assets[a].model, &ck[a]))) return r;
+  const gs::SetK sk = make_setk(cam, set);
+  const int K3 = (sh_degree + 1) * (sh_degree + 1) * 3;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint2* partial = static_cast<uint2*>(workspace);
+  int blocks = 0;
+  hipError_t e = hipSuccess;
+  for (int a = 0; a < n_assets && e == hipSuccess; ++a) {
+    const int64_t o = assets[a].offset, c = assets[a].count;
+    if (c == 0) continue;
+    e = gs::launch_preprocess((int)c, means + 3 * o, log_scales + 3 * o, quats + 4 * o,
+                              opacity_logits + o, sh + K3 * o, sh_degree, ck[a], sk, splats + o,
+                              depth_keys + o, partial + blocks, st);
+    blocks += gs::preprocess_blocks(c);
+  }
+  if (e == hipSuccess) e = gs::launch_count_finalize(partial, blocks, counts, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
 int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales, const float* quats,
                       const float* opacity_logits, const float* sh, int32_t sh_degree,
                       const float* model, const gs_camera* cam, const gs_settings* set,
                       gs_splat* splats, uint32_t* depth_keys, uint32_t* counts, void* workspace,
                       size_t workspace_bytes, void* stream) {
-  int32_t r;
-  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
-  if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
-  if ((r = check_dev(counts))) return r;
-  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)))) return r;
-  if (workspace_bytes < gs::preprocess_ws_bytes(n)) return GS_ERR_WORKSPACE;
-  if ((r = check_dev(workspace))) return r;
-  gs::CamK ck;
-  if ((r = make_camk(cam, set, model, &ck))) return r;
-  const gs::SetK sk = make_setk(cam, set);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = gs::launch_preprocess((int)n, means, log_scales, quats, opacity_logits, sh,
-                                       sh_degree, ck, sk, splats, depth_keys, counts, workspace,
-                                       st);
-  if (e != hipSuccess) return hip_fail(e);
-  gs::trace_mark(st, "");
-  return GS_OK;
+  if (n < 0 || n >= kMaxN) return GS_ERR_INVALID_ARGUMENT;
+  const gs_asset one = {0, n, model};
+  return gs_preprocess_assets(1, &one, n, means, log_scales, quats, opacity_logits, sh,
+                              sh_degree, cam, set, splats, depth_keys, counts, workspace,
+                              workspace_bytes, stream);
 }
 
 int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
@@ -429,19 +465,18 @@ int32_t gs_rasterize(const gs_splat* splats, const uint32_t* values, const uint3
   return GS_OK;
 }
 
-int32_t gs_rasterize_backward(int64_t n, const float* means, const float* log_scales,
-                              const float* quats, const float* opacity_logits, const float* sh,
-                              int32_t sh_degree, const float* model, const gs_camera* cam,
-                              const gs_settings* set, const gs_splat* splats,
-                              const uint32_t* values, const uint32_t* tile_ranges,
-                              const float* T_final, const uint32_t* last,
-                              const float* dL_dimage, float* d_means, float* d_log_scales,
-                              float* d_quats, float* d_opacity_logits, float* d_sh,
-                              int32_t accumulate, void* workspace, size_t workspace_bytes,
-                              void* stream) {
+int32_t gs_rasterize_backward_assets(
+    int32_t n_assets, const gs_asset* assets, int64_t n, const float* means,
+    const float* log_scales, const float* quats, const float* opacity_logits, const float* sh,
+    int32_t sh_degree, const gs_camera* cam, const gs_settings* set, const gs_splat* splats,
+    const uint32_t* values, const uint32_t* tile_ranges, const float* T_final,
+    const uint32_t* last, const float* dL_dimage, float* d_means, float* d_log_scales,
+    float* d_quats, float* d_opacity_logits, float* d_sh, int32_t accumulate, void* workspace,
+    size_t workspace_bytes, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
+  if ((r = check_assets(n_assets, assets, n))) return r;
   if ((r = check_dev(tile_ranges)) || (r = check_dev(T_final)) || (r = check_dev(last)) ||
       (r = check_dev(dL_dimage)) || (r = check_dev(values, false)))
     return r;
@@ -452,10 +487,12 @@ int32_t gs_rasterize_backward(int64_t n, const float* means, const float* log_sc
   const size_t need = gs_workspace_size(GS_STAGE_BACKWARD, n, 0, cam, set);
   if (workspace_bytes < need) return GS_ERR_WORKSPACE;
   if ((r = check_dev(workspace))) return r;
-  gs::CamK ck;
-  if ((r = make_camk(cam, set, model, &ck))) return r;
+  gs::CamK ck[gs::kMaxAssets];
+  for (int a = 0; a < n_assets; ++a)
+    if ((r = make_camk(cam, set, assets[a].model, &ck[a]))) return r;
   const gs::SetK sk = make_setk(cam, set);
   if (n == 0) return GS_OK;
+  const int K3 = (sh_degree + 1) * (sh_degree + 1) * 3;
   hipStream_t st = static_cast<hipStream_t>(stream);
   float* grad2d = static_cast<float*>(workspace);
   gs::trace_mark(st, "bwd_clear");
@@ -466,13 +503,37 @@ int32_t gs_rasterize_backward(int64_t n, const float* means, const float* log_sc
   e = gs::launch_rasterize_backward(splats, values, tile_ranges, sk, cam->width, cam->height,
                                     T_final, last, dL_dimage, grad2d, st);
   if (e != hipSuccess) return hip_fail(e);
-  gs::trace_mark(st, "preprocess_bwd");
-  e = gs::launch_preprocess_backward((int)n, means, log_scales, quats, opacity_logits, sh,
-                                     sh_degree, ck, sk, splats, grad2d, d_means, d_log_scales,
-                                     d_quats, d_opacity_logits, d_sh, accumulate, st);
+  for (int a = 0; a < n_assets && e == hipSuccess; ++a) {
+    const int64_t o = assets[a].offset, c = assets[a].count;
+    if (c == 0) continue;
+    gs::trace_mark(st, "preprocess_bwd");
+    e = gs::launch_preprocess_backward(
+        (int)c, means + 3 * o, log_scales + 3 * o, quats + 4 * o, opacity_logits + o, sh + K3 * o,
+        sh_degree, ck[a], sk, splats + o, grad2d + gs::kGrad2dStride * o, d_means + 3 * o,
+        d_log_scales + 3 * o, d_quats + 4 * o, d_opacity_logits + o, d_sh + K3 * o, accumulate,
+        st);
+  }
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;
+}
+
+int32_t gs_rasterize_backward(int64_t n, const float* means, const float* log_scales,
+                              const float* quats, const float* opacity_logits, const float* sh,
+                              int32_t sh_degree, const float* model, const gs_camera* cam,
+                              const gs_settings* set, const gs_splat* splats,
+                              const uint32_t* values, const uint32_t* tile_ranges,
+                              const float* T_final, const uint32_t* last, const float* dL_dimage,
+                              float* d_means, float* d_log_scales, float* d_quats,
+                              float* d_opacity_logits, float* d_sh, int32_t accumulate,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+  if (n < 0 || n >= kMaxN) return GS_ERR_INVALID_ARGUMENT;
+  const gs_asset one = {0, n, model};
+  return gs_rasterize_backward_assets(1, &one, n, means, log_scales, quats, opacity_logits, sh,
+                                      sh_degree, cam, set, splats, values, tile_ranges, T_final,
+                                      last, dL_dimage, d_means, d_log_scales, d_quats,
+                                      d_opacity_logits, d_sh, accumulate, workspace,
+                                      workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -75,12 +75,19 @@ struct RadixArgs {
 };
 
 // Launchers (enqueue only; return the first launch error).
+constexpr int kMaxAssets = 64;       // assets per preprocess / backward call
 size_t preprocess_ws_bytes(int64_t n);
+int preprocess_blocks(int64_t n);
+// Projection of n Gaussians; per-block (instances, visible) partial sums go
+// to partial[0 .. preprocess_blocks(n)).
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
-                             gs_splat* splats, uint32_t* depth_keys, uint32_t* counts,
-                             void* ws, hipStream_t st);
+                             gs_splat* splats, uint32_t* depth_keys, uint2* partial,
+                             hipStream_t st);
+// counts[0] = sum of partial[].x (instances), counts[1] = sum of partial[].y (visible)
+hipError_t launch_count_finalize(const uint2* partial, int blocks, uint32_t* counts,
+                                 hipStream_t st);
 hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
                             int tiles, uint32_t* status_flag, const uint32_t* total_src,
                             int64_t capacity, hipStream_t st);

@@ -550,18 +550,19 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(
 
 }  // namespace
 
+int preprocess_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+// one partial slot per block of every asset: at most blocks(n) + assets
 size_t preprocess_ws_bytes(int64_t n) {
-  const int64_t blocks = (n + kBlock - 1) / kBlock;
-  return align_up((size_t)(blocks > 0 ? blocks : 1) * 8, 256);
+  return align_up((size_t)(preprocess_blocks(n) + kMaxAssets) * 8, 256);
 }
 
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
-                             gs_splat* splats, uint32_t* depth_keys, uint32_t* counts,
-                             void* ws, hipStream_t st) {
-  const int blocks = (n + kBlock - 1) / kBlock;
-  uint2* partial = static_cast<uint2*>(ws);
+                             gs_splat* splats, uint32_t* depth_keys, uint2* partial,
+                             hipStream_t st) {
+  const int blocks = preprocess_blocks(n);
   if (n > 0) {
     trace_mark(st, "preprocess");
     const float4* q4 = reinterpret_cast<const float4*>(quats);
@@ -574,6 +575,11 @@ hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
     }
 #undef GS_PRE
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_count_finalize(const uint2* partial, int blocks, uint32_t* counts,
+                                 hipStream_t st) {
   trace_mark(st, "count_finalize");
   hipLaunchKernelGGL(k_count_finalize, dim3(1), dim3(kBlock), 0, st, partial, blocks, counts);
   return hipGetLastError();

@@ -33,10 +33,27 @@ class GaussianParams:
     sh: torch.Tensor
     sh_degree: int
     model: object = None  # 3x4 similarity transform or None
+    # several assets concatenated: [(offset, count, model or None)] (None = one asset)
+    assets: object = None
 
     @property
     def n(self):
         return int(self.means.shape[0])
+
+    @staticmethod
+    def concat(parts):
+        """One parameter set holding several assets (each GaussianParams with
+        its own model transform), for one global sort per view."""
+        degs = {q.sh_degree for q in parts}
+        if len(degs) != 1:
+            raise ValueError("all assets must share one SH degree")
+        table, off = [], 0
+        for q in parts:
+            table.append((off, q.n, q.model))
+            off += q.n
+        cat = lambda name: torch.cat([getattr(q, name) for q in parts]).contiguous()
+        return GaussianParams(cat("means"), cat("log_scales"), cat("quats"),
+                              cat("opacity_logits"), cat("sh"), degs.pop(), None, table)
 
     @staticmethod
     def from_scene(scene, device="cuda", requires_grad=False):
@@ -100,10 +117,17 @@ class Renderer:
         counts = self._buf("counts", 8, reuse).view(torch.int32)[:2]
         ws_bytes = lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, n, 0, ctypes.byref(c), ctypes.byref(s))
         ws = self._buf("ws_pre", ws_bytes, reuse)
-        st = lib.gs_preprocess(n, *[_p(t) for t in p.tensors()], p.sh_degree, L.model_array(p.model),
-                               ctypes.byref(c), ctypes.byref(s), _p(splats), _p(dkeys), _p(counts),
-                               _p(ws), ws.numel(), _stream())
-        L.check(st, "gs_preprocess")
+        if p.assets is not None:
+            tab, _keep = L.asset_table(p.assets)
+            st = lib.gs_preprocess_assets(len(p.assets), tab, n, *[_p(t) for t in p.tensors()],
+                                          p.sh_degree, ctypes.byref(c), ctypes.byref(s), _p(splats),
+                                          _p(dkeys), _p(counts), _p(ws), ws.numel(), _stream())
+            L.check(st, "gs_preprocess_assets")
+        else:
+            st = lib.gs_preprocess(n, *[_p(t) for t in p.tensors()], p.sh_degree,
+                                   L.model_array(p.model), ctypes.byref(c), ctypes.byref(s),
+                                   _p(splats), _p(dkeys), _p(counts), _p(ws), ws.numel(), _stream())
+            L.check(st, "gs_preprocess")
         return splats, dkeys, counts
 
     def sort(self, n, splats, dkeys, counts, cam, capacity=None, reuse=True, want_keys=False):
@@ -160,12 +184,21 @@ class Renderer:
         dL = dL_dimage.to(torch.float32).contiguous()
         ws_bytes = lib.gs_workspace_size(L.GS_STAGE_BACKWARD, n, 0, ctypes.byref(c), ctypes.byref(s))
         ws = self._buf("ws_bwd", ws_bytes)
-        st = lib.gs_rasterize_backward(
-            n, *[_p(t) for t in p.tensors()], p.sh_degree, L.model_array(p.model), ctypes.byref(c),
-            ctypes.byref(s), _p(fr.splats), _p(fr.values), _p(fr.ranges), _p(fr.T_final),
-            _p(fr.last), _p(dL), *[_p(t) for t in out], int(bool(accumulate)), _p(ws), ws.numel(),
-            _stream())
-        L.check(st, "gs_rasterize_backward")
+        if p.assets is not None:
+            tab, _keep = L.asset_table(p.assets)
+            st = lib.gs_rasterize_backward_assets(
+                len(p.assets), tab, n, *[_p(t) for t in p.tensors()], p.sh_degree, ctypes.byref(c),
+                ctypes.byref(s), _p(fr.splats), _p(fr.values), _p(fr.ranges), _p(fr.T_final),
+                _p(fr.last), _p(dL), *[_p(t) for t in out], int(bool(accumulate)), _p(ws),
+                ws.numel(), _stream())
+            L.check(st, "gs_rasterize_backward_assets")
+        else:
+            st = lib.gs_rasterize_backward(
+                n, *[_p(t) for t in p.tensors()], p.sh_degree, L.model_array(p.model),
+                ctypes.byref(c), ctypes.byref(s), _p(fr.splats), _p(fr.values), _p(fr.ranges),
+                _p(fr.T_final), _p(fr.last), _p(dL), *[_p(t) for t in out], int(bool(accumulate)),
+                _p(ws), ws.numel(), _stream())
+            L.check(st, "gs_rasterize_backward")
         return out
 
 
@@ -173,9 +206,10 @@ class GsRender(torch.autograd.Function):
     """image = render(params); backward through libgs's hand-written kernels."""
 
     @staticmethod
-    def forward(ctx, means, log_scales, quats, opacity_logits, sh, renderer, cam, sh_degree, model):
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, renderer, cam, sh_degree, model,
+                assets=None):
         p = GaussianParams(means.detach(), log_scales.detach(), quats.detach(),
-                           opacity_logits.detach(), sh.detach(), sh_degree, model)
+                           opacity_logits.detach(), sh.detach(), sh_degree, model, assets)
         fr = renderer.forward(p, cam, reuse=False)
         ctx.renderer, ctx.cam, ctx.p, ctx.frame = renderer, cam, p, fr
         return fr.image
@@ -183,11 +217,11 @@ class GsRender(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_image):
         g = ctx.renderer.backward(ctx.p, ctx.cam, ctx.frame, grad_image)
-        return (*g, None, None, None, None)
+        return (*g, None, None, None, None, None)
 
 
 def render(params: GaussianParams, cam, renderer: Renderer = None):
     """Differentiable render of ``params`` from ``cam``: (H, W, 4) RGBA."""
     renderer = renderer or Renderer()
     return GsRender.apply(params.means, params.log_scales, params.quats, params.opacity_logits,
-                          params.sh, renderer, cam, params.sh_degree, params.model)
+                          params.sh, renderer, cam, params.sh_degree, params.model, params.assets)

@@ -168,3 +168,30 @@ def test_raster_argument_validation(lib):
     r = lib.gs_rasterize_backward(4, F, F, F, F, F, 3, None, ctypes.byref(c), ctypes.byref(s),
                                   F, F, F, F, F, F, F, F, F, F, F, 0, F, 8, None)
     assert r == L.GS_ERR_WORKSPACE
+
+
+def test_asset_table_validation(lib):
+    c, s = cam_1080(), L.default_settings()
+    F = ctypes.c_void_p(FAKE)
+
+    def pa(table, n, n_assets=None):
+        arr, keep = L.asset_table(table)
+        na = len(table) if n_assets is None else n_assets
+        return lib.gs_preprocess_assets(na, arr, n, *[F] * 5, 0, ctypes.byref(c), ctypes.byref(s),
+                                        F, F, F, F, 1 << 20, None)
+
+    def ba(table, n):
+        arr, keep = L.asset_table(table)
+        return lib.gs_rasterize_backward_assets(len(table), arr, n, *[F] * 5, 0, ctypes.byref(c),
+                                                ctypes.byref(s), F, F, F, F, F, F, F, F, F, F, F,
+                                                0, F, 1 << 30, None)
+    assert pa([(0, 4, None), (5, 4, None)], 9) == L.GS_ERR_INVALID_ARGUMENT   # gap
+    assert pa([(0, 4, None), (4, 4, None)], 9) == L.GS_ERR_INVALID_ARGUMENT   # short of n
+    assert pa([(0, 4, None), (4, -1, None)], 3) == L.GS_ERR_INVALID_ARGUMENT  # negative count
+    assert pa([(1, 4, None)], 5) == L.GS_ERR_INVALID_ARGUMENT                 # not from 0
+    assert pa([(0, 4, None)], 4, n_assets=0) == L.GS_ERR_INVALID_ARGUMENT
+    assert pa([(0, 1, None)] + [(1 + k, 1, None) for k in range(64)], 65) == L.GS_ERR_INVALID_ARGUMENT
+    shear = [[1, 0.5, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]]
+    assert pa([(0, 4, None), (4, 4, shear)], 8) == L.GS_ERR_INVALID_ARGUMENT
+    assert ba([(0, 4, None), (5, 4, None)], 9) == L.GS_ERR_INVALID_ARGUMENT
+    assert ba([(0, 4, None), (4, 4, shear)], 8) == L.GS_ERR_INVALID_ARGUMENT

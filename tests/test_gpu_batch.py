@@ -1,0 +1,165 @@
+"""GPU tests of the multi-asset entry points and the batched graph path.
+
+Multi-asset frames are checked against the FP64 oracle (records, pixels
+and gradients); the graph-captured batch against the plain view-by-view
+path: images bitwise equal on every replay, gradients equal up to the
+order of float atomics; the autotuner's choice leaves images unchanged.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2512_08478_amd import scenes as S
+from gpu_util import image_check, print_case, splats_np
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_08478_amd.render import Renderer
+    return Renderer()
+
+
+def small_batch(n_views=4, scale=0.01, seed=6):
+    return S.batched_scenes(seed=seed, scale=scale, n_views=n_views, max_wh=(480, 320),
+                            min_wh=(160, 128))
+
+
+def concat_params(assets):
+    from paper_2512_08478_amd.render import GaussianParams
+    return GaussianParams.concat([GaussianParams.from_scene(a) for a in assets])
+
+
+def targets_for(cams):
+    return [torch.from_numpy(S.random_target(100 + v, c.height, c.width)).cuda()
+            for v, c in enumerate(cams)]
+
+
+def test_multi_asset_records_equal_single_asset_records(R):
+    print_case("multi-asset preprocess == per-asset preprocess")
+    from paper_2512_08478_amd.render import GaussianParams
+    assets, cams = small_batch(n_views=1)
+    p = concat_params(assets)
+    cam = cams[0]
+    splats, _, counts = R.preprocess(p, cam, reuse=False)
+    rec = splats_np(splats, p.n)
+    c_all = counts.cpu().numpy().view(np.uint32)
+    tot = np.zeros(2, np.int64)
+    off = 0
+    for a in assets:
+        s1, _, c1 = R.preprocess(GaussianParams.from_scene(a), cam, reuse=False)
+        r1 = splats_np(s1, a.n)
+        assert r1.tobytes() == rec[off:off + a.n].tobytes()
+        tot += c1.cpu().numpy().view(np.uint32)
+        off += a.n
+    assert list(tot) == list(c_all)
+    print(f"{len(assets)} assets, {p.n} Gaussians, instances {c_all[0]}, visible {c_all[1]}")
+
+
+def test_multi_asset_view_vs_oracle(R, orc):
+    print_case("multi-asset view vs oracle, sampled pixels")
+    assets, cams = small_batch(n_views=2)
+    p = concat_params(assets)
+    for cam in cams:
+        fr = R.forward(p, cam)
+        img = fr.image.cpu().numpy()
+        rng = np.random.default_rng(cam.width)
+        pix = np.stack([rng.integers(0, cam.width, 256), rng.integers(0, cam.height, 256)], 1)
+        ref = orc.render_pixels(orc.preprocess_many(assets, cam), cam, pix)
+        e, nflag = image_check(img[pix[:, 1], pix[:, 0]], ref)
+        assert ref["rgba"][:, 3].max() > 0.1
+        print(f"{cam.width}x{cam.height}: max err {e:.2e}, flagged {nflag}")
+
+
+def test_multi_asset_backward_vs_oracle(R, orc):
+    print_case("multi-asset backward vs autograd oracle")
+    from scipy.spatial.transform import Rotation
+    from oracle import grad as og
+    from paper_2512_08478_amd.render import GaussianParams
+    sc, cam = S.fd_scene()
+    A = 0.9 * Rotation.from_euler("xyz", [0.1, -0.4, 0.25]).as_matrix()
+    model = np.concatenate([A, np.array([[0.05], [0.1], [-0.2]])], 1)
+    h = sc.n // 2
+    part = lambda sl, m: S.Scene(*(np.ascontiguousarray(getattr(sc, k)[sl]) for k in NAMES),
+                                 sc.sh_degree, m)
+    assets = [part(slice(0, h), None), part(slice(h, None), model)]
+    pix = orc.all_pixels(cam)
+    ref = orc.render_pixels(orc.preprocess_many(assets, cam), cam, pix)
+    rng = np.random.default_rng(12)
+    G = rng.standard_normal((len(pix), 4))
+    G[(ref["margin"] < 1e-4) | (ref["flags"] != 0)] = 0.0
+    _, g_ref = og.render_and_grad_assets(assets, cam, pix, G)
+    p = GaussianParams.concat([GaussianParams.from_scene(a) for a in assets])
+    fr = R.forward(p, cam, reuse=False)
+    g = R.backward(p, cam, fr, torch.from_numpy(G.reshape(cam.height, cam.width, 4)).float().cuda())
+    for k, nm in enumerate(NAMES):
+        got = g[k].cpu().numpy().astype(np.float64)
+        want = np.concatenate([g_ref[0][nm], g_ref[1][nm]])
+        e = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-30)
+        print(f"{nm}: rel L2 {e:.2e}")
+        assert e <= 1e-3, (nm, e)
+
+
+def _rel_max(a, b):
+    a, b = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+def test_graph_batch_matches_plain_views_on_every_replay(R):
+    print_case("graph-captured batch vs plain views, 3 replays")
+    from paper_2512_08478_amd.batch import BatchRenderer, plain_views
+    assets, cams = small_batch(n_views=4)
+    p = concat_params(assets)
+    tg = targets_for(cams)
+    imgs_ref, grads_ref = plain_views(p, cams, tg)
+    br = BatchRenderer(p, cams, tg)
+    br.capture()
+    noise = torch.randn(512, 512, device="cuda")
+    for rep in range(3):
+        imgs = br.replay()
+        for v in range(len(cams)):
+            assert torch.equal(imgs[v], imgs_ref[v]), (rep, v)
+        for k, nm in enumerate(NAMES):
+            d = _rel_max(br.grads[k], grads_ref[k])
+            assert d <= 1e-5, (rep, nm, d)
+        # the program's own eager work between replays
+        noise = (noise @ noise.T).tanh_()
+        torch.cuda.synchronize()
+    print(f"{len(cams)} views, {p.n} Gaussians, capacities {br.capacity}")
+
+
+def test_batch_capacity_overflow_is_reported(R):
+    print_case("batched capacity overflow flag")
+    from paper_2512_08478_amd.batch import BatchRenderer
+    assets, cams = small_batch(n_views=2)
+    p = concat_params(assets)
+    br = BatchRenderer(p, cams, targets_for(cams))
+    br.plan()
+    br.capacity = [64 for _ in cams]
+    br.run_eager()
+    torch.cuda.synchronize()
+    with pytest.raises(RuntimeError, match="capacity"):
+        br._check_flags()
+
+
+def test_autotuned_settings_leave_images_unchanged(R):
+    print_case("autotune: tile shape / digit width / sort mode choice keeps images")
+    from paper_2512_08478_amd.batch import BatchRenderer, autotune
+    assets, cams = small_batch(n_views=2)
+    p = concat_params(assets)
+    tg = targets_for(cams)
+    best, table = autotune(p, cams, tg, reps=1, tiles=((16, 16), (8, 8), (32, 8)), bits=(8, 6),
+                           modes=(0, 1))
+    assert len(table) == 3 + 1 + 1
+    ref = BatchRenderer(p, cams, tg)
+    ref_imgs = [im.clone() for im in ref.run_eager()]
+    tuned = BatchRenderer(p, cams, tg, best)
+    imgs = tuned.run_eager()
+    for a, b in zip(imgs, ref_imgs):
+        assert torch.equal(a, b)
+    print(f"autotune picked {best}")
