@@ -52,6 +52,27 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
   return v;
 }
 
+// Sum of v over the 64 lanes, returned wave-uniform.  Inside each row of 16
+// lanes, DPP row shifts by 1, 2, 4 and 8 leave the row's sum in its lane 15
+// (lanes shifted in from outside the row read 0); row broadcasts then add
+// row 0's sum into row 1 and row 2's into row 3, and row 1's into rows 2-3,
+// so lane 63 ends with the total.  Register-to-register only: no LDS
+// traffic, unlike a ds_bpermute butterfly.  Every lane must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
+}
+
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_f32<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_f32<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_f32<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_f32<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_f32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f32<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Lanes of the wave whose `d` (BITS wide) equals this lane's, among `active`.
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {

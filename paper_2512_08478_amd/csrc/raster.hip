@@ -255,6 +255,11 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
   if (mylast) atomicMax(&s_maxlast, mylast);
   __syncthreads();
   const uint32_t nlast = s_maxlast;
+  // this wave's largest `last`: splats at or past it blend into none of its pixels
+  uint32_t wlast = mylast;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) wlast = max(wlast, shfl_u32(wlast, lane ^ d));
+  wlast = __builtin_amdgcn_readfirstlane(wlast);
   const float bgdot = dC0 * set.bg[0] + dC1 * set.bg[1] + dC2 * set.bg[2];
   float S0 = 0.f, S1 = 0.f, S2 = 0.f, B = 1.f;
 
@@ -272,7 +277,10 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
     quadrant_hits<TW, TH>(S, cnt, lane, qbit, hm);
 #pragma unroll
     for (int c = St::NCH - 1; c >= 0; --c) {
-      uint64_t m = hm[c];
+      // positions bs + c*64 + k with k < wlast - bs - c*64 only
+      const int64_t room = (int64_t)wlast - (int64_t)bs - c * 64;
+      const uint64_t keep = room >= 64 ? ~0ull : room <= 0 ? 0ull : ((1ull << room) - 1ull);
+      uint64_t m = hm[c] & keep;
       while (m) {
         const int j = c * 64 + 63 - __builtin_clzll(m);
         m &= ~(1ull << (j - c * 64));
@@ -316,10 +324,10 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
           }
         }
         if (ballot(contrib)) {
-          gmx = wave_sum_f32(gmx); gmy = wave_sum_f32(gmy);
-          gqa = wave_sum_f32(gqa); gqb = wave_sum_f32(gqb); gqc = wave_sum_f32(gqc);
-          gop = wave_sum_f32(gop);
-          gr = wave_sum_f32(gr); gg = wave_sum_f32(gg); gb = wave_sum_f32(gb);
+          gmx = wave_sum_dpp(gmx); gmy = wave_sum_dpp(gmy);
+          gqa = wave_sum_dpp(gqa); gqb = wave_sum_dpp(gqb); gqc = wave_sum_dpp(gqc);
+          gop = wave_sum_dpp(gop);
+          gr = wave_sum_dpp(gr); gg = wave_sum_dpp(gg); gb = wave_sum_dpp(gb);
           if (lane == 0) {
             float* dst = grad2d + (size_t)S.gid[j] * kGrad2dStride;
             atomicAdd(dst + 0, gmx); atomicAdd(dst + 1, gmy);
