@@ -62,7 +62,7 @@ struct Stage {
   static constexpr int BATCH = NT < 128 ? NT : 128;
   static constexpr int NCH = (BATCH + 63) / 64;  // 64-slot chunks per batch
   float4 hdr[BATCH];          // qa', r, g, b
-  float4 aux[BATCH];          // qb, qc', my, opacity
+  float4 aux[BATCH];          // qb, qc', my, 1 / opacity
   float2 ml[BATCH];           // mx, log2(opacity)
   float rt[BATCH][TH];        // log2(o) - qc' dy^2 per tile row
   float ub[BATCH][QX][TH];    // dx - qb dy at column 0 of each 8-column group
@@ -98,7 +98,7 @@ __device__ __forceinline__ void stage_params(Stage<TW, TH>& S, int j,
     m |= hit ? (1u << q) : 0u;
   }
   S.hdr[j] = make_float4(qa_, b.z, b.w, c);
-  S.aux[j] = make_float4(qb, qc_, my, b.y);
+  S.aux[j] = make_float4(qb, qc_, my, 1.f / b.y);
   S.ml[j] = make_float2(mx, lo);
   S.mask[j] = m;
   S.gid[j] = g;
@@ -111,7 +111,7 @@ __device__ __forceinline__ void stage_rows(Stage<TW, TH>& S, int cnt, int tx0, i
   using St = Stage<TW, TH>;
   for (int item = threadIdx.x; item < cnt * TH; item += St::NT) {
     const int j = item / TH, r = item % TH;
-    const float4 x = S.aux[j];   // qb, qc', my, opacity
+    const float4 x = S.aux[j];   // qb, qc', my, 1 / opacity
     const float2 ml = S.ml[j];   // mx, log2(opacity)
     const float dy = (ty0 + r + 0.5f) - x.z;
     S.rt[j][r] = fmaf(-x.y, dy * dy, ml.y);
@@ -213,31 +213,40 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
 //   S_i = colour composited behind i (normalised by T_{i+1}),
 //   B_i = T_final / T_{i+1},
 // dC/dalpha_i = T_i (c_i - S_i - B_i bg) and dA/dalpha_i = T_i B_i.
-// Per splat the 9 partial derivatives are summed over the wave and added
-// to the Gaussian's 2-D gradient record with one atomic per value.
+// Per splat the 9 partial derivatives are summed over the wave with DPP
+// and added to the Gaussian's 2-D gradient record with one float atomic per
+// value.
+//
+// Each 8x8 quadrant of a TW x TH tile is its own one-wave workgroup that
+// walks the tile's whole list (skipping splats that miss the quadrant), so
+// a frame has tiles * (TW/8) * (TH/8) small workgroups: the per-pair work
+// here is heavy, and small workgroups balance it across the CUs far better
+// than one workgroup per tile.  A quadrant stages exactly the row terms the
+// forward kernel used for its pixels, so every skip decision matches.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restrict__ splats,
-                                                       const uint32_t* __restrict__ values,
-                                                       const uint32_t* __restrict__ ranges,
-                                                       SetK set, int W, int H,
-                                                       const float* __restrict__ T_final,
-                                                       const uint32_t* __restrict__ last,
-                                                       const float* __restrict__ dL_dimage,
-                                                       float* __restrict__ grad2d) {
-  using St = Stage<TW, TH>;
+__global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ splats,
+                                                   const uint32_t* __restrict__ values,
+                                                   const uint32_t* __restrict__ ranges,
+                                                   SetK set, int W, int H,
+                                                   const float* __restrict__ T_final,
+                                                   const uint32_t* __restrict__ last,
+                                                   const float* __restrict__ dL_dimage,
+                                                   float* __restrict__ grad2d) {
+  using St = Stage<8, 8>;
+  constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ St S;
-  __shared__ uint32_t s_maxlast;
   const int tiles = set.tiles_x * set.tiles_y;
-  const int tile = xcd_tile(blockIdx.x, tiles);
-  if (tile >= tiles) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int qx = wave % St::QX, qy = wave / St::QX;
-  const int tx0 = (tile % set.tiles_x) * TW, ty0 = (tile / set.tiles_x) * TH;
-  const int lx = lane & 7, row = qy * 8 + (lane >> 3);
-  const int px = tx0 + qx * 8 + lx, py = ty0 + row;
+  const int unit = xcd_tile(blockIdx.x, tiles * NQ);  // quadrants of a tile stay on one XCD
+  if (unit >= tiles * NQ) return;
+  const int tile = unit / NQ, q = unit % NQ;
+  const int tx0 = (tile % set.tiles_x) * TW + 8 * (q % QX);
+  const int ty0 = (tile / set.tiles_x) * TH + 8 * (q / QX);
+  if (tx0 >= W || ty0 >= H) return;  // quadrant wholly outside the image
+  const int lane = threadIdx.x;
+  const int lx = lane & 7, row = lane >> 3;
+  const int px = tx0 + lx, py = ty0 + row;
   const bool inside = px < W && py < H;
   const float lxf = (float)lx, fy = py + 0.5f;
-  const uint32_t qbit = 1u << wave;
   const uint32_t start = ranges[2 * tile];
   const float log2_tau = set.log2_tau;
 
@@ -250,16 +259,11 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
     const float4 g = reinterpret_cast<const float4*>(dL_dimage)[p];
     dC0 = g.x; dC1 = g.y; dC2 = g.z; dA = g.w;
   }
-  if (tid == 0) s_maxlast = 0;
-  __syncthreads();
-  if (mylast) atomicMax(&s_maxlast, mylast);
-  __syncthreads();
-  const uint32_t nlast = s_maxlast;
-  // this wave's largest `last`: splats at or past it blend into none of its pixels
-  uint32_t wlast = mylast;
+  // the quadrant's largest `last`: later splats blend into none of its pixels
+  uint32_t nlast = mylast;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) wlast = max(wlast, shfl_u32(wlast, lane ^ d));
-  wlast = __builtin_amdgcn_readfirstlane(wlast);
+  for (int d = 32; d >= 1; d >>= 1) nlast = max(nlast, shfl_u32(nlast, lane ^ d));
+  nlast = __builtin_amdgcn_readfirstlane(nlast);
   const float bgdot = dC0 * set.bg[0] + dC1 * set.bg[1] + dC2 * set.bg[2];
   float S0 = 0.f, S1 = 0.f, S2 = 0.f, B = 1.f;
 
@@ -269,72 +273,65 @@ __global__ __launch_bounds__(TW* TH) void k_raster_bwd(const gs_splat* __restric
     const uint32_t bs = (uint32_t)bi * St::BATCH;
     __syncthreads();
     const int cnt = (int)min((uint32_t)St::BATCH, nlast - bs);
-    if (tid < cnt) stage_params<TW, TH>(S, tid, splats, values[start + bs + tid], tx0, ty0, log2_tau);
+    if (lane < cnt) stage_params<8, 8>(S, lane, splats, values[start + bs + lane], tx0, ty0, log2_tau);
     __syncthreads();
-    stage_rows<TW, TH>(S, cnt, tx0, ty0);
+    stage_rows<8, 8>(S, cnt, tx0, ty0);
     __syncthreads();
-    uint64_t hm[St::NCH];
-    quadrant_hits<TW, TH>(S, cnt, lane, qbit, hm);
-#pragma unroll
-    for (int c = St::NCH - 1; c >= 0; --c) {
-      // positions bs + c*64 + k with k < wlast - bs - c*64 only
-      const int64_t room = (int64_t)wlast - (int64_t)bs - c * 64;
-      const uint64_t keep = room >= 64 ? ~0ull : room <= 0 ? 0ull : ((1ull << room) - 1ull);
-      uint64_t m = hm[c] & keep;
-      while (m) {
-        const int j = c * 64 + 63 - __builtin_clzll(m);
-        m &= ~(1ull << (j - c * 64));
-        float gmx = 0.f, gmy = 0.f, gqa = 0.f, gqb = 0.f, gqc = 0.f, gop = 0.f;
-        float gr = 0.f, gg = 0.f, gb = 0.f;
-        bool contrib = false;
-        if (bs + j < mylast) {
-          const float u = S.ub[j][qx][row] + lxf;
-          const float4 h = S.hdr[j];
-          const float e = fmaf(-h.x, u * u, S.rt[j][row]);
-          if (e >= log2_tau) {
-            contrib = true;
-            const float4 x = S.aux[j];  // qb, qc', my, opacity
-            const float gw = hw_exp2(e);
-            const float alpha = fminf(set.amax, gw);
-            const float om = 1.f - alpha;
-            const float Ti = T / om;
-            const float cr = h.y, cg = h.z, cb = h.w;
-            const float w = alpha * Ti;
-            gr = dC0 * w; gg = dC1 * w; gb = dC2 * w;
-            const float dalpha = Ti * (dC0 * (cr - S0) + dC1 * (cg - S1) + dC2 * (cb - S2) -
-                                       B * bgdot + dA * B);
-            S0 = fmaf(alpha, cr - S0, S0);
-            S1 = fmaf(alpha, cg - S1, S1);
-            S2 = fmaf(alpha, cb - S2, S2);
-            B *= om;
-            T = Ti;
-            if (gw < set.amax) {
-              // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
-              // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y
-              const float dy = fy - x.z;
-              gop = dalpha * gw / x.w;
-              const float dQ = -kLn2 * gw * dalpha;  // dL/dQ'
-              const float qau = h.x * u;
-              gqa = dQ * kHalfLog2e * (u * u);
-              gqb = -2.f * dQ * qau * dy;
-              gqc = dQ * kHalfLog2e * (dy * dy);
-              gmx = -2.f * dQ * qau;
-              gmy = 2.f * dQ * (qau * x.x - x.y * dy);
-            }
+    uint64_t m = ballot(lane < cnt && (S.mask[lane < cnt ? lane : 0] & 1u) != 0u);
+    while (m) {
+      const int j = 63 - __builtin_clzll(m);
+      m &= ~(1ull << j);
+      float gmx = 0.f, gmy = 0.f, gqa = 0.f, gqb = 0.f, gqc = 0.f, gop = 0.f;
+      float gr = 0.f, gg = 0.f, gb = 0.f;
+      bool contrib = false;
+      if (bs + j < mylast) {
+        const float u = S.ub[j][0][row] + lxf;
+        const float4 h = S.hdr[j];
+        const float e = fmaf(-h.x, u * u, S.rt[j][row]);
+        if (e >= log2_tau) {
+          contrib = true;
+          const float4 x = S.aux[j];  // qb, qc', my, 1 / opacity
+          const float gw = hw_exp2(e);
+          const float alpha = fminf(set.amax, gw);
+          const float om = 1.f - alpha;
+          // T before this splat; 1 - alpha >= 1 - alpha_max, far from 0
+          const float Ti = T * __builtin_amdgcn_rcpf(om);
+          const float cr = h.y, cg = h.z, cb = h.w;
+          const float w = alpha * Ti;
+          gr = dC0 * w; gg = dC1 * w; gb = dC2 * w;
+          const float dalpha = Ti * (dC0 * (cr - S0) + dC1 * (cg - S1) + dC2 * (cb - S2) -
+                                     B * bgdot + dA * B);
+          S0 = fmaf(alpha, cr - S0, S0);
+          S1 = fmaf(alpha, cg - S1, S1);
+          S2 = fmaf(alpha, cb - S2, S2);
+          B *= om;
+          T = Ti;
+          if (gw < set.amax) {
+            // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
+            // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y
+            const float dy = fy - x.z;
+            gop = dalpha * gw * x.w;
+            const float dQ = -kLn2 * gw * dalpha;  // dL/dQ'
+            const float qau = h.x * u;
+            gqa = dQ * kHalfLog2e * (u * u);
+            gqb = -2.f * dQ * qau * dy;
+            gqc = dQ * kHalfLog2e * (dy * dy);
+            gmx = -2.f * dQ * qau;
+            gmy = 2.f * dQ * (qau * x.x - x.y * dy);
           }
         }
-        if (ballot(contrib)) {
-          gmx = wave_sum_dpp(gmx); gmy = wave_sum_dpp(gmy);
-          gqa = wave_sum_dpp(gqa); gqb = wave_sum_dpp(gqb); gqc = wave_sum_dpp(gqc);
-          gop = wave_sum_dpp(gop);
-          gr = wave_sum_dpp(gr); gg = wave_sum_dpp(gg); gb = wave_sum_dpp(gb);
-          if (lane == 0) {
-            float* dst = grad2d + (size_t)S.gid[j] * kGrad2dStride;
-            atomicAdd(dst + 0, gmx); atomicAdd(dst + 1, gmy);
-            atomicAdd(dst + 2, gqa); atomicAdd(dst + 3, gqb); atomicAdd(dst + 4, gqc);
-            atomicAdd(dst + 5, gop);
-            atomicAdd(dst + 6, gr); atomicAdd(dst + 7, gg); atomicAdd(dst + 8, gb);
-          }
+      }
+      if (ballot(contrib)) {
+        gmx = wave_sum_dpp(gmx); gmy = wave_sum_dpp(gmy);
+        gqa = wave_sum_dpp(gqa); gqb = wave_sum_dpp(gqb); gqc = wave_sum_dpp(gqc);
+        gop = wave_sum_dpp(gop);
+        gr = wave_sum_dpp(gr); gg = wave_sum_dpp(gg); gb = wave_sum_dpp(gb);
+        if (lane == 0) {
+          float* dst = grad2d + (size_t)S.gid[j] * kGrad2dStride;
+          atomicAdd(dst + 0, gmx); atomicAdd(dst + 1, gmy);
+          atomicAdd(dst + 2, gqa); atomicAdd(dst + 3, gqb); atomicAdd(dst + 4, gqc);
+          atomicAdd(dst + 5, gop);
+          atomicAdd(dst + 6, gr); atomicAdd(dst + 7, gg); atomicAdd(dst + 8, gb);
         }
       }
     }
@@ -354,8 +351,8 @@ template <int TW, int TH>
 void raster_bwd(const gs_splat* splats, const uint32_t* values, const uint32_t* ranges,
                 const SetK& set, int W, int H, const float* T_final, const uint32_t* last,
                 const float* dL_dimage, float* grad2d, hipStream_t st) {
-  const int tiles = set.tiles_x * set.tiles_y;
-  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(xcd_grid(tiles)), dim3(TW * TH), 0, st,
+  const int units = set.tiles_x * set.tiles_y * (TW / 8) * (TH / 8);
+  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(xcd_grid(units)), dim3(64), 0, st,
                      splats, values, ranges, set, W, H, T_final, last, dL_dimage, grad2d);
 }
 
