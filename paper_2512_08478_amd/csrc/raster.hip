@@ -214,8 +214,8 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
 //   B_i = T_final / T_{i+1},
 // dC/dalpha_i = T_i (c_i - S_i - B_i bg) and dA/dalpha_i = T_i B_i.
 // Per splat the 9 partial derivatives are summed over the wave with DPP
-// and added to the Gaussian's 2-D gradient record with one float atomic per
-// value.
+// and added to the Gaussian's 2-D gradient record by one float-atomic
+// instruction (lanes 0-8, one value each).
 //
 // Each 8x8 quadrant of a TW x TH tile is its own one-wave workgroup that
 // walks the tile's whole list (skipping splats that miss the quadrant), so
@@ -326,13 +326,12 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
         gqa = wave_sum_dpp(gqa); gqb = wave_sum_dpp(gqb); gqc = wave_sum_dpp(gqc);
         gop = wave_sum_dpp(gop);
         gr = wave_sum_dpp(gr); gg = wave_sum_dpp(gg); gb = wave_sum_dpp(gb);
-        if (lane == 0) {
-          float* dst = grad2d + (size_t)S.gid[j] * kGrad2dStride;
-          atomicAdd(dst + 0, gmx); atomicAdd(dst + 1, gmy);
-          atomicAdd(dst + 2, gqa); atomicAdd(dst + 3, gqb); atomicAdd(dst + 4, gqc);
-          atomicAdd(dst + 5, gop);
-          atomicAdd(dst + 6, gr); atomicAdd(dst + 7, gg); atomicAdd(dst + 8, gb);
-        }
+        // lane k adds value k: one atomic instruction over 9 consecutive words
+        const float sums[9] = {gmx, gmy, gqa, gqb, gqc, gop, gr, gg, gb};
+        float v = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v = lane == k ? sums[k] : v;
+        if (lane < 9) atomicAdd(grad2d + (size_t)S.gid[j] * kGrad2dStride + lane, v);
       }
     }
   }
