@@ -170,7 +170,15 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
     __syncthreads();
     uint64_t hm[St::NCH];
     quadrant_hits<TW, TH>(S, cnt, lane, qbit, hm);
-    if (!done) {
+    // Lanes never branch apart here: a pair a lane must not blend (weight
+    // below alpha_min, or the pixel already stopped) gets alpha = 0, which
+    // leaves C and T bitwise unchanged; only wave-uniform branches remain
+    // (no lane blends this splat; every pixel of the wave has stopped).
+    // `live` is 1 while the pixel composites and 0 once it stopped (or
+    // lies outside the image), kept as a float so that the loop needs no
+    // lane-mask bookkeeping.
+    float live = done ? 0.f : 1.f;
+    if (ballot(live != 0.f)) {
 #pragma unroll
       for (int c = 0; c < St::NCH; ++c) {
         uint64_t m = hm[c];
@@ -180,23 +188,23 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
           const float u = S.ub[j][qx][row] + lxf;
           const float4 h = S.hdr[j];
           const float e = fmaf(-h.x, u * u, S.rt[j][row]);
-          if (e < log2_tau) continue;  // weight below alpha_min: skipped
-          const float alpha = fminf(set.amax, hw_exp2(e));
+          const bool take = e >= log2_tau && live != 0.f;
+          if (!ballot(take)) continue;
+          const float alpha = take ? fminf(set.amax, hw_exp2(e)) : 0.f;
           const float w = alpha * T;
           C0 = fmaf(w, h.y, C0);
           C1 = fmaf(w, h.z, C1);
           C2 = fmaf(w, h.w, C2);
           T = T * (1.f - alpha);
-          lastc = bs + j + 1 - start;
-          ++nb;
-          if (T < set.t_eps) {
-            done = true;
-            break;
-          }
+          lastc = take ? bs + j + 1 - start : lastc;
+          nb += take ? 1u : 0u;
+          live = T < set.t_eps ? 0.f : live;
+          if (!ballot(live != 0.f)) break;
         }
-        if (done) break;
+        if (!ballot(live != 0.f)) break;
       }
     }
+    done = live == 0.f;
   }
   if (inside) {
     const int p = py * W + px;
