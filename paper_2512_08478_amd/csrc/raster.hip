@@ -70,15 +70,29 @@ struct Stage {
   uint32_t gid[BATCH];        // Gaussian index
 };
 
+// The fields of a splat record the compositing kernels read.
+struct SplatRec {
+  float4 a;  // mx, my, qa, qb
+  float4 b;  // qc, opacity, r, g
+  float c;   // b
+};
+
+__device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ splats, uint32_t g) {
+  const float4* rec = reinterpret_cast<const float4*>(splats + g);
+  SplatRec r;
+  r.a = rec[0];
+  r.b = rec[1];
+  r.c = rec[2].x;
+  return r;
+}
+
 // Phase 1 of staging: splat j's parameters, footprint mask and index.
 template <int TW, int TH>
-__device__ __forceinline__ void stage_params(Stage<TW, TH>& S, int j,
-                                             const gs_splat* __restrict__ splats, uint32_t g,
-                                             int tx0, int ty0, float log2_tau) {
+__device__ __forceinline__ void stage_params(Stage<TW, TH>& S, int j, const SplatRec& r,
+                                             uint32_t g, int tx0, int ty0, float log2_tau) {
   using St = Stage<TW, TH>;
-  const float4* rec = reinterpret_cast<const float4*>(splats + g);
-  const float4 a = rec[0], b = rec[1];
-  const float c = rec[2].x;
+  const float4 a = r.a, b = r.b;
+  const float c = r.c;
   const float mx = a.x, my = a.y, qb = a.w;
   const float qa_ = a.z * kHalfLog2e, qc_ = b.x * kHalfLog2e;
   const float lo = log2f(b.y);
@@ -161,10 +175,27 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t lastc = 0, nb = 0;
   bool done = !inside;
+  // Software pipeline over batches: while a batch composites, the records
+  // of the next batch and the indices of the one after are in flight.
+  // Every thread loads (threads past the batch repeat slot tid % BATCH),
+  // and loads past the range are clamped to its last entry; the extra
+  // values are never staged.  Branch-free loads let the compiler keep them
+  // in flight across the compositing of the current batch.
+  const uint32_t slot = (uint32_t)tid & (St::BATCH - 1);
+  const uint32_t lastpos = end > start ? end - 1 : start;
+  uint32_t g_cur = 0, g_next = 0;
+  SplatRec r_cur = {};
+  if (start < end) {
+    g_cur = values[min(start + slot, lastpos)];
+    g_next = values[min(start + St::BATCH + slot, lastpos)];
+    r_cur = load_splat(splats, g_cur);
+  }
   for (uint32_t bs = start; bs < end; bs += St::BATCH) {
     if (__syncthreads_count(done) == St::NT) break;
     const int cnt = (int)min((uint32_t)St::BATCH, end - bs);
-    if (tid < cnt) stage_params<TW, TH>(S, tid, splats, values[bs + tid], tx0, ty0, log2_tau);
+    if (tid < cnt) stage_params<TW, TH>(S, tid, r_cur, g_cur, tx0, ty0, log2_tau);
+    const SplatRec r_next = load_splat(splats, g_next);
+    const uint32_t g_after = values[min(bs + 2 * St::BATCH + slot, lastpos)];
     __syncthreads();
     stage_rows<TW, TH>(S, cnt, tx0, ty0);
     __syncthreads();
@@ -205,6 +236,9 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
       }
     }
     done = live == 0.f;
+    g_cur = g_next;
+    r_cur = r_next;
+    g_next = g_after;
   }
   if (inside) {
     const int p = py * W + px;
@@ -281,7 +315,10 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
     const uint32_t bs = (uint32_t)bi * St::BATCH;
     __syncthreads();
     const int cnt = (int)min((uint32_t)St::BATCH, nlast - bs);
-    if (lane < cnt) stage_params<8, 8>(S, lane, splats, values[start + bs + lane], tx0, ty0, log2_tau);
+    if (lane < cnt) {
+      const uint32_t g = values[start + bs + lane];
+      stage_params<8, 8>(S, lane, load_splat(splats, g), g, tx0, ty0, log2_tau);
+    }
     __syncthreads();
     stage_rows<8, 8>(S, cnt, tx0, ty0);
     __syncthreads();
