@@ -49,6 +49,7 @@ struct SortLayout {
   size_t dk[2], dv[2], tk[2], tv[2], tkf, hist, tickets, lookback, table, totals, kg_counts, count;
   size_t bytes;
   int parts;     // 4096-key partitions of the largest sort
+  int rs_parts;  // 1024-key partitions of the largest sort (reduce-then-scan table rows)
   int kg_parts;  // keygen slices
 };
 SortLayout sort_layout(int64_t n, int64_t capacity);

@@ -38,6 +38,7 @@ constexpr int kHistMax = 2048;     // LDS histogram bins (passes x 2^bits)
 constexpr int kLbWindow = 8;       // look-back status words in flight per digit
 constexpr int kKgItems = 4;        // sorted Gaussians per thread in the keygen
 constexpr int kKgPart = kBlock * kKgItems;
+constexpr int kRsMinParts = 768;   // reduce-then-scan passes aim for at least this many partitions
 
 __global__ __launch_bounds__(kBlock) void k_sort_init(uint32_t* hist, int hist_len,
                                                       uint32_t* tickets, int ntickets,
@@ -100,27 +101,28 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp,
 
 // Digit counts of one 4096-key partition per workgroup, written digit-major
 // into table[d * P + partition] (zeros past the end).
-template <typename KeyT, int BITS>
+template <typename KeyT, int BITS, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ kin,
                                                        const uint32_t* __restrict__ count,
                                                        int64_t n_host, int shift,
                                                        uint32_t* __restrict__ table, int P) {
   constexpr int NB = 1 << BITS;
+  constexpr int PART = kBlock * ITEMS;
   __shared__ uint32_t s_h[NB];
   const int t = threadIdx.x;
   for (int d = t; d < NB; d += kBlock) s_h[d] = 0;
   __syncthreads();
   const uint32_t n = read_n(count, n_host);
-  const uint32_t base = blockIdx.x * kSortPart;
+  const uint32_t base = blockIdx.x * PART;
   if (base < n) {
-    KeyT k[kSortItems];
+    KeyT k[ITEMS];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
       const uint32_t idx = base + i * kBlock + t;
       k[i] = idx < n ? kin[idx] : KeyT(0);
     }
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i)
+    for (int i = 0; i < ITEMS; ++i)
       wave_hist_add<BITS>(s_h, digit_of<KeyT, BITS>(k[i], shift), base + i * kBlock + t < n);
   }
   __syncthreads();
@@ -202,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_histogram(const KeyT* __restrict__ k
 //   histogram, offsets by decoupled look-back over lb.
 // WRITE_KEYS = false skips the key stores of a last pass whose keys nobody
 // reads.
-template <typename KeyT, int BITS, bool WRITE_KEYS, bool LOOKBACK>
+template <typename KeyT, int BITS, int ITEMS, bool WRITE_KEYS, bool LOOKBACK>
 __global__ __launch_bounds__(kBlock) void k_radix_pass(
     const KeyT* __restrict__ kin, const uint32_t* __restrict__ vin, KeyT* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ count, int64_t n_host, int shift,
@@ -210,11 +212,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
     uint32_t* __restrict__ ticket, uint32_t* __restrict__ lb, uint32_t* __restrict__ lb_next) {
   constexpr int NB = 1 << BITS;
   constexpr int NW = kBlock / 64;
+  constexpr int PART = kBlock * ITEMS;
   __shared__ uint32_t s_whist[NW][NB];
   __shared__ uint32_t s_local[NB];
   __shared__ uint32_t s_gbase[NB];
-  __shared__ KeyT s_keys[kSortPart];
-  __shared__ uint8_t s_dig[kSortPart];
+  __shared__ KeyT s_keys[PART];
+  __shared__ uint8_t s_dig[PART];
   __shared__ uint32_t s_scan[2][NW];
   __shared__ uint32_t s_part;
 
@@ -224,23 +227,23 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
   __syncthreads();
   const uint32_t part = LOOKBACK ? s_part : blockIdx.x;
   const uint32_t n = read_n(count, n_host);
-  const uint32_t base = part * kSortPart;
+  const uint32_t base = part * PART;
   if (base >= n) return;
   if (LOOKBACK)
     for (int b = t; b < NB; b += kBlock) lb_next[part * NB + b] = 0;
 
   // warp-striped load: wave w owns keys [w*64*ITEMS, (w+1)*64*ITEMS)
-  KeyT k[kSortItems];
-  uint32_t pos[kSortItems];
-  const uint32_t wbase = base + wave * 64 * kSortItems + lane;
+  KeyT k[ITEMS];
+  uint32_t pos[ITEMS];
+  const uint32_t wbase = base + wave * 64 * ITEMS + lane;
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const uint32_t idx = wbase + i * 64;
     k[i] = idx < n ? kin[idx] : ~KeyT(0);  // past the end: last digit, ranked last
   }
   const uint64_t lt = lanemask_lt();
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const uint32_t d = digit_of<KeyT, BITS>(k[i], shift);
     const uint64_t peers = match_digit<BITS>(d, ~0ull);
     const uint32_t c = s_whist[wave][d];
@@ -309,13 +312,13 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
   __syncthreads();
 
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const uint32_t d = digit_of<KeyT, BITS>(k[i], shift);
     pos[i] += s_local[d] + s_whist[wave][d];
     s_keys[pos[i]] = k[i];
   }
   __syncthreads();
-  for (int j = t; j < kSortPart; j += kBlock) {
+  for (int j = t; j < PART; j += kBlock) {
     const KeyT key = s_keys[j];
     const uint32_t d = digit_of<KeyT, BITS>(key, shift);
     s_dig[j] = (uint8_t)d;
@@ -327,12 +330,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
   __syncthreads();
   uint32_t* s_vals = reinterpret_cast<uint32_t*>(s_keys);
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const uint32_t idx = wbase + i * 64;
     s_vals[pos[i]] = idx < n ? (vin ? vin[idx] : idx) : 0u;
   }
   __syncthreads();
-  for (int j = t; j < kSortPart; j += kBlock) {
+  for (int j = t; j < PART; j += kBlock) {
     const uint32_t g = s_gbase[s_dig[j]] + j;
     if (g < n) vout[g] = s_vals[j];
   }
@@ -522,35 +525,56 @@ int stream_grid(int64_t items, int cap = 2048) {
   return (int)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
+// Keys per thread of a reduce-then-scan pass: enough partitions to give
+// every CU a few workgroups (small passes are latency-bound), else 16.
+inline int rs_items(int64_t n) {
+  if ((n + kBlock * 16 - 1) / (kBlock * 16) >= kRsMinParts) return 16;
+  if ((n + kBlock * 8 - 1) / (kBlock * 8) >= kRsMinParts) return 8;
+  return 4;
+}
+
+template <typename KeyT, int BITS, int ITEMS>
+void rs_pass(const RadixArgs<KeyT>& a, int p, const KeyT* ki, const uint32_t* vi, KeyT* kd,
+             uint32_t* vd, bool write_keys, hipStream_t st) {
+  constexpr int PART = kBlock * ITEMS;
+  const int parts = (int)((a.n_grid + PART - 1) / PART);
+  const int shift = p * BITS;
+  hipLaunchKernelGGL((k_rs_upsweep<KeyT, BITS, ITEMS>), dim3(parts), dim3(kBlock), 0, st, ki,
+                     a.count, a.n_grid, shift, a.table, parts);
+  hipLaunchKernelGGL(k_row_scan, dim3(1 << BITS), dim3(kBlock), 0, st, a.table, parts, a.totals);
+  if (write_keys)
+    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, true, false>), dim3(parts), dim3(kBlock),
+                       0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
+                       nullptr, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, false, false>), dim3(parts), dim3(kBlock),
+                       0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
+                       nullptr, nullptr, nullptr);
+}
+
 template <typename KeyT, int BITS>
 void pass_t(const RadixArgs<KeyT>& a, int p, int q, const KeyT* ki, const uint32_t* vi, KeyT* kd,
             uint32_t* vd, bool write_keys, hipStream_t st) {
-  const int parts = (int)((a.n_grid + kSortPart - 1) / kSortPart);
   const int shift = p * BITS;
   if (a.mode == 1) {
+    const int parts = (int)((a.n_grid + kSortPart - 1) / kSortPart);
     uint32_t* lb = a.lookback + (size_t)(q & 1) * a.lb_parts * 256;
     uint32_t* lb_next = a.lookback + (size_t)((q + 1) & 1) * a.lb_parts * 256;
     const uint32_t* h = a.hist + p * 256;
     if (write_keys)
-      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, true, true>), dim3(parts), dim3(kBlock), 0, st,
-                         ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0, h, a.tickets + q, lb,
-                         lb_next);
+      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, kSortItems, true, true>), dim3(parts),
+                         dim3(kBlock), 0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0,
+                         h, a.tickets + q, lb, lb_next);
     else
-      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, false, true>), dim3(parts), dim3(kBlock), 0, st,
-                         ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0, h, a.tickets + q, lb,
-                         lb_next);
+      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, kSortItems, false, true>), dim3(parts),
+                         dim3(kBlock), 0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0,
+                         h, a.tickets + q, lb, lb_next);
   } else {
-    hipLaunchKernelGGL((k_rs_upsweep<KeyT, BITS>), dim3(parts), dim3(kBlock), 0, st, ki, a.count,
-                       a.n_grid, shift, a.table, parts);
-    hipLaunchKernelGGL(k_row_scan, dim3(1 << BITS), dim3(kBlock), 0, st, a.table, parts, a.totals);
-    if (write_keys)
-      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, true, false>), dim3(parts), dim3(kBlock), 0, st,
-                         ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
-                         nullptr, nullptr, nullptr);
-    else
-      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, false, false>), dim3(parts), dim3(kBlock), 0, st,
-                         ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
-                         nullptr, nullptr, nullptr);
+    switch (rs_items(a.n_grid)) {
+      case 16: rs_pass<KeyT, BITS, 16>(a, p, ki, vi, kd, vd, write_keys, st); break;
+      case 8: rs_pass<KeyT, BITS, 8>(a, p, ki, vi, kd, vd, write_keys, st); break;
+      default: rs_pass<KeyT, BITS, 4>(a, p, ki, vi, kd, vd, write_keys, st); break;
+    }
   }
 }
 
@@ -568,6 +592,7 @@ SortLayout sort_layout(int64_t n, int64_t capacity) {
   const int64_t nn = n > 0 ? n : 1, cap = capacity > 0 ? capacity : 1;
   const int64_t big = nn > cap ? nn : cap;
   L.parts = (int)((big + kSortPart - 1) / kSortPart);
+  L.rs_parts = (int)((big + kBlock * 4 - 1) / (kBlock * 4));
   L.kg_parts = (int)((nn + kKgPart - 1) / kKgPart);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -583,7 +608,7 @@ SortLayout sort_layout(int64_t n, int64_t capacity) {
   L.hist = take((size_t)kMaxPassTotal * 256 * 4);
   L.tickets = take((size_t)kMaxPassTotal * 4);
   L.lookback = take((size_t)2 * L.parts * 256 * 4);
-  L.table = take((size_t)L.parts * 256 * 4);
+  L.table = take((size_t)L.rs_parts * 256 * 4);
   L.totals = take(256 * 4);
   L.kg_counts = take((size_t)L.kg_parts * 4);
   L.count = take(4);
@@ -595,6 +620,7 @@ SortLayout pairs_layout(int64_t n) {
   SortLayout L;
   const int64_t nn = n > 0 ? n : 1;
   L.parts = (int)((nn + kSortPart - 1) / kSortPart);
+  L.rs_parts = (int)((nn + kBlock * 4 - 1) / (kBlock * 4));
   L.kg_parts = 0;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -608,7 +634,7 @@ SortLayout pairs_layout(int64_t n) {
   L.hist = take((size_t)kMaxPassTotal * 256 * 4);
   L.tickets = take((size_t)kMaxPassTotal * 4);
   L.lookback = take((size_t)2 * L.parts * 256 * 4);
-  L.table = take((size_t)L.parts * 256 * 4);
+  L.table = take((size_t)L.rs_parts * 256 * 4);
   L.totals = take(256 * 4);
   L.kg_counts = 0;
   L.count = take(4);
