@@ -99,18 +99,21 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp,
 
 // ---------------------------------------------------------------- counting
 
-// Digit counts of one 4096-key partition per workgroup, written digit-major
-// into table[d * P + partition] (zeros past the end).
+// Digit counts of one partition (kBlock * ITEMS keys) per workgroup,
+// written digit-major into table[d * P + partition] (zeros past the end).
+// Counting needs no order, so each key is one LDS atomic increment into its
+// wave's own sub-histogram (no ballot matching).
 template <typename KeyT, int BITS, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ kin,
                                                        const uint32_t* __restrict__ count,
                                                        int64_t n_host, int shift,
                                                        uint32_t* __restrict__ table, int P) {
   constexpr int NB = 1 << BITS;
+  constexpr int NW = kBlock / 64;
   constexpr int PART = kBlock * ITEMS;
-  __shared__ uint32_t s_h[NB];
-  const int t = threadIdx.x;
-  for (int d = t; d < NB; d += kBlock) s_h[d] = 0;
+  __shared__ uint32_t s_h[NW][NB];
+  const int t = threadIdx.x, wave = t >> 6;
+  for (int d = t; d < NW * NB; d += kBlock) (&s_h[0][0])[d] = 0;
   __syncthreads();
   const uint32_t n = read_n(count, n_host);
   const uint32_t base = blockIdx.x * PART;
@@ -123,10 +126,15 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ 
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i)
-      wave_hist_add<BITS>(s_h, digit_of<KeyT, BITS>(k[i], shift), base + i * kBlock + t < n);
+      if (base + i * kBlock + t < n) atomicAdd(&s_h[wave][digit_of<KeyT, BITS>(k[i], shift)], 1u);
   }
   __syncthreads();
-  for (int d = t; d < NB; d += kBlock) table[(size_t)d * P + blockIdx.x] = s_h[d];
+  for (int d = t; d < NB; d += kBlock) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) c += s_h[w][d];
+    table[(size_t)d * P + blockIdx.x] = c;
+  }
 }
 
 // Exclusive scan of each row of a rows x P table in place (one workgroup
