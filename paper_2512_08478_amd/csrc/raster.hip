@@ -213,14 +213,11 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
 #pragma unroll
       for (int c = 0; c < St::NCH; ++c) {
         uint64_t m = hm[c];
-        while (m) {
-          const int j = c * 64 + __builtin_ctzll(m);
-          m &= m - 1;
-          const float u = S.ub[j][qx][row] + lxf;
-          const float4 h = S.hdr[j];
-          const float e = fmaf(-h.x, u * u, S.rt[j][row]);
+        // two hit splats per step: both splats' LDS reads are issued before
+        // the first one blends, hiding one read latency per pair
+        auto blend = [&](int j, float e, const float4& h) {
           const bool take = e >= log2_tau && live != 0.f;
-          if (!ballot(take)) continue;
+          if (!ballot(take)) return;
           const float alpha = take ? fminf(set.amax, hw_exp2(e)) : 0.f;
           const float w = alpha * T;
           C0 = fmaf(w, h.y, C0);
@@ -230,6 +227,19 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
           lastc = take ? bs + j + 1 - start : lastc;
           nb += take ? 1u : 0u;
           live = T < set.t_eps ? 0.f : live;
+        };
+        while (m) {
+          const int j0 = c * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          const bool two = m != 0;
+          const int j1 = two ? c * 64 + __builtin_ctzll(m) : j0;
+          if (two) m &= m - 1;
+          const float u0 = S.ub[j0][qx][row] + lxf, u1 = S.ub[j1][qx][row] + lxf;
+          const float4 h0 = S.hdr[j0], h1 = S.hdr[j1];
+          const float e0 = fmaf(-h0.x, u0 * u0, S.rt[j0][row]);
+          const float e1 = fmaf(-h1.x, u1 * u1, S.rt[j1][row]);
+          blend(j0, e0, h0);
+          if (two) blend(j1, e1, h1);
           if (!ballot(live != 0.f)) break;
         }
         if (!ballot(live != 0.f)) break;
