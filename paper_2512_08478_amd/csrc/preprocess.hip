@@ -85,14 +85,15 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int i, c
   rgb[0] = acc[0]; rgb[1] = acc[1]; rgb[2] = acc[2];
 }
 
-// Eq. 1 and the colour for Gaussian i; writes its record and returns the
-// number of tiles it touches (0 if culled).
-template <int DEG>
+// Eq. 1 and the colour for Gaussian i; fills its record r0..r2 and returns
+// the number of tiles it touches (0 if culled).  With STAGED_SH the colour
+// is left to the caller, which gets the SH view direction in dir[].
+template <int DEG, bool STAGED_SH>
 __device__ __forceinline__ uint32_t project_one(
     int i, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float4* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, const CamK& cam, const SetK& set,
-    gs_splat* __restrict__ splats, float* tz_out) {
+    const float* __restrict__ sh, const CamK& cam, const SetK& set, float4& r0, float4& r1,
+    float4& r2, float* dir) {
   const float p0 = means[3 * i], p1 = means[3 * i + 1], p2 = means[3 * i + 2];
   const float4 q = quats[i];
   const float lg = logits[i];
@@ -112,7 +113,9 @@ __device__ __forceinline__ uint32_t project_one(
   const float o = 1.f / (1.f + expf(-lg));
   const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
 
-  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+  r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+  r1 = r0;
+  r2 = r0;
   uint32_t tiles = 0;
   uint32_t rect_lo = 0x0000FFFFu, rect_hi = 0u;  // tx0=0xFFFF ty0=0 | tx1=0 ty1=0: empty
 
@@ -195,46 +198,105 @@ __device__ __forceinline__ uint32_t project_one(
           const float e2 = cam.Rk[2] * d0 + cam.Rk[5] * d1 + cam.Rk[8] * d2;
           d0 = e0; d1 = e1; d2 = e2;
         }
-        float Y[16];
-        sh_basis<DEG>(d0, d1, d2, Y);
-        float rgb[3];
-        sh_colour<DEG>(sh, i, Y, rgb);
         r0 = make_float4(mx, my, qa, qb);
-        r1 = make_float4(qc, o, fmaxf(rgb[0], 0.f), fmaxf(rgb[1], 0.f));
-        r2.x = fmaxf(rgb[2], 0.f);
+        r1 = make_float4(qc, o, 0.f, 0.f);
+        if (STAGED_SH) {
+          dir[0] = d0; dir[1] = d1; dir[2] = d2;
+        } else {
+          float Y[16];
+          sh_basis<DEG>(d0, d1, d2, Y);
+          float rgb[3];
+          sh_colour<DEG>(sh, i, Y, rgb);
+          r1.z = fmaxf(rgb[0], 0.f);
+          r1.w = fmaxf(rgb[1], 0.f);
+          r2.x = fmaxf(rgb[2], 0.f);
+        }
       }
     }
   }
   r2.y = tz;
   r2.z = __uint_as_float(rect_lo);
   r2.w = __uint_as_float(rect_hi);
-  float4* dst = reinterpret_cast<float4*>(splats + i);
-  dst[0] = r0;
-  dst[1] = r1;
-  dst[2] = r2;
-  *tz_out = tz;
   return tiles;
 }
+
+// SH rows per wave staged through LDS at a time (half a wave's Gaussians).
+constexpr int kShRows = 32;
 
 // Record of Gaussian i and its depth sort key (float32 bits of the
 // camera-space depth; the largest key when culled, so culled Gaussians sort
 // last).  Each workgroup writes its tile and visible counts to its own
 // slot of `partial`; k_count_finalize sums the slots.
+//
+// At SH degrees 1 and 3 a Gaussian's SH row is a whole number of 16-byte
+// vectors (48 or 192 bytes).  Instead of each lane reading its own row (a
+// wave-wide load then touches one 16-byte piece of each of 64 rows), the
+// wave copies the rows of its visible Gaussians into LDS with contiguous
+// 16-byte loads, 32 rows at a time, and each lane reads its row from LDS.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_preprocess(
     int n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float4* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, CamK cam, SetK set, gs_splat* __restrict__ splats,
     uint32_t* __restrict__ depth_keys, uint2* __restrict__ partial) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr bool STAGED = DEG == 1 || DEG == 3;
+  constexpr int F4 = STAGED ? K * 3 / 4 : 1;  // float4 per SH row
   __shared__ uint32_t s_vis[kBlock / 64], s_til[kBlock / 64];
+  __shared__ float4 s_sh[STAGED ? kBlock / 64 : 1][kShRows * F4];
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  uint32_t tiles = 0;
-  if (i < n) {
-    float tz = 0.f;
-    tiles = project_one<DEG>(i, means, log_scales, quats, logits, sh, cam, set, splats, &tz);
-    depth_keys[i] = tiles ? __float_as_uint(tz) : 0xFFFFFFFFu;
-  }
   const int lane = lane_id(), wave = threadIdx.x >> 6;
+  uint32_t tiles = 0;
+  float4 r0, r1, r2;
+  float dir[3] = {0.f, 0.f, 0.f};
+  if (i < n) {
+    tiles = project_one<DEG, STAGED>(i, means, log_scales, quats, logits, sh, cam, set, r0, r1,
+                                     r2, dir);
+    depth_keys[i] = tiles ? __float_as_uint(r2.y) : 0xFFFFFFFFu;
+  }
+  if constexpr (STAGED) {
+    const uint64_t need = ballot(tiles > 0);
+    const int i0 = blockIdx.x * kBlock + wave * 64;  // this wave's first Gaussian
+    const float4* sh4 = reinterpret_cast<const float4*>(sh);
+    float4* buf = s_sh[wave];
+#pragma unroll
+    for (int h = 0; h < 64 / kShRows; ++h) {
+      if (!((need >> (h * kShRows)) & ((1ull << kShRows) - 1ull))) continue;
+#pragma unroll
+      for (int k = 0; k < (kShRows * F4 + 63) / 64; ++k) {
+        const int f = lane + 64 * k, row = f / F4;
+        if (f < kShRows * F4 && ((need >> (h * kShRows + row)) & 1ull))
+          buf[f] = sh4[(size_t)(i0 + h * kShRows + row) * F4 + f % F4];
+      }
+      if (tiles > 0 && lane / kShRows == h) {
+        const float4* rowp = buf + (lane - h * kShRows) * F4;
+        float v[K * 3];
+#pragma unroll
+        for (int j = 0; j < F4; ++j) {
+          const float4 q = rowp[j];
+          v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
+        }
+        float Y[16];
+        sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+        float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          acc[0] = fmaf(v[3 * k], Y[k], acc[0]);
+          acc[1] = fmaf(v[3 * k + 1], Y[k], acc[1]);
+          acc[2] = fmaf(v[3 * k + 2], Y[k], acc[2]);
+        }
+        r1.z = fmaxf(acc[0], 0.f);
+        r1.w = fmaxf(acc[1], 0.f);
+        r2.x = fmaxf(acc[2], 0.f);
+      }
+    }
+  }
+  if (i < n) {
+    float4* dst = reinterpret_cast<float4*>(splats + i);
+    dst[0] = r0;
+    dst[1] = r1;
+    dst[2] = r2;
+  }
   const uint32_t wv = (uint32_t)__builtin_popcountll(ballot(tiles > 0));
   const uint32_t wt = wave_sum_u32(tiles);
   if (lane == 0) {
