@@ -172,6 +172,9 @@ int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set);
  *   depth_keys[n]   u32 depth sort key per Gaussian: the float32 bits of its
  *                   camera-space depth (Algorithm 1's `depths`), or
  *                   0xFFFFFFFF when culled, so culled Gaussians sort last.
+ *   tile_rects[2n]  u32 pair per Gaussian: the tile rect of its record,
+ *                   (tx0 | ty0 << 16, tx1 | ty1 << 16), packed densely so
+ *                   that key generation gathers 8 bytes per Gaussian.
  *   counts[2]       u32: counts[0] = (Gaussian, tile) instances in total,
  *                   counts[1] = visible Gaussians.
  * Culled (record with an empty rect, zero tiles): camera depth <= znear,
@@ -185,8 +188,9 @@ int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales,
                       const float* quats, const float* opacity_logits,
                       const float* sh, int32_t sh_degree, const float* model,
                       const gs_camera* cam, const gs_settings* set,
-                      gs_splat* splats, uint32_t* depth_keys, uint32_t* counts,
-                      void* workspace, size_t workspace_bytes, void* stream);
+                      gs_splat* splats, uint32_t* depth_keys, uint32_t* tile_rects,
+                      uint32_t* counts, void* workspace, size_t workspace_bytes,
+                      void* stream);
 
 /*
  * One asset of a multi-asset scene (Algorithm 1 loops over models, each with
@@ -216,8 +220,8 @@ int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n
                              const float* quats, const float* opacity_logits,
                              const float* sh, int32_t sh_degree, const gs_camera* cam,
                              const gs_settings* set, gs_splat* splats,
-                             uint32_t* depth_keys, uint32_t* counts, void* workspace,
-                             size_t workspace_bytes, void* stream);
+                             uint32_t* depth_keys, uint32_t* tile_rects, uint32_t* counts,
+                             void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * gs_sort -- key generation and the per-frame GPU radix sort (Algorithm 1,
@@ -233,7 +237,8 @@ int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n
  * the instances.  Sorting all n depth keys keeps equal depths in index
  * order, which replaces Algorithm 1's nondeterministic atomic append.
  *
- * Reads splats[n], depth_keys[n] and counts (device, from gs_preprocess).  Writes values[capacity] (u32 Gaussian index per sorted
+ * Reads splats[n], depth_keys[n], tile_rects[2n] and counts (device, from
+ * gs_preprocess).  Writes values[capacity] (u32 Gaussian index per sorted
  * instance), tile_ranges[2*tiles] (u32 [start, end) of each tile in the
  * sorted list, tiles = ceil(W/tile_w) * ceil(H/tile_h), row-major) and, if
  * `keys` is not NULL, keys[capacity] (the sorted u64 keys above).  Only the
@@ -246,7 +251,7 @@ int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n
  * Workspace: gs_workspace_size(GS_STAGE_SORT, n, capacity, cam, set).
  */
 int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
-                const uint32_t* counts, const gs_camera* cam,
+                const uint32_t* tile_rects, const uint32_t* counts, const gs_camera* cam,
                 const gs_settings* set, int64_t capacity,
                 uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
                 uint32_t* status_flag, void* workspace, size_t workspace_bytes,

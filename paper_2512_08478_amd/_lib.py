@@ -109,9 +109,9 @@ def load():
     lib.gs_sort_key_bits.restype = I32
     lib.gs_sort_key_bits.argtypes = [CAM, SET]
     lib.gs_preprocess.restype = I32
-    lib.gs_preprocess.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, SZ, P]
+    lib.gs_preprocess.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, P, SZ, P]
     lib.gs_sort.restype = I32
-    lib.gs_sort.argtypes = [I64, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ, P]
+    lib.gs_sort.argtypes = [I64, P, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ, P]
     lib.gs_sort_pairs.restype = I32
     lib.gs_sort_pairs.argtypes = [I64, P, P, I32, P, P, SET, P, SZ, P]
     lib.gs_rasterize.restype = I32
@@ -122,7 +122,7 @@ def load():
     AS = ctypes.POINTER(GsAsset)
     lib.gs_preprocess_assets.restype = I32
     lib.gs_preprocess_assets.argtypes = [I32, AS, I64, P, P, P, P, P, I32, CAM, SET, P, P, P, P,
-                                         SZ, P]
+                                         P, SZ, P]
     lib.gs_rasterize_backward_assets.restype = I32
     lib.gs_rasterize_backward_assets.argtypes = [I32, AS, I64, P, P, P, P, P, I32, CAM, SET, P, P,
                                                  P, P, P, P, P, P, P, P, P, I32, P, SZ, P]

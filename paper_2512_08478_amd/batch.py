@@ -65,7 +65,7 @@ class BatchRenderer:
         """Per-view instance capacities from one counting pass (syncs once per view)."""
         caps = []
         for cam in self.cams:
-            _, _, counts = self.R.preprocess(self.p, cam)
+            _, _, _, counts = self.R.preprocess(self.p, cam)
             caps.append(int(counts[:1].item()) & 0xFFFFFFFF)
         self.capacity = [max(256, int(c * self.headroom)) for c in caps]
         return list(caps)

@@ -287,14 +287,16 @@ int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n
                              const float* means, const float* log_scales, const float* quats,
                              const float* opacity_logits, const float* sh, int32_t sh_degree,
                              const gs_camera* cam, const gs_settings* set, gs_splat* splats,
-                             uint32_t* depth_keys, uint32_t* counts, void* workspace,
-                             size_t workspace_bytes, void* stream) {
+                             uint32_t* depth_keys, uint32_t* tile_rects, uint32_t* counts,
+                             void* workspace, size_t workspace_bytes, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
   if ((r = check_assets(n_assets, assets, n))) return r;
   if ((r = check_dev(counts))) return r;
-  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)))) return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)) ||
+                (r = check_dev(tile_rects))))
+    return r;
   if (workspace_bytes < gs::preprocess_ws_bytes(n)) return GS_ERR_WORKSPACE;
   if ((r = check_dev(workspace))) return r;
   gs::CamK ck[gs::kMaxAssets];
@@ -311,7 +313,7 @@ int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n
     if (c == 0) continue;
     e = gs::launch_preprocess((int)c, means + 3 * o, log_scales + 3 * o, quats + 4 * o,
                               opacity_logits + o, sh + K3 * o, sh_degree, ck[a], sk, splats + o,
-                              depth_keys + o, partial + blocks, st);
+                              depth_keys + o, tile_rects + 2 * o, partial + blocks, st);
     blocks += gs::preprocess_blocks(c);
   }
   if (e == hipSuccess) e = gs::launch_count_finalize(partial, blocks, counts, st);
@@ -323,24 +325,27 @@ int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n
 int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales, const float* quats,
                       const float* opacity_logits, const float* sh, int32_t sh_degree,
                       const float* model, const gs_camera* cam, const gs_settings* set,
-                      gs_splat* splats, uint32_t* depth_keys, uint32_t* counts, void* workspace,
-                      size_t workspace_bytes, void* stream) {
+                      gs_splat* splats, uint32_t* depth_keys, uint32_t* tile_rects,
+                      uint32_t* counts, void* workspace, size_t workspace_bytes, void* stream) {
   if (n < 0 || n >= kMaxN) return GS_ERR_INVALID_ARGUMENT;
   const gs_asset one = {0, n, model};
   return gs_preprocess_assets(1, &one, n, means, log_scales, quats, opacity_logits, sh,
-                              sh_degree, cam, set, splats, depth_keys, counts, workspace,
-                              workspace_bytes, stream);
+                              sh_degree, cam, set, splats, depth_keys, tile_rects, counts,
+                              workspace, workspace_bytes, stream);
 }
 
 int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
-                const uint32_t* counts, const gs_camera* cam, const gs_settings* set,
+                const uint32_t* tile_rects, const uint32_t* counts, const gs_camera* cam,
+                const gs_settings* set,
                 int64_t capacity, uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
                 uint32_t* status_flag, void* workspace, size_t workspace_bytes, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if (n < 0 || n >= kMaxN || capacity < 0 || capacity > kMaxInstances) return GS_ERR_INVALID_ARGUMENT;
   if ((r = check_dev(counts)) || (r = check_dev(tile_ranges))) return r;
-  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)))) return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)) ||
+                (r = check_dev(tile_rects))))
+    return r;
   if (capacity > 0 && (r = check_dev(values))) return r;
   if ((r = check_dev(keys, false)) || (r = check_dev(status_flag, false))) return r;
   const gs::SortLayout L = gs::sort_layout(n, capacity);
@@ -377,7 +382,7 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   e = gs::launch_radix_sort<uint32_t>(d, bits, pd, 0, false, "depth_pass", st);
   if (e != hipSuccess) return hip_fail(e);
   // instances of the visible Gaussians in depth order, then the tile digits
-  e = gs::launch_keygen(n, U(L.dv[0]), counts + 1, splats, tiles_x, count, U(L.kg_counts),
+  e = gs::launch_keygen(n, U(L.dv[0]), counts + 1, tile_rects, tiles_x, count, U(L.kg_counts),
                         U(L.totals), U(L.tk[0]), U(L.tv[0]), st);
   if (e != hipSuccess) return hip_fail(e);
   gs::RadixArgs<uint32_t> t = d;

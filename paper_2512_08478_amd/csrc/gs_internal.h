@@ -84,8 +84,8 @@ int preprocess_blocks(int64_t n);
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
-                             gs_splat* splats, uint32_t* depth_keys, uint2* partial,
-                             hipStream_t st);
+                             gs_splat* splats, uint32_t* depth_keys, uint32_t* tile_rects,
+                             uint2* partial, hipStream_t st);
 // counts[0] = sum of partial[].x (instances), counts[1] = sum of partial[].y (visible)
 hipError_t launch_count_finalize(const uint2* partial, int blocks, uint32_t* counts,
                                  hipStream_t st);
@@ -96,7 +96,7 @@ template <typename KeyT>
 hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int pass_base,
                              bool last_keys, const char* label, hipStream_t st);
 hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                         const gs_splat* splats, int tiles_x, const uint32_t* inst_count,
+                         const uint32_t* tile_rects, int tiles_x, const uint32_t* inst_count,
                          uint32_t* kg_counts, uint32_t* kg_total, uint32_t* tkeys, uint32_t* tvals,
                          hipStream_t st);
 hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,

@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
     int n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float4* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, CamK cam, SetK set, gs_splat* __restrict__ splats,
-    uint32_t* __restrict__ depth_keys, uint2* __restrict__ partial) {
+    uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint2* __restrict__ partial) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr bool STAGED = DEG == 1 || DEG == 3;
   constexpr int F4 = STAGED ? K * 3 / 4 : 1;  // float4 per SH row
@@ -253,6 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
     tiles = project_one<DEG, STAGED>(i, means, log_scales, quats, logits, sh, cam, set, r0, r1,
                                      r2, dir);
     depth_keys[i] = tiles ? __float_as_uint(r2.y) : 0xFFFFFFFFu;
+    rects[i] = make_uint2(__float_as_uint(r2.z), __float_as_uint(r2.w));
   }
   if constexpr (STAGED) {
     const uint64_t need = ballot(tiles > 0);
@@ -319,11 +320,22 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
 __global__ __launch_bounds__(kBlock) void k_count_finalize(const uint2* __restrict__ partial,
                                                            int blocks, uint32_t* __restrict__ counts) {
   __shared__ uint32_t s_a[kBlock / 64], s_b[kBlock / 64];
+  // 16 independent loads in flight per thread and step: one workgroup
+  // reads tens of thousands of slots, so load latency, not bandwidth, rules
+  constexpr int U = 16;
   uint32_t a = 0, b = 0;
-  for (int i = threadIdx.x; i < blocks; i += kBlock) {
-    const uint2 v = partial[i];
-    a += v.x;
-    b += v.y;
+  for (int base = 0; base < blocks; base += kBlock * U) {
+    uint2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * kBlock + (int)threadIdx.x;
+      v[u] = i < blocks ? partial[i] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a += v[u].x;
+      b += v[u].y;
+    }
   }
   a = wave_sum_u32(a);
   b = wave_sum_u32(b);
@@ -622,13 +634,13 @@ size_t preprocess_ws_bytes(int64_t n) {
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
-                             gs_splat* splats, uint32_t* depth_keys, uint2* partial,
-                             hipStream_t st) {
+                             gs_splat* splats, uint32_t* depth_keys, uint32_t* tile_rects,
+                             uint2* partial, hipStream_t st) {
   const int blocks = preprocess_blocks(n);
   if (n > 0) {
     trace_mark(st, "preprocess");
     const float4* q4 = reinterpret_cast<const float4*>(quats);
-#define GS_PRE(D) hipLaunchKernelGGL(k_preprocess<D>, dim3(blocks), dim3(kBlock), 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, depth_keys, partial)
+#define GS_PRE(D) hipLaunchKernelGGL(k_preprocess<D>, dim3(blocks), dim3(kBlock), 0, st, n, means, log_scales, q4, logits, sh, cam, set, splats, depth_keys, reinterpret_cast<uint2*>(tile_rects), partial)
     switch (degree) {
       case 0: GS_PRE(0); break;
       case 1: GS_PRE(1); break;

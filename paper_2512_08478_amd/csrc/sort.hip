@@ -358,7 +358,7 @@ __device__ __forceinline__ uint32_t rect_tiles(uint32_t lo, uint32_t hi) {
 // Tiles touched by each 1024-Gaussian slice of the depth-sorted visible list.
 __global__ __launch_bounds__(kBlock) void k_kg_count(const uint32_t* __restrict__ sorted_idx,
                                                      const uint32_t* __restrict__ vis_count,
-                                                     const gs_splat* __restrict__ splats,
+                                                     const uint2* __restrict__ rects,
                                                      uint32_t* __restrict__ kg_counts) {
   __shared__ uint32_t s_tmp[kBlock / 64];
   const uint32_t nvis = *vis_count;
@@ -368,8 +368,8 @@ __global__ __launch_bounds__(kBlock) void k_kg_count(const uint32_t* __restrict_
   for (int j = 0; j < kKgItems; ++j) {
     const uint32_t p = base + j * kBlock + threadIdx.x;
     if (p < nvis) {
-      const float4 r2 = reinterpret_cast<const float4*>(splats + sorted_idx[p])[2];
-      sum += rect_tiles(__float_as_uint(r2.z), __float_as_uint(r2.w));
+      const uint2 r = rects[sorted_idx[p]];
+      sum += rect_tiles(r.x, r.y);
     }
   }
   uint32_t tot;
@@ -410,7 +410,7 @@ constexpr int kKgWinItems = kKgWin / kBlock;
 // splats do not serialise a thread.
 __global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict__ sorted_idx,
                                                      const uint32_t* __restrict__ vis_count,
-                                                     const gs_splat* __restrict__ splats,
+                                                     const uint2* __restrict__ rects,
                                                      int tiles_x,
                                                      const uint32_t* __restrict__ inst_count,
                                                      const uint32_t* __restrict__ kg_prefix,
@@ -432,9 +432,9 @@ __global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict_
     uint32_t g = 0, lo = 0, hi = 0, c = 0;
     if (p < nvis) {
       g = sorted_idx[p];
-      const float4 r2 = reinterpret_cast<const float4*>(splats + g)[2];
-      lo = __float_as_uint(r2.z);
-      hi = __float_as_uint(r2.w);
+      const uint2 r = rects[g];
+      lo = r.x;
+      hi = r.y;
       c = rect_tiles(lo, hi);
     }
     s_g[li] = g;
@@ -702,18 +702,19 @@ template hipError_t launch_radix_sort<uint64_t>(const RadixArgs<uint64_t>&, int,
                                                 const char*, hipStream_t);
 
 hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                         const gs_splat* splats, int tiles_x, const uint32_t* inst_count,
+                         const uint32_t* tile_rects, int tiles_x, const uint32_t* inst_count,
                          uint32_t* kg_counts, uint32_t* kg_total, uint32_t* tkeys, uint32_t* tvals,
                          hipStream_t st) {
   const int parts = (int)((n + kKgPart - 1) / kKgPart);
   if (parts == 0) return hipSuccess;
   trace_mark(st, "kg_count");
-  hipLaunchKernelGGL(k_kg_count, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count, splats,
+  const uint2* rects = reinterpret_cast<const uint2*>(tile_rects);
+  hipLaunchKernelGGL(k_kg_count, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count, rects,
                      kg_counts);
   trace_mark(st, "kg_scan");
   hipLaunchKernelGGL(k_row_scan, dim3(1), dim3(kBlock), 0, st, kg_counts, parts, kg_total);
   trace_mark(st, "keygen");
-  hipLaunchKernelGGL(k_kg_write, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count, splats,
+  hipLaunchKernelGGL(k_kg_write, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count, rects,
                      tiles_x, inst_count, kg_counts, tkeys, tvals);
   return hipGetLastError();
 }

@@ -74,6 +74,7 @@ class Frame:
     last: torch.Tensor       # (H, W) int32 (u32 on the device)
     splats: torch.Tensor     # (n*48,) uint8
     depth_keys: torch.Tensor  # (n,) int32 (u32): depth sort keys
+    rects: torch.Tensor      # (2n,) int32 (u32 pairs): tile rect per Gaussian
     counts: torch.Tensor     # (2,) int32 (u32), device: instances, visible
     keys: torch.Tensor       # (capacity,) int64 (u64) or None
     values: torch.Tensor     # (capacity,) int32 (u32)
@@ -114,6 +115,7 @@ class Renderer:
         n = p.n
         splats = self._buf("splats", n * L.SPLAT_BYTES, reuse)[:n * L.SPLAT_BYTES]
         dkeys = self._buf("depth_keys", n * 4, reuse).view(torch.int32)[:n]
+        rects = self._buf("rects", n * 8, reuse).view(torch.int32)[:2 * n]
         counts = self._buf("counts", 8, reuse).view(torch.int32)[:2]
         ws_bytes = lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, n, 0, ctypes.byref(c), ctypes.byref(s))
         ws = self._buf("ws_pre", ws_bytes, reuse)
@@ -121,16 +123,19 @@ class Renderer:
             tab, _keep = L.asset_table(p.assets)
             st = lib.gs_preprocess_assets(len(p.assets), tab, n, *[_p(t) for t in p.tensors()],
                                           p.sh_degree, ctypes.byref(c), ctypes.byref(s), _p(splats),
-                                          _p(dkeys), _p(counts), _p(ws), ws.numel(), _stream())
+                                          _p(dkeys), _p(rects), _p(counts), _p(ws), ws.numel(),
+                                          _stream())
             L.check(st, "gs_preprocess_assets")
         else:
             st = lib.gs_preprocess(n, *[_p(t) for t in p.tensors()], p.sh_degree,
                                    L.model_array(p.model), ctypes.byref(c), ctypes.byref(s),
-                                   _p(splats), _p(dkeys), _p(counts), _p(ws), ws.numel(), _stream())
+                                   _p(splats), _p(dkeys), _p(rects), _p(counts), _p(ws), ws.numel(),
+                                   _stream())
             L.check(st, "gs_preprocess")
-        return splats, dkeys, counts
+        return splats, dkeys, rects, counts
 
-    def sort(self, n, splats, dkeys, counts, cam, capacity=None, reuse=True, want_keys=False):
+    def sort(self, n, splats, dkeys, rects, counts, cam, capacity=None, reuse=True,
+             want_keys=False):
         """capacity=None reads the instance count back (one sync)."""
         lib = L.load()
         c, s = L.make_camera(cam), self.settings
@@ -145,7 +150,8 @@ class Renderer:
         if ws_bytes == 0:
             raise L.GsError(L.GS_ERR_INVALID_ARGUMENT, "gs_workspace_size(sort)")
         ws = self._buf("ws_sort", ws_bytes)
-        st = lib.gs_sort(n, _p(splats), _p(dkeys), _p(counts), ctypes.byref(c), ctypes.byref(s),
+        st = lib.gs_sort(n, _p(splats), _p(dkeys), _p(rects), _p(counts), ctypes.byref(c),
+                         ctypes.byref(s),
                          capacity, _p(keys), _p(values), _p(ranges), _p(flag), _p(ws), ws.numel(),
                          _stream())
         L.check(st, "gs_sort")
@@ -169,11 +175,11 @@ class Renderer:
         return image, T, last
 
     def forward(self, p: GaussianParams, cam, capacity=None, reuse=True, want_keys=False) -> Frame:
-        splats, dkeys, counts = self.preprocess(p, cam, reuse)
-        keys, values, ranges, flag, cap = self.sort(p.n, splats, dkeys, counts, cam, capacity,
+        splats, dkeys, rects, counts = self.preprocess(p, cam, reuse)
+        keys, values, ranges, flag, cap = self.sort(p.n, splats, dkeys, rects, counts, cam, capacity,
                                                     reuse, want_keys)
         image, T, last = self.rasterize(splats, values, ranges, cam)
-        return Frame(image, T, last, splats, dkeys, counts, keys, values, ranges, flag, cap)
+        return Frame(image, T, last, splats, dkeys, rects, counts, keys, values, ranges, flag, cap)
 
     def backward(self, p: GaussianParams, cam, fr: Frame, dL_dimage, out=None, accumulate=False):
         lib = L.load()

@@ -84,7 +84,8 @@ def pre(lib, n=4, deg=0, cam=None, st=None, ptrs=None, total=FAKE, ws_bytes=1 <<
     p = ptrs or [FAKE] * 5
     return lib.gs_preprocess(n, *[ctypes.c_void_p(x) if x else None for x in p], deg, None,
                              ctypes.byref(c), ctypes.byref(s), ctypes.c_void_p(FAKE),
-                             ctypes.c_void_p(FAKE), ctypes.c_void_p(total) if total else None,
+                             ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
+                             ctypes.c_void_p(total) if total else None,
                              ctypes.c_void_p(FAKE), ws_bytes, None)
 
 
@@ -118,11 +119,11 @@ def test_model_transform_must_be_similarity(lib):
     c, s = cam_1080(), L.default_settings()
     F = ctypes.c_void_p(FAKE)
     shear = (ctypes.c_float * 12)(1, 0.5, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
-    r = lib.gs_preprocess(4, *[F] * 5, 0, shear, ctypes.byref(c), ctypes.byref(s), F, F, F, F,
+    r = lib.gs_preprocess(4, *[F] * 5, 0, shear, ctypes.byref(c), ctypes.byref(s), F, F, F, F, F,
                           1 << 20, None)
     assert r == L.GS_ERR_INVALID_ARGUMENT
     mirror = (ctypes.c_float * 12)(-1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
-    r = lib.gs_preprocess(4, *[F] * 5, 0, mirror, ctypes.byref(c), ctypes.byref(s), F, F, F, F,
+    r = lib.gs_preprocess(4, *[F] * 5, 0, mirror, ctypes.byref(c), ctypes.byref(s), F, F, F, F, F,
                           1 << 20, None)
     assert r == L.GS_ERR_INVALID_ARGUMENT
 
@@ -132,7 +133,7 @@ def test_sort_argument_validation(lib):
     F = ctypes.c_void_p(FAKE)
 
     def srt(n=4, cap=16, keys=F, values=F, ws=1 << 30, flag=None):
-        return lib.gs_sort(n, F, F, F, ctypes.byref(c), ctypes.byref(s), cap, keys, values, F,
+        return lib.gs_sort(n, F, F, F, F, ctypes.byref(c), ctypes.byref(s), cap, keys, values, F,
                            flag, F, ws, None)
     assert srt(cap=-1) == L.GS_ERR_INVALID_ARGUMENT
     assert srt(cap=1 << 30) == L.GS_ERR_INVALID_ARGUMENT
@@ -178,7 +179,7 @@ def test_asset_table_validation(lib):
         arr, keep = L.asset_table(table)
         na = len(table) if n_assets is None else n_assets
         return lib.gs_preprocess_assets(na, arr, n, *[F] * 5, 0, ctypes.byref(c), ctypes.byref(s),
-                                        F, F, F, F, 1 << 20, None)
+                                        F, F, F, F, F, 1 << 20, None)
 
     def ba(table, n):
         arr, keep = L.asset_table(table)

@@ -46,13 +46,13 @@ def test_multi_asset_records_equal_single_asset_records(R):
     assets, cams = small_batch(n_views=1)
     p = concat_params(assets)
     cam = cams[0]
-    splats, _, counts = R.preprocess(p, cam, reuse=False)
+    splats, _, _, counts = R.preprocess(p, cam, reuse=False)
     rec = splats_np(splats, p.n)
     c_all = counts.cpu().numpy().view(np.uint32)
     tot = np.zeros(2, np.int64)
     off = 0
     for a in assets:
-        s1, _, c1 = R.preprocess(GaussianParams.from_scene(a), cam, reuse=False)
+        s1, _, _, c1 = R.preprocess(GaussianParams.from_scene(a), cam, reuse=False)
         r1 = splats_np(s1, a.n)
         assert r1.tobytes() == rec[off:off + a.n].tobytes()
         tot += c1.cpu().numpy().view(np.uint32)

@@ -77,7 +77,7 @@ def extra_pairs_harmless(orc, ref, rec, cam, v):
 def test_preprocess_tiny(R, orc):
     print_case("preprocess tiny 4096")
     sc, cam = S.tiny_scene()
-    splats, dkeys, counts = R.preprocess(gp(sc), cam)
+    splats, dkeys, rects, counts = R.preprocess(gp(sc), cam)
     torch.cuda.synchronize()
     rec = splats_np(splats, sc.n)
     ref = orc.preprocess(sc, cam)
@@ -359,7 +359,7 @@ def test_capacity_overflow_flag(R):
     sc, cam = S.tiny_scene()
     p = gp(sc)
     pre = R.preprocess(p, cam)
-    tot = int(u32(pre[2])[0])
+    tot = int(u32(pre[3])[0])  # counts[0]: instances
     keys, values, ranges, flag, cap = R.sort(sc.n, *pre, cam, capacity=tot // 2)
     torch.cuda.synchronize()
     assert int(u32(flag)[0]) & 1 == 1
