@@ -379,13 +379,22 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   d.k_out = U(L.dk[0]); d.v_out = U(L.dv[0]);
   d.table = U(L.table); d.totals = U(L.totals);
   d.hist = U(L.hist); d.tickets = U(L.tickets); d.lookback = U(L.lookback); d.lb_parts = L.parts;
+  // the last depth pass also gathers the visible Gaussians' tile rects into
+  // depth order, so key generation reads them contiguously
+  uint2* drect = reinterpret_cast<uint2*>(ws + L.drect);
+  d.gather_src = reinterpret_cast<const uint2*>(tile_rects);
+  d.gather_dst = drect;
+  d.gather_count = counts + 1;
   e = gs::launch_radix_sort<uint32_t>(d, bits, pd, 0, false, "depth_pass", st);
   if (e != hipSuccess) return hip_fail(e);
   // instances of the visible Gaussians in depth order, then the tile digits
-  e = gs::launch_keygen(n, U(L.dv[0]), counts + 1, tile_rects, tiles_x, count, U(L.kg_counts),
+  e = gs::launch_keygen(n, U(L.dv[0]), counts + 1, drect, tiles_x, count, U(L.kg_counts),
                         U(L.totals), U(L.tk[0]), U(L.tv[0]), st);
   if (e != hipSuccess) return hip_fail(e);
   gs::RadixArgs<uint32_t> t = d;
+  t.gather_src = nullptr;
+  t.gather_dst = nullptr;
+  t.gather_count = nullptr;
   t.n_grid = capacity;
   t.count = count;
   t.kin = U(L.tk[0]);

@@ -46,7 +46,8 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // tickets and look-back words (two buffers), the reduce-then-scan count
 // table and digit totals, keygen slice counts, the kept instance count.
 struct SortLayout {
-  size_t dk[2], dv[2], tk[2], tv[2], tkf, hist, tickets, lookback, table, totals, kg_counts, count;
+  size_t dk[2], dv[2], drect, tk[2], tv[2], tkf, hist, tickets, lookback, table, totals, kg_counts,
+      count;
   size_t bytes;
   int parts;     // 4096-key partitions of the largest sort
   int rs_parts;  // 1024-key partitions of the largest sort (reduce-then-scan table rows)
@@ -73,6 +74,11 @@ struct RadixArgs {
   uint32_t* tickets;        // mode 1: one per pass
   uint32_t* lookback;       // mode 1: two buffers of lb_parts x 256 words
   int lb_parts;
+  // optional: the last pass also writes gather_dst[i] = gather_src[value of
+  // sorted position i] for positions i < *gather_count
+  const uint2* gather_src;
+  uint2* gather_dst;
+  const uint32_t* gather_count;
 };
 
 // Launchers (enqueue only; return the first launch error).
@@ -96,7 +102,7 @@ template <typename KeyT>
 hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int pass_base,
                              bool last_keys, const char* label, hipStream_t st);
 hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                         const uint32_t* tile_rects, int tiles_x, const uint32_t* inst_count,
+                         const uint2* sorted_rects, int tiles_x, const uint32_t* inst_count,
                          uint32_t* kg_counts, uint32_t* kg_total, uint32_t* tkeys, uint32_t* tvals,
                          hipStream_t st);
 hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,

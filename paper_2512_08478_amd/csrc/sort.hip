@@ -217,7 +217,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
     const KeyT* __restrict__ kin, const uint32_t* __restrict__ vin, KeyT* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ count, int64_t n_host, int shift,
     const uint32_t* __restrict__ table, int P, const uint32_t* __restrict__ totals,
-    uint32_t* __restrict__ ticket, uint32_t* __restrict__ lb, uint32_t* __restrict__ lb_next) {
+    uint32_t* __restrict__ ticket, uint32_t* __restrict__ lb, uint32_t* __restrict__ lb_next,
+    const uint2* __restrict__ gsrc, uint2* __restrict__ gdst, const uint32_t* __restrict__ gath_n) {
   constexpr int NB = 1 << BITS;
   constexpr int NW = kBlock / 64;
   constexpr int PART = kBlock * ITEMS;
@@ -343,9 +344,14 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
     s_vals[pos[i]] = idx < n ? (vin ? vin[idx] : idx) : 0u;
   }
   __syncthreads();
+  const uint32_t gn = gdst ? *gath_n : 0u;
   for (int j = t; j < PART; j += kBlock) {
     const uint32_t g = s_gbase[s_dig[j]] + j;
-    if (g < n) vout[g] = s_vals[j];
+    if (g < n) {
+      const uint32_t v = s_vals[j];
+      vout[g] = v;
+      if (g < gn) gdst[g] = gsrc[v];
+    }
   }
 }
 
@@ -356,9 +362,8 @@ __device__ __forceinline__ uint32_t rect_tiles(uint32_t lo, uint32_t hi) {
 }
 
 // Tiles touched by each 1024-Gaussian slice of the depth-sorted visible list.
-__global__ __launch_bounds__(kBlock) void k_kg_count(const uint32_t* __restrict__ sorted_idx,
-                                                     const uint32_t* __restrict__ vis_count,
-                                                     const uint2* __restrict__ rects,
+__global__ __launch_bounds__(kBlock) void k_kg_count(const uint32_t* __restrict__ vis_count,
+                                                     const uint2* __restrict__ sorted_rects,
                                                      uint32_t* __restrict__ kg_counts) {
   __shared__ uint32_t s_tmp[kBlock / 64];
   const uint32_t nvis = *vis_count;
@@ -368,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_kg_count(const uint32_t* __restrict_
   for (int j = 0; j < kKgItems; ++j) {
     const uint32_t p = base + j * kBlock + threadIdx.x;
     if (p < nvis) {
-      const uint2 r = rects[sorted_idx[p]];
+      const uint2 r = sorted_rects[p];
       sum += rect_tiles(r.x, r.y);
     }
   }
@@ -410,7 +415,7 @@ constexpr int kKgWinItems = kKgWin / kBlock;
 // splats do not serialise a thread.
 __global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict__ sorted_idx,
                                                      const uint32_t* __restrict__ vis_count,
-                                                     const uint2* __restrict__ rects,
+                                                     const uint2* __restrict__ sorted_rects,
                                                      int tiles_x,
                                                      const uint32_t* __restrict__ inst_count,
                                                      const uint32_t* __restrict__ kg_prefix,
@@ -432,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict_
     uint32_t g = 0, lo = 0, hi = 0, c = 0;
     if (p < nvis) {
       g = sorted_idx[p];
-      const uint2 r = rects[g];
+      const uint2 r = sorted_rects[p];
       lo = r.x;
       hi = r.y;
       c = rect_tiles(lo, hi);
@@ -543,7 +548,10 @@ inline int rs_items(int64_t n) {
 
 template <typename KeyT, int BITS, int ITEMS>
 void rs_pass(const RadixArgs<KeyT>& a, int p, const KeyT* ki, const uint32_t* vi, KeyT* kd,
-             uint32_t* vd, bool write_keys, hipStream_t st) {
+             uint32_t* vd, bool write_keys, bool gather, hipStream_t st) {
+  const uint2* gs = gather ? a.gather_src : nullptr;
+  uint2* gd = gather ? a.gather_dst : nullptr;
+  const uint32_t* gc = gather ? a.gather_count : nullptr;
   constexpr int PART = kBlock * ITEMS;
   const int parts = (int)((a.n_grid + PART - 1) / PART);
   const int shift = p * BITS;
@@ -553,17 +561,20 @@ void rs_pass(const RadixArgs<KeyT>& a, int p, const KeyT* ki, const uint32_t* vi
   if (write_keys)
     hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, true, false>), dim3(parts), dim3(kBlock),
                        0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
-                       nullptr, nullptr, nullptr);
+                       nullptr, nullptr, nullptr, gs, gd, gc);
   else
     hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, false, false>), dim3(parts), dim3(kBlock),
                        0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
-                       nullptr, nullptr, nullptr);
+                       nullptr, nullptr, nullptr, gs, gd, gc);
 }
 
 template <typename KeyT, int BITS>
 void pass_t(const RadixArgs<KeyT>& a, int p, int q, const KeyT* ki, const uint32_t* vi, KeyT* kd,
-            uint32_t* vd, bool write_keys, hipStream_t st) {
+            uint32_t* vd, bool write_keys, bool gather, hipStream_t st) {
   const int shift = p * BITS;
+  const uint2* gs = gather ? a.gather_src : nullptr;
+  uint2* gd = gather ? a.gather_dst : nullptr;
+  const uint32_t* gc = gather ? a.gather_count : nullptr;
   if (a.mode == 1) {
     const int parts = (int)((a.n_grid + kSortPart - 1) / kSortPart);
     uint32_t* lb = a.lookback + (size_t)(q & 1) * a.lb_parts * 256;
@@ -572,16 +583,16 @@ void pass_t(const RadixArgs<KeyT>& a, int p, int q, const KeyT* ki, const uint32
     if (write_keys)
       hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, kSortItems, true, true>), dim3(parts),
                          dim3(kBlock), 0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0,
-                         h, a.tickets + q, lb, lb_next);
+                         h, a.tickets + q, lb, lb_next, gs, gd, gc);
     else
       hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, kSortItems, false, true>), dim3(parts),
                          dim3(kBlock), 0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0,
-                         h, a.tickets + q, lb, lb_next);
+                         h, a.tickets + q, lb, lb_next, gs, gd, gc);
   } else {
     switch (rs_items(a.n_grid)) {
-      case 16: rs_pass<KeyT, BITS, 16>(a, p, ki, vi, kd, vd, write_keys, st); break;
-      case 8: rs_pass<KeyT, BITS, 8>(a, p, ki, vi, kd, vd, write_keys, st); break;
-      default: rs_pass<KeyT, BITS, 4>(a, p, ki, vi, kd, vd, write_keys, st); break;
+      case 16: rs_pass<KeyT, BITS, 16>(a, p, ki, vi, kd, vd, write_keys, gather, st); break;
+      case 8: rs_pass<KeyT, BITS, 8>(a, p, ki, vi, kd, vd, write_keys, gather, st); break;
+      default: rs_pass<KeyT, BITS, 4>(a, p, ki, vi, kd, vd, write_keys, gather, st); break;
     }
   }
 }
@@ -610,6 +621,7 @@ SortLayout sort_layout(int64_t n, int64_t capacity) {
   };
   L.dk[0] = take((size_t)nn * 4); L.dv[0] = take((size_t)nn * 4);
   L.dk[1] = take((size_t)nn * 4); L.dv[1] = take((size_t)nn * 4);
+  L.drect = take((size_t)nn * 8);
   L.tk[0] = take((size_t)cap * 4); L.tv[0] = take((size_t)cap * 4);
   L.tk[1] = take((size_t)cap * 4); L.tv[1] = take((size_t)cap * 4);
   L.tkf = take((size_t)cap * 4);
@@ -638,7 +650,7 @@ SortLayout pairs_layout(int64_t n) {
   };
   L.dk[0] = take((size_t)nn * 8);  // alternate key buffer (u64)
   L.dv[0] = take((size_t)nn * 4);  // alternate value buffer
-  L.dk[1] = L.dv[1] = L.tk[0] = L.tv[0] = L.tk[1] = L.tv[1] = L.tkf = 0;
+  L.dk[1] = L.dv[1] = L.drect = L.tk[0] = L.tv[0] = L.tk[1] = L.tv[1] = L.tkf = 0;
   L.hist = take((size_t)kMaxPassTotal * 256 * 4);
   L.tickets = take((size_t)kMaxPassTotal * 4);
   L.lookback = take((size_t)2 * L.parts * 256 * 4);
@@ -685,11 +697,12 @@ hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int
     KeyT* kd = to_out ? a.k_out : a.k_alt;
     uint32_t* vd = to_out ? a.v_out : a.v_alt;
     const bool wk = (p + 1 < passes) || last_keys;
+    const bool ga = p + 1 == passes && a.gather_dst != nullptr;
     trace_mark(st, label);
     switch (bits) {
-      case 6: pass_t<KeyT, 6>(a, p, q, ki, vi, kd, vd, wk, st); break;
-      case 7: pass_t<KeyT, 7>(a, p, q, ki, vi, kd, vd, wk, st); break;
-      default: pass_t<KeyT, 8>(a, p, q, ki, vi, kd, vd, wk, st); break;
+      case 6: pass_t<KeyT, 6>(a, p, q, ki, vi, kd, vd, wk, ga, st); break;
+      case 7: pass_t<KeyT, 7>(a, p, q, ki, vi, kd, vd, wk, ga, st); break;
+      default: pass_t<KeyT, 8>(a, p, q, ki, vi, kd, vd, wk, ga, st); break;
     }
     ki = kd;
     vi = vd;
@@ -702,19 +715,19 @@ template hipError_t launch_radix_sort<uint64_t>(const RadixArgs<uint64_t>&, int,
                                                 const char*, hipStream_t);
 
 hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                         const uint32_t* tile_rects, int tiles_x, const uint32_t* inst_count,
+                         const uint2* sorted_rects, int tiles_x, const uint32_t* inst_count,
                          uint32_t* kg_counts, uint32_t* kg_total, uint32_t* tkeys, uint32_t* tvals,
                          hipStream_t st) {
   const int parts = (int)((n + kKgPart - 1) / kKgPart);
   if (parts == 0) return hipSuccess;
   trace_mark(st, "kg_count");
-  const uint2* rects = reinterpret_cast<const uint2*>(tile_rects);
-  hipLaunchKernelGGL(k_kg_count, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count, rects,
+  hipLaunchKernelGGL(k_kg_count, dim3(parts), dim3(kBlock), 0, st, vis_count, sorted_rects,
                      kg_counts);
   trace_mark(st, "kg_scan");
   hipLaunchKernelGGL(k_row_scan, dim3(1), dim3(kBlock), 0, st, kg_counts, parts, kg_total);
   trace_mark(st, "keygen");
-  hipLaunchKernelGGL(k_kg_write, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count, rects,
+  hipLaunchKernelGGL(k_kg_write, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count,
+                     sorted_rects,
                      tiles_x, inst_count, kg_counts, tkeys, tvals);
   return hipGetLastError();
 }
