@@ -1,31 +1,33 @@
 // Tile compositing (Section 3.2 Eqs. 2-3) forward and backward.
 //
-// One workgroup per tile; each wave owns one 8x8 pixel quadrant of the tile
-// and each lane one pixel.  The tile's splats (already in (depth, index)
-// order) are staged through LDS in batches.  While staging, every splat
-// gets
-//   * a quadrant mask: the quadrants its opacity-aware footprint (where
-//     o exp(-Q/2) >= alpha_min) can reach, from the ellipse's exact extents
-//     with a small outward margin, so that a wave skips a splat with a
-//     scalar test and no vector work;
+// The sort groups splats by tile (TW x TH pixels).  Both kernels run one
+// 64-thread workgroup -- one wave -- per 8x8 quadrant of a tile, each lane
+// owning one pixel; the quadrant walks its tile's whole list (in (depth,
+// index) order) and works only on the splats that reach it.  Quadrants of
+// one tile never wait on each other, and the grid has four to eight times
+// as many workgroups as tiles, which balances uneven lists.  Splats are
+// staged through LDS in batches of 64.  While staging, every splat gets
+//   * a quadrant mask: whether its opacity-aware footprint (where
+//     o exp(-Q/2) >= alpha_min) can reach the quadrant, from the ellipse's
+//     exact extents with a small outward margin, so that the wave skips
+//     the splat with a scalar test;
 //   * per-row terms of the log2 weight
-//       e = log2(o) - (log2e/2) Q = rowterm[r] - qa' (ubase[r][g] + lx)^2,
+//       e = log2(o) - (log2e/2) Q = rowterm[r] - qa' (ubase[r] + lx)^2,
 //     with Q = qa (dx - qb dy)^2 + qc dy^2, qa' = qa log2e/2, and
-//     ubase[r][g] the value of dx - qb dy at column 0 of the 8-pixel column
-//     group g of row r.  A pixel then costs an add, a multiply and an fma.
-//     The terms depend only on the pixel's row and 8-aligned column group,
-//     never on the tile shape, so every tile shape gives bitwise-identical
-//     images; the backward kernel stages them identically, so its
-//     skip decisions match the forward pass exactly.
+//     ubase[r] the value of dx - qb dy at the quadrant's first column in
+//     row r.  A pixel then costs an add, a multiply and an fma.  The terms
+//     depend only on the pixel's row and 8-aligned column group, never on
+//     the tile shape, so every tile shape gives bitwise-identical images;
+//     the backward kernel stages them identically, so its skip decisions
+//     match the forward pass exactly.
 // Per pixel, front to back: skip when e < log2(alpha_min); otherwise
 // alpha = min(alpha_max, 2^e), C += T alpha rgb, T *= 1 - alpha, and stop
-// right after the blend that takes T below t_eps.  A wave whose pixels have
-// all stopped skips the batch loop; the workgroup leaves once every pixel
-// has stopped.
+// right after the blend that takes T below t_eps.  The workgroup leaves
+// once all its pixels have stopped.
 //
-// Tiles are assigned XCD-major: the hardware deals consecutive workgroups
-// round-robin to the 8 XCDs, so workgroup b works on tile
-// (b % 8) * ceil(tiles/8) + b / 8 and each XCD's L2 sees one contiguous band
+// Quadrants are assigned XCD-major: the hardware deals consecutive
+// workgroups round-robin to the 8 XCDs, so workgroup b works on quadrant
+// (b % 8) * ceil(units/8) + b / 8; each XCD's L2 sees one contiguous band
 // of tiles, whose splats it shares.
 #include "gs_device.h"
 #include "gs_internal.h"
@@ -147,28 +149,36 @@ __device__ __forceinline__ void quadrant_hits(const Stage<TW, TH>& S, int cnt, i
   }
 }
 
+// One 64-thread workgroup (one wave) per 8x8 quadrant of a TW x TH tile:
+// it walks the tile's whole list and composites the splats that reach its
+// quadrant.  Waves of one tile never wait on each other, and a quadrant
+// whose pixels have all stopped leaves at once.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ splats,
-                                                   const uint32_t* __restrict__ values,
-                                                   const uint32_t* __restrict__ ranges,
-                                                   SetK set, int W, int H,
-                                                   float* __restrict__ image,
-                                                   float* __restrict__ T_final,
-                                                   uint32_t* __restrict__ last,
-                                                   uint32_t* __restrict__ n_blend) {
-  using St = Stage<TW, TH>;
+__global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ splats,
+                                               const uint32_t* __restrict__ values,
+                                               const uint32_t* __restrict__ ranges,
+                                               SetK set, int W, int H,
+                                               float* __restrict__ image,
+                                               float* __restrict__ T_final,
+                                               uint32_t* __restrict__ last,
+                                               uint32_t* __restrict__ n_blend) {
+  using St = Stage<8, 8>;
+  constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ St S;
   const int tiles = set.tiles_x * set.tiles_y;
-  const int tile = xcd_tile(blockIdx.x, tiles);
-  if (tile >= tiles) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int qx = wave % St::QX, qy = wave / St::QX;
-  const int tx0 = (tile % set.tiles_x) * TW, ty0 = (tile / set.tiles_x) * TH;
-  const int lx = lane & 7, row = qy * 8 + (lane >> 3);
-  const int px = tx0 + qx * 8 + lx, py = ty0 + row;
+  const int unit = xcd_tile(blockIdx.x, tiles * NQ);  // quadrants of a tile stay on one XCD
+  if (unit >= tiles * NQ) return;
+  const int tile = unit / NQ, q = unit % NQ;
+  const int tx0 = (tile % set.tiles_x) * TW + 8 * (q % QX);
+  const int ty0 = (tile / set.tiles_x) * TH + 8 * (q / QX);
+  if (tx0 >= W || ty0 >= H) return;  // quadrant wholly outside the image
+  const int tid = threadIdx.x, lane = tid;
+  constexpr int qx = 0;
+  const int lx = lane & 7, row = lane >> 3;
+  const int px = tx0 + lx, py = ty0 + row;
   const bool inside = px < W && py < H;
   const float lxf = (float)lx;
-  const uint32_t qbit = 1u << wave;
+  const uint32_t qbit = 1u;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
   const float log2_tau = set.log2_tau;
 
@@ -193,14 +203,14 @@ __global__ __launch_bounds__(TW* TH) void k_raster(const gs_splat* __restrict__ 
   for (uint32_t bs = start; bs < end; bs += St::BATCH) {
     if (__syncthreads_count(done) == St::NT) break;
     const int cnt = (int)min((uint32_t)St::BATCH, end - bs);
-    if (tid < cnt) stage_params<TW, TH>(S, tid, r_cur, g_cur, tx0, ty0, log2_tau);
+    if (tid < cnt) stage_params<8, 8>(S, tid, r_cur, g_cur, tx0, ty0, log2_tau);
     const SplatRec r_next = load_splat(splats, g_next);
     const uint32_t g_after = values[min(bs + 2 * St::BATCH + slot, lastpos)];
     __syncthreads();
-    stage_rows<TW, TH>(S, cnt, tx0, ty0);
+    stage_rows<8, 8>(S, cnt, tx0, ty0);
     __syncthreads();
     uint64_t hm[St::NCH];
-    quadrant_hits<TW, TH>(S, cnt, lane, qbit, hm);
+    quadrant_hits<8, 8>(S, cnt, lane, qbit, hm);
     // Lanes never branch apart here: a pair a lane must not blend (weight
     // below alpha_min, or the pixel already stopped) gets alpha = 0, which
     // leaves C and T bitwise unchanged; only wave-uniform branches remain
@@ -396,8 +406,8 @@ template <int TW, int TH>
 void raster_fwd(const gs_splat* splats, const uint32_t* values, const uint32_t* ranges,
                 const SetK& set, int W, int H, float* image, float* T_final, uint32_t* last,
                 uint32_t* n_blend, hipStream_t st) {
-  const int tiles = set.tiles_x * set.tiles_y;
-  hipLaunchKernelGGL((k_raster<TW, TH>), dim3(xcd_grid(tiles)), dim3(TW * TH), 0, st, splats,
+  const int units = set.tiles_x * set.tiles_y * (TW / 8) * (TH / 8);
+  hipLaunchKernelGGL((k_raster<TW, TH>), dim3(xcd_grid(units)), dim3(64), 0, st, splats,
                      values, ranges, set, W, H, image, T_final, last, n_blend);
 }
 
