@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto",
+                    help="WxH, or auto: the autotuner picks tile shape and digit width")
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--sort-mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -137,9 +138,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    tw, th = map(int, args.tile.split("x"))
     sc, cam = make_workload(args.workload)
-    R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=args.radix_bits, sort_mode=args.sort_mode))
     p = GaussianParams.from_scene(sc)
     backward = args.workload == "diff"
     H, W = cam.height, cam.width
@@ -147,6 +146,19 @@ def main():
     if backward:
         from paper_2512_08478_amd import scenes as S
         target = torch.from_numpy(S.random_target(4, H, W)).cuda()
+    tuned = None
+    if args.tile == "auto":
+        from paper_2512_08478_amd.batch import autotune_view
+        best, table = autotune_view(p, cam, backward=backward, target=target,
+                                    base_settings=dict(sort_mode=args.sort_mode))
+        tw, th, bits = best["tile_w"], best["tile_h"], best["radix_bits"]
+        tuned = [[f"{t[0]['tile_w']}x{t[0]['tile_h']}/{t[0]['radix_bits']}b",
+                  round(t[1] * 1e3, 4)] for t in table]
+    else:
+        tw, th = map(int, args.tile.split("x"))
+        bits = args.radix_bits
+    args.radix_bits = bits
+    R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=args.sort_mode))
 
     # first frame: read the instance count once to size the sort buffers
     fr = R.forward(p, cam)
@@ -251,7 +263,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_gaussians": sc.n, "width": W,
-                   "height": H, "tile": args.tile, "radix_bits": args.radix_bits,
+                   "height": H, "tile": f"{tw}x{th}", "radix_bits": args.radix_bits,
                    "visible": n_vis, "instances": inst, "key_bits": key_bits,
                    "depth_passes": passes[0], "tile_passes": passes[1]},
         "sort_gkeys_per_s": round(inst / (sort_ms * 1e-3) / 1e9, 3) if sort_ms > 0 else None,
@@ -259,6 +271,8 @@ def main():
         "stages": stages,
         "roofline": roofline,
     }
+    if tuned is not None:
+        out["autotune_ms_per_frame"] = tuned
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels)

@@ -178,3 +178,46 @@ def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
         if t < best_t:
             best_t, best = t, dict(best, sort_mode=m)
     return dict(base, **best), table
+
+
+def autotune_view(params: GaussianParams, cam, backward=False, target=None, reps=3,
+                  tiles=TILE_SHAPES, bits=RADIX_BITS, base_settings=None, log=None):
+    """Tile shape, then digit width, for one view (forward, or forward +
+    backward with an L1 loss against `target`), by the wall time of `reps`
+    frames each after one warm-up frame.  Returns (settings dict, table)."""
+    base = dict(base_settings or {})
+    table = []
+
+    def measure(over):
+        R = Renderer(dict(base, **over))
+        fr = R.forward(params, cam)
+        torch.cuda.synchronize()
+        cap = fr.capacity
+
+        def frame():
+            f = R.forward(params, cam, capacity=cap)
+            if backward:
+                R.backward(params, cam, f, l1_grad(f.image, target))
+        frame()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            frame()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        table.append((dict(over), t))
+        if log:
+            log(f"autotune {over}: {t * 1e3:.3f} ms per frame")
+        return t
+
+    best = dict(tile_w=tiles[0][0], tile_h=tiles[0][1], radix_bits=bits[0])
+    best_t = None
+    for tw, th in tiles:
+        t = measure(dict(best, tile_w=tw, tile_h=th))
+        if best_t is None or t < best_t:
+            best_t, best = t, dict(best, tile_w=tw, tile_h=th)
+    for b in bits[1:]:
+        t = measure(dict(best, radix_bits=b))
+        if t < best_t:
+            best_t, best = t, dict(best, radix_bits=b)
+    return dict(base, **best), table
