@@ -414,6 +414,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(
   const float4 r2 = reinterpret_cast<const float4*>(splats + i)[2];
   const uint32_t rl = __float_as_uint(r2.z), rh = __float_as_uint(r2.w);
   const bool visible = (rh & 0xFFFFu) >= (rl & 0xFFFFu);
+  // a culled Gaussian's gradient is zero: adding it changes nothing
+  if (accumulate && !visible) return;
   if (visible) {
     const float* G = grad2d + (size_t)i * kGrad2dStride;
     const float gmx = G[0], gmy = G[1], gqa = G[2], gqb = G[3], gqc = G[4], gop = G[5];
