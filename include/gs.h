@@ -329,6 +329,39 @@ int32_t gs_rasterize_backward_assets(
     float* d_sh, int32_t accumulate, void* workspace, size_t workspace_bytes,
     void* stream);
 
+/*
+ * gs_rasterize_backward_2d -- the compositing half of gs_rasterize_backward:
+ * for one frame made by gs_rasterize, writes grad2d[n * 12] (floats; per
+ * Gaussian the gradient of the loss with respect to its 2-D record --
+ * mean2d x, y, the whitened form qa, qb, qc, opacity, r, g, b -- then three
+ * unused words).  The array is cleared first; Gaussians that reach no
+ * pixel keep an all-zero row.  Feed the rows of several views to
+ * gs_preprocess_backward_views.
+ */
+int32_t gs_rasterize_backward_2d(const gs_splat* splats, const uint32_t* values,
+                                 const uint32_t* tile_ranges, const gs_camera* cam,
+                                 const gs_settings* set, const float* T_final,
+                                 const uint32_t* last, const float* dL_dimage, int64_t n,
+                                 float* grad2d, void* stream);
+
+/*
+ * gs_preprocess_backward_views -- the chain rule of gs_rasterize_backward
+ * (Section 3.2) for n_views views at once: cams[v] (host array) and
+ * grad2d[v] (host array of device pointers, each an n * 12 float array
+ * from gs_rasterize_backward_2d) for the same Gaussians and asset table.
+ * Per Gaussian the inputs are read once, the chain runs for every view
+ * whose row is non-zero, and the summed input gradients are written to
+ * d_means[n*3], d_log_scales[n*3], d_quats[n*4], d_opacity_logits[n],
+ * d_sh[n*K*3] (overwritten, or added to when `accumulate` is non-zero).
+ * Views are processed 8 per kernel launch.
+ */
+int32_t gs_preprocess_backward_views(
+    int32_t n_views, const gs_camera* cams, const float* const* grad2d, int32_t n_assets,
+    const gs_asset* assets, int64_t n, const float* means, const float* log_scales,
+    const float* quats, const float* opacity_logits, const float* sh, int32_t sh_degree,
+    const gs_settings* set, float* d_means, float* d_log_scales, float* d_quats,
+    float* d_opacity_logits, float* d_sh, int32_t accumulate, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

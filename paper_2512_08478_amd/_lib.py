@@ -30,8 +30,11 @@ EXPORTED = (
     "gs_version", "gs_status_string", "gs_last_hip_error", "gs_default_settings",
     "gs_workspace_size", "gs_sort_key_bits", "gs_preprocess", "gs_sort", "gs_sort_pairs",
     "gs_rasterize", "gs_rasterize_backward", "gs_trace_enable", "gs_trace_read",
-    "gs_preprocess_assets", "gs_rasterize_backward_assets",
+    "gs_preprocess_assets", "gs_rasterize_backward_assets", "gs_rasterize_backward_2d",
+    "gs_preprocess_backward_views",
 )
+BWD_VIEWS_PER_LAUNCH = 8
+GRAD2D_STRIDE = 12  # floats per Gaussian in a 2-D gradient record
 MAX_ASSETS = 64
 
 
@@ -126,6 +129,12 @@ def load():
     lib.gs_rasterize_backward_assets.restype = I32
     lib.gs_rasterize_backward_assets.argtypes = [I32, AS, I64, P, P, P, P, P, I32, CAM, SET, P, P,
                                                  P, P, P, P, P, P, P, P, P, I32, P, SZ, P]
+    lib.gs_rasterize_backward_2d.restype = I32
+    lib.gs_rasterize_backward_2d.argtypes = [P, P, P, CAM, SET, P, P, P, I64, P, P]
+    lib.gs_preprocess_backward_views.restype = I32
+    lib.gs_preprocess_backward_views.argtypes = [I32, CAM, ctypes.POINTER(ctypes.c_void_p), I32, AS,
+                                                 I64, P, P, P, P, P, I32, SET, P, P, P, P, P, I32,
+                                                 P]
     lib.gs_trace_enable.restype = I32
     lib.gs_trace_enable.argtypes = [I32]
     lib.gs_trace_read.restype = I32

@@ -3,11 +3,14 @@
 Every view renders all assets of the scene with one global depth order
 (Algorithm 1 feeds every model's Gaussians to one sort), then runs the
 hand-written backward; gradients of all views add up in one set of
-parameter-gradient buffers.  `BatchRenderer.capture()` records the whole
-batch -- every view's preprocess, sort, compositing, loss gradient and
-backward -- into one HIP graph (through torch's graph capture, on the
-library's stream), so a step is a single graph launch with no host
-synchronisation.  Instance capacities are planned beforehand from one
+parameter-gradient buffers.  Each view's compositing backward leaves a
+48-byte 2-D gradient record per Gaussian; every 8 views, one multi-view
+chain-rule pass turns those records into input gradients, reading and
+writing each Gaussian's parameter gradient once for the 8 views instead of
+once per view.  `BatchRenderer.capture()` records the whole batch -- every
+view's preprocess, sort, compositing, loss gradient and backward -- into
+one HIP graph (through torch's graph capture, on the library's stream), so
+a step is a single graph launch with no host synchronisation.  Instance capacities are planned beforehand from one
 counting pass; a view that exceeds its capacity raises its overflow flag,
 which `replay()` checks.
 
@@ -22,6 +25,7 @@ import time
 
 import torch
 
+from . import _lib as L
 from .render import GaussianParams, Renderer
 
 TILE_SHAPES = ((16, 16), (16, 8), (32, 8), (8, 8), (32, 16))
@@ -54,6 +58,9 @@ class BatchRenderer:
         self.images = None
         self.grads = tuple(torch.zeros_like(t) for t in params.tensors())
         self.flags = torch.zeros(len(self.cams), dtype=torch.int32, device=device)
+        self.chunk = L.BWD_VIEWS_PER_LAUNCH
+        self.g2d = [torch.empty((params.n, L.GRAD2D_STRIDE), dtype=torch.float32, device=device)
+                    for _ in range(min(self.chunk, len(self.cams)))]
 
     @property
     def settings(self):
@@ -73,12 +80,17 @@ class BatchRenderer:
     def _enqueue(self):
         """All views' forward + backward on the current stream; no host sync."""
         images = []
-        for v, cam in enumerate(self.cams):
-            fr = self.R.forward(self.p, cam, capacity=self.capacity[v])
-            self.flags[v:v + 1].copy_(fr.flag)
-            g = l1_grad(fr.image, self.targets[v])
-            self.R.backward(self.p, cam, fr, g, out=self.grads, accumulate=v > 0)
-            images.append(fr.image)
+        for v0 in range(0, len(self.cams), self.chunk):
+            cams = self.cams[v0:v0 + self.chunk]
+            for k, cam in enumerate(cams):
+                v = v0 + k
+                fr = self.R.forward(self.p, cam, capacity=self.capacity[v])
+                self.flags[v:v + 1].copy_(fr.flag)
+                g = l1_grad(fr.image, self.targets[v])
+                self.R.backward_2d(self.p, cam, fr, g, self.g2d[k])
+                images.append(fr.image)
+            self.R.backward_views(self.p, cams, self.g2d[:len(cams)], out=self.grads,
+                                  accumulate=v0 > 0)
         return images
 
     def run_eager(self):

@@ -550,4 +550,88 @@ int32_t gs_rasterize_backward(int64_t n, const float* means, const float* log_sc
                                       workspace_bytes, stream);
 }
 
+int32_t gs_rasterize_backward_2d(const gs_splat* splats, const uint32_t* values,
+                                 const uint32_t* tile_ranges, const gs_camera* cam,
+                                 const gs_settings* set, const float* T_final,
+                                 const uint32_t* last, const float* dL_dimage, int64_t n,
+                                 float* grad2d, void* stream) {
+  int32_t r;
+  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
+  if (n < 0 || n >= kMaxN) return GS_ERR_INVALID_ARGUMENT;
+  if ((r = check_dev(tile_ranges)) || (r = check_dev(T_final)) || (r = check_dev(last)) ||
+      (r = check_dev(dL_dimage)) || (r = check_dev(values, false)))
+    return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(grad2d)))) return r;
+  if (n == 0) return GS_OK;
+  const gs::SetK sk = make_setk(cam, set);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  gs::trace_mark(st, "bwd_clear");
+  hipError_t e = gs::launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u,
+                                     n * gs::kGrad2dStride, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "raster_bwd");
+  e = gs::launch_rasterize_backward(splats, values, tile_ranges, sk, cam->width, cam->height,
+                                    T_final, last, dL_dimage, grad2d, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
+int32_t gs_preprocess_backward_views(
+    int32_t n_views, const gs_camera* cams, const float* const* grad2d, int32_t n_assets,
+    const gs_asset* assets, int64_t n, const float* means, const float* log_scales,
+    const float* quats, const float* opacity_logits, const float* sh, int32_t sh_degree,
+    const gs_settings* set, float* d_means, float* d_log_scales, float* d_quats,
+    float* d_opacity_logits, float* d_sh, int32_t accumulate, void* stream) {
+  int32_t r;
+  if ((r = check_settings(set))) return r;
+  if (n_views < 1 || !cams || !grad2d) return GS_ERR_INVALID_ARGUMENT;
+  if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
+  if ((r = check_assets(n_assets, assets, n))) return r;
+  for (int v = 0; v < n_views; ++v) {
+    if ((r = check_camera(&cams[v], set))) return r;
+    if (n > 0 && (r = check_dev(grad2d[v]))) return r;
+  }
+  if (n > 0 && ((r = check_dev(d_means)) || (r = check_dev(d_log_scales)) ||
+                (r = check_dev(d_quats)) || (r = check_dev(d_opacity_logits)) ||
+                (r = check_dev(d_sh))))
+    return r;
+  // every camera must be valid for every asset before anything is launched
+  for (int v = 0; v < n_views; ++v)
+    for (int a = 0; a < n_assets; ++a) {
+      gs::CamK ck;
+      if ((r = make_camk(&cams[v], set, assets[a].model, &ck))) return r;
+    }
+  if (n == 0) return GS_OK;
+  const gs::SetK sk = make_setk(&cams[0], set);
+  const int K3 = (sh_degree + 1) * (sh_degree + 1) * 3;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  gs::trace_mark(st, "preprocess_bwd");
+  for (int a = 0; a < n_assets && e == hipSuccess; ++a) {
+    const int64_t o = assets[a].offset, c = assets[a].count;
+    if (c == 0) continue;
+    for (int v0 = 0; v0 < n_views && e == hipSuccess; v0 += gs::kBwdViews) {
+      gs::ViewsK vk;
+      vk.nv = n_views - v0 < gs::kBwdViews ? n_views - v0 : gs::kBwdViews;
+      for (int k = 0; k < gs::kBwdViews; ++k) {
+        if (k < vk.nv) {
+          make_camk(&cams[v0 + k], set, assets[a].model, &vk.cam[k]);
+          vk.g2d[k] = grad2d[v0 + k] + gs::kGrad2dStride * o;
+        } else {
+          vk.cam[k] = vk.cam[0];
+          vk.g2d[k] = nullptr;
+        }
+      }
+      e = gs::launch_preprocess_backward_views(
+          (int)c, means + 3 * o, log_scales + 3 * o, quats + 4 * o, opacity_logits + o,
+          sh + K3 * o, sh_degree, vk, sk, d_means + 3 * o, d_log_scales + 3 * o, d_quats + 4 * o,
+          d_opacity_logits + o, d_sh + K3 * o, (v0 > 0 || accumulate) ? 1 : 0, st);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
 }  // extern "C"

@@ -32,6 +32,15 @@ struct CamK {
   int has_model;
 };
 
+// Cameras (as seen by one asset) and 2-D gradient records of up to
+// kBwdViews views, for the multi-view preprocess backward.
+constexpr int kBwdViews = 8;
+struct ViewsK {
+  CamK cam[kBwdViews];
+  const float* g2d[kBwdViews];
+  int nv;
+};
+
 struct SetK {
   int tile_w, tile_h, tiles_x, tiles_y;
   float eps2d, tau, log2_tau, amax, t_eps;
@@ -125,6 +134,12 @@ hipError_t launch_preprocess_backward(int n, const float* means, const float* lo
                                       float* d_means, float* d_log_scales, float* d_quats,
                                       float* d_logits, float* d_sh, int accumulate,
                                       hipStream_t st);
+hipError_t launch_preprocess_backward_views(int n, const float* means, const float* log_scales,
+                                            const float* quats, const float* logits,
+                                            const float* sh, int degree, const ViewsK& views,
+                                            const SetK& set, float* d_means, float* d_log_scales,
+                                            float* d_quats, float* d_logits, float* d_sh,
+                                            int accumulate, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
 
 // Opt-in kernel tracer: when enabled, trace_mark records a HIP event on the

@@ -392,6 +392,198 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const f
   g[0] = gx; g[1] = gy; g[2] = gz;
 }
 
+// Chain rule for Gaussian i under one camera: from its 2-D gradient record
+// G = d(mean2d, qa, qb, qc, opacity, rgb) back to the raw inputs,
+// recomputing the forward quantities; the input gradients are added to
+// gp, gls, gq, glogit and gsh.
+template <int DEG>
+__device__ __forceinline__ void chain_one(
+    int i, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, const CamK& cam, const SetK& set, const float* G, float* gp,
+    float* gls, float* gq, float& glogit, float* gsh) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+    const float gmx = G[0], gmy = G[1], gqa = G[2], gqb = G[3], gqc = G[4], gop = G[5];
+  const float grgb[3] = {G[6], G[7], G[8]};
+
+  // ---- recompute the forward quantities
+  const float p0 = means[3 * i], p1 = means[3 * i + 1], p2 = means[3 * i + 2];
+  const float4 q = quats[i];
+  const float lg = logits[i];
+  float w0 = p0, w1 = p1, w2 = p2;
+  if (cam.has_model) {
+    w0 = fmaf(cam.A[0], p0, fmaf(cam.A[1], p1, fmaf(cam.A[2], p2, cam.A[3])));
+    w1 = fmaf(cam.A[4], p0, fmaf(cam.A[5], p1, fmaf(cam.A[6], p2, cam.A[7])));
+    w2 = fmaf(cam.A[8], p0, fmaf(cam.A[9], p1, fmaf(cam.A[10], p2, cam.A[11])));
+  }
+  const float tx = fmaf(cam.V[0], w0, fmaf(cam.V[1], w1, fmaf(cam.V[2], w2, cam.V[3])));
+  const float ty = fmaf(cam.V[4], w0, fmaf(cam.V[5], w1, fmaf(cam.V[6], w2, cam.V[7])));
+  const float tz = fmaf(cam.V[8], w0, fmaf(cam.V[9], w1, fmaf(cam.V[10], w2, cam.V[11])));
+  const float o = 1.f / (1.f + expf(-lg));
+  const float s[3] = {expf(log_scales[3 * i]), expf(log_scales[3 * i + 1]),
+                      expf(log_scales[3 * i + 2])};
+  const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+  const float inv = 1.f / sqrtf(qn2);
+  const float qw = q.x * inv, qx = q.y * inv, qy = q.z * inv, qz = q.w * inv;
+  float R[9];
+  R[0] = 1.f - 2.f * (qy * qy + qz * qz); R[1] = 2.f * (qx * qy - qw * qz); R[2] = 2.f * (qx * qz + qw * qy);
+  R[3] = 2.f * (qx * qy + qw * qz); R[4] = 1.f - 2.f * (qx * qx + qz * qz); R[5] = 2.f * (qy * qz - qw * qx);
+  R[6] = 2.f * (qx * qz - qw * qy); R[7] = 2.f * (qy * qz + qw * qx); R[8] = 1.f - 2.f * (qx * qx + qy * qy);
+  float P[9];  // T3 R
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      P[3 * r + c] = fmaf(cam.T3[3 * r], R[c], fmaf(cam.T3[3 * r + 1], R[3 + c], cam.T3[3 * r + 2] * R[6 + c]));
+  float N[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) N[3 * r + c] = P[3 * r + c] * s[c];
+  const float iz = 1.f / tz;
+  const float xr = tx * iz, yr = ty * iz;
+  const bool xclamp = xr < -cam.limx || xr > cam.limx;
+  const bool yclamp = yr < -cam.limy || yr > cam.limy;
+  const float xt = fminf(cam.limx, fmaxf(-cam.limx, xr));
+  const float yt = fminf(cam.limy, fmaxf(-cam.limy, yr));
+  const float j00 = cam.fx * iz, j02 = -cam.fx * xt * iz;
+  const float j11 = cam.fy * iz, j12 = -cam.fy * yt * iz;
+  float m0[3], m1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    m0[c] = fmaf(j00, N[c], j02 * N[6 + c]);
+    m1[c] = fmaf(j11, N[3 + c], j12 * N[6 + c]);
+  }
+  const float aa = fmaf(m0[0], m0[0], fmaf(m0[1], m0[1], m0[2] * m0[2]));
+  const float cc = fmaf(m1[0], m1[0], fmaf(m1[1], m1[1], m1[2] * m1[2]));
+  const float b = fmaf(m0[0], m1[0], fmaf(m0[1], m1[1], m0[2] * m1[2]));
+  const float c = cc + set.eps2d;
+  const float x0 = det2(m0[1], m0[2], m1[1], m1[2]);
+  const float x1 = det2(m0[2], m0[0], m1[2], m1[0]);
+  const float x2 = det2(m0[0], m0[1], m1[0], m1[1]);
+  const float D = fmaf(x0, x0, fmaf(x1, x1, x2 * x2)) +
+                  set.eps2d * (aa + cc) + set.eps2d * set.eps2d;
+  const float qa = c / D, qb = b / c, qc = 1.f / c;
+
+  // ---- colour: rgb = max(0, sum_k sh_k Y_k(dl) + 1/2)
+  float v0 = w0 - cam.campos[0], v1 = w1 - cam.campos[1], v2 = w2 - cam.campos[2];
+  const float vn = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+  const float ivn = 1.f / vn;
+  const float d0 = v0 * ivn, d1 = v1 * ivn, d2 = v2 * ivn;
+  float e0 = d0, e1 = d1, e2 = d2;
+  if (cam.has_model) {
+    e0 = cam.Rk[0] * d0 + cam.Rk[3] * d1 + cam.Rk[6] * d2;
+    e1 = cam.Rk[1] * d0 + cam.Rk[4] * d1 + cam.Rk[7] * d2;
+    e2 = cam.Rk[2] * d0 + cam.Rk[5] * d1 + cam.Rk[8] * d2;
+  }
+  float Y[16];
+  sh_basis<DEG>(e0, e1, e2, Y);
+  float rgb[3];
+  sh_colour<DEG>(sh, i, Y, rgb);
+  float graw[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) graw[ch] = rgb[ch] > 0.f ? grgb[ch] : 0.f;
+  float wk[16];
+  const float* shrow = sh + (size_t)i * K * 3;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    gsh[3 * k] += graw[0] * Y[k];
+    gsh[3 * k + 1] += graw[1] * Y[k];
+    gsh[3 * k + 2] += graw[2] * Y[k];
+    wk[k] = graw[0] * shrow[3 * k] + graw[1] * shrow[3 * k + 1] + graw[2] * shrow[3 * k + 2];
+  }
+  float gdl[3];
+  sh_basis_grad<DEG>(e0, e1, e2, wk, gdl);
+  float gd0 = gdl[0], gd1 = gdl[1], gd2 = gdl[2];
+  if (cam.has_model) {  // dl = Rk^T d  ->  dL/dd = Rk dL/ddl
+    gd0 = cam.Rk[0] * gdl[0] + cam.Rk[1] * gdl[1] + cam.Rk[2] * gdl[2];
+    gd1 = cam.Rk[3] * gdl[0] + cam.Rk[4] * gdl[1] + cam.Rk[5] * gdl[2];
+    gd2 = cam.Rk[6] * gdl[0] + cam.Rk[7] * gdl[1] + cam.Rk[8] * gdl[2];
+  }
+  const float dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
+  float gw[3] = {(gd0 - dd * d0) * ivn, (gd1 - dd * d1) * ivn, (gd2 - dd * d2) * ivn};
+
+  // ---- opacity
+  glogit += gop * o * (1.f - o);
+
+  // ---- (qa, qb, qc) -> S = [[a, b], [b, c]]
+  const float ga = -gqa * qa * qa;
+  const float gb = 2.f * gqa * qa * qa * qb + gqb * qc;
+  const float gc = -gqa * qa * qa * qb * qb - gqb * qb * qc - gqc * qc * qc;
+  // ---- S = M M^T + eps I
+  float gm0[3], gm1[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    gm0[k] = 2.f * ga * m0[k] + gb * m1[k];
+    gm1[k] = gb * m0[k] + 2.f * gc * m1[k];
+  }
+  // ---- M = J N  (rows m0 = j00 N0 + j02 N2, m1 = j11 N1 + j12 N2)
+  float gj00 = 0.f, gj02 = 0.f, gj11 = 0.f, gj12 = 0.f;
+  float gN[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    gj00 += gm0[k] * N[k];
+    gj02 += gm0[k] * N[6 + k];
+    gj11 += gm1[k] * N[3 + k];
+    gj12 += gm1[k] * N[6 + k];
+    gN[k] = j00 * gm0[k];
+    gN[3 + k] = j11 * gm1[k];
+    gN[6 + k] = j02 * gm0[k] + j12 * gm1[k];
+  }
+  // ---- N = P diag(s), P = T3 R
+  float gR[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float gs = gN[c] * P[c] + gN[3 + c] * P[3 + c] + gN[6 + c] * P[6 + c];
+    gls[c] += gs * s[c];
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)  // dL/dR_rc = sum_i T3_ir gP_ic, gP_ic = gN_ic s_c
+      gR[3 * r + c] = (cam.T3[r] * gN[c] + cam.T3[3 + r] * gN[3 + c] + cam.T3[6 + r] * gN[6 + c]) * s[c];
+  // ---- R(q^) -> q^
+  const float gqw = 2.f * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+  const float gqx = 2.f * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.f * qx * gR[4] - qw * gR[5] +
+                           qz * gR[6] + qw * gR[7] - 2.f * qx * gR[8]);
+  const float gqy = 2.f * (-2.f * qy * gR[0] + qx * gR[1] + qw * gR[2] + qx * gR[3] + qz * gR[5] -
+                           qw * gR[6] + qz * gR[7] - 2.f * qy * gR[8]);
+  const float gqz = 2.f * (-2.f * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.f * qz * gR[4] +
+                           qy * gR[5] + qx * gR[6] + qy * gR[7]);
+  // ---- normalisation q^ = q/|q|
+  const float qd = gqw * qw + gqx * qx + gqy * qy + gqz * qz;
+  gq[0] += (gqw - qd * qw) * inv;
+  gq[1] += (gqx - qd * qx) * inv;
+  gq[2] += (gqy - qd * qy) * inv;
+  gq[3] += (gqz - qd * qz) * inv;
+  // ---- J and mean2d -> camera-space t
+  const float iz2 = iz * iz;
+  float gtx = gmx * cam.fx * iz, gty = gmy * cam.fy * iz;
+  float gtz = -(gmx * cam.fx * tx + gmy * cam.fy * ty) * iz2;
+  gtz += -gj00 * cam.fx * iz2 - gj11 * cam.fy * iz2;
+  if (xclamp) {
+    gtz += gj02 * cam.fx * xt * iz2;
+  } else {
+    gtx += -gj02 * cam.fx * iz2;
+    gtz += 2.f * gj02 * cam.fx * tx * iz2 * iz;
+  }
+  if (yclamp) {
+    gtz += gj12 * cam.fy * yt * iz2;
+  } else {
+    gty += -gj12 * cam.fy * iz2;
+    gtz += 2.f * gj12 * cam.fy * ty * iz2 * iz;
+  }
+  // ---- t = V w + v  ->  w; w = A p + t_k  ->  p
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gw[k] += cam.V[k] * gtx + cam.V[4 + k] * gty + cam.V[8 + k] * gtz;
+  if (cam.has_model) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gp[k] += cam.A[k] * gw[0] + cam.A[4 + k] * gw[1] + cam.A[8 + k] * gw[2];
+  } else {
+    gp[0] += gw[0]; gp[1] += gw[1]; gp[2] += gw[2];
+  }
+}
+
 // Chain rule from the 2-D gradient record d(mean2d, qa, qb, qc, opacity,
 // rgb) back to the raw inputs, recomputing the forward quantities.
 template <int DEG>
@@ -417,188 +609,72 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_bwd(
   // a culled Gaussian's gradient is zero: adding it changes nothing
   if (accumulate && !visible) return;
   if (visible) {
-    const float* G = grad2d + (size_t)i * kGrad2dStride;
-    const float gmx = G[0], gmy = G[1], gqa = G[2], gqb = G[3], gqc = G[4], gop = G[5];
-    const float grgb[3] = {G[6], G[7], G[8]};
-
-    // ---- recompute the forward quantities
-    const float p0 = means[3 * i], p1 = means[3 * i + 1], p2 = means[3 * i + 2];
-    const float4 q = quats[i];
-    const float lg = logits[i];
-    float w0 = p0, w1 = p1, w2 = p2;
-    if (cam.has_model) {
-      w0 = fmaf(cam.A[0], p0, fmaf(cam.A[1], p1, fmaf(cam.A[2], p2, cam.A[3])));
-      w1 = fmaf(cam.A[4], p0, fmaf(cam.A[5], p1, fmaf(cam.A[6], p2, cam.A[7])));
-      w2 = fmaf(cam.A[8], p0, fmaf(cam.A[9], p1, fmaf(cam.A[10], p2, cam.A[11])));
-    }
-    const float tx = fmaf(cam.V[0], w0, fmaf(cam.V[1], w1, fmaf(cam.V[2], w2, cam.V[3])));
-    const float ty = fmaf(cam.V[4], w0, fmaf(cam.V[5], w1, fmaf(cam.V[6], w2, cam.V[7])));
-    const float tz = fmaf(cam.V[8], w0, fmaf(cam.V[9], w1, fmaf(cam.V[10], w2, cam.V[11])));
-    const float o = 1.f / (1.f + expf(-lg));
-    const float s[3] = {expf(log_scales[3 * i]), expf(log_scales[3 * i + 1]),
-                        expf(log_scales[3 * i + 2])};
-    const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
-    const float inv = 1.f / sqrtf(qn2);
-    const float qw = q.x * inv, qx = q.y * inv, qy = q.z * inv, qz = q.w * inv;
-    float R[9];
-    R[0] = 1.f - 2.f * (qy * qy + qz * qz); R[1] = 2.f * (qx * qy - qw * qz); R[2] = 2.f * (qx * qz + qw * qy);
-    R[3] = 2.f * (qx * qy + qw * qz); R[4] = 1.f - 2.f * (qx * qx + qz * qz); R[5] = 2.f * (qy * qz - qw * qx);
-    R[6] = 2.f * (qx * qz - qw * qy); R[7] = 2.f * (qy * qz + qw * qx); R[8] = 1.f - 2.f * (qx * qx + qy * qy);
-    float P[9];  // T3 R
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        P[3 * r + c] = fmaf(cam.T3[3 * r], R[c], fmaf(cam.T3[3 * r + 1], R[3 + c], cam.T3[3 * r + 2] * R[6 + c]));
-    float N[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) N[3 * r + c] = P[3 * r + c] * s[c];
-    const float iz = 1.f / tz;
-    const float xr = tx * iz, yr = ty * iz;
-    const bool xclamp = xr < -cam.limx || xr > cam.limx;
-    const bool yclamp = yr < -cam.limy || yr > cam.limy;
-    const float xt = fminf(cam.limx, fmaxf(-cam.limx, xr));
-    const float yt = fminf(cam.limy, fmaxf(-cam.limy, yr));
-    const float j00 = cam.fx * iz, j02 = -cam.fx * xt * iz;
-    const float j11 = cam.fy * iz, j12 = -cam.fy * yt * iz;
-    float m0[3], m1[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      m0[c] = fmaf(j00, N[c], j02 * N[6 + c]);
-      m1[c] = fmaf(j11, N[3 + c], j12 * N[6 + c]);
-    }
-    const float aa = fmaf(m0[0], m0[0], fmaf(m0[1], m0[1], m0[2] * m0[2]));
-    const float cc = fmaf(m1[0], m1[0], fmaf(m1[1], m1[1], m1[2] * m1[2]));
-    const float b = fmaf(m0[0], m1[0], fmaf(m0[1], m1[1], m0[2] * m1[2]));
-    const float c = cc + set.eps2d;
-    const float x0 = det2(m0[1], m0[2], m1[1], m1[2]);
-    const float x1 = det2(m0[2], m0[0], m1[2], m1[0]);
-    const float x2 = det2(m0[0], m0[1], m1[0], m1[1]);
-    const float D = fmaf(x0, x0, fmaf(x1, x1, x2 * x2)) +
-                    set.eps2d * (aa + cc) + set.eps2d * set.eps2d;
-    const float qa = c / D, qb = b / c, qc = 1.f / c;
-
-    // ---- colour: rgb = max(0, sum_k sh_k Y_k(dl) + 1/2)
-    float v0 = w0 - cam.campos[0], v1 = w1 - cam.campos[1], v2 = w2 - cam.campos[2];
-    const float vn = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
-    const float ivn = 1.f / vn;
-    const float d0 = v0 * ivn, d1 = v1 * ivn, d2 = v2 * ivn;
-    float e0 = d0, e1 = d1, e2 = d2;
-    if (cam.has_model) {
-      e0 = cam.Rk[0] * d0 + cam.Rk[3] * d1 + cam.Rk[6] * d2;
-      e1 = cam.Rk[1] * d0 + cam.Rk[4] * d1 + cam.Rk[7] * d2;
-      e2 = cam.Rk[2] * d0 + cam.Rk[5] * d1 + cam.Rk[8] * d2;
-    }
-    float Y[16];
-    sh_basis<DEG>(e0, e1, e2, Y);
-    float rgb[3];
-    sh_colour<DEG>(sh, i, Y, rgb);
-    float graw[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) graw[ch] = rgb[ch] > 0.f ? grgb[ch] : 0.f;
-    float wk[16];
-    const float* shrow = sh + (size_t)i * K * 3;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      gsh[3 * k] = graw[0] * Y[k];
-      gsh[3 * k + 1] = graw[1] * Y[k];
-      gsh[3 * k + 2] = graw[2] * Y[k];
-      wk[k] = graw[0] * shrow[3 * k] + graw[1] * shrow[3 * k + 1] + graw[2] * shrow[3 * k + 2];
-    }
-    float gdl[3];
-    sh_basis_grad<DEG>(e0, e1, e2, wk, gdl);
-    float gd0 = gdl[0], gd1 = gdl[1], gd2 = gdl[2];
-    if (cam.has_model) {  // dl = Rk^T d  ->  dL/dd = Rk dL/ddl
-      gd0 = cam.Rk[0] * gdl[0] + cam.Rk[1] * gdl[1] + cam.Rk[2] * gdl[2];
-      gd1 = cam.Rk[3] * gdl[0] + cam.Rk[4] * gdl[1] + cam.Rk[5] * gdl[2];
-      gd2 = cam.Rk[6] * gdl[0] + cam.Rk[7] * gdl[1] + cam.Rk[8] * gdl[2];
-    }
-    const float dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
-    float gw[3] = {(gd0 - dd * d0) * ivn, (gd1 - dd * d1) * ivn, (gd2 - dd * d2) * ivn};
-
-    // ---- opacity
-    glogit = gop * o * (1.f - o);
-
-    // ---- (qa, qb, qc) -> S = [[a, b], [b, c]]
-    const float ga = -gqa * qa * qa;
-    const float gb = 2.f * gqa * qa * qa * qb + gqb * qc;
-    const float gc = -gqa * qa * qa * qb * qb - gqb * qb * qc - gqc * qc * qc;
-    // ---- S = M M^T + eps I
-    float gm0[3], gm1[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      gm0[k] = 2.f * ga * m0[k] + gb * m1[k];
-      gm1[k] = gb * m0[k] + 2.f * gc * m1[k];
-    }
-    // ---- M = J N  (rows m0 = j00 N0 + j02 N2, m1 = j11 N1 + j12 N2)
-    float gj00 = 0.f, gj02 = 0.f, gj11 = 0.f, gj12 = 0.f;
-    float gN[9];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      gj00 += gm0[k] * N[k];
-      gj02 += gm0[k] * N[6 + k];
-      gj11 += gm1[k] * N[3 + k];
-      gj12 += gm1[k] * N[6 + k];
-      gN[k] = j00 * gm0[k];
-      gN[3 + k] = j11 * gm1[k];
-      gN[6 + k] = j02 * gm0[k] + j12 * gm1[k];
-    }
-    // ---- N = P diag(s), P = T3 R
-    float gR[9];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float gs = gN[c] * P[c] + gN[3 + c] * P[3 + c] + gN[6 + c] * P[6 + c];
-      gls[c] = gs * s[c];
-    }
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)  // dL/dR_rc = sum_i T3_ir gP_ic, gP_ic = gN_ic s_c
-        gR[3 * r + c] = (cam.T3[r] * gN[c] + cam.T3[3 + r] * gN[3 + c] + cam.T3[6 + r] * gN[6 + c]) * s[c];
-    // ---- R(q^) -> q^
-    const float gqw = 2.f * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
-    const float gqx = 2.f * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.f * qx * gR[4] - qw * gR[5] +
-                             qz * gR[6] + qw * gR[7] - 2.f * qx * gR[8]);
-    const float gqy = 2.f * (-2.f * qy * gR[0] + qx * gR[1] + qw * gR[2] + qx * gR[3] + qz * gR[5] -
-                             qw * gR[6] + qz * gR[7] - 2.f * qy * gR[8]);
-    const float gqz = 2.f * (-2.f * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.f * qz * gR[4] +
-                             qy * gR[5] + qx * gR[6] + qy * gR[7]);
-    // ---- normalisation q^ = q/|q|
-    const float qd = gqw * qw + gqx * qx + gqy * qy + gqz * qz;
-    gq[0] = (gqw - qd * qw) * inv;
-    gq[1] = (gqx - qd * qx) * inv;
-    gq[2] = (gqy - qd * qy) * inv;
-    gq[3] = (gqz - qd * qz) * inv;
-    // ---- J and mean2d -> camera-space t
-    const float iz2 = iz * iz;
-    float gtx = gmx * cam.fx * iz, gty = gmy * cam.fy * iz;
-    float gtz = -(gmx * cam.fx * tx + gmy * cam.fy * ty) * iz2;
-    gtz += -gj00 * cam.fx * iz2 - gj11 * cam.fy * iz2;
-    if (xclamp) {
-      gtz += gj02 * cam.fx * xt * iz2;
-    } else {
-      gtx += -gj02 * cam.fx * iz2;
-      gtz += 2.f * gj02 * cam.fx * tx * iz2 * iz;
-    }
-    if (yclamp) {
-      gtz += gj12 * cam.fy * yt * iz2;
-    } else {
-      gty += -gj12 * cam.fy * iz2;
-      gtz += 2.f * gj12 * cam.fy * ty * iz2 * iz;
-    }
-    // ---- t = V w + v  ->  w; w = A p + t_k  ->  p
-#pragma unroll
-    for (int k = 0; k < 3; ++k) gw[k] += cam.V[k] * gtx + cam.V[4 + k] * gty + cam.V[8 + k] * gtz;
-    if (cam.has_model) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) gp[k] = cam.A[k] * gw[0] + cam.A[4 + k] * gw[1] + cam.A[8 + k] * gw[2];
-    } else {
-      gp[0] = gw[0]; gp[1] = gw[1]; gp[2] = gw[2];
-    }
+    chain_one<DEG>(i, means, log_scales, quats, logits, sh, cam, set,
+                   grad2d + (size_t)i * kGrad2dStride, gp, gls, gq, glogit, gsh);
   }
 
+  if (accumulate) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      d_means[3 * i + k] += gp[k];
+      d_log_scales[3 * i + k] += gls[k];
+    }
+    float4 dq = d_quats[i];
+    dq.x += gq[0]; dq.y += gq[1]; dq.z += gq[2]; dq.w += gq[3];
+    d_quats[i] = dq;
+    d_logits[i] += glogit;
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) d_sh[(size_t)i * K * 3 + k] += gsh[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      d_means[3 * i + k] = gp[k];
+      d_log_scales[3 * i + k] = gls[k];
+    }
+    d_quats[i] = make_float4(gq[0], gq[1], gq[2], gq[3]);
+    d_logits[i] = glogit;
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) d_sh[(size_t)i * K * 3 + k] = gsh[k];
+  }
+}
+
+// The same chain rule for several views at once: per Gaussian the inputs
+// are read once, the chain runs for every view whose 2-D gradient record
+// is non-zero (a view that culled the Gaussian, or to whose pixels it
+// contributed nothing, has an all-zero record), and the input gradients
+// are written, or added, once.  Compared with one backward per view, the
+// 236-byte gradient of a degree-3 Gaussian is read and written once per
+// kBwdViews views instead of once per view.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_preprocess_bwd_views(
+    int n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, ViewsK views, SetK set, float* __restrict__ d_means,
+    float* __restrict__ d_log_scales, float4* __restrict__ d_quats,
+    float* __restrict__ d_logits, float* __restrict__ d_sh, int accumulate) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float gp[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
+  float glogit = 0.f;
+  float gsh[K * 3];
+#pragma unroll
+  for (int k = 0; k < K * 3; ++k) gsh[k] = 0.f;
+  bool any = false;
+  for (int v = 0; v < views.nv; ++v) {
+    const float4* row = reinterpret_cast<const float4*>(views.g2d[v] + (size_t)i * kGrad2dStride);
+    const float4 a = row[0], b = row[1];
+    const float c = row[2].x;
+    const float G[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c};
+    bool nz = false;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) nz = nz || G[k] != 0.f;
+    if (!nz) continue;
+    any = true;
+    chain_one<DEG>(i, means, log_scales, quats, logits, sh, views.cam[v], set, G, gp, gls, gq,
+                   glogit, gsh);
+  }
+  if (accumulate && !any) return;
   if (accumulate) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -680,6 +756,27 @@ hipError_t launch_preprocess_backward(int n, const float* means, const float* lo
     default: GS_PBWD(3); break;
   }
 #undef GS_PBWD
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_backward_views(int n, const float* means, const float* log_scales,
+                                            const float* quats, const float* logits,
+                                            const float* sh, int degree, const ViewsK& views,
+                                            const SetK& set, float* d_means, float* d_log_scales,
+                                            float* d_quats, float* d_logits, float* d_sh,
+                                            int accumulate, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid((n + kBlock - 1) / kBlock), block(kBlock);
+  const float4* q4 = reinterpret_cast<const float4*>(quats);
+  float4* dq4 = reinterpret_cast<float4*>(d_quats);
+#define GS_PBWDV(D) hipLaunchKernelGGL(k_preprocess_bwd_views<D>, grid, block, 0, st, n, means, log_scales, q4, logits, sh, views, set, d_means, d_log_scales, dq4, d_logits, d_sh, accumulate)
+  switch (degree) {
+    case 0: GS_PBWDV(0); break;
+    case 1: GS_PBWDV(1); break;
+    case 2: GS_PBWDV(2); break;
+    default: GS_PBWDV(3); break;
+  }
+#undef GS_PBWDV
   return hipGetLastError();
 }
 

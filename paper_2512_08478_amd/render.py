@@ -208,6 +208,39 @@ class Renderer:
         return out
 
 
+    def backward_2d(self, p: GaussianParams, cam, fr: Frame, dL_dimage, grad2d=None):
+        """The compositing backward only: per-Gaussian 2-D gradient records
+        (n, 12) float32 of this view, for backward_views."""
+        lib = L.load()
+        c, s = L.make_camera(cam), self.settings
+        n = p.n
+        if grad2d is None:
+            grad2d = torch.empty((n, L.GRAD2D_STRIDE), dtype=torch.float32, device=self.device)
+        dL = dL_dimage.to(torch.float32).contiguous()
+        st = lib.gs_rasterize_backward_2d(_p(fr.splats), _p(fr.values), _p(fr.ranges),
+                                          ctypes.byref(c), ctypes.byref(s), _p(fr.T_final),
+                                          _p(fr.last), _p(dL), n, _p(grad2d), _stream())
+        L.check(st, "gs_rasterize_backward_2d")
+        return grad2d
+
+    def backward_views(self, p: GaussianParams, cams, grad2ds, out=None, accumulate=False):
+        """Input gradients summed over views from their 2-D gradient records."""
+        lib = L.load()
+        s = self.settings
+        n = p.n
+        if out is None:
+            out = tuple(torch.zeros_like(t) for t in p.tensors())
+        cam_arr = (L.GsCamera * len(cams))(*[L.make_camera(c) for c in cams])
+        ptrs = (ctypes.c_void_p * len(grad2ds))(*[g.data_ptr() for g in grad2ds])
+        assets = p.assets if p.assets is not None else [(0, n, p.model)]
+        tab, _keep = L.asset_table(assets)
+        st = lib.gs_preprocess_backward_views(
+            len(cams), cam_arr, ptrs, len(assets), tab, n, *[_p(t) for t in p.tensors()],
+            p.sh_degree, ctypes.byref(s), *[_p(t) for t in out], int(bool(accumulate)), _stream())
+        L.check(st, "gs_preprocess_backward_views")
+        return out
+
+
 class GsRender(torch.autograd.Function):
     """image = render(params); backward through libgs's hand-written kernels."""
 

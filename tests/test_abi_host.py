@@ -196,3 +196,26 @@ def test_asset_table_validation(lib):
     assert pa([(0, 4, None), (4, 4, shear)], 8) == L.GS_ERR_INVALID_ARGUMENT
     assert ba([(0, 4, None), (5, 4, None)], 9) == L.GS_ERR_INVALID_ARGUMENT
     assert ba([(0, 4, None), (4, 4, shear)], 8) == L.GS_ERR_INVALID_ARGUMENT
+
+
+def test_multi_view_backward_validation(lib):
+    c, s = cam_1080(), L.default_settings()
+    F = ctypes.c_void_p(FAKE)
+    cams = (L.GsCamera * 2)(c, c)
+    ptrs = (ctypes.c_void_p * 2)(FAKE, FAKE)
+
+    def pv(nv=2, table=((0, 4, None),), n=4, cam_arr=cams, p=ptrs):
+        arr, keep = L.asset_table(list(table))
+        return lib.gs_preprocess_backward_views(nv, cam_arr, p, len(table), arr, n, *[F] * 5, 0,
+                                                ctypes.byref(s), *[F] * 5, 0, None)
+    assert pv(nv=0) == L.GS_ERR_INVALID_ARGUMENT
+    assert pv(table=((0, 3, None),)) == L.GS_ERR_INVALID_ARGUMENT
+    bad = (L.GsCamera * 2)(c, c)
+    bad[1].width = 0
+    assert pv(cam_arr=bad) == L.GS_ERR_INVALID_ARGUMENT
+    assert pv(p=(ctypes.c_void_p * 2)(FAKE, FAKE + 4)) == L.GS_ERR_MISALIGNED
+    r = lib.gs_rasterize_backward_2d(F, F, F, ctypes.byref(c), ctypes.byref(s), F, F, F, -1, F, None)
+    assert r == L.GS_ERR_INVALID_ARGUMENT
+    r = lib.gs_rasterize_backward_2d(F, F, F, ctypes.byref(c), ctypes.byref(s), F, F, F, 4,
+                                     ctypes.c_void_p(FAKE + 4), None)
+    assert r == L.GS_ERR_MISALIGNED

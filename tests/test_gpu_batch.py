@@ -163,3 +163,28 @@ def test_autotuned_settings_leave_images_unchanged(R):
     for a, b in zip(imgs, ref_imgs):
         assert torch.equal(a, b)
     print(f"autotune picked {best}")
+
+
+def test_multi_view_backward_matches_per_view_backward(R):
+    print_case("multi-view chain rule (10 views, two launches) vs per-view backward")
+    from paper_2512_08478_amd.batch import l1_grad
+    assets, cams = S.batched_scenes(seed=7, scale=0.004, n_views=10, max_wh=(200, 160),
+                                    min_wh=(96, 80))
+    p = concat_params(assets)
+    tg = targets_for(cams)
+    ref = tuple(torch.zeros_like(t) for t in p.tensors())
+    g2d = []
+    for v, cam in enumerate(cams):
+        fr = R.forward(p, cam, reuse=False)
+        g = l1_grad(fr.image, tg[v])
+        R.backward(p, cam, fr, g, out=ref, accumulate=v > 0)
+        g2d.append(R.backward_2d(p, cam, fr, g))
+    got = R.backward_views(p, cams, g2d)
+    for k, nm in enumerate(NAMES):
+        d = _rel_max(got[k], ref[k])
+        print(f"{nm}: max |views - per view| / max |per view| = {d:.2e}")
+        assert d <= 1e-5, (nm, d)
+    # accumulate adds onto what is there
+    again = R.backward_views(p, cams, g2d, out=tuple(t.clone() for t in got), accumulate=True)
+    for k in range(5):
+        assert _rel_max(again[k], 2 * got[k]) <= 1e-6
