@@ -343,61 +343,64 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
     stage_rows<8, 8>(S, cnt, tx0, ty0);
     __syncthreads();
     uint64_t m = ballot(lane < cnt && (S.mask[lane < cnt ? lane : 0] & 1u) != 0u);
-    while (m) {
-      const int j = 63 - __builtin_clzll(m);
-      m &= ~(1ull << j);
-      float gmx = 0.f, gmy = 0.f, gqa = 0.f, gqb = 0.f, gqc = 0.f, gop = 0.f;
-      float gr = 0.f, gg = 0.f, gb = 0.f;
-      bool contrib = false;
-      if (bs + j < mylast) {
-        const float u = S.ub[j][0][row] + lxf;
-        const float4 h = S.hdr[j];
-        const float e = fmaf(-h.x, u * u, S.rt[j][row]);
-        if (e >= log2_tau) {
-          contrib = true;
-          const float4 x = S.aux[j];  // qb, qc', my, 1 / opacity
-          const float gw = hw_exp2(e);
-          const float alpha = fminf(set.amax, gw);
-          const float om = 1.f - alpha;
-          // T before this splat; 1 - alpha >= 1 - alpha_max, far from 0
-          const float Ti = T * __builtin_amdgcn_rcpf(om);
-          const float cr = h.y, cg = h.z, cb = h.w;
-          const float w = alpha * Ti;
-          gr = dC0 * w; gg = dC1 * w; gb = dC2 * w;
-          const float dalpha = Ti * (dC0 * (cr - S0) + dC1 * (cg - S1) + dC2 * (cb - S2) -
-                                     B * bgdot + dA * B);
-          S0 = fmaf(alpha, cr - S0, S0);
-          S1 = fmaf(alpha, cg - S1, S1);
-          S2 = fmaf(alpha, cb - S2, S2);
-          B *= om;
-          T = Ti;
-          if (gw < set.amax) {
-            // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
-            // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y
-            const float dy = fy - x.z;
-            gop = dalpha * gw * x.w;
-            const float dQ = -kLn2 * gw * dalpha;  // dL/dQ'
-            const float qau = h.x * u;
-            gqa = dQ * kHalfLog2e * (u * u);
-            gqb = -2.f * dQ * qau * dy;
-            gqc = dQ * kHalfLog2e * (dy * dy);
-            gmx = -2.f * dQ * qau;
-            gmy = 2.f * dQ * (qau * x.x - x.y * dy);
-          }
-        }
-      }
-      if (ballot(contrib)) {
-        gmx = wave_sum_dpp(gmx); gmy = wave_sum_dpp(gmy);
-        gqa = wave_sum_dpp(gqa); gqb = wave_sum_dpp(gqb); gqc = wave_sum_dpp(gqc);
-        gop = wave_sum_dpp(gop);
-        gr = wave_sum_dpp(gr); gg = wave_sum_dpp(gg); gb = wave_sum_dpp(gb);
-        // lane k adds value k: one atomic instruction over 9 consecutive words
-        const float sums[9] = {gmx, gmy, gqa, gqb, gqc, gop, gr, gg, gb};
-        float v = 0.f;
+    // Lanes never branch apart: a pair a lane must not revisit (position at
+    // or past its `last`, or weight below alpha_min) gets alpha = 0, which
+    // leaves T, S and B bitwise unchanged and yields zero gradients.
+    auto visit = [&](int j, float u, float e, const float4& h) {
+      const bool take = bs + j < mylast && e >= log2_tau;
+      if (!ballot(take)) return;
+      const float4 x = S.aux[j];  // qb, qc', my, 1 / opacity
+      const float gw = take ? hw_exp2(e) : 0.f;
+      const float alpha = fminf(set.amax, gw);
+      const float om = 1.f - alpha;
+      // T before this splat; 1 - alpha >= 1 - alpha_max, far from 0
+      const float Ti = take ? T * __builtin_amdgcn_rcpf(om) : T;
+      const float cr = h.y, cg = h.z, cb = h.w;
+      const float w = alpha * Ti;
+      const float gr = dC0 * w, gg = dC1 * w, gb = dC2 * w;
+      const float dalpha = Ti * (dC0 * (cr - S0) + dC1 * (cg - S1) + dC2 * (cb - S2) -
+                                 B * bgdot + dA * B);
+      S0 = fmaf(alpha, cr - S0, S0);
+      S1 = fmaf(alpha, cg - S1, S1);
+      S2 = fmaf(alpha, cb - S2, S2);
+      B *= om;
+      T = Ti;
+      // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
+      // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y;
+      // no gradient flows through alpha where the alpha_max clamp binds
+      const float dy = fy - x.z;
+      const float dal = take && gw < set.amax ? dalpha : 0.f;
+      const float gop = dal * gw * x.w;
+      const float dQ = -kLn2 * gw * dal;  // dL/dQ'
+      const float qau = h.x * u;
+      const float gqa = dQ * kHalfLog2e * (u * u);
+      const float gqb = -2.f * dQ * qau * dy;
+      const float gqc = dQ * kHalfLog2e * (dy * dy);
+      const float gmx = -2.f * dQ * qau;
+      const float gmy = 2.f * dQ * (qau * x.x - x.y * dy);
+      const float sums[9] = {wave_sum_dpp(gmx), wave_sum_dpp(gmy), wave_sum_dpp(gqa),
+                             wave_sum_dpp(gqb), wave_sum_dpp(gqc), wave_sum_dpp(gop),
+                             wave_sum_dpp(gr),  wave_sum_dpp(gg),  wave_sum_dpp(gb)};
+      // lane k adds value k: one atomic instruction over 9 consecutive words
+      float v = 0.f;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) v = lane == k ? sums[k] : v;
-        if (lane < 9) atomicAdd(grad2d + (size_t)S.gid[j] * kGrad2dStride + lane, v);
-      }
+      for (int k = 0; k < 9; ++k) v = lane == k ? sums[k] : v;
+      if (lane < 9) atomicAdd(grad2d + (size_t)S.gid[j] * kGrad2dStride + lane, v);
+    };
+    // two splats per step, back to front: both LDS reads are in flight
+    // before the first one is visited
+    while (m) {
+      const int j0 = 63 - __builtin_clzll(m);
+      m &= ~(1ull << j0);
+      const bool two = m != 0;
+      const int j1 = two ? 63 - __builtin_clzll(m) : j0;
+      if (two) m &= ~(1ull << j1);
+      const float u0 = S.ub[j0][0][row] + lxf, u1 = S.ub[j1][0][row] + lxf;
+      const float4 h0 = S.hdr[j0], h1 = S.hdr[j1];
+      const float e0 = fmaf(-h0.x, u0 * u0, S.rt[j0][row]);
+      const float e1 = fmaf(-h1.x, u1 * u1, S.rt[j1][row]);
+      visit(j0, u0, e0, h0);
+      if (two) visit(j1, u1, e1, h1);
     }
   }
 }
