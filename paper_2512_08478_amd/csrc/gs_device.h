@@ -73,6 +73,16 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Sum of v over each row of 16 lanes, left in the row's lane 15 (DPP row
+// shifts by 1, 2, 4 and 8; lanes shifted in from outside the row read 0).
+__device__ __forceinline__ float row_sum_dpp(float v) {
+  v += dpp_f32<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_f32<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_f32<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_f32<0x118, 0xF>(v);  // row_shr:8
+  return v;
+}
+
 // Lanes of the wave whose `d` (BITS wide) equals this lane's, among `active`.
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {

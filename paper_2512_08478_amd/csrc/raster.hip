@@ -275,9 +275,10 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
 //   S_i = colour composited behind i (normalised by T_{i+1}),
 //   B_i = T_final / T_{i+1},
 // dC/dalpha_i = T_i (c_i - S_i - B_i bg) and dA/dalpha_i = T_i B_i.
-// Per splat the 9 partial derivatives are summed over the wave with DPP
-// and added to the Gaussian's 2-D gradient record by one float-atomic
-// instruction (lanes 0-8, one value each).
+// Per splat the 9 partial derivatives are summed over each row of 16 lanes
+// with DPP; the last lane of each row stores its 9 row sums to LDS, lanes
+// 0-8 each add up one value's 4 row sums and add it to the Gaussian's 2-D
+// gradient record: one float-atomic instruction per splat and quadrant.
 //
 // Each 8x8 quadrant of a TW x TH tile is its own one-wave workgroup that
 // walks the tile's whole list (skipping splats that miss the quadrant), so
@@ -297,6 +298,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
   using St = Stage<8, 8>;
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ St S;
+  __shared__ float s_red[4][12];  // per 16-lane row: its 9 gradient sums
   const int tiles = set.tiles_x * set.tiles_y;
   const int unit = xcd_tile(blockIdx.x, tiles * NQ);  // quadrants of a tile stay on one XCD
   if (unit >= tiles * NQ) return;
@@ -378,14 +380,20 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       const float gqc = dQ * kHalfLog2e * (dy * dy);
       const float gmx = -2.f * dQ * qau;
       const float gmy = 2.f * dQ * (qau * x.x - x.y * dy);
-      const float sums[9] = {wave_sum_dpp(gmx), wave_sum_dpp(gmy), wave_sum_dpp(gqa),
-                             wave_sum_dpp(gqb), wave_sum_dpp(gqc), wave_sum_dpp(gop),
-                             wave_sum_dpp(gr),  wave_sum_dpp(gg),  wave_sum_dpp(gb)};
+      const float rs[9] = {row_sum_dpp(gmx), row_sum_dpp(gmy), row_sum_dpp(gqa),
+                           row_sum_dpp(gqb), row_sum_dpp(gqc), row_sum_dpp(gop),
+                           row_sum_dpp(gr),  row_sum_dpp(gg),  row_sum_dpp(gb)};
+      if ((lane & 15) == 15) {
+        float* dst = s_red[lane >> 4];
+        *reinterpret_cast<float4*>(dst) = make_float4(rs[0], rs[1], rs[2], rs[3]);
+        *reinterpret_cast<float4*>(dst + 4) = make_float4(rs[4], rs[5], rs[6], rs[7]);
+        dst[8] = rs[8];
+      }
       // lane k adds value k: one atomic instruction over 9 consecutive words
-      float v = 0.f;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) v = lane == k ? sums[k] : v;
-      if (lane < 9) atomicAdd(grad2d + (size_t)S.gid[j] * kGrad2dStride + lane, v);
+      if (lane < 9) {
+        const float v = (s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane]);
+        atomicAdd(grad2d + (size_t)S.gid[j] * kGrad2dStride + lane, v);
+      }
     };
     // two splats per step, back to front: both LDS reads are in flight
     // before the first one is visited
