@@ -83,6 +83,16 @@ __device__ __forceinline__ float row_sum_dpp(float v) {
   return v;
 }
 
+// Sum of v over each group of 8 lanes, left in the group's last lane (7,
+// 15, ..., 63): DPP row shifts by 1, 2 and 4 accumulate the 8 lanes ending
+// at each lane, and lanes shifted in from outside a 16-lane row read 0.
+__device__ __forceinline__ float oct_sum_dpp(float v) {
+  v += dpp_f32<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_f32<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_f32<0x114, 0xF>(v);  // row_shr:4
+  return v;
+}
+
 // Lanes of the wave whose `d` (BITS wide) equals this lane's, among `active`.
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {

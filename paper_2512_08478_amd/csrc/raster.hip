@@ -275,10 +275,11 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
 //   S_i = colour composited behind i (normalised by T_{i+1}),
 //   B_i = T_final / T_{i+1},
 // dC/dalpha_i = T_i (c_i - S_i - B_i bg) and dA/dalpha_i = T_i B_i.
-// Per splat the 9 partial derivatives are summed over each row of 16 lanes
-// with DPP; the last lane of each row stores its 9 row sums to LDS, lanes
-// 0-8 each add up one value's 4 row sums and add it to the Gaussian's 2-D
-// gradient record: one float-atomic instruction per splat and quadrant.
+// Per splat the 9 partial derivatives are summed over each pixel row (8
+// lanes) with DPP; the last lane of each row stores its 9 sums to LDS,
+// lanes 0-8 each add up one value's 8 row sums and add it to the
+// Gaussian's 2-D gradient record: one float-atomic instruction per splat
+// and quadrant.
 //
 // Each 8x8 quadrant of a TW x TH tile is its own one-wave workgroup that
 // walks the tile's whole list (skipping splats that miss the quadrant), so
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
   using St = Stage<8, 8>;
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ St S;
-  __shared__ float s_red[4][12];  // per 16-lane row: its 9 gradient sums
+  __shared__ float s_red[8][12];  // per 8-lane group (pixel row): its 9 gradient sums
   const int tiles = set.tiles_x * set.tiles_y;
   const int unit = xcd_tile(blockIdx.x, tiles * NQ);  // quadrants of a tile stay on one XCD
   if (unit >= tiles * NQ) return;
@@ -380,18 +381,19 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       const float gqc = dQ * kHalfLog2e * (dy * dy);
       const float gmx = -2.f * dQ * qau;
       const float gmy = 2.f * dQ * (qau * x.x - x.y * dy);
-      const float rs[9] = {row_sum_dpp(gmx), row_sum_dpp(gmy), row_sum_dpp(gqa),
-                           row_sum_dpp(gqb), row_sum_dpp(gqc), row_sum_dpp(gop),
-                           row_sum_dpp(gr),  row_sum_dpp(gg),  row_sum_dpp(gb)};
-      if ((lane & 15) == 15) {
-        float* dst = s_red[lane >> 4];
+      const float rs[9] = {oct_sum_dpp(gmx), oct_sum_dpp(gmy), oct_sum_dpp(gqa),
+                           oct_sum_dpp(gqb), oct_sum_dpp(gqc), oct_sum_dpp(gop),
+                           oct_sum_dpp(gr),  oct_sum_dpp(gg),  oct_sum_dpp(gb)};
+      if ((lane & 7) == 7) {
+        float* dst = s_red[lane >> 3];
         *reinterpret_cast<float4*>(dst) = make_float4(rs[0], rs[1], rs[2], rs[3]);
         *reinterpret_cast<float4*>(dst + 4) = make_float4(rs[4], rs[5], rs[6], rs[7]);
         dst[8] = rs[8];
       }
       // lane k adds value k: one atomic instruction over 9 consecutive words
       if (lane < 9) {
-        const float v = (s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane]);
+        const float v = ((s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane])) +
+                        ((s_red[4][lane] + s_red[5][lane]) + (s_red[6][lane] + s_red[7][lane]));
         atomicAdd(grad2d + (size_t)S.gid[j] * kGrad2dStride + lane, v);
       }
     };
