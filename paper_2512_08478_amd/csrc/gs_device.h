@@ -1,5 +1,6 @@
-// Device helpers for wave64 (gfx950): lane queries, ballots, wave scans and
-// agent-scope atomic loads/stores for cross-workgroup look-back.
+// Device helpers for wave64 (gfx950): lane queries, ballots, wave scans,
+// DPP group sums and agent-scope atomic loads/stores for cross-workgroup
+// look-back.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,10 +24,6 @@ __device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
 }
 
-__device__ __forceinline__ float shfl_f32(float v, int src) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
-}
-
 // Inclusive scan of u32 over the 64 lanes.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   const int l = lane_id();
@@ -45,42 +42,11 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ float wave_sum_f32(float v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += shfl_f32(v, l ^ d);
-  return v;
-}
-
-// Sum of v over the 64 lanes, returned wave-uniform.  Inside each row of 16
-// lanes, DPP row shifts by 1, 2, 4 and 8 leave the row's sum in its lane 15
-// (lanes shifted in from outside the row read 0); row broadcasts then add
-// row 0's sum into row 1 and row 2's into row 3, and row 1's into rows 2-3,
-// so lane 63 ends with the total.  Register-to-register only: no LDS
-// traffic, unlike a ds_bpermute butterfly.  Every lane must be active.
+// x from another lane of the same 16-lane row by the DPP control CTRL
+// (lanes whose source is outside the row read 0).
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_f32(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
-}
-
-__device__ __forceinline__ float wave_sum_dpp(float v) {
-  v += dpp_f32<0x111, 0xF>(v);  // row_shr:1
-  v += dpp_f32<0x112, 0xF>(v);  // row_shr:2
-  v += dpp_f32<0x114, 0xF>(v);  // row_shr:4
-  v += dpp_f32<0x118, 0xF>(v);  // row_shr:8
-  v += dpp_f32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_f32<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-
-// Sum of v over each row of 16 lanes, left in the row's lane 15 (DPP row
-// shifts by 1, 2, 4 and 8; lanes shifted in from outside the row read 0).
-__device__ __forceinline__ float row_sum_dpp(float v) {
-  v += dpp_f32<0x111, 0xF>(v);  // row_shr:1
-  v += dpp_f32<0x112, 0xF>(v);  // row_shr:2
-  v += dpp_f32<0x114, 0xF>(v);  // row_shr:4
-  v += dpp_f32<0x118, 0xF>(v);  // row_shr:8
-  return v;
 }
 
 // Sum of v over each group of 8 lanes, left in the group's last lane (7,
@@ -112,12 +78,6 @@ __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_agent64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent64(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

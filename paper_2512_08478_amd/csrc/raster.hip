@@ -52,24 +52,19 @@ __device__ __forceinline__ int xcd_tile(int b, int tiles) {
 
 inline int xcd_grid(int tiles) { return ((tiles + kXcds - 1) / kXcds) * kXcds; }
 
-// LDS staging shared by the forward and backward kernels.  Row terms are
-// stored row-contiguous per splat ([splat][group][row]), so that the writes
-// (consecutive threads on consecutive rows) and a wave's reads (its 8 rows
-// of one splat) both touch consecutive words.
-template <int TW, int TH>
+// LDS staging of one batch of splats for one 8x8 quadrant, shared by the
+// forward and backward kernels.  Row terms are stored row-contiguous per
+// splat, so the writes (consecutive threads on consecutive rows) and the
+// wave's reads (its 8 rows of one splat) both touch consecutive words.
+constexpr int kBatch = 64;  // splats per batch: one per lane
 struct Stage {
-  static constexpr int NT = TW * TH;
-  static constexpr int QX = TW / 8;          // quadrant columns (= 8-column groups)
-  static constexpr int NQ = NT / 64;         // quadrants = waves
-  static constexpr int BATCH = NT < 128 ? NT : 128;
-  static constexpr int NCH = (BATCH + 63) / 64;  // 64-slot chunks per batch
-  float4 hdr[BATCH];          // qa', r, g, b
-  float4 aux[BATCH];          // qb, qc', my, 1 / opacity
-  float2 ml[BATCH];           // mx, log2(opacity)
-  float rt[BATCH][TH];        // log2(o) - qc' dy^2 per tile row
-  float ub[BATCH][QX][TH];    // dx - qb dy at column 0 of each 8-column group
-  uint32_t mask[BATCH];       // quadrants the footprint reaches
-  uint32_t gid[BATCH];        // Gaussian index
+  float4 hdr[kBatch];   // qa', r, g, b
+  float4 aux[kBatch];   // qb, qc', my, 1 / opacity
+  float2 ml[kBatch];    // mx, log2(opacity)
+  float rt[kBatch][8];  // log2(o) - qc' dy^2 per quadrant row
+  float ub[kBatch][8];  // dx - qb dy at the quadrant's first column, per row
+  uint32_t hit[kBatch]; // footprint reaches the quadrant
+  uint32_t gid[kBatch]; // Gaussian index
 };
 
 // The fields of a splat record the compositing kernels read.
@@ -88,11 +83,10 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
   return r;
 }
 
-// Phase 1 of staging: splat j's parameters, footprint mask and index.
-template <int TW, int TH>
-__device__ __forceinline__ void stage_params(Stage<TW, TH>& S, int j, const SplatRec& r,
-                                             uint32_t g, int tx0, int ty0, float log2_tau) {
-  using St = Stage<TW, TH>;
+// Phase 1 of staging: splat j's parameters, whether its footprint reaches
+// the quadrant whose top-left pixel is (qx0, qy0), and its index.
+__device__ __forceinline__ void stage_params(Stage& S, int j, const SplatRec& r, uint32_t g,
+                                             int qx0, int qy0, float log2_tau) {
   const float4 a = r.a, b = r.b;
   const float c = r.c;
   const float mx = a.x, my = a.y, qb = a.w;
@@ -105,48 +99,33 @@ __device__ __forceinline__ void stage_params(Stage<TW, TH>& S, int j, const Spla
   float rx = sqrtf(qm * (qb * qb / qc_ + 1.f / qa_));
   ry = ry * (1.f + 1e-4f) + 1e-3f;
   rx = rx * (1.f + 1e-4f) + 1e-3f;
-  uint32_t m = 0;
-#pragma unroll
-  for (int q = 0; q < St::NQ; ++q) {
-    const float x0 = tx0 + 8 * (q % St::QX) + 0.5f, y0 = ty0 + 8 * (q / St::QX) + 0.5f;
-    const bool hit = (mx + rx >= x0) && (mx - rx <= x0 + 7.f) && (my + ry >= y0) &&
-                     (my - ry <= y0 + 7.f);
-    m |= hit ? (1u << q) : 0u;
-  }
+  const float x0 = qx0 + 0.5f, y0 = qy0 + 0.5f;
+  const bool hit = (mx + rx >= x0) && (mx - rx <= x0 + 7.f) && (my + ry >= y0) &&
+                   (my - ry <= y0 + 7.f);
   S.hdr[j] = make_float4(qa_, b.z, b.w, c);
   S.aux[j] = make_float4(qb, qc_, my, 1.f / b.y);
   S.ml[j] = make_float2(mx, lo);
-  S.mask[j] = m;
+  S.hit[j] = hit ? 1u : 0u;
   S.gid[j] = g;
 }
 
 // Phase 2 of staging: the row terms of every staged splat, one (splat, row)
-// pair per thread and step.
-template <int TW, int TH>
-__device__ __forceinline__ void stage_rows(Stage<TW, TH>& S, int cnt, int tx0, int ty0) {
-  using St = Stage<TW, TH>;
-  for (int item = threadIdx.x; item < cnt * TH; item += St::NT) {
-    const int j = item / TH, r = item % TH;
+// pair per lane and step.
+__device__ __forceinline__ void stage_rows(Stage& S, int cnt, int qx0, int qy0) {
+  for (int item = threadIdx.x; item < cnt * 8; item += 64) {
+    const int j = item / 8, r = item % 8;
     const float4 x = S.aux[j];   // qb, qc', my, 1 / opacity
     const float2 ml = S.ml[j];   // mx, log2(opacity)
-    const float dy = (ty0 + r + 0.5f) - x.z;
+    const float dy = (qy0 + r + 0.5f) - x.z;
     S.rt[j][r] = fmaf(-x.y, dy * dy, ml.y);
-#pragma unroll
-    for (int q = 0; q < St::QX; ++q) S.ub[j][q][r] = fmaf(-x.x, dy, (tx0 + 8 * q + 0.5f) - ml.x);
+    S.ub[j][r] = fmaf(-x.x, dy, (qx0 + 0.5f) - ml.x);
   }
 }
 
-// The staged splats whose footprint reaches this wave's quadrant, as one
-// 64-bit mask per 64 batch slots (every lane of the wave must take part).
-template <int TW, int TH>
-__device__ __forceinline__ void quadrant_hits(const Stage<TW, TH>& S, int cnt, int lane,
-                                              uint32_t qbit,
-                                              uint64_t (&hm)[Stage<TW, TH>::NCH]) {
-#pragma unroll
-  for (int c = 0; c < Stage<TW, TH>::NCH; ++c) {
-    const int j = c * 64 + lane;
-    hm[c] = ballot(j < cnt && (S.mask[j < cnt ? j : 0] & qbit) != 0u);
-  }
+// The staged splats whose footprint reaches the quadrant, one bit each
+// (every lane of the wave must take part).
+__device__ __forceinline__ uint64_t quadrant_hits(const Stage& S, int cnt, int lane) {
+  return ballot(lane < cnt && S.hit[lane < cnt ? lane : 0] != 0u);
 }
 
 // One 64-thread workgroup (one wave) per 8x8 quadrant of a TW x TH tile:
@@ -162,9 +141,8 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
                                                float* __restrict__ T_final,
                                                uint32_t* __restrict__ last,
                                                uint32_t* __restrict__ n_blend) {
-  using St = Stage<8, 8>;
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
-  __shared__ St S;
+  __shared__ Stage S;
   const int tiles = set.tiles_x * set.tiles_y;
   const int unit = xcd_tile(blockIdx.x, tiles * NQ);  // quadrants of a tile stay on one XCD
   if (unit >= tiles * NQ) return;
@@ -172,13 +150,11 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   const int tx0 = (tile % set.tiles_x) * TW + 8 * (q % QX);
   const int ty0 = (tile / set.tiles_x) * TH + 8 * (q / QX);
   if (tx0 >= W || ty0 >= H) return;  // quadrant wholly outside the image
-  const int tid = threadIdx.x, lane = tid;
-  constexpr int qx = 0;
+  const int lane = threadIdx.x;
   const int lx = lane & 7, row = lane >> 3;
   const int px = tx0 + lx, py = ty0 + row;
   const bool inside = px < W && py < H;
   const float lxf = (float)lx;
-  const uint32_t qbit = 1u;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
   const float log2_tau = set.log2_tau;
 
@@ -187,30 +163,28 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   bool done = !inside;
   // Software pipeline over batches: while a batch composites, the records
   // of the next batch and the indices of the one after are in flight.
-  // Every thread loads (threads past the batch repeat slot tid % BATCH),
-  // and loads past the range are clamped to its last entry; the extra
-  // values are never staged.  Branch-free loads let the compiler keep them
-  // in flight across the compositing of the current batch.
-  const uint32_t slot = (uint32_t)tid & (St::BATCH - 1);
+  // Loads past the range are clamped to its last entry (their values are
+  // never staged); branch-free loads let the compiler keep them in flight
+  // across the compositing of the current batch.
   const uint32_t lastpos = end > start ? end - 1 : start;
   uint32_t g_cur = 0, g_next = 0;
   SplatRec r_cur = {};
   if (start < end) {
-    g_cur = values[min(start + slot, lastpos)];
-    g_next = values[min(start + St::BATCH + slot, lastpos)];
+    g_cur = values[min(start + lane, lastpos)];
+    g_next = values[min(start + kBatch + lane, lastpos)];
     r_cur = load_splat(splats, g_cur);
   }
-  for (uint32_t bs = start; bs < end; bs += St::BATCH) {
-    if (__syncthreads_count(done) == St::NT) break;
-    const int cnt = (int)min((uint32_t)St::BATCH, end - bs);
-    if (tid < cnt) stage_params<8, 8>(S, tid, r_cur, g_cur, tx0, ty0, log2_tau);
+  for (uint32_t bs = start; bs < end; bs += kBatch) {
+    if (!ballot(!done)) break;
+    const int cnt = (int)min((uint32_t)kBatch, end - bs);
+    __syncthreads();  // the previous batch's reads of S are done
+    if (lane < cnt) stage_params(S, lane, r_cur, g_cur, tx0, ty0, log2_tau);
     const SplatRec r_next = load_splat(splats, g_next);
-    const uint32_t g_after = values[min(bs + 2 * St::BATCH + slot, lastpos)];
+    const uint32_t g_after = values[min(bs + 2 * kBatch + lane, lastpos)];
     __syncthreads();
-    stage_rows<8, 8>(S, cnt, tx0, ty0);
+    stage_rows(S, cnt, tx0, ty0);
     __syncthreads();
-    uint64_t hm[St::NCH];
-    quadrant_hits<8, 8>(S, cnt, lane, qbit, hm);
+    uint64_t m = quadrant_hits(S, cnt, lane);
     // Lanes never branch apart here: a pair a lane must not blend (weight
     // below alpha_min, or the pixel already stopped) gets alpha = 0, which
     // leaves C and T bitwise unchanged; only wave-uniform branches remain
@@ -219,41 +193,34 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     // lies outside the image), kept as a float so that the loop needs no
     // lane-mask bookkeeping.
     float live = done ? 0.f : 1.f;
-    if (ballot(live != 0.f)) {
-#pragma unroll
-      for (int c = 0; c < St::NCH; ++c) {
-        uint64_t m = hm[c];
-        // two hit splats per step: both splats' LDS reads are issued before
-        // the first one blends, hiding one read latency per pair
-        auto blend = [&](int j, float e, const float4& h) {
-          const bool take = e >= log2_tau && live != 0.f;
-          if (!ballot(take)) return;
-          const float alpha = take ? fminf(set.amax, hw_exp2(e)) : 0.f;
-          const float w = alpha * T;
-          C0 = fmaf(w, h.y, C0);
-          C1 = fmaf(w, h.z, C1);
-          C2 = fmaf(w, h.w, C2);
-          T = T * (1.f - alpha);
-          lastc = take ? bs + j + 1 - start : lastc;
-          nb += take ? 1u : 0u;
-          live = T < set.t_eps ? 0.f : live;
-        };
-        while (m) {
-          const int j0 = c * 64 + __builtin_ctzll(m);
-          m &= m - 1;
-          const bool two = m != 0;
-          const int j1 = two ? c * 64 + __builtin_ctzll(m) : j0;
-          if (two) m &= m - 1;
-          const float u0 = S.ub[j0][qx][row] + lxf, u1 = S.ub[j1][qx][row] + lxf;
-          const float4 h0 = S.hdr[j0], h1 = S.hdr[j1];
-          const float e0 = fmaf(-h0.x, u0 * u0, S.rt[j0][row]);
-          const float e1 = fmaf(-h1.x, u1 * u1, S.rt[j1][row]);
-          blend(j0, e0, h0);
-          if (two) blend(j1, e1, h1);
-          if (!ballot(live != 0.f)) break;
-        }
-        if (!ballot(live != 0.f)) break;
-      }
+    // two hit splats per step: both splats' LDS reads are issued before
+    // the first one blends, hiding one read latency per pair
+    auto blend = [&](int j, float e, const float4& h) {
+      const bool take = e >= log2_tau && live != 0.f;
+      if (!ballot(take)) return;
+      const float alpha = take ? fminf(set.amax, hw_exp2(e)) : 0.f;
+      const float w = alpha * T;
+      C0 = fmaf(w, h.y, C0);
+      C1 = fmaf(w, h.z, C1);
+      C2 = fmaf(w, h.w, C2);
+      T = T * (1.f - alpha);
+      lastc = take ? bs + j + 1 - start : lastc;
+      nb += take ? 1u : 0u;
+      live = T < set.t_eps ? 0.f : live;
+    };
+    while (m) {
+      const int j0 = __builtin_ctzll(m);
+      m &= m - 1;
+      const bool two = m != 0;
+      const int j1 = two ? __builtin_ctzll(m) : j0;
+      if (two) m &= m - 1;
+      const float u0 = S.ub[j0][row] + lxf, u1 = S.ub[j1][row] + lxf;
+      const float4 h0 = S.hdr[j0], h1 = S.hdr[j1];
+      const float e0 = fmaf(-h0.x, u0 * u0, S.rt[j0][row]);
+      const float e1 = fmaf(-h1.x, u1 * u1, S.rt[j1][row]);
+      blend(j0, e0, h0);
+      if (two) blend(j1, e1, h1);
+      if (!ballot(live != 0.f)) break;
     }
     done = live == 0.f;
     g_cur = g_next;
@@ -296,9 +263,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
                                                    const uint32_t* __restrict__ last,
                                                    const float* __restrict__ dL_dimage,
                                                    float* __restrict__ grad2d) {
-  using St = Stage<8, 8>;
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
-  __shared__ St S;
+  __shared__ Stage S;
   __shared__ float s_red[8][12];  // per 8-lane group (pixel row): its 9 gradient sums
   const int tiles = set.tiles_x * set.tiles_y;
   const int unit = xcd_tile(blockIdx.x, tiles * NQ);  // quadrants of a tile stay on one XCD
@@ -333,19 +299,19 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
   float S0 = 0.f, S1 = 0.f, S2 = 0.f, B = 1.f;
 
   // batches cover positions [0, nlast) of the tile's range, last batch first
-  const int nb = (int)((nlast + St::BATCH - 1) / St::BATCH);
+  const int nb = (int)((nlast + kBatch - 1) / kBatch);
   for (int bi = nb - 1; bi >= 0; --bi) {
-    const uint32_t bs = (uint32_t)bi * St::BATCH;
+    const uint32_t bs = (uint32_t)bi * kBatch;
     __syncthreads();
-    const int cnt = (int)min((uint32_t)St::BATCH, nlast - bs);
+    const int cnt = (int)min((uint32_t)kBatch, nlast - bs);
     if (lane < cnt) {
       const uint32_t g = values[start + bs + lane];
-      stage_params<8, 8>(S, lane, load_splat(splats, g), g, tx0, ty0, log2_tau);
+      stage_params(S, lane, load_splat(splats, g), g, tx0, ty0, log2_tau);
     }
     __syncthreads();
-    stage_rows<8, 8>(S, cnt, tx0, ty0);
+    stage_rows(S, cnt, tx0, ty0);
     __syncthreads();
-    uint64_t m = ballot(lane < cnt && (S.mask[lane < cnt ? lane : 0] & 1u) != 0u);
+    uint64_t m = quadrant_hits(S, cnt, lane);
     // Lanes never branch apart: a pair a lane must not revisit (position at
     // or past its `last`, or weight below alpha_min) gets alpha = 0, which
     // leaves T, S and B bitwise unchanged and yields zero gradients.
@@ -405,7 +371,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       const bool two = m != 0;
       const int j1 = two ? 63 - __builtin_clzll(m) : j0;
       if (two) m &= ~(1ull << j1);
-      const float u0 = S.ub[j0][0][row] + lxf, u1 = S.ub[j1][0][row] + lxf;
+      const float u0 = S.ub[j0][row] + lxf, u1 = S.ub[j1][row] + lxf;
       const float4 h0 = S.hdr[j0], h1 = S.hdr[j1];
       const float e0 = fmaf(-h0.x, u0 * u0, S.rt[j0][row]);
       const float e1 = fmaf(-h1.x, u1 * u1, S.rt[j1][row]);
