@@ -98,8 +98,10 @@ typedef struct gs_settings {
  *     Q(dx, dy) = (dx, dy) S^-1 (dx, dy)^T = qa * (dx - qb*dy)^2 + qc * dy^2
  * with S = [[a, b], [b, c]], qa = c/det S, qb = b/c, qc = 1/c.  Both terms
  * are non-negative, so Q is evaluated without cancellation.
- * Tile rect [tx0..tx1] x [ty0..ty1] is inclusive; a culled Gaussian has
- * tx1 < tx0 and touches no tile.
+ * Pixel bbox [px0..px1] x [py0..py1] is inclusive: the pixels whose
+ * centres the opacity-aware footprint (o exp(-Q/2) >= alpha_min) can reach,
+ * rounded outwards; a culled Gaussian has px1 < px0 and reaches no pixel.
+ * Its tiles are the tiles this bbox overlaps (gs_preprocess's tile_rects).
  */
 typedef struct gs_splat {
   float mean_x, mean_y;
@@ -107,7 +109,7 @@ typedef struct gs_splat {
   float qc, opacity;
   float r, g, b;
   float depth;
-  uint16_t tx0, ty0, tx1, ty1;
+  uint16_t px0, py0, px1, py1;
 } gs_splat;
 
 /* Workspace stages for gs_workspace_size. */

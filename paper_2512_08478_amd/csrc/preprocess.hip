@@ -93,7 +93,7 @@ __device__ __forceinline__ uint32_t project_one(
     int i, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float4* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, const CamK& cam, const SetK& set, float4& r0, float4& r1,
-    float4& r2, float* dir) {
+    float4& r2, uint2& trect, float* dir) {
   const float p0 = means[3 * i], p1 = means[3 * i + 1], p2 = means[3 * i + 2];
   const float4 q = quats[i];
   const float lg = logits[i];
@@ -117,7 +117,9 @@ __device__ __forceinline__ uint32_t project_one(
   r1 = r0;
   r2 = r0;
   uint32_t tiles = 0;
-  uint32_t rect_lo = 0x0000FFFFu, rect_hi = 0u;  // tx0=0xFFFF ty0=0 | tx1=0 ty1=0: empty
+  // empty rects: x0 = 0xFFFF, y0 = 0 | x1 = 0, y1 = 0
+  uint32_t rect_lo = 0x0000FFFFu, rect_hi = 0u;  // pixel bbox
+  trect = make_uint2(0x0000FFFFu, 0u);            // tile rect
 
   bool ok = (tz > cam.znear) && (o >= set.tau) && (qn2 > 0.f) &&
             __builtin_isfinite(tx) && __builtin_isfinite(ty) && __builtin_isfinite(qn2);
@@ -186,8 +188,10 @@ __device__ __forceinline__ uint32_t project_one(
         const int tx0 = px0 / set.tile_w, tx1 = px1 / set.tile_w;
         const int ty0 = py0 / set.tile_h, ty1 = py1 / set.tile_h;
         tiles = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-        rect_lo = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
-        rect_hi = (uint32_t)tx1 | ((uint32_t)ty1 << 16);
+        rect_lo = (uint32_t)px0 | ((uint32_t)py0 << 16);
+        rect_hi = (uint32_t)px1 | ((uint32_t)py1 << 16);
+        trect = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16),
+                           (uint32_t)tx1 | ((uint32_t)ty1 << 16));
         // view direction for the colour, in the asset's frame
         float d0 = w0 - cam.campos[0], d1 = w1 - cam.campos[1], d2 = w2 - cam.campos[2];
         const float dn = 1.f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
@@ -248,12 +252,13 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   uint32_t tiles = 0;
   float4 r0, r1, r2;
+  uint2 trect;
   float dir[3] = {0.f, 0.f, 0.f};
   if (i < n) {
     tiles = project_one<DEG, STAGED>(i, means, log_scales, quats, logits, sh, cam, set, r0, r1,
-                                     r2, dir);
+                                     r2, trect, dir);
     depth_keys[i] = tiles ? __float_as_uint(r2.y) : 0xFFFFFFFFu;
-    rects[i] = make_uint2(__float_as_uint(r2.z), __float_as_uint(r2.w));
+    rects[i] = trect;
   }
   if constexpr (STAGED) {
     const uint64_t need = ballot(tiles > 0);

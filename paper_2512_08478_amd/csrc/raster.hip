@@ -65,6 +65,7 @@ struct Stage {
   float ub[kBatch][8];  // dx - qb dy at the quadrant's first column, per row
   uint32_t hit[kBatch]; // footprint reaches the quadrant
   uint32_t gid[kBatch]; // Gaussian index
+  uint32_t list[kBatch];  // batch slots of the splats that reach the quadrant
 };
 
 // The fields of a splat record the compositing kernels read.
@@ -72,6 +73,7 @@ struct SplatRec {
   float4 a;  // mx, my, qa, qb
   float4 b;  // qc, opacity, r, g
   float c;   // b
+  uint32_t lo, hi;  // pixel bbox: px0 | py0 << 16, px1 | py1 << 16
 };
 
 __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ splats, uint32_t g) {
@@ -79,29 +81,27 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
   SplatRec r;
   r.a = rec[0];
   r.b = rec[1];
-  r.c = rec[2].x;
+  const float4 t = rec[2];
+  r.c = t.x;
+  r.lo = __float_as_uint(t.z);
+  r.hi = __float_as_uint(t.w);
   return r;
 }
 
 // Phase 1 of staging: splat j's parameters, whether its footprint reaches
-// the quadrant whose top-left pixel is (qx0, qy0), and its index.
+// the quadrant whose top-left pixel is (qx0, qy0), and its index.  The
+// reach test uses the record's pixel bbox, which preprocess rounded
+// outwards from the opacity-aware footprint.
 __device__ __forceinline__ void stage_params(Stage& S, int j, const SplatRec& r, uint32_t g,
-                                             int qx0, int qy0, float log2_tau) {
+                                             int qx0, int qy0) {
   const float4 a = r.a, b = r.b;
   const float c = r.c;
   const float mx = a.x, my = a.y, qb = a.w;
   const float qa_ = a.z * kHalfLog2e, qc_ = b.x * kHalfLog2e;
   const float lo = log2f(b.y);
-  // footprint e >= log2(alpha_min) <=> Q' <= qm; its extents are
-  // |dy| <= sqrt(qm / qc') and |dx| <= sqrt(qm (qb^2 / qc' + 1 / qa')).
-  const float qm = fmaxf(lo - log2_tau, 0.f);
-  float ry = sqrtf(qm / qc_);
-  float rx = sqrtf(qm * (qb * qb / qc_ + 1.f / qa_));
-  ry = ry * (1.f + 1e-4f) + 1e-3f;
-  rx = rx * (1.f + 1e-4f) + 1e-3f;
-  const float x0 = qx0 + 0.5f, y0 = qy0 + 0.5f;
-  const bool hit = (mx + rx >= x0) && (mx - rx <= x0 + 7.f) && (my + ry >= y0) &&
-                   (my - ry <= y0 + 7.f);
+  const int px0 = (int)(r.lo & 0xFFFFu), py0 = (int)(r.lo >> 16);
+  const int px1 = (int)(r.hi & 0xFFFFu), py1 = (int)(r.hi >> 16);
+  const bool hit = px0 <= qx0 + 7 && px1 >= qx0 && py0 <= qy0 + 7 && py1 >= qy0;
   S.hdr[j] = make_float4(qa_, b.z, b.w, c);
   S.aux[j] = make_float4(qb, qc_, my, 1.f / b.y);
   S.ml[j] = make_float2(mx, lo);
@@ -109,23 +109,24 @@ __device__ __forceinline__ void stage_params(Stage& S, int j, const SplatRec& r,
   S.gid[j] = g;
 }
 
-// Phase 2 of staging: the row terms of every staged splat, one (splat, row)
-// pair per lane and step.
-__device__ __forceinline__ void stage_rows(Stage& S, int cnt, int qx0, int qy0) {
-  for (int item = threadIdx.x; item < cnt * 8; item += 64) {
-    const int j = item / 8, r = item % 8;
+// Phase 2 of staging: the row terms of the staged splats that reach the
+// quadrant (hits: their batch-slot mask), one (splat, row) pair per lane
+// and step.  Returns the mask.
+__device__ __forceinline__ uint64_t stage_rows(Stage& S, int cnt, int qx0, int qy0, int lane) {
+  const uint64_t hits = ballot(lane < cnt && S.hit[lane < cnt ? lane : 0] != 0u);
+  if ((hits >> lane) & 1ull)
+    S.list[__builtin_popcountll(hits & ((1ull << lane) - 1ull))] = (uint32_t)lane;
+  __syncthreads();
+  const int nh = __builtin_popcountll(hits);
+  for (int item = lane; item < nh * 8; item += 64) {
+    const int j = (int)S.list[item / 8], r = item % 8;
     const float4 x = S.aux[j];   // qb, qc', my, 1 / opacity
     const float2 ml = S.ml[j];   // mx, log2(opacity)
     const float dy = (qy0 + r + 0.5f) - x.z;
     S.rt[j][r] = fmaf(-x.y, dy * dy, ml.y);
     S.ub[j][r] = fmaf(-x.x, dy, (qx0 + 0.5f) - ml.x);
   }
-}
-
-// The staged splats whose footprint reaches the quadrant, one bit each
-// (every lane of the wave must take part).
-__device__ __forceinline__ uint64_t quadrant_hits(const Stage& S, int cnt, int lane) {
-  return ballot(lane < cnt && S.hit[lane < cnt ? lane : 0] != 0u);
+  return hits;
 }
 
 // One 64-thread workgroup (one wave) per 8x8 quadrant of a TW x TH tile:
@@ -178,13 +179,12 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     if (!ballot(!done)) break;
     const int cnt = (int)min((uint32_t)kBatch, end - bs);
     __syncthreads();  // the previous batch's reads of S are done
-    if (lane < cnt) stage_params(S, lane, r_cur, g_cur, tx0, ty0, log2_tau);
+    if (lane < cnt) stage_params(S, lane, r_cur, g_cur, tx0, ty0);
     const SplatRec r_next = load_splat(splats, g_next);
     const uint32_t g_after = values[min(bs + 2 * kBatch + lane, lastpos)];
     __syncthreads();
-    stage_rows(S, cnt, tx0, ty0);
+    uint64_t m = stage_rows(S, cnt, tx0, ty0, lane);
     __syncthreads();
-    uint64_t m = quadrant_hits(S, cnt, lane);
     // Lanes never branch apart here: a pair a lane must not blend (weight
     // below alpha_min, or the pixel already stopped) gets alpha = 0, which
     // leaves C and T bitwise unchanged; only wave-uniform branches remain
@@ -306,12 +306,11 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
     const int cnt = (int)min((uint32_t)kBatch, nlast - bs);
     if (lane < cnt) {
       const uint32_t g = values[start + bs + lane];
-      stage_params(S, lane, load_splat(splats, g), g, tx0, ty0, log2_tau);
+      stage_params(S, lane, load_splat(splats, g), g, tx0, ty0);
     }
     __syncthreads();
-    stage_rows(S, cnt, tx0, ty0);
+    uint64_t m = stage_rows(S, cnt, tx0, ty0, lane);
     __syncthreads();
-    uint64_t m = quadrant_hits(S, cnt, lane);
     // Lanes never branch apart: a pair a lane must not revisit (position at
     // or past its `last`, or weight below alpha_min) gets alpha = 0, which
     // leaves T, S and B bitwise unchanged and yields zero gradients.

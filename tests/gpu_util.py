@@ -5,12 +5,26 @@ import torch
 
 SPLAT_DTYPE = np.dtype([("mx", "<f4"), ("my", "<f4"), ("qa", "<f4"), ("qb", "<f4"), ("qc", "<f4"),
                         ("op", "<f4"), ("r", "<f4"), ("g", "<f4"), ("b", "<f4"), ("depth", "<f4"),
-                        ("tx0", "<u2"), ("ty0", "<u2"), ("tx1", "<u2"), ("ty1", "<u2")])
+                        ("px0", "<u2"), ("py0", "<u2"), ("px1", "<u2"), ("py1", "<u2")])
 assert SPLAT_DTYPE.itemsize == 48
+_TILED = np.dtype(SPLAT_DTYPE.descr + [("tx0", "<i8"), ("ty0", "<i8"), ("tx1", "<i8"), ("ty1", "<i8")])
 
 
-def splats_np(splats_u8, n):
-    return splats_u8[: n * 48].cpu().numpy().view(SPLAT_DTYPE)
+def splats_np(splats_u8, n, tile=(16, 16)):
+    """The records as a structured array, plus the tile rect (tx0, ty0,
+    tx1, ty1) of each record's pixel bbox for tiles of `tile` pixels
+    (culled records keep an empty rect, tx1 < tx0)."""
+    raw = splats_u8[: n * 48].cpu().numpy().view(SPLAT_DTYPE)
+    out = np.zeros(raw.shape, _TILED)
+    for f in SPLAT_DTYPE.names:
+        out[f] = raw[f]
+    vis = raw["px1"] >= raw["px0"]
+    tw, th = tile
+    out["tx0"] = np.where(vis, raw["px0"] // tw, 1)
+    out["tx1"] = np.where(vis, raw["px1"] // tw, 0)
+    out["ty0"] = np.where(vis, raw["py0"] // th, 0)
+    out["ty1"] = np.where(vis, raw["py1"] // th, 0)
+    return out
 
 
 def conic_from_whitened(rec):

@@ -50,9 +50,11 @@ def compare_records(orc, rec, ref, cam):
     ref_con = d[:, orc.D_CA:orc.D_CC + 1]
     scale = np.abs(ref_con).max(1, keepdims=True)
     np.testing.assert_allclose(con / scale, ref_con / scale, atol=2e-5)
-    # tile rects: the GPU's may only be larger, by tiles that hold no pixel
-    # with weight >= alpha_min
+    # pixel bboxes and tile rects: the GPU's may only be larger, by pixels
+    # and tiles that hold no pixel with weight >= alpha_min
     it = ref.i[v]
+    assert np.all(r["px0"] <= it[:, orc.I_PX0]) and np.all(r["px1"] >= it[:, orc.I_PX1])
+    assert np.all(r["py0"] <= it[:, orc.I_PY0]) and np.all(r["py1"] >= it[:, orc.I_PY1])
     assert np.all(r["tx0"] <= it[:, orc.I_TX0]) and np.all(r["tx1"] >= it[:, orc.I_TX1])
     assert np.all(r["ty0"] <= it[:, orc.I_TY0]) and np.all(r["ty1"] >= it[:, orc.I_TY1])
     return v
@@ -87,6 +89,12 @@ def test_preprocess_tiny(R, orc):
     cnt = np.where(vis, (rec["tx1"].astype(np.int64) - rec["tx0"] + 1) * (rec["ty1"].astype(np.int64) - rec["ty0"] + 1), 0)
     c = u32(counts)
     assert int(c[0]) == cnt.sum() and int(c[1]) == vis.sum()
+    # the compact tile rects match the records' pixel bboxes
+    tr = u32(rects).reshape(-1, 2)[vis]
+    np.testing.assert_array_equal(tr[:, 0] & 0xFFFF, rec["tx0"][vis])
+    np.testing.assert_array_equal(tr[:, 0] >> 16, rec["ty0"][vis])
+    np.testing.assert_array_equal(tr[:, 1] & 0xFFFF, rec["tx1"][vis])
+    np.testing.assert_array_equal(tr[:, 1] >> 16, rec["ty1"][vis])
     # depth sort keys: float32 depth bits, the largest key when culled
     expect = np.where(vis, rec["depth"].view(np.uint32), np.uint32(0xFFFFFFFF))
     np.testing.assert_array_equal(u32(dkeys), expect)
