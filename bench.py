@@ -38,6 +38,9 @@ WORKLOADS = {
     "medium": "medium: 1,000,000 Gaussians (64 clusters in [-5,5]^3), SH degree 3, 1920x1080, forward",
     "large": "large: 6,000,000 Gaussians (64 clusters in [-20,20]^3), SH degree 3, 1920x1080 eye inside, forward",
     "diff": "diff: 500,000 Gaussians, SH degree 3, 800x800, forward+backward (L1)",
+    "sort32": "sort32: depth-only global sort of the 32-bit depth keys (culled = largest key) of "
+              "the 6M-generator scene at 0.758/1.515/3.031/6.062 M Gaussians, 1920x1080 camera "
+              "inside the cloud",
     "batched": "batched: 2M-Gaussian scene + 8 placed assets (50k-1M, 4.5M total), SH degree 3, "
                "32 views 512..1920 x 512..1080, forward+backward (L1), one graph launch, "
                "autotuned tile shape / digit width / sort mode",
@@ -132,6 +135,8 @@ def main():
 
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "sort32":
+        return run_sort32(args)
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib * 2**20 // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -276,6 +281,82 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels)
+    print(json.dumps(out), flush=True)
+
+
+# the paper's Table 1 "Sort" column (RTX 4090, WebGPU; context, not a target)
+PAPER_SORT_MS = {758_000: 0.20, 1_515_000: 0.22, 3_031_000: 0.32, 6_062_000: 0.58}
+
+
+def run_sort32(args):
+    """Depth-only 32-bit key sort (the sort the paper times in Table 1) over
+    the Table-1-shaped sweep of Gaussian counts."""
+    import ctypes
+    import torch
+    from paper_2512_08478_amd import _lib as L
+    from paper_2512_08478_amd import scenes as S
+    from paper_2512_08478_amd.render import GaussianParams, Renderer
+
+    sc, cam = S.large_scene(n=max(PAPER_SORT_MS))
+    R = Renderer(dict(radix_bits=args.radix_bits, sort_mode=args.sort_mode))
+    p = GaussianParams.from_scene(sc)
+    _, dkeys, _, _ = R.preprocess(p, cam, reuse=False)
+    torch.cuda.synchronize()
+    rows, ms_at_max = [], None
+    for n in sorted(PAPER_SORT_MS):
+        keys = dkeys[:n]  # the generator's draws are i.i.d., so a prefix is a random subset
+        for _ in range(args.warmup):
+            R.sort_pairs32(keys)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            R.sort_pairs32(keys)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        rows.append({"n": n, "ms": round(ms, 4), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
+                     "paper_ms_rtx4090": PAPER_SORT_MS[n]})
+        ms_at_max = ms
+    n = max(PAPER_SORT_MS)
+    # per-kernel times at the largest size (HIP events on the library's stream)
+    L.trace_enable(True)
+    R.sort_pairs32(dkeys[:n])
+    tr = L.trace_read(4096)
+    L.trace_enable(False)
+    pass_ms = [ms for lab, ms in tr if lab == "sort32_pass"]
+    passes = len(pass_ms)
+    # algorithmic bytes of one pass: key + value read and written per key
+    gbs = 16 * n / (sum(pass_ms) / passes * 1e-3) / 1e9 if passes else 0.0
+    out = {
+        "metric": METRIC,
+        "value": round(n / (ms_at_max * 1e-3) / 1e9, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_at_max, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["sort32"], "n_keys": n, "radix_bits": args.radix_bits,
+                   "passes": passes},
+        "sweep": rows,
+        "roofline": {"kernel": "sort32_pass", "bound": "hbm", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algo_bytes_per_launch": 16 * n,
+                     "ms_per_launch": round(sum(pass_ms) / passes, 5) if passes else None},
+    }
+    if not args.no_cpu_baseline:
+        import numpy as np
+        import oracle
+        k = dkeys[:n].cpu().numpy().view(np.uint32).astype(np.uint64)
+        t0 = time.perf_counter()
+        oracle.stable_sort_pairs(k, np.arange(n, dtype=np.uint32))
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(n / t / 1e9, 4), "unit": "Gkeys/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"std::stable_sort of the same {n} keys ({t:.2f} s)"}
     print(json.dumps(out), flush=True)
 
 

@@ -273,6 +273,21 @@ int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in,
                       size_t workspace_bytes, void* stream);
 
 /*
+ * gs_sort_pairs32 -- the same sort for 32-bit keys, e.g. the depth-only
+ * global sort of Algorithm 1 (Section 3.4 sorts splats by depth alone):
+ * sorts n (key u32, value u32) pairs by the low `key_bits` bits of the key
+ * (1..32; higher bits must be zero), stably.  values_in may be NULL, which
+ * stands for values 0..n-1 (the result is then the sorting permutation);
+ * keys_out may be NULL when only the values are wanted.  keys_in and
+ * values_in are not modified; outputs are distinct buffers.
+ * Workspace: gs_workspace_size(GS_STAGE_SORT_PAIRS, 0, n, NULL, set).
+ */
+int32_t gs_sort_pairs32(int64_t n, const uint32_t* keys_in, const uint32_t* values_in,
+                        int32_t key_bits, uint32_t* keys_out, uint32_t* values_out,
+                        const gs_settings* set, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/*
  * gs_rasterize -- Eqs. 2-3 per pixel.  For each tile, its splats are
  * visited in sorted (depth, index) order; per pixel
  *   alpha = min(alpha_max, opacity * exp(-Q/2)); skip if alpha < alpha_min;

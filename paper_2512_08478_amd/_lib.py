@@ -31,7 +31,7 @@ EXPORTED = (
     "gs_workspace_size", "gs_sort_key_bits", "gs_preprocess", "gs_sort", "gs_sort_pairs",
     "gs_rasterize", "gs_rasterize_backward", "gs_trace_enable", "gs_trace_read",
     "gs_preprocess_assets", "gs_rasterize_backward_assets", "gs_rasterize_backward_2d",
-    "gs_preprocess_backward_views",
+    "gs_preprocess_backward_views", "gs_sort_pairs32",
 )
 BWD_VIEWS_PER_LAUNCH = 8
 GRAD2D_STRIDE = 12  # floats per Gaussian in a 2-D gradient record
@@ -117,6 +117,8 @@ def load():
     lib.gs_sort.argtypes = [I64, P, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ, P]
     lib.gs_sort_pairs.restype = I32
     lib.gs_sort_pairs.argtypes = [I64, P, P, I32, P, P, SET, P, SZ, P]
+    lib.gs_sort_pairs32.restype = I32
+    lib.gs_sort_pairs32.argtypes = [I64, P, P, I32, P, P, SET, P, SZ, P]
     lib.gs_rasterize.restype = I32
     lib.gs_rasterize.argtypes = [P, P, P, CAM, SET, P, P, P, P, P]
     lib.gs_rasterize_backward.restype = I32

@@ -460,6 +460,55 @@ int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in, const uint32_t* values
   return GS_OK;
 }
 
+int32_t gs_sort_pairs32(int64_t n, const uint32_t* keys_in, const uint32_t* values_in,
+                        int32_t key_bits, uint32_t* keys_out, uint32_t* values_out,
+                        const gs_settings* set, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+  int32_t r;
+  if ((r = check_settings(set))) return r;
+  if (n < 0 || n > kMaxInstances || key_bits < 1 || key_bits > 32) return GS_ERR_INVALID_ARGUMENT;
+  if (n > 0) {
+    if ((r = check_dev(keys_in)) || (r = check_dev(values_in, false)) ||
+        (r = check_dev(keys_out, false)) || (r = check_dev(values_out)))
+      return r;
+    if ((const void*)keys_in == (const void*)keys_out ||
+        (values_in && (const void*)values_in == (const void*)values_out))
+      return GS_ERR_INVALID_ARGUMENT;
+  }
+  const gs::SortLayout L = gs::pairs_layout(n);
+  if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
+  if (n == 0) return GS_OK;
+  const int bits = set->radix_bits;
+  const int passes = (key_bits + bits - 1) / bits;
+  char* ws = static_cast<char*>(workspace);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
+  gs::trace_mark(st, "sort_init");
+  hipError_t e = gs::launch_sort_init(L, ws, set->sort_mode, nullptr, 0, nullptr, nullptr, n, st);
+  if (e != hipSuccess) return hip_fail(e);
+  // a last pass without keys_out writes no keys: the other buffer of the
+  // ping-pong pair stands in for keys_out
+  uint32_t* kalt = U(L.dk[0]);
+  uint32_t* kout = keys_out ? keys_out : U(L.dk[0]) + (size_t)n;
+  gs::RadixArgs<uint32_t> a{};
+  a.mode = set->sort_mode;
+  a.n_grid = n;
+  a.count = nullptr;
+  a.kin = keys_in;
+  a.vin = values_in;
+  a.k_alt = kalt;
+  a.v_alt = U(L.dv[0]);
+  a.k_out = kout;
+  a.v_out = values_out;
+  a.table = U(L.table); a.totals = U(L.totals);
+  a.hist = U(L.hist); a.tickets = U(L.tickets); a.lookback = U(L.lookback); a.lb_parts = L.parts;
+  e = gs::launch_radix_sort<uint32_t>(a, bits, passes, 0, keys_out != nullptr, "sort32_pass", st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
 int32_t gs_rasterize(const gs_splat* splats, const uint32_t* values, const uint32_t* tile_ranges,
                      const gs_camera* cam, const gs_settings* set, float* image, float* T_final,
                      uint32_t* last, uint32_t* n_blend, void* stream) {

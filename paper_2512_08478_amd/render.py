@@ -157,6 +157,22 @@ class Renderer:
         L.check(st, "gs_sort")
         return keys, values, ranges, flag, capacity
 
+    def sort_pairs32(self, keys, values=None, key_bits=32, want_keys=False):
+        """Stable sort of 32-bit keys (int32 tensor holding u32 bit patterns)
+        with u32 payloads (values=None: 0..n-1).  Returns (sorted keys or
+        None, sorted values)."""
+        lib = L.load()
+        s = self.settings
+        n = int(keys.numel())
+        kout = self._buf("s32_keys", n * 4).view(torch.int32)[:n] if want_keys else None
+        vout = self._buf("s32_vals", n * 4).view(torch.int32)[:n]
+        ws_bytes = lib.gs_workspace_size(L.GS_STAGE_SORT_PAIRS, 0, n, None, ctypes.byref(s))
+        ws = self._buf("ws_s32", ws_bytes)
+        st = lib.gs_sort_pairs32(n, _p(keys), _p(values), key_bits, _p(kout), _p(vout),
+                                 ctypes.byref(s), _p(ws), ws.numel(), _stream())
+        L.check(st, "gs_sort_pairs32")
+        return kout, vout
+
     def rasterize(self, splats, values, ranges, cam, n_blend=None):
         """Eqs. 2-3.  `n_blend`, if given, is an int32 (H, W) tensor that
         receives the number of splats blended into each pixel."""

@@ -219,3 +219,20 @@ def test_multi_view_backward_validation(lib):
     r = lib.gs_rasterize_backward_2d(F, F, F, ctypes.byref(c), ctypes.byref(s), F, F, F, 4,
                                      ctypes.c_void_p(FAKE + 4), None)
     assert r == L.GS_ERR_MISALIGNED
+
+
+def test_sort_pairs32_validation(lib):
+    s = L.default_settings()
+    F = ctypes.c_void_p(FAKE)
+
+    def sp(n=8, kb=32, kin=F, vin=None, kout=ctypes.c_void_p(FAKE + 4096),
+           vout=ctypes.c_void_p(FAKE + 8192), ws=1 << 30):
+        return lib.gs_sort_pairs32(n, kin, vin, kb, kout, vout, ctypes.byref(s), F, ws, None)
+    assert sp(kb=0) == L.GS_ERR_INVALID_ARGUMENT
+    assert sp(kb=33) == L.GS_ERR_INVALID_ARGUMENT
+    assert sp(n=-1) == L.GS_ERR_INVALID_ARGUMENT
+    assert sp(kout=F) == L.GS_ERR_INVALID_ARGUMENT            # in == out
+    assert sp(vin=ctypes.c_void_p(FAKE + 8192)) == L.GS_ERR_INVALID_ARGUMENT
+    assert sp(vout=None) == L.GS_ERR_INVALID_ARGUMENT
+    assert sp(vout=ctypes.c_void_p(FAKE + 8196)) == L.GS_ERR_MISALIGNED
+    assert sp(ws=0) == L.GS_ERR_WORKSPACE

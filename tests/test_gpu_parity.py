@@ -293,10 +293,13 @@ def sampled_pixels(cam, n, seed):
     return np.concatenate([pix, corners]).astype(np.int32)
 
 
-def test_render_medium_1080p_sampled(R, orc):
-    print_case("render 1M 1920x1080 sampled pixels")
+@pytest.mark.parametrize("shape", [(16, 16, 8), (32, 16, 7)])
+def test_render_medium_1080p_sampled(R, orc, shape):
+    print_case(f"render 1M 1920x1080 sampled pixels, tiles {shape[0]}x{shape[1]}, {shape[2]}-bit digits")
+    from paper_2512_08478_amd.render import Renderer
+    Rs = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2]))
     sc, cam = S.medium_scene()
-    fr = R.forward(gp(sc), cam)
+    fr = Rs.forward(gp(sc), cam)
     img = fr.image.cpu().numpy()
     pix = sampled_pixels(cam, 256, 11)
     ref = orc.render_pixels(orc.preprocess(sc, cam), cam, pix)
@@ -304,10 +307,13 @@ def test_render_medium_1080p_sampled(R, orc):
     print(f"1M max err {e:.2e}, flagged {nflag}, instances {fr.capacity}")
 
 
-def test_render_large_6m_sampled(R, orc):
-    print_case("render 6M 1920x1080 sampled pixels")
+@pytest.mark.parametrize("shape", [(16, 16, 8), (8, 8, 8)])
+def test_render_large_6m_sampled(R, orc, shape):
+    print_case(f"render 6M 1920x1080 sampled pixels, tiles {shape[0]}x{shape[1]}")
+    from paper_2512_08478_amd.render import Renderer
+    Rs = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2]))
     sc, cam = S.large_scene()
-    fr = R.forward(gp(sc), cam)
+    fr = Rs.forward(gp(sc), cam)
     img = fr.image.cpu().numpy()
     rec = splats_np(fr.splats, sc.n)
     culled = float(np.mean(rec["tx1"] < rec["tx0"]))
@@ -377,3 +383,31 @@ def test_capacity_overflow_flag(R):
     keys, values, ranges, flag, cap = R.sort(sc.n, *pre, cam, capacity=tot)
     torch.cuda.synchronize()
     assert int(u32(flag)[0]) == 0
+
+
+@pytest.mark.parametrize("bits", [6, 8])
+def test_sort_pairs32_bitexact(R, bits):
+    """The 32-bit-key sort: keys and the permutation equal NumPy's stable
+    argsort, with and without explicit values and output keys."""
+    from paper_2512_08478_amd.render import Renderer
+    Rs = Renderer(dict(radix_bits=bits))
+    rng = np.random.default_rng(77)
+    for n in (1, 63, 64, 4097, 100003, 1_500_000):
+        for kind in ("random", "depth", "few"):
+            print_case(f"sort_pairs32 {kind} n={n} bits={bits}")
+            if kind == "random":
+                k = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+            elif kind == "depth":
+                k = rng.uniform(0.2, 40.0, n).astype(np.float32).view(np.uint32)
+                k[rng.random(n) < 0.3] = 0xFFFFFFFF  # culled
+            else:
+                k = rng.integers(0, 3, n).astype(np.uint32) << np.uint32(20)
+            kt = torch.from_numpy(k.view(np.int32)).cuda()
+            perm = np.argsort(k, kind="stable").astype(np.uint32)
+            ks, vs = Rs.sort_pairs32(kt, want_keys=True)
+            np.testing.assert_array_equal(u32(vs), perm)
+            np.testing.assert_array_equal(u32(ks), k[perm])
+            vals = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+            _, vs2 = Rs.sort_pairs32(kt, torch.from_numpy(vals.view(np.int32)).cuda())
+            np.testing.assert_array_equal(u32(vs2), vals[perm])
+            np.testing.assert_array_equal(u32(kt), k)  # input untouched
