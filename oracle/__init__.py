@@ -9,7 +9,10 @@ generator, which holds none of the method's arithmetic.
 implements the forward definition: the per-Gaussian projection of Eq. 1,
 the SH colour, and the per-pixel compositing of Eqs. 2-3 by brute force in
 ascending (depth, index) order; plus the (tile, depth) key list and a
-library stable sort.  ``grad.py`` gives reference gradients by float64
+library stable sort.  ``prepack`` / ``preprocess_packed`` give the FP16
+pre-pack of Section 3.4 (one rounding of float64 values to binary16) and
+the projection from the packed mean, opacity and upper covariance.
+``grad.py`` gives reference gradients by float64
 automatic differentiation of the same definition (Section 3.2: the
 formulation is differentiable).
 
@@ -18,7 +21,10 @@ and off the optical axis, two ordered Gaussians and n coincident Gaussians;
 covariance eigen-invariants; the SH basis against SciPy's complex
 harmonics and by quadrature; the sort against NumPy's stable argsort and a
 brute-force sort; front-to-back against back-to-front compositing; and the
-gradients against central finite differences of the C forward.
+gradients against central finite differences of the C forward; the
+covariance-input projection against the raw-parameter one at a SciPy
+covariance, and the binary16 rounding against IEEE 754's ties-to-even
+cases.
 """
 from __future__ import annotations
 
@@ -76,6 +82,7 @@ def _load():
         I64 = ctypes.c_int64
         lib.orc_preprocess.argtypes = [I64, P, P, P, P, P, ctypes.c_int, P, P, P, P, P]
         lib.orc_preprocess_f64.argtypes = [I64, P, P, P, P, P, ctypes.c_int, P, P, P, P, P]
+        lib.orc_preprocess_cov.argtypes = [I64, P, P, P, P, ctypes.c_int, P, P, P, P, P]
         lib.orc_render_pixels.argtypes = [I64, P, P, P, P, I64, P, P, P, P, P, P]
         lib.orc_keys.argtypes = [I64, P, P, ctypes.c_int, P, P]
         lib.orc_count_instances.argtypes = [I64, P]
@@ -153,6 +160,63 @@ def preprocess(scene, cam, settings=None, f64_inputs=False) -> Records:
             _p(ca), _p(sa), _p(d), _p(iv))
     if rc != 0:
         raise ValueError("orc_preprocess rejected its arguments")
+    return Records(d, iv)
+
+
+def covariance(scene) -> np.ndarray:
+    """Sigma = R(q/|q|) diag(exp(log_s))^2 R^T per Gaussian (float64, (N,3,3))
+    from the float32 inputs (Section 3.2; Algorithm 1, CovFromScaleRot)."""
+    q = np.asarray(scene.quats, np.float32).astype(np.float64)
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    R = np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                  2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                  2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1)
+    R = R.reshape(-1, 3, 3)
+    s = np.exp(np.asarray(scene.log_scales, np.float32).astype(np.float64))
+    M = R * s[:, None, :]
+    return M @ np.transpose(M, (0, 2, 1))
+
+
+def to_fp16(x) -> np.ndarray:
+    """One rounding of float64 values to IEEE binary16, to nearest, ties to
+    even (NumPy converts from the float64 bits directly)."""
+    with np.errstate(over="ignore"):
+        return np.asarray(x, np.float64).astype(np.float16)
+
+
+def prepack(scene) -> dict:
+    """The pre-pack of Algorithm 1 / Section 3.4: mean, activated opacity,
+    the upper covariance triangle (xx, xy, xz, yy, yz, zz) and the SH
+    coefficients, each computed in float64 from the float32 inputs and
+    rounded once to binary16."""
+    Sig = covariance(scene)
+    iu = ([0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2])
+    logit = np.asarray(scene.opacity_logits, np.float32).astype(np.float64)
+    return dict(means=to_fp16(np.asarray(scene.means, np.float32)),
+                opacity=to_fp16(1.0 / (1.0 + np.exp(-logit))),
+                cov6=to_fp16(Sig[:, iu[0], iu[1]]),
+                sh=to_fp16(np.asarray(scene.sh, np.float32)),
+                sh_degree=int(scene.sh_degree), model=scene.model)
+
+
+def preprocess_packed(packed, cam, settings=None) -> Records:
+    """Eq. 1 + colour + culls from pre-packed values (any float dtype; they
+    are used exactly, as float64)."""
+    lib = _load()
+    f = lambda a: np.ascontiguousarray(np.asarray(a, np.float64))
+    means, opac = f(packed["means"]), f(packed["opacity"]).reshape(-1)
+    cov6, sh = f(packed["cov6"]).reshape(-1, 6), f(packed["sh"])
+    n = means.shape[0]
+    d = np.zeros((n, 24), np.float64)
+    iv = np.zeros((n, 11), np.int32)
+    model = packed.get("model")
+    model = None if model is None else np.ascontiguousarray(model, np.float64)
+    ca, sa = cam_array(cam), set_array(settings)
+    rc = lib.orc_preprocess_cov(n, _p(means), _p(opac), _p(cov6), _p(sh), int(packed["sh_degree"]),
+                                _p(model), _p(ca), _p(sa), _p(d), _p(iv))
+    if rc != 0:
+        raise ValueError("orc_preprocess_cov rejected its arguments")
     return Records(d, iv)
 
 

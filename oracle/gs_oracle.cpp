@@ -12,7 +12,9 @@
 //     and rotation (Algorithm 1, CovFromScaleRot), optional per-model
 //     similarity transform, camera transform, near/opacity/frustum culls,
 //     EWA footprint S = J W Sigma W^T J^T (+ eps I), its inverse, the 2-D
-//     mean, and the view-dependent SH colour (Section 3.2 / 3.4);
+//     mean, and the view-dependent SH colour (Section 3.2 / 3.4); the same
+//     projection from a Gaussian given by mean, activated opacity and upper
+//     covariance triangle (the pre-packed form of Section 3.4);
 //   * the per-pixel colour of Eq. 3 with the 2-D weight of Eq. 2, taken by
 //     brute force over every surviving Gaussian in ascending (depth, index)
 //     order -- no tiles, no sort keys;
@@ -168,40 +170,24 @@ bool finite_all(const double* v, int n) {
   return true;
 }
 
-// One Gaussian: Eq. 1 and the colour, with every cull of Algorithm 1.
-// Real is float (the library's input type) or double (finite differences).
+// One Gaussian from its raw parameters: activations and the covariance
+// Sigma = R diag(s^2) R^T (Algorithm 1, CovFromScaleRot; Section 3.2), then
+// the common projection below.  Real is float (the library's input type)
+// or double (finite differences).
 template <typename Real>
 void preprocess_one(int64_t i, const Real* means, const Real* log_scales,
                     const Real* quats, const Real* logits, const Real* sh,
                     int degree, const double* model, const Cam& cam,
-                    const Set& set, double* d, int32_t* iv) {
-  for (int k = 0; k < REC_D; ++k) d[k] = 0.0;
-  for (int k = 0; k < REC_I; ++k) iv[k] = 0;
-  iv[I_PX0] = iv[I_PY0] = iv[I_TX0] = iv[I_TY0] = 0;
-  iv[I_PX1] = iv[I_PY1] = iv[I_TX1] = iv[I_TY1] = -1;
+                    const Set& set, double* d, int32_t* iv);
+
+// Eq. 1 and the colour for one Gaussian with mean mu, activated opacity o,
+// world covariance Sig (asset frame) and SH row sh_row, with every cull of
+// Algorithm 1.
+template <typename ShT>
+void project_gaussian(const double* mu, double o, const double* Sig, const ShT* sh_row,
+                      int degree, const double* model, const Cam& cam, const Set& set,
+                      double* d, int32_t* iv) {
   const int K = (degree + 1) * (degree + 1);
-
-  double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
-  double s[3] = {std::exp((double)log_scales[3 * i]), std::exp((double)log_scales[3 * i + 1]),
-                 std::exp((double)log_scales[3 * i + 2])};
-  double q[4] = {quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
-  double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-  double o = 1.0 / (1.0 + std::exp(-(double)logits[i]));
-  d[D_OPAC] = o;
-  if (!(qn > 0.0) || !std::isfinite(qn) || !finite_all(mu, 3) || !finite_all(s, 3) ||
-      !std::isfinite(o)) {
-    iv[I_CULL] = C_INVALID;
-    return;
-  }
-  for (int k = 0; k < 4; ++k) q[k] /= qn;
-
-  // Sigma = R diag(s^2) R^T   (Algorithm 1, CovFromScaleRot; Section 3.2)
-  double R[9], M[9], Sig[9];
-  quat_to_rot(q[0], q[1], q[2], q[3], R);
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) M[3 * r + c] = R[3 * r + c] * s[c];
-  matmul3_bt(M, M, Sig);
-
   // Per-model similarity transform A = s_k R_k, translation t_k
   // (Algorithm 1, ModelParams; Section 3.4 step (i)).
   double A[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, tk[3] = {0, 0, 0}, Rk[9];
@@ -253,7 +239,7 @@ void preprocess_one(int64_t i, const Real* means, const Real* log_scales,
   sh_basis(degree, dl[0], dl[1], dl[2], Y);
   for (int ch = 0; ch < 3; ++ch) {
     double acc = 0.0;
-    for (int k = 0; k < K; ++k) acc += (double)sh[((size_t)i * K + k) * 3 + ch] * Y[k];
+    for (int k = 0; k < K; ++k) acc += (double)sh_row[k * 3 + ch] * Y[k];
     acc += 0.5;
     d[D_RR + ch] = acc;
     d[D_R + ch] = acc > 0.0 ? acc : 0.0;
@@ -330,6 +316,61 @@ void preprocess_one(int64_t i, const Real* means, const Real* log_scales,
     iv[I_TILES] = (iv[I_TX1] - iv[I_TX0] + 1) * (iv[I_TY1] - iv[I_TY0] + 1);
 }
 
+void clear_record(double* d, int32_t* iv) {
+  for (int k = 0; k < REC_D; ++k) d[k] = 0.0;
+  for (int k = 0; k < REC_I; ++k) iv[k] = 0;
+  iv[I_PX0] = iv[I_PY0] = iv[I_TX0] = iv[I_TY0] = 0;
+  iv[I_PX1] = iv[I_PY1] = iv[I_TX1] = iv[I_TY1] = -1;
+}
+
+template <typename Real>
+void preprocess_one(int64_t i, const Real* means, const Real* log_scales,
+                    const Real* quats, const Real* logits, const Real* sh,
+                    int degree, const double* model, const Cam& cam,
+                    const Set& set, double* d, int32_t* iv) {
+  clear_record(d, iv);
+  const int K = (degree + 1) * (degree + 1);
+  double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
+  double s[3] = {std::exp((double)log_scales[3 * i]), std::exp((double)log_scales[3 * i + 1]),
+                 std::exp((double)log_scales[3 * i + 2])};
+  double q[4] = {quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
+  double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  double o = 1.0 / (1.0 + std::exp(-(double)logits[i]));
+  d[D_OPAC] = o;
+  if (!(qn > 0.0) || !std::isfinite(qn) || !finite_all(mu, 3) || !finite_all(s, 3) ||
+      !std::isfinite(o)) {
+    iv[I_CULL] = C_INVALID;
+    return;
+  }
+  for (int k = 0; k < 4; ++k) q[k] /= qn;
+  double R[9], M[9], Sig[9];
+  quat_to_rot(q[0], q[1], q[2], q[3], R);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) M[3 * r + c] = R[3 * r + c] * s[c];
+  matmul3_bt(M, M, Sig);
+  project_gaussian(mu, o, Sig, sh + (size_t)i * K * 3, degree, model, cam, set, d, iv);
+}
+
+// One Gaussian given directly by its mean, activated opacity and the upper
+// triangle (xx, xy, xz, yy, yz, zz) of its covariance: the input of the
+// pre-packed layout (Algorithm 1, Pre-pack; Section 3.4).
+void preprocess_cov_one(int64_t i, const double* means, const double* opac, const double* cov6,
+                        const double* sh, int degree, const double* model, const Cam& cam,
+                        const Set& set, double* d, int32_t* iv) {
+  clear_record(d, iv);
+  const int K = (degree + 1) * (degree + 1);
+  const double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
+  const double* u = cov6 + 6 * i;
+  const double Sig[9] = {u[0], u[1], u[2], u[1], u[3], u[4], u[2], u[4], u[5]};
+  const double o = opac[i];
+  d[D_OPAC] = o;
+  if (!finite_all(mu, 3) || !finite_all(Sig, 9) || !std::isfinite(o)) {
+    iv[I_CULL] = C_INVALID;
+    return;
+  }
+  project_gaussian(mu, o, Sig, sh + (size_t)i * K * 3, degree, model, cam, set, d, iv);
+}
+
 inline double pixel_weight(const double* d, double px, double py) {
   // Eq. 2 without the alpha clamp: o * exp(-1/2 dx^T S^-1 dx)
   const double dx = px - d[D_MX], dy = py - d[D_MY];
@@ -389,6 +430,22 @@ int orc_preprocess_f64(int64_t n, const double* means, const double* log_scales,
   for (int64_t i = 0; i < n; ++i)
     preprocess_one<double>(i, means, log_scales, quats, logits, sh, degree, model, cam, set,
                            rec_d + (size_t)i * REC_D, rec_i + (size_t)i * REC_I);
+  return 0;
+}
+
+// From the pre-packed representation: means (n*3), activated opacities (n),
+// upper covariance triangles (n*6: xx, xy, xz, yy, yz, zz) and SH (n*K*3),
+// all float64 (the caller decodes whatever rounded values it packs).
+int orc_preprocess_cov(int64_t n, const double* means, const double* opac, const double* cov6,
+                       const double* sh, int degree, const double* model, const double* cam_in,
+                       const double* set_in, double* rec_d, int32_t* rec_i) {
+  if (n < 0 || degree < 0 || degree > 3) return 1;
+  const Cam cam = load_cam(cam_in);
+  const Set set = load_set(set_in);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    preprocess_cov_one(i, means, opac, cov6, sh, degree, model, cam, set,
+                       rec_d + (size_t)i * REC_D, rec_i + (size_t)i * REC_I);
   return 0;
 }
 

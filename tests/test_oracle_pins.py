@@ -406,3 +406,81 @@ def test_keys_structure(orc):
     assert np.all((iv[:, orc.I_TX0] <= x) & (x <= iv[:, orc.I_TX1]))
     assert np.all((iv[:, orc.I_TY0] <= y) & (y <= iv[:, orc.I_TY1]))
     assert np.all(np.diff(v.astype(np.int64)) >= 0)  # Gaussian-major
+
+
+# ---------------------------------------------------------------- Pre-pack (Section 3.4)
+
+def _cov6_scipy(sc):
+    """Upper triangle of R diag(s^2) R^T with R from SciPy (scalar-last)."""
+    q = sc.quats.astype(np.float32).astype(np.float64)
+    R = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()
+    s2 = np.exp(2 * sc.log_scales.astype(np.float32).astype(np.float64))
+    Sig = np.einsum("nik,nk,njk->nij", R, s2, R)
+    return Sig[:, [0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
+
+
+def test_covariance_helper_matches_scipy(orc):
+    sc, _ = S.tiny_scene(n=512)
+    Sig = orc.covariance(sc)
+    np.testing.assert_allclose(Sig[:, [0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]], _cov6_scipy(sc),
+                               rtol=1e-12, atol=1e-18)
+
+
+@pytest.mark.parametrize("with_model", [False, True])
+def test_covariance_input_path_matches_raw_parameters(orc, with_model):
+    # The pre-packed inputs without the fp16 rounding (mean, sigmoid of the
+    # logit, SciPy covariance, SH, all float64) reproduce the raw-parameter
+    # records: the two front ends meet at the same Sigma.
+    sc, cam = S.medium_scene(n=3000)
+    if with_model:
+        rot = Rotation.from_euler("xyz", [0.2, 0.5, -0.3])
+        model = np.concatenate([0.8 * rot.as_matrix(), np.array([[0.3], [-0.2], [0.1]])], 1)
+        sc = S.Scene(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh, sc.sh_degree, model)
+    r_raw = orc.preprocess(sc, cam)
+    logit = sc.opacity_logits.astype(np.float32).astype(np.float64)
+    packed = dict(means=sc.means.astype(np.float32), opacity=1 / (1 + np.exp(-logit)),
+                  cov6=_cov6_scipy(sc), sh=sc.sh.astype(np.float32), sh_degree=sc.sh_degree,
+                  model=sc.model)
+    r_cov = orc.preprocess_packed(packed, cam)
+    assert r_raw.visible.sum() > 500
+    np.testing.assert_array_equal(r_cov.i[:, orc.I_CULL], r_raw.i[:, orc.I_CULL])
+    v = r_raw.visible
+    np.testing.assert_array_equal(r_cov.i[v], r_raw.i[v])
+    np.testing.assert_allclose(r_cov.d[v], r_raw.d[v], rtol=1e-9, atol=1e-12)
+
+
+def test_fp16_rounding_is_ieee_nearest_even(orc):
+    # Round-to-nearest-even into binary16 (11-bit significand, subnormals
+    # down to 2**-24, overflow past 65520), as IEEE 754 defines it.
+    u = 2.0 ** -10
+    cases = [(1 + u / 2, 1.0),                    # tie -> even
+             (1 + 3 * u / 2, 1 + 2 * u),          # tie -> even (up)
+             (1 + u / 2 + 2.0 ** -40, 1 + u),     # just past the tie
+             (2.0 ** -25, 0.0),                   # tie at the smallest subnormal
+             (2.0 ** -25 * 1.0000001, 2.0 ** -24),
+             (3 * 2.0 ** -26, 2.0 ** -24),
+             (65504.0, 65504.0), (65519.99, 65504.0), (65520.0, np.inf),
+             (-(1 + 3 * u / 2), -(1 + 2 * u))]
+    got = orc.to_fp16(np.array([x for x, _ in cases]))
+    assert got.dtype == np.float16
+    want = np.array([w for _, w in cases])
+    np.testing.assert_array_equal(got.astype(np.float64), want)
+
+
+def test_prepack_fields(orc):
+    sc, _ = S.medium_scene(n=2000)
+    p = orc.prepack(sc)
+    assert all(p[k].dtype == np.float16 for k in ("means", "opacity", "cov6", "sh"))
+    Sig = orc.covariance(sc)
+    iu = ([0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2])
+    exact = Sig[:, iu[0], iu[1]]
+    # each packed covariance entry is the nearest binary16 value: within
+    # half a spacing of the exact one
+    got = p["cov6"].astype(np.float64)
+    sp = np.spacing(np.abs(got).astype(np.float16)).astype(np.float64)
+    assert np.all(np.abs(got - exact) <= 0.5 * sp * (1 + 1e-12))
+    logit = sc.opacity_logits.astype(np.float32).astype(np.float64)
+    o = p["opacity"].astype(np.float64)
+    assert np.all(np.abs(o - 1 / (1 + np.exp(-logit))) <= 0.5 * np.spacing(p["opacity"]).astype(np.float64))
+    np.testing.assert_array_equal(p["means"], sc.means.astype(np.float32).astype(np.float16))
+    np.testing.assert_array_equal(p["sh"], sc.sh.astype(np.float32).astype(np.float16))
