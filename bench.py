@@ -5,6 +5,11 @@ Default workload: the 1,000,000-Gaussian clustered scene (SH degree 3) at
 inputs resident in HBM.  A step is one whole frame.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload medium|large|diff|tiny]
+                  [--packed]
+
+--packed renders from the FP16 pre-pack (Section 3.4): the Gaussians are
+pre-packed once before timing, and every frame preprocesses the binary16
+mean, opacity, upper covariance and SH (forward workloads only).
 """
 from __future__ import annotations
 
@@ -29,8 +34,8 @@ FLOPS_PER_BLEND = 24
 
 SORT_KERNELS = ("sort_init", "radix_hist", "depth_pass", "kg_count", "kg_scan", "keygen",
                 "tile_pass", "tile_ranges")
-HBM_KERNELS = ("preprocess", "depth_pass", "keygen", "kg_count", "tile_pass", "tile_ranges",
-               "preprocess_bwd")
+HBM_KERNELS = ("preprocess", "preprocess_packed", "depth_pass", "keygen", "kg_count", "tile_pass",
+               "tile_ranges", "preprocess_bwd")
 ALU_KERNELS = ("raster", "raster_bwd")
 
 WORKLOADS = {
@@ -57,6 +62,8 @@ def parse():
                     help="WxH, or auto: the autotuner picks tile shape and digit width")
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--sort-mode", type=int, default=0)
+    ap.add_argument("--packed", action="store_true",
+                    help="forward from the FP16 pre-packed inputs (pre-packed once, untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=2048)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -78,12 +85,19 @@ def make_workload(name):
     raise ValueError(name)
 
 
+def packed_sh_halves(K):
+    return (3 * K + 3) // 4 * 4
+
+
 def algorithmic_bytes(n, n_vis, inst, K, W, H, tiles):
     """Bytes each kernel must move (reads + writes), per launch."""
     return {
         # means 12 + log-scales 12 + quats 16 + logit 4 read, 48 B record + 4 B depth key
-        # written per Gaussian; SH 12K bytes read per visible one
-        "preprocess": n * (44 + 52) + n_vis * 12 * K,
+        # + 8 B tile rect written per Gaussian; SH 12K bytes read per visible one
+        "preprocess": n * (44 + 60) + n_vis * 12 * K,
+        # binary16 mean + opacity 8 + covariance 12 read, the same 60 B written per
+        # Gaussian; the packed SH row (2 bytes a half) read per visible one
+        "preprocess_packed": n * (20 + 60) + n_vis * 2 * packed_sh_halves(K),
         # per depth pass: u32 key + u32 value read and written per Gaussian (upsweep,
         # scan and downsweep together)
         "depth_pass": n * 16,
@@ -133,6 +147,9 @@ def main():
     from paper_2512_08478_amd import _lib as L
     from paper_2512_08478_amd.render import GaussianParams, Renderer
 
+    if args.packed and args.workload not in ("tiny", "medium", "large"):
+        print(json.dumps({"error": "--packed applies to the forward workloads tiny, medium, large"}))
+        sys.exit(2)
     if args.workload == "batched":
         return run_batched(args)
     if args.workload == "sort32":
@@ -145,6 +162,10 @@ def main():
         del src, dst
     sc, cam = make_workload(args.workload)
     p = GaussianParams.from_scene(sc)
+    if args.packed:
+        # the pre-pack runs once per asset, before any frame (Algorithm 1)
+        p = Renderer().prepack(p)
+        torch.cuda.synchronize()
     backward = args.workload == "diff"
     H, W = cam.height, cam.width
     target = None
@@ -267,7 +288,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "n_gaussians": sc.n, "width": W,
+        "config": {"workload": WORKLOADS[args.workload] + (
+                       ", FP16 pre-packed inputs" if args.packed else ""),
+                   "n_gaussians": sc.n, "width": W,
                    "height": H, "tile": f"{tw}x{th}", "radix_bits": args.radix_bits,
                    "visible": n_vis, "instances": inst, "key_bits": key_bits,
                    "depth_passes": passes[0], "tile_passes": passes[1]},
@@ -280,7 +303,7 @@ def main():
         out["autotune_ms_per_frame"] = tuned
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels)
+        out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels, packed=args.packed)
     print(json.dumps(out), flush=True)
 
 
@@ -456,14 +479,19 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(sc, cam, n_pix, scale_pixels=None):
+def cpu_baseline(sc, cam, n_pix, scale_pixels=None, packed=False):
     """The FP64 oracle, as it stands, on a bounded sample of the same frame:
     preprocess of every Gaussian + brute-force compositing of n_pix random
-    pixels, scaled to a whole frame."""
+    pixels, scaled to a whole frame.  With `packed`, the oracle pre-packs
+    first (untimed, as on the GPU) and preprocesses the packed values."""
     import numpy as np
     import oracle
+    pk = oracle.prepack(sc) if packed else None
     t0 = time.perf_counter()
-    if isinstance(sc, (list, tuple)):   # several assets, one view of the batch
+    if pk is not None:
+        rec = oracle.preprocess_packed(pk, cam)
+        n = sc.n
+    elif isinstance(sc, (list, tuple)):   # several assets, one view of the batch
         rec = oracle.preprocess_many(sc, cam)
         n = sum(a.n for a in sc)
     else:
@@ -484,7 +512,8 @@ def cpu_baseline(sc, cam, n_pix, scale_pixels=None):
         what = f"scaled to the batch's {scale_pixels} pixels, reported per view"
     return {"value": round(1.0 / frame_s, 8), "unit": "frames/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"FP64 oracle, forward only: preprocess of all {n} Gaussians "
+            "sample": f"FP64 oracle, forward only: preprocess of all {n} "
+                      f"{'pre-packed ' if pk is not None else ''}Gaussians "
                       f"({t1 - t0:.2f} s) + brute-force Eq. 3 at {n_pix} random pixels "
                       f"({t2 - t1:.2f} s), {what}"}
 

@@ -226,6 +226,49 @@ int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n
                              void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * FP16 pre-pack (Algorithm 1's Pre-pack step; Section 3.4): scale and
+ * rotation become the covariance Sigma = R diag(s^2) R^T, and the mean,
+ * activated opacity, upper triangle of Sigma and SH coefficients are stored
+ * as IEEE binary16, two to a 32-bit word.  Layout (device, little-endian
+ * halves, n Gaussians):
+ *   posop[n*4]  (mu_x, mu_y, mu_z, alpha), alpha = sigmoid(logit)
+ *   cov[n*6]    (xx, xy, xz, yy, yz, zz) of Sigma
+ *   sh16[n*S]   the K*3 SH coefficients in the raw order (coefficient-major,
+ *               RGB innermost), zero-padded to S = gs_packed_sh_stride()
+ * gs_packed_sh_stride returns S for sh_degree 0..3 (4, 12, 28, 48), -1
+ * otherwise.
+ */
+int32_t gs_packed_sh_stride(int32_t sh_degree);
+
+/*
+ * gs_prepack -- converts n raw Gaussians (the inputs of gs_preprocess) to
+ * the layout above; run once per asset.  Opacity and covariance are
+ * computed in float64 and rounded once to the nearest binary16 (ties to
+ * even); means and SH are rounded from float32 directly.  Values beyond
+ * the binary16 range become infinities, and gs_preprocess_packed culls
+ * such Gaussians.  The outputs must not overlap the inputs.
+ */
+int32_t gs_prepack(int64_t n, const float* means, const float* log_scales, const float* quats,
+                   const float* opacity_logits, const float* sh, int32_t sh_degree,
+                   uint16_t* posop, uint16_t* cov, uint16_t* sh16, void* stream);
+
+/*
+ * gs_preprocess_packed -- gs_preprocess_assets from the pre-packed layout:
+ * the same culls, records, depth keys, tile rects and counts, computed from
+ * the binary16 mean, opacity, covariance and SH (exactly as decoded).  The
+ * 2-D covariance J W Sigma W^T J^T and its determinant are formed in
+ * float64.  Asset offsets index Gaussians (posop + 4*offset, cov +
+ * 6*offset, sh16 + S*offset).  Forward only: the packed form has no
+ * backward.  Same workspace as gs_preprocess for n Gaussians.
+ */
+int32_t gs_preprocess_packed(int32_t n_assets, const gs_asset* assets, int64_t n,
+                             const uint16_t* posop, const uint16_t* cov, const uint16_t* sh16,
+                             int32_t sh_degree, const gs_camera* cam, const gs_settings* set,
+                             gs_splat* splats, uint32_t* depth_keys, uint32_t* tile_rects,
+                             uint32_t* counts, void* workspace, size_t workspace_bytes,
+                             void* stream);
+
+/*
  * gs_sort -- key generation and the per-frame GPU radix sort (Algorithm 1,
  * Radix Sort; Section 3.4).  The sort order is that of the 64-bit keys
  *     key = tile_id << 32 | bits(float32 depth)

@@ -31,7 +31,8 @@ EXPORTED = (
     "gs_workspace_size", "gs_sort_key_bits", "gs_preprocess", "gs_sort", "gs_sort_pairs",
     "gs_rasterize", "gs_rasterize_backward", "gs_trace_enable", "gs_trace_read",
     "gs_preprocess_assets", "gs_rasterize_backward_assets", "gs_rasterize_backward_2d",
-    "gs_preprocess_backward_views", "gs_sort_pairs32",
+    "gs_preprocess_backward_views", "gs_sort_pairs32", "gs_packed_sh_stride", "gs_prepack",
+    "gs_preprocess_packed",
 )
 BWD_VIEWS_PER_LAUNCH = 8
 GRAD2D_STRIDE = 12  # floats per Gaussian in a 2-D gradient record
@@ -137,6 +138,12 @@ def load():
     lib.gs_preprocess_backward_views.argtypes = [I32, CAM, ctypes.POINTER(ctypes.c_void_p), I32, AS,
                                                  I64, P, P, P, P, P, I32, SET, P, P, P, P, P, I32,
                                                  P]
+    lib.gs_packed_sh_stride.restype = I32
+    lib.gs_packed_sh_stride.argtypes = [I32]
+    lib.gs_prepack.restype = I32
+    lib.gs_prepack.argtypes = [I64, P, P, P, P, P, I32, P, P, P, P]
+    lib.gs_preprocess_packed.restype = I32
+    lib.gs_preprocess_packed.argtypes = [I32, AS, I64, P, P, P, I32, CAM, SET, P, P, P, P, P, SZ, P]
     lib.gs_trace_enable.restype = I32
     lib.gs_trace_enable.argtypes = [I32]
     lib.gs_trace_read.restype = I32
@@ -159,6 +166,14 @@ def trace_read(max_entries: int = 512):
     raw = labels.raw
     return [(raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode(), float(ms[i]))
             for i in range(cnt.value)]
+
+
+def packed_sh_stride(sh_degree: int) -> int:
+    """Halves per packed SH row (4, 12, 28, 48 for degrees 0..3)."""
+    S = load().gs_packed_sh_stride(int(sh_degree))
+    if S < 0:
+        raise GsError(GS_ERR_UNSUPPORTED, "gs_packed_sh_stride")
+    return S
 
 
 def status_string(status: int) -> str:

@@ -334,6 +334,64 @@ int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales, co
                               workspace, workspace_bytes, stream);
 }
 
+int32_t gs_packed_sh_stride(int32_t sh_degree) { return gs::packed_sh_stride(sh_degree); }
+
+int32_t gs_prepack(int64_t n, const float* means, const float* log_scales, const float* quats,
+                   const float* opacity_logits, const float* sh, int32_t sh_degree,
+                   uint16_t* posop, uint16_t* cov, uint16_t* sh16, void* stream) {
+  int32_t r;
+  if ((r = check_inputs(n, means, log_scales, quats, opacity_logits, sh, sh_degree))) return r;
+  if (n > 0 && ((r = check_dev(posop)) || (r = check_dev(cov)) || (r = check_dev(sh16))))
+    return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = gs::launch_prepack((int)n, means, log_scales, quats, opacity_logits, sh,
+                                          sh_degree, posop, cov, sh16, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
+int32_t gs_preprocess_packed(int32_t n_assets, const gs_asset* assets, int64_t n,
+                             const uint16_t* posop, const uint16_t* cov, const uint16_t* sh16,
+                             int32_t sh_degree, const gs_camera* cam, const gs_settings* set,
+                             gs_splat* splats, uint32_t* depth_keys, uint32_t* tile_rects,
+                             uint32_t* counts, void* workspace, size_t workspace_bytes,
+                             void* stream) {
+  int32_t r;
+  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
+  if (n < 0 || n >= kMaxN) return GS_ERR_INVALID_ARGUMENT;
+  if (sh_degree < 0 || sh_degree > 3) return GS_ERR_UNSUPPORTED;
+  if ((r = check_assets(n_assets, assets, n))) return r;
+  if ((r = check_dev(counts))) return r;
+  if (n > 0 && ((r = check_dev(posop)) || (r = check_dev(cov)) || (r = check_dev(sh16)) ||
+                (r = check_dev(splats)) || (r = check_dev(depth_keys)) ||
+                (r = check_dev(tile_rects))))
+    return r;
+  if (workspace_bytes < gs::preprocess_ws_bytes(n)) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
+  gs::CamK ck[gs::kMaxAssets];
+  for (int a = 0; a < n_assets; ++a)
+    if ((r = make_camk(cam, set, assets[a].model, &ck[a]))) return r;
+  const gs::SetK sk = make_setk(cam, set);
+  const int S = gs::packed_sh_stride(sh_degree);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint2* partial = static_cast<uint2*>(workspace);
+  int blocks = 0;
+  hipError_t e = hipSuccess;
+  for (int a = 0; a < n_assets && e == hipSuccess; ++a) {
+    const int64_t o = assets[a].offset, c = assets[a].count;
+    if (c == 0) continue;
+    e = gs::launch_preprocess_packed((int)c, posop + 4 * o, cov + 6 * o, sh16 + S * o, sh_degree,
+                                     ck[a], sk, splats + o, depth_keys + o, tile_rects + 2 * o,
+                                     partial + blocks, st);
+    blocks += gs::preprocess_blocks(c);
+  }
+  if (e == hipSuccess) e = gs::launch_count_finalize(partial, blocks, counts, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
 int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
                 const uint32_t* tile_rects, const uint32_t* counts, const gs_camera* cam,
                 const gs_settings* set,

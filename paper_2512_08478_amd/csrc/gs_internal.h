@@ -101,6 +101,16 @@ hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              int degree, const CamK& cam, const SetK& set,
                              gs_splat* splats, uint32_t* depth_keys, uint32_t* tile_rects,
                              uint2* partial, hipStream_t st);
+// FP16 pre-pack (binary16 posop n*4, cov n*6, sh16 n*packed_sh_stride) and
+// the projection that reads it; same outputs as launch_preprocess.
+int packed_sh_stride(int degree);
+hipError_t launch_prepack(int n, const float* means, const float* log_scales, const float* quats,
+                          const float* logits, const float* sh, int degree, uint16_t* posop,
+                          uint16_t* cov, uint16_t* sh16, hipStream_t st);
+hipError_t launch_preprocess_packed(int n, const uint16_t* posop, const uint16_t* cov,
+                                    const uint16_t* sh16, int degree, const CamK& cam,
+                                    const SetK& set, gs_splat* splats, uint32_t* depth_keys,
+                                    uint32_t* tile_rects, uint2* partial, hipStream_t st);
 // counts[0] = sum of partial[].x (instances), counts[1] = sum of partial[].y (visible)
 hipError_t launch_count_finalize(const uint2* partial, int blocks, uint32_t* counts,
                                  hipStream_t st);

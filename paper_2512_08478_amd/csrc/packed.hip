@@ -1,0 +1,289 @@
+// FP16 pre-pack and the preprocess that reads it (Algorithm 1's Pre-pack
+// step and Section 3.4's FP16 layout).
+//
+// Pre-pack, once per asset: the covariance Sigma = R diag(s^2) R^T is formed
+// from scale and rotation, and the mean, the activated opacity, the upper
+// triangle of Sigma and the SH coefficients are stored as binary16, two to
+// a 32-bit word.  Per frame, the packed preprocess reads 24 + 2*S bytes per
+// Gaussian (S halves of SH, 48 at degree 3) instead of 48 + 4*3K, and
+// writes the same records, depth keys and tile rects as the raw-parameter
+// preprocess, so sorting and compositing are shared.
+//
+// Layout (n Gaussians, little-endian halves):
+//   posop  n x 4  (mu_x, mu_y, mu_z, alpha)                 8 bytes
+//   cov    n x 6  (xx, xy, xz, yy, yz, zz) of Sigma          12 bytes
+//   sh16   n x S  the 3K coefficients, coefficient-major, RGB innermost,
+//                 zero-padded to S = 3K rounded up to a multiple of 4
+//                 (4, 12, 28, 48 halves for degrees 0..3)
+//
+// Opacity and covariance are computed in float64 and rounded once to the
+// nearest binary16 (ties to even): float64 -> float32 rounds to odd, which
+// makes the second rounding, float32 -> binary16, exact-nearest.  Means and
+// SH are float32 inputs rounded directly.
+//
+// The packed preprocess forms the 2-D covariance S = P Sigma P^T (P = J W,
+// 2x3) and its determinant in float64: Sigma arrives as a matrix, not as
+// factors, so the Cauchy-Binet form of the raw path is not available and
+// det = ac - b^2 would cancel in float32 for thin splats seen edge-on.
+#include "gs_device.h"
+#include "gs_internal.h"
+#include "gs_project.h"
+
+namespace gs {
+namespace {
+
+__device__ __forceinline__ uint16_t f32_to_f16(float f) {
+  return __builtin_bit_cast(uint16_t, static_cast<_Float16>(f));
+}
+
+__device__ __forceinline__ float f16_to_f32(uint32_t h) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(h & 0xFFFFu)));
+}
+
+// Nearest binary16 of a float64 value, ties to even.  Rounding to float32
+// by round-to-odd first (truncate, then set the last bit if anything was
+// cut off) keeps enough information for the final rounding to be correct.
+__device__ __forceinline__ uint16_t f64_to_f16(double d) {
+  float f = static_cast<float>(d);
+  const double back = static_cast<double>(f);
+  if (back != d && d == d) {
+    uint32_t u = __float_as_uint(f);
+    if (fabs(back) > fabs(d)) u -= 1u;  // rounded away from zero: step back
+    f = __uint_as_float(u | 1u);
+  }
+  return f32_to_f16(f);
+}
+
+__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) {
+  return (uint32_t)lo | ((uint32_t)hi << 16);
+}
+
+template <int DEG>
+struct ShPack {
+  static constexpr int K3 = (DEG + 1) * (DEG + 1) * 3;
+  static constexpr int S = (K3 + 3) / 4 * 4;  // halves per packed row
+  static constexpr int U2 = S / 4;            // 8-byte words per packed row
+};
+
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_prepack(
+    int n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, uint2* __restrict__ posop, uint32_t* __restrict__ cov,
+    uint2* __restrict__ sh16) {
+  using P = ShPack<DEG>;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double o = 1.0 / (1.0 + exp(-(double)logits[i]));
+  posop[i] = make_uint2(pack2(f32_to_f16(means[3 * i]), f32_to_f16(means[3 * i + 1])),
+                        pack2(f32_to_f16(means[3 * i + 2]), f64_to_f16(o)));
+  // Sigma = M M^T with M = R diag(s)
+  const float4 q = quats[i];
+  double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
+  const double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+  const double R[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz),
+                       2.0 * (qx * qz + qw * qy),       2.0 * (qx * qy + qw * qz),
+                       1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+                       2.0 * (qx * qz - qw * qy),       2.0 * (qy * qz + qw * qx),
+                       1.0 - 2.0 * (qx * qx + qy * qy)};
+  const double s[3] = {exp((double)log_scales[3 * i]), exp((double)log_scales[3 * i + 1]),
+                       exp((double)log_scales[3 * i + 2])};
+  double M[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) M[3 * r + c] = R[3 * r + c] * s[c];
+  auto sig = [&](int r, int c) {
+    return M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+  };
+  cov[3 * i] = pack2(f64_to_f16(sig(0, 0)), f64_to_f16(sig(0, 1)));
+  cov[3 * i + 1] = pack2(f64_to_f16(sig(0, 2)), f64_to_f16(sig(1, 1)));
+  cov[3 * i + 2] = pack2(f64_to_f16(sig(1, 2)), f64_to_f16(sig(2, 2)));
+  const float* row = sh + (size_t)i * P::K3;
+  uint2* out = sh16 + (size_t)i * P::U2;
+#pragma unroll
+  for (int w = 0; w < P::U2; ++w) {
+    uint16_t h[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = 4 * w + k;
+      h[k] = e < P::K3 ? f32_to_f16(row[e]) : (uint16_t)0;
+    }
+    out[w] = make_uint2(pack2(h[0], h[1]), pack2(h[2], h[3]));
+  }
+}
+
+// Eq. 1 from the packed layout.  Each wave copies the packed SH rows of its
+// visible Gaussians into LDS with contiguous 8-byte loads (the rows of 64
+// consecutive Gaussians are one span), and each lane decodes its own row.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_preprocess_packed(
+    int n, const uint2* __restrict__ posop, const uint32_t* __restrict__ cov,
+    const uint2* __restrict__ sh16, CamK cam, SetK set, gs_splat* __restrict__ splats,
+    uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint2* __restrict__ partial) {
+  using P = ShPack<DEG>;
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr bool STAGED = DEG >= 1;
+  __shared__ uint2 s_sh[STAGED ? kBlock / 64 : 1][STAGED ? 64 * P::U2 : 1];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  uint32_t tiles = 0;
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+  uint32_t rect_lo = 0x0000FFFFu, rect_hi = 0u;  // empty pixel bbox
+  uint2 trect = make_uint2(0x0000FFFFu, 0u);      // empty tile rect
+  float dir[3] = {0.f, 0.f, 0.f};
+  if (i < n) {
+    const uint2 po = posop[i];
+    const float o = f16_to_f32(po.y >> 16);
+    float w[3], t[3];
+    place_mean(f16_to_f32(po.x), f16_to_f32(po.x >> 16), f16_to_f32(po.y), cam, w, t);
+    const float tx = t[0], ty = t[1], tz = t[2];
+    if ((tz > cam.znear) && (o >= set.tau) && __builtin_isfinite(tx) && __builtin_isfinite(ty)) {
+      const uint32_t c0 = cov[3 * i], c1 = cov[3 * i + 1], c2 = cov[3 * i + 2];
+      const double sxx = f16_to_f32(c0), sxy = f16_to_f32(c0 >> 16), sxz = f16_to_f32(c1),
+                   syy = f16_to_f32(c1 >> 16), syz = f16_to_f32(c2), szz = f16_to_f32(c2 >> 16);
+      // Jacobian of the perspective division at t (x/z, y/z clamped)
+      const float iz = 1.f / tz;
+      const float xt = fminf(cam.limx, fmaxf(-cam.limx, tx * iz));
+      const float yt = fminf(cam.limy, fmaxf(-cam.limy, ty * iz));
+      const double j00 = cam.fx * iz, j02 = -cam.fx * xt * iz;
+      const double j11 = cam.fy * iz, j12 = -cam.fy * yt * iz;
+      // P = J T3 (rows p, r); then Sigma p, Sigma r
+      double p[3], r[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        p[c] = j00 * (double)cam.T3[c] + j02 * (double)cam.T3[6 + c];
+        r[c] = j11 * (double)cam.T3[3 + c] + j12 * (double)cam.T3[6 + c];
+      }
+      const double sp0 = sxx * p[0] + sxy * p[1] + sxz * p[2];
+      const double sp1 = sxy * p[0] + syy * p[1] + syz * p[2];
+      const double sp2 = sxz * p[0] + syz * p[1] + szz * p[2];
+      const double aa = p[0] * sp0 + p[1] * sp1 + p[2] * sp2;
+      const double b = r[0] * sp0 + r[1] * sp1 + r[2] * sp2;
+      const double cc = r[0] * (sxx * r[0] + sxy * r[1] + sxz * r[2]) +
+                        r[1] * (sxy * r[0] + syy * r[1] + syz * r[2]) +
+                        r[2] * (sxz * r[0] + syz * r[1] + szz * r[2]);
+      const double e = set.eps2d;
+      const double a = aa + e, c = cc + e;
+      const double D = a * c - b * b;
+      tiles = footprint(tx, ty, iz, w[0], w[1], w[2], (float)a, (float)b, (float)c, (float)D, o,
+                        cam, set, r0, r1, rect_lo, rect_hi, trect, dir);
+    }
+    r2.y = tz;
+    r2.z = __uint_as_float(rect_lo);
+    r2.w = __uint_as_float(rect_hi);
+    depth_keys[i] = tiles ? __float_as_uint(tz) : 0xFFFFFFFFu;
+    rects[i] = trect;
+  }
+  float v[P::S];
+  if constexpr (STAGED) {
+    const uint64_t need = ballot(tiles > 0);
+    if (need) {
+      const int i0 = blockIdx.x * kBlock + wave * 64;  // this wave's first Gaussian
+      const uint2* src = sh16 + (size_t)i0 * P::U2;
+      uint2* buf = s_sh[wave];
+#pragma unroll
+      for (int k = 0; k < P::U2; ++k) {
+        const int f = lane + 64 * k, row = f / P::U2;
+        if ((need >> row) & 1ull) buf[f] = src[f];
+      }
+      if (tiles > 0) {
+#pragma unroll
+        for (int k = 0; k < P::U2; ++k) {
+          const uint2 u = buf[lane * P::U2 + k];
+          v[4 * k] = f16_to_f32(u.x);
+          v[4 * k + 1] = f16_to_f32(u.x >> 16);
+          v[4 * k + 2] = f16_to_f32(u.y);
+          v[4 * k + 3] = f16_to_f32(u.y >> 16);
+        }
+      }
+    }
+  } else if (tiles > 0) {
+    const uint2 u = sh16[i];
+    v[0] = f16_to_f32(u.x);
+    v[1] = f16_to_f32(u.x >> 16);
+    v[2] = f16_to_f32(u.y);
+    v[3] = 0.f;
+  }
+  if (tiles > 0) {
+    float Y[16];
+    sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+    float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[0] = fmaf(v[3 * k], Y[k], acc[0]);
+      acc[1] = fmaf(v[3 * k + 1], Y[k], acc[1]);
+      acc[2] = fmaf(v[3 * k + 2], Y[k], acc[2]);
+    }
+    r1.z = fmaxf(acc[0], 0.f);
+    r1.w = fmaxf(acc[1], 0.f);
+    r2.x = fmaxf(acc[2], 0.f);
+  }
+  if (i < n) {
+    float4* dst = reinterpret_cast<float4*>(splats + i);
+    dst[0] = r0;
+    dst[1] = r1;
+    dst[2] = r2;
+  }
+  block_counts(tiles, partial);
+}
+
+}  // namespace
+
+int packed_sh_stride(int degree) {
+  switch (degree) {
+    case 0: return ShPack<0>::S;
+    case 1: return ShPack<1>::S;
+    case 2: return ShPack<2>::S;
+    case 3: return ShPack<3>::S;
+    default: return -1;
+  }
+}
+
+hipError_t launch_prepack(int n, const float* means, const float* log_scales, const float* quats,
+                          const float* logits, const float* sh, int degree, uint16_t* posop,
+                          uint16_t* cov, uint16_t* sh16, hipStream_t st) {
+  if (n > 0) {
+    trace_mark(st, "prepack");
+    const dim3 grid((n + kBlock - 1) / kBlock);
+    const float4* q4 = reinterpret_cast<const float4*>(quats);
+    uint2* po = reinterpret_cast<uint2*>(posop);
+    uint32_t* cv = reinterpret_cast<uint32_t*>(cov);
+    uint2* s16 = reinterpret_cast<uint2*>(sh16);
+#define GS_PP(D) hipLaunchKernelGGL(k_prepack<D>, grid, dim3(kBlock), 0, st, n, means, log_scales, q4, logits, sh, po, cv, s16)
+    switch (degree) {
+      case 0: GS_PP(0); break;
+      case 1: GS_PP(1); break;
+      case 2: GS_PP(2); break;
+      default: GS_PP(3); break;
+    }
+#undef GS_PP
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_packed(int n, const uint16_t* posop, const uint16_t* cov,
+                                    const uint16_t* sh16, int degree, const CamK& cam,
+                                    const SetK& set, gs_splat* splats, uint32_t* depth_keys,
+                                    uint32_t* tile_rects, uint2* partial, hipStream_t st) {
+  const int blocks = preprocess_blocks(n);
+  if (n > 0) {
+    trace_mark(st, "preprocess_packed");
+    const uint2* po = reinterpret_cast<const uint2*>(posop);
+    const uint32_t* cv = reinterpret_cast<const uint32_t*>(cov);
+    const uint2* s16 = reinterpret_cast<const uint2*>(sh16);
+    uint2* tr = reinterpret_cast<uint2*>(tile_rects);
+#define GS_PK(D) hipLaunchKernelGGL(k_preprocess_packed<D>, dim3(blocks), dim3(kBlock), 0, st, n, po, cv, s16, cam, set, splats, depth_keys, tr, partial)
+    switch (degree) {
+      case 0: GS_PK(0); break;
+      case 1: GS_PK(1); break;
+      case 2: GS_PK(2); break;
+      default: GS_PK(3); break;
+    }
+#undef GS_PK
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gs

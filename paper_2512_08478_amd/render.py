@@ -12,7 +12,7 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["GaussianParams", "Renderer", "Frame", "render", "GsRender"]
+__all__ = ["GaussianParams", "PackedParams", "Renderer", "Frame", "render", "GsRender"]
 
 
 def _p(t):
@@ -67,6 +67,27 @@ class GaussianParams:
 
 
 @dataclass
+class PackedParams:
+    """The FP16 pre-packed form (int16 tensors holding binary16 bits):
+    posop (n, 4) = mean, opacity; cov (n, 6) = upper covariance triangle;
+    sh16 (n, S) = SH coefficients padded to S halves.  Forward only."""
+    posop: torch.Tensor
+    cov: torch.Tensor
+    sh16: torch.Tensor
+    sh_degree: int
+    model: object = None
+    assets: object = None
+
+    @property
+    def n(self):
+        return int(self.posop.shape[0])
+
+    def halves(self):
+        """(posop, cov, sh16) viewed as float16."""
+        return tuple(t.view(torch.float16) for t in (self.posop, self.cov, self.sh16))
+
+
+@dataclass
 class Frame:
     """Forward outputs plus the state the backward pass re-walks."""
     image: torch.Tensor      # (H, W, 4)
@@ -109,7 +130,22 @@ class Renderer:
         return ((cam.width + s.tile_w - 1) // s.tile_w) * ((cam.height + s.tile_h - 1) // s.tile_h)
 
     # ------------------------------------------------------------ stages
-    def preprocess(self, p: GaussianParams, cam, reuse=True):
+    def prepack(self, p: GaussianParams) -> PackedParams:
+        """The FP16 pre-pack of every Gaussian (once per asset set)."""
+        lib = L.load()
+        n, S = p.n, L.packed_sh_stride(p.sh_degree)
+        dev = p.means.device
+        posop = torch.empty((n, 4), dtype=torch.int16, device=dev)
+        cov = torch.empty((n, 6), dtype=torch.int16, device=dev)
+        sh16 = torch.empty((n, S), dtype=torch.int16, device=dev)
+        st = lib.gs_prepack(n, *[_p(t) for t in p.tensors()], p.sh_degree, _p(posop), _p(cov),
+                            _p(sh16), _stream())
+        L.check(st, "gs_prepack")
+        return PackedParams(posop, cov, sh16, p.sh_degree, p.model, p.assets)
+
+    def preprocess(self, p, cam, reuse=True):
+        """Eq. 1 for every Gaussian of `p` (GaussianParams, or PackedParams
+        for the pre-packed path): (splats, depth keys, tile rects, counts)."""
         lib = L.load()
         c, s = L.make_camera(cam), self.settings
         n = p.n
@@ -119,7 +155,15 @@ class Renderer:
         counts = self._buf("counts", 8, reuse).view(torch.int32)[:2]
         ws_bytes = lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, n, 0, ctypes.byref(c), ctypes.byref(s))
         ws = self._buf("ws_pre", ws_bytes, reuse)
-        if p.assets is not None:
+        if isinstance(p, PackedParams):
+            table = p.assets if p.assets is not None else [(0, n, p.model)]
+            tab, _keep = L.asset_table(table)
+            st = lib.gs_preprocess_packed(len(table), tab, n, _p(p.posop), _p(p.cov),
+                                          _p(p.sh16), p.sh_degree, ctypes.byref(c), ctypes.byref(s),
+                                          _p(splats), _p(dkeys), _p(rects), _p(counts), _p(ws),
+                                          ws.numel(), _stream())
+            L.check(st, "gs_preprocess_packed")
+        elif p.assets is not None:
             tab, _keep = L.asset_table(p.assets)
             st = lib.gs_preprocess_assets(len(p.assets), tab, n, *[_p(t) for t in p.tensors()],
                                           p.sh_degree, ctypes.byref(c), ctypes.byref(s), _p(splats),
@@ -190,7 +234,7 @@ class Renderer:
         L.check(st, "gs_rasterize")
         return image, T, last
 
-    def forward(self, p: GaussianParams, cam, capacity=None, reuse=True, want_keys=False) -> Frame:
+    def forward(self, p, cam, capacity=None, reuse=True, want_keys=False) -> Frame:
         splats, dkeys, rects, counts = self.preprocess(p, cam, reuse)
         keys, values, ranges, flag, cap = self.sort(p.n, splats, dkeys, rects, counts, cam, capacity,
                                                     reuse, want_keys)

@@ -236,3 +236,34 @@ def test_sort_pairs32_validation(lib):
     assert sp(vout=None) == L.GS_ERR_INVALID_ARGUMENT
     assert sp(vout=ctypes.c_void_p(FAKE + 8196)) == L.GS_ERR_MISALIGNED
     assert sp(ws=0) == L.GS_ERR_WORKSPACE
+
+
+def test_packed_layout_and_validation(lib):
+    assert [lib.gs_packed_sh_stride(d) for d in range(4)] == [4, 12, 28, 48]
+    assert lib.gs_packed_sh_stride(4) == -1 and lib.gs_packed_sh_stride(-1) == -1
+    c, s = cam_1080(), L.default_settings()
+    F = ctypes.c_void_p(FAKE)
+    G = lambda k: ctypes.c_void_p(FAKE + 4096 * k)
+
+    def pp(n=8, deg=3, means=F, out=(G(1), G(2), G(3))):
+        return lib.gs_prepack(n, means, F, F, F, F, deg, *out, None)
+    assert pp(n=-1) == L.GS_ERR_INVALID_ARGUMENT
+    assert pp(deg=4) == L.GS_ERR_UNSUPPORTED
+    assert pp(means=None) == L.GS_ERR_INVALID_ARGUMENT
+    assert pp(out=(G(1), None, G(3))) == L.GS_ERR_INVALID_ARGUMENT
+    assert pp(out=(G(1), G(2), ctypes.c_void_p(FAKE + 3 * 4096 + 8))) == L.GS_ERR_MISALIGNED
+
+    tab, _keep = L.asset_table([(0, 8, None)])
+    bad_tab, _k2 = L.asset_table([(0, 7, None)])
+
+    def pk(n=8, deg=3, tab=tab, na=1, cov=G(2), ws=1 << 20, sset=s):
+        return lib.gs_preprocess_packed(na, tab, n, G(1), cov, G(3), deg, ctypes.byref(c),
+                                        ctypes.byref(sset), G(4), G(5), G(6), G(7), G(8), ws, None)
+    assert pk(deg=5) == L.GS_ERR_UNSUPPORTED
+    assert pk(n=-1) == L.GS_ERR_INVALID_ARGUMENT
+    assert pk(tab=bad_tab) == L.GS_ERR_INVALID_ARGUMENT
+    assert pk(na=0) == L.GS_ERR_INVALID_ARGUMENT
+    assert pk(cov=None) == L.GS_ERR_INVALID_ARGUMENT
+    assert pk(cov=ctypes.c_void_p(FAKE + 2 * 4096 + 4)) == L.GS_ERR_MISALIGNED
+    assert pk(ws=0) == L.GS_ERR_WORKSPACE
+    assert pk(sset=L.default_settings(tile_w=12)) == L.GS_ERR_UNSUPPORTED

@@ -1,0 +1,183 @@
+"""GPU tests of the FP16 pre-pack (Algorithm 1's Pre-pack; Section 3.4).
+
+The pre-pack against the oracle's (float64, one rounding to binary16):
+bit-exact.  The packed preprocess and the frame rendered from it against
+the oracle fed the same binary16 values (decoded exactly): records within
+the float32 tolerances of the raw path, images within 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2512_08478_amd import scenes as S
+from gpu_util import (compare_records, extra_pairs_harmless, image_check, print_case,
+                      sampled_pixels, splats_np)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_08478_amd.render import Renderer
+    return Renderer()
+
+
+def gp(scene):
+    from paper_2512_08478_amd.render import GaussianParams
+    return GaussianParams.from_scene(scene)
+
+
+def with_degree(sc, deg, seed):
+    rng = np.random.default_rng(seed)
+    K = (deg + 1) ** 2
+    sh = np.zeros((sc.n, K, 3), np.float32)
+    k0 = min(K, sc.sh.shape[1])
+    sh[:, :k0] = sc.sh[:, :k0]
+    if K > k0:
+        sh[:, k0:] = rng.normal(0, 0.2, (sc.n, K - k0, 3))
+    return S.Scene(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sh, deg, sc.model)
+
+
+def halves(t):
+    return t.cpu().numpy().view(np.float16)
+
+
+def decoded(pk, model=None):
+    """The GPU's packed values as the oracle's packed dict (binary16)."""
+    K3 = 3 * (pk.sh_degree + 1) ** 2
+    return dict(means=halves(pk.posop)[:, :3], opacity=halves(pk.posop)[:, 3],
+                cov6=halves(pk.cov), sh=halves(pk.sh16)[:, :K3].reshape(pk.n, -1, 3),
+                sh_degree=pk.sh_degree, model=model)
+
+
+def near_tie(x, h):
+    """True where float64 x lies within float64 rounding of the midpoint
+    between binary16 h and a neighbour (either answer is then correct)."""
+    x = np.asarray(x, np.float64)
+    hf = h.astype(np.float64)
+    sp = np.spacing(np.abs(h)).astype(np.float64)
+    mid = np.abs(np.abs(x) - np.abs(hf))
+    return np.abs(mid - 0.5 * sp) <= 1e-12 * np.maximum(np.abs(x), 1e-30)
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2, 3])
+def test_prepack_bitexact_vs_oracle(R, orc, deg):
+    print_case(f"prepack bit-exact, sh degree {deg}")
+    sc, _ = S.medium_scene(n=50_000 + 37)
+    sc = with_degree(sc, deg, 60 + deg)
+    pk = R.prepack(gp(sc))
+    torch.cuda.synchronize()
+    ref = orc.prepack(sc)
+    K3 = 3 * (deg + 1) ** 2
+    S16 = pk.sh16.shape[1]
+    assert S16 == (K3 + 3) // 4 * 4
+    po, cv, sh = halves(pk.posop), halves(pk.cov), halves(pk.sh16)
+    np.testing.assert_array_equal(po[:, :3].view(np.uint16), ref["means"].view(np.uint16))
+    np.testing.assert_array_equal(sh[:, :K3].view(np.uint16),
+                                  ref["sh"].reshape(sc.n, -1).view(np.uint16))
+    assert not sh[:, K3:].view(np.uint16).any()  # zero padding
+    # opacity and covariance: computed in float64, rounded once
+    Sig = orc.covariance(sc)
+    exact = Sig[:, [0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
+    logit = sc.opacity_logits.astype(np.float64)
+    o_exact = 1 / (1 + np.exp(-logit))
+    for got, want, x in ((po[:, 3], ref["opacity"], o_exact), (cv, ref["cov6"], exact)):
+        diff = got.view(np.uint16) != want.view(np.uint16)
+        tie = near_tie(x, want)
+        assert not (diff & ~tie).any(), np.argwhere(diff & ~tie)[:5]
+        print(f"differing {int(diff.sum())} (all within float64 rounding of a tie: "
+              f"{int(tie.sum())} such values)")
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_packed_records_vs_oracle(R, orc, deg):
+    print_case(f"packed preprocess records vs oracle, sh degree {deg}")
+    sc, cam = S.medium_scene(n=40_000)
+    sc = with_degree(sc, deg, 70 + deg)
+    cam = S.pinhole_camera(S.look_at((2.0, 1.0, -9.0)), 640, 480, 60.0)
+    pk = R.prepack(gp(sc))
+    splats, dkeys, rects, counts = R.preprocess(pk, cam)
+    torch.cuda.synchronize()
+    rec = splats_np(splats, sc.n)
+    ref = orc.preprocess_packed(decoded(pk), cam)
+    v = compare_records(orc, rec, ref, cam)
+    assert v.sum() > 1000
+    extra_pairs_harmless(orc, ref, rec, cam, v)
+
+
+def test_packed_model_transform_and_assets(R, orc):
+    print_case("packed preprocess, two assets with model transforms")
+    from paper_2512_08478_amd.render import GaussianParams
+    assets, cams = S.batched_scenes(seed=6, scale=0.01, n_views=1, max_wh=(480, 320),
+                                    min_wh=(160, 128))
+    cam = cams[0]
+    p = GaussianParams.concat([gp(a) for a in assets])
+    pk = R.prepack(p)
+    splats = R.preprocess(pk, cam)[0]
+    torch.cuda.synchronize()
+    rec = splats_np(splats, p.n)
+    off, refs = 0, []
+    for a in assets:
+        sub = type(pk)(pk.posop[off:off + a.n], pk.cov[off:off + a.n], pk.sh16[off:off + a.n],
+                       pk.sh_degree)
+        refs.append(orc.preprocess_packed(decoded(sub, a.model), cam))
+        off += a.n
+    ref = refs[0]
+    for r in refs[1:]:
+        ref = ref.concat(r)
+    assert any(a.model is not None for a in assets)
+    v = compare_records(orc, rec, ref, cam)
+    assert v.sum() > 100
+
+
+def test_packed_render_tiny_whole_image(R, orc):
+    print_case("packed render tiny 256x256 vs brute force")
+    sc, cam = S.tiny_scene()
+    pk = R.prepack(gp(sc))
+    fr = R.forward(pk, cam)
+    img = fr.image.cpu().numpy().reshape(-1, 4)
+    ref = orc.render_image(orc.preprocess_packed(decoded(pk), cam), cam)
+    flat = {k: v.reshape(-1, 4) if k == "rgba" else v.reshape(-1) for k, v in ref.items()}
+    e, nflag = image_check(img, flat)
+    print(f"tiny packed max err {e:.2e}, flagged {nflag}")
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 8), (32, 16, 7)])
+def test_packed_render_medium_1080p_sampled(R, orc, shape):
+    print_case(f"packed render 1M 1920x1080 sampled, tiles {shape[0]}x{shape[1]}, {shape[2]}-bit")
+    from paper_2512_08478_amd.render import Renderer
+    Rs = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2]))
+    sc, cam = S.medium_scene()
+    pk = Rs.prepack(gp(sc))
+    fr = Rs.forward(pk, cam)
+    img = fr.image.cpu().numpy()
+    pix = sampled_pixels(cam, 256, 13)
+    ref = orc.render_pixels(orc.preprocess_packed(decoded(pk), cam), cam, pix)
+    e, nflag = image_check(img[pix[:, 1], pix[:, 0]], ref)
+    # how far the binary16 inputs move the image from the float32 render
+    raw = Rs.forward(gp(sc), cam).image
+    d = (raw - fr.image).abs()
+    print(f"1M packed max err {e:.2e}, flagged {nflag}; |packed - float32 render| "
+          f"mean {d.mean().item():.2e} max {d.max().item():.2e}")
+
+
+def test_packed_empty_and_overflow(R):
+    print_case("packed: n = 0, and binary16 overflow culls")
+    from paper_2512_08478_amd.render import GaussianParams
+    sc, cam = S.tiny_scene(n=256)
+    sc.log_scales[:8] = 6.0          # s^2 = e^12 > 65504: covariance overflows to inf
+    sc.means[8:16, 0] = 1e6          # mean overflows to inf
+    pk = R.prepack(gp(sc))
+    splats, dkeys, _, counts = R.preprocess(pk, cam)
+    rec = splats_np(splats, sc.n)
+    assert np.isinf(halves(pk.cov)[:8]).any(axis=1).all()
+    assert np.isinf(halves(pk.posop)[8:16, 0]).all()
+    assert (rec["px1"][:16] < rec["px0"][:16]).all()
+    assert (dkeys[:16].cpu().numpy().view(np.uint32) == 0xFFFFFFFF).all()
+    e = GaussianParams(*[t[:0] for t in gp(sc).tensors()], sc.sh_degree)
+    pk0 = R.prepack(e)
+    assert pk0.n == 0
+    fr = R.forward(pk0, cam)
+    assert float(fr.image.abs().max()) == 0.0

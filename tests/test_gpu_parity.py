@@ -10,8 +10,8 @@ import pytest
 import torch
 
 from paper_2512_08478_amd import scenes as S
-from gpu_util import (SPLAT_DTYPE, conic_from_whitened, image_check, print_case, splats_np, u32,
-                      u64)
+from gpu_util import (compare_records, extra_pairs_harmless, image_check, print_case,
+                      sampled_pixels, splats_np, u32, u64)
 
 pytestmark = pytest.mark.gpu
 
@@ -30,51 +30,6 @@ def gp(scene):
 
 
 # ------------------------------------------------------------------ preprocess
-
-def compare_records(orc, rec, ref, cam):
-    """GPU per-Gaussian records vs oracle records (Eq. 1, colour, culls)."""
-    vis_o = ref.visible
-    vis_g = rec["tx1"] >= rec["tx0"]
-    amb = ref.i[:, orc.I_AMBIG] == 1
-    mismatch = (vis_o != vis_g) & ~amb
-    assert not mismatch.any(), np.nonzero(mismatch)[0][:10]
-    v = vis_o & vis_g
-    d = ref.d[v]
-    r = rec[v]
-    np.testing.assert_allclose(r["mx"], d[:, orc.D_MX], rtol=2e-6, atol=2e-3)
-    np.testing.assert_allclose(r["my"], d[:, orc.D_MY], rtol=2e-6, atol=2e-3)
-    np.testing.assert_allclose(r["depth"], d[:, orc.D_DEPTH], rtol=1e-6)
-    np.testing.assert_allclose(r["op"], d[:, orc.D_OPAC], rtol=2e-6)
-    np.testing.assert_allclose(np.stack([r["r"], r["g"], r["b"]], 1), d[:, orc.D_R:orc.D_B + 1], atol=2e-6)
-    con = conic_from_whitened(r)
-    ref_con = d[:, orc.D_CA:orc.D_CC + 1]
-    scale = np.abs(ref_con).max(1, keepdims=True)
-    np.testing.assert_allclose(con / scale, ref_con / scale, atol=2e-5)
-    # pixel bboxes and tile rects: the GPU's may only be larger, by pixels
-    # and tiles that hold no pixel with weight >= alpha_min
-    it = ref.i[v]
-    assert np.all(r["px0"] <= it[:, orc.I_PX0]) and np.all(r["px1"] >= it[:, orc.I_PX1])
-    assert np.all(r["py0"] <= it[:, orc.I_PY0]) and np.all(r["py1"] >= it[:, orc.I_PY1])
-    assert np.all(r["tx0"] <= it[:, orc.I_TX0]) and np.all(r["tx1"] >= it[:, orc.I_TX1])
-    assert np.all(r["ty0"] <= it[:, orc.I_TY0]) and np.all(r["ty1"] >= it[:, orc.I_TY1])
-    return v
-
-
-def extra_pairs_harmless(orc, ref, rec, cam, v):
-    tx_n = (cam.width + 15) // 16
-    gs, tiles = [], []
-    for g in np.nonzero(v)[0]:
-        a, b = rec[g], ref.i[g]
-        for ty in range(a["ty0"], a["ty1"] + 1):
-            for tx in range(a["tx0"], a["tx1"] + 1):
-                if not (b[orc.I_TX0] <= tx <= b[orc.I_TX1] and b[orc.I_TY0] <= ty <= b[orc.I_TY1]):
-                    gs.append(g)
-                    tiles.append(ty * tx_n + tx)
-    if gs:
-        w = orc.pair_max_weight(ref, cam, np.array(gs), np.array(tiles))
-        assert w.max() < (1.0 / 255.0) * (1 + 1e-5)
-    return len(gs)
-
 
 def test_preprocess_tiny(R, orc):
     print_case("preprocess tiny 4096")
@@ -283,14 +238,6 @@ def test_blend_counts_match_oracle(R, orc):
         last = fr.last.cpu().numpy()[pix[:, 1], pix[:, 0]]
         assert (got <= last).all()
         print(f"n_blend mean {got.mean():.1f}, checked {int(ok.sum())} px")
-
-
-def sampled_pixels(cam, n, seed):
-    rng = np.random.default_rng(seed)
-    pix = np.stack([rng.integers(0, cam.width, n), rng.integers(0, cam.height, n)], 1)
-    corners = np.array([[0, 0], [cam.width - 1, cam.height - 1], [cam.width // 2, cam.height // 2],
-                        [cam.width - 1, 0], [0, cam.height - 1]])
-    return np.concatenate([pix, corners]).astype(np.int32)
 
 
 @pytest.mark.parametrize("shape", [(16, 16, 8), (32, 16, 7)])
