@@ -4,7 +4,7 @@
 // Pre-pack, once per asset: the covariance Sigma = R diag(s^2) R^T is formed
 // from scale and rotation, and the mean, the activated opacity, the upper
 // triangle of Sigma and the SH coefficients are stored as binary16, two to
-// a 32-bit word.  Per frame, the packed preprocess reads 24 + 2*S bytes per
+// a 32-bit word.  Per frame, the packed preprocess reads 20 + 2*S bytes per
 // Gaussian (S halves of SH, 48 at degree 3) instead of 48 + 4*3K, and
 // writes the same records, depth keys and tile rects as the raw-parameter
 // preprocess, so sorting and compositing are shared.
@@ -114,33 +114,62 @@ __global__ __launch_bounds__(kBlock) void k_prepack(
   }
 }
 
-// Eq. 1 from the packed layout.  Each wave copies the packed SH rows of its
-// visible Gaussians into LDS with contiguous 8-byte loads (the rows of 64
-// consecutive Gaussians are one span), and each lane decodes its own row.
+// Packed SH row of Gaussian i, loaded whole: 16-byte loads when a row is a
+// whole number of 16-byte vectors (degree 3: 96 bytes), else 8-byte loads.
+template <int DEG>
+struct ShRow {
+  static constexpr int S = ShPack<DEG>::S;
+  static constexpr bool V16 = (S % 8) == 0;
+  static constexpr int WORDS = S / 2;  // 32-bit words
+  uint32_t w[WORDS];
+  __device__ __forceinline__ void load(const uint2* __restrict__ sh16, int i) {
+    if constexpr (V16) {
+      const uint4* row = reinterpret_cast<const uint4*>(sh16) + (size_t)i * (S / 8);
+#pragma unroll
+      for (int k = 0; k < S / 8; ++k) {
+        const uint4 u = row[k];
+        w[4 * k] = u.x; w[4 * k + 1] = u.y; w[4 * k + 2] = u.z; w[4 * k + 3] = u.w;
+      }
+    } else {
+      const uint2* row = sh16 + (size_t)i * (S / 4);
+#pragma unroll
+      for (int k = 0; k < S / 4; ++k) {
+        const uint2 u = row[k];
+        w[2 * k] = u.x; w[2 * k + 1] = u.y;
+      }
+    }
+  }
+  __device__ __forceinline__ float at(int e) const {
+    return f16_to_f32(e & 1 ? w[e >> 1] >> 16 : w[e >> 1]);
+  }
+};
+
+// Eq. 1 from the packed layout.  The packed SH row is loaded together with
+// the mean, opacity and covariance, before the culls: one round trip to
+// memory per Gaussian instead of two (the loads of a culled Gaussian's row
+// are wasted, which costs less than a second dependent round trip).
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_preprocess_packed(
     int n, const uint2* __restrict__ posop, const uint32_t* __restrict__ cov,
     const uint2* __restrict__ sh16, CamK cam, SetK set, gs_splat* __restrict__ splats,
     uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint2* __restrict__ partial) {
-  using P = ShPack<DEG>;
   constexpr int K = (DEG + 1) * (DEG + 1);
-  constexpr bool STAGED = DEG >= 1;
-  __shared__ uint2 s_sh[STAGED ? kBlock / 64 : 1][STAGED ? 64 * P::U2 : 1];
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
   uint32_t tiles = 0;
-  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-  uint32_t rect_lo = 0x0000FFFFu, rect_hi = 0u;  // empty pixel bbox
-  uint2 trect = make_uint2(0x0000FFFFu, 0u);      // empty tile rect
-  float dir[3] = {0.f, 0.f, 0.f};
   if (i < n) {
     const uint2 po = posop[i];
+    const uint32_t c0 = cov[3 * i], c1 = cov[3 * i + 1], c2 = cov[3 * i + 2];
+    ShRow<DEG> shr;
+    shr.load(sh16, i);
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    uint32_t rect_lo = 0x0000FFFFu, rect_hi = 0u;  // empty pixel bbox
+    uint2 trect = make_uint2(0x0000FFFFu, 0u);      // empty tile rect
+    float dir[3] = {0.f, 0.f, 0.f};
     const float o = f16_to_f32(po.y >> 16);
     float w[3], t[3];
     place_mean(f16_to_f32(po.x), f16_to_f32(po.x >> 16), f16_to_f32(po.y), cam, w, t);
     const float tx = t[0], ty = t[1], tz = t[2];
     if ((tz > cam.znear) && (o >= set.tau) && __builtin_isfinite(tx) && __builtin_isfinite(ty)) {
-      const uint32_t c0 = cov[3 * i], c1 = cov[3 * i + 1], c2 = cov[3 * i + 2];
       const double sxx = f16_to_f32(c0), sxy = f16_to_f32(c0 >> 16), sxz = f16_to_f32(c1),
                    syy = f16_to_f32(c1 >> 16), syz = f16_to_f32(c2), szz = f16_to_f32(c2 >> 16);
       // Jacobian of the perspective division at t (x/z, y/z clamped)
@@ -169,58 +198,26 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_packed(
       const double D = a * c - b * b;
       tiles = footprint(tx, ty, iz, w[0], w[1], w[2], (float)a, (float)b, (float)c, (float)D, o,
                         cam, set, r0, r1, rect_lo, rect_hi, trect, dir);
+      if (tiles) {
+        float Y[16];
+        sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+        float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          acc[0] = fmaf(shr.at(3 * k), Y[k], acc[0]);
+          acc[1] = fmaf(shr.at(3 * k + 1), Y[k], acc[1]);
+          acc[2] = fmaf(shr.at(3 * k + 2), Y[k], acc[2]);
+        }
+        r1.z = fmaxf(acc[0], 0.f);
+        r1.w = fmaxf(acc[1], 0.f);
+        r2.x = fmaxf(acc[2], 0.f);
+      }
     }
     r2.y = tz;
     r2.z = __uint_as_float(rect_lo);
     r2.w = __uint_as_float(rect_hi);
     depth_keys[i] = tiles ? __float_as_uint(tz) : 0xFFFFFFFFu;
     rects[i] = trect;
-  }
-  float v[P::S];
-  if constexpr (STAGED) {
-    const uint64_t need = ballot(tiles > 0);
-    if (need) {
-      const int i0 = blockIdx.x * kBlock + wave * 64;  // this wave's first Gaussian
-      const uint2* src = sh16 + (size_t)i0 * P::U2;
-      uint2* buf = s_sh[wave];
-#pragma unroll
-      for (int k = 0; k < P::U2; ++k) {
-        const int f = lane + 64 * k, row = f / P::U2;
-        if ((need >> row) & 1ull) buf[f] = src[f];
-      }
-      if (tiles > 0) {
-#pragma unroll
-        for (int k = 0; k < P::U2; ++k) {
-          const uint2 u = buf[lane * P::U2 + k];
-          v[4 * k] = f16_to_f32(u.x);
-          v[4 * k + 1] = f16_to_f32(u.x >> 16);
-          v[4 * k + 2] = f16_to_f32(u.y);
-          v[4 * k + 3] = f16_to_f32(u.y >> 16);
-        }
-      }
-    }
-  } else if (tiles > 0) {
-    const uint2 u = sh16[i];
-    v[0] = f16_to_f32(u.x);
-    v[1] = f16_to_f32(u.x >> 16);
-    v[2] = f16_to_f32(u.y);
-    v[3] = 0.f;
-  }
-  if (tiles > 0) {
-    float Y[16];
-    sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
-    float acc[3] = {0.5f, 0.5f, 0.5f};
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      acc[0] = fmaf(v[3 * k], Y[k], acc[0]);
-      acc[1] = fmaf(v[3 * k + 1], Y[k], acc[1]);
-      acc[2] = fmaf(v[3 * k + 2], Y[k], acc[2]);
-    }
-    r1.z = fmaxf(acc[0], 0.f);
-    r1.w = fmaxf(acc[1], 0.f);
-    r2.x = fmaxf(acc[2], 0.f);
-  }
-  if (i < n) {
     float4* dst = reinterpret_cast<float4*>(splats + i);
     dst[0] = r0;
     dst[1] = r1;
