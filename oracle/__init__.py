@@ -83,7 +83,7 @@ def _load():
         lib.orc_preprocess.argtypes = [I64, P, P, P, P, P, ctypes.c_int, P, P, P, P, P]
         lib.orc_preprocess_f64.argtypes = [I64, P, P, P, P, P, ctypes.c_int, P, P, P, P, P]
         lib.orc_preprocess_cov.argtypes = [I64, P, P, P, P, ctypes.c_int, P, P, P, P, P]
-        lib.orc_render_pixels.argtypes = [I64, P, P, P, P, I64, P, P, P, P, P, P]
+        lib.orc_render_pixels.argtypes = [I64, P, P, P, P, I64, P, P, P, P, P, P, P, P]
         lib.orc_keys.argtypes = [I64, P, P, ctypes.c_int, P, P]
         lib.orc_count_instances.argtypes = [I64, P]
         lib.orc_count_instances.restype = I64
@@ -229,9 +229,27 @@ def preprocess_many(scenes, cam, settings=None, f64_inputs=False) -> Records:
     return recs
 
 
-def render_pixels(recs: Records, cam, pix, settings=None):
+def mesh_at(mesh, pix):
+    """(depth (P,), rgb (P,3) or None) of a mesh prepass dict
+    {depth: (H,W), rgb: (H,W,3) or None} at pixels (P,2) of x, y."""
+    if mesh is None:
+        return None, None
+    pix = np.asarray(pix).reshape(-1, 2)
+    md = mesh.get("depth")
+    mr = mesh.get("rgb")
+    d = None if md is None else np.ascontiguousarray(
+        np.asarray(md, np.float64)[pix[:, 1], pix[:, 0]])
+    r = None if mr is None else np.ascontiguousarray(
+        np.asarray(mr, np.float64)[pix[:, 1], pix[:, 0]].reshape(-1, 3))
+    return d, r
+
+
+def render_pixels(recs: Records, cam, pix, settings=None, mesh=None):
     """Eq. 3 by brute force at the given pixels (int array (P,2) of x, y).
 
+    ``mesh``: optional mesh prepass {depth: (H,W) camera-space z, +inf where
+    no mesh; rgb: (H,W,3) or None}: Gaussians deeper than the mesh are
+    hidden and the mesh colour replaces the background (Section 3.4).
     Returns dict(rgba (P,4), T (P,), n_blend (P,), margin (P,), flags (P,))."""
     lib = _load()
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
@@ -239,8 +257,9 @@ def render_pixels(recs: Records, cam, pix, settings=None):
     out = dict(rgba=np.zeros((P, 4)), T=np.zeros(P), n_blend=np.zeros(P, np.int32),
                margin=np.zeros(P), flags=np.zeros(P, np.int32))
     ca, sa = cam_array(cam), set_array(settings)
+    md, mr = mesh_at(mesh, pix)
     lib.orc_render_pixels(recs.n, _p(recs.d), _p(recs.i), _p(ca), _p(sa), P, _p(pix),
-                          _p(out["rgba"]), _p(out["T"]), _p(out["n_blend"]),
+                          _p(md), _p(mr), _p(out["rgba"]), _p(out["T"]), _p(out["n_blend"]),
                           _p(out["margin"]), _p(out["flags"]))
     return out
 
@@ -250,9 +269,9 @@ def all_pixels(cam) -> np.ndarray:
     return np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
 
 
-def render_image(recs: Records, cam, settings=None):
+def render_image(recs: Records, cam, settings=None, mesh=None):
     """Full image (H,W,4) plus T, n_blend, margin, flags as (H,W) maps."""
-    o = render_pixels(recs, cam, all_pixels(cam), settings)
+    o = render_pixels(recs, cam, all_pixels(cam), settings, mesh)
     H, W = cam.height, cam.width
     return dict(rgba=o["rgba"].reshape(H, W, 4), T=o["T"].reshape(H, W),
                 n_blend=o["n_blend"].reshape(H, W), margin=o["margin"].reshape(H, W),

@@ -143,23 +143,30 @@ def scene_tensors(scene, requires_grad=True):
             f(scene.sh)]
 
 
-def render_and_grad(scene, cam, pix, dL_drgba, settings=None, chunk=64):
+def render_and_grad(scene, cam, pix, dL_drgba, settings=None, chunk=64, mesh=None):
     """rgba at ``pix`` (P,4) and d(sum dL_drgba * rgba)/d(inputs).
 
     Returns (rgba numpy (P,4), dict of float64 numpy gradients with keys
     means, log_scales, quats, opacity_logits, sh)."""
-    rgba, grads = render_and_grad_assets([scene], cam, pix, dL_drgba, settings, chunk)
+    rgba, grads = render_and_grad_assets([scene], cam, pix, dL_drgba, settings, chunk, mesh)
     return rgba, grads[0]
 
 
-def render_and_grad_assets(scenes, cam, pix, dL_drgba, settings=None, chunk=64):
+def render_and_grad_assets(scenes, cam, pix, dL_drgba, settings=None, chunk=64, mesh=None):
     """As render_and_grad for several assets rendered together: every asset
     is projected with its own model transform and all visible Gaussians are
     composited in one global (depth, global index) order, the global index
     running over the assets in list order (Algorithm 1's single sort over
-    all models).  Returns (rgba (P,4), [gradient dict per asset])."""
+    all models).  ``mesh`` ({depth: (H,W), rgb: (H,W,3) or None}) hides the
+    Gaussians deeper than the mesh at each pixel and puts the mesh colour
+    behind the rest (Section 3.4); the mesh itself is not differentiated.
+    Returns (rgba (P,4), [gradient dict per asset])."""
+    from . import mesh_at
     st = _settings(settings)
     pix = np.asarray(pix, np.int64).reshape(-1, 2)
+    md, mr = mesh_at(mesh, pix)
+    if md is None:
+        md = np.full(len(pix), np.inf)
     G = torch.as_tensor(np.asarray(dL_drgba, np.float64).reshape(-1, 4), dtype=_F)
     params = [scene_tensors(sc) for sc in scenes]
     offs = np.cumsum([0] + [sc.n for sc in scenes])
@@ -174,7 +181,10 @@ def render_and_grad_assets(scenes, cam, pix, dL_drgba, settings=None, chunk=64):
         used = np.zeros(len(order), bool)
         for s0 in range(0, len(pix), chunk):
             pp = torch.as_tensor(pix[s0:s0 + chunk] + 0.5, dtype=_F)
-            m = _blend_masks(_weights(pord, pp[:, 0], pp[:, 1]), st)
+            # in front of (or at) the mesh; in depth order, so the first
+            # hidden Gaussian hides every later one
+            front = pord["depth"][None, :] <= torch.as_tensor(md[s0:s0 + chunk], dtype=_F)[:, None]
+            m = _blend_masks(_weights(pord, pp[:, 0], pp[:, 1]) * front, st)
             masks.append(m)
             used |= m.any(0).numpy()
         cols = np.nonzero(used)[0]
@@ -204,8 +214,11 @@ def render_and_grad_assets(scenes, cam, pix, dL_drgba, settings=None, chunk=64):
     Tb = torch.cat([torch.ones((len(pix), 1), dtype=_F), torch.cumprod(one_m, 1)[:, :-1]], 1)
     C = torch.einsum("pn,nc->pc", a * Tb, q["rgb"])
     Tf = torch.prod(one_m, 1)
-    bg = torch.as_tensor(np.asarray(st["bg"], np.float64), dtype=_F)
-    rgba = torch.cat([C + Tf[:, None] * bg[None], (1.0 - Tf)[:, None]], 1)
+    if mr is None:
+        bg = torch.as_tensor(np.asarray(st["bg"], np.float64), dtype=_F)[None]
+    else:
+        bg = torch.as_tensor(mr, dtype=_F)
+    rgba = torch.cat([C + Tf[:, None] * bg, (1.0 - Tf)[:, None]], 1)
     L = (G * rgba).sum()
     flat = [t for ts in params for t in ts]
     grads = torch.autograd.grad(L, flat, allow_unused=True) if L.requires_grad else [None] * len(flat)

@@ -455,11 +455,21 @@ int orc_preprocess_cov(int64_t n, const double* means, const double* opac, const
 // Gaussians, the smallest relative margin to any discrete decision taken
 // (pixel skip alpha<tau, clamp at alpha_max, stop at T<t_eps), and flags:
 //   1 = two blended Gaussians closer in depth than a relative 1e-6;
-//   2 = a Gaussian culled within a relative 1e-5 of a threshold covers it.
+//   2 = a Gaussian culled within a relative 1e-5 of a threshold covers it;
+//   4 = a Gaussian with weight >= tau lies within a relative 1e-5 of the
+//       mesh depth.
+// Mesh depth composition (Algorithm 1, DrawSplatsWithMeshDepth; Section
+// 3.4): with mesh_depth (one value per requested pixel, camera-space z of
+// the mesh surface; +inf where there is none), a Gaussian whose depth is
+// greater than the pixel's mesh depth is hidden by the mesh, and so is
+// every Gaussian after it in depth order; mesh_rgb (three values per
+// pixel) replaces the background colour behind the Gaussians.  Either may
+// be NULL.
 int orc_render_pixels(int64_t n, const double* rec_d, const int32_t* rec_i,
                       const double* cam_in, const double* set_in, int64_t npix,
-                      const int32_t* pix, double* rgba, double* T_out,
-                      int32_t* n_blend, double* margin, int32_t* flags) {
+                      const int32_t* pix, const double* mesh_depth, const double* mesh_rgb,
+                      double* rgba, double* T_out, int32_t* n_blend, double* margin,
+                      int32_t* flags) {
   const Cam cam = load_cam(cam_in);
   const Set set = load_set(set_in);
   std::vector<int64_t> order;
@@ -481,9 +491,13 @@ int orc_render_pixels(int64_t n, const double* rec_d, const int32_t* rec_i,
     double C[3] = {0, 0, 0}, T = 1.0, mrg = std::numeric_limits<double>::infinity();
     int32_t nb = 0, fl = 0;
     double last_depth = -1.0;
+    const double D = mesh_depth ? mesh_depth[p] : std::numeric_limits<double>::infinity();
     for (int64_t idx : order) {
       const double* d = rec_d + (size_t)idx * REC_D;
       const double g = pixel_weight(d, px, py);
+      if (std::isfinite(D) && g >= set.tau && std::fabs(d[D_DEPTH] - D) <= 1e-5 * std::fabs(D))
+        fl |= 4;
+      if (d[D_DEPTH] > D) break;  // hidden by the mesh, as is everything behind
       mrg = std::min(mrg, std::fabs(g - set.tau) / set.tau);
       if (g < set.tau) continue;
       mrg = std::min(mrg, std::fabs(g - set.amax) / set.amax);
@@ -503,7 +517,8 @@ int orc_render_pixels(int64_t n, const double* rec_d, const int32_t* rec_i,
         mrg = 0.0;
       }
     }
-    for (int c = 0; c < 3; ++c) rgba[4 * p + c] = C[c] + T * set.bg[c];
+    for (int c = 0; c < 3; ++c)
+      rgba[4 * p + c] = C[c] + T * (mesh_rgb ? mesh_rgb[3 * p + c] : set.bg[c]);
     rgba[4 * p + 3] = 1.0 - T;
     T_out[p] = T;
     n_blend[p] = nb;

@@ -288,6 +288,43 @@ SORT_KEY_KINDS = ("random64", "random45", "all_equal", "sorted", "reversed",
                   "two_unique", "tile_runs", "depth_like")
 
 
+def plane_mesh(cam: Camera, normal, offset, seed=0, cell=0.5, occupancy=1.0):
+    """A mesh prepass stand-in: the per-pixel camera-space depth and colour
+    of the world plane {X : normal . X = offset} seen through `cam` (pixel
+    centres at +1/2), as float32 (H,W) depth (+inf where the ray misses the
+    plane, or where a cell of the plane is left out) and (H,W,3) colour (a
+    seeded random colour per `cell`-sized square of the plane).  With
+    occupancy < 1 only that fraction of the cells is present (a wall with
+    holes)."""
+    rng = np.random.default_rng(seed)
+    n = np.asarray(normal, np.float64)
+    n = n / np.linalg.norm(n)
+    V = np.asarray(cam.viewmat, np.float64).reshape(4, 4)
+    Rv, tv = V[:3, :3], V[:3, 3]
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    dc = np.stack([(xs + 0.5 - cam.cx) / cam.fx, (ys + 0.5 - cam.cy) / cam.fy,
+                   np.ones(xs.shape)], -1)                       # camera-space ray, z = 1
+    nw = Rv @ n                                                  # plane normal in camera space
+    h = offset + n @ (Rv.T @ tv)                                 # plane: nw . x_c = h
+    den = dc @ nw
+    with np.errstate(divide="ignore", invalid="ignore"):
+        z = np.where(np.abs(den) > 1e-12, h / den, np.inf)
+    z = np.where(z > 0, z, np.inf)
+    Xw = (np.where(np.isfinite(z), z, 0.0)[..., None] * dc - tv) @ Rv   # world points
+    # two in-plane axes for the cell pattern
+    a = np.cross(n, [0.0, 0.0, 1.0] if abs(n[2]) < 0.9 else [1.0, 0.0, 0.0])
+    a /= np.linalg.norm(a)
+    b = np.cross(n, a)
+    ci = np.floor(Xw @ a / cell).astype(np.int64)
+    cj = np.floor(Xw @ b / cell).astype(np.int64)
+    palette = rng.uniform(0.0, 1.0, (64, 3))
+    keep = rng.uniform(0.0, 1.0, 64) < occupancy
+    cid = (ci * 7 + cj * 13) % 64
+    z = np.where(keep[cid], z, np.inf)
+    rgb = np.where(np.isfinite(z)[..., None], palette[cid], 0.0)
+    return dict(depth=z.astype(np.float32), rgb=rgb.astype(np.float32))
+
+
 def sort_keys(kind: str, n: int, seed: int = 0, key_bits: int = 64):
     """Adversarial (keys uint64, values uint32) sets for the radix sort.
 

@@ -147,3 +147,60 @@ def test_multi_asset_gradients_match_central_differences(orc):
             ad = g_ad[a][nm].reshape(-1)[idx]
             scale = max(np.abs(fd).max(), 1e-12)
             np.testing.assert_allclose(ad, fd, rtol=1e-5, atol=1e-6 * scale, err_msg=f"asset {a} {nm}")
+
+
+def test_mesh_autograd_forward_matches_c_forward(orc):
+    from oracle import grad as og
+    sc, cam = S.tiny_scene(n=512)
+    mesh = S.plane_mesh(cam, (0.3, 0.2, 1.0), 0.1, seed=2, occupancy=0.6)
+    pix = orc.all_pixels(cam)[::53]
+    G = np.zeros((len(pix), 4))
+    rgba, _ = og.render_and_grad(sc, cam, pix, G, mesh=mesh)
+    ref = orc.render_pixels(orc.preprocess(sc, cam), cam, pix, mesh=mesh)
+    np.testing.assert_allclose(rgba, ref["rgba"], atol=1e-12)
+    plain = orc.render_pixels(orc.preprocess(sc, cam), cam, pix)
+    assert (ref["n_blend"] < plain["n_blend"]).sum() > 10   # the wall hides something
+
+
+def test_mesh_gradients_match_central_differences(orc):
+    from oracle import grad as og
+    sc, cam = S.fd_scene()
+    sc = _f64(sc)
+    pix = orc.all_pixels(cam)
+    r0 = orc.preprocess(sc, cam, f64_inputs=True)
+    depth = r0.d[r0.visible, orc.D_DEPTH]
+    mesh = S.plane_mesh(cam, (0.2, -0.1, 1.0), 0.0, seed=9, occupancy=0.7)
+    # move the wall into the middle of the Gaussians' depth range
+    fin = np.isfinite(mesh["depth"])
+    mesh["depth"][fin] += np.float32(np.median(depth) - np.median(mesh["depth"][fin]))
+    base = orc.render_pixels(r0, cam, pix, mesh=mesh)
+    plain = orc.render_pixels(r0, cam, pix)
+    assert (base["n_blend"] < plain["n_blend"]).sum() > 20
+    rng = np.random.default_rng(22)
+    G = rng.standard_normal((len(pix), 4))
+    safe = (base["margin"] > 1e-3) & (base["flags"] == 0)
+    G[~safe] = 0.0
+    assert safe.mean() > 0.9
+    _, g_ad = og.render_and_grad(sc, cam, pix, G, mesh=mesh)
+
+    def loss(s):
+        out = orc.render_pixels(orc.preprocess(s, cam, f64_inputs=True), cam, pix, mesh=mesh)
+        return float((out["rgba"] * G).sum())
+    h = 1e-6
+    for nm in ["means", "log_scales", "opacity_logits", "sh"]:
+        arr = getattr(sc, nm)
+        flat = arr.reshape(-1)
+        idx = rng.choice(flat.size, min(flat.size, 120), replace=False)
+        fd = np.zeros(len(idx))
+        for j, k in enumerate(idx):
+            v = flat[k]
+            flat[k] = v + h
+            lp = loss(sc)
+            flat[k] = v - h
+            lm = loss(sc)
+            flat[k] = v
+            fd[j] = (lp - lm) / (2 * h)
+        ad = g_ad[nm].reshape(-1)[idx]
+        scale = np.abs(fd).max()
+        assert scale > 0, nm
+        np.testing.assert_allclose(ad, fd, rtol=1e-5, atol=1e-6 * scale, err_msg=nm)

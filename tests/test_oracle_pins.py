@@ -484,3 +484,83 @@ def test_prepack_fields(orc):
     assert np.all(np.abs(o - 1 / (1 + np.exp(-logit))) <= 0.5 * np.spacing(p["opacity"]).astype(np.float64))
     np.testing.assert_array_equal(p["means"], sc.means.astype(np.float32).astype(np.float16))
     np.testing.assert_array_equal(p["sh"], sc.sh.astype(np.float32).astype(np.float16))
+
+
+# ---------------------------------------------------------------- mesh depth composition (Section 3.4)
+
+def _const_mesh(cam, depth, seed=3):
+    rng = np.random.default_rng(seed)
+    return dict(depth=np.full((cam.height, cam.width), depth, np.float32),
+                rgb=rng.uniform(0, 1, (cam.height, cam.width, 3)).astype(np.float32))
+
+
+def test_mesh_wall_behind_everything_is_a_background(orc):
+    # A wall behind every Gaussian hides nothing: the image is the plain one
+    # with the wall's colour in place of the background, C + T * rgb_mesh.
+    sc, cam = S.tiny_scene(n=1024)
+    r = orc.preprocess(sc, cam)
+    pix = orc.all_pixels(cam)[::7]
+    plain = orc.render_pixels(r, cam, pix)
+    mesh = _const_mesh(cam, 1e4)
+    m = orc.render_pixels(r, cam, pix, mesh=mesh)
+    rgb = mesh["rgb"][pix[:, 1], pix[:, 0]].astype(np.float64)
+    np.testing.assert_array_equal(m["T"], plain["T"])
+    np.testing.assert_array_equal(m["n_blend"], plain["n_blend"])
+    np.testing.assert_allclose(m["rgba"][:, :3], plain["rgba"][:, :3] + plain["T"][:, None] * rgb,
+                               atol=1e-15)
+    np.testing.assert_array_equal(m["rgba"][:, 3], plain["rgba"][:, 3])
+    assert plain["n_blend"].max() > 0
+
+
+def test_mesh_wall_in_front_hides_everything(orc):
+    sc, cam = S.tiny_scene(n=1024)
+    r = orc.preprocess(sc, cam)
+    pix = orc.all_pixels(cam)[::5]
+    mesh = _const_mesh(cam, 0.1)   # nearer than the near plane: every Gaussian is behind
+    m = orc.render_pixels(r, cam, pix, mesh=mesh)
+    np.testing.assert_array_equal(m["n_blend"], 0)
+    np.testing.assert_array_equal(m["T"], 1.0)
+    np.testing.assert_array_equal(m["rgba"][:, :3], mesh["rgb"][pix[:, 1], pix[:, 0]].astype(np.float64))
+    np.testing.assert_array_equal(m["rgba"][:, 3], 0.0)
+
+
+def test_mesh_wall_between_two_gaussians(orc):
+    # The two-Gaussian scene of P4 (depths 2 and 4) with a wall at depth 3:
+    # only the near Gaussian is composited, over the wall's colour.
+    l = np.float32(math.log(0.08))
+    sc = one_scene([[0, 0, 4.0], [0, 0, 2.0]], l, [0.5, 2.0], [[1.0, 0, 0], [0, 1.0, 0]])
+    cam = axis_camera(16, 16, 30.0)
+    r = orc.preprocess(sc, cam)
+    o_near = 1 / (1 + math.exp(-2.0))
+    sig = float(np.exp(np.float64(l)))
+    s2 = (cam.fx * sig / 2.0) ** 2 + 0.3
+    c_near = np.array([0, 1.0, 0]) / (2 * math.sqrt(math.pi)) + 0.5
+    pts = [[8, 8], [9, 7], [3, 12]]
+    for D in (3.0, 2.0):   # D = 2 exactly: a Gaussian at the mesh depth is kept
+        mesh = _const_mesh(cam, D, seed=4)
+        out = orc.render_pixels(r, cam, pts, mesh=mesh)
+        for p, (x, y) in enumerate(pts):
+            a = closed_form_weight(cam, 8, 8, s2, o_near, x, y)
+            a = a if a >= TAU else 0.0
+            wall = mesh["rgb"][y, x].astype(np.float64)
+            np.testing.assert_allclose(out["rgba"][p, :3], c_near * a + wall * (1 - a), atol=1e-13)
+            np.testing.assert_allclose(out["T"][p], 1 - a, atol=1e-13)
+            assert out["n_blend"][p] == (1 if a > 0 else 0)
+            # a blended Gaussian exactly at the mesh depth is flagged
+            assert bool(out["flags"][p] & 4) == (D == 2.0 and a > 0)
+
+
+def test_plane_mesh_depth_is_the_ray_plane_intersection(orc):
+    # the input generator's wall: at each pixel, the camera-space point
+    # z * ((x + 1/2 - cx)/fx, (y + 1/2 - cy)/fy, 1) lies on the world plane
+    sc, cam = S.tiny_scene(n=4)
+    n, h = np.array([0.3, 0.2, 1.0]), 0.2
+    m = S.plane_mesh(cam, n, h)
+    V = cam.viewmat.astype(np.float64)
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    z = m["depth"].astype(np.float64)
+    ok = np.isfinite(z)
+    assert ok.mean() > 0.5
+    xc = np.stack([(xs + 0.5 - cam.cx) / cam.fx * z, (ys + 0.5 - cam.cy) / cam.fy * z, z], -1)[ok]
+    Xw = (xc - V[:3, 3]) @ V[:3, :3]
+    np.testing.assert_allclose(Xw @ (n / np.linalg.norm(n)), h, atol=1e-5)
