@@ -36,13 +36,15 @@ SORT_KERNELS = ("sort_init", "radix_hist", "depth_pass", "kg_count", "kg_scan", 
                 "tile_pass", "tile_ranges")
 HBM_KERNELS = ("preprocess", "preprocess_packed", "depth_pass", "keygen", "kg_count", "tile_pass",
                "tile_ranges", "preprocess_bwd")
-ALU_KERNELS = ("raster", "raster_bwd")
+ALU_KERNELS = ("raster", "raster_mesh", "raster_bwd")
 
 WORKLOADS = {
     "tiny": "tiny: 4,096 Gaussians, SH degree 0, 256x256, forward",
     "medium": "medium: 1,000,000 Gaussians (64 clusters in [-5,5]^3), SH degree 3, 1920x1080, forward",
     "large": "large: 6,000,000 Gaussians (64 clusters in [-20,20]^3), SH degree 3, 1920x1080 eye inside, forward",
     "diff": "diff: 500,000 Gaussians, SH degree 3, 800x800, forward+backward (L1)",
+    "mesh": "mesh: the medium scene composited with a mesh prepass (a plane through the "
+            "scene centre facing the camera, 40% of its cells left out), forward",
     "sort32": "sort32: depth-only global sort of the 32-bit depth keys (culled = largest key) of "
               "the 6M-generator scene at 0.758/1.515/3.031/6.062 M Gaussians, 1920x1080 camera "
               "inside the cloud",
@@ -82,7 +84,18 @@ def make_workload(name):
         return S.large_scene()
     if name == "diff":
         return S.diff_scene()
+    if name == "mesh":
+        return S.medium_scene()
     raise ValueError(name)
+
+
+def make_mesh(cam):
+    """The mesh workload's prepass: a plane through the origin, roughly
+    facing the camera, with holes."""
+    import numpy as np
+    from paper_2512_08478_amd import scenes as S
+    fwd = np.asarray(cam.viewmat, np.float64)[2, :3]
+    return S.plane_mesh(cam, fwd + np.array([0.1, 0.3, 0.0]), 0.0, seed=8, occupancy=0.6)
 
 
 def packed_sh_halves(K):
@@ -147,8 +160,9 @@ def main():
     from paper_2512_08478_amd import _lib as L
     from paper_2512_08478_amd.render import GaussianParams, Renderer
 
-    if args.packed and args.workload not in ("tiny", "medium", "large"):
-        print(json.dumps({"error": "--packed applies to the forward workloads tiny, medium, large"}))
+    if args.packed and args.workload not in ("tiny", "medium", "large", "mesh"):
+        print(json.dumps({"error": "--packed applies to the forward workloads tiny, medium, large, "
+                                   "mesh"}))
         sys.exit(2)
     if args.workload == "batched":
         return run_batched(args)
@@ -167,6 +181,7 @@ def main():
         p = Renderer().prepack(p)
         torch.cuda.synchronize()
     backward = args.workload == "diff"
+    mesh = make_mesh(cam) if args.workload == "mesh" else None
     H, W = cam.height, cam.width
     target = None
     if backward:
@@ -176,7 +191,7 @@ def main():
     if args.tile == "auto":
         from paper_2512_08478_amd.batch import autotune_view
         best, table = autotune_view(p, cam, backward=backward, target=target,
-                                    base_settings=dict(sort_mode=args.sort_mode))
+                                    base_settings=dict(sort_mode=args.sort_mode), mesh=mesh)
         tw, th, bits = best["tile_w"], best["tile_h"], best["radix_bits"]
         tuned = [[f"{t[0]['tile_w']}x{t[0]['tile_h']}/{t[0]['radix_bits']}b",
                   round(t[1] * 1e3, 4)] for t in table]
@@ -187,13 +202,14 @@ def main():
     R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=args.sort_mode))
 
     # first frame: read the instance count once to size the sort buffers
-    fr = R.forward(p, cam)
+    fr = R.forward(p, cam, mesh=mesh)
     torch.cuda.synchronize()
     inst = fr.capacity
+    mesh = fr.mesh   # device buffers, uploaded once
     capacity = inst
 
     def step():
-        f = R.forward(p, cam, capacity=capacity)
+        f = R.forward(p, cam, capacity=capacity, mesh=mesh)
         if backward:
             # L1 loss gradient w.r.t. RGB (the caller's loss, not part of the method)
             G = torch.zeros((H, W, 4), device="cuda")
@@ -231,7 +247,7 @@ def main():
 
     # composited (pixel, Gaussian) pairs of this frame, for the compositing roofline
     nbl = torch.empty((H, W), dtype=torch.int32, device="cuda")
-    R.rasterize(f.splats, f.values, f.ranges, cam, n_blend=nbl)
+    R.rasterize(f.splats, f.values, f.ranges, cam, n_blend=nbl, mesh=f.mesh)
     blends = int(nbl.sum(dtype=torch.int64).item())
     del nbl
 
@@ -252,7 +268,8 @@ def main():
         stages[k] = e
     # compositing: blended pairs x FLOPS_PER_BLEND (the backward revisits
     # every blended pair once more, with roughly twice the arithmetic)
-    flops = {"raster": blends * FLOPS_PER_BLEND, "raster_bwd": blends * 2 * FLOPS_PER_BLEND}
+    flops = {"raster": blends * FLOPS_PER_BLEND, "raster_mesh": blends * FLOPS_PER_BLEND,
+             "raster_bwd": blends * 2 * FLOPS_PER_BLEND}
     for k in ALU_KERNELS:
         if k in stages:
             tf = flops[k] / (kern_avg[k] * 1e-3) / 1e12
@@ -303,7 +320,8 @@ def main():
         out["autotune_ms_per_frame"] = tuned
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels, packed=args.packed)
+        out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels, packed=args.packed,
+                                           mesh=make_mesh(cam) if args.workload == "mesh" else None)
     print(json.dumps(out), flush=True)
 
 
@@ -479,7 +497,7 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(sc, cam, n_pix, scale_pixels=None, packed=False):
+def cpu_baseline(sc, cam, n_pix, scale_pixels=None, packed=False, mesh=None):
     """The FP64 oracle, as it stands, on a bounded sample of the same frame:
     preprocess of every Gaussian + brute-force compositing of n_pix random
     pixels, scaled to a whole frame.  With `packed`, the oracle pre-packs
@@ -500,7 +518,7 @@ def cpu_baseline(sc, cam, n_pix, scale_pixels=None, packed=False):
     t1 = time.perf_counter()
     rng = np.random.default_rng(123)
     pix = np.stack([rng.integers(0, cam.width, n_pix), rng.integers(0, cam.height, n_pix)], 1)
-    oracle.render_pixels(rec, cam, pix)
+    oracle.render_pixels(rec, cam, pix, mesh=mesh)
     t2 = time.perf_counter()
     if scale_pixels is None:
         frame_s = (t1 - t0) + (t2 - t1) * (cam.width * cam.height) / n_pix

@@ -348,6 +348,27 @@ int32_t gs_rasterize(const gs_splat* splats, const uint32_t* values,
                      uint32_t* last, uint32_t* n_blend, void* stream);
 
 /*
+ * gs_rasterize_mesh -- gs_rasterize composited with a mesh prepass
+ * (Algorithm 1, RenderMeshDepthPrepass / DrawSplatsWithMeshDepth; Section
+ * 3.4: depth test on, depth write off).  mesh_depth[H*W] (device float32,
+ * may be NULL) is the camera-space z of the mesh surface at each pixel
+ * centre (+inf where there is none); a splat whose depth is greater than
+ * it is hidden at that pixel, and since the list is in depth order the
+ * pixel stops there.  A splat exactly at the mesh depth is drawn.
+ * mesh_rgb[H*W*3] (device float32, may be NULL) is the mesh colour, used
+ * in place of the background behind the Gaussians:
+ *   RGB = C + T_final * mesh_rgb,  A = 1 - T_final (the Gaussians' cover).
+ * With both NULL this is gs_rasterize.  `last` counts only splats in
+ * front of the mesh, so the backward pass needs no depth buffer, only the
+ * colour: gs_rasterize_backward_2d_mesh.
+ */
+int32_t gs_rasterize_mesh(const gs_splat* splats, const uint32_t* values,
+                          const uint32_t* tile_ranges, const gs_camera* cam,
+                          const gs_settings* set, const float* mesh_depth,
+                          const float* mesh_rgb, float* image, float* T_final, uint32_t* last,
+                          uint32_t* n_blend, void* stream);
+
+/*
  * gs_rasterize_backward -- gradients of a loss L through Eqs. 1-3
  * (Section 3.2: the formulation is differentiable) for the same inputs and
  * forward outputs, given dL_dimage[H*W*4] (RGBA).
@@ -403,6 +424,19 @@ int32_t gs_rasterize_backward_2d(const gs_splat* splats, const uint32_t* values,
                                  const gs_settings* set, const float* T_final,
                                  const uint32_t* last, const float* dL_dimage, int64_t n,
                                  float* grad2d, void* stream);
+
+/*
+ * gs_rasterize_backward_2d_mesh -- gs_rasterize_backward_2d for a frame made
+ * by gs_rasterize_mesh: mesh_rgb (the same buffer, or NULL) is the colour
+ * behind the Gaussians at each pixel.  Hidden splats lie past each pixel's
+ * `last` and receive no gradient; the mesh itself is not differentiated.
+ */
+int32_t gs_rasterize_backward_2d_mesh(const gs_splat* splats, const uint32_t* values,
+                                      const uint32_t* tile_ranges, const gs_camera* cam,
+                                      const gs_settings* set, const float* mesh_rgb,
+                                      const float* T_final, const uint32_t* last,
+                                      const float* dL_dimage, int64_t n, float* grad2d,
+                                      void* stream);
 
 /*
  * gs_preprocess_backward_views -- the chain rule of gs_rasterize_backward

@@ -193,21 +193,22 @@ def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
 
 
 def autotune_view(params: GaussianParams, cam, backward=False, target=None, reps=3,
-                  tiles=TILE_SHAPES, bits=RADIX_BITS, base_settings=None, log=None):
+                  tiles=TILE_SHAPES, bits=RADIX_BITS, base_settings=None, log=None, mesh=None):
     """Tile shape, then digit width, for one view (forward, or forward +
-    backward with an L1 loss against `target`), by the wall time of `reps`
-    frames each after one warm-up frame.  Returns (settings dict, table)."""
+    backward with an L1 loss against `target`; composited with `mesh` if
+    given), by the wall time of `reps` frames each after one warm-up
+    frame.  Returns (settings dict, table)."""
     base = dict(base_settings or {})
     table = []
 
     def measure(over):
         R = Renderer(dict(base, **over))
-        fr = R.forward(params, cam)
+        fr = R.forward(params, cam, mesh=mesh)
         torch.cuda.synchronize()
-        cap = fr.capacity
+        cap, m = fr.capacity, fr.mesh
 
         def frame():
-            f = R.forward(params, cam, capacity=cap)
+            f = R.forward(params, cam, capacity=cap, mesh=m)
             if backward:
                 R.backward(params, cam, f, l1_grad(f.image, target))
         frame()

@@ -567,23 +567,33 @@ int32_t gs_sort_pairs32(int64_t n, const uint32_t* keys_in, const uint32_t* valu
   return GS_OK;
 }
 
-int32_t gs_rasterize(const gs_splat* splats, const uint32_t* values, const uint32_t* tile_ranges,
-                     const gs_camera* cam, const gs_settings* set, float* image, float* T_final,
-                     uint32_t* last, uint32_t* n_blend, void* stream) {
+int32_t gs_rasterize_mesh(const gs_splat* splats, const uint32_t* values,
+                          const uint32_t* tile_ranges, const gs_camera* cam,
+                          const gs_settings* set, const float* mesh_depth,
+                          const float* mesh_rgb, float* image, float* T_final, uint32_t* last,
+                          uint32_t* n_blend, void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if ((r = check_dev(splats, false)) || (r = check_dev(values, false)) ||
       (r = check_dev(tile_ranges)) || (r = check_dev(image)) || (r = check_dev(T_final)) ||
-      (r = check_dev(last)) || (n_blend && (r = check_dev(n_blend))))
+      (r = check_dev(last)) || (n_blend && (r = check_dev(n_blend))) ||
+      (r = check_dev(mesh_depth, false)) || (r = check_dev(mesh_rgb, false)))
     return r;
   const gs::SetK sk = make_setk(cam, set);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  gs::trace_mark(st, "raster");
+  gs::trace_mark(st, mesh_depth ? "raster_mesh" : "raster");
   hipError_t e = gs::launch_rasterize(splats, values, tile_ranges, sk, cam->width, cam->height,
-                                      image, T_final, last, n_blend, st);
+                                      mesh_depth, mesh_rgb, image, T_final, last, n_blend, st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;
+}
+
+int32_t gs_rasterize(const gs_splat* splats, const uint32_t* values, const uint32_t* tile_ranges,
+                     const gs_camera* cam, const gs_settings* set, float* image, float* T_final,
+                     uint32_t* last, uint32_t* n_blend, void* stream) {
+  return gs_rasterize_mesh(splats, values, tile_ranges, cam, set, nullptr, nullptr, image,
+                           T_final, last, n_blend, stream);
 }
 
 int32_t gs_rasterize_backward_assets(
@@ -622,7 +632,7 @@ int32_t gs_rasterize_backward_assets(
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "raster_bwd");
   e = gs::launch_rasterize_backward(splats, values, tile_ranges, sk, cam->width, cam->height,
-                                    T_final, last, dL_dimage, grad2d, st);
+                                    nullptr, T_final, last, dL_dimage, grad2d, st);
   if (e != hipSuccess) return hip_fail(e);
   for (int a = 0; a < n_assets && e == hipSuccess; ++a) {
     const int64_t o = assets[a].offset, c = assets[a].count;
@@ -662,11 +672,22 @@ int32_t gs_rasterize_backward_2d(const gs_splat* splats, const uint32_t* values,
                                  const gs_settings* set, const float* T_final,
                                  const uint32_t* last, const float* dL_dimage, int64_t n,
                                  float* grad2d, void* stream) {
+  return gs_rasterize_backward_2d_mesh(splats, values, tile_ranges, cam, set, nullptr, T_final,
+                                       last, dL_dimage, n, grad2d, stream);
+}
+
+int32_t gs_rasterize_backward_2d_mesh(const gs_splat* splats, const uint32_t* values,
+                                      const uint32_t* tile_ranges, const gs_camera* cam,
+                                      const gs_settings* set, const float* mesh_rgb,
+                                      const float* T_final, const uint32_t* last,
+                                      const float* dL_dimage, int64_t n, float* grad2d,
+                                      void* stream) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if (n < 0 || n >= kMaxN) return GS_ERR_INVALID_ARGUMENT;
   if ((r = check_dev(tile_ranges)) || (r = check_dev(T_final)) || (r = check_dev(last)) ||
-      (r = check_dev(dL_dimage)) || (r = check_dev(values, false)))
+      (r = check_dev(dL_dimage)) || (r = check_dev(values, false)) ||
+      (r = check_dev(mesh_rgb, false)))
     return r;
   if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(grad2d)))) return r;
   if (n == 0) return GS_OK;
@@ -678,7 +699,7 @@ int32_t gs_rasterize_backward_2d(const gs_splat* splats, const uint32_t* values,
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "raster_bwd");
   e = gs::launch_rasterize_backward(splats, values, tile_ranges, sk, cam->width, cam->height,
-                                    T_final, last, dL_dimage, grad2d, st);
+                                    mesh_rgb, T_final, last, dL_dimage, grad2d, st);
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;

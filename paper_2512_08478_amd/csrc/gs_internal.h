@@ -129,14 +129,18 @@ hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uin
 hipError_t launch_compose_keys(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
                                const uint32_t* values, const gs_splat* splats, uint64_t* keys,
                                hipStream_t st);
+// mesh_depth (H*W, camera-space z; NULL: no mesh) hides deeper splats;
+// mesh_rgb / bg_rgb (H*W*3; NULL: the settings' background) is the colour
+// behind the Gaussians.
 hipError_t launch_rasterize(const gs_splat* splats, const uint32_t* values,
                             const uint32_t* ranges, const SetK& set, int W, int H,
-                            float* image, float* T_final, uint32_t* last, uint32_t* n_blend,
-                            hipStream_t st);
+                            const float* mesh_depth, const float* mesh_rgb, float* image,
+                            float* T_final, uint32_t* last, uint32_t* n_blend, hipStream_t st);
 hipError_t launch_rasterize_backward(const gs_splat* splats, const uint32_t* values,
                                      const uint32_t* ranges, const SetK& set, int W, int H,
-                                     const float* T_final, const uint32_t* last,
-                                     const float* dL_dimage, float* grad2d, hipStream_t st);
+                                     const float* bg_rgb, const float* T_final,
+                                     const uint32_t* last, const float* dL_dimage, float* grad2d,
+                                     hipStream_t st);
 hipError_t launch_preprocess_backward(int n, const float* means, const float* log_scales,
                                       const float* quats, const float* logits, const float* sh,
                                       int degree, const CamK& cam, const SetK& set,

@@ -25,6 +25,12 @@
 // right after the blend that takes T below t_eps.  The workgroup leaves
 // once all its pixels have stopped.
 //
+// Mesh depth composition (Algorithm 1, DrawSplatsWithMeshDepth; Section
+// 3.4): given the camera-space depth D(p) of a mesh prepass, a splat whose
+// depth exceeds D(p) is hidden at pixel p; the list is in depth order, so
+// the pixel stops at the first such splat.  The mesh colour, if given,
+// takes the place of the background behind the Gaussians.
+//
 // Quadrants are assigned XCD-major: the hardware deals consecutive
 // workgroups round-robin to the 8 XCDs, so workgroup b works on quadrant
 // (b % 8) * ceil(units/8) + b / 8; each XCD's L2 sees one contiguous band
@@ -57,7 +63,8 @@ inline int xcd_grid(int tiles) { return ((tiles + kXcds - 1) / kXcds) * kXcds; }
 // splat, so the writes (consecutive threads on consecutive rows) and the
 // wave's reads (its 8 rows of one splat) both touch consecutive words.
 constexpr int kBatch = 64;  // splats per batch: one per lane
-struct Stage {
+template <bool DEPTH>
+struct StageT {
   float4 hdr[kBatch];   // qa', r, g, b
   float4 aux[kBatch];   // qb, qc', my, 1 / opacity
   float2 ml[kBatch];    // mx, log2(opacity)
@@ -66,13 +73,16 @@ struct Stage {
   uint32_t hit[kBatch]; // footprint reaches the quadrant
   uint32_t gid[kBatch]; // Gaussian index
   uint32_t list[kBatch];  // batch slots of the splats that reach the quadrant
+  float dep[DEPTH ? kBatch : 1];  // camera-space depth (mesh depth test only)
 };
+using Stage = StageT<false>;
 
 // The fields of a splat record the compositing kernels read.
 struct SplatRec {
   float4 a;  // mx, my, qa, qb
   float4 b;  // qc, opacity, r, g
   float c;   // b
+  float depth;
   uint32_t lo, hi;  // pixel bbox: px0 | py0 << 16, px1 | py1 << 16
 };
 
@@ -83,6 +93,7 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
   r.b = rec[1];
   const float4 t = rec[2];
   r.c = t.x;
+  r.depth = t.y;
   r.lo = __float_as_uint(t.z);
   r.hi = __float_as_uint(t.w);
   return r;
@@ -91,9 +102,10 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
 // Phase 1 of staging: splat j's parameters, whether its footprint reaches
 // the quadrant whose top-left pixel is (qx0, qy0), and its index.  The
 // reach test uses the record's pixel bbox, which preprocess rounded
-// outwards from the opacity-aware footprint.
-__device__ __forceinline__ void stage_params(Stage& S, int j, const SplatRec& r, uint32_t g,
-                                             int qx0, int qy0) {
+// outwards from the opacity-aware footprint.  DEPTH also stages the depth.
+template <bool DEPTH>
+__device__ __forceinline__ void stage_params(StageT<DEPTH>& S, int j, const SplatRec& r,
+                                             uint32_t g, int qx0, int qy0) {
   const float4 a = r.a, b = r.b;
   const float c = r.c;
   const float mx = a.x, my = a.y, qb = a.w;
@@ -107,12 +119,15 @@ __device__ __forceinline__ void stage_params(Stage& S, int j, const SplatRec& r,
   S.ml[j] = make_float2(mx, lo);
   S.hit[j] = hit ? 1u : 0u;
   S.gid[j] = g;
+  if constexpr (DEPTH) S.dep[j] = r.depth;
 }
 
 // Phase 2 of staging: the row terms of the staged splats that reach the
 // quadrant (hits: their batch-slot mask), one (splat, row) pair per lane
 // and step.  Returns the mask.
-__device__ __forceinline__ uint64_t stage_rows(Stage& S, int cnt, int qx0, int qy0, int lane) {
+template <bool DEPTH>
+__device__ __forceinline__ uint64_t stage_rows(StageT<DEPTH>& S, int cnt, int qx0, int qy0,
+                                               int lane) {
   const uint64_t hits = ballot(lane < cnt && S.hit[lane < cnt ? lane : 0] != 0u);
   if ((hits >> lane) & 1ull)
     S.list[__builtin_popcountll(hits & ((1ull << lane) - 1ull))] = (uint32_t)lane;
@@ -133,17 +148,19 @@ __device__ __forceinline__ uint64_t stage_rows(Stage& S, int cnt, int qx0, int q
 // it walks the tile's whole list and composites the splats that reach its
 // quadrant.  Waves of one tile never wait on each other, and a quadrant
 // whose pixels have all stopped leaves at once.
-template <int TW, int TH>
+template <int TW, int TH, bool MESH>
 __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ splats,
                                                const uint32_t* __restrict__ values,
                                                const uint32_t* __restrict__ ranges,
                                                SetK set, int W, int H,
+                                               const float* __restrict__ mesh_depth,
+                                               const float* __restrict__ mesh_rgb,
                                                float* __restrict__ image,
                                                float* __restrict__ T_final,
                                                uint32_t* __restrict__ last,
                                                uint32_t* __restrict__ n_blend) {
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
-  __shared__ Stage S;
+  __shared__ StageT<MESH> S;
   const int tiles = set.tiles_x * set.tiles_y;
   const int unit = xcd_tile(blockIdx.x, tiles * NQ);  // quadrants of a tile stay on one XCD
   if (unit >= tiles * NQ) return;
@@ -162,6 +179,9 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t lastc = 0, nb = 0;
   bool done = !inside;
+  // mesh depth at this pixel (splats deeper than it are hidden)
+  float D = __builtin_inff();
+  if (MESH && inside) D = mesh_depth[py * W + px];
   // Software pipeline over batches: while a batch composites, the records
   // of the next batch and the indices of the one after are in flight.
   // Loads past the range are clamped to its last entry (their values are
@@ -196,6 +216,7 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     // two hit splats per step: both splats' LDS reads are issued before
     // the first one blends, hiding one read latency per pair
     auto blend = [&](int j, float e, const float4& h) {
+      if constexpr (MESH) live = S.dep[j] > D ? 0.f : live;  // hidden from here on
       const bool take = e >= log2_tau && live != 0.f;
       if (!ballot(take)) return;
       const float alpha = take ? fminf(set.amax, hw_exp2(e)) : 0.f;
@@ -229,8 +250,14 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   }
   if (inside) {
     const int p = py * W + px;
+    float b0 = set.bg[0], b1 = set.bg[1], b2 = set.bg[2];
+    if (mesh_rgb) {
+      b0 = mesh_rgb[3 * p];
+      b1 = mesh_rgb[3 * p + 1];
+      b2 = mesh_rgb[3 * p + 2];
+    }
     reinterpret_cast<float4*>(image)[p] =
-        make_float4(fmaf(T, set.bg[0], C0), fmaf(T, set.bg[1], C1), fmaf(T, set.bg[2], C2), 1.f - T);
+        make_float4(fmaf(T, b0, C0), fmaf(T, b1, C1), fmaf(T, b2, C2), 1.f - T);
     T_final[p] = T;
     last[p] = lastc;
     if (n_blend) n_blend[p] = nb;
@@ -259,6 +286,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
                                                    const uint32_t* __restrict__ values,
                                                    const uint32_t* __restrict__ ranges,
                                                    SetK set, int W, int H,
+                                                   const float* __restrict__ bg_rgb,
                                                    const float* __restrict__ T_final,
                                                    const uint32_t* __restrict__ last,
                                                    const float* __restrict__ dL_dimage,
@@ -282,6 +310,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
   const float log2_tau = set.log2_tau;
 
   float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, dA = 0.f;
+  float b0 = set.bg[0], b1 = set.bg[1], b2 = set.bg[2];  // colour behind the Gaussians
   uint32_t mylast = 0;
   if (inside) {
     const int p = py * W + px;
@@ -289,13 +318,18 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
     mylast = last[p];
     const float4 g = reinterpret_cast<const float4*>(dL_dimage)[p];
     dC0 = g.x; dC1 = g.y; dC2 = g.z; dA = g.w;
+    if (bg_rgb) {
+      b0 = bg_rgb[3 * p];
+      b1 = bg_rgb[3 * p + 1];
+      b2 = bg_rgb[3 * p + 2];
+    }
   }
   // the quadrant's largest `last`: later splats blend into none of its pixels
   uint32_t nlast = mylast;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) nlast = max(nlast, shfl_u32(nlast, lane ^ d));
   nlast = __builtin_amdgcn_readfirstlane(nlast);
-  const float bgdot = dC0 * set.bg[0] + dC1 * set.bg[1] + dC2 * set.bg[2];
+  const float bgdot = dC0 * b0 + dC1 * b1 + dC2 * b2;
   float S0 = 0.f, S1 = 0.f, S2 = 0.f, B = 1.f;
 
   // batches cover positions [0, nlast) of the tile's range, last batch first
@@ -382,20 +416,26 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
 
 template <int TW, int TH>
 void raster_fwd(const gs_splat* splats, const uint32_t* values, const uint32_t* ranges,
-                const SetK& set, int W, int H, float* image, float* T_final, uint32_t* last,
-                uint32_t* n_blend, hipStream_t st) {
+                const SetK& set, int W, int H, const float* mesh_depth, const float* mesh_rgb,
+                float* image, float* T_final, uint32_t* last, uint32_t* n_blend, hipStream_t st) {
   const int units = set.tiles_x * set.tiles_y * (TW / 8) * (TH / 8);
-  hipLaunchKernelGGL((k_raster<TW, TH>), dim3(xcd_grid(units)), dim3(64), 0, st, splats,
-                     values, ranges, set, W, H, image, T_final, last, n_blend);
+  if (mesh_depth)
+    hipLaunchKernelGGL((k_raster<TW, TH, true>), dim3(xcd_grid(units)), dim3(64), 0, st, splats,
+                       values, ranges, set, W, H, mesh_depth, mesh_rgb, image, T_final, last,
+                       n_blend);
+  else
+    hipLaunchKernelGGL((k_raster<TW, TH, false>), dim3(xcd_grid(units)), dim3(64), 0, st, splats,
+                       values, ranges, set, W, H, nullptr, mesh_rgb, image, T_final, last,
+                       n_blend);
 }
 
 template <int TW, int TH>
 void raster_bwd(const gs_splat* splats, const uint32_t* values, const uint32_t* ranges,
-                const SetK& set, int W, int H, const float* T_final, const uint32_t* last,
-                const float* dL_dimage, float* grad2d, hipStream_t st) {
+                const SetK& set, int W, int H, const float* bg_rgb, const float* T_final,
+                const uint32_t* last, const float* dL_dimage, float* grad2d, hipStream_t st) {
   const int units = set.tiles_x * set.tiles_y * (TW / 8) * (TH / 8);
   hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(xcd_grid(units)), dim3(64), 0, st,
-                     splats, values, ranges, set, W, H, T_final, last, dL_dimage, grad2d);
+                     splats, values, ranges, set, W, H, bg_rgb, T_final, last, dL_dimage, grad2d);
 }
 
 }  // namespace
@@ -407,27 +447,32 @@ bool tile_shape_supported(int tw, int th) {
 
 hipError_t launch_rasterize(const gs_splat* splats, const uint32_t* values,
                             const uint32_t* ranges, const SetK& set, int W, int H,
-                            float* image, float* T_final, uint32_t* last, uint32_t* n_blend,
-                            hipStream_t st) {
+                            const float* mesh_depth, const float* mesh_rgb, float* image,
+                            float* T_final, uint32_t* last, uint32_t* n_blend, hipStream_t st) {
   const int tw = set.tile_w, th = set.tile_h;
-  if (tw == 8 && th == 8) raster_fwd<8, 8>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
-  else if (tw == 16 && th == 8) raster_fwd<16, 8>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
-  else if (tw == 16 && th == 16) raster_fwd<16, 16>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
-  else if (tw == 32 && th == 8) raster_fwd<32, 8>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
-  else raster_fwd<32, 16>(splats, values, ranges, set, W, H, image, T_final, last, n_blend, st);
+#define GS_RF(A, B) raster_fwd<A, B>(splats, values, ranges, set, W, H, mesh_depth, mesh_rgb, image, T_final, last, n_blend, st)
+  if (tw == 8 && th == 8) GS_RF(8, 8);
+  else if (tw == 16 && th == 8) GS_RF(16, 8);
+  else if (tw == 16 && th == 16) GS_RF(16, 16);
+  else if (tw == 32 && th == 8) GS_RF(32, 8);
+  else GS_RF(32, 16);
+#undef GS_RF
   return hipGetLastError();
 }
 
 hipError_t launch_rasterize_backward(const gs_splat* splats, const uint32_t* values,
                                      const uint32_t* ranges, const SetK& set, int W, int H,
-                                     const float* T_final, const uint32_t* last,
-                                     const float* dL_dimage, float* grad2d, hipStream_t st) {
+                                     const float* bg_rgb, const float* T_final,
+                                     const uint32_t* last, const float* dL_dimage, float* grad2d,
+                                     hipStream_t st) {
   const int tw = set.tile_w, th = set.tile_h;
-  if (tw == 8 && th == 8) raster_bwd<8, 8>(splats, values, ranges, set, W, H, T_final, last, dL_dimage, grad2d, st);
-  else if (tw == 16 && th == 8) raster_bwd<16, 8>(splats, values, ranges, set, W, H, T_final, last, dL_dimage, grad2d, st);
-  else if (tw == 16 && th == 16) raster_bwd<16, 16>(splats, values, ranges, set, W, H, T_final, last, dL_dimage, grad2d, st);
-  else if (tw == 32 && th == 8) raster_bwd<32, 8>(splats, values, ranges, set, W, H, T_final, last, dL_dimage, grad2d, st);
-  else raster_bwd<32, 16>(splats, values, ranges, set, W, H, T_final, last, dL_dimage, grad2d, st);
+#define GS_RB(A, B) raster_bwd<A, B>(splats, values, ranges, set, W, H, bg_rgb, T_final, last, dL_dimage, grad2d, st)
+  if (tw == 8 && th == 8) GS_RB(8, 8);
+  else if (tw == 16 && th == 8) GS_RB(16, 8);
+  else if (tw == 16 && th == 16) GS_RB(16, 16);
+  else if (tw == 32 && th == 8) GS_RB(32, 8);
+  else GS_RB(32, 16);
+#undef GS_RB
   return hipGetLastError();
 }
 

@@ -12,7 +12,8 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["GaussianParams", "PackedParams", "Renderer", "Frame", "render", "GsRender"]
+__all__ = ["GaussianParams", "PackedParams", "Renderer", "Frame", "render", "GsRender",
+           "mesh_buffers"]
 
 
 def _p(t):
@@ -102,6 +103,24 @@ class Frame:
     ranges: torch.Tensor     # (2*tiles,) int32 (u32)
     flag: torch.Tensor       # (1,) int32: bit 0 = capacity exceeded
     capacity: int
+    mesh: object = None      # the mesh prepass composited with (see Renderer.forward)
+
+
+def mesh_buffers(mesh, cam, device="cuda"):
+    """A mesh prepass {"depth": (H, W), "rgb": (H, W, 3) or None} (numpy or
+    torch) as contiguous float32 device tensors of the camera's size."""
+    H, W = cam.height, cam.width
+    out = {}
+    for k, shape in (("depth", (H, W)), ("rgb", (H, W, 3))):
+        v = mesh.get(k)
+        if v is None:
+            out[k] = None
+            continue
+        t = torch.as_tensor(v).to(device=device, dtype=torch.float32).contiguous()
+        if tuple(t.shape) != shape:
+            raise ValueError(f"mesh {k} must have shape {shape}, got {tuple(t.shape)}")
+        out[k] = t
+    return out
 
 
 class Renderer:
@@ -217,9 +236,10 @@ class Renderer:
         L.check(st, "gs_sort_pairs32")
         return kout, vout
 
-    def rasterize(self, splats, values, ranges, cam, n_blend=None):
+    def rasterize(self, splats, values, ranges, cam, n_blend=None, mesh=None):
         """Eqs. 2-3.  `n_blend`, if given, is an int32 (H, W) tensor that
-        receives the number of splats blended into each pixel."""
+        receives the number of splats blended into each pixel.  `mesh`
+        (see mesh_buffers) composites with a mesh prepass."""
         lib = L.load()
         c, s = L.make_camera(cam), self.settings
         H, W = cam.height, cam.width
@@ -228,20 +248,38 @@ class Renderer:
         last = torch.empty((H, W), dtype=torch.int32, device=self.device)
         if n_blend is not None:
             assert n_blend.shape == (H, W) and n_blend.dtype == torch.int32 and n_blend.is_contiguous()
-        st = lib.gs_rasterize(_p(splats), _p(values), _p(ranges), ctypes.byref(c), ctypes.byref(s),
-                              _p(image), _p(T), _p(last), _p(n_blend) if n_blend is not None else None,
-                              _stream())
-        L.check(st, "gs_rasterize")
+        nb = _p(n_blend) if n_blend is not None else None
+        if mesh is not None:
+            md, mr = mesh.get("depth"), mesh.get("rgb")
+            st = lib.gs_rasterize_mesh(_p(splats), _p(values), _p(ranges), ctypes.byref(c),
+                                       ctypes.byref(s), _p(md), _p(mr), _p(image), _p(T),
+                                       _p(last), nb, _stream())
+            L.check(st, "gs_rasterize_mesh")
+        else:
+            st = lib.gs_rasterize(_p(splats), _p(values), _p(ranges), ctypes.byref(c),
+                                  ctypes.byref(s), _p(image), _p(T), _p(last), nb, _stream())
+            L.check(st, "gs_rasterize")
         return image, T, last
 
-    def forward(self, p, cam, capacity=None, reuse=True, want_keys=False) -> Frame:
+    def forward(self, p, cam, capacity=None, reuse=True, want_keys=False, mesh=None) -> Frame:
+        """One frame: preprocess, sort, composite (with a mesh prepass when
+        `mesh` is given: {"depth": (H, W) float32 camera-space z, +inf where
+        there is no mesh; "rgb": (H, W, 3) float32 or None}, device tensors,
+        see mesh_buffers)."""
+        if mesh is not None:
+            mesh = mesh_buffers(mesh, cam, self.device)
         splats, dkeys, rects, counts = self.preprocess(p, cam, reuse)
         keys, values, ranges, flag, cap = self.sort(p.n, splats, dkeys, rects, counts, cam, capacity,
                                                     reuse, want_keys)
-        image, T, last = self.rasterize(splats, values, ranges, cam)
-        return Frame(image, T, last, splats, dkeys, rects, counts, keys, values, ranges, flag, cap)
+        image, T, last = self.rasterize(splats, values, ranges, cam, mesh=mesh)
+        return Frame(image, T, last, splats, dkeys, rects, counts, keys, values, ranges, flag, cap,
+                     mesh)
 
     def backward(self, p: GaussianParams, cam, fr: Frame, dL_dimage, out=None, accumulate=False):
+        if fr.mesh is not None:
+            # compositing backward against the mesh colour, then the chain rule
+            g2d = self.backward_2d(p, cam, fr, dL_dimage)
+            return self.backward_views(p, [cam], [g2d], out=out, accumulate=accumulate)
         lib = L.load()
         c, s = L.make_camera(cam), self.settings
         n = p.n
@@ -277,10 +315,17 @@ class Renderer:
         if grad2d is None:
             grad2d = torch.empty((n, L.GRAD2D_STRIDE), dtype=torch.float32, device=self.device)
         dL = dL_dimage.to(torch.float32).contiguous()
-        st = lib.gs_rasterize_backward_2d(_p(fr.splats), _p(fr.values), _p(fr.ranges),
-                                          ctypes.byref(c), ctypes.byref(s), _p(fr.T_final),
-                                          _p(fr.last), _p(dL), n, _p(grad2d), _stream())
-        L.check(st, "gs_rasterize_backward_2d")
+        if fr.mesh is not None:
+            st = lib.gs_rasterize_backward_2d_mesh(
+                _p(fr.splats), _p(fr.values), _p(fr.ranges), ctypes.byref(c), ctypes.byref(s),
+                _p(fr.mesh.get("rgb")), _p(fr.T_final), _p(fr.last), _p(dL), n, _p(grad2d),
+                _stream())
+            L.check(st, "gs_rasterize_backward_2d_mesh")
+        else:
+            st = lib.gs_rasterize_backward_2d(_p(fr.splats), _p(fr.values), _p(fr.ranges),
+                                              ctypes.byref(c), ctypes.byref(s), _p(fr.T_final),
+                                              _p(fr.last), _p(dL), n, _p(grad2d), _stream())
+            L.check(st, "gs_rasterize_backward_2d")
         return grad2d
 
     def backward_views(self, p: GaussianParams, cams, grad2ds, out=None, accumulate=False):
@@ -306,21 +351,23 @@ class GsRender(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, sh, renderer, cam, sh_degree, model,
-                assets=None):
+                assets=None, mesh=None):
         p = GaussianParams(means.detach(), log_scales.detach(), quats.detach(),
                            opacity_logits.detach(), sh.detach(), sh_degree, model, assets)
-        fr = renderer.forward(p, cam, reuse=False)
+        fr = renderer.forward(p, cam, reuse=False, mesh=mesh)
         ctx.renderer, ctx.cam, ctx.p, ctx.frame = renderer, cam, p, fr
         return fr.image
 
     @staticmethod
     def backward(ctx, grad_image):
         g = ctx.renderer.backward(ctx.p, ctx.cam, ctx.frame, grad_image)
-        return (*g, None, None, None, None, None)
+        return (*g, None, None, None, None, None, None)
 
 
-def render(params: GaussianParams, cam, renderer: Renderer = None):
-    """Differentiable render of ``params`` from ``cam``: (H, W, 4) RGBA."""
+def render(params: GaussianParams, cam, renderer: Renderer = None, mesh=None):
+    """Differentiable render of ``params`` from ``cam``: (H, W, 4) RGBA,
+    optionally composited with a mesh prepass (see Renderer.forward)."""
     renderer = renderer or Renderer()
     return GsRender.apply(params.means, params.log_scales, params.quats, params.opacity_logits,
-                          params.sh, renderer, cam, params.sh_degree, params.model, params.assets)
+                          params.sh, renderer, cam, params.sh_degree, params.model, params.assets,
+                          mesh)

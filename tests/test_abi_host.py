@@ -267,3 +267,24 @@ def test_packed_layout_and_validation(lib):
     assert pk(cov=ctypes.c_void_p(FAKE + 2 * 4096 + 4)) == L.GS_ERR_MISALIGNED
     assert pk(ws=0) == L.GS_ERR_WORKSPACE
     assert pk(sset=L.default_settings(tile_w=12)) == L.GS_ERR_UNSUPPORTED
+
+
+def test_mesh_entry_points_validation(lib):
+    c, s = cam_1080(), L.default_settings()
+    F = ctypes.c_void_p(FAKE)
+    G = lambda k: ctypes.c_void_p(FAKE + 4096 * k)
+    bad = ctypes.c_void_p(FAKE + 4)
+
+    def rm(md=G(5), mr=G(6), sset=s, img=G(7)):
+        return lib.gs_rasterize_mesh(F, G(1), G(2), ctypes.byref(c), ctypes.byref(sset), md, mr,
+                                     img, G(8), G(9), None, None)
+    assert rm(md=bad) == L.GS_ERR_MISALIGNED
+    assert rm(mr=bad) == L.GS_ERR_MISALIGNED
+    assert rm(img=None) == L.GS_ERR_INVALID_ARGUMENT
+    assert rm(sset=L.default_settings(radix_bits=9)) == L.GS_ERR_UNSUPPORTED
+
+    def rb(mr=G(6), n=8):
+        return lib.gs_rasterize_backward_2d_mesh(F, G(1), G(2), ctypes.byref(c), ctypes.byref(s),
+                                                 mr, G(3), G(4), G(5), n, G(7), None)
+    assert rb(mr=bad) == L.GS_ERR_MISALIGNED
+    assert rb(n=-1) == L.GS_ERR_INVALID_ARGUMENT
