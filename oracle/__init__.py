@@ -11,8 +11,10 @@ the SH colour, and the per-pixel compositing of Eqs. 2-3 by brute force in
 ascending (depth, index) order; plus the (tile, depth) key list and a
 library stable sort.  ``prepack`` / ``preprocess_packed`` give the FP16
 pre-pack of Section 3.4 (one rounding of float64 values to binary16) and
-the projection from the packed mean, opacity and upper covariance.
-``grad.py`` gives reference gradients by float64
+the projection from the packed mean, opacity and upper covariance;
+``lbs_deform`` the avatar pre-decoder's linear blend skinning (Section 3.3,
+Eqs. 5-6); ``render_pixels(..., mesh=)`` the mesh depth composition of
+Section 3.4.  ``grad.py`` gives reference gradients by float64
 automatic differentiation of the same definition (Section 3.2: the
 formulation is differentiable).
 
@@ -24,7 +26,9 @@ brute-force sort; front-to-back against back-to-front compositing; and the
 gradients against central finite differences of the C forward; the
 covariance-input projection against the raw-parameter one at a SciPy
 covariance, and the binary16 rounding against IEEE 754's ties-to-even
-cases.
+cases; mesh composition by walls behind, in front of and between
+Gaussians; skinning by the identity pose, a single rigid joint against the
+model transform, and closed-form blends of translations and rotations.
 """
 from __future__ import annotations
 
@@ -218,6 +222,28 @@ def preprocess_packed(packed, cam, settings=None) -> Records:
     if rc != 0:
         raise ValueError("orc_preprocess_cov rejected its arguments")
     return Records(d, iv)
+
+
+def lbs_deform(packed, joint_idx, joint_w, joints, rounded=True) -> dict:
+    """Linear blend skinning of pre-packed canonical Gaussians (Section 3.3,
+    Eqs. 5-6): T_i = sum_k w_ik M_k = [R_i | t_i], mu_i = R_i mu^_i + t_i,
+    Sigma_i = R_i Sigma^_i R_i^T, in float64 from the decoded canonical
+    values; with ``rounded`` the deformed mean and covariance are rounded
+    once to binary16 (opacity and SH pass through)."""
+    mu = np.asarray(packed["means"], np.float64)
+    c6 = np.asarray(packed["cov6"], np.float64)
+    Sig = np.stack([c6[:, [0, 1, 2]], c6[:, [1, 3, 4]], c6[:, [2, 4, 5]]], 1)
+    M = np.asarray(joints, np.float64).reshape(-1, 3, 4)
+    w = np.asarray(joint_w, np.float64)
+    T = np.einsum("nk,nkij->nij", w, M[np.asarray(joint_idx, np.int64)])
+    R, t = T[:, :, :3], T[:, :, 3]
+    mu_d = np.einsum("nij,nj->ni", R, mu) + t
+    Sig_d = R @ Sig @ np.transpose(R, (0, 2, 1))
+    cov6 = Sig_d[:, [0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
+    out = dict(packed)
+    out["means"] = to_fp16(mu_d) if rounded else mu_d
+    out["cov6"] = to_fp16(cov6) if rounded else cov6
+    return out
 
 
 def preprocess_many(scenes, cam, settings=None, f64_inputs=False) -> Records:

@@ -288,6 +288,56 @@ SORT_KEY_KINDS = ("random64", "random45", "all_equal", "sorted", "reversed",
                   "two_unique", "tile_runs", "depth_like")
 
 
+def skinning(means, n_joints=55, influences=4, seed=0):
+    """Synthetic linear-blend-skinning data for an avatar-like asset:
+    ``n_joints`` joint centres drawn (seeded) among the Gaussians' means;
+    each Gaussian is bound to its ``influences`` nearest joints with
+    weights proportional to 1 / (distance + 0.05)^2, normalised to sum to
+    one in float64.  Returns (centres (K,3) float32, joint indices (N,J)
+    uint8, weights (N,J) float32)."""
+    if not 1 <= n_joints <= 256:
+        raise ValueError("1..256 joints")
+    rng = np.random.default_rng(seed)
+    means = np.asarray(means, np.float64)
+    n = means.shape[0]
+    centres = means[rng.choice(n, n_joints, replace=n < n_joints)]
+    J = min(influences, n_joints)
+    idx = np.zeros((n, influences), np.uint8)
+    w = np.zeros((n, influences), np.float64)
+    for s0 in range(0, n, 65536):
+        d = np.linalg.norm(means[s0:s0 + 65536, None, :] - centres[None], axis=2)
+        near = np.argpartition(d, J - 1, axis=1)[:, :J] if J < n_joints else \
+            np.tile(np.arange(n_joints), (d.shape[0], 1))
+        dn = np.take_along_axis(d, near, 1)
+        ww = 1.0 / (dn + 0.05) ** 2
+        idx[s0:s0 + 65536, :J] = near
+        w[s0:s0 + 65536, :J] = ww / ww.sum(1, keepdims=True)
+    return centres.astype(np.float32), idx, w.astype(np.float32)
+
+
+def joint_pose(centres, seed=0, angle=0.35, shift=0.2):
+    """One pose: per joint a rigid motion about its centre c_k, rotation
+    by a seeded angle up to ``angle`` radians about a random axis, then a
+    shift up to ``shift``: M_k = [R_k | c_k - R_k c_k + d_k], float32
+    (K,3,4).  seed=None gives the identity pose."""
+    c = np.asarray(centres, np.float64)
+    K = c.shape[0]
+    M = np.zeros((K, 3, 4), np.float64)
+    M[:, :, :3] = np.eye(3)
+    if seed is None:
+        return M.astype(np.float32)
+    rng = np.random.default_rng(seed)
+    for k in range(K):
+        ax = rng.standard_normal(3)
+        ax /= np.linalg.norm(ax)
+        th = rng.uniform(-angle, angle)
+        Kx = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+        R = np.eye(3) + math.sin(th) * Kx + (1 - math.cos(th)) * (Kx @ Kx)
+        M[k, :, :3] = R
+        M[k, :, 3] = c[k] - R @ c[k] + rng.uniform(-shift, shift, 3)
+    return M.astype(np.float32)
+
+
 def plane_mesh(cam: Camera, normal, offset, seed=0, cell=0.5, occupancy=1.0):
     """A mesh prepass stand-in: the per-pixel camera-space depth and colour
     of the world plane {X : normal . X = offset} seen through `cam` (pixel

@@ -564,3 +564,89 @@ def test_plane_mesh_depth_is_the_ray_plane_intersection(orc):
     xc = np.stack([(xs + 0.5 - cam.cx) / cam.fx * z, (ys + 0.5 - cam.cy) / cam.fy * z, z], -1)[ok]
     Xw = (xc - V[:3, 3]) @ V[:3, :3]
     np.testing.assert_allclose(Xw @ (n / np.linalg.norm(n)), h, atol=1e-5)
+
+
+# ---------------------------------------------------------------- LBS pre-decoder (Section 3.3, Eqs. 5-6)
+
+def _skin_one(n, joints_of, weights_of):
+    idx = np.zeros((n, 4), np.uint8)
+    w = np.zeros((n, 4), np.float32)
+    idx[:, :len(joints_of)] = joints_of
+    w[:, :len(weights_of)] = weights_of
+    return idx, w
+
+
+def test_lbs_identity_pose_is_exact(orc):
+    sc, _ = S.medium_scene(n=3000)
+    pk = orc.prepack(sc)
+    centres, idx, w = S.skinning(sc.means, n_joints=20, seed=1)
+    out = orc.lbs_deform(pk, idx, w, S.joint_pose(centres, seed=None))
+    np.testing.assert_array_equal(out["means"].view(np.uint16), pk["means"].view(np.uint16))
+    np.testing.assert_array_equal(out["cov6"].view(np.uint16), pk["cov6"].view(np.uint16))
+    assert out["opacity"] is pk["opacity"] and out["sh"] is pk["sh"]
+
+
+def test_lbs_single_joint_equals_model_transform(orc):
+    # all weight on one rigid joint: the same records as rendering the
+    # canonical asset placed by that transform (colour is view-independent
+    # at SH degree 0, so it agrees too)
+    sc, cam = S.tiny_scene(n=2000)
+    pk = orc.prepack(sc)
+    R = Rotation.from_euler("xyz", [0.3, -0.5, 0.2]).as_matrix()
+    M = np.concatenate([R, np.array([[0.2], [-0.1], [0.3]])], 1)
+    joints = np.stack([np.eye(3, 4), M]).astype(np.float64)
+    idx, w = _skin_one(sc.n, [1], [1.0])
+    d = orc.lbs_deform(pk, idx, w, joints, rounded=False)
+    r_lbs = orc.preprocess_packed(dict(d, model=None), cam)
+    r_mod = orc.preprocess_packed(dict(pk, model=M), cam)
+    assert r_mod.visible.sum() > 500
+    np.testing.assert_array_equal(r_lbs.i[:, orc.I_CULL], r_mod.i[:, orc.I_CULL])
+    v = r_mod.visible
+    keep = [orc.D_MX, orc.D_MY, orc.D_SA, orc.D_SB, orc.D_SC, orc.D_DEPTH, orc.D_R, orc.D_G, orc.D_B]
+    np.testing.assert_allclose(r_lbs.d[v][:, keep], r_mod.d[v][:, keep], rtol=1e-10, atol=1e-12)
+
+
+def test_lbs_translation_blend_closed_form(orc):
+    sc, _ = S.tiny_scene(n=64)
+    pk = orc.prepack(sc)
+    a, b = np.array([1.0, 0.0, 0.5]), np.array([0.0, 2.0, -1.0])
+    joints = np.zeros((2, 3, 4))
+    joints[:, :, :3] = np.eye(3)
+    joints[0, :, 3], joints[1, :, 3] = a, b
+    idx, w = _skin_one(sc.n, [0, 1], [0.25, 0.75])   # exact in float32
+    d = orc.lbs_deform(pk, idx, w, joints, rounded=False)
+    np.testing.assert_allclose(d["means"], pk["means"].astype(np.float64) + 0.25 * a + 0.75 * b,
+                               rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(d["cov6"], pk["cov6"].astype(np.float64))
+
+
+def test_lbs_rotation_blend_shrinks_closed_form(orc):
+    # Blending a rotation about z by theta with the identity shrinks the
+    # xy-plane: R = w1 Rz + w2 I, R R^T = diag(a^2 + b^2, a^2 + b^2, 1) with
+    # a = w1 cos(theta) + w2, b = w1 sin(theta) (the LBS "candy wrapper").
+    th, w1, w2 = 1.1, 0.5, 0.5
+    pk = dict(means=np.array([[0.5, -0.25, 1.0]], np.float16), opacity=np.array([0.5], np.float16),
+              cov6=np.array([[0.25, 0, 0, 0.25, 0, 0.25]], np.float16),
+              sh=np.zeros((1, 1, 3), np.float16), sh_degree=0, model=None)
+    Rz = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    joints = np.stack([np.concatenate([Rz, np.zeros((3, 1))], 1), np.eye(3, 4)])
+    d = orc.lbs_deform(pk, np.array([[0, 1, 0, 0]], np.uint8), np.array([[w1, w2, 0, 0]], np.float32),
+                       joints, rounded=False)
+    a, b = w1 * math.cos(th) + w2, w1 * math.sin(th)
+    np.testing.assert_allclose(d["cov6"][0], 0.25 * np.array([a * a + b * b, 0, 0, a * a + b * b, 0, 1]),
+                               atol=1e-15)
+    mu = np.array([0.5, -0.25, 1.0])
+    np.testing.assert_allclose(d["means"][0], [a * mu[0] - b * mu[1], b * mu[0] + a * mu[1], mu[2]],
+                               atol=1e-15)
+
+
+def test_skinning_generator(orc):
+    sc, _ = S.medium_scene(n=5000)
+    centres, idx, w = S.skinning(sc.means, n_joints=55, seed=3)
+    assert centres.shape == (55, 3) and idx.shape == (5000, 4) and w.dtype == np.float32
+    np.testing.assert_allclose(w.astype(np.float64).sum(1), 1.0, atol=1e-6)
+    assert idx.max() < 55 and (w > 0).all()
+    # the first influence is a nearest joint
+    d = np.linalg.norm(sc.means[:, None, :].astype(np.float64) - centres[None].astype(np.float64), axis=2)
+    dsel = np.take_along_axis(d, idx.astype(np.int64), 1)
+    assert np.all(dsel.min(1) <= d.min(1) + 1e-6)
