@@ -34,7 +34,7 @@ FLOPS_PER_BLEND = 24
 
 SORT_KERNELS = ("sort_init", "radix_hist", "depth_pass", "kg_count", "kg_scan", "keygen",
                 "tile_pass", "tile_ranges")
-HBM_KERNELS = ("preprocess", "preprocess_packed", "depth_pass", "keygen", "kg_count", "tile_pass",
+HBM_KERNELS = ("preprocess", "preprocess_packed", "lbs", "depth_pass", "keygen", "kg_count", "tile_pass",
                "tile_ranges", "preprocess_bwd")
 ALU_KERNELS = ("raster", "raster_mesh", "raster_bwd")
 
@@ -43,6 +43,9 @@ WORKLOADS = {
     "medium": "medium: 1,000,000 Gaussians (64 clusters in [-5,5]^3), SH degree 3, 1920x1080, forward",
     "large": "large: 6,000,000 Gaussians (64 clusters in [-20,20]^3), SH degree 3, 1920x1080 eye inside, forward",
     "diff": "diff: 500,000 Gaussians, SH degree 3, 800x800, forward+backward (L1)",
+    "avatar": "avatar: the medium scene skinned to 55 joints (4 influences each), FP16 "
+              "pre-packed; every frame runs the linear-blend-skinning pre-decoder on a posed "
+              "skeleton, then the packed forward",
     "mesh": "mesh: the medium scene composited with a mesh prepass (a plane through the "
             "scene centre facing the camera, 40% of its cells left out), forward",
     "sort32": "sort32: depth-only global sort of the 32-bit depth keys (culled = largest key) of "
@@ -84,7 +87,7 @@ def make_workload(name):
         return S.large_scene()
     if name == "diff":
         return S.diff_scene()
-    if name == "mesh":
+    if name in ("mesh", "avatar"):
         return S.medium_scene()
     raise ValueError(name)
 
@@ -111,6 +114,9 @@ def algorithmic_bytes(n, n_vis, inst, K, W, H, tiles):
         # binary16 mean + opacity 8 + covariance 12 read, the same 60 B written per
         # Gaussian; the packed SH row (2 bytes a half) read per visible one
         "preprocess_packed": n * (20 + 60) + n_vis * 2 * packed_sh_halves(K),
+        # canonical mean/opacity 8 + covariance 12 + joint indices 4 + weights 16 read,
+        # deformed mean/opacity 8 + covariance 12 written per Gaussian
+        "lbs": n * 60,
         # per depth pass: u32 key + u32 value read and written per Gaussian (upsweep,
         # scan and downsweep together)
         "depth_pass": n * 16,
@@ -176,9 +182,19 @@ def main():
         del src, dst
     sc, cam = make_workload(args.workload)
     p = GaussianParams.from_scene(sc)
-    if args.packed:
+    if args.packed or args.workload == "avatar":
         # the pre-pack runs once per asset, before any frame (Algorithm 1)
         p = Renderer().prepack(p)
+        torch.cuda.synchronize()
+    skin = skin_np = None
+    if args.workload == "avatar":
+        from paper_2512_08478_amd import scenes as S
+        centres, jidx, jw = S.skinning(sc.means, n_joints=55, seed=0)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        skin_np = (jidx, jw, S.joint_pose(centres, seed=1))
+        skin = tuple(dev(a) for a in skin_np)
+        canon = p
+        p = Renderer().lbs_deform(canon, *skin)   # the posed frame, for tuning and sizing
         torch.cuda.synchronize()
     backward = args.workload == "diff"
     mesh = make_mesh(cam) if args.workload == "mesh" else None
@@ -209,6 +225,8 @@ def main():
     capacity = inst
 
     def step():
+        if skin is not None:
+            R.lbs_deform(canon, *skin, out=p)   # the pre-decoder runs every frame
         f = R.forward(p, cam, capacity=capacity, mesh=mesh)
         if backward:
             # L1 loss gradient w.r.t. RGB (the caller's loss, not part of the method)
@@ -306,7 +324,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload] + (
-                       ", FP16 pre-packed inputs" if args.packed else ""),
+                       ", FP16 pre-packed inputs" if args.packed and args.workload != "avatar"
+                       else ""),
                    "n_gaussians": sc.n, "width": W,
                    "height": H, "tile": f"{tw}x{th}", "radix_bits": args.radix_bits,
                    "visible": n_vis, "instances": inst, "key_bits": key_bits,
@@ -320,8 +339,10 @@ def main():
         out["autotune_ms_per_frame"] = tuned
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels, packed=args.packed,
-                                           mesh=make_mesh(cam) if args.workload == "mesh" else None)
+        out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels,
+                                           packed=args.packed or skin_np is not None,
+                                           mesh=make_mesh(cam) if args.workload == "mesh" else None,
+                                           skin=skin_np)
     print(json.dumps(out), flush=True)
 
 
@@ -497,16 +518,19 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(sc, cam, n_pix, scale_pixels=None, packed=False, mesh=None):
+def cpu_baseline(sc, cam, n_pix, scale_pixels=None, packed=False, mesh=None, skin=None):
     """The FP64 oracle, as it stands, on a bounded sample of the same frame:
     preprocess of every Gaussian + brute-force compositing of n_pix random
     pixels, scaled to a whole frame.  With `packed`, the oracle pre-packs
-    first (untimed, as on the GPU) and preprocesses the packed values."""
+    first (untimed, as on the GPU) and preprocesses the packed values; with
+    `skin` (joint indices, weights, joints) it also skins them each frame."""
     import numpy as np
     import oracle
     pk = oracle.prepack(sc) if packed else None
     t0 = time.perf_counter()
     if pk is not None:
+        if skin is not None:
+            pk = oracle.lbs_deform(pk, *skin)
         rec = oracle.preprocess_packed(pk, cam)
         n = sc.n
     elif isinstance(sc, (list, tuple)):   # several assets, one view of the batch

@@ -253,6 +253,26 @@ int32_t gs_prepack(int64_t n, const float* means, const float* log_scales, const
                    uint16_t* posop, uint16_t* cov, uint16_t* sh16, void* stream);
 
 /*
+ * gs_lbs_deform -- the avatar pre-decoder (Section 3.3, Eqs. 5-6): linear
+ * blend skinning of n pre-packed canonical Gaussians.  Per Gaussian i,
+ *   T_i = sum_k w_ik M_{j_ik} = [R_i | t_i]   (k = 0..3),
+ *   mu_i = R_i mu^_i + t_i,   Sigma_i = R_i Sigma^_i R_i^T.
+ * canon_posop[n*4], canon_cov[n*6]: the canonical Gaussians in the
+ * gs_prepack layout (binary16).  joint_idx[n*4] (u8) and joint_w[n*4]
+ * (float32): four joint influences per Gaussian (weight 0 for unused
+ * slots).  joints[n_joints*12]: device float32 3x4 row-major joint
+ * transforms M_k, n_joints in 1..256; an index >= n_joints contributes
+ * nothing.  Writes posop[n*4] (deformed mean, opacity copied) and
+ * cov[n*6], computed in float64 from the decoded canonical values and
+ * rounded once to binary16 (the identity pose reproduces the input bits);
+ * outputs must not alias the canonical inputs.  SH pass through unchanged:
+ * render the result with gs_preprocess_packed and the canonical sh16.
+ */
+int32_t gs_lbs_deform(int64_t n, const uint16_t* canon_posop, const uint16_t* canon_cov,
+                      const uint8_t* joint_idx, const float* joint_w, int32_t n_joints,
+                      const float* joints, uint16_t* posop, uint16_t* cov, void* stream);
+
+/*
  * gs_preprocess_packed -- gs_preprocess_assets from the pre-packed layout:
  * the same culls, records, depth keys, tile rects and counts, computed from
  * the binary16 mean, opacity, covariance and SH (exactly as decoded).  The

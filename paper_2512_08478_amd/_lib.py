@@ -32,7 +32,7 @@ EXPORTED = (
     "gs_rasterize", "gs_rasterize_backward", "gs_trace_enable", "gs_trace_read",
     "gs_preprocess_assets", "gs_rasterize_backward_assets", "gs_rasterize_backward_2d",
     "gs_preprocess_backward_views", "gs_sort_pairs32", "gs_packed_sh_stride", "gs_prepack",
-    "gs_preprocess_packed", "gs_rasterize_mesh", "gs_rasterize_backward_2d_mesh",
+    "gs_preprocess_packed", "gs_rasterize_mesh", "gs_rasterize_backward_2d_mesh", "gs_lbs_deform",
 )
 BWD_VIEWS_PER_LAUNCH = 8
 GRAD2D_STRIDE = 12  # floats per Gaussian in a 2-D gradient record
@@ -148,6 +148,8 @@ def load():
     lib.gs_rasterize_mesh.argtypes = [P, P, P, CAM, SET, P, P, P, P, P, P, P]
     lib.gs_rasterize_backward_2d_mesh.restype = I32
     lib.gs_rasterize_backward_2d_mesh.argtypes = [P, P, P, CAM, SET, P, P, P, P, I64, P, P]
+    lib.gs_lbs_deform.restype = I32
+    lib.gs_lbs_deform.argtypes = [I64, P, P, P, P, I32, P, P, P, P]
     lib.gs_trace_enable.restype = I32
     lib.gs_trace_enable.argtypes = [I32]
     lib.gs_trace_read.restype = I32

@@ -351,6 +351,25 @@ int32_t gs_prepack(int64_t n, const float* means, const float* log_scales, const
   return GS_OK;
 }
 
+int32_t gs_lbs_deform(int64_t n, const uint16_t* canon_posop, const uint16_t* canon_cov,
+                      const uint8_t* joint_idx, const float* joint_w, int32_t n_joints,
+                      const float* joints, uint16_t* posop, uint16_t* cov, void* stream) {
+  if (n < 0 || n >= kMaxN || n_joints < 1 || n_joints > 256) return GS_ERR_INVALID_ARGUMENT;
+  int32_t r;
+  if ((r = check_dev(joints))) return r;
+  if (n > 0 && ((r = check_dev(canon_posop)) || (r = check_dev(canon_cov)) ||
+                (r = check_dev(joint_idx)) || (r = check_dev(joint_w)) ||
+                (r = check_dev(posop)) || (r = check_dev(cov))))
+    return r;
+  if (n > 0 && (posop == canon_posop || cov == canon_cov)) return GS_ERR_INVALID_ARGUMENT;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = gs::launch_lbs((int)n, canon_posop, canon_cov, joint_idx, joint_w,
+                                      n_joints, joints, posop, cov, st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
 int32_t gs_preprocess_packed(int32_t n_assets, const gs_asset* assets, int64_t n,
                              const uint16_t* posop, const uint16_t* cov, const uint16_t* sh16,
                              int32_t sh_degree, const gs_camera* cam, const gs_settings* set,

@@ -107,6 +107,12 @@ int packed_sh_stride(int degree);
 hipError_t launch_prepack(int n, const float* means, const float* log_scales, const float* quats,
                           const float* logits, const float* sh, int degree, uint16_t* posop,
                           uint16_t* cov, uint16_t* sh16, hipStream_t st);
+// Linear blend skinning: packed canonical (posop, cov) -> deformed, with
+// 4 joint influences per Gaussian (u8 indices, f32 weights) and up to 256
+// 3x4 joint transforms.
+hipError_t launch_lbs(int n, const uint16_t* canon_posop, const uint16_t* canon_cov,
+                      const uint8_t* joint_idx, const float* joint_w, int n_joints,
+                      const float* joints, uint16_t* posop, uint16_t* cov, hipStream_t st);
 hipError_t launch_preprocess_packed(int n, const uint16_t* posop, const uint16_t* cov,
                                     const uint16_t* sh16, int degree, const CamK& cam,
                                     const SetK& set, gs_splat* splats, uint32_t* depth_keys,

@@ -1,5 +1,6 @@
 // FP16 pre-pack and the preprocess that reads it (Algorithm 1's Pre-pack
-// step and Section 3.4's FP16 layout).
+// step and Section 3.4's FP16 layout), and the linear-blend-skinning
+// pre-decoder that deforms packed canonical Gaussians (Section 3.3).
 //
 // Pre-pack, once per asset: the covariance Sigma = R diag(s^2) R^T is formed
 // from scale and rotation, and the mean, the activated opacity, the upper
@@ -226,6 +227,85 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_packed(
   block_counts(tiles, partial);
 }
 
+// Linear blend skinning of pre-packed canonical Gaussians (the avatar
+// pre-decoder of Section 3.3, Eqs. 5-6): T_i = sum_k w_ik M_k = [R_i | t_i],
+// mu_i = R_i mu^_i + t_i, Sigma_i = R_i Sigma^_i R_i^T.  The joint
+// transforms are staged in LDS, followed by one all-zero transform that
+// every index >= n_joints is clamped to (it contributes nothing); the
+// blend and both products run in float64 from the exactly decoded
+// canonical values and are rounded once to binary16, so the identity pose
+// reproduces the canonical values.  Opacity is copied.  Each thread skins
+// kLbsItems Gaussians a block-width apart, with all their loads issued
+// before the first is computed, which also spreads the LDS staging over
+// more Gaussians.
+constexpr int kMaxJoints = 256;
+constexpr int kInfluences = 4;
+constexpr int kLbsItems = 4;
+
+__global__ __launch_bounds__(kBlock) void k_lbs(
+    int n, const uint2* __restrict__ canon_posop, const uint32_t* __restrict__ canon_cov,
+    const uint32_t* __restrict__ joint_idx, const float4* __restrict__ joint_w, int n_joints,
+    const float* __restrict__ joints, uint2* __restrict__ posop, uint32_t* __restrict__ cov) {
+  __shared__ float s_m[(kMaxJoints + 1) * 12];
+  for (int e = threadIdx.x; e < (n_joints + 1) * 12; e += kBlock)
+    s_m[e] = e < n_joints * 12 ? joints[e] : 0.f;
+  __syncthreads();
+  const int base = blockIdx.x * kBlock * kLbsItems + threadIdx.x;
+  uint2 po[kLbsItems];
+  uint32_t c0[kLbsItems], c1[kLbsItems], c2[kLbsItems], ji[kLbsItems];
+  float4 wv[kLbsItems];
+#pragma unroll
+  for (int u = 0; u < kLbsItems; ++u) {
+    const int i = min(base + u * kBlock, n - 1);  // clamped: past-the-end items are not stored
+    po[u] = canon_posop[i];
+    c0[u] = canon_cov[3 * i];
+    c1[u] = canon_cov[3 * i + 1];
+    c2[u] = canon_cov[3 * i + 2];
+    ji[u] = joint_idx[i];
+    wv[u] = joint_w[i];
+  }
+#pragma unroll
+  for (int u = 0; u < kLbsItems; ++u) {
+    const int i = base + u * kBlock;
+    if (i >= n) break;
+    const float wk[kInfluences] = {wv[u].x, wv[u].y, wv[u].z, wv[u].w};
+    double T[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) T[e] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kInfluences; ++k) {
+      const int j = min((int)((ji[u] >> (8 * k)) & 0xFFu), n_joints);
+      const float* m = s_m + 12 * j;
+      const double w = wk[k];
+#pragma unroll
+      for (int e = 0; e < 12; ++e) T[e] += w * (double)m[e];
+    }
+    const double mu[3] = {f16_to_f32(po[u].x), f16_to_f32(po[u].x >> 16), f16_to_f32(po[u].y)};
+    double md[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      md[r] = T[4 * r] * mu[0] + T[4 * r + 1] * mu[1] + T[4 * r + 2] * mu[2] + T[4 * r + 3];
+    const double S[9] = {f16_to_f32(c0[u]),       f16_to_f32(c0[u] >> 16), f16_to_f32(c1[u]),
+                         f16_to_f32(c0[u] >> 16), f16_to_f32(c1[u] >> 16), f16_to_f32(c2[u]),
+                         f16_to_f32(c1[u]),       f16_to_f32(c2[u]),       f16_to_f32(c2[u] >> 16)};
+    // RS = R Sigma^, then Sigma = RS R^T (upper triangle)
+    double RS[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        RS[3 * r + c] = T[4 * r] * S[c] + T[4 * r + 1] * S[3 + c] + T[4 * r + 2] * S[6 + c];
+    auto sig = [&](int r, int c) {
+      return RS[3 * r] * T[4 * c] + RS[3 * r + 1] * T[4 * c + 1] + RS[3 * r + 2] * T[4 * c + 2];
+    };
+    posop[i] = make_uint2(pack2(f64_to_f16(md[0]), f64_to_f16(md[1])),
+                          pack2(f64_to_f16(md[2]), (uint16_t)(po[u].y >> 16)));
+    cov[3 * i] = pack2(f64_to_f16(sig(0, 0)), f64_to_f16(sig(0, 1)));
+    cov[3 * i + 1] = pack2(f64_to_f16(sig(0, 2)), f64_to_f16(sig(1, 1)));
+    cov[3 * i + 2] = pack2(f64_to_f16(sig(1, 2)), f64_to_f16(sig(2, 2)));
+  }
+}
+
 }  // namespace
 
 int packed_sh_stride(int degree) {
@@ -256,6 +336,22 @@ hipError_t launch_prepack(int n, const float* means, const float* log_scales, co
       default: GS_PP(3); break;
     }
 #undef GS_PP
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lbs(int n, const uint16_t* canon_posop, const uint16_t* canon_cov,
+                      const uint8_t* joint_idx, const float* joint_w, int n_joints,
+                      const float* joints, uint16_t* posop, uint16_t* cov, hipStream_t st) {
+  if (n > 0) {
+    trace_mark(st, "lbs");
+    const int per_block = kBlock * kLbsItems;
+    hipLaunchKernelGGL(k_lbs, dim3((n + per_block - 1) / per_block), dim3(kBlock), 0, st, n,
+                       reinterpret_cast<const uint2*>(canon_posop),
+                       reinterpret_cast<const uint32_t*>(canon_cov),
+                       reinterpret_cast<const uint32_t*>(joint_idx),
+                       reinterpret_cast<const float4*>(joint_w), n_joints, joints,
+                       reinterpret_cast<uint2*>(posop), reinterpret_cast<uint32_t*>(cov));
   }
   return hipGetLastError();
 }

@@ -162,6 +162,26 @@ class Renderer:
         L.check(st, "gs_prepack")
         return PackedParams(posop, cov, sh16, p.sh_degree, p.model, p.assets)
 
+    def lbs_deform(self, canon: PackedParams, joint_idx, joint_w, joints, out=None) -> PackedParams:
+        """Linear blend skinning of the packed canonical Gaussians (the avatar
+        pre-decoder): joint_idx (n, 4) uint8, joint_w (n, 4) float32, joints
+        (K, 3, 4) float32 device tensors.  Returns the deformed PackedParams
+        (new posop / cov, or those of `out`; SH shared with `canon`)."""
+        lib = L.load()
+        n = canon.n
+        if out is None:
+            out = PackedParams(torch.empty_like(canon.posop), torch.empty_like(canon.cov),
+                               canon.sh16, canon.sh_degree, canon.model, canon.assets)
+        idx = joint_idx.to(torch.uint8).contiguous()
+        w = joint_w.to(torch.float32).contiguous()
+        M = joints.to(torch.float32).contiguous()
+        if idx.shape != (n, 4) or w.shape != (n, 4):
+            raise ValueError("joint_idx and joint_w must be (n, 4)")
+        st = lib.gs_lbs_deform(n, _p(canon.posop), _p(canon.cov), _p(idx), _p(w),
+                               int(M.numel() // 12), _p(M), _p(out.posop), _p(out.cov), _stream())
+        L.check(st, "gs_lbs_deform")
+        return out
+
     def preprocess(self, p, cam, reuse=True):
         """Eq. 1 for every Gaussian of `p` (GaussianParams, or PackedParams
         for the pre-packed path): (splats, depth keys, tile rects, counts)."""

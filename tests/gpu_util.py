@@ -127,3 +127,16 @@ def sampled_pixels(cam, n, seed):
     corners = np.array([[0, 0], [cam.width - 1, cam.height - 1], [cam.width // 2, cam.height // 2],
                         [cam.width - 1, 0], [0, cam.height - 1]])
     return np.concatenate([pix, corners]).astype(np.int32)
+
+
+def near_tie(x, h, scale=None):
+    """True where float64 x lies within float64 rounding of the midpoint
+    between binary16 h and a neighbour (either answer is then correct).
+    The rounding of x is taken relative to max(|x|, scale): pass the
+    magnitude of the terms x was summed from where they may cancel."""
+    x = np.asarray(x, np.float64)
+    hf = h.astype(np.float64)
+    sp = np.spacing(np.abs(h)).astype(np.float64)
+    mid = np.abs(np.abs(x) - np.abs(hf))
+    mag = np.abs(x) if scale is None else np.maximum(np.abs(x), scale)
+    return np.abs(mid - 0.5 * sp) <= 1e-12 * np.maximum(mag, 1e-30)

@@ -288,3 +288,17 @@ def test_mesh_entry_points_validation(lib):
                                                  mr, G(3), G(4), G(5), n, G(7), None)
     assert rb(mr=bad) == L.GS_ERR_MISALIGNED
     assert rb(n=-1) == L.GS_ERR_INVALID_ARGUMENT
+
+
+def test_lbs_validation(lib):
+    F = ctypes.c_void_p(FAKE)
+    G = lambda k: ctypes.c_void_p(FAKE + 4096 * k)
+
+    def lb(n=8, nj=55, joints=G(5), po=G(6), cv=G(7)):
+        return lib.gs_lbs_deform(n, F, G(1), G(2), G(3), nj, joints, po, cv, None)
+    assert lb(nj=0) == L.GS_ERR_INVALID_ARGUMENT
+    assert lb(nj=257) == L.GS_ERR_INVALID_ARGUMENT
+    assert lb(n=-1) == L.GS_ERR_INVALID_ARGUMENT
+    assert lb(joints=None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lb(po=F) == L.GS_ERR_INVALID_ARGUMENT          # aliases the canonical input
+    assert lb(cv=ctypes.c_void_p(FAKE + 7 * 4096 + 2)) == L.GS_ERR_MISALIGNED

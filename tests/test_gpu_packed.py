@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from paper_2512_08478_amd import scenes as S
-from gpu_util import (compare_records, extra_pairs_harmless, image_check, print_case,
+from gpu_util import (compare_records, extra_pairs_harmless, image_check, near_tie, print_case,
                       sampled_pixels, splats_np)
 
 pytestmark = pytest.mark.gpu
@@ -52,16 +52,6 @@ def decoded(pk, model=None):
                 sh_degree=pk.sh_degree, model=model)
 
 
-def near_tie(x, h):
-    """True where float64 x lies within float64 rounding of the midpoint
-    between binary16 h and a neighbour (either answer is then correct)."""
-    x = np.asarray(x, np.float64)
-    hf = h.astype(np.float64)
-    sp = np.spacing(np.abs(h)).astype(np.float64)
-    mid = np.abs(np.abs(x) - np.abs(hf))
-    return np.abs(mid - 0.5 * sp) <= 1e-12 * np.maximum(np.abs(x), 1e-30)
-
-
 @pytest.mark.parametrize("deg", [0, 1, 2, 3])
 def test_prepack_bitexact_vs_oracle(R, orc, deg):
     print_case(f"prepack bit-exact, sh degree {deg}")
@@ -83,9 +73,11 @@ def test_prepack_bitexact_vs_oracle(R, orc, deg):
     exact = Sig[:, [0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
     logit = sc.opacity_logits.astype(np.float64)
     o_exact = 1 / (1 + np.exp(-logit))
-    for got, want, x in ((po[:, 3], ref["opacity"], o_exact), (cv, ref["cov6"], exact)):
+    cscale = np.abs(exact).max(1, keepdims=True)
+    for got, want, x, scale in ((po[:, 3], ref["opacity"], o_exact, None),
+                                (cv, ref["cov6"], exact, cscale)):
         diff = got.view(np.uint16) != want.view(np.uint16)
-        tie = near_tie(x, want)
+        tie = near_tie(x, want, scale)
         assert not (diff & ~tie).any(), np.argwhere(diff & ~tie)[:5]
         print(f"differing {int(diff.sum())} (all within float64 rounding of a tie: "
               f"{int(tie.sum())} such values)")
