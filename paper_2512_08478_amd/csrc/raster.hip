@@ -31,10 +31,9 @@
 // the pixel stops at the first such splat.  The mesh colour, if given,
 // takes the place of the background behind the Gaussians.
 //
-// Quadrants are assigned XCD-major: the hardware deals consecutive
-// workgroups round-robin to the 8 XCDs, so workgroup b works on quadrant
-// (b % 8) * ceil(units/8) + b / 8; each XCD's L2 sees one contiguous band
-// of tiles, whose splats it shares.
+// Quadrants are dealt to the XCDs block-cyclically (see xcd_tile): each
+// XCD's L2 shares the splats of runs of neighbouring tiles, and dense
+// image regions are spread over all XCDs.
 #include "gs_device.h"
 #include "gs_internal.h"
 
@@ -44,6 +43,7 @@ namespace {
 constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr int kXcds = 8;
+constexpr int kRunTiles = 16;  // tiles per XCD run
 
 // 2^e on the hardware exponential unit.  Only exponents at or above
 // log2(alpha_min) reach it, far from the denormal range, so the library's
@@ -51,12 +51,20 @@ constexpr int kXcds = 8;
 // see the same alpha.
 __device__ __forceinline__ float hw_exp2(float e) { return __builtin_amdgcn_exp2f(e); }
 
-__device__ __forceinline__ int xcd_tile(int b, int tiles) {
-  const int chunk = (tiles + kXcds - 1) / kXcds;
-  return (b % kXcds) * chunk + b / kXcds;
+// Block-cyclic over the XCDs: runs of `run` consecutive units (whole
+// tiles' quadrants, neighbouring tiles of one tile row) go to the XCDs in
+// turn, so every XCD's L2 sees coherent runs while dense image regions are
+// spread over all eight.  Units past the end return at once.
+__device__ __forceinline__ int xcd_tile(int b, int run) {
+  const int x = b % kXcds, i = b / kXcds;
+  return ((i / run) * kXcds + x) * run + i % run;
 }
 
-inline int xcd_grid(int tiles) { return ((tiles + kXcds - 1) / kXcds) * kXcds; }
+inline int xcd_grid(int units, int run) {
+  const int per = kXcds * run;
+  return (units + per - 1) / per * per;
+}
+
 
 // LDS staging of one batch of splats for one 8x8 quadrant, shared by the
 // forward and backward kernels.  Row terms are stored row-contiguous per
@@ -122,12 +130,18 @@ __device__ __forceinline__ void stage_params(StageT<DEPTH>& S, int j, const Spla
   if constexpr (DEPTH) S.dep[j] = r.depth;
 }
 
-// Phase 2 of staging: the row terms of the staged splats that reach the
-// quadrant (hits: their batch-slot mask), one (splat, row) pair per lane
-// and step.  Returns the mask.
+// Phase 2 of staging: the row terms of the staged splats whose bbox
+// reaches the quadrant, one (splat, row) pair per lane and step.  Each
+// pair also finds the row's largest exponent: e(lx) = rt - qa' (ub + lx)^2
+// is concave in lx, so over lx = 0..7 it peaks at the floor or the ceiling
+// of -ub (clamped).  A splat none of whose rows reaches log2(alpha_min)
+// blends into no pixel of the quadrant and is dropped from the mask; the
+// test keeps a margin far above the rounding of e, so it never drops a
+// splat that a pixel would blend.  Returns the mask of the remaining
+// splats' batch slots.
 template <bool DEPTH>
 __device__ __forceinline__ uint64_t stage_rows(StageT<DEPTH>& S, int cnt, int qx0, int qy0,
-                                               int lane) {
+                                               int lane, float log2_tau) {
   const uint64_t hits = ballot(lane < cnt && S.hit[lane < cnt ? lane : 0] != 0u);
   if ((hits >> lane) & 1ull)
     S.list[__builtin_popcountll(hits & ((1ull << lane) - 1ull))] = (uint32_t)lane;
@@ -148,7 +162,7 @@ __device__ __forceinline__ uint64_t stage_rows(StageT<DEPTH>& S, int cnt, int qx
 // it walks the tile's whole list and composites the splats that reach its
 // quadrant.  Waves of one tile never wait on each other, and a quadrant
 // whose pixels have all stopped leaves at once.
-template <int TW, int TH, bool MESH>
+template <int TW, int TH, bool MESH, bool COUNT>
 __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ splats,
                                                const uint32_t* __restrict__ values,
                                                const uint32_t* __restrict__ ranges,
@@ -162,7 +176,7 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ StageT<MESH> S;
   const int tiles = set.tiles_x * set.tiles_y;
-  const int unit = xcd_tile(blockIdx.x, tiles * NQ);  // quadrants of a tile stay on one XCD
+  const int unit = xcd_tile(blockIdx.x, kRunTiles * NQ);
   if (unit >= tiles * NQ) return;
   const int tile = unit / NQ, q = unit % NQ;
   const int tx0 = (tile % set.tiles_x) * TW + 8 * (q % QX);
@@ -174,11 +188,15 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   const bool inside = px < W && py < H;
   const float lxf = (float)lx;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-  const float log2_tau = set.log2_tau;
+  const float log2_tau = set.log2_tau, t_eps = set.t_eps;
+  const float amax = set.amax;
 
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  // A pixel composites while T >= t_eps (blend, then stop: T only falls
+  // on a blend); pixels outside the image start at T = 0 and never blend.
+  float T = inside ? 1.f : 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t lastc = 0, nb = 0;
   bool done = !inside;
+  float live = 1.f;  // with a mesh: drops to 0 at the first hidden splat
   // mesh depth at this pixel (splats deeper than it are hidden)
   float D = __builtin_inff();
   if (MESH && inside) D = mesh_depth[py * W + px];
@@ -203,31 +221,27 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     const SplatRec r_next = load_splat(splats, g_next);
     const uint32_t g_after = values[min(bs + 2 * kBatch + lane, lastpos)];
     __syncthreads();
-    uint64_t m = stage_rows(S, cnt, tx0, ty0, lane);
+    uint64_t m = stage_rows(S, cnt, tx0, ty0, lane, log2_tau);
     __syncthreads();
     // Lanes never branch apart here: a pair a lane must not blend (weight
     // below alpha_min, or the pixel already stopped) gets alpha = 0, which
     // leaves C and T bitwise unchanged; only wave-uniform branches remain
     // (no lane blends this splat; every pixel of the wave has stopped).
-    // `live` is 1 while the pixel composites and 0 once it stopped (or
-    // lies outside the image), kept as a float so that the loop needs no
-    // lane-mask bookkeeping.
-    float live = done ? 0.f : 1.f;
     // two hit splats per step: both splats' LDS reads are issued before
     // the first one blends, hiding one read latency per pair
     auto blend = [&](int j, float e, const float4& h) {
       if constexpr (MESH) live = S.dep[j] > D ? 0.f : live;  // hidden from here on
-      const bool take = e >= log2_tau && live != 0.f;
+      const bool take = e >= log2_tau && T >= t_eps && (!MESH || live != 0.f);
       if (!ballot(take)) return;
-      const float alpha = take ? fminf(set.amax, hw_exp2(e)) : 0.f;
+      // min(alpha_max, 2^e) as a median (2^e > 0): one instruction
+      const float alpha = take ? __builtin_amdgcn_fmed3f(hw_exp2(e), 0.f, amax) : 0.f;
       const float w = alpha * T;
       C0 = fmaf(w, h.y, C0);
       C1 = fmaf(w, h.z, C1);
       C2 = fmaf(w, h.w, C2);
       T = T * (1.f - alpha);
       lastc = take ? bs + j + 1 - start : lastc;
-      nb += take ? 1u : 0u;
-      live = T < set.t_eps ? 0.f : live;
+      if constexpr (COUNT) nb += take ? 1u : 0u;
     };
     while (m) {
       const int j0 = __builtin_ctzll(m);
@@ -241,9 +255,9 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       const float e1 = fmaf(-h1.x, u1 * u1, S.rt[j1][row]);
       blend(j0, e0, h0);
       if (two) blend(j1, e1, h1);
-      if (!ballot(live != 0.f)) break;
+      if (!ballot(T >= t_eps && (!MESH || live != 0.f))) break;
     }
-    done = live == 0.f;
+    done = !(T >= t_eps) || (MESH && live == 0.f);
     g_cur = g_next;
     r_cur = r_next;
     g_next = g_after;
@@ -260,7 +274,7 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
         make_float4(fmaf(T, b0, C0), fmaf(T, b1, C1), fmaf(T, b2, C2), 1.f - T);
     T_final[p] = T;
     last[p] = lastc;
-    if (n_blend) n_blend[p] = nb;
+    if (COUNT) n_blend[p] = nb;
   }
 }
 
@@ -295,7 +309,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
   __shared__ Stage S;
   __shared__ float s_red[8][12];  // per 8-lane group (pixel row): its 9 gradient sums
   const int tiles = set.tiles_x * set.tiles_y;
-  const int unit = xcd_tile(blockIdx.x, tiles * NQ);  // quadrants of a tile stay on one XCD
+  const int unit = xcd_tile(blockIdx.x, kRunTiles * NQ);
   if (unit >= tiles * NQ) return;
   const int tile = unit / NQ, q = unit % NQ;
   const int tx0 = (tile % set.tiles_x) * TW + 8 * (q % QX);
@@ -343,7 +357,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       stage_params(S, lane, load_splat(splats, g), g, tx0, ty0);
     }
     __syncthreads();
-    uint64_t m = stage_rows(S, cnt, tx0, ty0, lane);
+    uint64_t m = stage_rows(S, cnt, tx0, ty0, lane, log2_tau);
     __syncthreads();
     // Lanes never branch apart: a pair a lane must not revisit (position at
     // or past its `last`, or weight below alpha_min) gets alpha = 0, which
@@ -353,7 +367,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       if (!ballot(take)) return;
       const float4 x = S.aux[j];  // qb, qc', my, 1 / opacity
       const float gw = take ? hw_exp2(e) : 0.f;
-      const float alpha = fminf(set.amax, gw);
+      const float alpha = __builtin_amdgcn_fmed3f(gw, 0.f, set.amax);  // as the forward
       const float om = 1.f - alpha;
       // T before this splat; 1 - alpha >= 1 - alpha_max, far from 0
       const float Ti = take ? T * __builtin_amdgcn_rcpf(om) : T;
@@ -419,14 +433,13 @@ void raster_fwd(const gs_splat* splats, const uint32_t* values, const uint32_t* 
                 const SetK& set, int W, int H, const float* mesh_depth, const float* mesh_rgb,
                 float* image, float* T_final, uint32_t* last, uint32_t* n_blend, hipStream_t st) {
   const int units = set.tiles_x * set.tiles_y * (TW / 8) * (TH / 8);
-  if (mesh_depth)
-    hipLaunchKernelGGL((k_raster<TW, TH, true>), dim3(xcd_grid(units)), dim3(64), 0, st, splats,
-                       values, ranges, set, W, H, mesh_depth, mesh_rgb, image, T_final, last,
-                       n_blend);
-  else
-    hipLaunchKernelGGL((k_raster<TW, TH, false>), dim3(xcd_grid(units)), dim3(64), 0, st, splats,
-                       values, ranges, set, W, H, nullptr, mesh_rgb, image, T_final, last,
-                       n_blend);
+#define GS_K(M, C) hipLaunchKernelGGL((k_raster<TW, TH, M, C>), dim3(xcd_grid(units, kRunTiles * (TW / 8) * (TH / 8))), dim3(64), 0, st, splats, values, ranges, set, W, H, mesh_depth, mesh_rgb, image, T_final, last, n_blend)
+  if (mesh_depth) {
+    if (n_blend) GS_K(true, true); else GS_K(true, false);
+  } else {
+    if (n_blend) GS_K(false, true); else GS_K(false, false);
+  }
+#undef GS_K
 }
 
 template <int TW, int TH>
@@ -434,7 +447,7 @@ void raster_bwd(const gs_splat* splats, const uint32_t* values, const uint32_t* 
                 const SetK& set, int W, int H, const float* bg_rgb, const float* T_final,
                 const uint32_t* last, const float* dL_dimage, float* grad2d, hipStream_t st) {
   const int units = set.tiles_x * set.tiles_y * (TW / 8) * (TH / 8);
-  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(xcd_grid(units)), dim3(64), 0, st,
+  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(xcd_grid(units, kRunTiles * (TW / 8) * (TH / 8))), dim3(64), 0, st,
                      splats, values, ranges, set, W, H, bg_rgb, T_final, last, dL_dimage, grad2d);
 }
 
