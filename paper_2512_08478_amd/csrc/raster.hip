@@ -191,12 +191,14 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   const float log2_tau = set.log2_tau, t_eps = set.t_eps;
   const float amax = set.amax;
 
-  // A pixel composites while T >= t_eps (blend, then stop: T only falls
-  // on a blend); pixels outside the image start at T = 0 and never blend.
-  float T = inside ? 1.f : 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t lastc = 0, nb = 0;
   bool done = !inside;
-  float live = 1.f;  // with a mesh: drops to 0 at the first hidden splat
+  // `live` is 1 while the pixel composites and 0 once it stopped (T fell
+  // below t_eps, a mesh hides the splats from here on, or the pixel lies
+  // outside the image), kept as a float so that the loop needs no
+  // lane-mask bookkeeping
+  float live = 1.f;
   // mesh depth at this pixel (splats deeper than it are hidden)
   float D = __builtin_inff();
   if (MESH && inside) D = mesh_depth[py * W + px];
@@ -229,9 +231,10 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     // (no lane blends this splat; every pixel of the wave has stopped).
     // two hit splats per step: both splats' LDS reads are issued before
     // the first one blends, hiding one read latency per pair
+    live = done ? 0.f : 1.f;
     auto blend = [&](int j, float e, const float4& h) {
       if constexpr (MESH) live = S.dep[j] > D ? 0.f : live;  // hidden from here on
-      const bool take = e >= log2_tau && T >= t_eps && (!MESH || live != 0.f);
+      const bool take = e >= log2_tau && live != 0.f;
       if (!ballot(take)) return;
       // min(alpha_max, 2^e) as a median (2^e > 0): one instruction
       const float alpha = take ? __builtin_amdgcn_fmed3f(hw_exp2(e), 0.f, amax) : 0.f;
@@ -242,6 +245,7 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       T = T * (1.f - alpha);
       lastc = take ? bs + j + 1 - start : lastc;
       if constexpr (COUNT) nb += take ? 1u : 0u;
+      live = T < t_eps ? 0.f : live;
     };
     while (m) {
       const int j0 = __builtin_ctzll(m);
@@ -255,9 +259,9 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       const float e1 = fmaf(-h1.x, u1 * u1, S.rt[j1][row]);
       blend(j0, e0, h0);
       if (two) blend(j1, e1, h1);
-      if (!ballot(T >= t_eps && (!MESH || live != 0.f))) break;
+      if (!ballot(live != 0.f)) break;
     }
-    done = !(T >= t_eps) || (MESH && live == 0.f);
+    done = live == 0.f;
     g_cur = g_next;
     r_cur = r_next;
     g_next = g_after;
