@@ -33,7 +33,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 FLOPS_PER_BLEND = 24
 
 SORT_KERNELS = ("sort_init", "radix_hist", "depth_pass", "kg_count", "kg_scan", "keygen",
-                "tile_pass", "tile_ranges")
+                "tile_pass", "tile_ranges", "tile_order")
 HBM_KERNELS = ("preprocess", "preprocess_packed", "lbs", "depth_pass", "keygen", "kg_count", "tile_pass",
                "tile_ranges", "preprocess_bwd")
 ALU_KERNELS = ("raster", "raster_mesh", "raster_bwd")
@@ -67,6 +67,8 @@ def parse():
                     help="WxH, or auto: the autotuner picks tile shape and digit width")
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--sort-mode", type=int, default=0)
+    ap.add_argument("--raster-order", type=int, default=1,
+                    help="with a fixed --tile: 1 = longest tile lists first, 0 = spatial runs")
     ap.add_argument("--packed", action="store_true",
                     help="forward from the FP16 pre-packed inputs (pre-packed once, untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -209,13 +211,16 @@ def main():
         best, table = autotune_view(p, cam, backward=backward, target=target,
                                     base_settings=dict(sort_mode=args.sort_mode), mesh=mesh)
         tw, th, bits = best["tile_w"], best["tile_h"], best["radix_bits"]
-        tuned = [[f"{t[0]['tile_w']}x{t[0]['tile_h']}/{t[0]['radix_bits']}b",
+        order = best["raster_order"]
+        tuned = [[f"{t[0]['tile_w']}x{t[0]['tile_h']}/{t[0]['radix_bits']}b/o{t[0]['raster_order']}",
                   round(t[1] * 1e3, 4)] for t in table]
     else:
         tw, th = map(int, args.tile.split("x"))
         bits = args.radix_bits
+        order = args.raster_order
     args.radix_bits = bits
-    R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=args.sort_mode))
+    R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=args.sort_mode,
+                      raster_order=order))
 
     # first frame: read the instance count once to size the sort buffers
     fr = R.forward(p, cam, mesh=mesh)
@@ -326,7 +331,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload] + (
                        ", FP16 pre-packed inputs" if args.packed and args.workload != "avatar"
                        else ""),
-                   "n_gaussians": sc.n, "width": W,
+                   "n_gaussians": sc.n, "width": W, "raster_order": order,
                    "height": H, "tile": f"{tw}x{th}", "radix_bits": args.radix_bits,
                    "visible": n_vis, "instances": inst, "key_bits": key_bits,
                    "depth_passes": passes[0], "tile_passes": passes[1]},

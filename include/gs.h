@@ -78,6 +78,12 @@ typedef struct gs_camera {
  *                    kernels; no workgroup waits on another); 1: onesweep
  *                    passes with decoupled look-back between workgroups.
  *                    Both give the same (unique) stable result.
+ *   raster_order 1   order in which the compositing kernels take the tiles:
+ *                    0: runs of neighbouring tiles dealt to the GPU's XCDs
+ *                    in turn; 1: tiles with the longest splat lists first
+ *                    (gs_sort then also writes that order).  gs_sort and
+ *                    the compositing calls of a frame must use the same
+ *                    value.  Images do not depend on it.
  */
 typedef struct gs_settings {
   int32_t tile_w, tile_h;
@@ -89,6 +95,7 @@ typedef struct gs_settings {
   float bg[3];
   int32_t radix_bits;
   int32_t sort_mode;
+  int32_t raster_order;
 } gs_settings;
 
 /*
@@ -304,8 +311,11 @@ int32_t gs_preprocess_packed(int32_t n_assets, const gs_asset* assets, int64_t n
  *
  * Reads splats[n], depth_keys[n], tile_rects[2n] and counts (device, from
  * gs_preprocess).  Writes values[capacity] (u32 Gaussian index per sorted
- * instance), tile_ranges[2*tiles] (u32 [start, end) of each tile in the
- * sorted list, tiles = ceil(W/tile_w) * ceil(H/tile_h), row-major) and, if
+ * instance), tile_ranges[3*tiles] (u32: first the [start, end) of each
+ * tile in the sorted list, tiles = ceil(W/tile_w) * ceil(H/tile_h),
+ * row-major; then, with raster_order 1, the tiles in the order the
+ * compositing kernels take them: by decreasing floor(log2(list length + 1)),
+ * in an unspecified order within a class) and, if
  * `keys` is not NULL, keys[capacity] (the sorted u64 keys above).  Only the
  * first counts[0] entries are meaningful.
  *

@@ -63,7 +63,8 @@ class GsSettings(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("eps2d", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_eps", ctypes.c_float), ("clip", ctypes.c_float), ("bg", ctypes.c_float * 3),
-                ("radix_bits", ctypes.c_int32), ("sort_mode", ctypes.c_int32)]
+                ("radix_bits", ctypes.c_int32), ("sort_mode", ctypes.c_int32),
+                ("raster_order", ctypes.c_int32)]
 
 
 class GsAsset(ctypes.Structure):

@@ -31,6 +31,7 @@ from .render import GaussianParams, Renderer
 TILE_SHAPES = ((16, 16), (16, 8), (32, 8), (8, 8), (32, 16))
 RADIX_BITS = (8, 7, 6)
 SORT_MODES = (0, 1)
+RASTER_ORDERS = (1, 0)
 
 
 def l1_grad(image, target):
@@ -66,7 +67,7 @@ class BatchRenderer:
     def settings(self):
         s = self.R.settings
         return dict(tile_w=s.tile_w, tile_h=s.tile_h, radix_bits=s.radix_bits,
-                    sort_mode=s.sort_mode)
+                    sort_mode=s.sort_mode, raster_order=s.raster_order)
 
     def plan(self):
         """Per-view instance capacities from one counting pass (syncs once per view)."""
@@ -157,10 +158,11 @@ def _time_batch(br: BatchRenderer, reps: int):
 
 
 def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
-             tiles=TILE_SHAPES, bits=RADIX_BITS, modes=SORT_MODES, log=None):
+             tiles=TILE_SHAPES, bits=RADIX_BITS, modes=SORT_MODES, orders=RASTER_ORDERS, log=None):
     """Coordinate search: tile shape (at 8-bit digits, mode 0), then digit
-    width, then sort mode, each by the wall time of whole eager batches.
-    Returns (settings dict, [(settings, seconds)])."""
+    width, then sort mode, then the compositing order of the tiles, each by
+    the wall time of whole eager batches.  Returns (settings dict,
+    [(settings, seconds)])."""
     base = dict(base_settings or {})
     table = []
 
@@ -175,7 +177,8 @@ def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
         del br
         return t
 
-    best = dict(tile_w=tiles[0][0], tile_h=tiles[0][1], radix_bits=bits[0], sort_mode=modes[0])
+    best = dict(tile_w=tiles[0][0], tile_h=tiles[0][1], radix_bits=bits[0], sort_mode=modes[0],
+                raster_order=orders[0])
     best_t = None
     for tw, th in tiles:
         t = measure(dict(best, tile_w=tw, tile_h=th))
@@ -189,12 +192,18 @@ def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
         t = measure(dict(best, sort_mode=m))
         if t < best_t:
             best_t, best = t, dict(best, sort_mode=m)
+    for o in orders[1:]:
+        t = measure(dict(best, raster_order=o))
+        if t < best_t:
+            best_t, best = t, dict(best, raster_order=o)
     return dict(base, **best), table
 
 
 def autotune_view(params: GaussianParams, cam, backward=False, target=None, reps=3,
-                  tiles=TILE_SHAPES, bits=RADIX_BITS, base_settings=None, log=None, mesh=None):
-    """Tile shape, then digit width, for one view (forward, or forward +
+                  tiles=TILE_SHAPES, bits=RADIX_BITS, base_settings=None, log=None, mesh=None,
+                  orders=RASTER_ORDERS):
+    """Tile shape, then digit width, then the tiles' compositing order, for
+    one view (forward, or forward +
     backward with an L1 loss against `target`; composited with `mesh` if
     given), by the wall time of `reps` frames each after one warm-up
     frame.  Returns (settings dict, table)."""
@@ -223,7 +232,8 @@ def autotune_view(params: GaussianParams, cam, backward=False, target=None, reps
             log(f"autotune {over}: {t * 1e3:.3f} ms per frame")
         return t
 
-    best = dict(tile_w=tiles[0][0], tile_h=tiles[0][1], radix_bits=bits[0])
+    best = dict(tile_w=tiles[0][0], tile_h=tiles[0][1], radix_bits=bits[0],
+                raster_order=orders[0])
     best_t = None
     for tw, th in tiles:
         t = measure(dict(best, tile_w=tw, tile_h=th))
@@ -233,4 +243,8 @@ def autotune_view(params: GaussianParams, cam, backward=False, target=None, reps
         t = measure(dict(best, radix_bits=b))
         if t < best_t:
             best_t, best = t, dict(best, radix_bits=b)
+    for o in orders[1:]:
+        t = measure(dict(best, raster_order=o))
+        if t < best_t:
+            best_t, best = t, dict(best, raster_order=o)
     return dict(base, **best), table

@@ -55,6 +55,7 @@ int32_t check_settings(const gs_settings* s) {
   if (!gs::tile_shape_supported(s->tile_w, s->tile_h)) return GS_ERR_UNSUPPORTED;
   if (s->radix_bits < 6 || s->radix_bits > 8) return GS_ERR_UNSUPPORTED;
   if (s->sort_mode != 0 && s->sort_mode != 1) return GS_ERR_UNSUPPORTED;
+  if (s->raster_order != 0 && s->raster_order != 1) return GS_ERR_UNSUPPORTED;
   if (!(s->eps2d >= 0.f) || !std::isfinite(s->eps2d)) return GS_ERR_INVALID_ARGUMENT;
   if (!(s->alpha_min > 0.f) || !(s->alpha_max > s->alpha_min) || !(s->alpha_max < 1.f))
     return GS_ERR_INVALID_ARGUMENT;
@@ -104,6 +105,7 @@ gs::SetK make_setk(const gs_camera* c, const gs_settings* s) {
   k.tile_h = s->tile_h;
   k.tiles_x = tiles_x_of(c, s);
   k.tiles_y = tiles_y_of(c, s);
+  k.raster_order = s->raster_order;
   k.eps2d = s->eps2d;
   k.tau = s->alpha_min;
   k.log2_tau = (float)std::log2((double)s->alpha_min);
@@ -255,6 +257,7 @@ void gs_default_settings(gs_settings* s) {
   s->clip = 1.3f;
   s->radix_bits = 8;
   s->sort_mode = 0;
+  s->raster_order = 1;
 }
 
 int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set) {
@@ -272,7 +275,7 @@ size_t gs_workspace_size(int32_t stage, int64_t n, int64_t capacity, const gs_ca
     case GS_STAGE_SORT:
       if (check_settings(set) || check_camera(cam, set) || capacity > kMaxInstances || n >= kMaxN)
         return 0;
-      return gs::sort_layout(n, capacity).bytes;
+      return gs::sort_layout(n, capacity, tiles_x_of(cam, set) * tiles_y_of(cam, set)).bytes;
     case GS_STAGE_SORT_PAIRS:
       if (check_settings(set) || capacity > kMaxInstances) return 0;
       return gs::pairs_layout(capacity).bytes;
@@ -425,10 +428,12 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
     return r;
   if (capacity > 0 && (r = check_dev(values))) return r;
   if ((r = check_dev(keys, false)) || (r = check_dev(status_flag, false))) return r;
-  const gs::SortLayout L = gs::sort_layout(n, capacity);
+  const int tiles_all = tiles_x_of(cam, set) * tiles_y_of(cam, set);
+  const gs::SortLayout L = gs::sort_layout(n, capacity, tiles_all);
   if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
   if ((r = check_dev(workspace))) return r;
   const int bits = set->radix_bits, mode = set->sort_mode;
+  const bool heavy_first = set->raster_order == 1;
   const int tile_bits = key_bits_of(cam, set) - 32;
   const int pd = (32 + bits - 1) / bits;
   const int pt = tile_bits > 0 ? (tile_bits + bits - 1) / bits : 1;
@@ -439,9 +444,14 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   uint32_t* count = U(L.count);
   gs::trace_mark(st, "sort_init");
   hipError_t e = gs::launch_sort_init(L, ws, mode, tile_ranges, tiles, status_flag, counts,
-                                      capacity, st);
+                                      capacity, st, heavy_first ? U(L.tcls) : nullptr);
   if (e != hipSuccess) return hip_fail(e);
   if (n == 0 || capacity == 0) {
+    if (heavy_first) {
+      gs::trace_mark(st, "tile_order");
+      e = gs::launch_tile_order(tile_ranges, tiles, U(L.tcls), U(L.tseg), st);
+      if (e != hipSuccess) return hip_fail(e);
+    }
     gs::trace_mark(st, "");
     return GS_OK;
   }
@@ -484,6 +494,11 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   gs::trace_mark(st, "tile_ranges");
   e = gs::launch_tile_ranges(capacity, count, U(L.tkf), tile_ranges, st);
   if (e != hipSuccess) return hip_fail(e);
+  if (heavy_first) {
+    gs::trace_mark(st, "tile_order");
+    e = gs::launch_tile_order(tile_ranges, tiles, U(L.tcls), U(L.tseg), st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
   if (keys) {
     gs::trace_mark(st, "compose_keys");
     e = gs::launch_compose_keys(capacity, count, U(L.tkf), values, splats, keys, st);

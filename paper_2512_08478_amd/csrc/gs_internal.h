@@ -43,6 +43,7 @@ struct ViewsK {
 
 struct SetK {
   int tile_w, tile_h, tiles_x, tiles_y;
+  int raster_order;   // 0: spatial runs over the XCDs; 1: heavy tiles first
   float eps2d, tau, log2_tau, amax, t_eps;
   float bg[3];
 };
@@ -56,13 +57,17 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // table and digit totals, keygen slice counts, the kept instance count.
 struct SortLayout {
   size_t dk[2], dv[2], drect, tk[2], tv[2], tkf, hist, tickets, lookback, table, totals, kg_counts,
-      count;
+      count, tcls, tseg;
   size_t bytes;
   int parts;     // 4096-key partitions of the largest sort
   int rs_parts;  // 1024-key partitions of the largest sort (reduce-then-scan table rows)
   int kg_parts;  // keygen slices
 };
-SortLayout sort_layout(int64_t n, int64_t capacity);
+SortLayout sort_layout(int64_t n, int64_t capacity, int tiles);
+// Tile classes for the heavy-first compositing order: class k holds the
+// tiles with floor(log2(list length + 1)) = kTileClasses - 1 - k (the last
+// class also every shorter list).
+constexpr int kTileClasses = 16;
 SortLayout pairs_layout(int64_t n);  // gs_sort_pairs: dk[0]/dv[0] are the u64/u32 alternates
 
 // One stable LSD radix sort of (key, value) pairs.
@@ -122,7 +127,7 @@ hipError_t launch_count_finalize(const uint2* partial, int blocks, uint32_t* cou
                                  hipStream_t st);
 hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
                             int tiles, uint32_t* status_flag, const uint32_t* total_src,
-                            int64_t capacity, hipStream_t st);
+                            int64_t capacity, hipStream_t st, uint32_t* cls_count = nullptr);
 template <typename KeyT>
 hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int pass_base,
                              bool last_keys, const char* label, hipStream_t st);
@@ -132,6 +137,10 @@ hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* 
                          hipStream_t st);
 hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
                               uint32_t* ranges, hipStream_t st);
+// ranges[2*tiles .. 3*tiles) = the tiles, longest lists first (class
+// counters zeroed by launch_sort_init).
+hipError_t launch_tile_order(uint32_t* ranges, int tiles, uint32_t* cls_count, uint32_t* seg,
+                             hipStream_t st);
 hipError_t launch_compose_keys(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
                                const uint32_t* values, const gs_splat* splats, uint64_t* keys,
                                hipStream_t st);

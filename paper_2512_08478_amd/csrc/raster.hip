@@ -31,9 +31,11 @@
 // the pixel stops at the first such splat.  The mesh colour, if given,
 // takes the place of the background behind the Gaussians.
 //
-// Quadrants are dealt to the XCDs block-cyclically (see xcd_tile): each
-// XCD's L2 shares the splats of runs of neighbouring tiles, and dense
-// image regions are spread over all XCDs.
+// Order of the quadrants (pick_unit): by default the tiles with the
+// longest lists start first (the sort writes that order), which keeps a few
+// dense tiles from running alone at the end; or block-cyclic runs of
+// neighbouring tiles over the XCDs, whose L2s then share those tiles'
+// splats.  Either way dense regions are spread over all eight XCDs.
 #include "gs_device.h"
 #include "gs_internal.h"
 
@@ -60,9 +62,41 @@ __device__ __forceinline__ int xcd_tile(int b, int run) {
   return ((i / run) * kXcds + x) * run + i % run;
 }
 
+// The tile and quadrant of workgroup b.  raster_order 0: block-cyclic runs
+// (xcd_tile).  raster_order 1: the tiles in the heavy-first order that the
+// sort wrote after the ranges, one tile's quadrants on one XCD, tiles dealt
+// to the XCDs in turn, so that the longest lists start first and spread
+// over the chip.  False for padding workgroups (and for an order entry out
+// of range, which only a caller mixing raster_order values can produce).
+template <int NQ>
+__device__ __forceinline__ bool pick_unit(int b, const SetK& set,
+                                          const uint32_t* __restrict__ ranges, int& tile,
+                                          int& q) {
+  const int tiles = set.tiles_x * set.tiles_y;
+  if (set.raster_order == 1) {
+    const int x = b % kXcds, i = b / kXcds;
+    const int rank = (i / NQ) * kXcds + x;
+    if (rank >= tiles) return false;
+    tile = (int)ranges[2 * tiles + rank];
+    q = i % NQ;
+    return tile < tiles;
+  }
+  const int unit = xcd_tile(b, kRunTiles * NQ);
+  if (unit >= tiles * NQ) return false;
+  tile = unit / NQ;
+  q = unit % NQ;
+  return true;
+}
+
 inline int xcd_grid(int units, int run) {
   const int per = kXcds * run;
   return (units + per - 1) / per * per;
+}
+
+inline int raster_grid(const SetK& set, int tw, int th) {
+  const int tiles = set.tiles_x * set.tiles_y, nq = (tw / 8) * (th / 8);
+  if (set.raster_order == 1) return (tiles + kXcds - 1) / kXcds * kXcds * nq;
+  return xcd_grid(tiles * nq, kRunTiles * nq);
 }
 
 
@@ -175,10 +209,8 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
                                                uint32_t* __restrict__ n_blend) {
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ StageT<MESH> S;
-  const int tiles = set.tiles_x * set.tiles_y;
-  const int unit = xcd_tile(blockIdx.x, kRunTiles * NQ);
-  if (unit >= tiles * NQ) return;
-  const int tile = unit / NQ, q = unit % NQ;
+  int tile, q;
+  if (!pick_unit<NQ>(blockIdx.x, set, ranges, tile, q)) return;
   const int tx0 = (tile % set.tiles_x) * TW + 8 * (q % QX);
   const int ty0 = (tile / set.tiles_x) * TH + 8 * (q / QX);
   if (tx0 >= W || ty0 >= H) return;  // quadrant wholly outside the image
@@ -312,10 +344,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ Stage S;
   __shared__ float s_red[8][12];  // per 8-lane group (pixel row): its 9 gradient sums
-  const int tiles = set.tiles_x * set.tiles_y;
-  const int unit = xcd_tile(blockIdx.x, kRunTiles * NQ);
-  if (unit >= tiles * NQ) return;
-  const int tile = unit / NQ, q = unit % NQ;
+  int tile, q;
+  if (!pick_unit<NQ>(blockIdx.x, set, ranges, tile, q)) return;
   const int tx0 = (tile % set.tiles_x) * TW + 8 * (q % QX);
   const int ty0 = (tile / set.tiles_x) * TH + 8 * (q / QX);
   if (tx0 >= W || ty0 >= H) return;  // quadrant wholly outside the image
@@ -436,8 +466,7 @@ template <int TW, int TH>
 void raster_fwd(const gs_splat* splats, const uint32_t* values, const uint32_t* ranges,
                 const SetK& set, int W, int H, const float* mesh_depth, const float* mesh_rgb,
                 float* image, float* T_final, uint32_t* last, uint32_t* n_blend, hipStream_t st) {
-  const int units = set.tiles_x * set.tiles_y * (TW / 8) * (TH / 8);
-#define GS_K(M, C) hipLaunchKernelGGL((k_raster<TW, TH, M, C>), dim3(xcd_grid(units, kRunTiles * (TW / 8) * (TH / 8))), dim3(64), 0, st, splats, values, ranges, set, W, H, mesh_depth, mesh_rgb, image, T_final, last, n_blend)
+#define GS_K(M, C) hipLaunchKernelGGL((k_raster<TW, TH, M, C>), dim3(raster_grid(set, TW, TH)), dim3(64), 0, st, splats, values, ranges, set, W, H, mesh_depth, mesh_rgb, image, T_final, last, n_blend)
   if (mesh_depth) {
     if (n_blend) GS_K(true, true); else GS_K(true, false);
   } else {
@@ -450,8 +479,7 @@ template <int TW, int TH>
 void raster_bwd(const gs_splat* splats, const uint32_t* values, const uint32_t* ranges,
                 const SetK& set, int W, int H, const float* bg_rgb, const float* T_final,
                 const uint32_t* last, const float* dL_dimage, float* grad2d, hipStream_t st) {
-  const int units = set.tiles_x * set.tiles_y * (TW / 8) * (TH / 8);
-  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(xcd_grid(units, kRunTiles * (TW / 8) * (TH / 8))), dim3(64), 0, st,
+  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(raster_grid(set, TW, TH)), dim3(64), 0, st,
                      splats, values, ranges, set, W, H, bg_rgb, T_final, last, dL_dimage, grad2d);
 }
 

@@ -46,9 +46,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_init(uint32_t* hist, int hist_l
                                                       uint32_t* ranges, int ranges_len,
                                                       uint32_t* count, const uint32_t* total_src,
                                                       uint32_t host_total, int64_t capacity,
-                                                      uint32_t* status_flag) {
+                                                      uint32_t* status_flag, uint32_t* cls_count) {
   const int stride = gridDim.x * kBlock;
   const int i0 = blockIdx.x * kBlock + threadIdx.x;
+  if (cls_count && i0 < kTileClasses) cls_count[i0] = 0;
   for (int i = i0; i < lb_len; i += stride) lookback[i] = 0;
   for (int i = i0; i < ranges_len; i += stride) ranges[i] = 0;
   for (int i = i0; i < hist_len; i += stride) hist[i] = 0;
@@ -514,6 +515,47 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restri
   }
 }
 
+// Heavy-first tile order, step 1: each tile joins its class (by the
+// length of its list) at a position taken with one atomic per class and
+// wave; class k's members go to seg[k * tiles ..].
+__global__ __launch_bounds__(kBlock) void k_tile_classes(const uint32_t* __restrict__ ranges,
+                                                         int tiles, uint32_t* cls_count,
+                                                         uint32_t* __restrict__ seg) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const bool ok = t < tiles;
+  uint32_t k = 0;
+  if (ok) {
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    const int lg = 31 - __builtin_clz(len + 1u);  // floor(log2(len + 1)), len + 1 >= 1
+    k = (uint32_t)(kTileClasses - 1 - min(lg, kTileClasses - 1));
+  }
+  const uint64_t same = match_digit<4>(k, ballot(ok));
+  const int lane = lane_id();
+  const int leader = same ? __builtin_ctzll(same) : 0;
+  uint32_t base = 0;
+  if (ok && lane == leader) base = atomicAdd(cls_count + k, (uint32_t)__builtin_popcountll(same));
+  base = shfl_u32(base, leader);
+  if (ok) seg[(size_t)k * tiles + base + (uint32_t)__builtin_popcountll(same & lanemask_lt())] =
+      (uint32_t)t;
+}
+
+// Step 2: rank r of the order is member r - (members of earlier classes)
+// of the first class whose members reach past r.
+__global__ __launch_bounds__(kBlock) void k_tile_order(const uint32_t* __restrict__ cls_count,
+                                                       const uint32_t* __restrict__ seg,
+                                                       int tiles, uint32_t* __restrict__ order) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= tiles) return;
+  uint32_t before = 0;
+  int k = 0;
+  for (; k < kTileClasses - 1; ++k) {
+    const uint32_t c = cls_count[k];
+    if ((uint32_t)r < before + c) break;
+    before += c;
+  }
+  order[r] = seg[(size_t)k * tiles + ((uint32_t)r - before)];
+}
+
 // Optional 64-bit keys of the sorted list: tile << 32 | bits(float32 depth).
 __global__ __launch_bounds__(kBlock) void k_compose_keys(const uint32_t* __restrict__ count,
                                                          const uint32_t* __restrict__ tkeys,
@@ -606,7 +648,7 @@ void hist_t(const RadixArgs<KeyT>& a, int passes, hipStream_t st) {
 
 }  // namespace
 
-SortLayout sort_layout(int64_t n, int64_t capacity) {
+SortLayout sort_layout(int64_t n, int64_t capacity, int tiles) {
   SortLayout L;
   const int64_t nn = n > 0 ? n : 1, cap = capacity > 0 ? capacity : 1;
   const int64_t big = nn > cap ? nn : cap;
@@ -632,6 +674,8 @@ SortLayout sort_layout(int64_t n, int64_t capacity) {
   L.totals = take(256 * 4);
   L.kg_counts = take((size_t)L.kg_parts * 4);
   L.count = take(4);
+  L.tcls = take((size_t)kTileClasses * 4);
+  L.tseg = take((size_t)kTileClasses * (tiles > 0 ? tiles : 1) * 4);
   L.bytes = o;
   return L;
 }
@@ -664,7 +708,7 @@ SortLayout pairs_layout(int64_t n) {
 
 hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
                             int tiles, uint32_t* status_flag, const uint32_t* total_src,
-                            int64_t capacity, hipStream_t st) {
+                            int64_t capacity, hipStream_t st, uint32_t* cls_count) {
   const int lb_len = mode == 1 ? 2 * L.parts * 256 : 0;
   const int ranges_len = tile_ranges ? 2 * tiles : 0;
   const int64_t most = lb_len > ranges_len ? lb_len : ranges_len;
@@ -673,7 +717,7 @@ hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* t
                      reinterpret_cast<uint32_t*>(ws + L.tickets), kMaxPassTotal,
                      reinterpret_cast<uint32_t*>(ws + L.lookback), lb_len, tile_ranges, ranges_len,
                      reinterpret_cast<uint32_t*>(ws + L.count), total_src, (uint32_t)capacity,
-                     capacity, status_flag);
+                     capacity, status_flag, cls_count);
   return hipGetLastError();
 }
 
@@ -737,6 +781,17 @@ hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uin
   if (capacity == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_ranges, dim3(stream_grid(capacity, 4096)), dim3(kBlock), 0, st, count,
                      tkeys, ranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_order(uint32_t* ranges, int tiles, uint32_t* cls_count, uint32_t* seg,
+                             hipStream_t st) {
+  if (tiles <= 0) return hipSuccess;
+  const int grid = (tiles + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_tile_classes, dim3(grid), dim3(kBlock), 0, st, ranges, tiles, cls_count,
+                     seg);
+  hipLaunchKernelGGL(k_tile_order, dim3(grid), dim3(kBlock), 0, st, cls_count, seg, tiles,
+                     ranges + 2 * (size_t)tiles);
   return hipGetLastError();
 }
 

@@ -227,7 +227,8 @@ class Renderer:
         capacity = int(capacity)
         keys = self._buf("keys", capacity * 8, reuse).view(torch.int64)[:capacity] if want_keys else None
         values = self._buf("values", capacity * 4, reuse).view(torch.int32)[:capacity]
-        ranges = self._buf("ranges", self.tiles(cam) * 8, reuse).view(torch.int32)[:2 * self.tiles(cam)]
+        # [start, end) per tile, then the compositing order of the tiles
+        ranges = self._buf("ranges", self.tiles(cam) * 12, reuse).view(torch.int32)[:3 * self.tiles(cam)]
         flag = self._buf("flag", 4, reuse).view(torch.int32)[:1]
         ws_bytes = lib.gs_workspace_size(L.GS_STAGE_SORT, n, capacity, ctypes.byref(c), ctypes.byref(s))
         if ws_bytes == 0:

@@ -45,7 +45,7 @@ def test_version_and_status_strings(lib):
 
 def test_default_settings(lib):
     s = L.default_settings()
-    assert (s.tile_w, s.tile_h, s.radix_bits, s.sort_mode) == (16, 16, 8, 0)
+    assert (s.tile_w, s.tile_h, s.radix_bits, s.sort_mode, s.raster_order) == (16, 16, 8, 0, 1)
     assert s.eps2d == pytest.approx(0.3)
     assert s.alpha_min == pytest.approx(1 / 255)
     assert s.alpha_max == pytest.approx(0.99)
@@ -302,3 +302,13 @@ def test_lbs_validation(lib):
     assert lb(joints=None) == L.GS_ERR_INVALID_ARGUMENT
     assert lb(po=F) == L.GS_ERR_INVALID_ARGUMENT          # aliases the canonical input
     assert lb(cv=ctypes.c_void_p(FAKE + 7 * 4096 + 2)) == L.GS_ERR_MISALIGNED
+
+
+def test_raster_order_validation_and_sort_workspace(lib):
+    c = cam_1080()
+    bad = L.default_settings(raster_order=2)
+    assert lib.gs_sort_key_bits(ctypes.byref(c), ctypes.byref(bad)) == -1
+    s = L.default_settings()
+    # the sort workspace holds 16 tile-class segments of `tiles` entries
+    w = lib.gs_workspace_size(L.GS_STAGE_SORT, 1000, 1000, ctypes.byref(c), ctypes.byref(s))
+    assert w >= 16 * 120 * 68 * 4

@@ -155,7 +155,7 @@ def test_autotuned_settings_leave_images_unchanged(R):
     tg = targets_for(cams)
     best, table = autotune(p, cams, tg, reps=1, tiles=((16, 16), (8, 8), (32, 8)), bits=(8, 6),
                            modes=(0, 1))
-    assert len(table) == 3 + 1 + 1
+    assert len(table) == 3 + 1 + 1 + 1
     ref = BatchRenderer(p, cams, tg)
     ref_imgs = [im.clone() for im in ref.run_eager()]
     tuned = BatchRenderer(p, cams, tg, best)

@@ -182,7 +182,7 @@ def test_sort_keys_tiny(R, orc):
     np.testing.assert_array_equal(u64(fr.keys)[:n], ek)
     np.testing.assert_array_equal(u32(fr.values)[:n], ev)
     # tile ranges
-    rng = u32(fr.ranges).reshape(-1, 2)
+    rng = u32(fr.ranges)[:2 * R.tiles(cam)].reshape(-1, 2)
     tile = (ek >> np.uint64(32)).astype(np.int64)
     for t in range(rng.shape[0]):
         idx = np.nonzero(tile == t)[0]
@@ -297,11 +297,33 @@ def test_tile_shape_and_digit_width_invariance(R):
     sc, cam = S.tiny_scene()
     cam = S.pinhole_camera(S.look_at((0.3, -0.2, -3.0)), 250, 190, 60.0)  # ragged edge tiles
     base = R.forward(gp(sc), cam).image.cpu().numpy()
-    for tw, th, bits, mode in [(8, 8, 8, 0), (16, 8, 7, 1), (32, 8, 6, 0), (32, 16, 8, 1),
-                               (16, 16, 6, 1), (16, 16, 7, 0)]:
-        img = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=mode)).forward(
-            gp(sc), cam).image.cpu().numpy()
-        np.testing.assert_array_equal(img, base, err_msg=f"{tw}x{th} bits {bits} mode {mode}")
+    for tw, th, bits, mode, order in [(8, 8, 8, 0, 0), (16, 8, 7, 1, 1), (32, 8, 6, 0, 0),
+                                      (32, 16, 8, 1, 1), (16, 16, 6, 1, 0), (16, 16, 7, 0, 1),
+                                      (8, 8, 8, 0, 1), (32, 16, 7, 0, 0)]:
+        img = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=mode,
+                            raster_order=order)).forward(gp(sc), cam).image.cpu().numpy()
+        np.testing.assert_array_equal(img, base,
+                                      err_msg=f"{tw}x{th} bits {bits} mode {mode} order {order}")
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_tile_order_is_a_permutation(R, order):
+    print_case(f"tile order written by the sort (raster_order {order})")
+    from paper_2512_08478_amd.render import Renderer
+    Rs = Renderer(dict(tile_w=8, tile_h=8, raster_order=order))
+    sc, cam = S.medium_scene(n=200_000)
+    fr = Rs.forward(gp(sc), cam)
+    tiles = Rs.tiles(cam)
+    rg = u32(fr.ranges)
+    lens = (rg[1:2 * tiles:2].astype(np.int64) - rg[0:2 * tiles:2]).clip(min=0)
+    if order == 1:
+        perm = rg[2 * tiles:3 * tiles].astype(np.int64)
+        assert sorted(perm.tolist()) == list(range(tiles))
+        cls = np.minimum(np.floor(np.log2(lens[perm] + 1)), 15)
+        assert np.all(np.diff(cls) <= 0)      # longest classes first
+    # the backward walks the same order: gradients exist and are finite
+    g = Rs.backward(gp(sc), cam, fr, torch.ones_like(fr.image))
+    assert all(torch.isfinite(t).all() for t in g)
 
 
 def test_shuffle_and_repeat_invariance(R):
@@ -325,7 +347,7 @@ def test_capacity_overflow_flag(R):
     torch.cuda.synchronize()
     assert int(u32(flag)[0]) & 1 == 1
     # the kept half is the front of the depth order: every range lies inside it
-    rng = u32(ranges).reshape(-1, 2)
+    rng = u32(ranges)[:2 * R.tiles(cam)].reshape(-1, 2)
     assert rng[:, 1].max() <= tot // 2
     keys, values, ranges, flag, cap = R.sort(sc.n, *pre, cam, capacity=tot)
     torch.cuda.synchronize()
