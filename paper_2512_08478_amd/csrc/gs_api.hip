@@ -455,11 +455,14 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
     gs::trace_mark(st, "");
     return GS_OK;
   }
-  // depth digits over all n Gaussians (culled ones carry the largest key)
+  // depth digits: the first pass reads all n Gaussians and drops the culled
+  // ones (their key is all ones), the later passes sort the visible ones
   gs::RadixArgs<uint32_t> d{};
   d.mode = mode;
   d.n_grid = n;
   d.count = nullptr;
+  d.drop_first = 1;
+  d.count_rest = counts + 1;
   d.kin = depth_keys;
   d.vin = nullptr;
   d.k_alt = U(L.dk[1]); d.v_alt = U(L.dv[1]);
@@ -471,7 +474,6 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   uint2* drect = reinterpret_cast<uint2*>(ws + L.drect);
   d.gather_src = reinterpret_cast<const uint2*>(tile_rects);
   d.gather_dst = drect;
-  d.gather_count = counts + 1;
   e = gs::launch_radix_sort<uint32_t>(d, bits, pd, 0, false, "depth_pass", st);
   if (e != hipSuccess) return hip_fail(e);
   // instances of the visible Gaussians in depth order, then the tile digits
@@ -481,9 +483,10 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   gs::RadixArgs<uint32_t> t = d;
   t.gather_src = nullptr;
   t.gather_dst = nullptr;
-  t.gather_count = nullptr;
   t.n_grid = capacity;
   t.count = count;
+  t.drop_first = 0;
+  t.count_rest = nullptr;
   t.kin = U(L.tk[0]);
   t.vin = U(L.tv[0]);
   t.k_alt = U(L.tk[1]); t.v_alt = U(L.tv[1]);

@@ -76,23 +76,24 @@ struct RadixArgs {
   int mode;                 // 0 reduce-then-scan, 1 onesweep (decoupled look-back)
   int64_t n_grid;           // upper bound of n: sizes the grids
   const uint32_t* count;    // device n (NULL: n = n_grid)
+  int drop_first;           // the first pass drops all-ones keys ...
+  const uint32_t* count_rest;  // ... and the later passes sort *count_rest pairs
   const KeyT* kin;          // input keys (not modified)
   const uint32_t* vin;      // input values (NULL: value = position)
   KeyT* k_alt;              // ping-pong buffers
   uint32_t* v_alt;
   KeyT* k_out;              // the result
   uint32_t* v_out;
-  uint32_t* table;          // mode 0: 256 x partitions counts
+  uint32_t* table;          // mode 0: partitions x 2^bits counts (partition-major)
   uint32_t* totals;         // mode 0: 256 digit totals
   uint32_t* hist;           // mode 1: 256 bins per pass
   uint32_t* tickets;        // mode 1: one per pass
   uint32_t* lookback;       // mode 1: two buffers of lb_parts x 256 words
   int lb_parts;
-  // optional: the last pass also writes gather_dst[i] = gather_src[value of
-  // sorted position i] for positions i < *gather_count
+  // optional (32-bit keys, last pass writes no keys): the last pass also
+  // writes gather_dst[i] = gather_src[value of sorted position i]
   const uint2* gather_src;
   uint2* gather_dst;
-  const uint32_t* gather_count;
 };
 
 // Launchers (enqueue only; return the first launch error).

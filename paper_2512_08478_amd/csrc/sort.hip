@@ -100,41 +100,49 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp,
 
 // ---------------------------------------------------------------- counting
 
+// A key is sorted if it lies before the end and, in a dropping pass, is
+// not the all-ones key (the depth key of a culled Gaussian).
+template <typename KeyT>
+__device__ __forceinline__ bool key_kept(KeyT k, uint32_t idx, uint32_t n, int drop) {
+  return idx < n && !(drop && k == ~KeyT(0));
+}
+
 // Digit counts of one partition (kBlock * ITEMS keys) per workgroup,
-// written digit-major into table[d * P + partition] (zeros past the end).
-// Counting needs no order, so each key is one LDS atomic increment into its
-// wave's own sub-histogram (no ballot matching).
+// written partition-major into table[partition * NB + d], so one
+// workgroup's counts are one contiguous row.  Counting needs no order, so
+// each key is one LDS atomic increment into its wave's own sub-histogram
+// (no ballot matching).
 template <typename KeyT, int BITS, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ kin,
                                                        const uint32_t* __restrict__ count,
-                                                       int64_t n_host, int shift,
-                                                       uint32_t* __restrict__ table, int P) {
+                                                       int64_t n_host, int drop, int shift,
+                                                       uint32_t* __restrict__ table) {
   constexpr int NB = 1 << BITS;
   constexpr int NW = kBlock / 64;
   constexpr int PART = kBlock * ITEMS;
   __shared__ uint32_t s_h[NW][NB];
   const int t = threadIdx.x, wave = t >> 6;
-  for (int d = t; d < NW * NB; d += kBlock) (&s_h[0][0])[d] = 0;
-  __syncthreads();
   const uint32_t n = read_n(count, n_host);
   const uint32_t base = blockIdx.x * PART;
-  if (base < n) {
-    KeyT k[ITEMS];
+  if (base >= n) return;
+  for (int d = t; d < NW * NB; d += kBlock) (&s_h[0][0])[d] = 0;
+  KeyT k[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-      const uint32_t idx = base + i * kBlock + t;
-      k[i] = idx < n ? kin[idx] : KeyT(0);
-    }
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-      if (base + i * kBlock + t < n) atomicAdd(&s_h[wave][digit_of<KeyT, BITS>(k[i], shift)], 1u);
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t idx = base + i * kBlock + t;
+    k[i] = idx < n ? kin[idx] : KeyT(0);
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i)
+    if (key_kept(k[i], base + i * kBlock + t, n, drop))
+      atomicAdd(&s_h[wave][digit_of<KeyT, BITS>(k[i], shift)], 1u);
   __syncthreads();
   for (int d = t; d < NB; d += kBlock) {
     uint32_t c = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) c += s_h[w][d];
-    table[(size_t)d * P + blockIdx.x] = c;
+    table[(size_t)blockIdx.x * NB + d] = c;
   }
 }
 
@@ -169,12 +177,87 @@ __global__ __launch_bounds__(kBlock) void k_row_scan(uint32_t* __restrict__ tabl
   if (t == 0) totals[blockIdx.x] = carry;
 }
 
-// Digit histograms of `passes` digits of keys[0, n) for the onesweep mode;
-// global layout is 256 bins per pass.
+// Per-digit exclusive prefix over the partitions of the partition-major
+// count table (table[p * NB + d], p < the partitions that hold keys), in
+// place; the digit sums go to totals[d].  Workgroup w owns the 8 digits
+// [8w, 8w + 8): each thread reads 8 consecutive rows' 32-byte slices per
+// round, and the 8 digit columns are scanned side by side.
+template <int NB, int PART>
+__global__ __launch_bounds__(kBlock) void k_col_scan(uint32_t* __restrict__ table,
+                                                     const uint32_t* __restrict__ count,
+                                                     int64_t n_host,
+                                                     uint32_t* __restrict__ totals) {
+  constexpr int DG = 8, RPT = 8, NW = kBlock / 64;
+  __shared__ uint32_t s_w[DG][NW];
+  const uint32_t n = read_n(count, n_host);
+  const int P = (int)((n + PART - 1) / PART);
+  const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+  const int d0 = blockIdx.x * DG;
+  uint32_t carry[DG];
+#pragma unroll
+  for (int k = 0; k < DG; ++k) carry[k] = 0;
+  for (int r0 = 0; r0 < P; r0 += kBlock * RPT) {
+    uint32_t c[RPT][DG];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = r0 + t * RPT + i;
+      uint4 a = make_uint4(0u, 0u, 0u, 0u), b = a;
+      if (row < P) {
+        const uint4* src = reinterpret_cast<const uint4*>(table + (size_t)row * NB + d0);
+        a = src[0];
+        b = src[1];
+      }
+      c[i][0] = a.x; c[i][1] = a.y; c[i][2] = a.z; c[i][3] = a.w;
+      c[i][4] = b.x; c[i][5] = b.y; c[i][6] = b.z; c[i][7] = b.w;
+    }
+    uint32_t ex[DG];
+#pragma unroll
+    for (int k = 0; k < DG; ++k) {
+      uint32_t s = 0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) s += c[i][k];
+      const uint32_t incl = wave_incl_scan(s);
+      if (lane == 63) s_w[k][wave] = incl;
+      ex[k] = incl - s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < DG; ++k) {
+      uint32_t off = 0, tot = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t x = s_w[k][w];
+        off += w < wave ? x : 0u;
+        tot += x;
+      }
+      ex[k] += off + carry[k];
+      carry[k] += tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = r0 + t * RPT + i;
+      if (row < P) {
+        uint4* dst = reinterpret_cast<uint4*>(table + (size_t)row * NB + d0);
+        dst[0] = make_uint4(ex[0], ex[1], ex[2], ex[3]);
+        dst[1] = make_uint4(ex[4], ex[5], ex[6], ex[7]);
+      }
+#pragma unroll
+      for (int k = 0; k < DG; ++k) ex[k] += c[i][k];
+    }
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < DG; ++k) totals[d0 + k] = carry[k];
+  }
+}
+
+// Digit histograms of `passes` digits of keys[0, n) for the onesweep mode
+// (kept keys only); global layout is 256 bins per pass.
 template <typename KeyT, int BITS>
 __global__ __launch_bounds__(kBlock) void k_histogram(const KeyT* __restrict__ keys,
                                                       const uint32_t* __restrict__ count,
-                                                      int64_t n_host, int passes,
+                                                      int64_t n_host, int drop, int passes,
                                                       uint32_t* __restrict__ hist) {
   constexpr int NB = 1 << BITS;
   __shared__ uint32_t s_hist[kHistMax];
@@ -191,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_histogram(const KeyT* __restrict__ k
     }
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-      const bool valid = base + i * kBlock + t < n;
+      const bool valid = key_kept(k[i], base + i * kBlock + t, n, drop);
       for (int p = 0; p < passes; ++p)
         wave_hist_add<BITS>(s_hist + p * NB, digit_of<KeyT, BITS>(k[i], p * BITS), valid);
     }
@@ -205,21 +288,33 @@ __global__ __launch_bounds__(kBlock) void k_histogram(const KeyT* __restrict__ k
 
 // ---------------------------------------------------------------- scatter
 
+// Partition of workgroup b (b < P) in the reduce-then-scan downsweep.  The
+// hardware deals workgroups to the 8 XCDs in turn (b % 8); XCD x is given
+// the contiguous partitions [x q + min(x, r), ...) of P = 8 q + r, so the
+// runs that neighbouring partitions write for one digit meet in one XCD's
+// L2 instead of being split between two.
+__device__ __forceinline__ uint32_t xcd_part(uint32_t b, uint32_t P) {
+  const uint32_t q = P >> 3, r = P & 7u, x = b & 7u;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // One radix pass.  kin/vin hold n pairs (vin == NULL: value = position);
-// pairs are scattered to kout/vout by the digit at `shift`.
-// LOOKBACK = false: partition = workgroup, offsets from the scanned table
-//   (table[d * P + part]) and the per-digit totals.
+// the kept pairs (drop != 0 drops the all-ones key) are scattered to
+// kout/vout by the digit at `shift`.
+// LOOKBACK = false: partitions dealt by xcd_part, offsets from the scanned
+//   partition-major table (table[part * NB + d]) and the per-digit totals.
 // LOOKBACK = true: partition by ticket, `totals` is this pass's global digit
 //   histogram, offsets by decoupled look-back over lb.
 // WRITE_KEYS = false skips the key stores of a last pass whose keys nobody
-// reads.
-template <typename KeyT, int BITS, int ITEMS, bool WRITE_KEYS, bool LOOKBACK>
+//   reads.
+// GATHER = true also writes gdst[g] = gsrc[value] at every output position g.
+template <typename KeyT, int BITS, int ITEMS, bool WRITE_KEYS, bool LOOKBACK, bool GATHER>
 __global__ __launch_bounds__(kBlock) void k_radix_pass(
     const KeyT* __restrict__ kin, const uint32_t* __restrict__ vin, KeyT* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ count, int64_t n_host, int shift,
-    const uint32_t* __restrict__ table, int P, const uint32_t* __restrict__ totals,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ count, int64_t n_host, int drop,
+    int shift, const uint32_t* __restrict__ table, const uint32_t* __restrict__ totals,
     uint32_t* __restrict__ ticket, uint32_t* __restrict__ lb, uint32_t* __restrict__ lb_next,
-    const uint2* __restrict__ gsrc, uint2* __restrict__ gdst, const uint32_t* __restrict__ gath_n) {
+    const uint2* __restrict__ gsrc, uint2* __restrict__ gdst) {
   constexpr int NB = 1 << BITS;
   constexpr int NW = kBlock / 64;
   constexpr int PART = kBlock * ITEMS;
@@ -227,38 +322,56 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
   __shared__ uint32_t s_local[NB];
   __shared__ uint32_t s_gbase[NB];
   __shared__ KeyT s_keys[PART];
-  __shared__ uint8_t s_dig[PART];
+  __shared__ uint32_t s_vals[PART];
   __shared__ uint32_t s_scan[2][NW];
   __shared__ uint32_t s_part;
 
   const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-  if (LOOKBACK && t == 0) s_part = atomicAdd(ticket, 1u);
-  for (int b = t; b < NW * NB; b += kBlock) (&s_whist[0][0])[b] = 0;
-  __syncthreads();
-  const uint32_t part = LOOKBACK ? s_part : blockIdx.x;
   const uint32_t n = read_n(count, n_host);
-  const uint32_t base = part * PART;
-  if (base >= n) return;
-  if (LOOKBACK)
+  uint32_t part;
+  if (LOOKBACK) {
+    if (t == 0) s_part = atomicAdd(ticket, 1u);
+    for (int b = t; b < NW * NB; b += kBlock) (&s_whist[0][0])[b] = 0;
+    __syncthreads();
+    part = s_part;
+    if (part * PART >= n) return;
     for (int b = t; b < NB; b += kBlock) lb_next[part * NB + b] = 0;
+  } else {
+    const uint32_t P = (n + PART - 1) / PART;
+    if (blockIdx.x >= P) return;
+    part = xcd_part(blockIdx.x, P);
+    for (int b = t; b < NW * NB; b += kBlock) (&s_whist[0][0])[b] = 0;
+  }
+  const uint32_t base = part * PART;
 
-  // warp-striped load: wave w owns keys [w*64*ITEMS, (w+1)*64*ITEMS)
+  // warp-striped load: wave w owns keys [w*64*ITEMS, (w+1)*64*ITEMS); the
+  // values are loaded with the keys so both round trips overlap
   KeyT k[ITEMS];
-  uint32_t pos[ITEMS];
+  uint32_t v[ITEMS], pos[ITEMS];
   const uint32_t wbase = base + wave * 64 * ITEMS + lane;
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t idx = wbase + i * 64;
-    k[i] = idx < n ? kin[idx] : ~KeyT(0);  // past the end: last digit, ranked last
+    k[i] = idx < n ? kin[idx] : ~KeyT(0);
   }
-  const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t idx = wbase + i * 64;
+    v[i] = idx < n ? (vin ? vin[idx] : idx) : 0u;
+  }
+  if (!LOOKBACK) __syncthreads();  // s_whist zeroed
+  // rank within the wave: kept keys in index order, equal digits by lane
+  const uint64_t lt = lanemask_lt();
+  uint32_t kept = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const bool keep = key_kept(k[i], wbase + i * 64, n, drop);
+    kept |= (uint32_t)keep << i;
     const uint32_t d = digit_of<KeyT, BITS>(k[i], shift);
-    const uint64_t peers = match_digit<BITS>(d, ~0ull);
+    const uint64_t peers = match_digit<BITS>(d, ballot(keep));
     const uint32_t c = s_whist[wave][d];
     pos[i] = c + (uint32_t)__builtin_popcountll(peers & lt);
-    if ((peers & lt) == 0) s_whist[wave][d] = c + (uint32_t)__builtin_popcountll(peers);
+    if (keep && (peers & lt) == 0) s_whist[wave][d] = c + (uint32_t)__builtin_popcountll(peers);
   }
   __syncthreads();
 
@@ -293,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
     const uint32_t gstart = off_g + inc_g - gcount;
     uint32_t prefix = 0;
     if (!LOOKBACK) {
-      prefix = table[(size_t)t * P + part];
+      prefix = table[(size_t)part * NB + t];
     } else if (part > 0) {
       int j = (int)part - 1;
       while (true) {
@@ -319,39 +432,54 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
     s_local[t] = local;
     s_gbase[t] = gstart + prefix - local;
   }
+  uint32_t nkept = 0;  // kept keys of the partition
+#pragma unroll
+  for (int w = 0; w < NW; ++w) nkept += s_scan[0][w];
   __syncthreads();
 
+  // stage the pairs in digit order, then write them out so that
+  // consecutive threads store consecutive addresses of one digit run
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t d = digit_of<KeyT, BITS>(k[i], shift);
-    pos[i] += s_local[d] + s_whist[wave][d];
-    s_keys[pos[i]] = k[i];
-  }
-  __syncthreads();
-  for (int j = t; j < PART; j += kBlock) {
-    const KeyT key = s_keys[j];
-    const uint32_t d = digit_of<KeyT, BITS>(key, shift);
-    s_dig[j] = (uint8_t)d;
-    if (WRITE_KEYS) {
-      const uint32_t g = s_gbase[d] + j;
-      if (g < n) kout[g] = key;
+    if (kept >> i & 1u) {
+      const uint32_t d = digit_of<KeyT, BITS>(k[i], shift);
+      const uint32_t p = pos[i] + s_local[d] + s_whist[wave][d];
+      s_keys[p] = k[i];
+      s_vals[p] = v[i];
     }
   }
   __syncthreads();
-  uint32_t* s_vals = reinterpret_cast<uint32_t*>(s_keys);
+  if (!GATHER) {
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t idx = wbase + i * 64;
-    s_vals[pos[i]] = idx < n ? (vin ? vin[idx] : idx) : 0u;
-  }
-  __syncthreads();
-  const uint32_t gn = gdst ? *gath_n : 0u;
-  for (int j = t; j < PART; j += kBlock) {
-    const uint32_t g = s_gbase[s_dig[j]] + j;
-    if (g < n) {
-      const uint32_t v = s_vals[j];
-      vout[g] = v;
-      if (g < gn) gdst[g] = gsrc[v];
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t j = (uint32_t)(i * kBlock + t);
+      if (j < nkept) {
+        const KeyT key = s_keys[j];
+        const uint32_t g = s_gbase[digit_of<KeyT, BITS>(key, shift)] + j;
+        if (WRITE_KEYS) kout[g] = key;
+        vout[g] = s_vals[j];
+      }
+    }
+  } else {
+    // all gathers in flight before the first store
+    uint32_t g[ITEMS], val[ITEMS];
+    uint2 r[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t j = (uint32_t)(i * kBlock + t);
+      g[i] = 0xFFFFFFFFu;
+      if (j < nkept) {
+        g[i] = s_gbase[digit_of<KeyT, BITS>(s_keys[j], shift)] + j;
+        val[i] = s_vals[j];
+        r[i] = gsrc[val[i]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      if (g[i] != 0xFFFFFFFFu) {
+        vout[g[i]] = val[i];
+        gdst[g[i]] = r[i];
+      }
     }
   }
 }
@@ -503,15 +631,28 @@ __global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict_
   }
 }
 
+// Tile ranges of the sorted tile keys.  Each thread takes 4 consecutive
+// keys with one 16-byte load plus the keys on either side.  The key buffer
+// is padded to a multiple of 64 keys, so the vector load of the last group
+// stays inside it (keys past n are never used).
 __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restrict__ count,
                                                         const uint32_t* __restrict__ tkeys,
                                                         uint32_t* __restrict__ ranges) {
-  const uint32_t n = *count;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    const uint32_t tile = tkeys[i];
-    if (i == 0 || tkeys[i - 1] != tile) ranges[2 * tile] = (uint32_t)i;
-    if (i == (int64_t)n - 1 || tkeys[i + 1] != tile) ranges[2 * tile + 1] = (uint32_t)(i + 1);
+  const int64_t n = *count;
+  const int64_t stride = (int64_t)gridDim.x * kBlock * 4;
+  for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 4; i0 < n; i0 += stride) {
+    const uint4 q = *reinterpret_cast<const uint4*>(tkeys + i0);
+    const uint32_t kk[6] = {i0 > 0 ? tkeys[i0 - 1] : 0u, q.x, q.y, q.z, q.w,
+                            i0 + 4 < n ? tkeys[i0 + 4] : 0u};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t i = i0 + j;
+      if (i < n) {
+        const uint32_t tile = kk[j + 1];
+        if (i == 0 || kk[j] != tile) ranges[2 * tile] = (uint32_t)i;
+        if (i == n - 1 || kk[j + 2] != tile) ranges[2 * tile + 1] = (uint32_t)(i + 1);
+      }
+    }
   }
 }
 
@@ -588,53 +729,66 @@ inline int rs_items(int64_t n) {
   return 4;
 }
 
+// Launch of one downsweep kernel for the chosen key-store and gather
+// variants (gathers serve only 32-bit passes that write no keys).
+template <typename KeyT, int BITS, int ITEMS, bool LOOKBACK>
+void launch_pass(int grid, bool write_keys, bool gather, const KeyT* ki, const uint32_t* vi,
+                 KeyT* kd, uint32_t* vd, const uint32_t* cnt, int64_t n_grid, int drop, int shift,
+                 const uint32_t* table, const uint32_t* totals, uint32_t* ticket, uint32_t* lb,
+                 uint32_t* lb_next, const uint2* gs, uint2* gd, hipStream_t st) {
+  if (gather) {
+    if constexpr (sizeof(KeyT) == 4)
+      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, false, LOOKBACK, true>), dim3(grid),
+                         dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, shift, table,
+                         totals, ticket, lb, lb_next, gs, gd);
+  } else if (write_keys) {
+    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, true, LOOKBACK, false>), dim3(grid),
+                       dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, shift, table,
+                       totals, ticket, lb, lb_next, gs, gd);
+  } else {
+    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, false, LOOKBACK, false>), dim3(grid),
+                       dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, shift, table,
+                       totals, ticket, lb, lb_next, gs, gd);
+  }
+}
+
 template <typename KeyT, int BITS, int ITEMS>
-void rs_pass(const RadixArgs<KeyT>& a, int p, const KeyT* ki, const uint32_t* vi, KeyT* kd,
-             uint32_t* vd, bool write_keys, bool gather, hipStream_t st) {
-  const uint2* gs = gather ? a.gather_src : nullptr;
-  uint2* gd = gather ? a.gather_dst : nullptr;
-  const uint32_t* gc = gather ? a.gather_count : nullptr;
+void rs_pass(const RadixArgs<KeyT>& a, int p, const uint32_t* cnt, int drop, const KeyT* ki,
+             const uint32_t* vi, KeyT* kd, uint32_t* vd, bool write_keys, bool gather,
+             hipStream_t st) {
   constexpr int PART = kBlock * ITEMS;
+  constexpr int NB = 1 << BITS;
   const int parts = (int)((a.n_grid + PART - 1) / PART);
   const int shift = p * BITS;
-  hipLaunchKernelGGL((k_rs_upsweep<KeyT, BITS, ITEMS>), dim3(parts), dim3(kBlock), 0, st, ki,
-                     a.count, a.n_grid, shift, a.table, parts);
-  hipLaunchKernelGGL(k_row_scan, dim3(1 << BITS), dim3(kBlock), 0, st, a.table, parts, a.totals);
-  if (write_keys)
-    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, true, false>), dim3(parts), dim3(kBlock),
-                       0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
-                       nullptr, nullptr, nullptr, gs, gd, gc);
-  else
-    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, false, false>), dim3(parts), dim3(kBlock),
-                       0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, a.table, parts, a.totals,
-                       nullptr, nullptr, nullptr, gs, gd, gc);
+  hipLaunchKernelGGL((k_rs_upsweep<KeyT, BITS, ITEMS>), dim3(parts), dim3(kBlock), 0, st, ki, cnt,
+                     a.n_grid, drop, shift, a.table);
+  hipLaunchKernelGGL((k_col_scan<NB, PART>), dim3(NB / 8), dim3(kBlock), 0, st, a.table, cnt,
+                     a.n_grid, a.totals);
+  launch_pass<KeyT, BITS, ITEMS, false>(parts, write_keys, gather, ki, vi, kd, vd, cnt, a.n_grid,
+                                        drop, shift, a.table, a.totals, nullptr, nullptr, nullptr,
+                                        a.gather_src, a.gather_dst, st);
 }
 
 template <typename KeyT, int BITS>
 void pass_t(const RadixArgs<KeyT>& a, int p, int q, const KeyT* ki, const uint32_t* vi, KeyT* kd,
             uint32_t* vd, bool write_keys, bool gather, hipStream_t st) {
   const int shift = p * BITS;
-  const uint2* gs = gather ? a.gather_src : nullptr;
-  uint2* gd = gather ? a.gather_dst : nullptr;
-  const uint32_t* gc = gather ? a.gather_count : nullptr;
+  const bool first = p == 0;
+  const int drop = first && a.drop_first ? 1 : 0;
+  const uint32_t* cnt = (!first && a.drop_first) ? a.count_rest : a.count;
   if (a.mode == 1) {
     const int parts = (int)((a.n_grid + kSortPart - 1) / kSortPart);
     uint32_t* lb = a.lookback + (size_t)(q & 1) * a.lb_parts * 256;
     uint32_t* lb_next = a.lookback + (size_t)((q + 1) & 1) * a.lb_parts * 256;
     const uint32_t* h = a.hist + p * 256;
-    if (write_keys)
-      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, kSortItems, true, true>), dim3(parts),
-                         dim3(kBlock), 0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0,
-                         h, a.tickets + q, lb, lb_next, gs, gd, gc);
-    else
-      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, kSortItems, false, true>), dim3(parts),
-                         dim3(kBlock), 0, st, ki, vi, kd, vd, a.count, a.n_grid, shift, nullptr, 0,
-                         h, a.tickets + q, lb, lb_next, gs, gd, gc);
+    launch_pass<KeyT, BITS, kSortItems, true>(parts, write_keys, gather, ki, vi, kd, vd, cnt,
+                                              a.n_grid, drop, shift, nullptr, h, a.tickets + q, lb,
+                                              lb_next, a.gather_src, a.gather_dst, st);
   } else {
     switch (rs_items(a.n_grid)) {
-      case 16: rs_pass<KeyT, BITS, 16>(a, p, ki, vi, kd, vd, write_keys, gather, st); break;
-      case 8: rs_pass<KeyT, BITS, 8>(a, p, ki, vi, kd, vd, write_keys, gather, st); break;
-      default: rs_pass<KeyT, BITS, 4>(a, p, ki, vi, kd, vd, write_keys, gather, st); break;
+      case 16: rs_pass<KeyT, BITS, 16>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, gather, st); break;
+      case 8: rs_pass<KeyT, BITS, 8>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, gather, st); break;
+      default: rs_pass<KeyT, BITS, 4>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, gather, st); break;
     }
   }
 }
@@ -643,7 +797,7 @@ template <typename KeyT, int BITS>
 void hist_t(const RadixArgs<KeyT>& a, int passes, hipStream_t st) {
   const int parts = (int)((a.n_grid + kSortPart - 1) / kSortPart);
   hipLaunchKernelGGL((k_histogram<KeyT, BITS>), dim3(parts < 512 ? parts : 512), dim3(kBlock), 0,
-                     st, a.kin, a.count, a.n_grid, passes, a.hist);
+                     st, a.kin, a.count, a.n_grid, a.drop_first, passes, a.hist);
 }
 
 }  // namespace
@@ -741,7 +895,7 @@ hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int
     KeyT* kd = to_out ? a.k_out : a.k_alt;
     uint32_t* vd = to_out ? a.v_out : a.v_alt;
     const bool wk = (p + 1 < passes) || last_keys;
-    const bool ga = p + 1 == passes && a.gather_dst != nullptr;
+    const bool ga = p + 1 == passes && a.gather_dst != nullptr && !wk;
     trace_mark(st, label);
     switch (bits) {
       case 6: pass_t<KeyT, 6>(a, p, q, ki, vi, kd, vd, wk, ga, st); break;
@@ -779,7 +933,7 @@ hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* 
 hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
                               uint32_t* ranges, hipStream_t st) {
   if (capacity == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_ranges, dim3(stream_grid(capacity, 4096)), dim3(kBlock), 0, st, count,
+  hipLaunchKernelGGL(k_tile_ranges, dim3(stream_grid((capacity + 3) / 4, 4096)), dim3(kBlock), 0, st, count,
                      tkeys, ranges);
   return hipGetLastError();
 }

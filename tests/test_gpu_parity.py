@@ -203,6 +203,58 @@ def test_sort_keys_tiny(R, orc):
         assert w.max() < (1 / 255) * (1 + 1e-5)
 
 
+def expected_sorted_pairs_np(rec, tiles_x):
+    """Vectorised expected_sorted_pairs for full-size frames: every
+    (Gaussian, tile) pair of the GPU's own records, keyed by (tile, float32
+    depth bits), in numpy's stable order."""
+    vis = np.nonzero(rec["tx1"] >= rec["tx0"])[0]
+    r = rec[vis]
+    w = (r["tx1"] - r["tx0"] + 1).astype(np.int64)
+    h = (r["ty1"] - r["ty0"] + 1).astype(np.int64)
+    cnt = w * h
+    rep = np.repeat(np.arange(vis.size), cnt)
+    local = np.arange(int(cnt.sum()), dtype=np.int64) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    wr = w[rep]
+    ty = r["ty0"][rep] + local // wr
+    tx = r["tx0"][rep] + local % wr
+    zb = np.float32(r["depth"]).view(np.uint32).astype(np.uint64)[rep]
+    keys = ((ty * tiles_x + tx).astype(np.uint64) << np.uint64(32)) | zb
+    vals = vis[rep].astype(np.uint32)
+    perm = np.argsort(keys, kind="stable")
+    return keys[perm], vals[perm]
+
+
+@pytest.mark.parametrize("workload,shape", [("medium", (32, 16, 7)), ("medium", (16, 16, 8)),
+                                            ("large", (8, 8, 8)), ("large", (16, 8, 6))])
+def test_sort_keys_full_size(R, workload, shape):
+    """gs_sort at the benchmark sizes: keys, permutation and tile ranges
+    bit-exact against numpy's stable sort of the GPU's own pairs."""
+    tw, th, bits = shape
+    print_case(f"gs_sort keys {workload} tiles {tw}x{th} {bits}-bit digits")
+    from paper_2512_08478_amd.render import Renderer
+    Rs = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits))
+    sc, cam = S.medium_scene() if workload == "medium" else S.large_scene()
+    fr = Rs.forward(gp(sc), cam, want_keys=True)
+    torch.cuda.synchronize()
+    tiles_x = -(-cam.width // tw)
+    rec = splats_np(fr.splats, sc.n, (tw, th))
+    ek, ev = expected_sorted_pairs_np(rec, tiles_x)
+    n = fr.capacity
+    assert n == ek.size
+    np.testing.assert_array_equal(u64(fr.keys)[:n], ek)
+    np.testing.assert_array_equal(u32(fr.values)[:n], ev)
+    tiles = Rs.tiles(cam)
+    rng = u32(fr.ranges)[:2 * tiles].reshape(-1, 2).astype(np.int64)
+    tile = (ek >> np.uint64(32)).astype(np.int64)
+    starts = np.searchsorted(tile, np.arange(tiles), "left")
+    ends = np.searchsorted(tile, np.arange(tiles), "right")
+    nonempty = ends > starts
+    np.testing.assert_array_equal(rng[nonempty, 0], starts[nonempty])
+    np.testing.assert_array_equal(rng[nonempty, 1], ends[nonempty])
+    assert np.all(rng[~nonempty, 0] == rng[~nonempty, 1])
+    print(f"{workload}: {n} pairs, {int(nonempty.sum())} non-empty tiles")
+
+
 def test_render_tiny_whole_image(R, orc):
     print_case("render tiny 256x256 vs brute force")
     sc, cam = S.tiny_scene()
