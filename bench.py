@@ -32,9 +32,9 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # test 2, T*alpha and the three colour FMAs 7, T *= 1 - alpha 2, stop test 1.
 FLOPS_PER_BLEND = 24
 
-SORT_KERNELS = ("sort_init", "radix_hist", "depth_pass", "kg_count", "kg_scan", "keygen",
+SORT_KERNELS = ("sort_init", "radix_hist", "depth_pass", "kg_count", "kg_hist", "kg_scan", "keygen",
                 "tile_pass", "tile_ranges", "tile_order")
-HBM_KERNELS = ("preprocess", "preprocess_packed", "lbs", "depth_pass", "keygen", "kg_count", "tile_pass",
+HBM_KERNELS = ("preprocess", "preprocess_packed", "lbs", "depth_pass", "keygen", "kg_count", "kg_hist", "tile_pass",
                "tile_ranges", "preprocess_bwd")
 ALU_KERNELS = ("raster", "raster_mesh", "raster_bwd")
 
@@ -107,7 +107,7 @@ def packed_sh_halves(K):
     return (3 * K + 3) // 4 * 4
 
 
-def algorithmic_bytes(n, n_vis, inst, K, W, H, tiles):
+def algorithmic_bytes(n, n_vis, inst, K, W, H, tiles, depth_passes=4):
     """Bytes each kernel must move (reads + writes), per launch."""
     return {
         # means 12 + log-scales 12 + quats 16 + logit 4 read, 48 B record + 4 B depth key
@@ -119,13 +119,20 @@ def algorithmic_bytes(n, n_vis, inst, K, W, H, tiles):
         # canonical mean/opacity 8 + covariance 12 + joint indices 4 + weights 16 read,
         # deformed mean/opacity 8 + covariance 12 written per Gaussian
         "lbs": n * 60,
-        # per depth pass: u32 key + u32 value read and written per Gaussian (upsweep,
-        # scan and downsweep together)
-        "depth_pass": n * 16,
-        # sorted index 4 + record tail 16 read per visible Gaussian
+        # depth passes (upsweep, scan and downsweep together), averaged per pass:
+        # the first reads every Gaussian's u32 key (values are positions) and
+        # writes key + value of the visible ones; each later pass reads and
+        # writes u32 key + u32 value per visible Gaussian
+        "depth_pass": (n * 4 + n_vis * 8 + (depth_passes - 1) * n_vis * 16) / max(depth_passes, 1),
+        # sorted index 4 read, tile rect 8 gathered and written in depth order per
+        # visible Gaussian
         "kg_count": n_vis * 20,
-        # the same reads again; tile key 4 + value 4 written per instance
-        "keygen": n_vis * 20 + inst * 8,
+        # the same, plus the first-tile-digit histogram of each slice (LDS only)
+        "kg_hist": n_vis * 20,
+        # sorted index 4 + sorted rect 8 read per visible Gaussian; tile key 4 +
+        # value 4 written per instance (in the first tile pass's order when the
+        # keygen is fused with that pass)
+        "keygen": n_vis * 12 + inst * 8,
         # per tile pass: u32 key + u32 value read and written per instance
         "tile_pass": inst * 16,
         # sorted tile keys read, two u32 per tile written
@@ -281,7 +288,7 @@ def main():
     import ctypes
     key_bits = L.load().gs_sort_key_bits(ctypes.byref(L.make_camera(cam)), ctypes.byref(R.settings))
     passes = [-(-32 // args.radix_bits), -(-(key_bits - 32) // args.radix_bits)]
-    ab = algorithmic_bytes(sc.n, n_vis, inst, K, W, H, tiles)
+    ab = algorithmic_bytes(sc.n, n_vis, inst, K, W, H, tiles, depth_passes=passes[0])
     stages = {}
     for k, v in kern_avg.items():
         e = {"ms_per_launch": round(v, 5), "ms_per_frame": round(kern_ms[k], 5)}
@@ -334,7 +341,8 @@ def main():
                    "n_gaussians": sc.n, "width": W, "raster_order": order,
                    "height": H, "tile": f"{tw}x{th}", "radix_bits": args.radix_bits,
                    "visible": n_vis, "instances": inst, "key_bits": key_bits,
-                   "depth_passes": passes[0], "tile_passes": passes[1]},
+                   "depth_passes": passes[0], "tile_passes": passes[1],
+                   "first_tile_pass_fused_with_keygen": args.sort_mode == 0},
         "sort_gkeys_per_s": round(inst / (sort_ms * 1e-3) / 1e9, 3) if sort_ms > 0 else None,
         "sort_ms": round(sort_ms, 4),
         "stages": stages,
@@ -457,7 +465,7 @@ def run_batched(args):
     imgs = [im.clone() for im in br.images]
 
     # the plain path: view by view, one count readback per view
-    R = Renderer(best)
+    R = Renderer({k: v for k, v in best.items() if k != "streams"})
     plain_views(p, cams, targets, renderer=R)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -468,9 +476,14 @@ def run_batched(args):
     plain_ms = (time.perf_counter() - t0) * 1e3 / reps
     equal = all(torch.equal(a, b) for a, b in zip(imgs, pimgs))
 
-    # per-kernel times of one eager batch (HIP events on the library's stream)
+    # per-kernel times of one eager batch on one stream (HIP events on the
+    # library's stream)
+    br1 = BatchRenderer(p, cams, targets, dict(best, streams=1))
+    br1.capacity = br.capacity
+    br1.run_eager()
+    torch.cuda.synchronize()
     L.trace_enable(True)
-    br.run_eager()
+    br1.run_eager()
     tr = L.trace_read(4096)
     L.trace_enable(False)
     kern_ms, kern_n = {}, {}

@@ -14,13 +14,20 @@ a step is a single graph launch with no host synchronisation.  Instance capaciti
 counting pass; a view that exceeds its capacity raises its overflow flag,
 which `replay()` checks.
 
-`autotune()` picks the tile shape and the radix digit width (and sort mode)
-by timing whole batches.  Images do not depend on these choices (every tile
-shape composites the same pairs in the same order with the same
-arithmetic), so tuning never changes results.
+Views of one 8-view chunk can run on several HIP streams at once (one
+Renderer, with its own buffers, per stream; the chunk's chain rule joins
+them): a view's sort is a chain of small latency-bound kernels, which
+another view's compositing overlaps.  Captured, the streams become
+parallel branches of the graph.
+
+`autotune()` picks the tile shape and the radix digit width (and sort mode,
+compositing order and stream count) by timing whole batches.  Images do
+not depend on these choices (every tile shape composites the same pairs in
+the same order with the same arithmetic), so tuning never changes results.
 """
 from __future__ import annotations
 
+import contextlib
 import time
 
 import torch
@@ -32,6 +39,7 @@ TILE_SHAPES = ((16, 16), (16, 8), (32, 8), (8, 8), (32, 16))
 RADIX_BITS = (8, 7, 6)
 SORT_MODES = (0, 1)
 RASTER_ORDERS = (1, 0)
+STREAM_COUNTS = (1, 2, 4)
 
 
 def l1_grad(image, target):
@@ -46,13 +54,22 @@ class BatchRenderer:
     """Views x assets forward + backward with fixed per-view capacities."""
 
     def __init__(self, params: GaussianParams, cams, targets, settings=None, headroom=1.10,
-                 device="cuda"):
+                 device="cuda", streams=None):
         if len(cams) != len(targets):
             raise ValueError("one target image per view")
+        settings = dict(settings or {})
+        nst = int(settings.pop("streams", 1) if streams is None else streams)
+        settings.pop("streams", None)
+        if nst < 1:
+            raise ValueError("streams must be >= 1")
         self.p = params
         self.cams = list(cams)
         self.targets = [t.to(device=device, dtype=torch.float32).contiguous() for t in targets]
-        self.R = Renderer(settings, device)
+        # one Renderer (its own reusable buffers) per stream; streams at the
+        # default priority
+        self.Rs = [Renderer(settings, device) for _ in range(nst)]
+        self.R = self.Rs[0]
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(nst)] if nst > 1 else []
         self.headroom = headroom
         self.capacity = None
         self.graph = None
@@ -67,7 +84,7 @@ class BatchRenderer:
     def settings(self):
         s = self.R.settings
         return dict(tile_w=s.tile_w, tile_h=s.tile_h, radix_bits=s.radix_bits,
-                    sort_mode=s.sort_mode, raster_order=s.raster_order)
+                    sort_mode=s.sort_mode, raster_order=s.raster_order, streams=len(self.Rs))
 
     def plan(self):
         """Per-view instance capacities from one counting pass (syncs once per view)."""
@@ -79,17 +96,29 @@ class BatchRenderer:
         return list(caps)
 
     def _enqueue(self):
-        """All views' forward + backward on the current stream; no host sync."""
+        """All views' forward + backward, forked from and joined back into
+        the current stream per chunk; no host sync."""
         images = []
+        main = torch.cuda.current_stream()
+        nst = len(self.Rs)
         for v0 in range(0, len(self.cams), self.chunk):
             cams = self.cams[v0:v0 + self.chunk]
+            for st in self.streams:
+                st.wait_stream(main)
             for k, cam in enumerate(cams):
                 v = v0 + k
-                fr = self.R.forward(self.p, cam, capacity=self.capacity[v])
-                self.flags[v:v + 1].copy_(fr.flag)
-                g = l1_grad(fr.image, self.targets[v])
-                self.R.backward_2d(self.p, cam, fr, g, self.g2d[k])
+                R = self.Rs[k % nst]
+                ctx = torch.cuda.stream(self.streams[k % nst]) if self.streams else contextlib.nullcontext()
+                with ctx:
+                    fr = R.forward(self.p, cam, capacity=self.capacity[v])
+                    self.flags[v:v + 1].copy_(fr.flag)
+                    g = l1_grad(fr.image, self.targets[v])
+                    R.backward_2d(self.p, cam, fr, g, self.g2d[k])
+                if self.streams:
+                    fr.image.record_stream(main)
                 images.append(fr.image)
+            for st in self.streams:
+                main.wait_stream(st)
             self.R.backward_views(self.p, cams, self.g2d[:len(cams)], out=self.grads,
                                   accumulate=v0 > 0)
         return images
@@ -158,11 +187,12 @@ def _time_batch(br: BatchRenderer, reps: int):
 
 
 def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
-             tiles=TILE_SHAPES, bits=RADIX_BITS, modes=SORT_MODES, orders=RASTER_ORDERS, log=None):
-    """Coordinate search: tile shape (at 8-bit digits, mode 0), then digit
-    width, then sort mode, then the compositing order of the tiles, each by
-    the wall time of whole eager batches.  Returns (settings dict,
-    [(settings, seconds)])."""
+             tiles=TILE_SHAPES, bits=RADIX_BITS, modes=SORT_MODES, orders=RASTER_ORDERS,
+             streams=STREAM_COUNTS, log=None):
+    """Coordinate search: tile shape (at 8-bit digits, mode 0, one stream),
+    then digit width, then sort mode, then the compositing order of the
+    tiles, then the number of streams, each by the wall time of whole eager
+    batches.  Returns (settings dict, [(settings, seconds)])."""
     base = dict(base_settings or {})
     table = []
 
@@ -178,7 +208,7 @@ def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
         return t
 
     best = dict(tile_w=tiles[0][0], tile_h=tiles[0][1], radix_bits=bits[0], sort_mode=modes[0],
-                raster_order=orders[0])
+                raster_order=orders[0], streams=streams[0])
     best_t = None
     for tw, th in tiles:
         t = measure(dict(best, tile_w=tw, tile_h=th))
@@ -196,6 +226,10 @@ def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
         t = measure(dict(best, raster_order=o))
         if t < best_t:
             best_t, best = t, dict(best, raster_order=o)
+    for n in streams[1:]:
+        t = measure(dict(best, streams=n))
+        if t < best_t:
+            best_t, best = t, dict(best, streams=n)
     return dict(base, **best), table
 
 

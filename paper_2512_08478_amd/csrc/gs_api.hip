@@ -469,30 +469,38 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   d.k_out = U(L.dk[0]); d.v_out = U(L.dv[0]);
   d.table = U(L.table); d.totals = U(L.totals);
   d.hist = U(L.hist); d.tickets = U(L.tickets); d.lookback = U(L.lookback); d.lb_parts = L.parts;
-  // the last depth pass also gathers the visible Gaussians' tile rects into
-  // depth order, so key generation reads them contiguously
-  uint2* drect = reinterpret_cast<uint2*>(ws + L.drect);
-  d.gather_src = reinterpret_cast<const uint2*>(tile_rects);
-  d.gather_dst = drect;
   e = gs::launch_radix_sort<uint32_t>(d, bits, pd, 0, false, "depth_pass", st);
   if (e != hipSuccess) return hip_fail(e);
-  // instances of the visible Gaussians in depth order, then the tile digits
-  e = gs::launch_keygen(n, U(L.dv[0]), counts + 1, drect, tiles_x, count, U(L.kg_counts),
-                        U(L.totals), U(L.tk[0]), U(L.tv[0]), st);
-  if (e != hipSuccess) return hip_fail(e);
+  // instances of the visible Gaussians in depth order (their tile rects are
+  // gathered into depth order first), then the tile digits
+  uint2* drect = reinterpret_cast<uint2*>(ws + L.drect);
+  const uint2* rects = reinterpret_cast<const uint2*>(tile_rects);
   gs::RadixArgs<uint32_t> t = d;
-  t.gather_src = nullptr;
-  t.gather_dst = nullptr;
   t.n_grid = capacity;
   t.count = count;
   t.drop_first = 0;
   t.count_rest = nullptr;
-  t.kin = U(L.tk[0]);
-  t.vin = U(L.tv[0]);
   t.k_alt = U(L.tk[1]); t.v_alt = U(L.tv[1]);
   t.k_out = U(L.tkf); t.v_out = values;
   t.hist = U(L.hist) + pd * 256;
-  e = gs::launch_radix_sort<uint32_t>(t, bits, pt, pd, true, "tile_pass", st);
+  if (mode == 0) {
+    // key generation writes the output of the first tile pass directly
+    uint32_t* fk = pt > 1 ? U(L.tk[0]) : U(L.tkf);
+    uint32_t* fv = pt > 1 ? U(L.tv[0]) : values;
+    e = gs::launch_keygen_fused(n, bits, U(L.dv[0]), counts + 1, rects, drect, tiles_x, count,
+                                U(L.table), U(L.totals), fk, fv, st);
+    if (e != hipSuccess) return hip_fail(e);
+    t.kin = fk;
+    t.vin = fv;
+    e = gs::launch_radix_sort<uint32_t>(t, bits, pt, pd, true, "tile_pass", st, 1);
+  } else {
+    e = gs::launch_keygen(n, U(L.dv[0]), counts + 1, rects, drect, tiles_x, count,
+                          U(L.kg_counts), U(L.totals), U(L.tk[0]), U(L.tv[0]), st);
+    if (e != hipSuccess) return hip_fail(e);
+    t.kin = U(L.tk[0]);
+    t.vin = U(L.tv[0]);
+    e = gs::launch_radix_sort<uint32_t>(t, bits, pt, pd, true, "tile_pass", st);
+  }
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "tile_ranges");
   e = gs::launch_tile_ranges(capacity, count, U(L.tkf), tile_ranges, st);

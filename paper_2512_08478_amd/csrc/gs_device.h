@@ -24,17 +24,6 @@ __device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
 }
 
-// Inclusive scan of u32 over the 64 lanes.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = shfl_u32(v, l >= d ? l - d : l);
-    if (l >= d) v += o;
-  }
-  return v;
-}
-
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   const int l = lane_id();
 #pragma unroll
@@ -58,6 +47,43 @@ __device__ __forceinline__ float oct_sum_dpp(float v) {
   v += dpp_f32<0x114, 0xF>(v);  // row_shr:4
   return v;
 }
+
+// u32 from another lane by the DPP control CTRL; lanes of rows outside
+// ROW_MASK, and lanes whose source lies outside their row, read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xF, true);
+}
+
+// Inclusive scan of u32 over the 64 lanes on the DPP paths (no LDS): row
+// shifts by 1, 2, 4 and 8 scan each 16-lane row; row_bcast:15 then adds
+// the total of rows 0 and 2 to rows 1 and 3, and row_bcast:31 adds the
+// total of lanes 0-31 to rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
+  v += dpp_u32<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_u32<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_u32<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_u32<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_u32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_u32<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) { return wave_incl_scan_dpp(v); }
+
+// Inclusive max-scan of u32 over the 64 lanes, on the same DPP paths.
+__device__ __forceinline__ uint32_t wave_incl_max_dpp(uint32_t v) {
+  v = max(v, dpp_u32<0x111, 0xF>(v));
+  v = max(v, dpp_u32<0x112, 0xF>(v));
+  v = max(v, dpp_u32<0x114, 0xF>(v));
+  v = max(v, dpp_u32<0x118, 0xF>(v));
+  v = max(v, dpp_u32<0x142, 0xA>(v));
+  v = max(v, dpp_u32<0x143, 0xC>(v));
+  return v;
+}
+
+// The value of the next lower lane (0 for lane 0): DPP wave_shr:1.
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v) { return dpp_u32<0x138, 0xF>(v); }
 
 // Lanes of the wave whose `d` (BITS wide) equals this lane's, among `active`.
 template <int BITS>

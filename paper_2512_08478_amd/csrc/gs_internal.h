@@ -90,10 +90,6 @@ struct RadixArgs {
   uint32_t* tickets;        // mode 1: one per pass
   uint32_t* lookback;       // mode 1: two buffers of lb_parts x 256 words
   int lb_parts;
-  // optional (32-bit keys, last pass writes no keys): the last pass also
-  // writes gather_dst[i] = gather_src[value of sorted position i]
-  const uint2* gather_src;
-  uint2* gather_dst;
 };
 
 // Launchers (enqueue only; return the first launch error).
@@ -129,13 +125,28 @@ hipError_t launch_count_finalize(const uint2* partial, int blocks, uint32_t* cou
 hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
                             int tiles, uint32_t* status_flag, const uint32_t* total_src,
                             int64_t capacity, hipStream_t st, uint32_t* cls_count = nullptr);
+// Passes first_pass .. passes-1 (digit p at shift p * bits); the pass that
+// would have come before first_pass has left its output in kin/vin.
 template <typename KeyT>
 hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int pass_base,
-                             bool last_keys, const char* label, hipStream_t st);
+                             bool last_keys, const char* label, hipStream_t st,
+                             int first_pass = 0);
+// Instances of the depth-sorted visible Gaussians: gathers their tile rects
+// (rects -> sorted_rects, depth order), counts tiles per slice, scans the
+// slices and writes (tile, Gaussian) pairs in depth order.
 hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                         const uint2* sorted_rects, int tiles_x, const uint32_t* inst_count,
-                         uint32_t* kg_counts, uint32_t* kg_total, uint32_t* tkeys, uint32_t* tvals,
-                         hipStream_t st);
+                         const uint2* rects, uint2* sorted_rects, int tiles_x,
+                         const uint32_t* inst_count, uint32_t* kg_counts, uint32_t* kg_total,
+                         uint32_t* tkeys, uint32_t* tvals, hipStream_t st);
+// Key generation fused with the first tile-digit pass (reduce-then-scan
+// mode): the first-digit histogram of each slice (with the rect gather),
+// its column scan into table/totals, and the instances written in the
+// order of that pass to tkeys/tvals.
+hipError_t launch_keygen_fused(int64_t n, int bits, const uint32_t* sorted_idx,
+                               const uint32_t* vis_count, const uint2* rects,
+                               uint2* sorted_rects, int tiles_x, const uint32_t* inst_count,
+                               uint32_t* table, uint32_t* totals, uint32_t* tkeys,
+                               uint32_t* tvals, hipStream_t st);
 hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
                               uint32_t* ranges, hipStream_t st);
 // ranges[2*tiles .. 3*tiles) = the tiles, longest lists first (class

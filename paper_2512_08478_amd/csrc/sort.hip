@@ -109,23 +109,28 @@ __device__ __forceinline__ bool key_kept(KeyT k, uint32_t idx, uint32_t n, int d
 
 // Digit counts of one partition (kBlock * ITEMS keys) per workgroup,
 // written partition-major into table[partition * NB + d], so one
-// workgroup's counts are one contiguous row.  Counting needs no order, so
-// each key is one LDS atomic increment into its wave's own sub-histogram
-// (no ballot matching).
+// workgroup's counts are one contiguous row.  Counting needs no order.
+// LDS atomics that hit one address in one instruction serialise, and the
+// top digits of depth and tile keys cluster (a dense tile's instances
+// share theirs), so each instruction first peels off the digits of its
+// first two remaining lanes with a ballot each (one atomic adds the whole
+// group), and the rest add one per lane into the sub-histogram of their
+// 16-lane group (rows padded by one word, so the groups' copies of a digit
+// sit in different banks).
 template <typename KeyT, int BITS, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ kin,
                                                        const uint32_t* __restrict__ count,
                                                        int64_t n_host, int drop, int shift,
                                                        uint32_t* __restrict__ table) {
   constexpr int NB = 1 << BITS;
-  constexpr int NW = kBlock / 64;
+  constexpr int NS = kBlock / 16;  // sub-histograms
   constexpr int PART = kBlock * ITEMS;
-  __shared__ uint32_t s_h[NW][NB];
-  const int t = threadIdx.x, wave = t >> 6;
+  __shared__ uint32_t s_h[NS][NB + 1];
+  const int t = threadIdx.x, lane = lane_id();
   const uint32_t n = read_n(count, n_host);
   const uint32_t base = blockIdx.x * PART;
   if (base >= n) return;
-  for (int d = t; d < NW * NB; d += kBlock) (&s_h[0][0])[d] = 0;
+  for (int d = t; d < NS * (NB + 1); d += kBlock) (&s_h[0][0])[d] = 0;
   KeyT k[ITEMS];
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
@@ -133,15 +138,29 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ 
     k[i] = idx < n ? kin[idx] : KeyT(0);
   }
   __syncthreads();
+  uint32_t* h = s_h[t >> 4];
+  uint32_t* h0 = s_h[(t >> 6) * 4];  // the wave's first sub-histogram
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i)
-    if (key_kept(k[i], base + i * kBlock + t, n, drop))
-      atomicAdd(&s_h[wave][digit_of<KeyT, BITS>(k[i], shift)], 1u);
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t d = digit_of<KeyT, BITS>(k[i], shift);
+    uint64_t left = ballot(key_kept(k[i], base + i * kBlock + t, n, drop));
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (left) {
+        const int first = __builtin_ctzll(left);
+        const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)d, first);
+        const uint64_t same = ballot(d == dl) & left;
+        if (lane == first) atomicAdd(&h0[dl], (uint32_t)__builtin_popcountll(same));
+        left &= ~same;
+      }
+    }
+    if ((left >> lane) & 1ull) atomicAdd(&h[d], 1u);
+  }
   __syncthreads();
   for (int d = t; d < NB; d += kBlock) {
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) c += s_h[w][d];
+    for (int w = 0; w < NS; ++w) c += s_h[w][d];
     table[(size_t)blockIdx.x * NB + d] = c;
   }
 }
@@ -179,15 +198,16 @@ __global__ __launch_bounds__(kBlock) void k_row_scan(uint32_t* __restrict__ tabl
 
 // Per-digit exclusive prefix over the partitions of the partition-major
 // count table (table[p * NB + d], p < the partitions that hold keys), in
-// place; the digit sums go to totals[d].  Workgroup w owns the 8 digits
-// [8w, 8w + 8): each thread reads 8 consecutive rows' 32-byte slices per
-// round, and the 8 digit columns are scanned side by side.
+// place; the digit sums go to totals[d].  Workgroup w owns the 4 digits
+// [4w, 4w + 4): each thread reads the 16-byte slices of 16 consecutive
+// rows per round, and the 4 digit columns are scanned side by side with
+// DPP wave scans.
 template <int NB, int PART>
 __global__ __launch_bounds__(kBlock) void k_col_scan(uint32_t* __restrict__ table,
                                                      const uint32_t* __restrict__ count,
                                                      int64_t n_host,
                                                      uint32_t* __restrict__ totals) {
-  constexpr int DG = 8, RPT = 8, NW = kBlock / 64;
+  constexpr int DG = 4, RPT = 16, NW = kBlock / 64;
   __shared__ uint32_t s_w[DG][NW];
   const uint32_t n = read_n(count, n_host);
   const int P = (int)((n + PART - 1) / PART);
@@ -197,28 +217,27 @@ __global__ __launch_bounds__(kBlock) void k_col_scan(uint32_t* __restrict__ tabl
 #pragma unroll
   for (int k = 0; k < DG; ++k) carry[k] = 0;
   for (int r0 = 0; r0 < P; r0 += kBlock * RPT) {
-    uint32_t c[RPT][DG];
+    uint4 c[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int row = r0 + t * RPT + i;
-      uint4 a = make_uint4(0u, 0u, 0u, 0u), b = a;
-      if (row < P) {
-        const uint4* src = reinterpret_cast<const uint4*>(table + (size_t)row * NB + d0);
-        a = src[0];
-        b = src[1];
-      }
-      c[i][0] = a.x; c[i][1] = a.y; c[i][2] = a.z; c[i][3] = a.w;
-      c[i][4] = b.x; c[i][5] = b.y; c[i][6] = b.z; c[i][7] = b.w;
+      c[i] = row < P ? *reinterpret_cast<const uint4*>(table + (size_t)row * NB + d0)
+                     : make_uint4(0u, 0u, 0u, 0u);
+    }
+    uint32_t s[DG] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      s[0] += c[i].x;
+      s[1] += c[i].y;
+      s[2] += c[i].z;
+      s[3] += c[i].w;
     }
     uint32_t ex[DG];
 #pragma unroll
     for (int k = 0; k < DG; ++k) {
-      uint32_t s = 0;
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) s += c[i][k];
-      const uint32_t incl = wave_incl_scan(s);
+      const uint32_t incl = wave_incl_scan_dpp(s[k]);
       if (lane == 63) s_w[k][wave] = incl;
-      ex[k] = incl - s;
+      ex[k] = incl - s[k];
     }
     __syncthreads();
 #pragma unroll
@@ -237,13 +256,13 @@ __global__ __launch_bounds__(kBlock) void k_col_scan(uint32_t* __restrict__ tabl
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int row = r0 + t * RPT + i;
-      if (row < P) {
-        uint4* dst = reinterpret_cast<uint4*>(table + (size_t)row * NB + d0);
-        dst[0] = make_uint4(ex[0], ex[1], ex[2], ex[3]);
-        dst[1] = make_uint4(ex[4], ex[5], ex[6], ex[7]);
-      }
-#pragma unroll
-      for (int k = 0; k < DG; ++k) ex[k] += c[i][k];
+      if (row < P)
+        *reinterpret_cast<uint4*>(table + (size_t)row * NB + d0) =
+            make_uint4(ex[0], ex[1], ex[2], ex[3]);
+      ex[0] += c[i].x;
+      ex[1] += c[i].y;
+      ex[2] += c[i].z;
+      ex[3] += c[i].w;
     }
   }
   if (t == 0) {
@@ -307,14 +326,12 @@ __device__ __forceinline__ uint32_t xcd_part(uint32_t b, uint32_t P) {
 //   histogram, offsets by decoupled look-back over lb.
 // WRITE_KEYS = false skips the key stores of a last pass whose keys nobody
 //   reads.
-// GATHER = true also writes gdst[g] = gsrc[value] at every output position g.
-template <typename KeyT, int BITS, int ITEMS, bool WRITE_KEYS, bool LOOKBACK, bool GATHER>
+template <typename KeyT, int BITS, int ITEMS, bool WRITE_KEYS, bool LOOKBACK>
 __global__ __launch_bounds__(kBlock) void k_radix_pass(
     const KeyT* __restrict__ kin, const uint32_t* __restrict__ vin, KeyT* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ count, int64_t n_host, int drop,
     int shift, const uint32_t* __restrict__ table, const uint32_t* __restrict__ totals,
-    uint32_t* __restrict__ ticket, uint32_t* __restrict__ lb, uint32_t* __restrict__ lb_next,
-    const uint2* __restrict__ gsrc, uint2* __restrict__ gdst) {
+    uint32_t* __restrict__ ticket, uint32_t* __restrict__ lb, uint32_t* __restrict__ lb_next) {
   constexpr int NB = 1 << BITS;
   constexpr int NW = kBlock / 64;
   constexpr int PART = kBlock * ITEMS;
@@ -334,8 +351,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
     for (int b = t; b < NW * NB; b += kBlock) (&s_whist[0][0])[b] = 0;
     __syncthreads();
     part = s_part;
-    if (part * PART >= n) return;
+    // the next pass's look-back words of every partition of the grid are
+    // cleared, also by partitions that hold no keys in this pass: a later
+    // pass may hold keys there (the depth passes after the first sort
+    // fewer keys than it, the tile passes more)
     for (int b = t; b < NB; b += kBlock) lb_next[part * NB + b] = 0;
+    if (part * PART >= n) return;
   } else {
     const uint32_t P = (n + PART - 1) / PART;
     if (blockIdx.x >= P) return;
@@ -449,36 +470,15 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
     }
   }
   __syncthreads();
-  if (!GATHER) {
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-      const uint32_t j = (uint32_t)(i * kBlock + t);
-      if (j < nkept) {
-        const KeyT key = s_keys[j];
-        const uint32_t g = s_gbase[digit_of<KeyT, BITS>(key, shift)] + j;
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t j = (uint32_t)(i * kBlock + t);
+    if (j < nkept) {
+      const KeyT key = s_keys[j];
+      const uint32_t g = s_gbase[digit_of<KeyT, BITS>(key, shift)] + j;
+      if (g < n) {  // always true for consistent counts; never stores outside
         if (WRITE_KEYS) kout[g] = key;
         vout[g] = s_vals[j];
-      }
-    }
-  } else {
-    // all gathers in flight before the first store
-    uint32_t g[ITEMS], val[ITEMS];
-    uint2 r[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-      const uint32_t j = (uint32_t)(i * kBlock + t);
-      g[i] = 0xFFFFFFFFu;
-      if (j < nkept) {
-        g[i] = s_gbase[digit_of<KeyT, BITS>(s_keys[j], shift)] + j;
-        val[i] = s_vals[j];
-        r[i] = gsrc[val[i]];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-      if (g[i] != 0xFFFFFFFFu) {
-        vout[g[i]] = val[i];
-        gdst[g[i]] = r[i];
       }
     }
   }
@@ -490,20 +490,39 @@ __device__ __forceinline__ uint32_t rect_tiles(uint32_t lo, uint32_t hi) {
   return ((hi & 0xFFFFu) - (lo & 0xFFFFu) + 1) * ((hi >> 16) - (lo >> 16) + 1);
 }
 
-// Tiles touched by each 1024-Gaussian slice of the depth-sorted visible list.
-__global__ __launch_bounds__(kBlock) void k_kg_count(const uint32_t* __restrict__ vis_count,
-                                                     const uint2* __restrict__ sorted_rects,
+// Tiles touched by each 1024-Gaussian slice of the depth-sorted visible
+// list.  The kernel also gathers the slice's tile rects into depth order
+// (rects[sorted_idx[p]] -> sorted_rects[p]) for k_kg_write: a light kernel
+// with four independent gathers per thread keeps many random reads in
+// flight.
+__global__ __launch_bounds__(kBlock) void k_kg_count(uint32_t n, const uint32_t* __restrict__ vis_count,
+                                                     const uint32_t* __restrict__ sorted_idx,
+                                                     const uint2* __restrict__ rects,
+                                                     uint2* __restrict__ sorted_rects,
                                                      uint32_t* __restrict__ kg_counts) {
   __shared__ uint32_t s_tmp[kBlock / 64];
   const uint32_t nvis = *vis_count;
   const uint32_t base = blockIdx.x * kKgPart;
+  if (base >= nvis) {
+    if (threadIdx.x == 0) kg_counts[blockIdx.x] = 0;
+    return;
+  }
+  // branch-free loads (positions past the end read the last Gaussian and
+  // are ignored), so that all four gathers are in flight together
+  uint32_t g[kKgItems];
+  uint2 r[kKgItems];
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j)
+    g[j] = sorted_idx[min(base + j * kBlock + threadIdx.x, nvis - 1)];
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j) r[j] = rects[min(g[j], n - 1)];  // (indices are < n)
   uint32_t sum = 0;
 #pragma unroll
   for (int j = 0; j < kKgItems; ++j) {
     const uint32_t p = base + j * kBlock + threadIdx.x;
     if (p < nvis) {
-      const uint2 r = sorted_rects[p];
-      sum += rect_tiles(r.x, r.y);
+      sorted_rects[p] = r[j];
+      sum += rect_tiles(r[j].x, r[j].y);
     }
   }
   uint32_t tot;
@@ -515,14 +534,8 @@ __global__ __launch_bounds__(kBlock) void k_kg_count(const uint32_t* __restrict_
 // largest value held by any lower thread, 0 for thread 0.
 __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* s_tmp) {
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  uint32_t incl = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t o = shfl_u32(incl, lane >= d ? lane - d : lane);
-    if (lane >= d) incl = max(incl, o);
-  }
-  uint32_t excl = shfl_u32(incl, lane > 0 ? lane - 1 : 0);
-  if (lane == 0) excl = 0;
+  const uint32_t incl = wave_incl_max_dpp(v);
+  uint32_t excl = wave_shr1(incl);
   if (lane == 63) s_tmp[wave] = incl;
   __syncthreads();
 #pragma unroll
@@ -631,6 +644,252 @@ __global__ __launch_bounds__(kBlock) void k_kg_write(const uint32_t* __restrict_
   }
 }
 
+// ---------------------------------------------------------------- keygen + first tile pass
+
+// First-tile-digit histogram of each 1024-Gaussian slice of the depth-sorted
+// visible list, written partition-major (table[slice * NB + d]), with the
+// rect gather of k_kg_count.  The tiles of one row of a rect have
+// consecutive ids, so their digits are consecutive residues mod NB: each
+// row adds one over a circular range of digits, which a difference array
+// in LDS takes as two increments (four across the wrap), and each whole
+// turn of NB tiles adds one to every digit.
+template <int BITS>
+__global__ __launch_bounds__(kBlock) void k_kg_hist(uint32_t n, const uint32_t* __restrict__ vis_count,
+                                                    const uint32_t* __restrict__ sorted_idx,
+                                                    const uint2* __restrict__ rects,
+                                                    uint2* __restrict__ sorted_rects,
+                                                    int tiles_x, uint32_t* __restrict__ table) {
+  constexpr int NB = 1 << BITS;
+  __shared__ int s_diff[NB + 1];
+  __shared__ uint32_t s_tmp[kBlock / 64];
+  __shared__ uint32_t s_turns;
+  const int t = threadIdx.x;
+  const uint32_t nvis = *vis_count;
+  const uint32_t base = blockIdx.x * kKgPart;
+  if (base >= nvis) return;
+  for (int d = t; d <= NB; d += kBlock) s_diff[d] = 0;
+  if (t == 0) s_turns = 0;
+  // branch-free loads (positions past the end read the last Gaussian and
+  // are ignored), so that all four gathers are in flight together
+  uint32_t g[kKgItems];
+  uint2 r[kKgItems];
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j) g[j] = sorted_idx[min(base + j * kBlock + t, nvis - 1)];
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j) r[j] = rects[min(g[j], n - 1)];  // (indices are < n)
+  __syncthreads();
+  uint32_t turns = 0;
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j) {
+    const uint32_t p = base + j * kBlock + t;
+    if (p < nvis) {
+      sorted_rects[p] = r[j];
+      const uint32_t tx0 = r[j].x & 0xFFFFu, ty0 = r[j].x >> 16;
+      const uint32_t tx1 = r[j].y & 0xFFFFu, ty1 = r[j].y >> 16;
+      const uint32_t w = tx1 - tx0 + 1;
+      const uint32_t full = w >> BITS, rem = w & (NB - 1);
+      turns += full * (ty1 - ty0 + 1);
+      if (rem) {
+        for (uint32_t ty = ty0; ty <= ty1; ++ty) {
+          const uint32_t a = (ty * (uint32_t)tiles_x + tx0) & (NB - 1), e = a + rem;
+          atomicAdd(&s_diff[a], 1);
+          if (e <= NB) {
+            atomicAdd(&s_diff[e], -1);
+          } else {
+            atomicAdd(&s_diff[0], 1);
+            atomicAdd(&s_diff[e - NB], -1);
+          }
+        }
+      }
+    }
+  }
+  turns = wave_sum_u32(turns);
+  if (lane_id() == 0 && turns) atomicAdd(&s_turns, turns);
+  __syncthreads();
+  const uint32_t v = t < NB ? (uint32_t)s_diff[t] : 0u;
+  uint32_t tot;
+  const uint32_t incl = block_excl_scan(v, s_tmp, &tot) + v;
+  if (t < NB) table[(size_t)blockIdx.x * NB + t] = incl + s_turns;
+}
+
+// Key generation fused with the first radix pass over the tile keys.  Each
+// slice's instances (depth order, then row-major within a rect) are
+// expanded in windows of 2048 as in k_kg_write, ranked within the window by
+// their first tile digit (ballot matching, stable), staged in digit order
+// and written at the digit's running offset: its global start (scanned
+// digit totals), plus its count in the earlier slices (scanned table),
+// plus the earlier windows.  The result is the first pass's output, with
+// no key list written and read back in between.  Positions at or past
+// `cap` are skipped (capacity overflow); every position below it still
+// receives exactly one pair.
+template <int BITS>
+__global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restrict__ sorted_idx,
+                                                       const uint32_t* __restrict__ vis_count,
+                                                       const uint2* __restrict__ sorted_rects,
+                                                       int tiles_x,
+                                                       const uint32_t* __restrict__ inst_count,
+                                                       const uint32_t* __restrict__ table,
+                                                       const uint32_t* __restrict__ totals,
+                                                       uint32_t* __restrict__ tkeys,
+                                                       uint32_t* __restrict__ tvals) {
+  constexpr int NB = 1 << BITS;
+  constexpr int NW = kBlock / 64;
+  constexpr int IT = kKgWinItems;
+  __shared__ uint32_t s_off[kKgPart];
+  __shared__ uint32_t s_lo[kKgPart], s_hi[kKgPart], s_g[kKgPart];
+  __shared__ uint32_t s_own[kKgWin];  // window owners, then the staged keys
+  __shared__ uint32_t s_val[kKgWin];
+  __shared__ uint32_t s_whist[NW][NB];
+  __shared__ uint32_t s_local[NB], s_scat[NB];
+  __shared__ uint32_t s_tmp[NW], s_sc[NW];
+  const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+  const uint32_t nvis = *vis_count, cap = *inst_count;
+  const uint32_t nsl = (nvis + kKgPart - 1) / kKgPart;
+  if (blockIdx.x >= nsl) return;
+  const uint32_t slice = blockIdx.x;
+  const uint32_t base = slice * kKgPart;
+  // every load of the prologue is issued before the first is used
+  // (branch-free: positions past the end read the last Gaussian)
+  const uint32_t gcount = t < NB ? totals[t] : 0u;
+  const uint32_t tprefix = t < NB ? table[(size_t)slice * NB + t] : 0u;
+  uint32_t gi[kKgItems];
+  uint2 rr[kKgItems];
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j) {
+    const uint32_t pc = min(base + t * kKgItems + j, nvis - 1);
+    gi[j] = sorted_idx[pc];
+    rr[j] = sorted_rects[pc];
+  }
+  uint32_t cnt[kKgItems], off[kKgItems], sum = 0;
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j) {
+    const int li = t * kKgItems + j;
+    const bool ok = base + li < nvis;
+    const uint32_t c = ok ? rect_tiles(rr[j].x, rr[j].y) : 0u;
+    s_g[li] = gi[j];
+    s_lo[li] = rr[j].x;
+    s_hi[li] = rr[j].y;
+    cnt[j] = c;
+    sum += c;
+  }
+  uint32_t btot;
+  uint32_t run = block_excl_scan(sum, s_tmp, &btot);
+#pragma unroll
+  for (int j = 0; j < kKgItems; ++j) {
+    off[j] = run;
+    s_off[t * kKgItems + j] = run;
+    run += cnt[j];
+  }
+  // running write base of digit t: its global start plus its count in the
+  // earlier slices
+  uint32_t gb = 0;
+  {
+    uint32_t all;
+    const uint32_t gstart = block_excl_scan(gcount, s_sc, &all);
+    if (t < NB) gb = gstart + tprefix;
+  }
+  const uint64_t lt = lanemask_lt();
+  for (uint32_t w0 = 0; w0 < btot; w0 += kKgWin) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) s_own[t * IT + k] = 0;
+    for (int b = t; b < NW * NB; b += kBlock) (&s_whist[0][0])[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kKgItems; ++j) {
+      if (cnt[j] && off[j] < w0 + kKgWin && off[j] + cnt[j] > w0)
+        s_own[(off[j] > w0 ? off[j] : w0) - w0] = (uint32_t)(t * kKgItems + j) + 1;
+    }
+    __syncthreads();
+    {
+      uint32_t v[IT], m = 0;
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        v[k] = s_own[t * IT + k];
+        m = max(m, v[k]);
+      }
+      uint32_t carry = block_excl_max(m, s_tmp);
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        carry = max(carry, v[k]);
+        s_own[t * IT + k] = carry;
+      }
+    }
+    __syncthreads();
+    // this thread's instances, warp-striped: wave w holds window positions
+    // [w*64*IT, (w+1)*64*IT), lane-minor, so ranking order = window order
+    uint32_t key[IT], val[IT], pos[IT], kept = 0;
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const uint32_t q = (uint32_t)(wave * 64 * IT + i * 64 + lane);
+      const uint32_t kk = w0 + q;
+      key[i] = 0;
+      val[i] = 0;
+      if (kk < btot) {
+        const uint32_t li = s_own[q] - 1;
+        const uint32_t local = kk - s_off[li];
+        const uint32_t rl = s_lo[li], rh = s_hi[li];
+        const uint32_t tx0 = rl & 0xFFFFu, ty0 = rl >> 16, tx1 = rh & 0xFFFFu;
+        const uint32_t w = tx1 - tx0 + 1;
+        const uint32_t ry = local / w;
+        key[i] = (ty0 + ry) * (uint32_t)tiles_x + tx0 + (local - ry * w);
+        val[i] = s_g[li];
+        kept |= 1u << i;
+      }
+    }
+    __syncthreads();  // s_own is read; it stages the keys next
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const bool keep = (kept >> i) & 1u;
+      const uint32_t d = key[i] & (NB - 1);
+      const uint64_t peers = match_digit<BITS>(d, ballot(keep));
+      const uint32_t c = s_whist[wave][d];
+      pos[i] = c + (uint32_t)__builtin_popcountll(peers & lt);
+      if (keep && (peers & lt) == 0) s_whist[wave][d] = c + (uint32_t)__builtin_popcountll(peers);
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    if (t < NB) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t x = s_whist[w][t];
+        s_whist[w][t] = tot;
+        tot += x;
+      }
+    }
+    uint32_t nwin;
+    const uint32_t lstart = block_excl_scan(tot, s_sc, &nwin);
+    if (t < NB) {
+      s_local[t] = lstart;
+      s_scat[t] = gb - lstart;
+      gb += tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      if ((kept >> i) & 1u) {
+        const uint32_t d = key[i] & (NB - 1);
+        const uint32_t p = pos[i] + s_local[d] + s_whist[wave][d];
+        s_own[p] = key[i];
+        s_val[p] = val[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const uint32_t j = (uint32_t)(i * kBlock + t);
+      if (j < nwin) {
+        const uint32_t k = s_own[j];
+        const uint32_t g = s_scat[k & (NB - 1)] + j;
+        if (g < cap) {
+          tkeys[g] = k;
+          tvals[g] = s_val[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Tile ranges of the sorted tile keys.  Each thread takes 4 consecutive
 // keys with one 16-byte load plus the keys on either side.  The key buffer
 // is padded to a multiple of 64 keys, so the vector load of the last group
@@ -729,49 +988,40 @@ inline int rs_items(int64_t n) {
   return 4;
 }
 
-// Launch of one downsweep kernel for the chosen key-store and gather
-// variants (gathers serve only 32-bit passes that write no keys).
+// Launch of one downsweep kernel with or without key stores.
 template <typename KeyT, int BITS, int ITEMS, bool LOOKBACK>
-void launch_pass(int grid, bool write_keys, bool gather, const KeyT* ki, const uint32_t* vi,
-                 KeyT* kd, uint32_t* vd, const uint32_t* cnt, int64_t n_grid, int drop, int shift,
+void launch_pass(int grid, bool write_keys, const KeyT* ki, const uint32_t* vi, KeyT* kd,
+                 uint32_t* vd, const uint32_t* cnt, int64_t n_grid, int drop, int shift,
                  const uint32_t* table, const uint32_t* totals, uint32_t* ticket, uint32_t* lb,
-                 uint32_t* lb_next, const uint2* gs, uint2* gd, hipStream_t st) {
-  if (gather) {
-    if constexpr (sizeof(KeyT) == 4)
-      hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, false, LOOKBACK, true>), dim3(grid),
-                         dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, shift, table,
-                         totals, ticket, lb, lb_next, gs, gd);
-  } else if (write_keys) {
-    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, true, LOOKBACK, false>), dim3(grid),
+                 uint32_t* lb_next, hipStream_t st) {
+  if (write_keys)
+    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, true, LOOKBACK>), dim3(grid),
                        dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, shift, table,
-                       totals, ticket, lb, lb_next, gs, gd);
-  } else {
-    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, false, LOOKBACK, false>), dim3(grid),
+                       totals, ticket, lb, lb_next);
+  else
+    hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, false, LOOKBACK>), dim3(grid),
                        dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, shift, table,
-                       totals, ticket, lb, lb_next, gs, gd);
-  }
+                       totals, ticket, lb, lb_next);
 }
 
 template <typename KeyT, int BITS, int ITEMS>
 void rs_pass(const RadixArgs<KeyT>& a, int p, const uint32_t* cnt, int drop, const KeyT* ki,
-             const uint32_t* vi, KeyT* kd, uint32_t* vd, bool write_keys, bool gather,
-             hipStream_t st) {
+             const uint32_t* vi, KeyT* kd, uint32_t* vd, bool write_keys, hipStream_t st) {
   constexpr int PART = kBlock * ITEMS;
   constexpr int NB = 1 << BITS;
   const int parts = (int)((a.n_grid + PART - 1) / PART);
   const int shift = p * BITS;
   hipLaunchKernelGGL((k_rs_upsweep<KeyT, BITS, ITEMS>), dim3(parts), dim3(kBlock), 0, st, ki, cnt,
                      a.n_grid, drop, shift, a.table);
-  hipLaunchKernelGGL((k_col_scan<NB, PART>), dim3(NB / 8), dim3(kBlock), 0, st, a.table, cnt,
+  hipLaunchKernelGGL((k_col_scan<NB, PART>), dim3(NB / 4), dim3(kBlock), 0, st, a.table, cnt,
                      a.n_grid, a.totals);
-  launch_pass<KeyT, BITS, ITEMS, false>(parts, write_keys, gather, ki, vi, kd, vd, cnt, a.n_grid,
-                                        drop, shift, a.table, a.totals, nullptr, nullptr, nullptr,
-                                        a.gather_src, a.gather_dst, st);
+  launch_pass<KeyT, BITS, ITEMS, false>(parts, write_keys, ki, vi, kd, vd, cnt, a.n_grid, drop,
+                                        shift, a.table, a.totals, nullptr, nullptr, nullptr, st);
 }
 
 template <typename KeyT, int BITS>
 void pass_t(const RadixArgs<KeyT>& a, int p, int q, const KeyT* ki, const uint32_t* vi, KeyT* kd,
-            uint32_t* vd, bool write_keys, bool gather, hipStream_t st) {
+            uint32_t* vd, bool write_keys, hipStream_t st) {
   const int shift = p * BITS;
   const bool first = p == 0;
   const int drop = first && a.drop_first ? 1 : 0;
@@ -781,14 +1031,14 @@ void pass_t(const RadixArgs<KeyT>& a, int p, int q, const KeyT* ki, const uint32
     uint32_t* lb = a.lookback + (size_t)(q & 1) * a.lb_parts * 256;
     uint32_t* lb_next = a.lookback + (size_t)((q + 1) & 1) * a.lb_parts * 256;
     const uint32_t* h = a.hist + p * 256;
-    launch_pass<KeyT, BITS, kSortItems, true>(parts, write_keys, gather, ki, vi, kd, vd, cnt,
-                                              a.n_grid, drop, shift, nullptr, h, a.tickets + q, lb,
-                                              lb_next, a.gather_src, a.gather_dst, st);
+    launch_pass<KeyT, BITS, kSortItems, true>(parts, write_keys, ki, vi, kd, vd, cnt, a.n_grid,
+                                              drop, shift, nullptr, h, a.tickets + q, lb, lb_next,
+                                              st);
   } else {
     switch (rs_items(a.n_grid)) {
-      case 16: rs_pass<KeyT, BITS, 16>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, gather, st); break;
-      case 8: rs_pass<KeyT, BITS, 8>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, gather, st); break;
-      default: rs_pass<KeyT, BITS, 4>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, gather, st); break;
+      case 16: rs_pass<KeyT, BITS, 16>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, st); break;
+      case 8: rs_pass<KeyT, BITS, 8>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, st); break;
+      default: rs_pass<KeyT, BITS, 4>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, st); break;
     }
   }
 }
@@ -877,8 +1127,9 @@ hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* t
 
 template <typename KeyT>
 hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int pass_base,
-                             bool last_keys, const char* label, hipStream_t st) {
-  if (a.n_grid == 0 || passes == 0) return hipSuccess;
+                             bool last_keys, const char* label, hipStream_t st, int first_pass) {
+  if (a.n_grid == 0 || passes <= first_pass) return hipSuccess;
+  if (first_pass > 0 && a.mode == 1) return hipErrorInvalidValue;
   if (a.mode == 1) {
     trace_mark(st, "radix_hist");
     switch (bits) {
@@ -889,18 +1140,17 @@ hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int
   }
   const KeyT* ki = a.kin;
   const uint32_t* vi = a.vin;
-  for (int p = 0; p < passes; ++p) {
+  for (int p = first_pass; p < passes; ++p) {
     const int q = pass_base + p;  // global pass index: ticket and look-back buffer parity
     const bool to_out = ((passes - 1 - p) % 2) == 0;
     KeyT* kd = to_out ? a.k_out : a.k_alt;
     uint32_t* vd = to_out ? a.v_out : a.v_alt;
     const bool wk = (p + 1 < passes) || last_keys;
-    const bool ga = p + 1 == passes && a.gather_dst != nullptr && !wk;
     trace_mark(st, label);
     switch (bits) {
-      case 6: pass_t<KeyT, 6>(a, p, q, ki, vi, kd, vd, wk, ga, st); break;
-      case 7: pass_t<KeyT, 7>(a, p, q, ki, vi, kd, vd, wk, ga, st); break;
-      default: pass_t<KeyT, 8>(a, p, q, ki, vi, kd, vd, wk, ga, st); break;
+      case 6: pass_t<KeyT, 6>(a, p, q, ki, vi, kd, vd, wk, st); break;
+      case 7: pass_t<KeyT, 7>(a, p, q, ki, vi, kd, vd, wk, st); break;
+      default: pass_t<KeyT, 8>(a, p, q, ki, vi, kd, vd, wk, st); break;
     }
     ki = kd;
     vi = vd;
@@ -908,25 +1158,62 @@ hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int
   return hipGetLastError();
 }
 template hipError_t launch_radix_sort<uint32_t>(const RadixArgs<uint32_t>&, int, int, int, bool,
-                                                const char*, hipStream_t);
+                                                const char*, hipStream_t, int);
 template hipError_t launch_radix_sort<uint64_t>(const RadixArgs<uint64_t>&, int, int, int, bool,
-                                                const char*, hipStream_t);
+                                                const char*, hipStream_t, int);
 
 hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                         const uint2* sorted_rects, int tiles_x, const uint32_t* inst_count,
-                         uint32_t* kg_counts, uint32_t* kg_total, uint32_t* tkeys, uint32_t* tvals,
-                         hipStream_t st) {
+                         const uint2* rects, uint2* sorted_rects, int tiles_x,
+                         const uint32_t* inst_count, uint32_t* kg_counts, uint32_t* kg_total,
+                         uint32_t* tkeys, uint32_t* tvals, hipStream_t st) {
   const int parts = (int)((n + kKgPart - 1) / kKgPart);
   if (parts == 0) return hipSuccess;
   trace_mark(st, "kg_count");
-  hipLaunchKernelGGL(k_kg_count, dim3(parts), dim3(kBlock), 0, st, vis_count, sorted_rects,
-                     kg_counts);
+  hipLaunchKernelGGL(k_kg_count, dim3(parts), dim3(kBlock), 0, st, (uint32_t)n, vis_count,
+                     sorted_idx, rects, sorted_rects, kg_counts);
   trace_mark(st, "kg_scan");
   hipLaunchKernelGGL(k_row_scan, dim3(1), dim3(kBlock), 0, st, kg_counts, parts, kg_total);
   trace_mark(st, "keygen");
   hipLaunchKernelGGL(k_kg_write, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count,
                      sorted_rects,
                      tiles_x, inst_count, kg_counts, tkeys, tvals);
+  return hipGetLastError();
+}
+
+namespace {
+template <int BITS>
+void kg_fused_t(int64_t n, int parts, const uint32_t* sorted_idx, const uint32_t* vis_count,
+                const uint2* rects, uint2* sorted_rects, int tiles_x, const uint32_t* inst_count,
+                uint32_t* table, uint32_t* totals, uint32_t* tkeys, uint32_t* tvals,
+                hipStream_t st) {
+  constexpr int NB = 1 << BITS;
+  trace_mark(st, "kg_hist");
+  hipLaunchKernelGGL(k_kg_hist<BITS>, dim3(parts), dim3(kBlock), 0, st, (uint32_t)n, vis_count,
+                     sorted_idx, rects, sorted_rects, tiles_x, table);
+  trace_mark(st, "kg_scan");
+  hipLaunchKernelGGL((k_col_scan<NB, kKgPart>), dim3(NB / 4), dim3(kBlock), 0, st, table,
+                     vis_count, (int64_t)0, totals);
+  trace_mark(st, "keygen");
+  hipLaunchKernelGGL(k_kg_scatter<BITS>, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count,
+                     sorted_rects, tiles_x, inst_count, table, totals, tkeys, tvals);
+}
+}  // namespace
+
+hipError_t launch_keygen_fused(int64_t n, int bits, const uint32_t* sorted_idx,
+                               const uint32_t* vis_count, const uint2* rects,
+                               uint2* sorted_rects, int tiles_x, const uint32_t* inst_count,
+                               uint32_t* table, uint32_t* totals, uint32_t* tkeys,
+                               uint32_t* tvals, hipStream_t st) {
+  const int parts = (int)((n + kKgPart - 1) / kKgPart);
+  if (parts == 0) return hipSuccess;
+  switch (bits) {
+    case 6: kg_fused_t<6>(n, parts, sorted_idx, vis_count, rects, sorted_rects, tiles_x, inst_count,
+                          table, totals, tkeys, tvals, st); break;
+    case 7: kg_fused_t<7>(n, parts, sorted_idx, vis_count, rects, sorted_rects, tiles_x, inst_count,
+                          table, totals, tkeys, tvals, st); break;
+    default: kg_fused_t<8>(n, parts, sorted_idx, vis_count, rects, sorted_rects, tiles_x,
+                           inst_count, table, totals, tkeys, tvals, st); break;
+  }
   return hipGetLastError();
 }
 

@@ -110,14 +110,15 @@ def _rel_max(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
 
 
-def test_graph_batch_matches_plain_views_on_every_replay(R):
-    print_case("graph-captured batch vs plain views, 3 replays")
+@pytest.mark.parametrize("streams", [1, 3])
+def test_graph_batch_matches_plain_views_on_every_replay(R, streams):
+    print_case(f"graph-captured batch on {streams} stream(s) vs plain views, 3 replays")
     from paper_2512_08478_amd.batch import BatchRenderer, plain_views
     assets, cams = small_batch(n_views=4)
     p = concat_params(assets)
     tg = targets_for(cams)
     imgs_ref, grads_ref = plain_views(p, cams, tg)
-    br = BatchRenderer(p, cams, tg)
+    br = BatchRenderer(p, cams, tg, streams=streams)
     br.capture()
     noise = torch.randn(512, 512, device="cuda")
     for rep in range(3):
@@ -154,8 +155,8 @@ def test_autotuned_settings_leave_images_unchanged(R):
     p = concat_params(assets)
     tg = targets_for(cams)
     best, table = autotune(p, cams, tg, reps=1, tiles=((16, 16), (8, 8), (32, 8)), bits=(8, 6),
-                           modes=(0, 1))
-    assert len(table) == 3 + 1 + 1 + 1
+                           modes=(0, 1), streams=(1, 2))
+    assert len(table) == 3 + 1 + 1 + 1 + 1
     ref = BatchRenderer(p, cams, tg)
     ref_imgs = [im.clone() for im in ref.run_eager()]
     tuned = BatchRenderer(p, cams, tg, best)

@@ -224,15 +224,19 @@ def expected_sorted_pairs_np(rec, tiles_x):
     return keys[perm], vals[perm]
 
 
-@pytest.mark.parametrize("workload,shape", [("medium", (32, 16, 7)), ("medium", (16, 16, 8)),
-                                            ("large", (8, 8, 8)), ("large", (16, 8, 6))])
-def test_sort_keys_full_size(R, workload, shape):
+@pytest.mark.parametrize("workload,shape,mode", [("medium", (32, 16, 7), 0), ("medium", (16, 16, 8), 0),
+                                                 ("large", (8, 8, 8), 0), ("large", (16, 8, 6), 0),
+                                                 ("medium", (16, 16, 8), 1), ("large", (8, 8, 8), 1)])
+def test_sort_keys_full_size(R, workload, shape, mode):
     """gs_sort at the benchmark sizes: keys, permutation and tile ranges
-    bit-exact against numpy's stable sort of the GPU's own pairs."""
+    bit-exact against numpy's stable sort of the GPU's own pairs.  Sort mode
+    1 covers the onesweep look-back across the switch from the depth passes
+    (visible Gaussians only after the first) to the tile passes (more
+    partitions): every look-back word must be clear when its pass starts."""
     tw, th, bits = shape
-    print_case(f"gs_sort keys {workload} tiles {tw}x{th} {bits}-bit digits")
+    print_case(f"gs_sort keys {workload} tiles {tw}x{th} {bits}-bit digits, sort mode {mode}")
     from paper_2512_08478_amd.render import Renderer
-    Rs = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits))
+    Rs = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=mode))
     sc, cam = S.medium_scene() if workload == "medium" else S.large_scene()
     fr = Rs.forward(gp(sc), cam, want_keys=True)
     torch.cuda.synchronize()
