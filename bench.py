@@ -235,11 +235,12 @@ def main():
     inst = fr.capacity
     mesh = fr.mesh   # device buffers, uploaded once
     capacity = inst
+    depth_bits = fr.depth_bits   # the visible depth key range of this (static) view
 
     def step():
         if skin is not None:
             R.lbs_deform(canon, *skin, out=p)   # the pre-decoder runs every frame
-        f = R.forward(p, cam, capacity=capacity, mesh=mesh)
+        f = R.forward(p, cam, capacity=capacity, mesh=mesh, depth_bits=depth_bits)
         if backward:
             # L1 loss gradient w.r.t. RGB (the caller's loss, not part of the method)
             G = torch.zeros((H, W, 4), device="cuda")
@@ -259,6 +260,8 @@ def main():
     flag = int(f.flag[0].item()) & 0xFFFFFFFF
     if flag & 1:
         raise RuntimeError("instance capacity exceeded during the timed steps")
+    if flag & 2:
+        raise RuntimeError("depth key range wider than planned during the timed steps")
 
     # per-kernel durations, measured with HIP events recorded by libgs on the
     # stream its kernels run on
@@ -287,7 +290,11 @@ def main():
     tiles = R.tiles(cam)
     import ctypes
     key_bits = L.load().gs_sort_key_bits(ctypes.byref(L.make_camera(cam)), ctypes.byref(R.settings))
-    passes = [-(-32 // args.radix_bits), -(-(key_bits - 32) // args.radix_bits)]
+    if depth_bits > 0 and args.sort_mode == 0:
+        depth_passes = -(-depth_bits // 9)
+    else:
+        depth_passes = -(-(depth_bits or 32) // args.radix_bits)
+    passes = [depth_passes, -(-(key_bits - 32) // args.radix_bits)]
     ab = algorithmic_bytes(sc.n, n_vis, inst, K, W, H, tiles, depth_passes=passes[0])
     stages = {}
     for k, v in kern_avg.items():
@@ -341,7 +348,7 @@ def main():
                    "n_gaussians": sc.n, "width": W, "raster_order": order,
                    "height": H, "tile": f"{tw}x{th}", "radix_bits": args.radix_bits,
                    "visible": n_vis, "instances": inst, "key_bits": key_bits,
-                   "depth_passes": passes[0], "tile_passes": passes[1],
+                   "depth_bits": depth_bits, "depth_passes": passes[0], "tile_passes": passes[1],
                    "first_tile_pass_fused_with_keygen": args.sort_mode == 0},
         "sort_gkeys_per_s": round(inst / (sort_ms * 1e-3) / 1e9, 3) if sort_ms > 0 else None,
         "sort_ms": round(sort_ms, 4),

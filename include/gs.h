@@ -84,6 +84,17 @@ typedef struct gs_camera {
  *                    (gs_sort then also writes that order).  gs_sort and
  *                    the compositing calls of a frame must use the same
  *                    value.  Images do not depend on it.
+ *   depth_bits 0     how many bits of the depth keys gs_sort orders.  0:
+ *                    all 32 bits, in radix_bits-wide passes.  1..32: the
+ *                    keys relative to the smallest visible key (counts[2]
+ *                    of gs_preprocess), in ceil(depth_bits / 9) passes of
+ *                    at most 9 bits in sort mode 0 (radix_bits-wide passes
+ *                    in mode 1).  The caller takes it from the bit length
+ *                    of counts[3] - counts[2] (the same frame, or a
+ *                    previous one with headroom); if the frame's range does
+ *                    not fit, gs_sort sets bit 1 of status_flag, the order
+ *                    is not valid, and the caller sorts again with more
+ *                    bits.  The order, when valid, does not depend on it.
  */
 typedef struct gs_settings {
   int32_t tile_w, tile_h;
@@ -96,6 +107,7 @@ typedef struct gs_settings {
   int32_t radix_bits;
   int32_t sort_mode;
   int32_t raster_order;
+  int32_t depth_bits;
 } gs_settings;
 
 /*
@@ -184,8 +196,11 @@ int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set);
  *   tile_rects[2n]  u32 pair per Gaussian: the tile rect of its record,
  *                   (tx0 | ty0 << 16, tx1 | ty1 << 16), packed densely so
  *                   that key generation gathers 8 bytes per Gaussian.
- *   counts[2]       u32: counts[0] = (Gaussian, tile) instances in total,
- *                   counts[1] = visible Gaussians.
+ *   counts[4]       u32: counts[0] = (Gaussian, tile) instances in total,
+ *                   counts[1] = visible Gaussians, counts[2] and counts[3]
+ *                   = the smallest and the largest depth key of a visible
+ *                   Gaussian (0xFFFFFFFF and 0 when none is visible); the
+ *                   host may read the range back to plan depth_bits.
  * Culled (record with an empty rect, zero tiles): camera depth <= znear,
  * opacity < alpha_min, non-finite values, zero quaternion, or a footprint
  * whose opacity-aware bounding box (where o*exp(-Q/2) >= alpha_min)
@@ -322,7 +337,8 @@ int32_t gs_preprocess_packed(int32_t n_assets, const gs_asset* assets, int64_t n
  * Counts are read on the device; there is no host sync.  When counts[0] >
  * capacity, only the first `capacity` instances in depth order are kept,
  * `status_flag[0]` (device u32, may be NULL) gets bit 0 set, and the caller
- * retries with a larger capacity after checking the flag.
+ * retries with a larger capacity after checking the flag.  Bit 1 reports a
+ * depth key range wider than settings.depth_bits (see gs_settings).
  * Workspace: gs_workspace_size(GS_STAGE_SORT, n, capacity, cam, set).
  */
 int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,

@@ -64,7 +64,7 @@ class GsSettings(ctypes.Structure):
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_eps", ctypes.c_float), ("clip", ctypes.c_float), ("bg", ctypes.c_float * 3),
                 ("radix_bits", ctypes.c_int32), ("sort_mode", ctypes.c_int32),
-                ("raster_order", ctypes.c_int32)]
+                ("raster_order", ctypes.c_int32), ("depth_bits", ctypes.c_int32)]
 
 
 class GsAsset(ctypes.Structure):

@@ -33,7 +33,7 @@ import time
 import torch
 
 from . import _lib as L
-from .render import GaussianParams, Renderer
+from .render import GaussianParams, Renderer, depth_range_bits
 
 TILE_SHAPES = ((16, 16), (16, 8), (32, 8), (8, 8), (32, 16))
 RADIX_BITS = (8, 7, 6)
@@ -87,12 +87,16 @@ class BatchRenderer:
                     sort_mode=s.sort_mode, raster_order=s.raster_order, streams=len(self.Rs))
 
     def plan(self):
-        """Per-view instance capacities from one counting pass (syncs once per view)."""
-        caps = []
+        """Per-view instance capacities and depth key bits from one counting
+        pass (syncs once per view)."""
+        caps, bits = [], []
         for cam in self.cams:
             _, _, _, counts = self.R.preprocess(self.p, cam)
-            caps.append(int(counts[:1].item()) & 0xFFFFFFFF)
+            cn = [int(x) & 0xFFFFFFFF for x in counts[:4].tolist()]
+            caps.append(cn[0])
+            bits.append(depth_range_bits(cn))
         self.capacity = [max(256, int(c * self.headroom)) for c in caps]
+        self.depth_bits = bits
         return list(caps)
 
     def _enqueue(self):
@@ -110,7 +114,8 @@ class BatchRenderer:
                 R = self.Rs[k % nst]
                 ctx = torch.cuda.stream(self.streams[k % nst]) if self.streams else contextlib.nullcontext()
                 with ctx:
-                    fr = R.forward(self.p, cam, capacity=self.capacity[v])
+                    fr = R.forward(self.p, cam, capacity=self.capacity[v],
+                                   depth_bits=self.depth_bits[v])
                     self.flags[v:v + 1].copy_(fr.flag)
                     g = l1_grad(fr.image, self.targets[v])
                     R.backward_2d(self.p, cam, fr, g, self.g2d[k])
@@ -159,6 +164,9 @@ class BatchRenderer:
         if bad:
             raise RuntimeError(f"instance capacity exceeded in views {bad}; plan() again "
                                f"with more headroom")
+        bad = torch.nonzero(self.flags & 2).flatten().tolist()
+        if bad:
+            raise RuntimeError(f"depth key range wider than planned in views {bad}; plan() again")
 
 
 def plain_views(params: GaussianParams, cams, targets, settings=None, renderer=None):
@@ -248,10 +256,10 @@ def autotune_view(params: GaussianParams, cam, backward=False, target=None, reps
         R = Renderer(dict(base, **over))
         fr = R.forward(params, cam, mesh=mesh)
         torch.cuda.synchronize()
-        cap, m = fr.capacity, fr.mesh
+        cap, m, db = fr.capacity, fr.mesh, fr.depth_bits
 
         def frame():
-            f = R.forward(params, cam, capacity=cap, mesh=m)
+            f = R.forward(params, cam, capacity=cap, mesh=m, depth_bits=db)
             if backward:
                 R.backward(params, cam, f, l1_grad(f.image, target))
         frame()

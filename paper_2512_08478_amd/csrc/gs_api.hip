@@ -56,6 +56,7 @@ int32_t check_settings(const gs_settings* s) {
   if (s->radix_bits < 6 || s->radix_bits > 8) return GS_ERR_UNSUPPORTED;
   if (s->sort_mode != 0 && s->sort_mode != 1) return GS_ERR_UNSUPPORTED;
   if (s->raster_order != 0 && s->raster_order != 1) return GS_ERR_UNSUPPORTED;
+  if (s->depth_bits < 0 || s->depth_bits > 32) return GS_ERR_INVALID_ARGUMENT;
   if (!(s->eps2d >= 0.f) || !std::isfinite(s->eps2d)) return GS_ERR_INVALID_ARGUMENT;
   if (!(s->alpha_min > 0.f) || !(s->alpha_max > s->alpha_min) || !(s->alpha_max < 1.f))
     return GS_ERR_INVALID_ARGUMENT;
@@ -258,6 +259,7 @@ void gs_default_settings(gs_settings* s) {
   s->radix_bits = 8;
   s->sort_mode = 0;
   s->raster_order = 1;
+  s->depth_bits = 0;
 }
 
 int32_t gs_sort_key_bits(const gs_camera* cam, const gs_settings* set) {
@@ -308,7 +310,7 @@ int32_t gs_preprocess_assets(int32_t n_assets, const gs_asset* assets, int64_t n
   const gs::SetK sk = make_setk(cam, set);
   const int K3 = (sh_degree + 1) * (sh_degree + 1) * 3;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint2* partial = static_cast<uint2*>(workspace);
+  uint4* partial = static_cast<uint4*>(workspace);
   int blocks = 0;
   hipError_t e = hipSuccess;
   for (int a = 0; a < n_assets && e == hipSuccess; ++a) {
@@ -397,7 +399,7 @@ int32_t gs_preprocess_packed(int32_t n_assets, const gs_asset* assets, int64_t n
   const gs::SetK sk = make_setk(cam, set);
   const int S = gs::packed_sh_stride(sh_degree);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint2* partial = static_cast<uint2*>(workspace);
+  uint4* partial = static_cast<uint4*>(workspace);
   int blocks = 0;
   hipError_t e = hipSuccess;
   for (int a = 0; a < n_assets && e == hipSuccess; ++a) {
@@ -435,7 +437,22 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   const int bits = set->radix_bits, mode = set->sort_mode;
   const bool heavy_first = set->raster_order == 1;
   const int tile_bits = key_bits_of(cam, set) - 32;
-  const int pd = (32 + bits - 1) / bits;
+  // depth passes: all 32 bits in radix_bits-wide passes, or (depth_bits > 0)
+  // depth_bits bits of the keys relative to the smallest visible key, in
+  // balanced passes of at most 9 bits (mode 0) or radix_bits (mode 1)
+  const int db = set->depth_bits;
+  int widths[gs::kMaxPassTotal] = {};
+  int pd;
+  if (db > 0 && mode == 0) {
+    pd = (db + 8) / 9;
+    for (int p = 0; p < pd; ++p) {
+      const int w = db / pd + (p < db % pd ? 1 : 0);
+      widths[p] = w < 6 ? 6 : w;
+    }
+  } else {
+    pd = ((db > 0 ? db : 32) + bits - 1) / bits;
+    for (int p = 0; p < pd; ++p) widths[p] = bits;
+  }
   const int pt = tile_bits > 0 ? (tile_bits + bits - 1) / bits : 1;
   const int tiles_x = tiles_x_of(cam, set), tiles = tiles_x * tiles_y_of(cam, set);
   char* ws = static_cast<char*>(workspace);
@@ -444,7 +461,7 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   uint32_t* count = U(L.count);
   gs::trace_mark(st, "sort_init");
   hipError_t e = gs::launch_sort_init(L, ws, mode, tile_ranges, tiles, status_flag, counts,
-                                      capacity, st, heavy_first ? U(L.tcls) : nullptr);
+                                      capacity, st, heavy_first ? U(L.tcls) : nullptr, db);
   if (e != hipSuccess) return hip_fail(e);
   if (n == 0 || capacity == 0) {
     if (heavy_first) {
@@ -469,7 +486,11 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   d.k_out = U(L.dk[0]); d.v_out = U(L.dv[0]);
   d.table = U(L.table); d.totals = U(L.totals);
   d.hist = U(L.hist); d.tickets = U(L.tickets); d.lookback = U(L.lookback); d.lb_parts = L.parts;
-  e = gs::launch_radix_sort<uint32_t>(d, bits, pd, 0, false, "depth_pass", st);
+  d.kbase = db > 0 ? counts + 2 : nullptr;
+  if (mode == 0)
+    e = gs::launch_radix_sort_widths(d, widths, pd, false, "depth_pass", st);
+  else
+    e = gs::launch_radix_sort<uint32_t>(d, bits, pd, 0, false, "depth_pass", st);
   if (e != hipSuccess) return hip_fail(e);
   // instances of the visible Gaussians in depth order (their tile rects are
   // gathered into depth order first), then the tile digits
@@ -480,6 +501,7 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   t.count = count;
   t.drop_first = 0;
   t.count_rest = nullptr;
+  t.kbase = nullptr;
   t.k_alt = U(L.tk[1]); t.v_alt = U(L.tv[1]);
   t.k_out = U(L.tkf); t.v_out = values;
   t.hist = U(L.hist) + pd * 256;

@@ -78,6 +78,7 @@ struct RadixArgs {
   const uint32_t* count;    // device n (NULL: n = n_grid)
   int drop_first;           // the first pass drops all-ones keys ...
   const uint32_t* count_rest;  // ... and the later passes sort *count_rest pairs
+  const uint32_t* kbase;    // the first pass orders and writes key - *kbase (NULL: key)
   const KeyT* kin;          // input keys (not modified)
   const uint32_t* vin;      // input values (NULL: value = position)
   KeyT* k_alt;              // ping-pong buffers
@@ -96,13 +97,13 @@ struct RadixArgs {
 constexpr int kMaxAssets = 64;       // assets per preprocess / backward call
 size_t preprocess_ws_bytes(int64_t n);
 int preprocess_blocks(int64_t n);
-// Projection of n Gaussians; per-block (instances, visible) partial sums go
-// to partial[0 .. preprocess_blocks(n)).
+// Projection of n Gaussians; per-block (instances, visible, smallest and
+// largest visible depth key) partials go to partial[0 .. preprocess_blocks(n)).
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
                              gs_splat* splats, uint32_t* depth_keys, uint32_t* tile_rects,
-                             uint2* partial, hipStream_t st);
+                             uint4* partial, hipStream_t st);
 // FP16 pre-pack (binary16 posop n*4, cov n*6, sh16 n*packed_sh_stride) and
 // the projection that reads it; same outputs as launch_preprocess.
 int packed_sh_stride(int degree);
@@ -118,13 +119,19 @@ hipError_t launch_lbs(int n, const uint16_t* canon_posop, const uint16_t* canon_
 hipError_t launch_preprocess_packed(int n, const uint16_t* posop, const uint16_t* cov,
                                     const uint16_t* sh16, int degree, const CamK& cam,
                                     const SetK& set, gs_splat* splats, uint32_t* depth_keys,
-                                    uint32_t* tile_rects, uint2* partial, hipStream_t st);
-// counts[0] = sum of partial[].x (instances), counts[1] = sum of partial[].y (visible)
-hipError_t launch_count_finalize(const uint2* partial, int blocks, uint32_t* counts,
+                                    uint32_t* tile_rects, uint4* partial, hipStream_t st);
+// counts[0] = sum of partial[].x (instances), counts[1] = sum of partial[].y
+// (visible), counts[2] = min of partial[].z, counts[3] = max of partial[].w
+// (the visible depth key range)
+hipError_t launch_count_finalize(const uint4* partial, int blocks, uint32_t* counts,
                                  hipStream_t st);
+// total_src (device counts of gs_preprocess, or NULL: host_total) gives the
+// instance count; with depth_bits in 1..31 bit 1 of status_flag reports a
+// visible depth key range that does not fit in depth_bits.
 hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
                             int tiles, uint32_t* status_flag, const uint32_t* total_src,
-                            int64_t capacity, hipStream_t st, uint32_t* cls_count = nullptr);
+                            int64_t capacity, hipStream_t st, uint32_t* cls_count = nullptr,
+                            int depth_bits = 0);
 // Passes first_pass .. passes-1 (digit p at shift p * bits); the pass that
 // would have come before first_pass has left its output in kin/vin.
 template <typename KeyT>
@@ -138,6 +145,10 @@ hipError_t launch_keygen(int64_t n, const uint32_t* sorted_idx, const uint32_t* 
                          const uint2* rects, uint2* sorted_rects, int tiles_x,
                          const uint32_t* inst_count, uint32_t* kg_counts, uint32_t* kg_total,
                          uint32_t* tkeys, uint32_t* tvals, hipStream_t st);
+// A reduce-then-scan sort (mode 0) of u32 keys whose pass p takes widths[p]
+// (6..9) bits, the shifts adding up from bit 0.
+hipError_t launch_radix_sort_widths(const RadixArgs<uint32_t>& a, const int* widths, int passes,
+                                    bool last_keys, const char* label, hipStream_t st);
 // Key generation fused with the first tile-digit pass (reduce-then-scan
 // mode): the first-digit histogram of each slice (with the rect gather),
 // its column scan into table/totals, and the instances written in the

@@ -117,24 +117,35 @@ __device__ __forceinline__ void place_mean(float p0, float p1, float p2, const C
 
 // Each workgroup's (instances, visible) totals into its slot of `partial`
 // (summed later by k_count_finalize); tiles = this thread's tile count.
-__device__ __forceinline__ void block_counts(uint32_t tiles, uint2* __restrict__ partial) {
-  __shared__ uint32_t s_vis[kBlock / 64], s_til[kBlock / 64];
+__device__ __forceinline__ void block_counts(uint32_t tiles, uint32_t dkey, uint4* __restrict__ partial) {
+  __shared__ uint32_t s_vis[kBlock / 64], s_til[kBlock / 64], s_min[kBlock / 64], s_max[kBlock / 64];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const uint32_t wv = (uint32_t)__builtin_popcountll(ballot(tiles > 0));
   const uint32_t wt = wave_sum_u32(tiles);
+  // depth key range of the visible Gaussians (culled keys are all ones)
+  uint32_t kmin = dkey, kmax = tiles > 0 ? dkey : 0u;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    kmin = min(kmin, shfl_u32(kmin, lane ^ d));
+    kmax = max(kmax, shfl_u32(kmax, lane ^ d));
+  }
   if (lane == 0) {
     s_vis[wave] = wv;
     s_til[wave] = wt;
+    s_min[wave] = kmin;
+    s_max[wave] = kmax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t bv = 0, bt = 0;
+    uint32_t bv = 0, bt = 0, bmin = 0xFFFFFFFFu, bmax = 0u;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) {
       bv += s_vis[w];
       bt += s_til[w];
+      bmin = min(bmin, s_min[w]);
+      bmax = max(bmax, s_max[w]);
     }
-    partial[blockIdx.x] = make_uint2(bt, bv);
+    partial[blockIdx.x] = make_uint4(bt, bv, bmin, bmax);
   }
 }
 

@@ -153,10 +153,10 @@ template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_preprocess_packed(
     int n, const uint2* __restrict__ posop, const uint32_t* __restrict__ cov,
     const uint2* __restrict__ sh16, CamK cam, SetK set, gs_splat* __restrict__ splats,
-    uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint2* __restrict__ partial) {
+    uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint4* __restrict__ partial) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  uint32_t tiles = 0;
+  uint32_t tiles = 0, dkey = 0xFFFFFFFFu;
   if (i < n) {
     const uint2 po = posop[i];
     const uint32_t c0 = cov[3 * i], c1 = cov[3 * i + 1], c2 = cov[3 * i + 2];
@@ -217,14 +217,15 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_packed(
     r2.y = tz;
     r2.z = __uint_as_float(rect_lo);
     r2.w = __uint_as_float(rect_hi);
-    depth_keys[i] = tiles ? __float_as_uint(tz) : 0xFFFFFFFFu;
+    dkey = tiles ? __float_as_uint(tz) : 0xFFFFFFFFu;
+    depth_keys[i] = dkey;
     rects[i] = trect;
     float4* dst = reinterpret_cast<float4*>(splats + i);
     dst[0] = r0;
     dst[1] = r1;
     dst[2] = r2;
   }
-  block_counts(tiles, partial);
+  block_counts(tiles, dkey, partial);
 }
 
 // Linear blend skinning of pre-packed canonical Gaussians (the avatar
@@ -359,7 +360,7 @@ hipError_t launch_lbs(int n, const uint16_t* canon_posop, const uint16_t* canon_
 hipError_t launch_preprocess_packed(int n, const uint16_t* posop, const uint16_t* cov,
                                     const uint16_t* sh16, int degree, const CamK& cam,
                                     const SetK& set, gs_splat* splats, uint32_t* depth_keys,
-                                    uint32_t* tile_rects, uint2* partial, hipStream_t st) {
+                                    uint32_t* tile_rects, uint4* partial, hipStream_t st) {
   const int blocks = preprocess_blocks(n);
   if (n > 0) {
     trace_mark(st, "preprocess_packed");

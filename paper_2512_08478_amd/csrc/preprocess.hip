@@ -152,21 +152,22 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
     int n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float4* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, CamK cam, SetK set, gs_splat* __restrict__ splats,
-    uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint2* __restrict__ partial) {
+    uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint4* __restrict__ partial) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr bool STAGED = DEG == 1 || DEG == 3;
   constexpr int F4 = STAGED ? K * 3 / 4 : 1;  // float4 per SH row
   __shared__ float4 s_sh[STAGED ? kBlock / 64 : 1][kShRows * F4];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  uint32_t tiles = 0;
+  uint32_t tiles = 0, dkey = 0xFFFFFFFFu;
   float4 r0, r1, r2;
   uint2 trect;
   float dir[3] = {0.f, 0.f, 0.f};
   if (i < n) {
     tiles = project_one<DEG, STAGED>(i, means, log_scales, quats, logits, sh, cam, set, r0, r1,
                                      r2, trect, dir);
-    depth_keys[i] = tiles ? __float_as_uint(r2.y) : 0xFFFFFFFFu;
+    dkey = tiles ? __float_as_uint(r2.y) : 0xFFFFFFFFu;
+    depth_keys[i] = dkey;
     rects[i] = trect;
   }
   if constexpr (STAGED) {
@@ -212,47 +213,64 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
     dst[1] = r1;
     dst[2] = r2;
   }
-  block_counts(tiles, partial);
+  block_counts(tiles, dkey, partial);
 }
 
-// counts[0] = total instances, counts[1] = visible Gaussians.
-__global__ __launch_bounds__(kBlock) void k_count_finalize(const uint2* __restrict__ partial,
+// counts[0] = total instances, counts[1] = visible Gaussians, counts[2] and
+// counts[3] = the smallest and largest depth key of a visible Gaussian
+// (all ones and 0 when none is visible).
+__global__ __launch_bounds__(kBlock) void k_count_finalize(const uint4* __restrict__ partial,
                                                            int blocks, uint32_t* __restrict__ counts) {
-  __shared__ uint32_t s_a[kBlock / 64], s_b[kBlock / 64];
+  __shared__ uint32_t s_a[kBlock / 64], s_b[kBlock / 64], s_lo[kBlock / 64], s_hi[kBlock / 64];
   // 16 independent loads in flight per thread and step: one workgroup
   // reads tens of thousands of slots, so load latency, not bandwidth, rules
   constexpr int U = 16;
-  uint32_t a = 0, b = 0;
+  uint32_t a = 0, b = 0, lo = 0xFFFFFFFFu, hi = 0u;
   for (int base = 0; base < blocks; base += kBlock * U) {
-    uint2 v[U];
+    // branch-free loads (past the end: the last slot, ignored), so that
+    // all U are in flight together
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = partial[min(base + u * kBlock + (int)threadIdx.x, blocks - 1)];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int i = base + u * kBlock + (int)threadIdx.x;
-      v[u] = i < blocks ? partial[i] : make_uint2(0u, 0u);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      a += v[u].x;
-      b += v[u].y;
+      if (base + u * kBlock + (int)threadIdx.x < blocks) {
+        a += v[u].x;
+        b += v[u].y;
+        lo = min(lo, v[u].z);
+        hi = max(hi, v[u].w);
+      }
     }
   }
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
   a = wave_sum_u32(a);
   b = wave_sum_u32(b);
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    lo = min(lo, shfl_u32(lo, lane ^ d));
+    hi = max(hi, shfl_u32(hi, lane ^ d));
+  }
   if (lane == 0) {
     s_a[wave] = a;
     s_b[wave] = b;
+    s_lo[wave] = lo;
+    s_hi[wave] = hi;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t ta = 0, tb = 0;
+    uint32_t ta = 0, tb = 0, tlo = 0xFFFFFFFFu, thi = 0u;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) {
       ta += s_a[w];
       tb += s_b[w];
+      tlo = min(tlo, s_lo[w]);
+      thi = max(thi, s_hi[w]);
     }
     counts[0] = ta;
     counts[1] = tb;
+    counts[2] = tlo;
+    counts[3] = thi;
   }
 }
 
@@ -605,14 +623,14 @@ int preprocess_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 // one partial slot per block of every asset: at most blocks(n) + assets
 size_t preprocess_ws_bytes(int64_t n) {
-  return align_up((size_t)(preprocess_blocks(n) + kMaxAssets) * 8, 256);
+  return align_up((size_t)(preprocess_blocks(n) + kMaxAssets) * 16, 256);
 }
 
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
                              gs_splat* splats, uint32_t* depth_keys, uint32_t* tile_rects,
-                             uint2* partial, hipStream_t st) {
+                             uint4* partial, hipStream_t st) {
   const int blocks = preprocess_blocks(n);
   if (n > 0) {
     trace_mark(st, "preprocess");
@@ -629,7 +647,7 @@ hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
   return hipGetLastError();
 }
 
-hipError_t launch_count_finalize(const uint2* partial, int blocks, uint32_t* counts,
+hipError_t launch_count_finalize(const uint4* partial, int blocks, uint32_t* counts,
                                  hipStream_t st) {
   trace_mark(st, "count_finalize");
   hipLaunchKernelGGL(k_count_finalize, dim3(1), dim3(kBlock), 0, st, partial, blocks, counts);

@@ -35,6 +35,7 @@ namespace gs {
 namespace {
 
 constexpr int kHistMax = 2048;     // LDS histogram bins (passes x 2^bits)
+constexpr int kMaxDigits = 512;    // digits of the widest (9-bit) pass
 constexpr int kLbWindow = 8;       // look-back status words in flight per digit
 constexpr int kKgItems = 4;        // sorted Gaussians per thread in the keygen
 constexpr int kKgPart = kBlock * kKgItems;
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_init(uint32_t* hist, int hist_l
                                                       uint32_t* ranges, int ranges_len,
                                                       uint32_t* count, const uint32_t* total_src,
                                                       uint32_t host_total, int64_t capacity,
-                                                      uint32_t* status_flag, uint32_t* cls_count) {
+                                                      uint32_t* status_flag, uint32_t* cls_count,
+                                                      int depth_bits) {
   const int stride = gridDim.x * kBlock;
   const int i0 = blockIdx.x * kBlock + threadIdx.x;
   if (cls_count && i0 < kTileClasses) cls_count[i0] = 0;
@@ -58,7 +60,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_init(uint32_t* hist, int hist_l
     const uint32_t tot = total_src ? *total_src : host_total;
     const bool over = (int64_t)tot > capacity;
     *count = over ? (uint32_t)capacity : tot;
-    if (status_flag) *status_flag = over ? 1u : 0u;
+    // total_src = counts: counts[1] visible, counts[2..3] their depth key range
+    bool range_over = false;
+    if (total_src && depth_bits > 0 && depth_bits < 32 && total_src[1] > 0)
+      range_over = ((total_src[3] - total_src[2]) >> depth_bits) != 0u;
+    if (status_flag) *status_flag = (over ? 1u : 0u) | (range_over ? 2u : 0u);
   }
 }
 
@@ -120,8 +126,9 @@ __device__ __forceinline__ bool key_kept(KeyT k, uint32_t idx, uint32_t n, int d
 template <typename KeyT, int BITS, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ kin,
                                                        const uint32_t* __restrict__ count,
-                                                       int64_t n_host, int drop, int shift,
-                                                       uint32_t* __restrict__ table) {
+                                                       int64_t n_host, int drop,
+                                                       const uint32_t* __restrict__ kbase,
+                                                       int shift, uint32_t* __restrict__ table) {
   constexpr int NB = 1 << BITS;
   constexpr int NS = kBlock / 16;  // sub-histograms
   constexpr int PART = kBlock * ITEMS;
@@ -137,12 +144,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ 
     const uint32_t idx = base + i * kBlock + t;
     k[i] = idx < n ? kin[idx] : KeyT(0);
   }
+  const KeyT kb = kbase ? (KeyT)*kbase : KeyT(0);
   __syncthreads();
   uint32_t* h = s_h[t >> 4];
   uint32_t* h0 = s_h[(t >> 6) * 4];  // the wave's first sub-histogram
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t d = digit_of<KeyT, BITS>(k[i], shift);
+    const uint32_t d = digit_of<KeyT, BITS>(k[i] - kb, shift);
     uint64_t left = ballot(key_kept(k[i], base + i * kBlock + t, n, drop));
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -276,14 +284,16 @@ __global__ __launch_bounds__(kBlock) void k_col_scan(uint32_t* __restrict__ tabl
 template <typename KeyT, int BITS>
 __global__ __launch_bounds__(kBlock) void k_histogram(const KeyT* __restrict__ keys,
                                                       const uint32_t* __restrict__ count,
-                                                      int64_t n_host, int drop, int passes,
-                                                      uint32_t* __restrict__ hist) {
+                                                      int64_t n_host, int drop,
+                                                      const uint32_t* __restrict__ kbase,
+                                                      int passes, uint32_t* __restrict__ hist) {
   constexpr int NB = 1 << BITS;
   __shared__ uint32_t s_hist[kHistMax];
   const int t = threadIdx.x;
   for (int b = t; b < passes * NB; b += kBlock) s_hist[b] = 0;
   __syncthreads();
   const uint32_t n = read_n(count, n_host);
+  const KeyT kb = kbase ? (KeyT)*kbase : KeyT(0);
   for (uint32_t base = blockIdx.x * kSortPart; base < n; base += gridDim.x * kSortPart) {
     KeyT k[kSortItems];
 #pragma unroll
@@ -295,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_histogram(const KeyT* __restrict__ k
     for (int i = 0; i < kSortItems; ++i) {
       const bool valid = key_kept(k[i], base + i * kBlock + t, n, drop);
       for (int p = 0; p < passes; ++p)
-        wave_hist_add<BITS>(s_hist + p * NB, digit_of<KeyT, BITS>(k[i], p * BITS), valid);
+        wave_hist_add<BITS>(s_hist + p * NB, digit_of<KeyT, BITS>(k[i] - kb, p * BITS), valid);
     }
   }
   __syncthreads();
@@ -330,7 +340,8 @@ template <typename KeyT, int BITS, int ITEMS, bool WRITE_KEYS, bool LOOKBACK>
 __global__ __launch_bounds__(kBlock) void k_radix_pass(
     const KeyT* __restrict__ kin, const uint32_t* __restrict__ vin, KeyT* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ count, int64_t n_host, int drop,
-    int shift, const uint32_t* __restrict__ table, const uint32_t* __restrict__ totals,
+    const uint32_t* __restrict__ kbase, int shift, const uint32_t* __restrict__ table,
+    const uint32_t* __restrict__ totals,
     uint32_t* __restrict__ ticket, uint32_t* __restrict__ lb, uint32_t* __restrict__ lb_next) {
   constexpr int NB = 1 << BITS;
   constexpr int NW = kBlock / 64;
@@ -364,6 +375,16 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
     for (int b = t; b < NW * NB; b += kBlock) (&s_whist[0][0])[b] = 0;
   }
   const uint32_t base = part * PART;
+  // this thread's digits' global totals and (reduce-then-scan) partition
+  // prefixes, loaded now so that they arrive during the ranking
+  constexpr int DPT = NB > kBlock ? NB / kBlock : 1;
+  uint32_t pf_tot[DPT], pf_tab[DPT];
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int d = t * DPT + k;
+    pf_tot[k] = d < NB ? totals[d] : 0u;
+    pf_tab[k] = (!LOOKBACK && d < NB) ? table[(size_t)part * NB + d] : 0u;
+  }
 
   // warp-striped load: wave w owns keys [w*64*ITEMS, (w+1)*64*ITEMS); the
   // values are loaded with the keys so both round trips overlap
@@ -381,12 +402,15 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
     v[i] = idx < n ? (vin ? vin[idx] : idx) : 0u;
   }
   if (!LOOKBACK) __syncthreads();  // s_whist zeroed
-  // rank within the wave: kept keys in index order, equal digits by lane
+  // rank within the wave: kept keys in index order, equal digits by lane;
+  // keys are taken relative to *kbase (the pass writes them so)
+  const KeyT kb = kbase ? (KeyT)*kbase : KeyT(0);
   const uint64_t lt = lanemask_lt();
   uint32_t kept = 0;
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const bool keep = key_kept(k[i], wbase + i * 64, n, drop);
+    k[i] -= kb;
     kept |= (uint32_t)keep << i;
     const uint32_t d = digit_of<KeyT, BITS>(k[i], shift);
     const uint64_t peers = match_digit<BITS>(d, ballot(keep));
@@ -397,61 +421,80 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(
   __syncthreads();
 
   // per digit: offsets of each wave, partition total, global digit start
-  uint32_t tot = 0, gcount = 0;
-  if (t < NB) {
-    uint32_t run = 0;
+  // (DPT consecutive digits per thread when there are more digits than
+  // threads)
+  static_assert(!LOOKBACK || NB <= kBlock, "look-back passes take at most 8-bit digits");
+  uint32_t tot[DPT], gcount[DPT], tsum = 0, gsum = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const uint32_t x = s_whist[w][t];
-      s_whist[w][t] = run;
-      run += x;
+  for (int k = 0; k < DPT; ++k) {
+    const int d = t * DPT + k;
+    tot[k] = 0;
+    gcount[k] = 0;
+    if (d < NB) {
+      uint32_t run = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t x = s_whist[w][d];
+        s_whist[w][d] = run;
+        run += x;
+      }
+      tot[k] = run;
+      gcount[k] = pf_tot[k];
+      if (LOOKBACK) st_agent(&lb[part * NB + d], (part == 0 ? kLbFlagInc : kLbFlagAgg) | run);
     }
-    tot = run;
-    gcount = totals[t];
-    if (LOOKBACK) st_agent(&lb[part * NB + t], (part == 0 ? kLbFlagInc : kLbFlagAgg) | tot);
+    tsum += tot[k];
+    gsum += gcount[k];
   }
-  const uint32_t inc_tot = wave_incl_scan(tot);
-  const uint32_t inc_g = wave_incl_scan(gcount);
+  const uint32_t inc_tot = wave_incl_scan(tsum);
+  const uint32_t inc_g = wave_incl_scan(gsum);
   if (lane == 63) {
     s_scan[0][wave] = inc_tot;
     s_scan[1][wave] = inc_g;
   }
   __syncthreads();
-  if (t < NB) {
+  {
     uint32_t off_tot = 0, off_g = 0;
     for (int w = 0; w < wave; ++w) {
       off_tot += s_scan[0][w];
       off_g += s_scan[1][w];
     }
-    const uint32_t local = off_tot + inc_tot - tot;
-    const uint32_t gstart = off_g + inc_g - gcount;
-    uint32_t prefix = 0;
-    if (!LOOKBACK) {
-      prefix = table[(size_t)part * NB + t];
-    } else if (part > 0) {
-      int j = (int)part - 1;
-      while (true) {
-        uint32_t s[kLbWindow];
+    uint32_t local = off_tot + inc_tot - tsum;
+    uint32_t gstart = off_g + inc_g - gsum;
 #pragma unroll
-        for (int w = 0; w < kLbWindow; ++w)
-          s[w] = (j - w >= 0) ? ld_agent(&lb[(j - w) * NB + t]) : kLbFlagInc;
-        int used = 0;
-        bool done = false;
+    for (int k = 0; k < DPT; ++k) {
+      const int d = t * DPT + k;
+      if (d < NB) {
+        uint32_t prefix = 0;
+        if (!LOOKBACK) {
+          prefix = pf_tab[k];
+        } else if (part > 0) {
+          int j = (int)part - 1;
+          while (true) {
+            uint32_t sw[kLbWindow];
 #pragma unroll
-        for (int w = 0; w < kLbWindow; ++w) {
-          if (done || used < w) continue;  // stop at the first unpublished word
-          if ((s[w] & (kLbFlagAgg | kLbFlagInc)) == 0) continue;
-          prefix += s[w] & kLbValue;
-          used = w + 1;
-          if (s[w] & kLbFlagInc) done = true;
+            for (int w = 0; w < kLbWindow; ++w)
+              sw[w] = (j - w >= 0) ? ld_agent(&lb[(j - w) * NB + d]) : kLbFlagInc;
+            int used = 0;
+            bool done = false;
+#pragma unroll
+            for (int w = 0; w < kLbWindow; ++w) {
+              if (done || used < w) continue;  // stop at the first unpublished word
+              if ((sw[w] & (kLbFlagAgg | kLbFlagInc)) == 0) continue;
+              prefix += sw[w] & kLbValue;
+              used = w + 1;
+              if (sw[w] & kLbFlagInc) done = true;
+            }
+            if (done) break;
+            j -= used;
+          }
+          st_agent(&lb[part * NB + d], kLbFlagInc | (prefix + tot[k]));
         }
-        if (done) break;
-        j -= used;
+        s_local[d] = local;
+        s_gbase[d] = gstart + prefix - local;
       }
-      st_agent(&lb[part * NB + t], kLbFlagInc | (prefix + tot));
+      local += tot[k];
+      gstart += gcount[k];
     }
-    s_local[t] = local;
-    s_gbase[t] = gstart + prefix - local;
   }
   uint32_t nkept = 0;  // kept keys of the partition
 #pragma unroll
@@ -991,55 +1034,69 @@ inline int rs_items(int64_t n) {
 // Launch of one downsweep kernel with or without key stores.
 template <typename KeyT, int BITS, int ITEMS, bool LOOKBACK>
 void launch_pass(int grid, bool write_keys, const KeyT* ki, const uint32_t* vi, KeyT* kd,
-                 uint32_t* vd, const uint32_t* cnt, int64_t n_grid, int drop, int shift,
-                 const uint32_t* table, const uint32_t* totals, uint32_t* ticket, uint32_t* lb,
-                 uint32_t* lb_next, hipStream_t st) {
+                 uint32_t* vd, const uint32_t* cnt, int64_t n_grid, int drop,
+                 const uint32_t* kbase, int shift, const uint32_t* table, const uint32_t* totals,
+                 uint32_t* ticket, uint32_t* lb, uint32_t* lb_next, hipStream_t st) {
   if (write_keys)
     hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, true, LOOKBACK>), dim3(grid),
-                       dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, shift, table,
-                       totals, ticket, lb, lb_next);
+                       dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, kbase, shift,
+                       table, totals, ticket, lb, lb_next);
   else
     hipLaunchKernelGGL((k_radix_pass<KeyT, BITS, ITEMS, false, LOOKBACK>), dim3(grid),
-                       dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, shift, table,
-                       totals, ticket, lb, lb_next);
+                       dim3(kBlock), 0, st, ki, vi, kd, vd, cnt, n_grid, drop, kbase, shift,
+                       table, totals, ticket, lb, lb_next);
 }
 
 template <typename KeyT, int BITS, int ITEMS>
-void rs_pass(const RadixArgs<KeyT>& a, int p, const uint32_t* cnt, int drop, const KeyT* ki,
-             const uint32_t* vi, KeyT* kd, uint32_t* vd, bool write_keys, hipStream_t st) {
+void rs_pass(const RadixArgs<KeyT>& a, int shift, const uint32_t* cnt, int drop,
+             const uint32_t* kbase, const KeyT* ki, const uint32_t* vi, KeyT* kd, uint32_t* vd,
+             bool write_keys, hipStream_t st) {
   constexpr int PART = kBlock * ITEMS;
   constexpr int NB = 1 << BITS;
   const int parts = (int)((a.n_grid + PART - 1) / PART);
-  const int shift = p * BITS;
   hipLaunchKernelGGL((k_rs_upsweep<KeyT, BITS, ITEMS>), dim3(parts), dim3(kBlock), 0, st, ki, cnt,
-                     a.n_grid, drop, shift, a.table);
+                     a.n_grid, drop, kbase, shift, a.table);
   hipLaunchKernelGGL((k_col_scan<NB, PART>), dim3(NB / 4), dim3(kBlock), 0, st, a.table, cnt,
                      a.n_grid, a.totals);
   launch_pass<KeyT, BITS, ITEMS, false>(parts, write_keys, ki, vi, kd, vd, cnt, a.n_grid, drop,
-                                        shift, a.table, a.totals, nullptr, nullptr, nullptr, st);
+                                        kbase, shift, a.table, a.totals, nullptr, nullptr, nullptr,
+                                        st);
+}
+
+// Pass p of a sort whose first pass may drop all-ones keys and take the
+// keys relative to *kbase (later passes see the relative keys it wrote).
+template <typename KeyT, int BITS>
+void rs_pass_items(const RadixArgs<KeyT>& a, int p, int shift, const KeyT* ki, const uint32_t* vi,
+                   KeyT* kd, uint32_t* vd, bool write_keys, hipStream_t st) {
+  const bool first = p == 0;
+  const int drop = first && a.drop_first ? 1 : 0;
+  const uint32_t* kbase = first ? a.kbase : nullptr;
+  const uint32_t* cnt = (!first && a.drop_first) ? a.count_rest : a.count;
+  switch (rs_items(a.n_grid)) {
+    case 16: rs_pass<KeyT, BITS, 16>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, st); break;
+    case 8: rs_pass<KeyT, BITS, 8>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, st); break;
+    default: rs_pass<KeyT, BITS, 4>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, st); break;
+  }
 }
 
 template <typename KeyT, int BITS>
 void pass_t(const RadixArgs<KeyT>& a, int p, int q, const KeyT* ki, const uint32_t* vi, KeyT* kd,
             uint32_t* vd, bool write_keys, hipStream_t st) {
   const int shift = p * BITS;
-  const bool first = p == 0;
-  const int drop = first && a.drop_first ? 1 : 0;
-  const uint32_t* cnt = (!first && a.drop_first) ? a.count_rest : a.count;
   if (a.mode == 1) {
+    const bool first = p == 0;
+    const int drop = first && a.drop_first ? 1 : 0;
+    const uint32_t* kbase = first ? a.kbase : nullptr;
+    const uint32_t* cnt = (!first && a.drop_first) ? a.count_rest : a.count;
     const int parts = (int)((a.n_grid + kSortPart - 1) / kSortPart);
     uint32_t* lb = a.lookback + (size_t)(q & 1) * a.lb_parts * 256;
     uint32_t* lb_next = a.lookback + (size_t)((q + 1) & 1) * a.lb_parts * 256;
     const uint32_t* h = a.hist + p * 256;
     launch_pass<KeyT, BITS, kSortItems, true>(parts, write_keys, ki, vi, kd, vd, cnt, a.n_grid,
-                                              drop, shift, nullptr, h, a.tickets + q, lb, lb_next,
-                                              st);
+                                              drop, kbase, shift, nullptr, h, a.tickets + q, lb,
+                                              lb_next, st);
   } else {
-    switch (rs_items(a.n_grid)) {
-      case 16: rs_pass<KeyT, BITS, 16>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, st); break;
-      case 8: rs_pass<KeyT, BITS, 8>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, st); break;
-      default: rs_pass<KeyT, BITS, 4>(a, p, cnt, drop, ki, vi, kd, vd, write_keys, st); break;
-    }
+    rs_pass_items<KeyT, BITS>(a, p, shift, ki, vi, kd, vd, write_keys, st);
   }
 }
 
@@ -1047,7 +1104,7 @@ template <typename KeyT, int BITS>
 void hist_t(const RadixArgs<KeyT>& a, int passes, hipStream_t st) {
   const int parts = (int)((a.n_grid + kSortPart - 1) / kSortPart);
   hipLaunchKernelGGL((k_histogram<KeyT, BITS>), dim3(parts < 512 ? parts : 512), dim3(kBlock), 0,
-                     st, a.kin, a.count, a.n_grid, a.drop_first, passes, a.hist);
+                     st, a.kin, a.count, a.n_grid, a.drop_first, a.kbase, passes, a.hist);
 }
 
 }  // namespace
@@ -1074,8 +1131,8 @@ SortLayout sort_layout(int64_t n, int64_t capacity, int tiles) {
   L.hist = take((size_t)kMaxPassTotal * 256 * 4);
   L.tickets = take((size_t)kMaxPassTotal * 4);
   L.lookback = take((size_t)2 * L.parts * 256 * 4);
-  L.table = take((size_t)L.rs_parts * 256 * 4);
-  L.totals = take(256 * 4);
+  L.table = take((size_t)L.rs_parts * kMaxDigits * 4);
+  L.totals = take(kMaxDigits * 4);
   L.kg_counts = take((size_t)L.kg_parts * 4);
   L.count = take(4);
   L.tcls = take((size_t)kTileClasses * 4);
@@ -1102,8 +1159,8 @@ SortLayout pairs_layout(int64_t n) {
   L.hist = take((size_t)kMaxPassTotal * 256 * 4);
   L.tickets = take((size_t)kMaxPassTotal * 4);
   L.lookback = take((size_t)2 * L.parts * 256 * 4);
-  L.table = take((size_t)L.rs_parts * 256 * 4);
-  L.totals = take(256 * 4);
+  L.table = take((size_t)L.rs_parts * kMaxDigits * 4);
+  L.totals = take(kMaxDigits * 4);
   L.kg_counts = 0;
   L.count = take(4);
   L.bytes = o;
@@ -1112,7 +1169,8 @@ SortLayout pairs_layout(int64_t n) {
 
 hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
                             int tiles, uint32_t* status_flag, const uint32_t* total_src,
-                            int64_t capacity, hipStream_t st, uint32_t* cls_count) {
+                            int64_t capacity, hipStream_t st, uint32_t* cls_count,
+                            int depth_bits) {
   const int lb_len = mode == 1 ? 2 * L.parts * 256 : 0;
   const int ranges_len = tile_ranges ? 2 * tiles : 0;
   const int64_t most = lb_len > ranges_len ? lb_len : ranges_len;
@@ -1121,7 +1179,7 @@ hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* t
                      reinterpret_cast<uint32_t*>(ws + L.tickets), kMaxPassTotal,
                      reinterpret_cast<uint32_t*>(ws + L.lookback), lb_len, tile_ranges, ranges_len,
                      reinterpret_cast<uint32_t*>(ws + L.count), total_src, (uint32_t)capacity,
-                     capacity, status_flag, cls_count);
+                     capacity, status_flag, cls_count, depth_bits);
   return hipGetLastError();
 }
 
@@ -1157,6 +1215,33 @@ hipError_t launch_radix_sort(const RadixArgs<KeyT>& a, int bits, int passes, int
   }
   return hipGetLastError();
 }
+hipError_t launch_radix_sort_widths(const RadixArgs<uint32_t>& a, const int* widths, int passes,
+                                    bool last_keys, const char* label, hipStream_t st) {
+  if (a.n_grid == 0 || passes == 0) return hipSuccess;
+  if (a.mode != 0) return hipErrorInvalidValue;
+  const uint32_t* ki = a.kin;
+  const uint32_t* vi = a.vin;
+  int shift = 0;
+  for (int p = 0; p < passes; ++p) {
+    const bool to_out = ((passes - 1 - p) % 2) == 0;
+    uint32_t* kd = to_out ? a.k_out : a.k_alt;
+    uint32_t* vd = to_out ? a.v_out : a.v_alt;
+    const bool wk = (p + 1 < passes) || last_keys;
+    trace_mark(st, label);
+    switch (widths[p]) {
+      case 6: rs_pass_items<uint32_t, 6>(a, p, shift, ki, vi, kd, vd, wk, st); break;
+      case 7: rs_pass_items<uint32_t, 7>(a, p, shift, ki, vi, kd, vd, wk, st); break;
+      case 8: rs_pass_items<uint32_t, 8>(a, p, shift, ki, vi, kd, vd, wk, st); break;
+      case 9: rs_pass_items<uint32_t, 9>(a, p, shift, ki, vi, kd, vd, wk, st); break;
+      default: return hipErrorInvalidValue;
+    }
+    shift += widths[p];
+    ki = kd;
+    vi = vd;
+  }
+  return hipGetLastError();
+}
+
 template hipError_t launch_radix_sort<uint32_t>(const RadixArgs<uint32_t>&, int, int, int, bool,
                                                 const char*, hipStream_t, int);
 template hipError_t launch_radix_sort<uint64_t>(const RadixArgs<uint64_t>&, int, int, int, bool,

@@ -97,13 +97,14 @@ class Frame:
     splats: torch.Tensor     # (n*48,) uint8
     depth_keys: torch.Tensor  # (n,) int32 (u32): depth sort keys
     rects: torch.Tensor      # (2n,) int32 (u32 pairs): tile rect per Gaussian
-    counts: torch.Tensor     # (2,) int32 (u32), device: instances, visible
+    counts: torch.Tensor     # (4,) int32 (u32), device: instances, visible, depth key range
     keys: torch.Tensor       # (capacity,) int64 (u64) or None
     values: torch.Tensor     # (capacity,) int32 (u32)
     ranges: torch.Tensor     # (2*tiles,) int32 (u32)
-    flag: torch.Tensor       # (1,) int32: bit 0 = capacity exceeded
+    flag: torch.Tensor       # (1,) int32: bit 0 = capacity exceeded, bit 1 = depth range
     capacity: int
     mesh: object = None      # the mesh prepass composited with (see Renderer.forward)
+    depth_bits: int = 0      # depth key bits the sort ordered (0: all 32)
 
 
 def mesh_buffers(mesh, cam, device="cuda"):
@@ -123,11 +124,24 @@ def mesh_buffers(mesh, cam, device="cuda"):
     return out
 
 
+def depth_range_bits(counts, headroom_bits=0):
+    """Depth key bits the sort must order for gs_preprocess counts
+    (instances, visible, smallest and largest visible depth key): the bit
+    length of the key range (at least 1), plus `headroom_bits` for later
+    frames of a moving camera, at most 32; 0 (all bits) when nothing is
+    visible."""
+    if int(counts[1]) == 0:
+        return 0
+    r = (int(counts[3]) & 0xFFFFFFFF) - (int(counts[2]) & 0xFFFFFFFF)
+    return min(32, max(1, r.bit_length()) + int(headroom_bits))
+
+
 class Renderer:
     """Holds settings and reusable workspaces for one device."""
 
     def __init__(self, settings=None, device="cuda"):
         self.settings = L.default_settings(**(settings or {}))
+        self.last_depth_bits = self.settings.depth_bits
         self.device = torch.device(device)
         self._bufs = {}
         L.load()
@@ -191,7 +205,7 @@ class Renderer:
         splats = self._buf("splats", n * L.SPLAT_BYTES, reuse)[:n * L.SPLAT_BYTES]
         dkeys = self._buf("depth_keys", n * 4, reuse).view(torch.int32)[:n]
         rects = self._buf("rects", n * 8, reuse).view(torch.int32)[:2 * n]
-        counts = self._buf("counts", 8, reuse).view(torch.int32)[:2]
+        counts = self._buf("counts", 16, reuse).view(torch.int32)[:4]
         ws_bytes = lib.gs_workspace_size(L.GS_STAGE_PREPROCESS, n, 0, ctypes.byref(c), ctypes.byref(s))
         ws = self._buf("ws_pre", ws_bytes, reuse)
         if isinstance(p, PackedParams):
@@ -218,13 +232,23 @@ class Renderer:
         return splats, dkeys, rects, counts
 
     def sort(self, n, splats, dkeys, rects, counts, cam, capacity=None, reuse=True,
-             want_keys=False):
-        """capacity=None reads the instance count back (one sync)."""
+             want_keys=False, depth_bits=None):
+        """capacity=None reads the counts back (one sync): the instance
+        count sizes the buffers, and the visible depth key range sets the
+        depth bits to sort unless `depth_bits` is given (otherwise the
+        settings' depth_bits)."""
         lib = L.load()
-        c, s = L.make_camera(cam), self.settings
+        c = L.make_camera(cam)
         if capacity is None:
-            capacity = int(counts[:1].item()) & 0xFFFFFFFF
+            cn = [int(x) & 0xFFFFFFFF for x in counts[:4].tolist()]
+            capacity = cn[0]
+            if depth_bits is None:
+                depth_bits = depth_range_bits(cn)
         capacity = int(capacity)
+        s = self.settings
+        if depth_bits is not None and int(depth_bits) != s.depth_bits:
+            s = L.GsSettings.from_buffer_copy(s)
+            s.depth_bits = int(depth_bits)
         keys = self._buf("keys", capacity * 8, reuse).view(torch.int64)[:capacity] if want_keys else None
         values = self._buf("values", capacity * 4, reuse).view(torch.int32)[:capacity]
         # [start, end) per tile, then the compositing order of the tiles
@@ -239,6 +263,7 @@ class Renderer:
                          capacity, _p(keys), _p(values), _p(ranges), _p(flag), _p(ws), ws.numel(),
                          _stream())
         L.check(st, "gs_sort")
+        self.last_depth_bits = s.depth_bits
         return keys, values, ranges, flag, capacity
 
     def sort_pairs32(self, keys, values=None, key_bits=32, want_keys=False):
@@ -282,7 +307,8 @@ class Renderer:
             L.check(st, "gs_rasterize")
         return image, T, last
 
-    def forward(self, p, cam, capacity=None, reuse=True, want_keys=False, mesh=None) -> Frame:
+    def forward(self, p, cam, capacity=None, reuse=True, want_keys=False, mesh=None,
+                depth_bits=None) -> Frame:
         """One frame: preprocess, sort, composite (with a mesh prepass when
         `mesh` is given: {"depth": (H, W) float32 camera-space z, +inf where
         there is no mesh; "rgb": (H, W, 3) float32 or None}, device tensors,
@@ -291,10 +317,10 @@ class Renderer:
             mesh = mesh_buffers(mesh, cam, self.device)
         splats, dkeys, rects, counts = self.preprocess(p, cam, reuse)
         keys, values, ranges, flag, cap = self.sort(p.n, splats, dkeys, rects, counts, cam, capacity,
-                                                    reuse, want_keys)
+                                                    reuse, want_keys, depth_bits)
         image, T, last = self.rasterize(splats, values, ranges, cam, mesh=mesh)
         return Frame(image, T, last, splats, dkeys, rects, counts, keys, values, ranges, flag, cap,
-                     mesh)
+                     mesh, self.last_depth_bits)
 
     def backward(self, p: GaussianParams, cam, fr: Frame, dL_dimage, out=None, accumulate=False):
         if fr.mesh is not None:

@@ -46,6 +46,7 @@ def test_version_and_status_strings(lib):
 def test_default_settings(lib):
     s = L.default_settings()
     assert (s.tile_w, s.tile_h, s.radix_bits, s.sort_mode, s.raster_order) == (16, 16, 8, 0, 1)
+    assert s.depth_bits == 0
     assert s.eps2d == pytest.approx(0.3)
     assert s.alpha_min == pytest.approx(1 / 255)
     assert s.alpha_max == pytest.approx(0.99)
@@ -101,6 +102,8 @@ def test_preprocess_argument_validation(lib):
     assert pre(lib, ws_bytes=0) == L.GS_ERR_WORKSPACE
     assert pre(lib, st=L.default_settings(tile_w=12)) == L.GS_ERR_UNSUPPORTED
     assert pre(lib, st=L.default_settings(radix_bits=9)) == L.GS_ERR_UNSUPPORTED
+    assert pre(lib, st=L.default_settings(depth_bits=33)) == L.GS_ERR_INVALID_ARGUMENT
+    assert pre(lib, st=L.default_settings(depth_bits=-1)) == L.GS_ERR_INVALID_ARGUMENT
     assert pre(lib, st=L.default_settings(alpha_max=1.0)) == L.GS_ERR_INVALID_ARGUMENT
     assert pre(lib, st=L.default_settings(alpha_min=0.0)) == L.GS_ERR_INVALID_ARGUMENT
     assert pre(lib, st=L.default_settings(eps2d=-1.0)) == L.GS_ERR_INVALID_ARGUMENT

@@ -50,14 +50,18 @@ def test_multi_asset_records_equal_single_asset_records(R):
     rec = splats_np(splats, p.n)
     c_all = counts.cpu().numpy().view(np.uint32)
     tot = np.zeros(2, np.int64)
+    kmin, kmax = 0xFFFFFFFF, 0
     off = 0
     for a in assets:
         s1, _, _, c1 = R.preprocess(GaussianParams.from_scene(a), cam, reuse=False)
         r1 = splats_np(s1, a.n)
         assert r1.tobytes() == rec[off:off + a.n].tobytes()
-        tot += c1.cpu().numpy().view(np.uint32)
+        c1 = c1.cpu().numpy().view(np.uint32)
+        tot += c1[:2]
+        kmin, kmax = min(kmin, int(c1[2])), max(kmax, int(c1[3]))
         off += a.n
-    assert list(tot) == list(c_all)
+    assert list(tot) == list(c_all[:2])
+    assert (kmin, kmax) == (int(c_all[2]), int(c_all[3]))
     print(f"{len(assets)} assets, {p.n} Gaussians, instances {c_all[0]}, visible {c_all[1]}")
 
 

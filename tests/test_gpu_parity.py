@@ -44,6 +44,9 @@ def test_preprocess_tiny(R, orc):
     cnt = np.where(vis, (rec["tx1"].astype(np.int64) - rec["tx0"] + 1) * (rec["ty1"].astype(np.int64) - rec["ty0"] + 1), 0)
     c = u32(counts)
     assert int(c[0]) == cnt.sum() and int(c[1]) == vis.sum()
+    # the visible depth key range
+    vk = rec["depth"][vis].astype(np.float32).view(np.uint32)
+    assert int(c[2]) == int(vk.min()) and int(c[3]) == int(vk.max())
     # the compact tile rects match the records' pixel bboxes
     tr = u32(rects).reshape(-1, 2)[vis]
     np.testing.assert_array_equal(tr[:, 0] & 0xFFFF, rec["tx0"][vis])
@@ -257,6 +260,36 @@ def test_sort_keys_full_size(R, workload, shape, mode):
     np.testing.assert_array_equal(rng[nonempty, 1], ends[nonempty])
     assert np.all(rng[~nonempty, 0] == rng[~nonempty, 1])
     print(f"{workload}: {n} pairs, {int(nonempty.sum())} non-empty tiles")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sort_depth_bits(R, mode):
+    """The depth passes over the visible key range (depth_bits planned from
+    the counts) give the same sort as all 32 bits; a range wider than the
+    planned bits raises bit 1 of the status flag."""
+    print_case(f"gs_sort depth_bits, sort mode {mode}")
+    from paper_2512_08478_amd.render import Renderer, depth_range_bits
+    Rs = Renderer(dict(tile_w=16, tile_h=16, radix_bits=8, sort_mode=mode))
+    sc, cam = S.medium_scene(n=300_000)
+    p = gp(sc)
+    full = Rs.forward(p, cam, depth_bits=0, want_keys=True)
+    torch.cuda.synchronize()
+    cn = u32(full.counts)
+    b = depth_range_bits(cn)
+    print(f"visible depth key range {int(cn[3]) - int(cn[2])}: {b} bits")
+    assert 20 <= b <= 30
+    ref_v, ref_k = u32(full.values).copy(), u64(full.keys).copy()
+    for bits in (b, b + 1, 32):
+        fr = Rs.forward(p, cam, depth_bits=bits, want_keys=True)
+        torch.cuda.synchronize()
+        assert int(u32(fr.flag)[0]) == 0, bits
+        np.testing.assert_array_equal(u32(fr.values), ref_v, err_msg=f"depth_bits {bits}")
+        np.testing.assert_array_equal(u64(fr.keys), ref_k, err_msg=f"depth_bits {bits}")
+    # too few bits: reported, and the sort stays a permutation of the pairs
+    fr = Rs.forward(p, cam, capacity=full.capacity, depth_bits=b - 2)
+    torch.cuda.synchronize()
+    assert int(u32(fr.flag)[0]) & 2
+    assert sorted(u32(fr.values).tolist()) == sorted(ref_v.tolist())
 
 
 def test_render_tiny_whole_image(R, orc):
