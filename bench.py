@@ -456,7 +456,7 @@ def run_batched(args):
     targets = [torch.from_numpy(S.random_target(100 + v, c.height, c.width)).cuda()
                for v, c in enumerate(cams)]
     log = (lambda m: print(m, file=sys.stderr, flush=True))
-    best, table = autotune(p, cams, targets, reps=1, log=log)
+    best, table = autotune(p, cams, targets, reps=2, log=log)
     br = BatchRenderer(p, cams, targets, best)
     caps = br.plan()
     br.capture()
@@ -487,6 +487,7 @@ def run_batched(args):
     # library's stream)
     br1 = BatchRenderer(p, cams, targets, dict(best, streams=1))
     br1.capacity = br.capacity
+    br1.depth_bits = br.depth_bits
     br1.run_eager()
     torch.cuda.synchronize()
     L.trace_enable(True)

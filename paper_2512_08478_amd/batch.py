@@ -72,6 +72,7 @@ class BatchRenderer:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(nst)] if nst > 1 else []
         self.headroom = headroom
         self.capacity = None
+        self.depth_bits = None   # per view, from plan() (None: all 32 bits)
         self.graph = None
         self.images = None
         self.grads = tuple(torch.zeros_like(t) for t in params.tensors())
@@ -115,7 +116,7 @@ class BatchRenderer:
                 ctx = torch.cuda.stream(self.streams[k % nst]) if self.streams else contextlib.nullcontext()
                 with ctx:
                     fr = R.forward(self.p, cam, capacity=self.capacity[v],
-                                   depth_bits=self.depth_bits[v])
+                                   depth_bits=self.depth_bits[v] if self.depth_bits else None)
                     self.flags[v:v + 1].copy_(fr.flag)
                     g = l1_grad(fr.image, self.targets[v])
                     R.backward_2d(self.p, cam, fr, g, self.g2d[k])
@@ -197,10 +198,12 @@ def _time_batch(br: BatchRenderer, reps: int):
 def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
              tiles=TILE_SHAPES, bits=RADIX_BITS, modes=SORT_MODES, orders=RASTER_ORDERS,
              streams=STREAM_COUNTS, log=None):
-    """Coordinate search: tile shape (at 8-bit digits, mode 0, one stream),
-    then digit width, then sort mode, then the compositing order of the
-    tiles, then the number of streams, each by the wall time of whole eager
-    batches.  Returns (settings dict, [(settings, seconds)])."""
+    """Coordinate search: the number of streams (at the first tile shape,
+    8-bit digits, mode 0), then tile shape, digit width, sort mode and the
+    compositing order of the tiles, each by the wall time of whole eager
+    batches.  Streams come first because they change what the other
+    settings trade against (an overlapped sort costs less).  Returns
+    (settings dict, [(settings, seconds)])."""
     base = dict(base_settings or {})
     table = []
 
@@ -218,9 +221,13 @@ def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
     best = dict(tile_w=tiles[0][0], tile_h=tiles[0][1], radix_bits=bits[0], sort_mode=modes[0],
                 raster_order=orders[0], streams=streams[0])
     best_t = None
-    for tw, th in tiles:
-        t = measure(dict(best, tile_w=tw, tile_h=th))
+    for n in streams:
+        t = measure(dict(best, streams=n))
         if best_t is None or t < best_t:
+            best_t, best = t, dict(best, streams=n)
+    for tw, th in tiles[1:]:
+        t = measure(dict(best, tile_w=tw, tile_h=th))
+        if t < best_t:
             best_t, best = t, dict(best, tile_w=tw, tile_h=th)
     for b in bits[1:]:
         t = measure(dict(best, radix_bits=b))
@@ -234,10 +241,6 @@ def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
         t = measure(dict(best, raster_order=o))
         if t < best_t:
             best_t, best = t, dict(best, raster_order=o)
-    for n in streams[1:]:
-        t = measure(dict(best, streams=n))
-        if t < best_t:
-            best_t, best = t, dict(best, streams=n)
     return dict(base, **best), table
 
 
