@@ -164,6 +164,43 @@ def measured_traffic(workload, kernel):
     return int(rec["bytes_per_launch"])
 
 
+def frame_percentiles(torch, step, n, flush):
+    """Median, p10 and p90 of n frame times (ms), each bracketed by events on
+    the stream the frame runs on; with `flush`, 1 GiB is written before every
+    frame (outside the events)."""
+    import numpy as np
+    ev = []
+    for _ in range(n):
+        if flush is not None:
+            flush.fill_(1.0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        step()
+        b.record()
+        ev.append((a, b))
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"median": round(float(np.median(t)), 4), "p10": round(float(np.percentile(t, 10)), 4),
+            "p90": round(float(np.percentile(t, 90)), 4)}
+
+
+def traced_stages(L, step, reps, flush):
+    """Per-frame and per-launch kernel times (ms) over `reps` frames, from the
+    HIP events libgs records around its own launches; with `flush`, 1 GiB is
+    written before every frame (not traced)."""
+    L.trace_enable(True)
+    acc, cnt = {}, {}
+    for _ in range(reps):
+        if flush is not None:
+            flush.fill_(1.0)
+        step()
+        for lab, ms in L.trace_read():
+            acc[lab] = acc.get(lab, 0.0) + ms
+            cnt[lab] = cnt.get(lab, 0) + 1
+    L.trace_enable(False)
+    return {k: acc[k] / reps for k in acc}, {k: acc[k] / cnt[k] for k in acc}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -263,20 +300,18 @@ def main():
     if flag & 2:
         raise RuntimeError("depth key range wider than planned during the timed steps")
 
+    # Warm frames run back to back; a cold frame first writes 1 GiB, four
+    # times the 256 MB last-level cache (MALL), so its inputs come from HBM.
+    flush = torch.empty(2**28, dtype=torch.float32, device="cuda")
+    frame_dist = {"warm": frame_percentiles(torch, step, args.steps, None),
+                  "cold": frame_percentiles(torch, step, args.steps, flush)}
+
     # per-kernel durations, measured with HIP events recorded by libgs on the
     # stream its kernels run on
-    L.trace_enable(True)
     reps = max(5, min(20, args.steps))
-    acc = {}
-    cnt = {}
-    for _ in range(reps):
-        step()
-        for lab, ms in L.trace_read():
-            acc[lab] = acc.get(lab, 0.0) + ms
-            cnt[lab] = cnt.get(lab, 0) + 1
-    L.trace_enable(False)
-    kern_ms = {k: acc[k] / reps for k in acc}          # per frame (all passes)
-    kern_avg = {k: acc[k] / cnt[k] for k in acc}       # per launch
+    kern_ms, kern_avg = traced_stages(L, step, reps, None)
+    cold_ms, cold_avg = traced_stages(L, step, reps, flush)
+    del flush
 
     # composited (pixel, Gaussian) pairs of this frame, for the compositing roofline
     nbl = torch.empty((H, W), dtype=torch.int32, device="cuda")
@@ -312,6 +347,13 @@ def main():
             tf = flops[k] / (kern_avg[k] * 1e-3) / 1e12
             stages[k].update(algo_flops=int(flops[k]), tflops=round(tf, 3),
                              alu_frac=round(tf / FP32_VECTOR_PEAK_TFLOPS, 4))
+    stages_cold = {}
+    for k, v in cold_avg.items():
+        e = {"ms_per_launch": round(v, 5)}
+        if k in ab:
+            gbs = ab[k] / (v * 1e-3) / 1e9
+            e.update(gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+        stages_cold[k] = e
     sort_ms = sum(kern_ms.get(k, 0.0) for k in SORT_KERNELS)
     # roofline of the kernel that takes the most time per frame
     dom = max(kern_ms, key=lambda k: kern_ms[k])
@@ -353,6 +395,8 @@ def main():
         "sort_gkeys_per_s": round(inst / (sort_ms * 1e-3) / 1e9, 3) if sort_ms > 0 else None,
         "sort_ms": round(sort_ms, 4),
         "stages": stages,
+        "frame_ms": frame_dist,
+        "stages_cold": stages_cold,
         "roofline": roofline,
     }
     if tuned is not None:
@@ -384,6 +428,7 @@ def run_sort32(args):
     p = GaussianParams.from_scene(sc)
     _, dkeys, _, _ = R.preprocess(p, cam, reuse=False)
     torch.cuda.synchronize()
+    flush = torch.empty(2**28, dtype=torch.float32, device="cuda")
     rows, ms_at_max = [], None
     for n in sorted(PAPER_SORT_MS):
         keys = dkeys[:n]  # the generator's draws are i.i.d., so a prefix is a random subset
@@ -395,8 +440,10 @@ def run_sort32(args):
             R.sort_pairs32(keys)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        # cold: 1 GiB written before each sort, so the keys come from HBM
+        cold = frame_percentiles(torch, lambda: R.sort_pairs32(keys), args.steps, flush)
         rows.append({"n": n, "ms": round(ms, 4), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
-                     "paper_ms_rtx4090": PAPER_SORT_MS[n]})
+                     "cold_ms_median": cold["median"], "paper_ms_rtx4090": PAPER_SORT_MS[n]})
         ms_at_max = ms
     n = max(PAPER_SORT_MS)
     # per-kernel times at the largest size (HIP events on the library's stream)

@@ -6,12 +6,13 @@
 // index) order) and works only on the splats that reach it.  Quadrants of
 // one tile never wait on each other, and the grid has four to eight times
 // as many workgroups as tiles, which balances uneven lists.  Splats are
-// staged through LDS in batches of 64.  While staging, every splat gets
-//   * a quadrant mask: whether its opacity-aware footprint (where
-//     o exp(-Q/2) >= alpha_min) can reach the quadrant, from the ellipse's
-//     exact extents with a small outward margin, so that the wave skips
-//     the splat with a scalar test;
-//   * per-row terms of the log2 weight
+// staged through LDS in batches of 64:
+//   * only the splats whose opacity-aware footprint (where
+//     o exp(-Q/2) >= alpha_min) reaches the quadrant -- by the pixel bbox
+//     that preprocess rounded outwards from the ellipse's exact extents --
+//     are staged, densely and in list order, so the compositing loops walk
+//     them with a plain counter and no per-splat mask bookkeeping;
+//   * each staged splat gets per-row terms of the log2 weight
 //       e = log2(o) - (log2e/2) Q = rowterm[r] - qa' (ubase[r] + lx)^2,
 //     with Q = qa (dx - qb dy)^2 + qc dy^2, qa' = qa log2e/2, and
 //     ubase[r] the value of dx - qb dy at the quadrant's first column in
@@ -101,20 +102,22 @@ inline int raster_grid(const SetK& set, int tw, int th) {
 
 
 // LDS staging of one batch of splats for one 8x8 quadrant, shared by the
-// forward and backward kernels.  Row terms are stored row-contiguous per
-// splat, so the writes (consecutive threads on consecutive rows) and the
-// wave's reads (its 8 rows of one splat) both touch consecutive words.
+// forward and backward kernels.  Only the splats whose footprint reaches
+// the quadrant are staged, densely in list order (their rank among the
+// batch's hits), so the compositing loops walk them with a plain counter.
+// Row terms are stored row-contiguous per splat, so the writes
+// (consecutive threads on consecutive rows) and the wave's reads (its 8
+// rows of one splat) both touch consecutive words.
 constexpr int kBatch = 64;  // splats per batch: one per lane
 template <bool DEPTH>
 struct StageT {
-  float4 hdr[kBatch];   // qa', r, g, b
-  float4 aux[kBatch];   // qb, qc', my, 1 / opacity
-  float2 ml[kBatch];    // mx, log2(opacity)
-  float rt[kBatch][8];  // log2(o) - qc' dy^2 per quadrant row
-  float ub[kBatch][8];  // dx - qb dy at the quadrant's first column, per row
-  uint32_t hit[kBatch]; // footprint reaches the quadrant
-  uint32_t gid[kBatch]; // Gaussian index
-  uint32_t list[kBatch];  // batch slots of the splats that reach the quadrant
+  float4 hdr[kBatch];      // qa', r, g, b
+  float4 aux[kBatch];      // qb, qc', my, 1 / opacity
+  float2 ml[kBatch];       // mx, log2(opacity)
+  float2 rows[kBatch][8];  // per quadrant row: log2(o) - qc' dy^2, and dx - qb dy at the
+                           // quadrant's first column
+  uint32_t gid[kBatch];    // Gaussian index
+  uint32_t pos[kBatch];    // the splat's position in the tile's list (as the kernel counts it)
   float dep[DEPTH ? kBatch : 1];  // camera-space depth (mesh depth test only)
 };
 using Stage = StageT<false>;
@@ -141,13 +144,17 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
   return r;
 }
 
-// Phase 1 of staging: splat j's parameters, whether its footprint reaches
-// the quadrant whose top-left pixel is (qx0, qy0), and its index.  The
-// reach test uses the record's pixel bbox, which preprocess rounded
-// outwards from the opacity-aware footprint.  DEPTH also stages the depth.
+// Phase 1 of staging, called by every lane of the wave (lane j holds the
+// batch's j-th splat when `valid`): whether the splat's footprint reaches
+// the quadrant whose top-left pixel is (qx0, qy0), and if so its
+// parameters, index and list position `pos`, written at its rank among the
+// batch's hits.  The reach test uses the record's pixel bbox, which
+// preprocess rounded outwards from the opacity-aware footprint.  DEPTH also
+// stages the depth.  Returns the number of hits.
 template <bool DEPTH>
-__device__ __forceinline__ void stage_params(StageT<DEPTH>& S, int j, const SplatRec& r,
-                                             uint32_t g, int qx0, int qy0) {
+__device__ __forceinline__ int stage_params(StageT<DEPTH>& S, bool valid, const SplatRec& r,
+                                            uint32_t g, uint32_t pos, int qx0, int qy0,
+                                            int lane) {
   const float4 a = r.a, b = r.b;
   const float c = r.c;
   const float mx = a.x, my = a.y, qb = a.w;
@@ -155,41 +162,42 @@ __device__ __forceinline__ void stage_params(StageT<DEPTH>& S, int j, const Spla
   const float lo = log2f(b.y);
   const int px0 = (int)(r.lo & 0xFFFFu), py0 = (int)(r.lo >> 16);
   const int px1 = (int)(r.hi & 0xFFFFu), py1 = (int)(r.hi >> 16);
-  const bool hit = px0 <= qx0 + 7 && px1 >= qx0 && py0 <= qy0 + 7 && py1 >= qy0;
-  S.hdr[j] = make_float4(qa_, b.z, b.w, c);
-  S.aux[j] = make_float4(qb, qc_, my, 1.f / b.y);
-  S.ml[j] = make_float2(mx, lo);
-  S.hit[j] = hit ? 1u : 0u;
-  S.gid[j] = g;
-  if constexpr (DEPTH) S.dep[j] = r.depth;
+  const bool hit = valid && px0 <= qx0 + 7 && px1 >= qx0 && py0 <= qy0 + 7 && py1 >= qy0;
+  const uint64_t hits = ballot(hit);
+  if (hit) {
+    const int k = __builtin_popcountll(hits & ((1ull << lane) - 1ull));
+    S.hdr[k] = make_float4(qa_, b.z, b.w, c);
+    S.aux[k] = make_float4(qb, qc_, my, 1.f / b.y);
+    S.ml[k] = make_float2(mx, lo);
+    S.gid[k] = g;
+    S.pos[k] = pos;
+    if constexpr (DEPTH) S.dep[k] = r.depth;
+  }
+  return __builtin_popcountll(hits);
 }
 
-// Phase 2 of staging: the row terms of the staged splats whose bbox
-// reaches the quadrant, one (splat, row) pair per lane and step.  Each
-// pair also finds the row's largest exponent: e(lx) = rt - qa' (ub + lx)^2
-// is concave in lx, so over lx = 0..7 it peaks at the floor or the ceiling
-// of -ub (clamped).  A splat none of whose rows reaches log2(alpha_min)
-// blends into no pixel of the quadrant and is dropped from the mask; the
-// test keeps a margin far above the rounding of e, so it never drops a
-// splat that a pixel would blend.  Returns the mask of the remaining
-// splats' batch slots.
+// Phase 2 of staging: the row terms of the nh staged splats, one (splat,
+// row) pair per lane and step.  An odd count is padded with one splat that
+// no pixel takes (its log2 weight is -inf and it hides nothing), so the
+// forward loop can take the splats in pairs without a test.
 template <bool DEPTH>
-__device__ __forceinline__ uint64_t stage_rows(StageT<DEPTH>& S, int cnt, int qx0, int qy0,
-                                               int lane, float log2_tau) {
-  const uint64_t hits = ballot(lane < cnt && S.hit[lane < cnt ? lane : 0] != 0u);
-  if ((hits >> lane) & 1ull)
-    S.list[__builtin_popcountll(hits & ((1ull << lane) - 1ull))] = (uint32_t)lane;
-  __syncthreads();
-  const int nh = __builtin_popcountll(hits);
+__device__ __forceinline__ void stage_rows(StageT<DEPTH>& S, int nh, int qx0, int qy0,
+                                           int lane) {
+#pragma unroll 1
   for (int item = lane; item < nh * 8; item += 64) {
-    const int j = (int)S.list[item / 8], r = item % 8;
-    const float4 x = S.aux[j];   // qb, qc', my, 1 / opacity
-    const float2 ml = S.ml[j];   // mx, log2(opacity)
+    const int k = item >> 3, r = item & 7;
+    const float4 x = S.aux[k];  // qb, qc', my, 1 / opacity
+    const float2 ml = S.ml[k];  // mx, log2(opacity)
     const float dy = (qy0 + r + 0.5f) - x.z;
-    S.rt[j][r] = fmaf(-x.y, dy * dy, ml.y);
-    S.ub[j][r] = fmaf(-x.x, dy, (qx0 + 0.5f) - ml.x);
+    S.rows[k][r] = make_float2(fmaf(-x.y, dy * dy, ml.y), fmaf(-x.x, dy, (qx0 + 0.5f) - ml.x));
   }
-  return hits;
+  if ((nh & 1) && lane < 8) {  // nh is odd, so slot nh < kBatch is free
+    S.rows[nh][lane] = make_float2(-__builtin_inff(), 0.f);
+    if (lane == 0) {
+      S.hdr[nh] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (DEPTH) S.dep[nh] = -__builtin_inff();
+    }
+  }
 }
 
 // One 64-thread workgroup (one wave) per 8x8 quadrant of a TW x TH tile:
@@ -226,11 +234,13 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t lastc = 0, nb = 0;
   bool done = !inside;
-  // `live` is 1 while the pixel composites and 0 once it stopped (T fell
-  // below t_eps, a mesh hides the splats from here on, or the pixel lies
-  // outside the image), kept as a float so that the loop needs no
-  // lane-mask bookkeeping
-  float live = 1.f;
+  // The pixel takes a splat when its log2 weight reaches `thr`:
+  // log2(alpha_min) while the pixel composites, +inf once it stopped (T
+  // fell below t_eps, a mesh hides the splats from here on, or the pixel
+  // lies outside the image), so one compare decides and the loop needs no
+  // lane-mask bookkeeping.  No log2 weight is +inf.
+  const float kStopped = __builtin_inff();
+  float thr = log2_tau;
   // mesh depth at this pixel (splats deeper than it are hidden)
   float D = __builtin_inff();
   if (MESH && inside) D = mesh_depth[py * W + px];
@@ -251,49 +261,51 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     if (!ballot(!done)) break;
     const int cnt = (int)min((uint32_t)kBatch, end - bs);
     __syncthreads();  // the previous batch's reads of S are done
-    if (lane < cnt) stage_params(S, lane, r_cur, g_cur, tx0, ty0);
+    const int nh = stage_params(S, lane < cnt, r_cur, g_cur, bs - start + lane + 1, tx0, ty0,
+                                lane);
     const SplatRec r_next = load_splat(splats, g_next);
     const uint32_t g_after = values[min(bs + 2 * kBatch + lane, lastpos)];
     __syncthreads();
-    uint64_t m = stage_rows(S, cnt, tx0, ty0, lane, log2_tau);
+    stage_rows(S, nh, tx0, ty0, lane);
     __syncthreads();
     // Lanes never branch apart here: a pair a lane must not blend (weight
     // below alpha_min, or the pixel already stopped) gets alpha = 0, which
     // leaves C and T bitwise unchanged; only wave-uniform branches remain
     // (no lane blends this splat; every pixel of the wave has stopped).
-    // two hit splats per step: both splats' LDS reads are issued before
-    // the first one blends, hiding one read latency per pair
-    live = done ? 0.f : 1.f;
-    auto blend = [&](int j, float e, const float4& h) {
-      if constexpr (MESH) live = S.dep[j] > D ? 0.f : live;  // hidden from here on
-      const bool take = e >= log2_tau && live != 0.f;
+    thr = done ? kStopped : log2_tau;
+    int lastk = -1;  // rank of this batch's last splat blended into the pixel
+    auto blend = [&](int k, float e, float cr, float cg, float cb) {
+      if constexpr (MESH) thr = S.dep[k] > D ? kStopped : thr;  // hidden from here on
+      const bool take = e >= thr;
       if (!ballot(take)) return;
       // min(alpha_max, 2^e) as a median (2^e > 0): one instruction
       const float alpha = take ? __builtin_amdgcn_fmed3f(hw_exp2(e), 0.f, amax) : 0.f;
       const float w = alpha * T;
-      C0 = fmaf(w, h.y, C0);
-      C1 = fmaf(w, h.z, C1);
-      C2 = fmaf(w, h.w, C2);
+      C0 = fmaf(w, cr, C0);
+      C1 = fmaf(w, cg, C1);
+      C2 = fmaf(w, cb, C2);
       T = T * (1.f - alpha);
-      lastc = take ? bs + j + 1 - start : lastc;
+      lastk = take ? k : lastk;
       if constexpr (COUNT) nb += take ? 1u : 0u;
-      live = T < t_eps ? 0.f : live;
+      thr = T < t_eps ? kStopped : thr;
     };
-    while (m) {
-      const int j0 = __builtin_ctzll(m);
-      m &= m - 1;
-      const bool two = m != 0;
-      const int j1 = two ? __builtin_ctzll(m) : j0;
-      if (two) m &= m - 1;
-      const float u0 = S.ub[j0][row] + lxf, u1 = S.ub[j1][row] + lxf;
-      const float4 h0 = S.hdr[j0], h1 = S.hdr[j1];
-      const float e0 = fmaf(-h0.x, u0 * u0, S.rt[j0][row]);
-      const float e1 = fmaf(-h1.x, u1 * u1, S.rt[j1][row]);
-      blend(j0, e0, h0);
-      if (two) blend(j1, e1, h1);
-      if (!ballot(live != 0.f)) break;
+    // two staged splats per step (an odd count ends on the padding splat)
+    for (int k = 0; k < nh; k += 2) {
+      const float2 q0 = S.rows[k][row], q1 = S.rows[k + 1][row];
+      const float4 h0 = S.hdr[k], h1 = S.hdr[k + 1];
+      // both headers whole in registers here: otherwise the colour reads
+      // sink into the blend and wait for LDS a second time
+      float r0 = h0.y, g0 = h0.z, b0 = h0.w;
+      asm volatile("" : "+v"(r0), "+v"(g0), "+v"(b0));
+      const float u0 = q0.y + lxf, u1 = q1.y + lxf;
+      const float e0 = fmaf(-h0.x, u0 * u0, q0.x);
+      const float e1 = fmaf(-h1.x, u1 * u1, q1.x);
+      blend(k, e0, r0, g0, b0);
+      blend(k + 1, e1, h1.y, h1.z, h1.w);
+      if (!ballot(thr != kStopped)) break;
     }
-    done = live == 0.f;
+    if (lastk >= 0) lastc = S.pos[lastk];
+    done = thr == kStopped;
     g_cur = g_next;
     r_cur = r_next;
     g_next = g_after;
@@ -386,20 +398,23 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
     const uint32_t bs = (uint32_t)bi * kBatch;
     __syncthreads();
     const int cnt = (int)min((uint32_t)kBatch, nlast - bs);
+    uint32_t g = 0;
+    SplatRec rec = {};
     if (lane < cnt) {
-      const uint32_t g = values[start + bs + lane];
-      stage_params(S, lane, load_splat(splats, g), g, tx0, ty0);
+      g = values[start + bs + lane];
+      rec = load_splat(splats, g);
     }
+    const int nh = stage_params(S, lane < cnt, rec, g, bs + lane, tx0, ty0, lane);
     __syncthreads();
-    uint64_t m = stage_rows(S, cnt, tx0, ty0, lane, log2_tau);
+    stage_rows(S, nh, tx0, ty0, lane);
     __syncthreads();
     // Lanes never branch apart: a pair a lane must not revisit (position at
     // or past its `last`, or weight below alpha_min) gets alpha = 0, which
     // leaves T, S and B bitwise unchanged and yields zero gradients.
-    auto visit = [&](int j, float u, float e, const float4& h) {
-      const bool take = bs + j < mylast && e >= log2_tau;
+    auto visit = [&](int k, float u, float e, const float4& h) {
+      const bool take = S.pos[k] < mylast && e >= log2_tau;
       if (!ballot(take)) return;
-      const float4 x = S.aux[j];  // qb, qc', my, 1 / opacity
+      const float4 x = S.aux[k];  // qb, qc', my, 1 / opacity
       const float gw = take ? hw_exp2(e) : 0.f;
       const float alpha = __builtin_amdgcn_fmed3f(gw, 0.f, set.amax);  // as the forward
       const float om = 1.f - alpha;
@@ -441,23 +456,21 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       if (lane < 9) {
         const float v = ((s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane])) +
                         ((s_red[4][lane] + s_red[5][lane]) + (s_red[6][lane] + s_red[7][lane]));
-        atomicAdd(grad2d + (size_t)S.gid[j] * kGrad2dStride + lane, v);
+        atomicAdd(grad2d + (size_t)S.gid[k] * kGrad2dStride + lane, v);
       }
     };
-    // two splats per step, back to front: both LDS reads are in flight
-    // before the first one is visited
-    while (m) {
-      const int j0 = 63 - __builtin_clzll(m);
-      m &= ~(1ull << j0);
-      const bool two = m != 0;
-      const int j1 = two ? 63 - __builtin_clzll(m) : j0;
-      if (two) m &= ~(1ull << j1);
-      const float u0 = S.ub[j0][row] + lxf, u1 = S.ub[j1][row] + lxf;
-      const float4 h0 = S.hdr[j0], h1 = S.hdr[j1];
-      const float e0 = fmaf(-h0.x, u0 * u0, S.rt[j0][row]);
-      const float e1 = fmaf(-h1.x, u1 * u1, S.rt[j1][row]);
-      visit(j0, u0, e0, h0);
-      if (two) visit(j1, u1, e1, h1);
+    // two staged splats per step, back to front: both LDS reads are in
+    // flight before the first one is visited
+    for (int k0 = nh - 1; k0 >= 0; k0 -= 2) {
+      const bool two = k0 > 0;
+      const int k1 = two ? k0 - 1 : k0;
+      const float2 q0 = S.rows[k0][row], q1 = S.rows[k1][row];
+      const float4 h0 = S.hdr[k0], h1 = S.hdr[k1];
+      const float u0 = q0.y + lxf, u1 = q1.y + lxf;
+      const float e0 = fmaf(-h0.x, u0 * u0, q0.x);
+      const float e1 = fmaf(-h1.x, u1 * u1, q1.x);
+      visit(k0, u0, e0, h0);
+      if (two) visit(k1, u1, e1, h1);
     }
   }
 }
