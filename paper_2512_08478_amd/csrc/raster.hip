@@ -37,6 +37,8 @@
 // dense tiles from running alone at the end; or block-cyclic runs of
 // neighbouring tiles over the XCDs, whose L2s then share those tiles'
 // splats.  Either way dense regions are spread over all eight XCDs.
+#include <utility>
+
 #include "gs_device.h"
 #include "gs_internal.h"
 
@@ -121,6 +123,13 @@ struct StageT {
   float dep[DEPTH ? kBatch : 1];  // camera-space depth (mesh depth test only)
 };
 using Stage = StageT<false>;
+
+// Calls f(0), f(2), f(4), ... with compile-time arguments until one returns
+// false: a fully unrolled walk over the pairs of a batch.
+template <typename F, int... K>
+__device__ __forceinline__ void walk_pairs(F&& f, std::integer_sequence<int, K...>) {
+  (void)(f(std::integral_constant<int, 2 * K>{}) && ...);
+}
 
 // The fields of a splat record the compositing kernels read.
 struct SplatRec {
@@ -289,8 +298,12 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       if constexpr (COUNT) nb += take ? 1u : 0u;
       thr = T < t_eps ? kStopped : thr;
     };
-    // two staged splats per step (an odd count ends on the padding splat)
-    for (int k = 0; k < nh; k += 2) {
+    // Two staged splats per step (an odd count ends on the padding splat),
+    // unrolled so that every LDS address and rank is a constant; the walk
+    // stops after the staged splats or once every pixel has stopped.
+    auto step = [&](auto kc) -> bool {
+      constexpr int k = decltype(kc)::value;
+      if (k >= nh) return false;
       const float2 q0 = S.rows[k][row], q1 = S.rows[k + 1][row];
       const float4 h0 = S.hdr[k], h1 = S.hdr[k + 1];
       // both headers whole in registers here: otherwise the colour reads
@@ -302,8 +315,9 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       const float e1 = fmaf(-h1.x, u1 * u1, q1.x);
       blend(k, e0, r0, g0, b0);
       blend(k + 1, e1, h1.y, h1.z, h1.w);
-      if (!ballot(thr != kStopped)) break;
-    }
+      return ballot(thr != kStopped) != 0;
+    };
+    walk_pairs(step, std::make_integer_sequence<int, kBatch / 2>{});
     if (lastk >= 0) lastc = S.pos[lastk];
     done = thr == kStopped;
     g_cur = g_next;
