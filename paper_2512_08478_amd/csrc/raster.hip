@@ -124,6 +124,21 @@ struct StageT {
 };
 using Stage = StageT<false>;
 
+// The LDS operands of staged splats k and k + 1 at one pixel row: the row
+// terms (log2 weight offset, dx - qb dy at the first column) and headers.
+struct PairOps {
+  float2 q0, q1;
+  float4 h0, h1;
+};
+template <bool DEPTH, int K>
+__device__ __forceinline__ void read_pair(const StageT<DEPTH>& S, std::integral_constant<int, K>,
+                                          int row, PairOps& o) {
+  o.q0 = S.rows[K][row];
+  o.q1 = S.rows[K + 1][row];
+  o.h0 = S.hdr[K];
+  o.h1 = S.hdr[K + 1];
+}
+
 // Calls f(0), f(2), f(4), ... with compile-time arguments until one returns
 // false: a fully unrolled walk over the pairs of a batch.
 template <typename F, int... K>
@@ -270,8 +285,10 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     if (!ballot(!done)) break;
     const int cnt = (int)min((uint32_t)kBatch, end - bs);
     __syncthreads();  // the previous batch's reads of S are done
-    const int nh = stage_params(S, lane < cnt, r_cur, g_cur, bs - start + lane + 1, tx0, ty0,
-                                lane);
+    int nh = stage_params(S, lane < cnt, r_cur, g_cur, bs - start + lane + 1, tx0, ty0, lane);
+    // an opaque 32-bit scalar, so that the walk's end tests stay one
+    // scalar compare (the compiler otherwise compares the 64-bit mask)
+    asm volatile("" : "+s"(nh));
     const SplatRec r_next = load_splat(splats, g_next);
     const uint32_t g_after = values[min(bs + 2 * kBatch + lane, lastpos)];
     __syncthreads();
@@ -300,21 +317,29 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     };
     // Two staged splats per step (an odd count ends on the padding splat),
     // unrolled so that every LDS address and rank is a constant; the walk
-    // stops after the staged splats or once every pixel has stopped.
+    // stops after the staged splats or once every pixel has stopped.  Each
+    // step first reads the next pair's operands into the other of two
+    // register sets (slots past the staged splats hold stale values that
+    // are never used), so a wave running alone does not wait for LDS on
+    // every step.
+    PairOps ops[2];
+    read_pair(S, std::integral_constant<int, 0>{}, row, ops[0]);
     auto step = [&](auto kc) -> bool {
       constexpr int k = decltype(kc)::value;
+      constexpr int cur = (k / 2) & 1;
       if (k >= nh) return false;
-      const float2 q0 = S.rows[k][row], q1 = S.rows[k + 1][row];
-      const float4 h0 = S.hdr[k], h1 = S.hdr[k + 1];
+      if constexpr (k + 2 < kBatch)
+        read_pair(S, std::integral_constant<int, k + 2>{}, row, ops[cur ^ 1]);
+      const PairOps& o = ops[cur];
       // both headers whole in registers here: otherwise the colour reads
       // sink into the blend and wait for LDS a second time
-      float r0 = h0.y, g0 = h0.z, b0 = h0.w;
+      float r0 = o.h0.y, g0 = o.h0.z, b0 = o.h0.w;
       asm volatile("" : "+v"(r0), "+v"(g0), "+v"(b0));
-      const float u0 = q0.y + lxf, u1 = q1.y + lxf;
-      const float e0 = fmaf(-h0.x, u0 * u0, q0.x);
-      const float e1 = fmaf(-h1.x, u1 * u1, q1.x);
+      const float u0 = o.q0.y + lxf, u1 = o.q1.y + lxf;
+      const float e0 = fmaf(-o.h0.x, u0 * u0, o.q0.x);
+      const float e1 = fmaf(-o.h1.x, u1 * u1, o.q1.x);
       blend(k, e0, r0, g0, b0);
-      blend(k + 1, e1, h1.y, h1.z, h1.w);
+      blend(k + 1, e1, o.h1.y, o.h1.z, o.h1.w);
       return ballot(thr != kStopped) != 0;
     };
     walk_pairs(step, std::make_integer_sequence<int, kBatch / 2>{});
