@@ -300,10 +300,13 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     // (no lane blends this splat; every pixel of the wave has stopped).
     thr = done ? kStopped : log2_tau;
     int lastk = -1;  // rank of this batch's last splat blended into the pixel
-    auto blend = [&](int k, float e, float cr, float cg, float cb) {
+    // `tested`: the caller has already found a lane that may take the
+    // splat (a superset: thresholds only rise), so the blend runs without
+    // a test of its own; lanes that do not take it leave everything as is.
+    auto blend = [&](int k, float e, float cr, float cg, float cb, bool tested) {
       if constexpr (MESH) thr = S.dep[k] > D ? kStopped : thr;  // hidden from here on
       const bool take = e >= thr;
-      if (!ballot(take)) return;
+      if (!tested && !ballot(take)) return;
       // min(alpha_max, 2^e) as a median (2^e > 0): one instruction
       const float alpha = take ? __builtin_amdgcn_fmed3f(hw_exp2(e), 0.f, amax) : 0.f;
       const float w = alpha * T;
@@ -338,8 +341,11 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       const float u0 = o.q0.y + lxf, u1 = o.q1.y + lxf;
       const float e0 = fmaf(-o.h0.x, u0 * u0, o.q0.x);
       const float e1 = fmaf(-o.h1.x, u1 * u1, o.q1.x);
-      blend(k, e0, r0, g0, b0);
-      blend(k + 1, e1, o.h1.y, o.h1.z, o.h1.w);
+      // whether a lane may take the second splat, decided before the first
+      // blends, so that branch does not wait on the first blend's results
+      const bool any1 = ballot(e1 >= thr) != 0;
+      blend(k, e0, r0, g0, b0, false);
+      if (any1) blend(k + 1, e1, o.h1.y, o.h1.z, o.h1.w, true);
       return ballot(thr != kStopped) != 0;
     };
     walk_pairs(step, std::make_integer_sequence<int, kBatch / 2>{});
