@@ -115,7 +115,6 @@ template <bool DEPTH>
 struct StageT {
   float4 hdr[kBatch];      // qa', r, g, b
   float4 aux[kBatch];      // qb, qc', my, 1 / opacity
-  float2 ml[kBatch];       // mx, log2(opacity)
   float2 rows[kBatch][8];  // per quadrant row: log2(o) - qc' dy^2, and dx - qb dy at the
                            // quadrant's first column
   uint32_t gid[kBatch];    // Gaussian index
@@ -168,17 +167,20 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
   return r;
 }
 
-// Phase 1 of staging, called by every lane of the wave (lane j holds the
+// Staging of one batch, called by every lane of the wave (lane j holds the
 // batch's j-th splat when `valid`): whether the splat's footprint reaches
 // the quadrant whose top-left pixel is (qx0, qy0), and if so its
-// parameters, index and list position `pos`, written at its rank among the
-// batch's hits.  The reach test uses the record's pixel bbox, which
-// preprocess rounded outwards from the opacity-aware footprint.  DEPTH also
-// stages the depth.  Returns the number of hits.
+// parameters, index, list position `pos` and per-row weight terms, written
+// at its rank among the batch's hits.  The reach test uses the record's
+// pixel bbox, which preprocess rounded outwards from the opacity-aware
+// footprint.  DEPTH also stages the depth.  An odd count is padded with
+// one splat that no pixel takes (its log2 weight is -inf and it hides
+// nothing), so the forward walk can take the splats in pairs without a
+// test.  Returns the number of hits.
 template <bool DEPTH>
-__device__ __forceinline__ int stage_params(StageT<DEPTH>& S, bool valid, const SplatRec& r,
-                                            uint32_t g, uint32_t pos, int qx0, int qy0,
-                                            int lane) {
+__device__ __forceinline__ int stage_batch(StageT<DEPTH>& S, bool valid, const SplatRec& r,
+                                           uint32_t g, uint32_t pos, int qx0, int qy0,
+                                           int lane) {
   const float4 a = r.a, b = r.b;
   const float c = r.c;
   const float mx = a.x, my = a.y, qb = a.w;
@@ -188,32 +190,26 @@ __device__ __forceinline__ int stage_params(StageT<DEPTH>& S, bool valid, const 
   const int px1 = (int)(r.hi & 0xFFFFu), py1 = (int)(r.hi >> 16);
   const bool hit = valid && px0 <= qx0 + 7 && px1 >= qx0 && py0 <= qy0 + 7 && py1 >= qy0;
   const uint64_t hits = ballot(hit);
+  const int nh = __builtin_popcountll(hits);
   if (hit) {
     const int k = __builtin_popcountll(hits & ((1ull << lane) - 1ull));
     S.hdr[k] = make_float4(qa_, b.z, b.w, c);
     S.aux[k] = make_float4(qb, qc_, my, 1.f / b.y);
-    S.ml[k] = make_float2(mx, lo);
     S.gid[k] = g;
     S.pos[k] = pos;
     if constexpr (DEPTH) S.dep[k] = r.depth;
-  }
-  return __builtin_popcountll(hits);
-}
-
-// Phase 2 of staging: the row terms of the nh staged splats, one (splat,
-// row) pair per lane and step.  An odd count is padded with one splat that
-// no pixel takes (its log2 weight is -inf and it hides nothing), so the
-// forward loop can take the splats in pairs without a test.
-template <bool DEPTH>
-__device__ __forceinline__ void stage_rows(StageT<DEPTH>& S, int nh, int qx0, int qy0,
-                                           int lane) {
-#pragma unroll 1
-  for (int item = lane; item < nh * 8; item += 64) {
-    const int k = item >> 3, r = item & 7;
-    const float4 x = S.aux[k];  // qb, qc', my, 1 / opacity
-    const float2 ml = S.ml[k];  // mx, log2(opacity)
-    const float dy = (qy0 + r + 0.5f) - x.z;
-    S.rows[k][r] = make_float2(fmaf(-x.y, dy * dy, ml.y), fmaf(-x.x, dy, (qx0 + 0.5f) - ml.x));
+    // log2(o) - qc' dy^2 and dx - qb dy at the first column, per row
+    const float ux = (qx0 + 0.5f) - mx;
+    float2 t[8];
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) {
+      const float dy = (qy0 + rr + 0.5f) - my;
+      t[rr] = make_float2(fmaf(-qc_, dy * dy, lo), fmaf(-qb, dy, ux));
+    }
+    float4* dst = reinterpret_cast<float4*>(S.rows[k]);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+      dst[rr] = make_float4(t[2 * rr].x, t[2 * rr].y, t[2 * rr + 1].x, t[2 * rr + 1].y);
   }
   if ((nh & 1) && lane < 8) {  // nh is odd, so slot nh < kBatch is free
     S.rows[nh][lane] = make_float2(-__builtin_inff(), 0.f);
@@ -222,6 +218,7 @@ __device__ __forceinline__ void stage_rows(StageT<DEPTH>& S, int nh, int qx0, in
       if constexpr (DEPTH) S.dep[nh] = -__builtin_inff();
     }
   }
+  return nh;
 }
 
 // One 64-thread workgroup (one wave) per 8x8 quadrant of a TW x TH tile:
@@ -285,14 +282,12 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     if (!ballot(!done)) break;
     const int cnt = (int)min((uint32_t)kBatch, end - bs);
     __syncthreads();  // the previous batch's reads of S are done
-    int nh = stage_params(S, lane < cnt, r_cur, g_cur, bs - start + lane + 1, tx0, ty0, lane);
+    int nh = stage_batch(S, lane < cnt, r_cur, g_cur, bs - start + lane + 1, tx0, ty0, lane);
     // an opaque 32-bit scalar, so that the walk's end tests stay one
     // scalar compare (the compiler otherwise compares the 64-bit mask)
     asm volatile("" : "+s"(nh));
     const SplatRec r_next = load_splat(splats, g_next);
     const uint32_t g_after = values[min(bs + 2 * kBatch + lane, lastpos)];
-    __syncthreads();
-    stage_rows(S, nh, tx0, ty0, lane);
     __syncthreads();
     // Lanes never branch apart here: a pair a lane must not blend (weight
     // below alpha_min, or the pixel already stopped) gets alpha = 0, which
@@ -449,9 +444,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       g = values[start + bs + lane];
       rec = load_splat(splats, g);
     }
-    const int nh = stage_params(S, lane < cnt, rec, g, bs + lane, tx0, ty0, lane);
-    __syncthreads();
-    stage_rows(S, nh, tx0, ty0, lane);
+    const int nh = stage_batch(S, lane < cnt, rec, g, bs + lane, tx0, ty0, lane);
     __syncthreads();
     // Lanes never branch apart: a pair a lane must not revisit (position at
     // or past its `last`, or weight below alpha_min) gets alpha = 0, which
