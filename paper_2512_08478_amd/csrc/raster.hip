@@ -315,7 +315,7 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     };
     // Two staged splats per step (an odd count ends on the padding splat),
     // unrolled so that every LDS address and rank is a constant; the walk
-    // stops after the staged splats or once every pixel has stopped.  Each
+    // stops after the staged splats or soon after every pixel has stopped.  Each
     // step first reads the next pair's operands into the other of two
     // register sets (slots past the staged splats hold stale values that
     // are never used), so a wave running alone does not wait for LDS on
@@ -341,7 +341,10 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       const bool any1 = ballot(e1 >= thr) != 0;
       blend(k, e0, r0, g0, b0, false);
       if (any1) blend(k + 1, e1, o.h1.y, o.h1.z, o.h1.w, true);
-      return ballot(thr != kStopped) != 0;
+      // whether every pixel has stopped, tested after every second pair (a
+      // wave that has stopped walks at most one pair more, with no effect)
+      if constexpr ((k / 2) % 2 == 1) return ballot(thr != kStopped) != 0;
+      return true;
     };
     walk_pairs(step, std::make_integer_sequence<int, kBatch / 2>{});
     if (lastk >= 0) lastc = S.pos[lastk];
