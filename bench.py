@@ -627,9 +627,16 @@ def cpu_baseline(sc, cam, n_pix, scale_pixels=None, packed=False, mesh=None, ski
         views = scale_pixels / (cam.width * cam.height)
         frame_s = ((t1 - t0) * views + (t2 - t1) * scale_pixels / n_pix) / views
         what = f"scaled to the batch's {scale_pixels} pixels, reported per view"
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": round(1.0 / frame_s, 8), "unit": "frames/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"FP64 oracle, forward only: preprocess of all {n} "
+            "sample": f"FP64 oracle on {oracle.num_threads()} threads of {cpu}, forward only: "
+                      f"preprocess of all {n} "
                       f"{'pre-packed ' if pk is not None else ''}Gaussians "
                       f"({t1 - t0:.2f} s) + brute-force Eq. 3 at {n_pix} random pixels "
                       f"({t2 - t1:.2f} s), {what}"}
