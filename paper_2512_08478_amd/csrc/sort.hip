@@ -39,7 +39,7 @@ constexpr int kMaxDigits = 512;    // digits of the widest (9-bit) pass
 constexpr int kLbWindow = 8;       // look-back status words in flight per digit
 constexpr int kKgItems = 4;        // sorted Gaussians per thread in the keygen
 constexpr int kKgPart = kBlock * kKgItems;
-constexpr int kRsMinParts = 768;   // reduce-then-scan passes aim for at least this many partitions
+constexpr int kRsMinParts = 384;   // reduce-then-scan passes aim for at least this many partitions
 
 __global__ __launch_bounds__(kBlock) void k_sort_init(uint32_t* hist, int hist_len,
                                                       uint32_t* tickets, int ntickets,
