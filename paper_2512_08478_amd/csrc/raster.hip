@@ -128,6 +128,7 @@ using Stage = StageT<false>;
 struct PairOps {
   float2 q0, q1;
   float4 h0, h1;
+  float d0, d1;  // depths (mesh depth test only)
 };
 template <bool DEPTH, int K>
 __device__ __forceinline__ void read_pair(const StageT<DEPTH>& S, std::integral_constant<int, K>,
@@ -136,6 +137,10 @@ __device__ __forceinline__ void read_pair(const StageT<DEPTH>& S, std::integral_
   o.q1 = S.rows[K + 1][row];
   o.h0 = S.hdr[K];
   o.h1 = S.hdr[K + 1];
+  if constexpr (DEPTH) {
+    o.d0 = S.dep[K];
+    o.d1 = S.dep[K + 1];
+  }
 }
 
 // Calls f(0), f(2), f(4), ... with compile-time arguments until one returns
@@ -298,8 +303,8 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     // `tested`: the caller has already found a lane that may take the
     // splat (a superset: thresholds only rise), so the blend runs without
     // a test of its own; lanes that do not take it leave everything as is.
-    auto blend = [&](int k, float e, float cr, float cg, float cb, bool tested) {
-      if constexpr (MESH) thr = S.dep[k] > D ? kStopped : thr;  // hidden from here on
+    auto blend = [&](int k, float e, float cr, float cg, float cb, float dep, bool tested) {
+      if constexpr (MESH) thr = dep > D ? kStopped : thr;  // hidden from here on
       const bool take = e >= thr;
       if (!tested && !ballot(take)) return;
       // min(alpha_max, 2^e) as a median (2^e > 0): one instruction
@@ -339,8 +344,8 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       // whether a lane may take the second splat, decided before the first
       // blends, so that branch does not wait on the first blend's results
       const bool any1 = ballot(e1 >= thr) != 0;
-      blend(k, e0, r0, g0, b0, false);
-      if (any1) blend(k + 1, e1, o.h1.y, o.h1.z, o.h1.w, true);
+      blend(k, e0, r0, g0, b0, o.d0, false);
+      if (any1) blend(k + 1, e1, o.h1.y, o.h1.z, o.h1.w, o.d1, true);
       // whether every pixel has stopped, tested after every second pair (a
       // wave that has stopped walks at most one pair more, with no effect)
       if constexpr ((k / 2) % 2 == 1) return ballot(thr != kStopped) != 0;
