@@ -175,14 +175,15 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
 // Staging of one batch, called by every lane of the wave (lane j holds the
 // batch's j-th splat when `valid`): whether the splat's footprint reaches
 // the quadrant whose top-left pixel is (qx0, qy0), and if so its
-// parameters, index, list position `pos` and per-row weight terms, written
+// parameters, list position `pos` and per-row weight terms (with BWD also
+// the backward's terms and the Gaussian index g), written
 // at its rank among the batch's hits.  The reach test uses the record's
 // pixel bbox, which preprocess rounded outwards from the opacity-aware
 // footprint.  DEPTH also stages the depth.  An odd count is padded with
 // one splat that no pixel takes (its log2 weight is -inf and it hides
 // nothing), so the forward walk can take the splats in pairs without a
 // test.  Returns the number of hits.
-template <bool DEPTH>
+template <bool DEPTH, bool BWD>
 __device__ __forceinline__ int stage_batch(StageT<DEPTH>& S, bool valid, const SplatRec& r,
                                            uint32_t g, uint32_t pos, int qx0, int qy0,
                                            int lane) {
@@ -199,8 +200,10 @@ __device__ __forceinline__ int stage_batch(StageT<DEPTH>& S, bool valid, const S
   if (hit) {
     const int k = __builtin_popcountll(hits & ((1ull << lane) - 1ull));
     S.hdr[k] = make_float4(qa_, b.z, b.w, c);
-    S.aux[k] = make_float4(qb, qc_, my, 1.f / b.y);
-    S.gid[k] = g;
+    if constexpr (BWD) {  // only the backward's gradient terms and atomics read these
+      S.aux[k] = make_float4(qb, qc_, my, 1.f / b.y);
+      S.gid[k] = g;
+    }
     S.pos[k] = pos;
     if constexpr (DEPTH) S.dep[k] = r.depth;
     // log2(o) - qc' dy^2 and dx - qb dy at the first column, per row
@@ -287,7 +290,8 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     if (!ballot(!done)) break;
     const int cnt = (int)min((uint32_t)kBatch, end - bs);
     __syncthreads();  // the previous batch's reads of S are done
-    int nh = stage_batch(S, lane < cnt, r_cur, g_cur, bs - start + lane + 1, tx0, ty0, lane);
+    int nh = stage_batch<MESH, false>(S, lane < cnt, r_cur, g_cur, bs - start + lane + 1, tx0,
+                                      ty0, lane);
     // an opaque 32-bit scalar, so that the walk's end tests stay one
     // scalar compare (the compiler otherwise compares the 64-bit mask)
     asm volatile("" : "+s"(nh));
@@ -452,7 +456,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       g = values[start + bs + lane];
       rec = load_splat(splats, g);
     }
-    const int nh = stage_batch(S, lane < cnt, rec, g, bs + lane, tx0, ty0, lane);
+    const int nh = stage_batch<false, true>(S, lane < cnt, rec, g, bs + lane, tx0, ty0, lane);
     __syncthreads();
     // Lanes never branch apart: a pair a lane must not revisit (position at
     // or past its `last`, or weight below alpha_min) gets alpha = 0, which
