@@ -175,14 +175,25 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
     const int i0 = blockIdx.x * kBlock + wave * 64;  // this wave's first Gaussian
     const float4* sh4 = reinterpret_cast<const float4*>(sh);
     float4* buf = s_sh[wave];
+    // both halves' rows are read from HBM at once (one round trip per
+    // wave), then staged through LDS half by half
+    constexpr int LPH = (kShRows * F4 + 63) / 64;  // 16-byte loads per lane and half
+    float4 pre[64 / kShRows][LPH];
+#pragma unroll
+    for (int h = 0; h < 64 / kShRows; ++h)
+#pragma unroll
+      for (int k = 0; k < LPH; ++k) {
+        const int f = lane + 64 * k, row = f / F4;
+        pre[h][k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (f < kShRows * F4 && ((need >> (h * kShRows + row)) & 1ull))
+          pre[h][k] = sh4[(size_t)(i0 + h * kShRows + row) * F4 + f % F4];
+      }
 #pragma unroll
     for (int h = 0; h < 64 / kShRows; ++h) {
-      if (!((need >> (h * kShRows)) & ((1ull << kShRows) - 1ull))) continue;
 #pragma unroll
-      for (int k = 0; k < (kShRows * F4 + 63) / 64; ++k) {
-        const int f = lane + 64 * k, row = f / F4;
-        if (f < kShRows * F4 && ((need >> (h * kShRows + row)) & 1ull))
-          buf[f] = sh4[(size_t)(i0 + h * kShRows + row) * F4 + f % F4];
+      for (int k = 0; k < LPH; ++k) {
+        const int f = lane + 64 * k;
+        if (f < kShRows * F4) buf[f] = pre[h][k];
       }
       if (tiles > 0 && lane / kShRows == h) {
         const float4* rowp = buf + (lane - h * kShRows) * F4;
