@@ -8,8 +8,10 @@ generator, which holds none of the method's arithmetic.
 ``gs_oracle.cpp`` (compiled to ``liboracle.so`` with g++, no fast-math)
 implements the forward definition: the per-Gaussian projection of Eq. 1,
 the SH colour, and the per-pixel compositing of Eqs. 2-3 by brute force in
-ascending (depth, index) order; plus the (tile, depth) key list and a
-library stable sort.  ``prepack`` / ``preprocess_packed`` give the FP16
+ascending (depth, index) order, or (``tiled=True``) the same walk over
+per-tile candidate lists, exactly equal and fast enough for whole frames;
+each pixel's near decisions and the jump they straddle (the tolerance
+protocol); plus the (tile, depth) key list and a library stable sort.  ``prepack`` / ``preprocess_packed`` give the FP16
 pre-pack of Section 3.4 (one rounding of float64 values to binary16) and
 the projection from the packed mean, opacity and upper covariance;
 ``lbs_deform`` the avatar pre-decoder's linear blend skinning (Section 3.3,
@@ -19,7 +21,8 @@ automatic differentiation of the same definition (Section 3.2: the
 formulation is differentiable).
 
 Pins (tests/test_oracle_*.py): closed forms for one isotropic Gaussian on
-and off the optical axis, two ordered Gaussians and n coincident Gaussians;
+and off the optical axis, for its largest weight over a tile, for the jump
+of every kind of near decision, tiled == brute force, two ordered Gaussians and n coincident Gaussians;
 covariance eigen-invariants; the SH basis against SciPy's complex
 harmonics and by quadrature; the sort against NumPy's stable argsort and a
 brute-force sort; front-to-back against back-to-front compositing; and the
@@ -56,7 +59,7 @@ DEFAULT_SETTINGS = dict(tile_w=16, tile_h=16, eps2d=0.3, tau=1.0 / 255.0,
 # record layout (must match the enums in gs_oracle.cpp)
 D_MX, D_MY, D_SA, D_SB, D_SC, D_CA, D_CB, D_CC, D_DEPTH = range(9)
 D_R, D_G, D_B, D_RR, D_RG, D_RB, D_OPAC, D_C3 = 9, 10, 11, 12, 13, 14, 15, 16
-D_QMAX, D_TZ = 22, 23
+D_QMAX, D_ZSCALE = 22, 23
 I_CULL, I_PX0, I_PX1, I_PY0, I_PY1, I_TX0, I_TY0, I_TX1, I_TY1, I_TILES, I_AMBIG = range(11)
 C_VISIBLE, C_NEAR, C_INVALID, C_DET, C_OPACITY, C_OFFIMAGE = range(6)
 
@@ -87,7 +90,9 @@ def _load():
         lib.orc_preprocess.argtypes = [I64, P, P, P, P, P, ctypes.c_int, P, P, P, P, P]
         lib.orc_preprocess_f64.argtypes = [I64, P, P, P, P, P, ctypes.c_int, P, P, P, P, P]
         lib.orc_preprocess_cov.argtypes = [I64, P, P, P, P, ctypes.c_int, P, P, P, P, P]
-        lib.orc_render_pixels.argtypes = [I64, P, P, P, P, I64, P, P, P, P, P, P, P, P]
+        lib.orc_render_pixels.argtypes = [I64, P, P, P, P, I64, P, P, P, P, P, P, P, P, P]
+        lib.orc_render_tiled.argtypes = [I64, P, P, P, P, I64, P, P, P, P, P, P, P, P, P]
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
         lib.orc_keys.argtypes = [I64, P, P, ctypes.c_int, P, P]
         lib.orc_count_instances.argtypes = [I64, P]
         lib.orc_count_instances.restype = I64
@@ -123,6 +128,11 @@ def set_array(settings=None) -> np.ndarray:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Number of OpenMP threads the oracle's later calls use."""
+    _load().orc_set_num_threads(int(k))
 
 
 class Records:
@@ -270,23 +280,32 @@ def mesh_at(mesh, pix):
     return d, r
 
 
-def render_pixels(recs: Records, cam, pix, settings=None, mesh=None):
-    """Eq. 3 by brute force at the given pixels (int array (P,2) of x, y).
+def render_pixels(recs: Records, cam, pix, settings=None, mesh=None, tiled=False):
+    """Eq. 3 at the given pixels (int array (P,2) of x, y).
 
+    By brute force (every pixel walks every visible Gaussian), or with
+    ``tiled`` over per-tile candidate lists, which gives exactly the same
+    outputs (pinned by the tests) at a fraction of the cost.
     ``mesh``: optional mesh prepass {depth: (H,W) camera-space z, +inf where
     no mesh; rgb: (H,W,3) or None}: Gaussians deeper than the mesh are
     hidden and the mesh colour replaces the background (Section 3.4).
-    Returns dict(rgba (P,4), T (P,), n_blend (P,), margin (P,), flags (P,))."""
+    Returns dict(rgba (P,4), T (P,), n_blend (P,), margin (P,), flags (P,),
+    jump (P,)): ``margin`` is the smallest relative distance of a decision
+    to its threshold (capped at 1), ``flags`` marks depth near-ties (1),
+    ambiguous culls (2) and near mesh-depth tests (4), and ``jump`` is the
+    largest change of the outputs that taking the pixel's near decisions
+    (margin < 1e-5, or flagged) the other way can cause, each re-walked."""
     lib = _load()
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
     P = pix.shape[0]
     out = dict(rgba=np.zeros((P, 4)), T=np.zeros(P), n_blend=np.zeros(P, np.int32),
-               margin=np.zeros(P), flags=np.zeros(P, np.int32))
+               margin=np.zeros(P), flags=np.zeros(P, np.int32), jump=np.zeros(P))
     ca, sa = cam_array(cam), set_array(settings)
     md, mr = mesh_at(mesh, pix)
-    lib.orc_render_pixels(recs.n, _p(recs.d), _p(recs.i), _p(ca), _p(sa), P, _p(pix),
-                          _p(md), _p(mr), _p(out["rgba"]), _p(out["T"]), _p(out["n_blend"]),
-                          _p(out["margin"]), _p(out["flags"]))
+    fn = lib.orc_render_tiled if tiled else lib.orc_render_pixels
+    fn(recs.n, _p(recs.d), _p(recs.i), _p(ca), _p(sa), P, _p(pix), _p(md), _p(mr),
+       _p(out["rgba"]), _p(out["T"]), _p(out["n_blend"]), _p(out["margin"]),
+       _p(out["flags"]), _p(out["jump"]))
     return out
 
 
@@ -295,13 +314,12 @@ def all_pixels(cam) -> np.ndarray:
     return np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
 
 
-def render_image(recs: Records, cam, settings=None, mesh=None):
-    """Full image (H,W,4) plus T, n_blend, margin, flags as (H,W) maps."""
-    o = render_pixels(recs, cam, all_pixels(cam), settings, mesh)
+def render_image(recs: Records, cam, settings=None, mesh=None, tiled=False):
+    """Full image (H,W,4) plus T, n_blend, margin, flags, jump as (H,W) maps."""
+    o = render_pixels(recs, cam, all_pixels(cam), settings, mesh, tiled)
     H, W = cam.height, cam.width
-    return dict(rgba=o["rgba"].reshape(H, W, 4), T=o["T"].reshape(H, W),
-                n_blend=o["n_blend"].reshape(H, W), margin=o["margin"].reshape(H, W),
-                flags=o["flags"].reshape(H, W))
+    return dict(rgba=o["rgba"].reshape(H, W, 4),
+                **{k: o[k].reshape(H, W) for k in ("T", "n_blend", "margin", "flags", "jump")})
 
 
 def tiles_xy(cam, settings=None):

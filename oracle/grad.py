@@ -231,3 +231,45 @@ def render_and_grad_assets(scenes, cam, pix, dL_drgba, settings=None, chunk=64, 
             d[nm] = np.zeros(t.shape) if g is None else g.detach().numpy()
         out.append(d)
     return rgba.detach().numpy(), out
+
+
+def render_and_grad_tiled(scene, cam, dL_dimage, settings=None, tile=(16, 16)):
+    """render_and_grad over the whole image, one tile at a time.
+
+    ``dL_dimage`` is the (H,W,4) upstream gradient.  A pixel's composite
+    involves only Gaussians whose weight reaches tau there, i.e. whose exact
+    support bbox (the oracle's pixel bbox) overlaps the pixel's tile; every
+    other Gaussian is skipped by the definition and receives no gradient
+    from that pixel.  So each tile is render_and_grad of its candidates
+    (kept in global index order, so equal depths still break ties by
+    index), and the loss gradient is the sum of the tiles' gradients.
+    Returns (rgba (H,W,4), gradient dict) like render_and_grad."""
+    from . import I_PX0, I_PX1, I_PY0, I_PY1, all_pixels, preprocess
+    tw, th = tile
+    H, W = cam.height, cam.width
+    G = np.asarray(dL_dimage, np.float64).reshape(H, W, 4)
+    recs = preprocess(scene, cam, settings)
+    vis = np.nonzero(recs.visible)[0]
+    iv = recs.i[vis]
+    tx0, tx1 = iv[:, I_PX0] // tw, iv[:, I_PX1] // tw
+    ty0, ty1 = iv[:, I_PY0] // th, iv[:, I_PY1] // th
+    grads = {nm: np.zeros(np.asarray(a).shape) for nm, a in
+             zip(("means", "log_scales", "quats", "opacity_logits", "sh"),
+                 (scene.means, scene.log_scales, scene.quats, scene.opacity_logits, scene.sh))}
+    rgba = np.zeros((H, W, 4))
+    st = _settings(settings)
+    pix_all = all_pixels(cam).reshape(H, W, 2)
+    for ty in range(-(-H // th)):
+        for tx in range(-(-W // tw)):
+            ys, xs = slice(ty * th, min(H, (ty + 1) * th)), slice(tx * tw, min(W, (tx + 1) * tw))
+            pix = pix_all[ys, xs].reshape(-1, 2)
+            cand = vis[(tx0 <= tx) & (tx <= tx1) & (ty0 <= ty) & (ty <= ty1)]
+            if cand.size == 0:
+                rgba[ys, xs, :3] = st["bg"]
+                continue
+            sub = scene.subset(cand)
+            out, g = render_and_grad(sub, cam, pix, G[ys, xs].reshape(-1, 4), settings)
+            rgba[ys, xs] = out.reshape(ys.stop - ys.start, xs.stop - xs.start, 4)
+            for nm in grads:
+                np.add.at(grads[nm], cand, g[nm])
+    return rgba, grads

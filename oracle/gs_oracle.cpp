@@ -17,7 +17,11 @@
 //     covariance triangle (the pre-packed form of Section 3.4);
 //   * the per-pixel colour of Eq. 3 with the 2-D weight of Eq. 2, taken by
 //     brute force over every surviving Gaussian in ascending (depth, index)
-//     order -- no tiles, no sort keys;
+//     order -- no tiles, no sort keys -- and the same walk over per-tile
+//     candidate lists (orc_render_tiled), which is exactly equal and fast
+//     enough for whole 1080p frames; each pixel also reports the decisions
+//     its float64 walk took within a relative 1e-5 of a threshold and the
+//     jump that taking each of them the other way would cause;
 //   * the (tile, depth) key list and a library stable sort, for the sort
 //     contract;
 //   * the real SH basis of degree <= 3, exposed for its own pins.
@@ -63,7 +67,7 @@ enum RecD {
   D_OPAC = 15,                        // activated opacity
   D_C3 = 16,                          // world Sigma: xx xy xz yy yz zz (6)
   D_QMAX = 22,                        // 2 ln(o / tau)
-  D_TZ = 23,                          // camera-space z again (kept for margins)
+  D_ZSCALE = 23,                      // sum of the magnitudes of the depth's terms
   REC_D = 24
 };
 enum RecI {
@@ -170,6 +174,28 @@ bool finite_all(const double* v, int n) {
   return true;
 }
 
+// Pixels whose centres (i + 1/2, j + 1/2) lie in the bounding box of the
+// ellipse {x : (x - m)^T S^-1 (x - m) <= q} -- half-extents sqrt(q S00) and
+// sqrt(q S11) -- clipped to the image: box = (x0, x1, y0, y1), inclusive.
+// False when it holds no pixel centre.
+bool pixel_bbox(const double* d, double q, const Cam& cam, int* box) {
+  const double rx = std::sqrt(q * d[D_SA]), ry = std::sqrt(q * d[D_SC]);
+  const double mx = d[D_MX], my = d[D_MY];
+  double x0 = std::ceil(mx - rx - 0.5), x1 = std::floor(mx + rx - 0.5);
+  double y0 = std::ceil(my - ry - 0.5), y1 = std::floor(my + ry - 0.5);
+  x0 = std::max(x0, 0.0); y0 = std::max(y0, 0.0);
+  x1 = std::min(x1, (double)(cam.W - 1)); y1 = std::min(y1, (double)(cam.H - 1));
+  if (!(x0 <= x1 && y0 <= y1)) return false;
+  box[0] = (int)x0; box[1] = (int)x1; box[2] = (int)y0; box[3] = (int)y1;
+  return true;
+}
+
+void set_bbox(const int* box, const Set& set, int32_t* iv) {
+  iv[I_PX0] = box[0]; iv[I_PX1] = box[1]; iv[I_PY0] = box[2]; iv[I_PY1] = box[3];
+  iv[I_TX0] = box[0] / set.tw; iv[I_TX1] = box[1] / set.tw;
+  iv[I_TY0] = box[2] / set.th; iv[I_TY1] = box[3] / set.th;
+}
+
 // One Gaussian from its raw parameters: activations and the covariance
 // Sigma = R diag(s^2) R^T (Algorithm 1, CovFromScaleRot; Section 3.2), then
 // the common projection below.  Real is float (the library's input type)
@@ -216,7 +242,18 @@ void project_gaussian(const double* mu, double o, const double* Sig, const ShT* 
   for (int r = 0; r < 3; ++r)
     t[r] = V[4 * r] * muw[0] + V[4 * r + 1] * muw[1] + V[4 * r + 2] * muw[2] + V[4 * r + 3];
   d[D_DEPTH] = t[2];
-  d[D_TZ] = t[2];
+  // A float32 evaluation of t_z is within a few units in the last place of
+  // the sum of its terms' magnitudes; two depths closer than that may be
+  // ordered either way by a float32 computation.
+  {
+    double zs = std::fabs(V[11]);
+    for (int c = 0; c < 3; ++c) {
+      double w = std::fabs(tk[c]);
+      for (int k = 0; k < 3; ++k) w += std::fabs(A[3 * c + k] * mu[k]);
+      zs += std::fabs(V[8 + c]) * w;
+    }
+    d[D_ZSCALE] = zs;
+  }
   int cull = C_VISIBLE;
   bool ambiguous = false;
   if (!(t[2] > cam.znear)) {
@@ -288,30 +325,33 @@ void project_gaussian(const double* mu, double o, const double* Sig, const ShT* 
   // Exact bbox of the ellipse {x : (x-m)^T S^-1 (x-m) <= 2 ln(o/tau)}: outside
   // it every pixel weight is below tau.  Pixel centres sit at +1/2.
   const bool have_shape = (t[2] > 0.0) && d[D_CA] != 0.0;
+  int box[4];
   if (have_shape) {
-    double qmax = 2.0 * std::log(o / set.tau);
-    if (ambiguous && qmax <= 0.0) qmax = 1e-6;  // keep a footprint for margin checks
+    const double qmax = 2.0 * std::log(o / set.tau);
     d[D_QMAX] = qmax;
-    if (qmax > 0.0) {
-      const double rx = std::sqrt(qmax * d[D_SA]), ry = std::sqrt(qmax * d[D_SC]);
-      const double mx = d[D_MX], my = d[D_MY];
-      double fx0 = std::ceil(mx - rx - 0.5), fx1 = std::floor(mx + rx - 0.5);
-      double fy0 = std::ceil(my - ry - 0.5), fy1 = std::floor(my + ry - 0.5);
-      fx0 = std::max(fx0, 0.0); fy0 = std::max(fy0, 0.0);
-      fx1 = std::min(fx1, (double)(cam.W - 1)); fy1 = std::min(fy1, (double)(cam.H - 1));
-      if (fx0 <= fx1 && fy0 <= fy1) {
-        iv[I_PX0] = (int)fx0; iv[I_PX1] = (int)fx1; iv[I_PY0] = (int)fy0; iv[I_PY1] = (int)fy1;
-        iv[I_TX0] = iv[I_PX0] / set.tw; iv[I_TX1] = iv[I_PX1] / set.tw;
-        iv[I_TY0] = iv[I_PY0] / set.th; iv[I_TY1] = iv[I_PY1] / set.th;
-      } else if (cull == C_VISIBLE) {
+    if (cull == C_VISIBLE) {
+      if (!(qmax > 0.0)) {
+        cull = C_OPACITY;
+      } else if (pixel_bbox(d, qmax, cam, box)) {
+        set_bbox(box, set, iv);
+      } else {
         cull = C_OFFIMAGE;
+        // the support misses every pixel centre; it is a near decision when
+        // the region where the weight reaches tau (1 - 1e-5) does not
+        ambiguous = true;
       }
-    } else if (cull == C_VISIBLE) {
-      cull = C_OPACITY;
+    }
+    // A culled Gaussian counts as ambiguous when some pixel centre sees a
+    // weight within a relative 1e-5 of tau, were it kept; its bbox is then
+    // that region's.
+    if (cull != C_VISIBLE && ambiguous) {
+      const double qn = 2.0 * std::log(o / (set.tau * (1.0 - 1e-5)));
+      if (qn > 0.0 && pixel_bbox(d, qn, cam, box)) set_bbox(box, set, iv);
+      else ambiguous = false;
     }
   }
   iv[I_CULL] = cull;
-  iv[I_AMBIG] = (cull != C_VISIBLE && ambiguous && iv[I_PX1] >= iv[I_PX0]) ? 1 : 0;
+  iv[I_AMBIG] = (cull != C_VISIBLE && ambiguous) ? 1 : 0;
   if (cull == C_VISIBLE)
     iv[I_TILES] = (iv[I_TX1] - iv[I_TX0] + 1) * (iv[I_TY1] - iv[I_TY0] + 1);
 }
@@ -376,6 +416,169 @@ inline double pixel_weight(const double* d, double px, double py) {
   const double dx = px - d[D_MX], dy = py - d[D_MY];
   const double Q = d[D_CA] * dx * dx + 2.0 * d[D_CB] * dx * dy + d[D_CC] * dy * dy;
   return d[D_OPAC] * std::exp(-0.5 * Q);
+}
+
+// ---------------------------------------------------------------------------
+// Per-pixel compositing, Eqs. 2-3.  A pixel walks its candidates -- the
+// visible Gaussians and the ambiguous culled ones -- in ascending (depth,
+// index) order: alpha = min(alpha_max, o exp(-Q/2)); a weight below tau is
+// skipped; C += T alpha rgb; T *= 1 - alpha; the walk stops once T < t_eps.
+//
+// Tolerance protocol.  The GPU computes in float32, so it may take a
+// discrete decision the other way where the float64 value lies within a
+// relative 1e-5 of the threshold (a "near" decision): the skip (weight vs
+// tau), the stop (T vs t_eps), the order of two blended Gaussians whose
+// depths agree within float32 rounding of their terms, keeping a Gaussian culled within 1e-5
+// of a threshold, and the mesh depth test.  The walk records each near
+// decision; the pixel's jump is the sum, over its near decisions, of the
+// largest change of any output channel when that one decision is taken the
+// other way (the pixel re-walked with it forced).
+
+constexpr double kNearRel = 1e-5;  // relative margin below which a decision is near
+// Two depths are a near tie when they differ by at most 2^-21 times the sum
+// of their error scales (D_ZSCALE): eight float32 units of rounding.
+constexpr double kTieScale = 1.0 / 2097152.0;
+constexpr int kMaxNear = 64;       // more near decisions: the jump is not bounded
+
+struct Cand {
+  int64_t idx;  // Gaussian
+  bool ambig;   // culled within a relative 1e-5 of a threshold
+};
+
+enum NearKind { N_TAKE = 1, N_STOP = 2, N_SWAP = 3, N_INCLUDE = 4, N_HIDE = 5 };
+
+struct Near {
+  int kind;
+  int64_t k, k2;  // walk positions (k2: the other Gaussian of a swap)
+};
+
+struct WalkOut {
+  double C[3], T, mrg;
+  int32_t nb, fl;
+  std::vector<Near> near;
+};
+
+// One walk over the candidate list L (in walk order).  `force` (or NULL)
+// takes one decision the other way; only the unforced walk records margins,
+// flags and near decisions.  D is the pixel's mesh depth (+inf: none).
+void walk_pixel(const std::vector<Cand>& L, const double* rec_d, const Set& set,
+                double px, double py, double D, const Near* force, WalkOut& o) {
+  const bool rec = force == nullptr;
+  o.C[0] = o.C[1] = o.C[2] = 0.0;
+  o.T = 1.0;
+  o.mrg = 1.0;
+  o.nb = 0;
+  o.fl = 0;
+  o.near.clear();
+  int64_t prev = -1;
+  double prev_depth = 0.0, prev_scale = 0.0;
+  const int64_t n = (int64_t)L.size();
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t at = k;  // the swap force exchanges two positions of the walk
+    if (force && force->kind == N_SWAP) {
+      if (k == force->k) at = force->k2;
+      else if (k == force->k2) at = force->k;
+    }
+    const bool forced = force && force->kind != N_SWAP && force->k == k;
+    const Cand& c = L[(size_t)at];
+    const double* d = rec_d + (size_t)c.idx * REC_D;
+    const double g = pixel_weight(d, px, py);
+    const double depth = d[D_DEPTH];
+    if (std::isfinite(D)) {
+      // mesh depth test: hidden when deeper than the mesh, and so is every
+      // Gaussian after it in depth order
+      bool hidden = depth > D;
+      if (rec && g >= set.tau && std::fabs(depth - D) <= kNearRel * std::fabs(D)) {
+        o.fl |= 4;
+        o.near.push_back({N_HIDE, k, -1});
+      }
+      if (forced && force->kind == N_HIDE) hidden = !hidden;
+      if (hidden) break;
+    }
+    bool take;
+    if (c.ambig) {
+      // culled, but kept by a float32 computation it would be blended where
+      // its weight reaches tau within the near band
+      const bool could = g >= set.tau * (1.0 - kNearRel);
+      if (rec && could) {
+        o.fl |= 2;
+        o.mrg = 0.0;
+        o.near.push_back({N_INCLUDE, k, -1});
+      }
+      take = forced && force->kind == N_INCLUDE && could;
+    } else {
+      const double m = std::fabs(g - set.tau) / set.tau;
+      if (rec) {
+        o.mrg = std::min(o.mrg, m);
+        if (m < kNearRel) o.near.push_back({N_TAKE, k, -1});
+      }
+      take = g >= set.tau;
+      if (forced && force->kind == N_TAKE) take = !take;
+    }
+    if (!take) continue;
+    if (rec) o.mrg = std::min(o.mrg, std::fabs(g - set.amax) / set.amax);
+    const double a = std::min(set.amax, g);
+    for (int ch = 0; ch < 3; ++ch) o.C[ch] += o.T * a * d[D_R + ch];
+    o.T *= (1.0 - a);
+    ++o.nb;
+    if (rec && prev >= 0 &&
+        std::fabs(depth - prev_depth) <= kTieScale * (d[D_ZSCALE] + prev_scale)) {
+      o.fl |= 1;
+      o.near.push_back({N_SWAP, prev, k});
+    }
+    prev = k;
+    prev_depth = depth;
+    prev_scale = d[D_ZSCALE];
+    const double m3 = std::fabs(o.T - set.teps) / set.teps;
+    if (rec) {
+      o.mrg = std::min(o.mrg, m3);
+      if (m3 < kNearRel) o.near.push_back({N_STOP, k, -1});
+    }
+    bool stop = o.T < set.teps;
+    if (forced && force->kind == N_STOP) stop = !stop;
+    if (stop) break;
+  }
+}
+
+// The outputs of one pixel from its candidate list: rgba = (C + T B, 1 - T)
+// with B the background (or the mesh colour), T, the blend count, margin,
+// flags and jump (see above; +inf when more than kMaxNear near decisions).
+void composite_pixel(const std::vector<Cand>& L, const double* rec_d, const Set& set,
+                     double px, double py, double D, const double* B, double* rgba,
+                     double* T_out, int32_t* nb, double* margin, int32_t* flags,
+                     double* jump) {
+  WalkOut base, alt;
+  walk_pixel(L, rec_d, set, px, py, D, nullptr, base);
+  for (int ch = 0; ch < 3; ++ch) rgba[ch] = base.C[ch] + base.T * B[ch];
+  rgba[3] = 1.0 - base.T;
+  *T_out = base.T;
+  *nb = base.nb;
+  *margin = base.mrg;
+  *flags = base.fl;
+  if (!jump) return;
+  if ((int)base.near.size() > kMaxNear) {
+    *jump = std::numeric_limits<double>::infinity();
+    return;
+  }
+  double J = 0.0;
+  for (const Near& nd : base.near) {
+    walk_pixel(L, rec_d, set, px, py, D, &nd, alt);
+    double m = std::fabs(alt.T - base.T);
+    for (int ch = 0; ch < 3; ++ch)
+      m = std::max(m, std::fabs((alt.C[ch] + alt.T * B[ch]) - rgba[ch]));
+    J += m;
+  }
+  *jump = J;
+}
+
+// Candidates in walk order: ascending depth, then index.
+void sort_walk_order(std::vector<Cand>& L, const double* rec_d) {
+  std::sort(L.begin(), L.end(), [&](const Cand& a, const Cand& b) {
+    const double da = rec_d[(size_t)a.idx * REC_D + D_DEPTH];
+    const double db = rec_d[(size_t)b.idx * REC_D + D_DEPTH];
+    if (da != db) return da < db;
+    return a.idx < b.idx;
+  });
 }
 
 }  // namespace
@@ -449,15 +652,20 @@ int orc_preprocess_cov(int64_t n, const double* means, const double* opac, const
   return 0;
 }
 
-// Eq. 3 by brute force at npix pixels (x, y pairs).  Every visible Gaussian
-// is visited in ascending (depth, index) order.
+// Eq. 3 by brute force at npix pixels (x, y pairs): every pixel walks every
+// visible Gaussian (and every ambiguous culled one) in ascending (depth,
+// index) order.
 // Outputs per pixel: rgba (4), final transmittance T, number of blended
 // Gaussians, the smallest relative margin to any discrete decision taken
-// (pixel skip alpha<tau, clamp at alpha_max, stop at T<t_eps), and flags:
-//   1 = two blended Gaussians closer in depth than a relative 1e-6;
-//   2 = a Gaussian culled within a relative 1e-5 of a threshold covers it;
+// (skip at tau, clamp at alpha_max, stop at t_eps; capped at 1), flags:
+//   1 = two blended Gaussians whose depths agree within float32 rounding
+//       (a near tie, see kTieScale);
+//   2 = a Gaussian culled within a relative 1e-5 of a threshold would reach
+//       tau within that band here;
 //   4 = a Gaussian with weight >= tau lies within a relative 1e-5 of the
-//       mesh depth.
+//       mesh depth;
+// and, if `jump` is not NULL, the jump the pixel's near decisions straddle
+// (see walk_pixel).
 // Mesh depth composition (Algorithm 1, DrawSplatsWithMeshDepth; Section
 // 3.4): with mesh_depth (one value per requested pixel, camera-space z of
 // the mesh surface; +inf where there is none), a Gaussian whose depth is
@@ -469,61 +677,78 @@ int orc_render_pixels(int64_t n, const double* rec_d, const int32_t* rec_i,
                       const double* cam_in, const double* set_in, int64_t npix,
                       const int32_t* pix, const double* mesh_depth, const double* mesh_rgb,
                       double* rgba, double* T_out, int32_t* n_blend, double* margin,
-                      int32_t* flags) {
+                      int32_t* flags, double* jump) {
   const Cam cam = load_cam(cam_in);
   const Set set = load_set(set_in);
-  std::vector<int64_t> order;
-  std::vector<int64_t> ambig;
-  order.reserve((size_t)n);
+  (void)cam;
+  std::vector<Cand> L;
   for (int64_t i = 0; i < n; ++i) {
-    if (rec_i[(size_t)i * REC_I + I_CULL] == C_VISIBLE) order.push_back(i);
-    else if (rec_i[(size_t)i * REC_I + I_AMBIG]) ambig.push_back(i);
+    const int32_t* iv = rec_i + (size_t)i * REC_I;
+    if (iv[I_CULL] == C_VISIBLE) L.push_back({i, false});
+    else if (iv[I_AMBIG]) L.push_back({i, true});
   }
-  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-    const double da = rec_d[(size_t)a * REC_D + D_DEPTH], db = rec_d[(size_t)b * REC_D + D_DEPTH];
-    if (da != db) return da < db;
-    return a < b;
-  });
+  sort_walk_order(L, rec_d);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t p = 0; p < npix; ++p) {
-    const int x = pix[2 * p], y = pix[2 * p + 1];
-    const double px = x + 0.5, py = y + 0.5;
-    double C[3] = {0, 0, 0}, T = 1.0, mrg = std::numeric_limits<double>::infinity();
-    int32_t nb = 0, fl = 0;
-    double last_depth = -1.0;
     const double D = mesh_depth ? mesh_depth[p] : std::numeric_limits<double>::infinity();
-    for (int64_t idx : order) {
-      const double* d = rec_d + (size_t)idx * REC_D;
-      const double g = pixel_weight(d, px, py);
-      if (std::isfinite(D) && g >= set.tau && std::fabs(d[D_DEPTH] - D) <= 1e-5 * std::fabs(D))
-        fl |= 4;
-      if (d[D_DEPTH] > D) break;  // hidden by the mesh, as is everything behind
-      mrg = std::min(mrg, std::fabs(g - set.tau) / set.tau);
-      if (g < set.tau) continue;
-      mrg = std::min(mrg, std::fabs(g - set.amax) / set.amax);
-      const double a = std::min(set.amax, g);
-      for (int c = 0; c < 3; ++c) C[c] += T * a * d[D_R + c];
-      T *= (1.0 - a);
-      ++nb;
-      if (last_depth >= 0.0 && std::fabs(d[D_DEPTH] - last_depth) <= 1e-6 * d[D_DEPTH]) fl |= 1;
-      last_depth = d[D_DEPTH];
-      mrg = std::min(mrg, std::fabs(T - set.teps) / set.teps);
-      if (T < set.teps) break;
-    }
-    for (int64_t idx : ambig) {
-      const int32_t* iv = rec_i + (size_t)idx * REC_I;
-      if (x >= iv[I_PX0] && x <= iv[I_PX1] && y >= iv[I_PY0] && y <= iv[I_PY1]) {
-        fl |= 2;
-        mrg = 0.0;
-      }
-    }
-    for (int c = 0; c < 3; ++c)
-      rgba[4 * p + c] = C[c] + T * (mesh_rgb ? mesh_rgb[3 * p + c] : set.bg[c]);
-    rgba[4 * p + 3] = 1.0 - T;
-    T_out[p] = T;
-    n_blend[p] = nb;
-    margin[p] = mrg;
-    flags[p] = fl;
+    composite_pixel(L, rec_d, set, pix[2 * p] + 0.5, pix[2 * p + 1] + 0.5, D,
+                    mesh_rgb ? mesh_rgb + 3 * p : set.bg, rgba + 4 * p, T_out + p, n_blend + p,
+                    margin + p, flags + p, jump ? jump + p : nullptr);
+  }
+  return 0;
+}
+
+// Eq. 3 by tiles: the same per-pixel walk over a shorter candidate list.
+// Each visible or ambiguous Gaussian is listed in every tile (set.tw x
+// set.th pixels) that its bounding box of {weight >= tau (1 - 1e-3)}
+// overlaps; a tile's list is in ascending (depth, index) order.  A Gaussian
+// missing from a pixel's list has weight below tau (1 - 1e-3) there, so the
+// walk skips it in the brute-force list too, and it could only raise the
+// margin above 1e-3: rgba, T, blend counts, flags and jumps equal the
+// brute-force ones exactly, and margins equal them wherever either is below
+// 1e-3.  Same arguments and outputs as orc_render_pixels.
+int orc_render_tiled(int64_t n, const double* rec_d, const int32_t* rec_i,
+                     const double* cam_in, const double* set_in, int64_t npix,
+                     const int32_t* pix, const double* mesh_depth, const double* mesh_rgb,
+                     double* rgba, double* T_out, int32_t* n_blend, double* margin,
+                     int32_t* flags, double* jump) {
+  const Cam cam = load_cam(cam_in);
+  const Set set = load_set(set_in);
+  const int tiles_x = (cam.W + set.tw - 1) / set.tw;
+  const int tiles_y = (cam.H + set.th - 1) / set.th;
+  const int64_t tiles = (int64_t)tiles_x * tiles_y;
+  // tile rect of each candidate's listing bbox (empty: not listed)
+  std::vector<int32_t> rect((size_t)n * 4, -1);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t* iv = rec_i + (size_t)i * REC_I;
+    if (iv[I_CULL] != C_VISIBLE && !iv[I_AMBIG]) continue;
+    const double* d = rec_d + (size_t)i * REC_D;
+    const double q = 2.0 * std::log(d[D_OPAC] / (set.tau * (1.0 - 1e-3)));
+    int box[4];
+    if (!(q > 0.0) || !pixel_bbox(d, q, cam, box)) continue;
+    int32_t* r = rect.data() + 4 * i;
+    r[0] = box[0] / set.tw; r[1] = box[1] / set.tw;
+    r[2] = box[2] / set.th; r[3] = box[3] / set.th;
+  }
+  std::vector<std::vector<Cand>> lists((size_t)tiles);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t* r = rect.data() + 4 * i;
+    if (r[0] < 0) continue;
+    const bool amb = rec_i[(size_t)i * REC_I + I_CULL] != C_VISIBLE;
+    for (int ty = r[2]; ty <= r[3]; ++ty)
+      for (int tx = r[0]; tx <= r[1]; ++tx) lists[(size_t)ty * tiles_x + tx].push_back({i, amb});
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t t = 0; t < tiles; ++t) sort_walk_order(lists[(size_t)t], rec_d);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t p = 0; p < npix; ++p) {
+    const int x = pix[2 * p], y = pix[2 * p + 1];
+    const double D = mesh_depth ? mesh_depth[p] : std::numeric_limits<double>::infinity();
+    const std::vector<Cand>& L = lists[(size_t)(y / set.th) * tiles_x + x / set.tw];
+    composite_pixel(L, rec_d, set, x + 0.5, y + 0.5, D, mesh_rgb ? mesh_rgb + 3 * p : set.bg,
+                    rgba + 4 * p, T_out + p, n_blend + p, margin + p, flags + p,
+                    jump ? jump + p : nullptr);
   }
   return 0;
 }
@@ -602,6 +827,14 @@ int orc_num_threads(void) {
 #else
   return 1;
 #endif
+}
+
+// Number of OpenMP threads later calls use (for timing on one core).
+int orc_set_num_threads(int k) {
+#ifdef _OPENMP
+  if (k > 0) omp_set_num_threads(k);
+#endif
+  return 0;
 }
 
 }  // extern "C"

@@ -45,25 +45,69 @@ def print_case(msg):
     print(f"[gpu case] {msg}", flush=True)
 
 
-def image_check(gpu_rgba, ref, tol=1e-4, flagged_tol=2e-2):
-    """Compare a GPU image (P,4) to oracle outputs at the same pixels.
+def image_check(gpu_rgba, ref, tol=1e-4, max_flagged=0.08, max_loosened=0.01, T=None):
+    """Compare a GPU image (P,4) to oracle outputs at the same pixels, by the
+    tolerance protocol.
 
-    Unflagged pixels (decision margin >= 1e-5, no depth tie, no ambiguous
-    cull) must be within `tol`; flagged ones within the jump they straddle
-    (bounded by `flagged_tol`).  Returns (max err unflagged, n flagged)."""
+    Unflagged pixels (every decision margin >= 1e-5, no depth near-tie, no
+    ambiguous cull, no near mesh test) must be within `tol` on RGB and A.
+    A flagged pixel must be within `tol` plus the jump its near decisions
+    straddle (the oracle re-walks each of them taken the other way).  At most
+    `max_flagged` of the pixels may be flagged, and at most `max_loosened`
+    may have a jump above `tol`.  With `T` (the GPU's final transmittance at
+    the same pixels) the same bounds hold for T.
+    Returns (max err unflagged, n flagged, n loosened)."""
     err = np.abs(gpu_rgba.astype(np.float64) - ref["rgba"]).max(1)
     flagged = (ref["margin"] < 1e-5) | (ref["flags"] != 0)
-    e_ok = err[~flagged].max() if (~flagged).any() else 0.0
-    assert e_ok <= tol, (e_ok, np.argmax(np.where(flagged, 0, err)))
-    if flagged.any():
-        assert err[flagged].max() <= flagged_tol, err[flagged].max()
-    return e_ok, int(flagged.sum())
+    jump = np.where(flagged, ref["jump"], 0.0)
+    assert np.isfinite(jump).all(), "a pixel with more near decisions than the oracle bounds"
+    bad = err > tol + jump
+    assert not bad.any(), (
+        f"{int(bad.sum())} pixels beyond tol + jump; worst: index {int(np.argmax(err - jump))}, "
+        f"err {float((err - jump).max()):.3e} over the allowance, flagged {bool(flagged[np.argmax(err - jump)])}")
+    if T is not None:
+        eT = np.abs(np.asarray(T, np.float64) - ref["T"])
+        assert not (eT > tol + jump).any(), float((eT - jump).max())
+    n = err.size
+    nf, nl = int(flagged.sum()), int((jump > tol).sum())
+    assert nf <= max_flagged * n, (nf, n)
+    assert nl <= max_loosened * n, (nl, n)
+    e_ok = float(err[~flagged].max()) if (~flagged).any() else 0.0
+    return e_ok, nf, nl
+
+
+def rect_pairs(px0, px1, py0, py1, idx, tw, th, tiles_x):
+    """(Gaussian, tile) pairs of pixel bboxes in tiles of tw x th: every
+    tile of each rect, as int64 codes gaussian * 2^32 + tile."""
+    tx0, tx1 = px0 // tw, px1 // tw
+    ty0, ty1 = py0 // th, py1 // th
+    w = (tx1 - tx0 + 1).astype(np.int64)
+    h = (ty1 - ty0 + 1).astype(np.int64)
+    cnt = w * h
+    rep = np.repeat(np.arange(idx.size), cnt)
+    local = np.arange(int(cnt.sum()), dtype=np.int64) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    ty = ty0[rep].astype(np.int64) + local // w[rep]
+    tx = tx0[rep].astype(np.int64) + local % w[rep]
+    return (idx[rep].astype(np.int64) << 32) | (ty * tiles_x + tx)
+
+
+def assert_pairs_harmless(orc, ref, cam, codes, tile=(16, 16)):
+    """Every (Gaussian, tile) pair in `codes` has weight below alpha_min at
+    every pixel centre of the tile (the oracle's exact maximum): the pair
+    cannot change any pixel."""
+    if codes.size == 0:
+        return 0
+    g = (codes >> 32).astype(np.uint32)
+    t = (codes & 0xFFFFFFFF).astype(np.uint32)
+    w = orc.pair_max_weight(ref, cam, g, t, dict(tile_w=tile[0], tile_h=tile[1]))
+    assert w.max() < (1.0 / 255.0), (float(w.max()), int(g[np.argmax(w)]))
+    return int(codes.size)
 
 
 def compare_records(orc, rec, ref, cam):
     """GPU per-Gaussian records vs oracle records (Eq. 1, colour, culls)."""
     vis_o = ref.visible
-    vis_g = rec["tx1"] >= rec["tx0"]
+    vis_g = rec["px1"] >= rec["px0"]
     amb = ref.i[:, orc.I_AMBIG] == 1
     # The GPU widens the opacity-aware bbox by a rounding margin, so a
     # Gaussian whose exact footprint holds no pixel centre can keep a
@@ -71,16 +115,11 @@ def compare_records(orc, rec, ref, cam):
     # weight below alpha_min (compositing then skips it everywhere).
     kept = vis_g & ~vis_o & ~amb & (ref.i[:, orc.I_CULL] == orc.C_OFFIMAGE)
     if kept.any():
-        tx_n = (cam.width + 15) // 16
-        gs, tiles = [], []
-        for g in np.nonzero(kept)[0]:
-            a = rec[g]
-            for ty in range(a["ty0"], a["ty1"] + 1):
-                for tx in range(a["tx0"], a["tx1"] + 1):
-                    gs.append(g)
-                    tiles.append(ty * tx_n + tx)
-        w = orc.pair_max_weight(ref, cam, np.array(gs), np.array(tiles))
-        assert w.max() < (1.0 / 255.0) * (1 + 1e-5), w.max()
+        k = np.nonzero(kept)[0]
+        r = rec[k]
+        tiles_x = (cam.width + 15) // 16
+        assert_pairs_harmless(orc, ref, cam, rect_pairs(r["px0"], r["px1"], r["py0"], r["py1"],
+                                                        k, 16, 16, tiles_x))
     mismatch = (vis_o != vis_g) & ~amb & ~kept
     assert not mismatch.any(), np.nonzero(mismatch)[0][:10]
     v = vis_o & vis_g
@@ -95,30 +134,49 @@ def compare_records(orc, rec, ref, cam):
     ref_con = d[:, orc.D_CA:orc.D_CC + 1]
     scale = np.abs(ref_con).max(1, keepdims=True)
     np.testing.assert_allclose(con / scale, ref_con / scale, atol=2e-5)
-    # pixel bboxes and tile rects: the GPU's may only be larger, by pixels
-    # and tiles that hold no pixel with weight >= alpha_min
+    # pixel bboxes: the GPU's may only be larger, by pixels that hold no
+    # weight >= alpha_min (extra_pairs_harmless checks the tiles)
     it = ref.i[v]
     assert np.all(r["px0"] <= it[:, orc.I_PX0]) and np.all(r["px1"] >= it[:, orc.I_PX1])
     assert np.all(r["py0"] <= it[:, orc.I_PY0]) and np.all(r["py1"] >= it[:, orc.I_PY1])
-    assert np.all(r["tx0"] <= it[:, orc.I_TX0]) and np.all(r["tx1"] >= it[:, orc.I_TX1])
-    assert np.all(r["ty0"] <= it[:, orc.I_TY0]) and np.all(r["ty1"] >= it[:, orc.I_TY1])
     return v
 
 
+def pair_set_check(orc, ref, rec, cam, v, tile=(16, 16)):
+    """The GPU's (Gaussian, tile) pairs of the Gaussians in `v` (from its
+    pixel bboxes) against the oracle's exact rects in tiles of `tile`:
+    every oracle pair is present, and every extra GPU pair is harmless.
+    Returns (oracle pairs, extra pairs)."""
+    tw, th = tile
+    tiles_x = -(-cam.width // tw)
+    idx = np.nonzero(v)[0]
+    r, it = rec[idx], ref.i[idx]
+    g = rect_pairs(r["px0"], r["px1"], r["py0"], r["py1"], idx, tw, th, tiles_x)
+    o = rect_pairs(it[:, orc.I_PX0], it[:, orc.I_PX1], it[:, orc.I_PY0], it[:, orc.I_PY1],
+                   idx, tw, th, tiles_x)
+    missing = np.setdiff1d(o, g, assume_unique=True)
+    assert missing.size == 0, missing[:5]
+    extra = np.setdiff1d(g, o, assume_unique=True)
+    assert_pairs_harmless(orc, ref, cam, extra, tile)
+    return int(o.size), int(extra.size)
+
+
 def extra_pairs_harmless(orc, ref, rec, cam, v):
-    tx_n = (cam.width + 15) // 16
-    gs, tiles = [], []
-    for g in np.nonzero(v)[0]:
-        a, b = rec[g], ref.i[g]
-        for ty in range(a["ty0"], a["ty1"] + 1):
-            for tx in range(a["tx0"], a["tx1"] + 1):
-                if not (b[orc.I_TX0] <= tx <= b[orc.I_TX1] and b[orc.I_TY0] <= ty <= b[orc.I_TY1]):
-                    gs.append(g)
-                    tiles.append(ty * tx_n + tx)
-    if gs:
-        w = orc.pair_max_weight(ref, cam, np.array(gs), np.array(tiles))
-        assert w.max() < (1.0 / 255.0) * (1 + 1e-5)
-    return len(gs)
+    return pair_set_check(orc, ref, rec, cam, v)[1]
+
+
+_SCENES = {}
+
+
+def scene_cached(name):
+    """The full-size medium (1M, view 0) or large (6M) scene and camera,
+    generated once per test process (read-only: do not modify)."""
+    from paper_2512_08478_amd import scenes as S
+    if name not in _SCENES:
+        if len(_SCENES) >= 2:
+            _SCENES.clear()
+        _SCENES[name] = {"medium": S.medium_scene, "large": S.large_scene}[name]()
+    return _SCENES[name]
 
 
 def sampled_pixels(cam, n, seed):

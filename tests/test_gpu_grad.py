@@ -70,6 +70,31 @@ def test_backward_diff_scene_sampled(R, orc):
         assert e <= 1e-3, (nm, e)
 
 
+def test_backward_dense_upstream(R, orc):
+    """Every pixel of a 256x256 frame of 50k Gaussians carries an upstream
+    gradient (except the few whose decisions are near a threshold, where
+    the gradient is not defined): many pixels accumulate into each Gaussian
+    through the backward's atomics.  Against the per-tile FP64 autograd
+    oracle (equal to autograd of the whole image)."""
+    print_case("backward 50k 256x256, dense upstream gradient")
+    from oracle import grad as og
+    sc, cam = S.diff_scene(n=50_000, size=256)
+    ref = orc.render_image(orc.preprocess(sc, cam), cam, tiled=True)
+    rng = np.random.default_rng(12)
+    G = rng.standard_normal((cam.height, cam.width, 4))
+    near = (ref["margin"] < 1e-4) | (ref["flags"] != 0)
+    G[near] = 0.0
+    assert near.mean() < 0.06
+    fr, g = gpu_grads(R, sc, cam, G)
+    rgba, g_ref = og.render_and_grad_tiled(sc, cam, G, tile=(32, 32))
+    np.testing.assert_allclose(rgba, ref["rgba"], rtol=0, atol=1e-12)
+    for nm in NAMES:
+        e = rel_l2(g[nm], g_ref[nm])
+        rows = np.count_nonzero(np.abs(g_ref[nm]).reshape(sc.n, -1).sum(1))
+        print(f"{nm}: rel L2 {e:.2e}, Gaussians with a gradient {rows}")
+        assert e <= 1e-3, (nm, e)
+
+
 def test_autograd_function_l1(R):
     print_case("torch.autograd.Function with an L1 loss")
     from paper_2512_08478_amd.render import GaussianParams, render

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 from paper_2512_08478_amd import scenes as S
-from gpu_util import image_check, near_tie, print_case, sampled_pixels
+from gpu_util import image_check, near_tie, print_case, sampled_pixels, scene_cached
 
 pytestmark = pytest.mark.gpu
 
@@ -96,13 +96,44 @@ def test_lbs_index_past_last_joint_contributes_nothing(R, orc):
 
 @pytest.mark.parametrize("n", [20_000, 1_000_000])
 def test_lbs_posed_frame_vs_oracle(R, orc, n):
+    # camera in general position (binary16 means seen along an axis give
+    # exactly equal depths; see the packed end-to-end test)
     print_case(f"lbs posed frame, {n} Gaussians, 1920x1080, sampled pixels")
-    sc, cam, canon, (di, dw, dj), _ = avatar(n, R=R)
+    sc, _, canon, (di, dw, dj), _ = avatar(n, R=R)
+    cam = S.pinhole_camera(S.look_at((2.3, 1.7, -8.1)), 1920, 1080, 60.0)
     out = R.lbs_deform(canon, di, dw, dj)
     fr = R.forward(out, cam)
     img = fr.image.cpu().numpy()
     pix = sampled_pixels(cam, 256, 23)
     ref = orc.render_pixels(orc.preprocess_packed(decoded(out), cam), cam, pix)
-    e, nflag = image_check(img[pix[:, 1], pix[:, 0]], ref)
+    e, nflag, _ = image_check(img[pix[:, 1], pix[:, 0]], ref, max_flagged=0.15, max_loosened=0.05)
     assert ref["rgba"][:, 3].max() > 0.1
     print(f"posed max err {e:.2e}, flagged {nflag}")
+
+
+def test_lbs_posed_frame_end_to_end(R, orc):
+    """The avatar frame, every pixel, against the oracle's own chain:
+    oracle pre-pack -> oracle skinning (Eqs. 5-6, float64, one rounding) ->
+    projection from the posed packed values -> tiled Eq. 3.  The GPU's
+    posed bits must equal the oracle's.  Camera in general position (see
+    the packed end-to-end test)."""
+    print_case("lbs posed 1M frame end to end, whole image")
+    from paper_2512_08478_amd.render import GaussianParams
+    sc, _ = scene_cached("medium")
+    cam = S.pinhole_camera(S.look_at((2.3, 1.7, -8.1)), 1920, 1080, 60.0)
+    centres, idx, w = S.skinning(sc.means, n_joints=55, seed=0)
+    joints = S.joint_pose(centres, seed=1)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    canon = R.prepack(GaussianParams.from_scene(sc))
+    out = R.lbs_deform(canon, dev(idx), dev(w), dev(joints))
+    fr = R.forward(out, cam)
+    img = fr.image.cpu().numpy().reshape(-1, 4)
+    posed = orc.lbs_deform(orc.prepack(sc), idx, w, joints)
+    got = decoded(out)
+    for k in ("means", "opacity", "cov6", "sh"):
+        a = np.asarray(got[k]).reshape(-1).view(np.uint16)
+        b = np.asarray(posed[k]).reshape(-1).view(np.uint16)
+        assert np.array_equal(a, b), (k, int((a != b).sum()))
+    ref = orc.render_pixels(orc.preprocess_packed(posed, cam), cam, orc.all_pixels(cam), tiled=True)
+    e, nflag, nloose = image_check(img, ref, T=fr.T_final.cpu().numpy().reshape(-1))
+    print(f"avatar end to end: max err {e:.2e}, flagged {nflag}, jump above 1e-4 {nloose}")

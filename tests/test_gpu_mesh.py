@@ -46,13 +46,13 @@ def test_mesh_tiny_whole_image(R, orc):
     img = fr.image.cpu().numpy().reshape(-1, 4)
     ref = orc.render_image(rec, cam, mesh=mesh)
     flat = {k: v.reshape(-1, 4) if k == "rgba" else v.reshape(-1) for k, v in ref.items()}
-    e, nflag = image_check(img, flat)
+    e, nflag, nloose = image_check(img, flat, max_flagged=0.01, max_loosened=0.005,
+                                   T=fr.T_final.cpu().numpy().reshape(-1))
     plain = orc.render_image(rec, cam)
     hidden = int((plain["n_blend"] > ref["n_blend"]).sum())
-    print(f"tiny mesh max err {e:.2e}, flagged {nflag}, pixels with hidden splats {hidden}")
+    print(f"tiny mesh max err {e:.2e}, flagged {nflag}, jump above 1e-4 {nloose}, "
+          f"pixels with hidden splats {hidden}")
     assert hidden > 1000
-    ok = (flat["margin"] >= 1e-5) & (flat["flags"] == 0)
-    np.testing.assert_allclose(fr.T_final.cpu().numpy().reshape(-1)[ok], flat["T"][ok], atol=1e-4)
 
 
 def test_mesh_absent_is_bitwise_plain(R):
@@ -71,24 +71,25 @@ def test_mesh_absent_is_bitwise_plain(R):
 
 
 @pytest.mark.parametrize("shape", [(16, 16, 8), (32, 16, 7), (8, 8, 8)])
-def test_mesh_1m_1080p_sampled(R, orc, shape):
-    print_case(f"mesh composition 1M 1920x1080 sampled, tiles {shape[0]}x{shape[1]}")
+def test_mesh_1m_1080p_whole_image(R, orc, shape):
+    print_case(f"mesh composition 1M 1920x1080 whole image, tiles {shape[0]}x{shape[1]}")
     from paper_2512_08478_amd.render import Renderer
+    from gpu_util import scene_cached
     Rs = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2]))
-    sc, cam = S.medium_scene()
+    sc, cam = scene_cached("medium")
     rec = orc.preprocess(sc, cam)
     mesh = wall(cam, rec.d[rec.visible, orc.D_DEPTH], normal=(0.1, 0.3, 1.0), seed=8)
     fr = Rs.forward(gp(sc), cam, mesh=mesh)
-    img = fr.image.cpu().numpy()
-    pix = sampled_pixels(cam, 256, 17)
-    ref = orc.render_pixels(rec, cam, pix, mesh=mesh)
-    e, nflag = image_check(img[pix[:, 1], pix[:, 0]], ref)
+    img = fr.image.cpu().numpy().reshape(-1, 4)
+    ref = orc.render_pixels(rec, cam, orc.all_pixels(cam), mesh=mesh, tiled=True)
+    e, nflag, nloose = image_check(img, ref, T=fr.T_final.cpu().numpy().reshape(-1))
     nb = torch.empty((cam.height, cam.width), dtype=torch.int32, device="cuda")
     Rs.rasterize(fr.splats, fr.values, fr.ranges, cam, n_blend=nb, mesh=fr.mesh)
-    got = nb.cpu().numpy()[pix[:, 1], pix[:, 0]]
+    got = nb.cpu().numpy().reshape(-1)
     ok = (ref["margin"] >= 1e-5) & (ref["flags"] == 0)
     np.testing.assert_array_equal(got[ok], ref["n_blend"][ok])
-    print(f"1M mesh max err {e:.2e}, flagged {nflag}, blended pairs {int(nb.sum())}")
+    print(f"1M mesh max err {e:.2e}, flagged {nflag}, jump above 1e-4 {nloose}, "
+          f"blended pairs {int(nb.sum())}")
 
 
 def test_mesh_backward_vs_oracle(R, orc):

@@ -1,17 +1,18 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
 Preprocess records, the bit-exact sort, the tile key lists and the rendered
-images, at the tiny size (whole image, every Gaussian) and at the full
-1M / 6M sizes in the launch configuration the benchmark times (sampled
-pixels the oracle computes one by one).
+images: at the tiny size against the brute-force oracle, and at the full
+1M / 6M sizes (every Gaussian, every key, every pixel, in the launch
+configurations the benchmark times) against the tiled oracle, which equals
+the brute-force definition.
 """
 import numpy as np
 import pytest
 import torch
 
 from paper_2512_08478_amd import scenes as S
-from gpu_util import (compare_records, extra_pairs_harmless, image_check, print_case,
-                      sampled_pixels, splats_np, u32, u64)
+from gpu_util import (assert_pairs_harmless, compare_records, extra_pairs_harmless, image_check,
+                      pair_set_check, print_case, rect_pairs, scene_cached, splats_np, u32, u64)
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +86,26 @@ def test_preprocess_model_transform(R, orc):
     splats = R.preprocess(gp(sc), cam)[0]
     torch.cuda.synchronize()
     compare_records(orc, splats_np(splats, sc.n), orc.preprocess(sc, cam), cam)
+
+
+@pytest.mark.parametrize("workload", ["medium", "large"])
+def test_preprocess_records_full_size(R, orc, workload):
+    """Every Gaussian's record of the 1M and 6M frames against the oracle,
+    and the (Gaussian, tile) pairs of the benchmark's tile shape: all of the
+    oracle's, plus only harmless extras."""
+    print_case(f"preprocess records, all Gaussians, {workload}")
+    sc, cam = scene_cached(workload)
+    splats, dkeys, rects, counts = R.preprocess(gp(sc), cam)
+    torch.cuda.synchronize()
+    rec = splats_np(splats, sc.n)
+    ref = orc.preprocess(sc, cam)
+    v = compare_records(orc, rec, ref, cam)
+    tile = (32, 16) if workload == "medium" else (8, 8)
+    n_o, n_x = pair_set_check(orc, ref, rec, cam, v, tile)
+    c = u32(counts)
+    assert int(c[1]) == int((rec["px1"] >= rec["px0"]).sum())
+    print(f"{workload}: {int(v.sum())} visible records compared, {n_o} oracle pairs, "
+          f"{n_x} harmless extra pairs")
 
 
 # ------------------------------------------------------------------ sort
@@ -203,7 +224,7 @@ def test_sort_keys_tiny(R, orc):
     if extra:
         t, g = map(np.array, zip(*extra))
         w = orc.pair_max_weight(ref, cam, g, t)
-        assert w.max() < (1 / 255) * (1 + 1e-5)
+        assert w.max() < 1 / 255
 
 
 def expected_sorted_pairs_np(rec, tiles_x):
@@ -230,7 +251,7 @@ def expected_sorted_pairs_np(rec, tiles_x):
 @pytest.mark.parametrize("workload,shape,mode", [("medium", (32, 16, 7), 0), ("medium", (16, 16, 8), 0),
                                                  ("large", (8, 8, 8), 0), ("large", (16, 8, 6), 0),
                                                  ("medium", (16, 16, 8), 1), ("large", (8, 8, 8), 1)])
-def test_sort_keys_full_size(R, workload, shape, mode):
+def test_sort_keys_full_size(R, orc, workload, shape, mode):
     """gs_sort at the benchmark sizes: keys, permutation and tile ranges
     bit-exact against numpy's stable sort of the GPU's own pairs.  Sort mode
     1 covers the onesweep look-back across the switch from the depth passes
@@ -240,7 +261,7 @@ def test_sort_keys_full_size(R, workload, shape, mode):
     print_case(f"gs_sort keys {workload} tiles {tw}x{th} {bits}-bit digits, sort mode {mode}")
     from paper_2512_08478_amd.render import Renderer
     Rs = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=mode))
-    sc, cam = S.medium_scene() if workload == "medium" else S.large_scene()
+    sc, cam = scene_cached(workload)
     fr = Rs.forward(gp(sc), cam, want_keys=True)
     torch.cuda.synchronize()
     tiles_x = -(-cam.width // tw)
@@ -259,7 +280,21 @@ def test_sort_keys_full_size(R, workload, shape, mode):
     np.testing.assert_array_equal(rng[nonempty, 0], starts[nonempty])
     np.testing.assert_array_equal(rng[nonempty, 1], ends[nonempty])
     assert np.all(rng[~nonempty, 0] == rng[~nonempty, 1])
-    print(f"{workload}: {n} pairs, {int(nonempty.sum())} non-empty tiles")
+    # the key list's (Gaussian, tile) pairs against the oracle's exact rects:
+    # every oracle pair is there, every extra one is harmless
+    ref = orc.preprocess(sc, cam)
+    vis = np.nonzero(ref.visible)[0]
+    it = ref.i[vis]
+    o = rect_pairs(it[:, orc.I_PX0], it[:, orc.I_PX1], it[:, orc.I_PY0], it[:, orc.I_PY1],
+                   vis, tw, th, tiles_x)
+    g = (ev.astype(np.int64) << 32) | tile
+    assert np.unique(g).size == g.size
+    missing = np.setdiff1d(o, g)
+    assert missing.size == 0, missing[:5]
+    extra = np.setdiff1d(g, o)
+    assert_pairs_harmless(orc, ref, cam, extra, (tw, th))
+    print(f"{workload}: {n} pairs ({o.size} oracle, {extra.size} harmless extra), "
+          f"{int(nonempty.sum())} non-empty tiles")
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -298,67 +333,76 @@ def test_render_tiny_whole_image(R, orc):
     fr = R.forward(gp(sc), cam)
     img = fr.image.cpu().numpy().reshape(-1, 4)
     T = fr.T_final.cpu().numpy().reshape(-1)
-    ref = orc.render_image(orc.preprocess(sc, cam), cam)
-    flat = {k: v.reshape(-1, 4) if k == "rgba" else v.reshape(-1) for k, v in ref.items()}
-    e, nflag = image_check(img, flat)
-    print(f"tiny max err {e:.2e}, flagged {nflag}")
-    np.testing.assert_allclose(T[flat["margin"] >= 1e-5], flat["T"][flat["margin"] >= 1e-5], atol=1e-4)
+    ref = orc.render_pixels(orc.preprocess(sc, cam), cam, orc.all_pixels(cam))
+    e, nflag, nloose = image_check(img, ref, max_flagged=0.005, max_loosened=0.001, T=T)
+    print(f"tiny max err {e:.2e}, flagged {nflag}, jump above 1e-4 {nloose}")
 
 
 def test_blend_counts_match_oracle(R, orc):
     """The optional per-pixel blend count equals the oracle's count of
-    composited Gaussians wherever no decision is within rounding of a
-    threshold, and requesting it leaves the image bitwise unchanged."""
-    print_case("n_blend tiny 256x256 + 1M sampled")
-    for sc, cam, pix in ((*S.tiny_scene(), None), (*S.medium_scene(), "sample")):
+    composited Gaussians wherever no decision is near a threshold (whole
+    tiny and 1M images), and requesting it leaves the image bitwise
+    unchanged."""
+    print_case("n_blend tiny 256x256 + 1M 1920x1080, whole images")
+    for sc, cam in (S.tiny_scene(), scene_cached("medium")):
         fr = R.forward(gp(sc), cam)
         nb = torch.empty((cam.height, cam.width), dtype=torch.int32, device="cuda")
         img2, T2, last2 = R.rasterize(fr.splats, fr.values, fr.ranges, cam, n_blend=nb)
         assert torch.equal(img2, fr.image) and torch.equal(last2, fr.last)
-        if pix is None:
-            pix = orc.all_pixels(cam)
-        else:
-            pix = sampled_pixels(cam, 256, 21)
-        ref = orc.render_pixels(orc.preprocess(sc, cam), cam, pix)
-        got = nb.cpu().numpy()[pix[:, 1], pix[:, 0]]
+        ref = orc.render_image(orc.preprocess(sc, cam), cam, tiled=True)
+        got = nb.cpu().numpy()
         ok = (ref["margin"] >= 1e-5) & (ref["flags"] == 0)
-        assert ok.mean() > 0.9
+        assert ok.mean() > 0.94
         np.testing.assert_array_equal(got[ok], ref["n_blend"][ok])
-        last = fr.last.cpu().numpy()[pix[:, 1], pix[:, 0]]
-        assert (got <= last).all()
+        assert (got <= fr.last.cpu().numpy()).all()
         print(f"n_blend mean {got.mean():.1f}, checked {int(ok.sum())} px")
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 8), (32, 16, 7)])
-def test_render_medium_1080p_sampled(R, orc, shape):
-    print_case(f"render 1M 1920x1080 sampled pixels, tiles {shape[0]}x{shape[1]}, {shape[2]}-bit digits")
-    from paper_2512_08478_amd.render import Renderer
-    Rs = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2]))
-    sc, cam = S.medium_scene()
-    fr = Rs.forward(gp(sc), cam)
-    img = fr.image.cpu().numpy()
-    pix = sampled_pixels(cam, 256, 11)
-    ref = orc.render_pixels(orc.preprocess(sc, cam), cam, pix)
-    e, nflag = image_check(img[pix[:, 1], pix[:, 0]], ref)
-    print(f"1M max err {e:.2e}, flagged {nflag}, instances {fr.capacity}")
+MEDIUM_CASES = [(v, (32, 16, 6)) for v in range(8)] + [(0, (16, 16, 8)), (0, (8, 8, 7))]
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 8), (8, 8, 8)])
-def test_render_large_6m_sampled(R, orc, shape):
-    print_case(f"render 6M 1920x1080 sampled pixels, tiles {shape[0]}x{shape[1]}")
+@pytest.mark.parametrize("view,shape", MEDIUM_CASES)
+def test_render_medium_1080p_whole_image(R, orc, view, shape):
+    """Every pixel of the 1M frame (each of the 8 orbit views, in the
+    benchmark's launch configuration and two others) against the tiled FP64
+    oracle, which equals the brute-force definition."""
+    print_case(f"render 1M 1920x1080 view {view}, whole image, tiles {shape[0]}x{shape[1]}, "
+               f"{shape[2]}-bit digits")
     from paper_2512_08478_amd.render import Renderer
     Rs = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2]))
-    sc, cam = S.large_scene()
+    sc, _ = scene_cached("medium")
+    cam = S.orbit_camera(view, 8, 8.0, 1920, 1080)
     fr = Rs.forward(gp(sc), cam)
-    img = fr.image.cpu().numpy()
+    img = fr.image.cpu().numpy().reshape(-1, 4)
+    T = fr.T_final.cpu().numpy().reshape(-1)
+    ref = orc.render_pixels(orc.preprocess(sc, cam), cam, orc.all_pixels(cam), tiled=True)
+    e, nflag, nloose = image_check(img, ref, T=T)
+    print(f"1M view {view}: max err unflagged {e:.2e}, flagged {nflag}, jump above 1e-4 {nloose}, "
+          f"instances {fr.capacity}")
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (16, 16, 8)])
+def test_render_large_6m_whole_image(R, orc, shape):
+    """Every pixel of the 6M frame (eye inside the cloud; its densest 8x8
+    tiles hold tens of thousands of splats) against the tiled oracle."""
+    print_case(f"render 6M 1920x1080 whole image, tiles {shape[0]}x{shape[1]}")
+    from paper_2512_08478_amd.render import Renderer
+    Rs = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2]))
+    sc, cam = scene_cached("large")
+    fr = Rs.forward(gp(sc), cam)
+    img = fr.image.cpu().numpy().reshape(-1, 4)
+    T = fr.T_final.cpu().numpy().reshape(-1)
     rec = splats_np(fr.splats, sc.n)
-    culled = float(np.mean(rec["tx1"] < rec["tx0"]))
+    culled = float(np.mean(rec["px1"] < rec["px0"]))
     print(f"6M culled fraction {culled:.3f}, instances {fr.capacity}")
     assert 0.35 <= culled <= 0.45
-    pix = sampled_pixels(cam, 64, 12)
-    ref = orc.render_pixels(orc.preprocess(sc, cam), cam, pix)
-    e, nflag = image_check(img[pix[:, 1], pix[:, 0]], ref)
-    print(f"6M max err {e:.2e}, flagged {nflag}")
+    ref = orc.render_pixels(orc.preprocess(sc, cam), cam, orc.all_pixels(cam), tiled=True)
+    e, nflag, nloose = image_check(img, ref, T=T)
+    # the densest tiles (where the compositing kernel's long walks run)
+    rng_ = u32(fr.ranges)[:2 * Rs.tiles(cam)].reshape(-1, 2).astype(np.int64)
+    lens = rng_[:, 1] - rng_[:, 0]
+    print(f"6M: max err unflagged {e:.2e}, flagged {nflag}, jump above 1e-4 {nloose}; "
+          f"longest tile list {lens.max()}, 99th percentile {np.percentile(lens, 99):.0f}")
 
 
 # ------------------------------------------------------------------ edge cases + invariances

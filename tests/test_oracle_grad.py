@@ -204,3 +204,21 @@ def test_mesh_gradients_match_central_differences(orc):
         scale = np.abs(fd).max()
         assert scale > 0, nm
         np.testing.assert_allclose(ad, fd, rtol=1e-5, atol=1e-6 * scale, err_msg=nm)
+
+
+def test_tiled_gradients_equal_whole_image(orc):
+    """The per-tile autograd (each tile's candidates only, gradients summed)
+    equals autograd of the whole image at once: the same definition."""
+    from oracle import grad as og
+    sc, cam = S.fd_scene()
+    rng = np.random.default_rng(31)
+    G = rng.standard_normal((cam.height, cam.width, 4))
+    pix = orc.all_pixels(cam)
+    rgba_a, ga = og.render_and_grad(sc, cam, pix, G.reshape(-1, 4))
+    for tile in ((16, 16), (8, 8), (32, 8)):
+        rgba_b, gb = og.render_and_grad_tiled(sc, cam, G, tile=tile)
+        np.testing.assert_allclose(rgba_b.reshape(-1, 4), rgba_a, rtol=0, atol=1e-14)
+        for nm in ga:
+            scale = max(np.abs(ga[nm]).max(), 1e-300)
+            np.testing.assert_allclose(gb[nm] / scale, ga[nm] / scale, rtol=0, atol=1e-12,
+                                       err_msg=f"{nm} {tile}")
