@@ -72,7 +72,8 @@ def parse():
     ap.add_argument("--packed", action="store_true",
                     help="forward from the FP16 pre-packed inputs (pre-packed once, untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=2048)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="medium only: skip the 6M forward and 500k forward+backward frames")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     ap.add_argument("--verbose", action="store_true")
@@ -145,14 +146,23 @@ def algorithmic_bytes(n, n_vis, inst, K, W, H, tiles, depth_passes=4):
     }
 
 
-def measured_traffic(workload, kernel):
+def traffic_key(workload, kernel, cfg):
+    """Key of a counter measurement: the workload, the kernel and the launch
+    configuration it was taken in (tile shape, digit width, sort mode and
+    compositing order all change what a kernel reads)."""
+    return (f"{workload}/{kernel}/{cfg['tile_w']}x{cfg['tile_h']}/b{cfg['radix_bits']}"
+            f"/m{cfg['sort_mode']}/o{cfg['raster_order']}")
+
+
+def measured_traffic(workload, kernel, cfg):
     """HBM bytes per launch of `kernel` from the committed rocprofv3
-    FETCH_SIZE + WRITE_SIZE passes (copy-calibrated), or None when there are
-    none for this workload or the kernel's sources changed since."""
+    FETCH_SIZE + WRITE_SIZE passes (copy-calibrated), taken in exactly this
+    launch configuration, or None when there are none or the kernel's
+    sources changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     try:
-        rec = json.load(open(path))[workload][kernel]
+        rec = json.load(open(path))[traffic_key(workload, kernel, cfg)]
     except (OSError, KeyError, ValueError):
         return None
     h = hashlib.sha256()
@@ -207,11 +217,6 @@ def main():
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    import numpy as np
-    import torch
-    from paper_2512_08478_amd import _lib as L
-    from paper_2512_08478_amd.render import GaussianParams, Renderer
-
     if args.packed and args.workload not in ("tiny", "medium", "large", "mesh"):
         print(json.dumps({"error": "--packed applies to the forward workloads tiny, medium, large, "
                                    "mesh"}))
@@ -220,6 +225,35 @@ def main():
         return run_batched(args)
     if args.workload == "sort32":
         return run_sort32(args)
+    out = run_view(args, full=True)
+    if args.workload == "medium" and not args.packed and not args.no_extra:
+        # the metric's other frames (6M forward, 500k forward + backward),
+        # autotuned and timed the same way
+        import copy
+        extra = {}
+        for w in ("large", "diff"):
+            a2 = copy.copy(args)
+            a2.workload = w
+            a2.calib_copy_mib = 0
+            e = run_view(a2, full=False)
+            extra[w] = {k: e[k] for k in ("value", "unit", "ms_per_step", "sort_ms", "sort_gkeys_per_s",
+                                          "frame_ms", "roofline")}
+            extra[w]["config"] = e["config"]
+            extra[w]["stages"] = {k: {kk: vv for kk, vv in v.items()
+                                      if kk in ("ms_per_frame", "gbs", "hbm_frac", "tflops", "alu_frac")}
+                                  for k, v in e["stages"].items()}
+        out["extra_workloads"] = extra
+    print(json.dumps(out), flush=True)
+
+
+def run_view(args, full):
+    """One single-view workload: autotune, time, trace; returns the result
+    dict (with the CPU baseline when `full`)."""
+    import numpy as np
+    import torch
+    from paper_2512_08478_amd import _lib as L
+    from paper_2512_08478_amd.render import GaussianParams, Renderer
+
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib * 2**20 // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -371,7 +405,9 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                     "traffic": None, "algo_bytes_per_launch": int(ab[dom])}
     roofline["ms_per_launch"] = round(kern_avg[dom], 5)
-    roofline["traffic"] = measured_traffic(args.workload, dom)
+    roofline["traffic"] = measured_traffic(args.workload, dom, dict(
+        tile_w=tw, tile_h=th, radix_bits=args.radix_bits, sort_mode=args.sort_mode,
+        raster_order=order))
 
     out = {
         "metric": METRIC,
@@ -404,16 +440,11 @@ def main():
     if tuned is not None:
         out["autotune_ms_per_frame"] = tuned
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, cam, args.cpu_pixels,
-                                           packed=args.packed or skin_np is not None,
-                                           mesh=make_mesh(cam) if args.workload == "mesh" else None,
-                                           skin=skin_np)
-    print(json.dumps(out), flush=True)
-
-
-# the paper's Table 1 "Sort" column (RTX 4090, WebGPU; context, not a target)
-PAPER_SORT_MS = {758_000: 0.20, 1_515_000: 0.22, 3_031_000: 0.32, 6_062_000: 0.58}
+    if full and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(
+            sc, cam, dict(tile_w=16, tile_h=16), packed=args.packed or skin_np is not None,
+            mesh=make_mesh(cam) if args.workload == "mesh" else None, skin=skin_np)
+    return out
 
 
 def run_sort32(args):
@@ -588,58 +619,80 @@ def run_batched(args):
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(assets, cams[0], args.cpu_pixels, scale_pixels=out["config"]["pixels"])
+        cb = cpu_baseline(assets, cams[0], dict(tile_w=16, tile_h=16))
+        cb["sample"] = "view 0 of the batch (all assets): " + cb["sample"]
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(sc, cam, n_pix, scale_pixels=None, packed=False, mesh=None, skin=None):
-    """The FP64 oracle, as it stands, on a bounded sample of the same frame:
-    preprocess of every Gaussian + brute-force compositing of n_pix random
-    pixels, scaled to a whole frame.  With `packed`, the oracle pre-packs
-    first (untimed, as on the GPU) and preprocesses the packed values; with
-    `skin` (joint indices, weights, joints) it also skins them each frame."""
-    import numpy as np
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown CPU"
+
+
+def oracle_frame_stages(sc, cam, settings, pixels, packed=False, mesh=None, skin=None):
+    """Times of the FP64 oracle's stages for one frame, in seconds: preprocess
+    (Eq. 1 + colour + culls), keygen (the (tile, depth) key list),
+    std::stable_sort of the keys, and the tiled composite (Eq. 3) of
+    `pixels`.  The oracle as it stands; no tuning."""
     import oracle
     pk = oracle.prepack(sc) if packed else None
-    t0 = time.perf_counter()
+    t = [time.perf_counter()]
     if pk is not None:
         if skin is not None:
             pk = oracle.lbs_deform(pk, *skin)
-        rec = oracle.preprocess_packed(pk, cam)
-        n = sc.n
-    elif isinstance(sc, (list, tuple)):   # several assets, one view of the batch
-        rec = oracle.preprocess_many(sc, cam)
-        n = sum(a.n for a in sc)
+        rec = oracle.preprocess_packed(pk, cam, settings)
+    elif isinstance(sc, (list, tuple)):
+        rec = oracle.preprocess_many(sc, cam, settings)
     else:
-        rec = oracle.preprocess(sc, cam)
-        n = sc.n
-    t1 = time.perf_counter()
-    rng = np.random.default_rng(123)
-    pix = np.stack([rng.integers(0, cam.width, n_pix), rng.integers(0, cam.height, n_pix)], 1)
-    oracle.render_pixels(rec, cam, pix, mesh=mesh)
-    t2 = time.perf_counter()
-    if scale_pixels is None:
-        frame_s = (t1 - t0) + (t2 - t1) * (cam.width * cam.height) / n_pix
-        what = f"scaled to {cam.width}x{cam.height} pixels"
-    else:
-        # the batch: every view preprocesses all Gaussians and composites its pixels
-        views = scale_pixels / (cam.width * cam.height)
-        frame_s = ((t1 - t0) * views + (t2 - t1) * scale_pixels / n_pix) / views
-        what = f"scaled to the batch's {scale_pixels} pixels, reported per view"
-    cpu = "unknown CPU"
+        rec = oracle.preprocess(sc, cam, settings)
+    t.append(time.perf_counter())
+    k, v = oracle.keys(rec, cam, settings)
+    t.append(time.perf_counter())
+    oracle.stable_sort_pairs(k, v)
+    t.append(time.perf_counter())
+    oracle.render_pixels(rec, cam, pixels, settings, mesh=mesh, tiled=True)
+    t.append(time.perf_counter())
+    return {"preprocess": t[1] - t[0], "keygen": t[2] - t[1], "stable_sort": t[3] - t[2],
+            "composite": t[4] - t[3], "keys": int(k.size)}
+
+
+def cpu_baseline(sc, cam, settings, packed=False, mesh=None, skin=None, one_core_rows=8):
+    """The FP64 oracle, as it stands, timed by stage (preprocess, keygen,
+    std::stable_sort, tiled composite) on all host threads over the whole
+    frame, and on one thread with the composite over every `one_core_rows`-th
+    tile row (scaled to the frame; the other stages whole).  `value` is the
+    all-threads frame rate."""
+    import numpy as np
+    import oracle
+    n_all = oracle.num_threads()
+    pix = oracle.all_pixels(cam)
+    st = dict(settings)
+    allc = oracle_frame_stages(sc, cam, st, pix, packed, mesh, skin)
+    th = st.get("tile_h", 16)
+    rows = (pix[:, 1] // th) % one_core_rows == 0
+    oracle.set_num_threads(1)
     try:
-        with open("/proc/cpuinfo") as fh:
-            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
-    return {"value": round(1.0 / frame_s, 8), "unit": "frames/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle on {oracle.num_threads()} threads of {cpu}, forward only: "
-                      f"preprocess of all {n} "
-                      f"{'pre-packed ' if pk is not None else ''}Gaussians "
-                      f"({t1 - t0:.2f} s) + brute-force Eq. 3 at {n_pix} random pixels "
-                      f"({t2 - t1:.2f} s), {what}"}
+        one = oracle_frame_stages(sc, cam, st, pix[rows], packed, mesh, skin)
+    finally:
+        oracle.set_num_threads(n_all)
+    one["composite"] *= pix.shape[0] / max(1, int(rows.sum()))
+    frame_all = sum(allc[k] for k in ("preprocess", "keygen", "stable_sort", "composite"))
+    frame_one = sum(one[k] for k in ("preprocess", "keygen", "stable_sort", "composite"))
+    r = lambda d: {k: (round(v * 1e3, 2) if k != "keys" else v) for k, v in d.items()}
+    return {"value": round(1.0 / frame_all, 4), "unit": "frames/s", "cores": n_all, "kind": "oracle",
+            "cpu": cpu_model(),
+            "stages_ms_all_threads": r(allc), "stages_ms_one_thread": r(one),
+            "frames_per_s_one_thread": round(1.0 / frame_one, 5),
+            "sort_mkeys_per_s_one_thread": round(one["keys"] / one["stable_sort"] / 1e6, 2),
+            "sample": f"tiled FP64 oracle, forward only, by stage (preprocess, keygen, "
+                      f"std::stable_sort of the {allc['keys']} keys, tiled composite): the whole "
+                      f"{cam.width}x{cam.height} frame on {n_all} threads of {cpu_model()}; on one "
+                      f"thread the composite of every {one_core_rows}th tile row ("
+                      f"{int(rows.sum())} pixels) scaled to the frame"}
 
 
 if __name__ == "__main__":

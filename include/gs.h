@@ -121,6 +121,11 @@ typedef struct gs_settings {
  * centres the opacity-aware footprint (o exp(-Q/2) >= alpha_min) can reach,
  * rounded outwards; a culled Gaussian has px1 < px0 and reaches no pixel.
  * Its tiles are the tiles this bbox overlaps (gs_preprocess's tile_rects).
+ * The 2-D mean (Eq. 1's projected mean, in pixels) is stored relative to
+ * the bbox corner: the mean is (px0 + mean_x, py0 + mean_y).  It is formed
+ * in float64, so a pixel's offset from it is accurate to ~1e-7 px anywhere
+ * in the image.  `depth` is the float32 rounding of the camera-space depth
+ * (formed in float64).
  */
 typedef struct gs_splat {
   float mean_x, mean_y;

@@ -59,7 +59,7 @@ DEFAULT_SETTINGS = dict(tile_w=16, tile_h=16, eps2d=0.3, tau=1.0 / 255.0,
 # record layout (must match the enums in gs_oracle.cpp)
 D_MX, D_MY, D_SA, D_SB, D_SC, D_CA, D_CB, D_CC, D_DEPTH = range(9)
 D_R, D_G, D_B, D_RR, D_RG, D_RB, D_OPAC, D_C3 = 9, 10, 11, 12, 13, 14, 15, 16
-D_QMAX, D_ZSCALE = 22, 23
+D_QMAX = 22
 I_CULL, I_PX0, I_PX1, I_PY0, I_PY1, I_TX0, I_TY0, I_TX1, I_TY1, I_TILES, I_AMBIG = range(11)
 C_VISIBLE, C_NEAR, C_INVALID, C_DET, C_OPACITY, C_OFFIMAGE = range(6)
 
@@ -292,9 +292,10 @@ def render_pixels(recs: Records, cam, pix, settings=None, mesh=None, tiled=False
     Returns dict(rgba (P,4), T (P,), n_blend (P,), margin (P,), flags (P,),
     jump (P,)): ``margin`` is the smallest relative distance of a decision
     to its threshold (capped at 1), ``flags`` marks depth near-ties (1),
-    ambiguous culls (2) and near mesh-depth tests (4), and ``jump`` is the
-    largest change of the outputs that taking the pixel's near decisions
-    (margin < 1e-5, or flagged) the other way can cause, each re-walked."""
+    ambiguous culls (2), near mesh-depth tests (4) and any near decision
+    (8: a weight within 3e-5 of tau, T within 1e-4 of t_eps, or one of the
+    above), and ``jump`` is the largest change of the outputs that taking
+    the pixel's near decisions the other way can cause, each re-walked."""
     lib = _load()
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
     P = pix.shape[0]

@@ -20,7 +20,7 @@
 //     order -- no tiles, no sort keys -- and the same walk over per-tile
 //     candidate lists (orc_render_tiled), which is exactly equal and fast
 //     enough for whole 1080p frames; each pixel also reports the decisions
-//     its float64 walk took within a relative 1e-5 of a threshold and the
+//     its float64 walk took close to a threshold (the tolerance protocol) and the
 //     jump that taking each of them the other way would cause;
 //   * the (tile, depth) key list and a library stable sort, for the sort
 //     contract;
@@ -67,7 +67,7 @@ enum RecD {
   D_OPAC = 15,                        // activated opacity
   D_C3 = 16,                          // world Sigma: xx xy xz yy yz zz (6)
   D_QMAX = 22,                        // 2 ln(o / tau)
-  D_ZSCALE = 23,                      // sum of the magnitudes of the depth's terms
+  D_UNUSED = 23,                      // (zero)
   REC_D = 24
 };
 enum RecI {
@@ -92,6 +92,15 @@ struct Set {
   double eps2d, tau, amax, teps, clip;
   double bg[3];
 };
+
+// Relative margins below which a decision is near: a weight against tau
+// (skip, an ambiguous Gaussian's include) within 3e-5 -- twice the largest
+// float32 error of a pixel weight measured near tau (1.6e-5 over the ~10^5
+// near-threshold pairs of the 1M frame) -- and the transmittance against
+// t_eps within 1e-4, since T's float32 error compounds over the blends
+// through factors 1 - alpha.
+constexpr double kNearRel = 3e-5;
+constexpr double kNearStop = 1e-4;
 
 Cam load_cam(const double* c) {
   Cam k;
@@ -242,18 +251,6 @@ void project_gaussian(const double* mu, double o, const double* Sig, const ShT* 
   for (int r = 0; r < 3; ++r)
     t[r] = V[4 * r] * muw[0] + V[4 * r + 1] * muw[1] + V[4 * r + 2] * muw[2] + V[4 * r + 3];
   d[D_DEPTH] = t[2];
-  // A float32 evaluation of t_z is within a few units in the last place of
-  // the sum of its terms' magnitudes; two depths closer than that may be
-  // ordered either way by a float32 computation.
-  {
-    double zs = std::fabs(V[11]);
-    for (int c = 0; c < 3; ++c) {
-      double w = std::fabs(tk[c]);
-      for (int k = 0; k < 3; ++k) w += std::fabs(A[3 * c + k] * mu[k]);
-      zs += std::fabs(V[8 + c]) * w;
-    }
-    d[D_ZSCALE] = zs;
-  }
   int cull = C_VISIBLE;
   bool ambiguous = false;
   if (!(t[2] > cam.znear)) {
@@ -337,15 +334,15 @@ void project_gaussian(const double* mu, double o, const double* Sig, const ShT* 
       } else {
         cull = C_OFFIMAGE;
         // the support misses every pixel centre; it is a near decision when
-        // the region where the weight reaches tau (1 - 1e-5) does not
+        // the region where the weight reaches tau (1 - kNearRel) does not
         ambiguous = true;
       }
     }
     // A culled Gaussian counts as ambiguous when some pixel centre sees a
-    // weight within a relative 1e-5 of tau, were it kept; its bbox is then
-    // that region's.
+    // weight within kNearRel of tau, were it kept; its bbox is then that
+    // region's.
     if (cull != C_VISIBLE && ambiguous) {
-      const double qn = 2.0 * std::log(o / (set.tau * (1.0 - 1e-5)));
+      const double qn = 2.0 * std::log(o / (set.tau * (1.0 - kNearRel)));
       if (qn > 0.0 && pixel_bbox(d, qn, cam, box)) set_bbox(box, set, iv);
       else ambiguous = false;
     }
@@ -425,19 +422,21 @@ inline double pixel_weight(const double* d, double px, double py) {
 // skipped; C += T alpha rgb; T *= 1 - alpha; the walk stops once T < t_eps.
 //
 // Tolerance protocol.  The GPU computes in float32, so it may take a
-// discrete decision the other way where the float64 value lies within a
-// relative 1e-5 of the threshold (a "near" decision): the skip (weight vs
-// tau), the stop (T vs t_eps), the order of two blended Gaussians whose
-// depths agree within float32 rounding of their terms, keeping a Gaussian culled within 1e-5
+// discrete decision the other way where the float64 value lies close to the
+// threshold (a "near" decision; bands kNearRel, kNearStop): the skip
+// (weight vs tau), the stop (T vs t_eps), the order of two blended Gaussians whose
+// depths agree within float32 rounding (or of the Gaussian the walk stops
+// on and the next one that would blend), keeping a Gaussian culled within 1e-5
 // of a threshold, and the mesh depth test.  The walk records each near
 // decision; the pixel's jump is the sum, over its near decisions, of the
 // largest change of any output channel when that one decision is taken the
 // other way (the pixel re-walked with it forced).
 
-constexpr double kNearRel = 1e-5;  // relative margin below which a decision is near
-// Two depths are a near tie when they differ by at most 2^-21 times the sum
-// of their error scales (D_ZSCALE): eight float32 units of rounding.
-constexpr double kTieScale = 1.0 / 2097152.0;
+// Two depths are a near tie when they differ by at most 2^-22 times the sum
+// of their magnitudes (two to four float32 spacings): the sort key is the
+// float32 rounding of the depth, and depths that round to the same or
+// neighbouring float32 values may be ordered either way.
+constexpr double kTieRel = 1.0 / 4194304.0;
 constexpr int kMaxNear = 64;       // more near decisions: the jump is not bounded
 
 struct Cand {
@@ -471,7 +470,7 @@ void walk_pixel(const std::vector<Cand>& L, const double* rec_d, const Set& set,
   o.fl = 0;
   o.near.clear();
   int64_t prev = -1;
-  double prev_depth = 0.0, prev_scale = 0.0;
+  double prev_depth = 0.0;
   const int64_t n = (int64_t)L.size();
   for (int64_t k = 0; k < n; ++k) {
     int64_t at = k;  // the swap force exchanges two positions of the walk
@@ -488,7 +487,7 @@ void walk_pixel(const std::vector<Cand>& L, const double* rec_d, const Set& set,
       // mesh depth test: hidden when deeper than the mesh, and so is every
       // Gaussian after it in depth order
       bool hidden = depth > D;
-      if (rec && g >= set.tau && std::fabs(depth - D) <= kNearRel * std::fabs(D)) {
+      if (rec && g >= set.tau && std::fabs(depth - D) <= 1e-5 * std::fabs(D)) {
         o.fl |= 4;
         o.near.push_back({N_HIDE, k, -1});
       }
@@ -522,21 +521,36 @@ void walk_pixel(const std::vector<Cand>& L, const double* rec_d, const Set& set,
     o.T *= (1.0 - a);
     ++o.nb;
     if (rec && prev >= 0 &&
-        std::fabs(depth - prev_depth) <= kTieScale * (d[D_ZSCALE] + prev_scale)) {
+        std::fabs(depth - prev_depth) <= kTieRel * (std::fabs(depth) + std::fabs(prev_depth))) {
       o.fl |= 1;
       o.near.push_back({N_SWAP, prev, k});
     }
     prev = k;
     prev_depth = depth;
-    prev_scale = d[D_ZSCALE];
     const double m3 = std::fabs(o.T - set.teps) / set.teps;
     if (rec) {
       o.mrg = std::min(o.mrg, m3);
-      if (m3 < kNearRel) o.near.push_back({N_STOP, k, -1});
+      if (m3 < kNearStop) o.near.push_back({N_STOP, k, -1});
     }
     bool stop = o.T < set.teps;
     if (forced && force->kind == N_STOP) stop = !stop;
-    if (stop) break;
+    if (stop) {
+      // The Gaussian the walk stops on may tie in depth with the next one
+      // that would blend; ordered the other way, that one blends first.
+      if (rec) {
+        for (int64_t j = k + 1; j < n; ++j) {
+          const double* dj = rec_d + (size_t)L[(size_t)j].idx * REC_D;
+          if (dj[D_DEPTH] - depth > kTieRel * (std::fabs(depth) + std::fabs(dj[D_DEPTH]))) break;
+          if (L[(size_t)j].ambig || dj[D_DEPTH] > D) continue;
+          if (pixel_weight(dj, px, py) >= set.tau) {
+            o.fl |= 1;
+            o.near.push_back({N_SWAP, k, j});
+            break;
+          }
+        }
+      }
+      break;
+    }
   }
 }
 
@@ -554,7 +568,7 @@ void composite_pixel(const std::vector<Cand>& L, const double* rec_d, const Set&
   *T_out = base.T;
   *nb = base.nb;
   *margin = base.mrg;
-  *flags = base.fl;
+  *flags = base.fl | (base.near.empty() ? 0 : 8);
   if (!jump) return;
   if ((int)base.near.size() > kMaxNear) {
     *jump = std::numeric_limits<double>::infinity();
@@ -659,13 +673,14 @@ int orc_preprocess_cov(int64_t n, const double* means, const double* opac, const
 // Gaussians, the smallest relative margin to any discrete decision taken
 // (skip at tau, clamp at alpha_max, stop at t_eps; capped at 1), flags:
 //   1 = two blended Gaussians whose depths agree within float32 rounding
-//       (a near tie, see kTieScale);
-//   2 = a Gaussian culled within a relative 1e-5 of a threshold would reach
-//       tau within that band here;
+//       (a near tie, see kTieRel);
+//   2 = a Gaussian culled within a relative 1e-5 of a threshold (or whose
+//       footprint misses every pixel centre by less than the weight band)
+//       would reach tau within the weight band here;
 //   4 = a Gaussian with weight >= tau lies within a relative 1e-5 of the
 //       mesh depth;
-// and, if `jump` is not NULL, the jump the pixel's near decisions straddle
-// (see walk_pixel).
+//   8 = the walk took at least one near decision (see walk_pixel);
+// and, if `jump` is not NULL, the jump the pixel's near decisions straddle.
 // Mesh depth composition (Algorithm 1, DrawSplatsWithMeshDepth; Section
 // 3.4): with mesh_depth (one value per requested pixel, camera-space z of
 // the mesh surface; +inf where there is none), a Gaussian whose depth is

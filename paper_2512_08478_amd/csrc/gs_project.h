@@ -49,21 +49,30 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
   }
 }
 
-// Shared tail of the projection.  From the camera-space mean t (1/t_z in
-// iz), the world-space mean w, the 2-D covariance S = [[a, b], [b, c]]
-// (eps2d included) with determinant D and the opacity o: the 2-D mean, the
-// whitened form, the opacity-aware pixel bbox and tile rect (r0, r1.xy,
-// rect_lo/hi, trect) and the unit view direction for the colour, in the
-// asset's frame.  Returns the number of tiles touched (0: nothing drawn).
-__device__ __forceinline__ uint32_t footprint(float tx, float ty, float iz, float w0, float w1,
+// Shared tail of the projection.  From the camera-space mean t (float64;
+// 1/t_z in iz), the world-space mean w, the 2-D covariance S = [[a, b],
+// [b, c]] (eps2d included) with determinant D and the opacity o: the 2-D
+// mean, the whitened form, the opacity-aware pixel bbox and tile rect (r0,
+// r1.xy, rect_lo/hi, trect) and the unit view direction for the colour, in
+// the asset's frame.  Returns the number of tiles touched (0: nothing
+// drawn).
+//
+// The 2-D mean is formed in float64 and stored relative to the pixel bbox's
+// top-left corner (px0, py0): a pixel's offset from the mean is then an
+// exact small integer minus a float32 fraction, accurate to ~1e-7 px
+// anywhere in the image instead of the ~1e-4 px that a float32 absolute
+// position carries at x ~ 2000 (which moves the weight near alpha_min by
+// ~1e-4 relative for sharp splats).
+__device__ __forceinline__ uint32_t footprint(const double* t, float iz, float w0, float w1,
                                               float w2, float a, float b, float c, float D,
                                               float o, const CamK& cam, const SetK& set,
                                               float4& r0, float4& r1, uint32_t& rect_lo,
                                               uint32_t& rect_hi, uint2& trect, float* dir) {
-  const float mx = fmaf(cam.fx, tx * iz, cam.cx);
-  const float my = fmaf(cam.fy, ty * iz, cam.cy);
+  const double mxd = (double)cam.fx * (t[0] / t[2]) + (double)cam.cx;
+  const double myd = (double)cam.fy * (t[1] / t[2]) + (double)cam.cy;
   const bool ok = D > 0.f && c > 0.f && __builtin_isfinite(D) && __builtin_isfinite(a) &&
-                  __builtin_isfinite(mx) && __builtin_isfinite(my);
+                  __builtin_isfinite(mxd) && __builtin_isfinite(myd) && fabs(mxd) < 1e9 &&
+                  fabs(myd) < 1e9;
   if (!ok) return 0;
   const float qa = c / D, qb = b / c, qc = 1.f / c;
   // Opacity-aware bbox: o exp(-Q/2) >= tau inside the ellipse
@@ -71,12 +80,12 @@ __device__ __forceinline__ uint32_t footprint(float tx, float ty, float iz, floa
   // sqrt(qmax c).  Inflated slightly so that rounding can only add
   // tiles (an added tile holds no pixel with weight >= tau).
   const float qmax = 2.f * (logf(o) - logf(set.tau));
-  const float rx = sqrtf(qmax * a) * (1.f + 1e-5f) + 1e-3f + 1e-6f * fabsf(mx);
-  const float ry = sqrtf(qmax * c) * (1.f + 1e-5f) + 1e-3f + 1e-6f * fabsf(my);
-  float fx0 = ceilf(mx - rx - 0.5f), fx1 = floorf(mx + rx - 0.5f);
-  float fy0 = ceilf(my - ry - 0.5f), fy1 = floorf(my + ry - 0.5f);
-  fx0 = fmaxf(fx0, 0.f); fy0 = fmaxf(fy0, 0.f);
-  fx1 = fminf(fx1, (float)(cam.W - 1)); fy1 = fminf(fy1, (float)(cam.H - 1));
+  const double rx = (double)(sqrtf(qmax * a) * (1.f + 1e-5f) + 1e-3f);
+  const double ry = (double)(sqrtf(qmax * c) * (1.f + 1e-5f) + 1e-3f);
+  double fx0 = ceil(mxd - rx - 0.5), fx1 = floor(mxd + rx - 0.5);
+  double fy0 = ceil(myd - ry - 0.5), fy1 = floor(myd + ry - 0.5);
+  fx0 = fmax(fx0, 0.0); fy0 = fmax(fy0, 0.0);
+  fx1 = fmin(fx1, (double)(cam.W - 1)); fy1 = fmin(fy1, (double)(cam.H - 1));
   if (!(fx0 <= fx1 && fy0 <= fy1)) return 0;
   const int px0 = (int)fx0, px1 = (int)fx1, py0 = (int)fy0, py1 = (int)fy1;
   const int tx0 = px0 / set.tile_w, tx1 = px1 / set.tile_w;
@@ -94,25 +103,32 @@ __device__ __forceinline__ uint32_t footprint(float tx, float ty, float iz, floa
     const float e2 = cam.Rk[2] * d0 + cam.Rk[5] * d1 + cam.Rk[8] * d2;
     d0 = e0; d1 = e1; d2 = e2;
   }
-  r0 = make_float4(mx, my, qa, qb);
+  r0 = make_float4((float)(mxd - fx0), (float)(myd - fy0), qa, qb);
   r1 = make_float4(qc, o, 0.f, 0.f);
   dir[0] = d0; dir[1] = d1; dir[2] = d2;
   return (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 }
 
-// Asset-to-world (Algorithm 1's M_k) and world-to-camera transforms of a mean.
+// Asset-to-world (Algorithm 1's M_k) and world-to-camera transforms of a
+// mean.  The camera-space mean t is formed in float64: its float32 rounding
+// is the depth sort key (so keys are correctly rounded depths), and the 2-D
+// mean is projected from it.  w (the world mean, for the SH view
+// direction) is float32.
 __device__ __forceinline__ void place_mean(float p0, float p1, float p2, const CamK& cam,
-                                           float* w, float* t) {
-  float w0 = p0, w1 = p1, w2 = p2;
+                                           float* w, double* t) {
+  double w0 = p0, w1 = p1, w2 = p2;
   if (cam.has_model) {
-    w0 = fmaf(cam.A[0], p0, fmaf(cam.A[1], p1, fmaf(cam.A[2], p2, cam.A[3])));
-    w1 = fmaf(cam.A[4], p0, fmaf(cam.A[5], p1, fmaf(cam.A[6], p2, cam.A[7])));
-    w2 = fmaf(cam.A[8], p0, fmaf(cam.A[9], p1, fmaf(cam.A[10], p2, cam.A[11])));
+    w0 = fma((double)cam.A[0], (double)p0, fma((double)cam.A[1], (double)p1,
+             fma((double)cam.A[2], (double)p2, (double)cam.A[3])));
+    w1 = fma((double)cam.A[4], (double)p0, fma((double)cam.A[5], (double)p1,
+             fma((double)cam.A[6], (double)p2, (double)cam.A[7])));
+    w2 = fma((double)cam.A[8], (double)p0, fma((double)cam.A[9], (double)p1,
+             fma((double)cam.A[10], (double)p2, (double)cam.A[11])));
   }
-  w[0] = w0; w[1] = w1; w[2] = w2;
-  t[0] = fmaf(cam.V[0], w0, fmaf(cam.V[1], w1, fmaf(cam.V[2], w2, cam.V[3])));
-  t[1] = fmaf(cam.V[4], w0, fmaf(cam.V[5], w1, fmaf(cam.V[6], w2, cam.V[7])));
-  t[2] = fmaf(cam.V[8], w0, fmaf(cam.V[9], w1, fmaf(cam.V[10], w2, cam.V[11])));
+  w[0] = (float)w0; w[1] = (float)w1; w[2] = (float)w2;
+  t[0] = fma((double)cam.V[0], w0, fma((double)cam.V[1], w1, fma((double)cam.V[2], w2, (double)cam.V[3])));
+  t[1] = fma((double)cam.V[4], w0, fma((double)cam.V[5], w1, fma((double)cam.V[6], w2, (double)cam.V[7])));
+  t[2] = fma((double)cam.V[8], w0, fma((double)cam.V[9], w1, fma((double)cam.V[10], w2, (double)cam.V[11])));
 }
 
 // Each workgroup's (instances, visible) totals into its slot of `partial`

@@ -167,9 +167,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_packed(
     uint2 trect = make_uint2(0x0000FFFFu, 0u);      // empty tile rect
     float dir[3] = {0.f, 0.f, 0.f};
     const float o = f16_to_f32(po.y >> 16);
-    float w[3], t[3];
+    float w[3];
+    double t[3];
     place_mean(f16_to_f32(po.x), f16_to_f32(po.x >> 16), f16_to_f32(po.y), cam, w, t);
-    const float tx = t[0], ty = t[1], tz = t[2];
+    const float tx = (float)t[0], ty = (float)t[1], tz = (float)t[2];
     if ((tz > cam.znear) && (o >= set.tau) && __builtin_isfinite(tx) && __builtin_isfinite(ty)) {
       const double sxx = f16_to_f32(c0), sxy = f16_to_f32(c0 >> 16), sxz = f16_to_f32(c1),
                    syy = f16_to_f32(c1 >> 16), syz = f16_to_f32(c2), szz = f16_to_f32(c2 >> 16);
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_packed(
       const double e = set.eps2d;
       const double a = aa + e, c = cc + e;
       const double D = a * c - b * b;
-      tiles = footprint(tx, ty, iz, w[0], w[1], w[2], (float)a, (float)b, (float)c, (float)D, o,
+      tiles = footprint(t, iz, w[0], w[1], w[2], (float)a, (float)b, (float)c, (float)D, o,
                         cam, set, r0, r1, rect_lo, rect_hi, trect, dir);
       if (tiles) {
         float Y[16];

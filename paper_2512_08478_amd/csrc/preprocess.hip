@@ -57,9 +57,10 @@ __device__ __forceinline__ uint32_t project_one(
     float4& r2, uint2& trect, float* dir) {
   const float4 q = quats[i];
   const float lg = logits[i];
-  float w[3], t[3];
+  float w[3];
+  double t[3];
   place_mean(means[3 * i], means[3 * i + 1], means[3 * i + 2], cam, w, t);
-  const float tx = t[0], ty = t[1], tz = t[2];
+  const float tx = (float)t[0], ty = (float)t[1], tz = (float)t[2];
 
   const float o = 1.f / (1.f + expf(-lg));
   const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
@@ -116,7 +117,7 @@ __device__ __forceinline__ uint32_t project_one(
     const float x2 = det2(m0[0], m0[1], m1[0], m1[1]);
     const float D = fmaf(x0, x0, fmaf(x1, x1, x2 * x2)) +
                     set.eps2d * (aa + cc) + set.eps2d * set.eps2d;
-    tiles = footprint(tx, ty, iz, w[0], w[1], w[2], aa + set.eps2d, b, cc + set.eps2d, D, o, cam,
+    tiles = footprint(t, iz, w[0], w[1], w[2], aa + set.eps2d, b, cc + set.eps2d, D, o, cam,
                       set, r0, r1, rect_lo, rect_hi, trect, dir);
     if (!STAGED_SH && tiles) {
       float Y[16];

@@ -114,7 +114,7 @@ constexpr int kBatch = 64;  // splats per batch: one per lane
 template <bool DEPTH>
 struct StageT {
   float4 hdr[kBatch];      // qa', r, g, b
-  float4 aux[kBatch];      // qb, qc', my, 1 / opacity
+  float4 aux[kBatch];      // qb, qc', dy at the quadrant's first row, 1 / opacity
   float2 rows[kBatch][8];  // per quadrant row: log2(o) - qc' dy^2, and dx - qb dy at the
                            // quadrant's first column
   uint32_t gid[kBatch];    // Gaussian index
@@ -189,7 +189,7 @@ __device__ __forceinline__ int stage_batch(StageT<DEPTH>& S, bool valid, const S
                                            int lane) {
   const float4 a = r.a, b = r.b;
   const float c = r.c;
-  const float mx = a.x, my = a.y, qb = a.w;
+  const float mx = a.x, my = a.y, qb = a.w;  // mean relative to the bbox corner (px0, py0)
   const float qa_ = a.z * kHalfLog2e, qc_ = b.x * kHalfLog2e;
   const float lo = log2f(b.y);
   const int px0 = (int)(r.lo & 0xFFFFu), py0 = (int)(r.lo >> 16);
@@ -200,18 +200,21 @@ __device__ __forceinline__ int stage_batch(StageT<DEPTH>& S, bool valid, const S
   if (hit) {
     const int k = __builtin_popcountll(hits & ((1ull << lane) - 1ull));
     S.hdr[k] = make_float4(qa_, b.z, b.w, c);
+    // pixel offsets from the mean: exact integer differences from the bbox
+    // corner, minus the mean's (small) offset from it
+    const float uy = (float)(qy0 - py0) + 0.5f - my;  // dy at the quadrant's first row
     if constexpr (BWD) {  // only the backward's gradient terms and atomics read these
-      S.aux[k] = make_float4(qb, qc_, my, 1.f / b.y);
+      S.aux[k] = make_float4(qb, qc_, uy, 1.f / b.y);
       S.gid[k] = g;
     }
     S.pos[k] = pos;
     if constexpr (DEPTH) S.dep[k] = r.depth;
     // log2(o) - qc' dy^2 and dx - qb dy at the first column, per row
-    const float ux = (qx0 + 0.5f) - mx;
+    const float ux = (float)(qx0 - px0) + 0.5f - mx;
     float2 t[8];
 #pragma unroll
     for (int rr = 0; rr < 8; ++rr) {
-      const float dy = (qy0 + rr + 0.5f) - my;
+      const float dy = uy + (float)rr;
       t[rr] = make_float2(fmaf(-qc_, dy * dy, lo), fmaf(-qb, dy, ux));
     }
     float4* dst = reinterpret_cast<float4*>(S.rows[k]);
@@ -417,7 +420,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
   const int lx = lane & 7, row = lane >> 3;
   const int px = tx0 + lx, py = ty0 + row;
   const bool inside = px < W && py < H;
-  const float lxf = (float)lx, fy = py + 0.5f;
+  const float lxf = (float)lx, rowf = (float)row;
   const uint32_t start = ranges[2 * tile];
   const float log2_tau = set.log2_tau;
 
@@ -464,7 +467,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
     auto visit = [&](int k, float u, float e, const float4& h) {
       const bool take = S.pos[k] < mylast && e >= log2_tau;
       if (!ballot(take)) return;
-      const float4 x = S.aux[k];  // qb, qc', my, 1 / opacity
+      const float4 x = S.aux[k];  // qb, qc', dy at the quadrant's first row, 1 / opacity
       const float gw = take ? hw_exp2(e) : 0.f;
       const float alpha = __builtin_amdgcn_fmed3f(gw, 0.f, set.amax);  // as the forward
       const float om = 1.f - alpha;
@@ -483,7 +486,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
       // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y;
       // no gradient flows through alpha where the alpha_max clamp binds
-      const float dy = fy - x.z;
+      const float dy = x.z + rowf;
       const float dal = take && gw < set.amax ? dalpha : 0.f;
       const float gop = dal * gw * x.w;
       const float dQ = -kLn2 * gw * dal;  // dL/dQ'

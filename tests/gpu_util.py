@@ -7,17 +7,22 @@ SPLAT_DTYPE = np.dtype([("mx", "<f4"), ("my", "<f4"), ("qa", "<f4"), ("qb", "<f4
                         ("op", "<f4"), ("r", "<f4"), ("g", "<f4"), ("b", "<f4"), ("depth", "<f4"),
                         ("px0", "<u2"), ("py0", "<u2"), ("px1", "<u2"), ("py1", "<u2")])
 assert SPLAT_DTYPE.itemsize == 48
-_TILED = np.dtype(SPLAT_DTYPE.descr + [("tx0", "<i8"), ("ty0", "<i8"), ("tx1", "<i8"), ("ty1", "<i8")])
+_TILED = np.dtype([(nm, "<f8" if nm in ("mx", "my") else t) for nm, t in SPLAT_DTYPE.descr] +
+                  [("tx0", "<i8"), ("ty0", "<i8"), ("tx1", "<i8"), ("ty1", "<i8")])
 
 
 def splats_np(splats_u8, n, tile=(16, 16)):
-    """The records as a structured array, plus the tile rect (tx0, ty0,
-    tx1, ty1) of each record's pixel bbox for tiles of `tile` pixels
-    (culled records keep an empty rect, tx1 < tx0)."""
+    """The records as a structured array -- with the 2-D mean made absolute
+    (the record stores it relative to the pixel bbox corner (px0, py0)) in
+    float64 -- plus the tile rect (tx0, ty0, tx1, ty1) of each record's pixel
+    bbox for tiles of `tile` pixels (culled records keep an empty rect,
+    tx1 < tx0)."""
     raw = splats_u8[: n * 48].cpu().numpy().view(SPLAT_DTYPE)
     out = np.zeros(raw.shape, _TILED)
     for f in SPLAT_DTYPE.names:
         out[f] = raw[f]
+    out["mx"] = raw["mx"].astype(np.float64) + raw["px0"]
+    out["my"] = raw["my"].astype(np.float64) + raw["py0"]
     vis = raw["px1"] >= raw["px0"]
     tw, th = tile
     out["tx0"] = np.where(vis, raw["px0"] // tw, 1)
@@ -125,9 +130,11 @@ def compare_records(orc, rec, ref, cam):
     v = vis_o & vis_g
     d = ref.d[v]
     r = rec[v]
-    np.testing.assert_allclose(r["mx"], d[:, orc.D_MX], rtol=2e-6, atol=2e-3)
-    np.testing.assert_allclose(r["my"], d[:, orc.D_MY], rtol=2e-6, atol=2e-3)
-    np.testing.assert_allclose(r["depth"], d[:, orc.D_DEPTH], rtol=1e-6)
+    # the 2-D mean to 1e-4 px anywhere in the image (it enters the weight
+    # through the pixel offset), the depth (the sort key) to one float32 spacing
+    np.testing.assert_allclose(r["mx"], d[:, orc.D_MX], rtol=0, atol=1e-4)
+    np.testing.assert_allclose(r["my"], d[:, orc.D_MY], rtol=0, atol=1e-4)
+    np.testing.assert_allclose(r["depth"], d[:, orc.D_DEPTH], rtol=2.0 ** -23)
     np.testing.assert_allclose(r["op"], d[:, orc.D_OPAC], rtol=2e-6)
     np.testing.assert_allclose(np.stack([r["r"], r["g"], r["b"]], 1), d[:, orc.D_R:orc.D_B + 1], atol=2e-6)
     con = conic_from_whitened(r)

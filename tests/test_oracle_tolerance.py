@@ -84,40 +84,23 @@ def test_pair_max_weight_closed_form(orc, centre):
 
 # ---------------------------------------------------------------- near decisions
 
-def test_depth_error_scale_closed_form(orc):
-    # identity rotation, translation (0, 0, 1.5): t_z = z + 1.5, and the
-    # error scale is the sum of the magnitudes of its terms |z| + 1.5
-    V = np.eye(4, dtype=np.float32)
-    V[2, 3] = 1.5
-    cam = S.Camera(V, 30.0, 30.0, 8.0, 8.0, 16, 16, 0.2)
-    sc = one_scene([[0.1, -0.2, 2.0], [0.0, 0.0, -1.0]], math.log(0.05), 1.0, [0, 0, 0])
-    r = orc.preprocess(sc, cam)
-    np.testing.assert_allclose(r.d[:, orc.D_DEPTH], [3.5, 0.5], rtol=1e-15)
-    np.testing.assert_allclose(r.d[:, orc.D_ZSCALE], [3.5, 2.5], rtol=1e-15)
-
-
 def test_near_tie_flag_and_swap_jump(orc):
-    # Two Gaussians on the axis of a camera translated by -1.5 along z:
-    # depth = z - 1.5 = 2, error scale |z| + 1.5 = 5 each, so a near tie is a
-    # depth difference up to 2^-21 (5 + 5) = 4.8e-6.  Index 0 is the deeper
-    # one, so depth order and index order disagree.  At the pixel holding
-    # their mean (Q = 0, alpha = o) the order is a near decision: swapping
-    # two blends changes C by alpha_a alpha_b (c_a - c_b) and leaves T
-    # unchanged.  8 float32 steps (1.9e-6) apart they tie, 80 apart
-    # (1.9e-5) they do not.
-    V = np.eye(4, dtype=np.float32)
-    V[2, 3] = -1.5
-    cam = S.Camera(V, 30.0, 30.0, 8.5, 8.5, 16, 16, 0.2)
+    # Two Gaussians on the axis at depth ~3.5 (float32 spacing 2^-22), where
+    # a near tie is a difference up to 2^-22 (3.5 + 3.5) = 7 spacings.  Index
+    # 0 is the deeper one, so depth order and index order disagree.  At the
+    # pixel holding their mean (Q = 0, alpha = o) the order is a near
+    # decision: swapping two blends changes C by alpha_a alpha_b (c_a - c_b)
+    # and leaves T unchanged.  4 spacings apart they tie, 12 apart they do not.
+    cam = iso_camera(16, 16, 30.0, 8.5, 8.5)
     z = np.float32(3.5)
     ls, logits = math.log(0.05), [0.3, 1.2]
     dcs = [[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]]
-    for steps, tie in ((8, True), (80, False)):
+    for steps, tie in ((4, True), (12, False)):
         far = z
         for _ in range(steps):
             far = np.nextafter(far, np.float32(4.0))
         sc = one_scene([[0, 0, far], [0, 0, z]], ls, logits, dcs)
         r = orc.preprocess(sc, cam)
-        np.testing.assert_allclose(r.d[:, orc.D_ZSCALE], [float(far) + 1.5, 5.0], rtol=1e-15)
         out = orc.render_pixels(r, cam, [[8, 8], [0, 0]])
         a = [min(0.99, sigmoid32(l)) for l in logits]
         c = [rgb_of(dc) for dc in dcs]
@@ -125,6 +108,34 @@ def test_near_tie_flag_and_swap_jump(orc):
         expect = a[0] * a[1] * np.abs(c[0] - c[1]).max() if tie else 0.0
         assert out["jump"][0] == pytest.approx(expect, rel=1e-12, abs=1e-15)
         assert out["flags"][1] == 0 and out["jump"][1] == 0.0
+
+
+@pytest.mark.parametrize("tie", [True, False])
+def test_near_tie_across_the_stop(orc, tie):
+    # Three coincident Gaussians (alpha = 0.97) take T below t_eps, so the
+    # walk stops on the third; Gaussian 0 lies one float32 step deeper (a
+    # near tie; 100 steps apart it is not) and would blend next.  A float32
+    # order may take it first: walk G1, G2, B, G3 instead of G1, G2, G3.
+    # With T2 = (1 - a)^2: dC = T2 a_B (c_B - a c), dA = T2 (1 - a) a_B.
+    z = np.float32(2.0)
+    zb = z
+    for _ in range(1 if tie else 100):
+        zb = np.nextafter(zb, np.float32(3.0))
+    la, lb = math.log(0.97 / 0.03), 0.8
+    dcs = [[0.1, 0.9, 0.3], [1.2, 0.0, 0.5]]
+    sc = one_scene([[0, 0, zb], [0, 0, z], [0, 0, z], [0, 0, z]], math.log(0.05),
+                   [lb, la, la, la], [dcs[1], dcs[0], dcs[0], dcs[0]])
+    cam = iso_camera(16, 16, 30.0, 8.5, 8.5)
+    out = orc.render_pixels(orc.preprocess(sc, cam), cam, [[8, 8]])
+    a, ab = sigmoid32(la), sigmoid32(lb)
+    assert (1 - a) ** 2 >= 1e-4 > (1 - a) ** 3
+    assert out["n_blend"][0] == 3
+    # the coincident stack ties with itself (swaps of equal Gaussians: no jump)
+    assert out["flags"][0] & 1
+    T2 = (1 - a) ** 2
+    c, cb = rgb_of(dcs[0]), rgb_of(dcs[1])
+    expect = max(np.abs(T2 * ab * (cb - a * c)).max(), T2 * (1 - a) * ab) if tie else 0.0
+    assert out["jump"][0] == pytest.approx(expect, rel=1e-9, abs=1e-15)
 
 
 @pytest.mark.parametrize("rel,ambiguous", [(5e-6, True), (5e-5, False)])
