@@ -222,6 +222,28 @@ int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales,
                       void* stream);
 
 /*
+ * gs_preprocess_noalloc -- gs_preprocess without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same inputs,
+ * outputs and results as gs_preprocess (bit for bit).  Its per-workgroup
+ * partial counts live in a 1 MiB array inside the library, one copy per GPU,
+ * kept until the process ends; each call writes every slot it reads, so no
+ * clearing is needed.  The call allocates nothing (no hipMalloc, no library
+ * allocation).  n may be at most gs_preprocess_noalloc_max_n() (16,760,832);
+ * larger n returns GS_ERR_WORKSPACE before any HIP call.  Calls that overlap
+ * in time on one GPU (other streams, other host threads) share that array
+ * and race: serialise them.  The first call on a device looks up its copy's
+ * address once (hipGetSymbolAddress with that device current).
+ */
+int32_t gs_preprocess_noalloc(int64_t n, const float* means, const float* log_scales,
+                              const float* quats, const float* opacity_logits, const float* sh,
+                              int32_t sh_degree, const float* model, const gs_camera* cam,
+                              const gs_settings* set, gs_splat* splats, uint32_t* depth_keys,
+                              uint32_t* tile_rects, uint32_t* counts, void* stream);
+/* Largest n gs_preprocess_noalloc accepts. */
+int64_t gs_preprocess_noalloc_max_n(void);
+
+/*
  * One asset of a multi-asset scene (Algorithm 1 loops over models, each with
  * its own model matrix M_k, and feeds all of them to one global sort).  The
  * assets' Gaussians are concatenated in the parameter arrays: asset a owns

@@ -33,6 +33,7 @@ EXPORTED = (
     "gs_preprocess_assets", "gs_rasterize_backward_assets", "gs_rasterize_backward_2d",
     "gs_preprocess_backward_views", "gs_sort_pairs32", "gs_packed_sh_stride", "gs_prepack",
     "gs_preprocess_packed", "gs_rasterize_mesh", "gs_rasterize_backward_2d_mesh", "gs_lbs_deform",
+    "gs_preprocess_noalloc", "gs_preprocess_noalloc_max_n",
 )
 BWD_VIEWS_PER_LAUNCH = 8
 GRAD2D_STRIDE = 12  # floats per Gaussian in a 2-D gradient record
@@ -115,6 +116,10 @@ def load():
     lib.gs_sort_key_bits.argtypes = [CAM, SET]
     lib.gs_preprocess.restype = I32
     lib.gs_preprocess.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, P, SZ, P]
+    lib.gs_preprocess_noalloc.restype = I32
+    lib.gs_preprocess_noalloc.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, P]
+    lib.gs_preprocess_noalloc_max_n.restype = I64
+    lib.gs_preprocess_noalloc_max_n.argtypes = []
     lib.gs_sort.restype = I32
     lib.gs_sort.argtypes = [I64, P, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ, P]
     lib.gs_sort_pairs.restype = I32

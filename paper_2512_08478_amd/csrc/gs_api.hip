@@ -2,6 +2,7 @@
 // Every check runs before the first HIP call.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "gs_internal.h"
 
@@ -337,6 +338,54 @@ int32_t gs_preprocess(int64_t n, const float* means, const float* log_scales, co
   return gs_preprocess_assets(1, &one, n, means, log_scales, quats, opacity_logits, sh,
                               sh_degree, cam, set, splats, depth_keys, tile_rects, counts,
                               workspace, workspace_bytes, stream);
+}
+
+// Scratch of gs_preprocess_noalloc: the per-workgroup partial counts of up
+// to kNoAllocMaxBytes.  Each GPU the library runs on holds its own copy until
+// the process ends; host code reaches a device's copy only through the
+// address hipGetSymbolAddress returns on that device.
+namespace {
+constexpr size_t kNoAllocMaxBytes = (size_t)1 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocMaxBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's scratch address, looked up once per device.
+int32_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= kMaxDevices) return GS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    if (!p) return GS_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
+}
+}  // namespace
+
+int32_t gs_preprocess_noalloc(int64_t n, const float* means, const float* log_scales,
+                              const float* quats, const float* opacity_logits, const float* sh,
+                              int32_t sh_degree, const float* model, const gs_camera* cam,
+                              const gs_settings* set, gs_splat* splats, uint32_t* depth_keys,
+                              uint32_t* tile_rects, uint32_t* counts, void* stream) {
+  if (n < 0 || n >= kMaxN) return GS_ERR_INVALID_ARGUMENT;
+  if (gs::preprocess_ws_bytes(n) > kNoAllocMaxBytes) return GS_ERR_WORKSPACE;
+  void* ws = nullptr;
+  int32_t r;
+  if ((r = scratch_address(&ws))) return r;
+  return gs_preprocess(n, means, log_scales, quats, opacity_logits, sh, sh_degree, model, cam, set,
+                       splats, depth_keys, tile_rects, counts, ws, kNoAllocMaxBytes, stream);
+}
+
+int64_t gs_preprocess_noalloc_max_n(void) {
+  return (int64_t)(kNoAllocMaxBytes / 16 - gs::kMaxAssets) * gs::kBlock;
 }
 
 int32_t gs_packed_sh_stride(int32_t sh_degree) { return gs::packed_sh_stride(sh_degree); }

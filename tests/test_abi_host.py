@@ -315,3 +315,16 @@ def test_raster_order_validation_and_sort_workspace(lib):
     # the sort workspace holds 16 tile-class segments of `tiles` entries
     w = lib.gs_workspace_size(L.GS_STAGE_SORT, 1000, 1000, ctypes.byref(c), ctypes.byref(s))
     assert w >= 16 * 120 * 68 * 4
+
+
+def test_preprocess_noalloc_limits(lib):
+    """The allocation-free preprocess states its limit and rejects larger n
+    (and negative n) before any HIP call, so no pointers are needed."""
+    m = lib.gs_preprocess_noalloc_max_n()
+    assert m == (2**20 // 16 - L.MAX_ASSETS) * 256 == 16_760_832
+    s = L.default_settings()
+    c = L.make_camera(S.pinhole_camera(S.look_at((0, 0, -3)), 64, 64))
+    args = [None] * 5 + [0, None, ctypes.byref(c), ctypes.byref(s)] + [None] * 4 + [None]
+    assert lib.gs_preprocess_noalloc(m + 1, *args) == L.GS_ERR_WORKSPACE
+    assert lib.gs_preprocess_noalloc(-1, *args) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_preprocess_noalloc(2**31, *args) == L.GS_ERR_INVALID_ARGUMENT
