@@ -64,7 +64,8 @@ typedef struct gs_camera {
 /*
  * Constants the paper leaves open, with the defaults gs_default_settings()
  * fills in:
- *   tile_w x tile_h   8x8, 16x8, 16x16 (default), 32x8 or 32x16 pixels
+ *   tile_w x tile_h   8x8, 16x8, 16x16 (default), 32x8, 32x16, 32x32, 64x16
+ *                    or 64x32 pixels
  *   eps2d      0.3   px^2 added to the diagonal of the 2-D covariance S
  *   alpha_min  1/255 opacity cull (Algorithm 1) and per-pixel skip
  *   alpha_max  0.99  clamp of the pixel weight of Eq. 2

@@ -35,7 +35,7 @@ import torch
 from . import _lib as L
 from .render import GaussianParams, Renderer, depth_range_bits
 
-TILE_SHAPES = ((16, 16), (16, 8), (32, 8), (8, 8), (32, 16))
+TILE_SHAPES = ((16, 16), (16, 8), (32, 8), (8, 8), (32, 16), (32, 32), (64, 16), (64, 32))
 RADIX_BITS = (8, 7, 6)
 SORT_MODES = (0, 1)
 RASTER_ORDERS = (1, 0)

@@ -553,7 +553,8 @@ void raster_bwd(const gs_splat* splats, const uint32_t* values, const uint32_t* 
 
 bool tile_shape_supported(int tw, int th) {
   return (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 16 && th == 16) ||
-         (tw == 32 && th == 8) || (tw == 32 && th == 16);
+         (tw == 32 && th == 8) || (tw == 32 && th == 16) || (tw == 32 && th == 32) ||
+         (tw == 64 && th == 16) || (tw == 64 && th == 32);
 }
 
 hipError_t launch_rasterize(const gs_splat* splats, const uint32_t* values,
@@ -566,7 +567,10 @@ hipError_t launch_rasterize(const gs_splat* splats, const uint32_t* values,
   else if (tw == 16 && th == 8) GS_RF(16, 8);
   else if (tw == 16 && th == 16) GS_RF(16, 16);
   else if (tw == 32 && th == 8) GS_RF(32, 8);
-  else GS_RF(32, 16);
+  else if (tw == 32 && th == 16) GS_RF(32, 16);
+  else if (tw == 32 && th == 32) GS_RF(32, 32);
+  else if (tw == 64 && th == 16) GS_RF(64, 16);
+  else GS_RF(64, 32);
 #undef GS_RF
   return hipGetLastError();
 }
@@ -582,7 +586,10 @@ hipError_t launch_rasterize_backward(const gs_splat* splats, const uint32_t* val
   else if (tw == 16 && th == 8) GS_RB(16, 8);
   else if (tw == 16 && th == 16) GS_RB(16, 16);
   else if (tw == 32 && th == 8) GS_RB(32, 8);
-  else GS_RB(32, 16);
+  else if (tw == 32 && th == 16) GS_RB(32, 16);
+  else if (tw == 32 && th == 32) GS_RB(32, 32);
+  else if (tw == 64 && th == 16) GS_RB(64, 16);
+  else GS_RB(64, 32);
 #undef GS_RB
   return hipGetLastError();
 }

@@ -249,6 +249,7 @@ def expected_sorted_pairs_np(rec, tiles_x):
 
 
 @pytest.mark.parametrize("workload,shape,mode", [("medium", (32, 16, 7), 0), ("medium", (16, 16, 8), 0),
+                                                 ("medium", (64, 32, 6), 0), ("medium", (64, 16, 8), 1),
                                                  ("large", (8, 8, 8), 0), ("large", (16, 8, 6), 0),
                                                  ("medium", (16, 16, 8), 1), ("large", (8, 8, 8), 1)])
 def test_sort_keys_full_size(R, orc, workload, shape, mode):
@@ -358,7 +359,8 @@ def test_blend_counts_match_oracle(R, orc):
         print(f"n_blend mean {got.mean():.1f}, checked {int(ok.sum())} px")
 
 
-MEDIUM_CASES = [(v, (32, 16, 6)) for v in range(8)] + [(0, (16, 16, 8)), (0, (8, 8, 7))]
+MEDIUM_CASES = ([(v, (32, 16, 6)) for v in range(8)] + [(0, (16, 16, 8)), (0, (8, 8, 7)),
+                                                         (0, (64, 32, 6)), (3, (32, 32, 7))])
 
 
 @pytest.mark.parametrize("view,shape", MEDIUM_CASES)
@@ -432,7 +434,8 @@ def test_tile_shape_and_digit_width_invariance(R):
     base = R.forward(gp(sc), cam).image.cpu().numpy()
     for tw, th, bits, mode, order in [(8, 8, 8, 0, 0), (16, 8, 7, 1, 1), (32, 8, 6, 0, 0),
                                       (32, 16, 8, 1, 1), (16, 16, 6, 1, 0), (16, 16, 7, 0, 1),
-                                      (8, 8, 8, 0, 1), (32, 16, 7, 0, 0)]:
+                                      (8, 8, 8, 0, 1), (32, 16, 7, 0, 0), (32, 32, 6, 0, 1),
+                                      (64, 16, 7, 1, 1), (64, 32, 8, 0, 0), (64, 32, 6, 0, 1)]:
         img = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=mode,
                             raster_order=order)).forward(gp(sc), cam).image.cpu().numpy()
         np.testing.assert_array_equal(img, base,
