@@ -377,6 +377,41 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
                 void* stream);
 
 /*
+ * gs_sort_plan -- host-only description of the radix passes gs_sort makes
+ * for n Gaussians, `capacity` instances, this camera and these settings
+ * (no HIP call; for tests and tools).  passes[0 .. *n_passes) in launch
+ * order: the depth passes, then the tile passes (in sort mode 0 key
+ * generation performs the first tile pass itself).  Each pass: its index
+ * (also the parity of the look-back words it reads in mode 1: half
+ * pass % 2), digit width, which count bounds its keys (GS_PASS_KEYS_ALL:
+ * n; _VISIBLE: counts[1]; _INSTANCES: counts[0], at most capacity), and in
+ * mode 1 the keys per partition and the partitions its grid launches (its
+ * workgroups take partitions 0 .. grid_partitions-1 by ticket; a partition
+ * holds keys when its first key index is below the pass's key count).
+ * *lookback_words is the mode-1 look-back buffer (two halves), 0 in mode 0.
+ * A mode-1 pass reads words [0, partitions holding keys * 2^digit_bits) of
+ * its half, publishes the same words, and clears words
+ * [0, grid_partitions * 2^digit_bits) of the other half; gs_sort clears both
+ * halves before the first pass.  GS_ERR_INVALID_ARGUMENT when more than
+ * max_passes passes.
+ */
+typedef enum gs_pass_keys {
+  GS_PASS_KEYS_ALL = 0,
+  GS_PASS_KEYS_VISIBLE = 1,
+  GS_PASS_KEYS_INSTANCES = 2
+} gs_pass_keys;
+typedef struct gs_sort_pass {
+  int32_t pass;
+  int32_t digit_bits;
+  int32_t keys;            /* gs_pass_keys */
+  int32_t partition_keys;  /* mode 1; 0 in mode 0 */
+  int32_t grid_partitions; /* mode 1; 0 in mode 0 */
+} gs_sort_pass;
+int32_t gs_sort_plan(int64_t n, int64_t capacity, const gs_camera* cam, const gs_settings* set,
+                     int32_t max_passes, gs_sort_pass* passes, int32_t* n_passes,
+                     int64_t* lookback_words);
+
+/*
  * gs_sort_pairs -- the stable LSD radix sort on its own: sorts n
  * (key u64, value u32) pairs by the low `key_bits` bits of the key
  * (1..64; higher bits must be zero).  keys_in/values_in are not modified;
@@ -529,6 +564,126 @@ int32_t gs_preprocess_backward_views(
     const float* quats, const float* opacity_logits, const float* sh, int32_t sh_degree,
     const gs_settings* set, float* d_means, float* d_log_scales, float* d_quats,
     float* d_opacity_logits, float* d_sh, int32_t accumulate, void* stream);
+
+/*
+ * Batches of views (Algorithm 1 renders every model with one global sort;
+ * Section 4.5 argues for a single global order).  A batch renders
+ * n_views cameras of one scene (an asset table over n Gaussians, as in
+ * gs_preprocess_assets) and, with targets, differentiates the mean L1 loss
+ * of every view:
+ *   L = sum over views v of mean over (H_v, W_v, 3) of |RGB_v - target_v|,
+ * accumulating every view's gradient into one set of parameter gradients.
+ *
+ * The whole batch is a fixed sequence of launches on one stream, whatever
+ * the number of views: one preprocess launch over every (view, asset,
+ * Gaussian), one global sort whose tile keys cover every view (the views'
+ * tile grids are stacked as bands of tile rows of one grid, as wide as the
+ * widest view, so a key is band row * width + column), one compositing
+ * launch over every view's tiles (longest lists first, over all views),
+ * and with targets one loss-gradient launch, one compositing-backward
+ * launch and the chain rule (one launch per asset and 8 views).  Counts are
+ * read on the device; only gs_batch_plan syncs.  Images equal those of
+ * single-view calls with the same settings, bit for bit.
+ *
+ * Sequence: gs_batch_create (host only; copies the tables) ->
+ * gs_batch_plan (one counting pass and one sync: the instance capacity and
+ * the depth key bits, each with headroom) -> gs_batch_workspace_size(b,
+ * capacity) bytes of workspace -> gs_batch_run (eager) or
+ * gs_batch_capture (the same launches recorded into a HIP graph by stream
+ * capture on `stream`, instantiated and kept in the batch) and
+ * gs_batch_launch (one graph launch).  status_flag (device u32, or NULL)
+ * gets bit 0 when a frame needs more instances than planned and bit 1
+ * when its depth key range outgrows the planned bits (then plan again; the
+ * images are not valid).  The workspace, outputs and status flag bound at
+ * capture are the ones every launch uses; they must stay allocated, and
+ * the parameters and targets keep their addresses (their values may
+ * change between launches; plan again if they change much).
+ *
+ * Layout of the per-pixel arrays: view v's H_v x W_v pixels start at pixel
+ * gs_batch_pixel_offset(b, v); images hold 4 floats per pixel (RGBA),
+ * targets 3 (RGB); gs_batch_pixels(b) pixels in all.
+ */
+typedef struct gs_batch gs_batch;
+typedef struct gs_batch_desc {
+  int32_t n_views;
+  const gs_camera* cams;    /* host, n_views */
+  int32_t n_assets;
+  const gs_asset* assets;   /* host; model transforms copied */
+  int64_t n;                /* Gaussians of all assets */
+  const float* means;       /* device: the gs_preprocess inputs */
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* sh;
+  int32_t sh_degree;
+  const float* targets;     /* device RGB targets, or NULL: forward only */
+} gs_batch_desc;
+
+/* Validates the description (the gs_preprocess_assets checks for every
+ * camera; at most 256 views) and makes the batch: host memory, plus one
+ * small pinned host block (hipHostMalloc) holding the camera and view
+ * tables that every run copies into the workspace, so that the copy is
+ * ordered on the stream.  No device memory.  GS_ERR_UNSUPPORTED when the
+ * stacked tile grid exceeds 65535 tile rows or 2^26 tiles; GS_ERR_HIP when
+ * the pinned block cannot be allocated. */
+int32_t gs_batch_create(const gs_batch_desc* desc, const gs_settings* set, gs_batch** batch);
+/* Frees the batch and its graph; call it once no work of the batch is
+ * pending on any stream. */
+void gs_batch_destroy(gs_batch* batch);
+int64_t gs_batch_pixels(const gs_batch* batch);
+int64_t gs_batch_pixel_offset(const gs_batch* batch, int32_t view);
+/* The planned instance capacity (-1 before gs_batch_plan). */
+int64_t gs_batch_capacity(const gs_batch* batch);
+/* Workspace bytes for an instance capacity (capacity 0: enough for
+ * gs_batch_plan). */
+size_t gs_batch_workspace_size(const gs_batch* batch, int64_t capacity);
+/* Counting pass: preprocesses every view into the workspace, waits for the
+ * stream, and sets the capacity to ceil(instances * headroom) (at least
+ * 256; headroom in [1, 4]) and the depth key bits to the visible range's
+ * bit length plus one.  *capacity receives the capacity.
+ * GS_ERR_CAPACITY when it would exceed 2^30 - 1 instances. */
+int32_t gs_batch_plan(gs_batch* batch, float headroom, void* workspace, size_t workspace_bytes,
+                      int64_t* capacity, void* stream);
+/* The batch, eagerly: images[pixels * 4] and, with targets, the parameter
+ * gradients (overwritten; laid out like the inputs). */
+int32_t gs_batch_run(gs_batch* batch, void* workspace, size_t workspace_bytes, float* images,
+                     float* d_means, float* d_log_scales, float* d_quats,
+                     float* d_opacity_logits, float* d_sh, uint32_t* status_flag, void* stream);
+/* gs_batch_run recorded into a HIP graph (stream capture on `stream`, which
+ * must not be NULL) and instantiated; nothing runs until gs_batch_launch. */
+int32_t gs_batch_capture(gs_batch* batch, void* workspace, size_t workspace_bytes, float* images,
+                         float* d_means, float* d_log_scales, float* d_quats,
+                         float* d_opacity_logits, float* d_sh, uint32_t* status_flag,
+                         void* stream);
+/* One launch of the captured graph on `stream`. */
+int32_t gs_batch_launch(gs_batch* batch, void* stream);
+
+/*
+ * gs_autotune -- picks tile shape, digit width, sort mode and compositing
+ * order for a batch by timing whole batches (HIP events; `reps` timed
+ * batches after a warm one): a coordinate search from `base`, one
+ * dimension at a time in that order, each over its listed values.  Results
+ * never depend on these settings, so tuning cannot change an image.
+ * Candidates whose workspace exceeds workspace_bytes are skipped.  Syncs
+ * the stream once per candidate.  *best, *best_ms and *evaluated
+ * (candidates timed; may be NULL) receive the result; GS_ERR_WORKSPACE when
+ * no candidate fits.
+ */
+typedef struct gs_autotune_space {
+  int32_t n_tiles;
+  int32_t tiles[32];        /* (tile_w, tile_h) pairs */
+  int32_t n_bits;
+  int32_t bits[8];          /* radix digit widths */
+  int32_t n_modes;
+  int32_t modes[2];         /* sort modes */
+  int32_t n_orders;
+  int32_t orders[2];        /* compositing orders */
+} gs_autotune_space;
+int32_t gs_autotune(const gs_batch_desc* desc, const gs_settings* base,
+                    const gs_autotune_space* space, int32_t reps, float headroom, void* workspace,
+                    size_t workspace_bytes, float* images, float* d_means, float* d_log_scales,
+                    float* d_quats, float* d_opacity_logits, float* d_sh, uint32_t* status_flag,
+                    gs_settings* best, float* best_ms, int32_t* evaluated, void* stream);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,10 @@ EXPORTED = (
     "gs_preprocess_assets", "gs_rasterize_backward_assets", "gs_rasterize_backward_2d",
     "gs_preprocess_backward_views", "gs_sort_pairs32", "gs_packed_sh_stride", "gs_prepack",
     "gs_preprocess_packed", "gs_rasterize_mesh", "gs_rasterize_backward_2d_mesh", "gs_lbs_deform",
-    "gs_preprocess_noalloc", "gs_preprocess_noalloc_max_n",
+    "gs_preprocess_noalloc", "gs_preprocess_noalloc_max_n", "gs_sort_plan",
+    "gs_batch_create", "gs_batch_destroy", "gs_batch_pixels", "gs_batch_pixel_offset",
+    "gs_batch_capacity", "gs_batch_workspace_size", "gs_batch_plan", "gs_batch_run",
+    "gs_batch_capture", "gs_batch_launch", "gs_autotune",
 )
 BWD_VIEWS_PER_LAUNCH = 8
 GRAD2D_STRIDE = 12  # floats per Gaussian in a 2-D gradient record
@@ -52,6 +55,29 @@ class GsError(RuntimeError):
         if status == GS_ERR_HIP:
             msg += f", hipError {hip_error}"
         super().__init__(msg + ")")
+
+
+class GsSortPass(ctypes.Structure):
+    _fields_ = [("pass_", ctypes.c_int32), ("digit_bits", ctypes.c_int32), ("keys", ctypes.c_int32),
+                ("partition_keys", ctypes.c_int32), ("grid_partitions", ctypes.c_int32)]
+
+
+GS_PASS_KEYS_ALL, GS_PASS_KEYS_VISIBLE, GS_PASS_KEYS_INSTANCES = 0, 1, 2
+
+
+class GsBatchDesc(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int32), ("cams", ctypes.c_void_p), ("n_assets", ctypes.c_int32),
+                ("assets", ctypes.c_void_p), ("n", ctypes.c_int64), ("means", ctypes.c_void_p),
+                ("log_scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacity_logits", ctypes.c_void_p), ("sh", ctypes.c_void_p),
+                ("sh_degree", ctypes.c_int32), ("targets", ctypes.c_void_p)]
+
+
+class GsAutotuneSpace(ctypes.Structure):
+    _fields_ = [("n_tiles", ctypes.c_int32), ("tiles", ctypes.c_int32 * 32),
+                ("n_bits", ctypes.c_int32), ("bits", ctypes.c_int32 * 8),
+                ("n_modes", ctypes.c_int32), ("modes", ctypes.c_int32 * 2),
+                ("n_orders", ctypes.c_int32), ("orders", ctypes.c_int32 * 2)]
 
 
 class GsCamera(ctypes.Structure):
@@ -118,6 +144,29 @@ def load():
     lib.gs_preprocess.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, P, SZ, P]
     lib.gs_preprocess_noalloc.restype = I32
     lib.gs_preprocess_noalloc.argtypes = [I64, P, P, P, P, P, I32, P, CAM, SET, P, P, P, P, P]
+    lib.gs_batch_create.restype = I32
+    lib.gs_batch_create.argtypes = [P, SET, P]
+    lib.gs_batch_destroy.restype = None
+    lib.gs_batch_destroy.argtypes = [P]
+    for nm in ("gs_batch_pixels", "gs_batch_capacity"):
+        getattr(lib, nm).restype = I64
+        getattr(lib, nm).argtypes = [P]
+    lib.gs_batch_pixel_offset.restype = I64
+    lib.gs_batch_pixel_offset.argtypes = [P, I32]
+    lib.gs_batch_workspace_size.restype = SZ
+    lib.gs_batch_workspace_size.argtypes = [P, I64]
+    lib.gs_batch_plan.restype = I32
+    lib.gs_batch_plan.argtypes = [P, ctypes.c_float, P, SZ, P, P]
+    for nm in ("gs_batch_run", "gs_batch_capture"):
+        getattr(lib, nm).restype = I32
+        getattr(lib, nm).argtypes = [P, P, SZ, P, P, P, P, P, P, P, P]
+    lib.gs_batch_launch.restype = I32
+    lib.gs_batch_launch.argtypes = [P, P]
+    lib.gs_autotune.restype = I32
+    lib.gs_autotune.argtypes = [P, SET, P, I32, ctypes.c_float, P, SZ, P, P, P, P, P, P, P, SET,
+                                P, P, P]
+    lib.gs_sort_plan.restype = I32
+    lib.gs_sort_plan.argtypes = [I64, I64, CAM, SET, I32, P, P, P]
     lib.gs_preprocess_noalloc_max_n.restype = I64
     lib.gs_preprocess_noalloc_max_n.argtypes = []
     lib.gs_sort.restype = I32
@@ -232,3 +281,16 @@ def model_array(model):
     if len(flat) != 12:
         raise ValueError("model transform must be 3x4")
     return (ctypes.c_float * 12)(*flat)
+
+
+def sort_plan(n, capacity, cam, settings, max_passes=32):
+    """gs_sort_plan: (list of pass dicts, look-back words)."""
+    lib = load()
+    c = make_camera(cam)
+    out = (GsSortPass * max_passes)()
+    cnt = ctypes.c_int32(0)
+    words = ctypes.c_int64(0)
+    check(lib.gs_sort_plan(n, capacity, ctypes.byref(c), ctypes.byref(settings), max_passes, out,
+                           ctypes.byref(cnt), ctypes.byref(words)), "gs_sort_plan")
+    return ([dict(index=o.pass_, digit_bits=o.digit_bits, keys=o.keys, partition_keys=o.partition_keys,
+                  grid_partitions=o.grid_partitions) for o in out[:cnt.value]], words.value)

@@ -1,45 +1,37 @@
-"""Batched multi-view, multi-asset forward + backward in one HIP graph.
+"""Batched multi-view, multi-asset forward + backward: a marshaller over
+the library's batch entry points (gs_batch_create / gs_batch_plan /
+gs_batch_capture / gs_batch_launch, gs_autotune).
 
-Every view renders all assets of the scene with one global depth order
-(Algorithm 1 feeds every model's Gaussians to one sort), then runs the
-hand-written backward; gradients of all views add up in one set of
-parameter-gradient buffers.  Each view's compositing backward leaves a
-48-byte 2-D gradient record per Gaussian; every 8 views, one multi-view
-chain-rule pass turns those records into input gradients, reading and
-writing each Gaussian's parameter gradient once for the 8 views instead of
-once per view.  `BatchRenderer.capture()` records the whole batch -- every
-view's preprocess, sort, compositing, loss gradient and backward -- into
-one HIP graph (through torch's graph capture, on the library's stream), so
-a step is a single graph launch with no host synchronisation.  Instance capacities are planned beforehand from one
-counting pass; a view that exceeds its capacity raises its overflow flag,
-which `replay()` checks.
+The library renders every view of a batch in one fixed sequence of
+launches on one stream: one preprocess launch over every (view, asset,
+Gaussian), one global sort whose tile keys cover every view (Algorithm 1
+feeds every model's Gaussians to one sort; here every view's too), one
+compositing launch over every view's tiles, then the L1 loss gradient, one
+compositing-backward launch and the chain rule.  `BatchRenderer.capture()`
+records that sequence into one HIP graph (stream capture inside the
+library); a step is one graph launch with no host synchronisation.
+Instance capacity and depth key bits are planned once from one counting
+pass; a batch that outgrows them raises a bit of the status flag, which
+`replay()` checks.
 
-Views of one 8-view chunk can run on several HIP streams at once (one
-Renderer, with its own buffers, per stream; the chunk's chain rule joins
-them): a view's sort is a chain of small latency-bound kernels, which
-another view's compositing overlaps.  Captured, the streams become
-parallel branches of the graph.
-
-`autotune()` picks the tile shape and the radix digit width (and sort mode,
-compositing order and stream count) by timing whole batches.  Images do
-not depend on these choices (every tile shape composites the same pairs in
-the same order with the same arithmetic), so tuning never changes results.
+`autotune()` picks tile shape, digit width, sort mode and compositing order
+with the library's gs_autotune (a coordinate search over whole batches).
+Images do not depend on these choices, so tuning never changes results.
 """
 from __future__ import annotations
 
-import contextlib
+import ctypes
 import time
 
 import torch
 
 from . import _lib as L
-from .render import GaussianParams, Renderer, depth_range_bits
+from .render import GaussianParams, Renderer
 
 TILE_SHAPES = ((16, 16), (16, 8), (32, 8), (8, 8), (32, 16), (32, 32), (64, 16), (64, 32))
 RADIX_BITS = (8, 7, 6)
 SORT_MODES = (0, 1)
 RASTER_ORDERS = (1, 0)
-STREAM_COUNTS = (1, 2, 4)
 
 
 def l1_grad(image, target):
@@ -50,124 +42,134 @@ def l1_grad(image, target):
     return g
 
 
-class BatchRenderer:
-    """Views x assets forward + backward with fixed per-view capacities."""
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
-    def __init__(self, params: GaussianParams, cams, targets, settings=None, headroom=1.10,
-                 device="cuda", streams=None):
-        if len(cams) != len(targets):
+
+class _Desc:
+    """A gs_batch_desc and the host buffers it points to."""
+
+    def __init__(self, params: GaussianParams, cams, targets):
+        table = params.assets if params.assets is not None else [(0, params.n, params.model)]
+        self.cams = (L.GsCamera * len(cams))(*[L.make_camera(c) for c in cams])
+        self.assets, self._keep = L.asset_table(table)
+        self.targets = targets
+        d = L.GsBatchDesc()
+        d.n_views = len(cams)
+        d.cams = ctypes.cast(self.cams, ctypes.c_void_p)
+        d.n_assets = len(table)
+        d.assets = ctypes.cast(self.assets, ctypes.c_void_p)
+        d.n = params.n
+        d.means, d.log_scales, d.quats, d.opacity_logits, d.sh = [t.data_ptr() for t in params.tensors()]
+        d.sh_degree = params.sh_degree
+        d.targets = targets.data_ptr() if targets is not None else None
+        self.desc = d
+
+
+class BatchRenderer:
+    """Views x assets forward (+ L1 backward with targets) as one batch."""
+
+    def __init__(self, params: GaussianParams, cams, targets=None, settings=None, headroom=1.10,
+                 device="cuda"):
+        if targets is not None and len(cams) != len(targets):
             raise ValueError("one target image per view")
-        settings = dict(settings or {})
-        nst = int(settings.pop("streams", 1) if streams is None else streams)
-        settings.pop("streams", None)
-        if nst < 1:
-            raise ValueError("streams must be >= 1")
+        self.lib = L.load()
         self.p = params
         self.cams = list(cams)
-        self.targets = [t.to(device=device, dtype=torch.float32).contiguous() for t in targets]
-        # one Renderer (its own reusable buffers) per stream; streams at the
-        # default priority
-        self.Rs = [Renderer(settings, device) for _ in range(nst)]
-        self.R = self.Rs[0]
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(nst)] if nst > 1 else []
+        self.settings = L.default_settings(**(settings or {}))
         self.headroom = headroom
-        self.capacity = None
-        self.depth_bits = None   # per view, from plan() (None: all 32 bits)
-        self.graph = None
-        self.images = None
+        self.device = device
+        tg = None
+        if targets is not None:
+            tg = torch.cat([t.to(device=device, dtype=torch.float32).reshape(-1) for t in targets])
+        self._d = _Desc(params, self.cams, tg)
+        h = ctypes.c_void_p()
+        L.check(self.lib.gs_batch_create(ctypes.byref(self._d.desc), ctypes.byref(self.settings),
+                                         ctypes.byref(h)), "gs_batch_create")
+        self.h = h
+        self.pixels = int(self.lib.gs_batch_pixels(h))
+        self.offsets = [int(self.lib.gs_batch_pixel_offset(h, v)) for v in range(len(self.cams))]
+        self.image_buf = torch.empty(self.pixels * 4, dtype=torch.float32, device=device)
+        self.images = [self.image_buf[4 * o:4 * (o + c.width * c.height)].view(c.height, c.width, 4)
+                       for o, c in zip(self.offsets, self.cams)]
         self.grads = tuple(torch.zeros_like(t) for t in params.tensors())
-        self.flags = torch.zeros(len(self.cams), dtype=torch.int32, device=device)
-        self.chunk = L.BWD_VIEWS_PER_LAUNCH
-        self.g2d = [torch.empty((params.n, L.GRAD2D_STRIDE), dtype=torch.float32, device=device)
-                    for _ in range(min(self.chunk, len(self.cams)))]
+        self.flag = torch.zeros(1, dtype=torch.int32, device=device)
+        self.ws = None
+        self.capacity = None
+        # the library's launches and captures run on a stream of their own
+        # (a graph cannot be captured on the legacy default stream)
+        self.stream = torch.cuda.Stream(device=device)
+        self.captured = False
 
-    @property
-    def settings(self):
-        s = self.R.settings
-        return dict(tile_w=s.tile_w, tile_h=s.tile_h, radix_bits=s.radix_bits,
-                    sort_mode=s.sort_mode, raster_order=s.raster_order, streams=len(self.Rs))
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.gs_batch_destroy(h)
+            self.h = None
+
+    def _st(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def _outs(self):
+        g = self.grads if self._d.targets is not None else (None,) * 5
+        return [_p(self.image_buf)] + [_p(t) for t in g] + [_p(self.flag)]
 
     def plan(self):
-        """Per-view instance capacities and depth key bits from one counting
-        pass (syncs once per view)."""
-        caps, bits = [], []
-        for cam in self.cams:
-            _, _, _, counts = self.R.preprocess(self.p, cam)
-            cn = [int(x) & 0xFFFFFFFF for x in counts[:4].tolist()]
-            caps.append(cn[0])
-            bits.append(depth_range_bits(cn))
-        self.capacity = [max(256, int(c * self.headroom)) for c in caps]
-        self.depth_bits = bits
-        return list(caps)
-
-    def _enqueue(self):
-        """All views' forward + backward, forked from and joined back into
-        the current stream per chunk; no host sync."""
-        images = []
-        main = torch.cuda.current_stream()
-        nst = len(self.Rs)
-        for v0 in range(0, len(self.cams), self.chunk):
-            cams = self.cams[v0:v0 + self.chunk]
-            for st in self.streams:
-                st.wait_stream(main)
-            for k, cam in enumerate(cams):
-                v = v0 + k
-                R = self.Rs[k % nst]
-                ctx = torch.cuda.stream(self.streams[k % nst]) if self.streams else contextlib.nullcontext()
-                with ctx:
-                    fr = R.forward(self.p, cam, capacity=self.capacity[v],
-                                   depth_bits=self.depth_bits[v] if self.depth_bits else None)
-                    self.flags[v:v + 1].copy_(fr.flag)
-                    g = l1_grad(fr.image, self.targets[v])
-                    R.backward_2d(self.p, cam, fr, g, self.g2d[k])
-                if self.streams:
-                    fr.image.record_stream(main)
-                images.append(fr.image)
-            for st in self.streams:
-                main.wait_stream(st)
-            self.R.backward_views(self.p, cams, self.g2d[:len(cams)], out=self.grads,
-                                  accumulate=v0 > 0)
-        return images
+        """Instance capacity and depth key bits from one counting pass (one
+        sync); sizes the workspace."""
+        lib = self.lib
+        need = lib.gs_batch_workspace_size(self.h, 0)
+        ws = self.ws if self.ws is not None and self.ws.numel() >= need else \
+            torch.empty(need, dtype=torch.uint8, device=self.device)
+        cap = ctypes.c_int64(0)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(lib.gs_batch_plan(self.h, ctypes.c_float(self.headroom), _p(ws), ws.numel(),
+                                  ctypes.byref(cap), self._st()), "gs_batch_plan")
+        self.capacity = int(cap.value)
+        need = lib.gs_batch_workspace_size(self.h, self.capacity)
+        if ws.numel() < need:
+            del ws
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self.ws = ws
+        self.captured = False
+        return self.capacity
 
     def run_eager(self):
-        """One batch without a graph (sizes every reusable buffer)."""
+        """One batch without a graph."""
         if self.capacity is None:
             self.plan()
-        self.images = self._enqueue()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(self.lib.gs_batch_run(self.h, _p(self.ws), self.ws.numel(), *self._outs(), self._st()),
+                "gs_batch_run")
+        torch.cuda.current_stream().wait_stream(self.stream)
         return self.images
 
     def capture(self):
-        """Record the whole batch into one HIP graph."""
+        """Record the whole batch into one HIP graph (inside the library)."""
         if self.capacity is None:
             self.plan()
-        # an eager pass first: grows every reusable buffer to its final size,
-        # so nothing is reallocated while capturing
-        self.run_eager()
-        torch.cuda.synchronize()
-        self._check_flags()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self.images = self._enqueue()
-        self.graph = g
-        return g
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(self.lib.gs_batch_capture(self.h, _p(self.ws), self.ws.numel(), *self._outs(),
+                                          self._st()), "gs_batch_capture")
+        self.captured = True
 
     def replay(self, check=True):
-        if self.graph is None:
+        if not self.captured:
             raise RuntimeError("capture() first")
-        self.graph.replay()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(self.lib.gs_batch_launch(self.h, self._st()), "gs_batch_launch")
+        torch.cuda.current_stream().wait_stream(self.stream)
         if check:
             torch.cuda.synchronize()
             self._check_flags()
         return self.images
 
     def _check_flags(self):
-        bad = torch.nonzero(self.flags & 1).flatten().tolist()
-        if bad:
-            raise RuntimeError(f"instance capacity exceeded in views {bad}; plan() again "
-                               f"with more headroom")
-        bad = torch.nonzero(self.flags & 2).flatten().tolist()
-        if bad:
-            raise RuntimeError(f"depth key range wider than planned in views {bad}; plan() again")
+        f = int(self.flag.item()) & 0xFFFFFFFF
+        if f & 1:
+            raise RuntimeError("instance capacity exceeded; plan() again with more headroom")
+        if f & 2:
+            raise RuntimeError("depth key range wider than planned; plan() again")
 
 
 def plain_views(params: GaussianParams, cams, targets, settings=None, renderer=None):
@@ -178,70 +180,61 @@ def plain_views(params: GaussianParams, cams, targets, settings=None, renderer=N
     images = []
     for v, cam in enumerate(cams):
         fr = R.forward(params, cam)
-        g = l1_grad(fr.image, targets[v].to(device=fr.image.device, dtype=torch.float32))
-        R.backward(params, cam, fr, g, out=grads, accumulate=v > 0)
+        if targets is not None:
+            g = l1_grad(fr.image, targets[v].to(device=fr.image.device, dtype=torch.float32))
+            R.backward(params, cam, fr, g, out=grads, accumulate=v > 0)
         images.append(fr.image.clone())
     return images, grads
 
 
-def _time_batch(br: BatchRenderer, reps: int):
-    br.run_eager()
-    torch.cuda.synchronize()
-    br._check_flags()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        br.run_eager()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps
-
-
-def autotune(params: GaussianParams, cams, targets, base_settings=None, reps=2,
+def autotune(params: GaussianParams, cams, targets=None, base_settings=None, reps=2,
              tiles=TILE_SHAPES, bits=RADIX_BITS, modes=SORT_MODES, orders=RASTER_ORDERS,
-             streams=STREAM_COUNTS, log=None):
-    """Coordinate search: the number of streams (at the first tile shape,
-    8-bit digits, mode 0), then tile shape, digit width, sort mode and the
-    compositing order of the tiles, each by the wall time of whole eager
-    batches.  Streams come first because they change what the other
-    settings trade against (an overlapped sort costs less).  Returns
-    (settings dict, [(settings, seconds)])."""
+             headroom=1.10, log=None):
+    """The library's batch autotuner (gs_autotune): a coordinate search over
+    tile shape, digit width, sort mode and compositing order from
+    `base_settings`, timing `reps` whole batches per candidate.  The
+    workspace is sized for the largest candidate (one counting pass per
+    tile shape).  Returns (settings dict, best ms per batch, candidates
+    timed)."""
+    lib = L.load()
     base = dict(base_settings or {})
-    table = []
-
-    def measure(over):
-        s = dict(base, **over)
-        br = BatchRenderer(params, cams, targets, s)
+    base.setdefault("tile_w", tiles[0][0])
+    base.setdefault("tile_h", tiles[0][1])
+    need = 0
+    for tw, th in {(base["tile_w"], base["tile_h"]), *tiles}:
+        br = BatchRenderer(params, cams, targets, dict(base, tile_w=tw, tile_h=th), headroom)
         br.plan()
-        t = _time_batch(br, reps)
-        table.append((dict(over), t))
-        if log:
-            log(f"autotune {over}: {t * 1e3:.2f} ms per batch")
+        need = max(need, br.ws.numel())
         del br
-        return t
-
-    best = dict(tile_w=tiles[0][0], tile_h=tiles[0][1], radix_bits=bits[0], sort_mode=modes[0],
-                raster_order=orders[0], streams=streams[0])
-    best_t = None
-    for n in streams:
-        t = measure(dict(best, streams=n))
-        if best_t is None or t < best_t:
-            best_t, best = t, dict(best, streams=n)
-    for tw, th in tiles[1:]:
-        t = measure(dict(best, tile_w=tw, tile_h=th))
-        if t < best_t:
-            best_t, best = t, dict(best, tile_w=tw, tile_h=th)
-    for b in bits[1:]:
-        t = measure(dict(best, radix_bits=b))
-        if t < best_t:
-            best_t, best = t, dict(best, radix_bits=b)
-    for m in modes[1:]:
-        t = measure(dict(best, sort_mode=m))
-        if t < best_t:
-            best_t, best = t, dict(best, sort_mode=m)
-    for o in orders[1:]:
-        t = measure(dict(best, raster_order=o))
-        if t < best_t:
-            best_t, best = t, dict(best, raster_order=o)
-    return dict(base, **best), table
+    probe = BatchRenderer(params, cams, targets, base, headroom)
+    ws = torch.empty(need, dtype=torch.uint8, device=probe.device)
+    sp = L.GsAutotuneSpace()
+    sp.n_tiles = len(tiles)
+    for k, (tw, th) in enumerate(tiles):
+        sp.tiles[2 * k], sp.tiles[2 * k + 1] = tw, th
+    sp.n_bits = len(bits)
+    for k, b in enumerate(bits):
+        sp.bits[k] = b
+    sp.n_modes = len(modes)
+    for k, m in enumerate(modes):
+        sp.modes[k] = m
+    sp.n_orders = len(orders)
+    for k, o in enumerate(orders):
+        sp.orders[k] = o
+    best = L.GsSettings()
+    ms = ctypes.c_float(0)
+    nev = ctypes.c_int32(0)
+    probe.stream.wait_stream(torch.cuda.current_stream())
+    L.check(lib.gs_autotune(ctypes.byref(probe._d.desc), ctypes.byref(probe.settings),
+                            ctypes.byref(sp), reps, ctypes.c_float(headroom), _p(ws), ws.numel(),
+                            *probe._outs(), ctypes.byref(best), ctypes.byref(ms),
+                            ctypes.byref(nev), probe._st()), "gs_autotune")
+    torch.cuda.current_stream().wait_stream(probe.stream)
+    out = dict(base, tile_w=best.tile_w, tile_h=best.tile_h, radix_bits=best.radix_bits,
+               sort_mode=best.sort_mode, raster_order=best.raster_order)
+    if log:
+        log(f"gs_autotune: {out} at {ms.value:.3f} ms per batch ({nev.value} candidates timed)")
+    return out, float(ms.value), int(nev.value)
 
 
 def autotune_view(params: GaussianParams, cam, backward=False, target=None, reps=3,

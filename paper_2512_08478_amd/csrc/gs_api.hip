@@ -1,8 +1,10 @@
 // C ABI of libgs: argument validation, workspace layout and launch order.
 // Every check runs before the first HIP call.
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "gs_internal.h"
 
@@ -37,6 +39,7 @@ thread_local int32_t g_last_hip_error = 0;
 
 constexpr int64_t kMaxN = (int64_t)1 << 31;           // Gaussians per call
 constexpr int64_t kMaxInstances = ((int64_t)1 << 30) - 1;  // look-back counters are 30 bits
+constexpr int kMaxBatchViews = 256;                           // views per batch
 
 int32_t hip_fail(hipError_t e) {
   g_last_hip_error = (int32_t)e;
@@ -114,6 +117,8 @@ gs::SetK make_setk(const gs_camera* c, const gs_settings* s) {
   k.amax = s->alpha_max;
   k.t_eps = s->t_eps;
   for (int i = 0; i < 3; ++i) k.bg[i] = s->bg[i];
+  k.views = nullptr;
+  k.n_views = 0;
   return k;
 }
 
@@ -465,45 +470,84 @@ int32_t gs_preprocess_packed(int32_t n_assets, const gs_asset* assets, int64_t n
   return GS_OK;
 }
 
-int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
-                const uint32_t* tile_rects, const uint32_t* counts, const gs_camera* cam,
-                const gs_settings* set,
-                int64_t capacity, uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
-                uint32_t* status_flag, void* workspace, size_t workspace_bytes, void* stream) {
+namespace {
+// The radix passes of one gs_sort call (shared by gs_sort and gs_sort_plan):
+// depth passes first (all 32 bits in radix_bits-wide passes, or depth_bits
+// bits of the keys relative to the smallest visible key in balanced passes
+// of at most 9 bits in mode 0 / radix_bits in mode 1), then the tile passes.
+struct SortPlan {
+  int pd = 0, pt = 0;
+  int widths[gs::kMaxPassTotal] = {};  // depth pass digit widths
+};
+
+int tile_bits_of(int64_t tiles) {
+  int b = 0;
+  while (((int64_t)1 << b) < tiles) ++b;
+  return b;
+}
+
+SortPlan plan_sort(int64_t tiles, const gs_settings* set) {
+  SortPlan P;
+  const int bits = set->radix_bits, mode = set->sort_mode, db = set->depth_bits;
+  if (db > 0 && mode == 0) {
+    P.pd = (db + 8) / 9;
+    for (int p = 0; p < P.pd; ++p) {
+      const int w = db / P.pd + (p < db % P.pd ? 1 : 0);
+      P.widths[p] = w < 6 ? 6 : w;
+    }
+  } else {
+    P.pd = ((db > 0 ? db : 32) + bits - 1) / bits;
+    for (int p = 0; p < P.pd; ++p) P.widths[p] = bits;
+  }
+  const int tile_bits = tile_bits_of(tiles);
+  P.pt = tile_bits > 0 ? (tile_bits + bits - 1) / bits : 1;
+  return P;
+}
+}  // namespace
+
+int32_t gs_sort_plan(int64_t n, int64_t capacity, const gs_camera* cam, const gs_settings* set,
+                     int32_t max_passes, gs_sort_pass* passes, int32_t* n_passes,
+                     int64_t* lookback_words) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if (n < 0 || n >= kMaxN || capacity < 0 || capacity > kMaxInstances) return GS_ERR_INVALID_ARGUMENT;
-  if ((r = check_dev(counts)) || (r = check_dev(tile_ranges))) return r;
-  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)) ||
-                (r = check_dev(tile_rects))))
-    return r;
-  if (capacity > 0 && (r = check_dev(values))) return r;
-  if ((r = check_dev(keys, false)) || (r = check_dev(status_flag, false))) return r;
-  const int tiles_all = tiles_x_of(cam, set) * tiles_y_of(cam, set);
-  const gs::SortLayout L = gs::sort_layout(n, capacity, tiles_all);
-  if (workspace_bytes < L.bytes) return GS_ERR_WORKSPACE;
-  if ((r = check_dev(workspace))) return r;
+  if (!passes || !n_passes || !lookback_words || max_passes < 0) return GS_ERR_INVALID_ARGUMENT;
+  const int tiles = tiles_x_of(cam, set) * tiles_y_of(cam, set);
+  const SortPlan P = plan_sort(tiles, set);
+  if (P.pd + P.pt > max_passes) return GS_ERR_INVALID_ARGUMENT;
+  const gs::SortLayout L = gs::sort_layout(n, capacity, tiles);
+  const int64_t part = set->sort_mode == 1 ? gs::kSortPart : 0;
+  for (int p = 0; p < P.pd + P.pt; ++p) {
+    gs_sort_pass& o = passes[p];
+    const bool depth = p < P.pd;
+    o.pass = p;
+    o.digit_bits = depth ? P.widths[p] : set->radix_bits;
+    o.keys = depth ? (p == 0 ? GS_PASS_KEYS_ALL : GS_PASS_KEYS_VISIBLE) : GS_PASS_KEYS_INSTANCES;
+    o.partition_keys = (int32_t)part;
+    const int64_t grid_n = depth ? n : capacity;
+    o.grid_partitions = part > 0 ? (int32_t)((grid_n + part - 1) / part) : 0;
+  }
+  // in mode 0 the key generation writes the first tile pass's output itself
+  *n_passes = P.pd + P.pt;
+  *lookback_words = set->sort_mode == 1 ? (int64_t)2 * L.parts * 256 : 0;
+  return GS_OK;
+}
+
+namespace {
+// gs_sort over a tile grid of tiles_x x tiles_y tiles (one view's, or a
+// batch's stacked grid); arguments already checked.
+int32_t sort_impl(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
+                  const uint32_t* tile_rects, const uint32_t* counts, int tiles_x, int tiles_y,
+                  const gs_settings* set, int64_t capacity, uint64_t* keys, uint32_t* values,
+                  uint32_t* tile_ranges, uint32_t* status_flag, void* workspace, void* stream) {
+  const int tiles = tiles_x * tiles_y;
+  const gs::SortLayout L = gs::sort_layout(n, capacity, tiles);
   const int bits = set->radix_bits, mode = set->sort_mode;
   const bool heavy_first = set->raster_order == 1;
-  const int tile_bits = key_bits_of(cam, set) - 32;
-  // depth passes: all 32 bits in radix_bits-wide passes, or (depth_bits > 0)
-  // depth_bits bits of the keys relative to the smallest visible key, in
-  // balanced passes of at most 9 bits (mode 0) or radix_bits (mode 1)
   const int db = set->depth_bits;
-  int widths[gs::kMaxPassTotal] = {};
-  int pd;
-  if (db > 0 && mode == 0) {
-    pd = (db + 8) / 9;
-    for (int p = 0; p < pd; ++p) {
-      const int w = db / pd + (p < db % pd ? 1 : 0);
-      widths[p] = w < 6 ? 6 : w;
-    }
-  } else {
-    pd = ((db > 0 ? db : 32) + bits - 1) / bits;
-    for (int p = 0; p < pd; ++p) widths[p] = bits;
-  }
-  const int pt = tile_bits > 0 ? (tile_bits + bits - 1) / bits : 1;
-  const int tiles_x = tiles_x_of(cam, set), tiles = tiles_x * tiles_y_of(cam, set);
+  const SortPlan plan = plan_sort(tiles, set);
+  const int* widths = plan.widths;
+  const int pd = plan.pd, pt = plan.pt;
   char* ws = static_cast<char*>(workspace);
   hipStream_t st = static_cast<hipStream_t>(stream);
   auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
@@ -588,6 +632,28 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   }
   gs::trace_mark(st, "");
   return GS_OK;
+}
+}  // namespace
+
+int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
+                const uint32_t* tile_rects, const uint32_t* counts, const gs_camera* cam,
+                const gs_settings* set,
+                int64_t capacity, uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
+                uint32_t* status_flag, void* workspace, size_t workspace_bytes, void* stream) {
+  int32_t r;
+  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
+  if (n < 0 || n >= kMaxN || capacity < 0 || capacity > kMaxInstances) return GS_ERR_INVALID_ARGUMENT;
+  if ((r = check_dev(counts)) || (r = check_dev(tile_ranges))) return r;
+  if (n > 0 && ((r = check_dev(splats)) || (r = check_dev(depth_keys)) ||
+                (r = check_dev(tile_rects))))
+    return r;
+  if (capacity > 0 && (r = check_dev(values))) return r;
+  if ((r = check_dev(keys, false)) || (r = check_dev(status_flag, false))) return r;
+  const int tx = tiles_x_of(cam, set), ty = tiles_y_of(cam, set);
+  if (workspace_bytes < gs::sort_layout(n, capacity, tx * ty).bytes) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
+  return sort_impl(n, splats, depth_keys, tile_rects, counts, tx, ty, set, capacity, keys, values,
+                   tile_ranges, status_flag, workspace, stream);
 }
 
 int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in, const uint32_t* values_in,
@@ -876,6 +942,467 @@ int32_t gs_preprocess_backward_views(
   if (e != hipSuccess) return hip_fail(e);
   gs::trace_mark(st, "");
   return GS_OK;
+}
+
+
+// ---------------------------------------------------------------- batches of views
+
+struct gs_batch {
+  int V = 0, A = 0, deg = 0;
+  int64_t n = 0;
+  const float *means = nullptr, *log_scales = nullptr, *quats = nullptr, *logits = nullptr,
+              *sh = nullptr, *targets = nullptr;
+  std::vector<gs_camera> cams;
+  std::vector<gs_asset> assets;
+  std::vector<std::array<float, 12>> models;
+  std::vector<gs::CamK> camk;   // V x A, view-major
+  std::vector<gs::ViewK> viewk;
+  gs::BatchPreK pre{};
+  gs_settings set{};            // with the planned depth_bits
+  int TX = 0, TY = 0, max_pix = 0;
+  int64_t pixels = 0, capacity = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // pinned host copies of the camera and view tables and the count
+  // read-back of gs_batch_plan: copies from pageable memory are not ordered
+  // behind the stream's waits on other streams, so a table copied from
+  // there could be overwritten by earlier work that still owns the memory
+  unsigned char* host = nullptr;
+  size_t host_camk = 0, host_viewk = 0, host_counts = 0;
+  ~gs_batch() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (host) hipHostFree(host);
+  }
+};
+
+namespace {
+struct BatchLayout {
+  size_t camk, viewk, recs, dkeys, rects, partial, counts, T, last, dL, g2d, values, ranges, sort,
+      bytes;
+};
+
+BatchLayout batch_layout(const gs_batch* b, int64_t capacity) {
+  BatchLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = gs::align_up(o + (bytes ? bytes : 1), 256);
+    return at;
+  };
+  const int64_t vn = (int64_t)b->V * b->n, cap = capacity > 0 ? capacity : 0;
+  const bool bwd = b->targets != nullptr;
+  L.camk = take(b->camk.size() * sizeof(gs::CamK));
+  L.viewk = take(b->viewk.size() * sizeof(gs::ViewK));
+  L.recs = take((size_t)vn * sizeof(gs_splat));
+  L.dkeys = take((size_t)vn * 4);
+  L.rects = take((size_t)vn * 8);
+  L.partial = take((size_t)b->V * b->pre.block0[b->A] * 16);
+  L.counts = take(16);
+  L.T = take((size_t)b->pixels * 4);
+  L.last = take((size_t)b->pixels * 4);
+  L.dL = take(bwd ? (size_t)b->pixels * 16 : 0);
+  L.g2d = take(bwd ? (size_t)vn * gs::kGrad2dStride * 4 : 0);
+  L.values = take((size_t)cap * 4);
+  L.ranges = take((size_t)3 * b->TX * b->TY * 4);
+  L.sort = take(gs::sort_layout(vn, cap, b->TX * b->TY).bytes);
+  L.bytes = o;
+  return L;
+}
+
+// the tables the kernels read, copied into the workspace (stream-ordered)
+hipError_t batch_upload(const gs_batch* b, char* ws, hipStream_t st) {
+  const BatchLayout L = batch_layout(b, b->capacity);
+  hipError_t e = hipMemcpyAsync(ws + L.camk, b->host + b->host_camk,
+                                b->camk.size() * sizeof(gs::CamK), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + L.viewk, b->host + b->host_viewk, b->viewk.size() * sizeof(gs::ViewK),
+                       hipMemcpyHostToDevice, st);
+  return e;
+}
+
+gs::SetK batch_setk(const gs_batch* b, const char* ws) {
+  gs::SetK sk = make_setk(&b->cams[0], &b->set);
+  sk.tiles_x = b->TX;
+  sk.tiles_y = b->TY;
+  sk.views = reinterpret_cast<const gs::ViewK*>(ws + batch_layout(b, b->capacity).viewk);
+  sk.n_views = b->V;
+  return sk;
+}
+
+// preprocess of every view and asset, and the global counts
+hipError_t batch_preprocess(const gs_batch* b, char* ws, hipStream_t st) {
+  const BatchLayout L = batch_layout(b, b->capacity);
+  const gs::SetK sk = batch_setk(b, ws);
+  hipError_t e = gs::launch_preprocess_views(
+      b->pre, b->V, b->means, b->log_scales, b->quats, b->logits, b->sh, b->deg,
+      reinterpret_cast<const gs::CamK*>(ws + L.camk), sk, reinterpret_cast<gs_splat*>(ws + L.recs),
+      reinterpret_cast<uint32_t*>(ws + L.dkeys), reinterpret_cast<uint32_t*>(ws + L.rects),
+      reinterpret_cast<uint4*>(ws + L.partial), st);
+  if (e == hipSuccess)
+    e = gs::launch_count_finalize(reinterpret_cast<const uint4*>(ws + L.partial),
+                                  b->V * b->pre.block0[b->A], reinterpret_cast<uint32_t*>(ws + L.counts),
+                                  st);
+  return e;
+}
+
+// the whole batch: preprocess, one global sort, compositing; with targets
+// the L1 gradient, compositing backward and the chain rule over all views
+int32_t batch_enqueue(const gs_batch* b, char* ws, float* images, float* d_means,
+                      float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_sh,
+                      uint32_t* status_flag, hipStream_t st) {
+  const BatchLayout L = batch_layout(b, b->capacity);
+  auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
+  const gs::SetK sk = batch_setk(b, ws);
+  hipError_t e = batch_preprocess(b, ws, st);
+  if (e != hipSuccess) return hip_fail(e);
+  const gs_splat* recs = reinterpret_cast<const gs_splat*>(ws + L.recs);
+  int32_t r = sort_impl((int64_t)b->V * b->n, recs, U(L.dkeys), U(L.rects), U(L.counts), b->TX,
+                        b->TY, &b->set, b->capacity, nullptr, U(L.values), U(L.ranges),
+                        status_flag, ws + L.sort, st);
+  if (r) return r;
+  gs::trace_mark(st, "raster");
+  e = gs::launch_rasterize(recs, U(L.values), U(L.ranges), sk, 0, 0, nullptr, nullptr, images,
+                           reinterpret_cast<float*>(ws + L.T), U(L.last), nullptr, st);
+  if (e != hipSuccess) return hip_fail(e);
+  if (!b->targets) {
+    gs::trace_mark(st, "");
+    return GS_OK;
+  }
+  float* dL = reinterpret_cast<float*>(ws + L.dL);
+  float* g2d = reinterpret_cast<float*>(ws + L.g2d);
+  e = gs::launch_l1_grad(reinterpret_cast<const gs::ViewK*>(ws + L.viewk), b->V, b->max_pix, images,
+                         b->targets, dL, st);
+  gs::trace_mark(st, "bwd_clear");
+  if (e == hipSuccess)
+    e = gs::launch_fill_u32(U(L.g2d), 0u, (int64_t)b->V * b->n * gs::kGrad2dStride, st);
+  gs::trace_mark(st, "raster_bwd");
+  if (e == hipSuccess)
+    e = gs::launch_rasterize_backward(recs, U(L.values), U(L.ranges), sk, 0, 0, nullptr,
+                                      reinterpret_cast<const float*>(ws + L.T), U(L.last), dL, g2d,
+                                      st);
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "preprocess_bwd");
+  const int K3 = (b->deg + 1) * (b->deg + 1) * 3;
+  const gs::SetK sk1 = make_setk(&b->cams[0], &b->set);
+  for (int a = 0; a < b->A && e == hipSuccess; ++a) {
+    const int64_t o = b->assets[a].offset, c = b->assets[a].count;
+    if (c == 0) continue;
+    for (int v0 = 0; v0 < b->V && e == hipSuccess; v0 += gs::kBwdViews) {
+      gs::ViewsK vk;
+      vk.nv = b->V - v0 < gs::kBwdViews ? b->V - v0 : gs::kBwdViews;
+      for (int k = 0; k < gs::kBwdViews; ++k) {
+        const int v = v0 + (k < vk.nv ? k : 0);
+        vk.cam[k] = b->camk[(size_t)v * b->A + a];
+        vk.g2d[k] = k < vk.nv ? g2d + gs::kGrad2dStride * ((int64_t)v * b->n + o) : nullptr;
+      }
+      e = gs::launch_preprocess_backward_views(
+          (int)c, b->means + 3 * o, b->log_scales + 3 * o, b->quats + 4 * o, b->logits + o,
+          b->sh + K3 * o, b->deg, vk, sk1, d_means + 3 * o, d_log_scales + 3 * o, d_quats + 4 * o,
+          d_opacity_logits + o, d_sh + K3 * o, v0 > 0 ? 1 : 0, st);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  gs::trace_mark(st, "");
+  return GS_OK;
+}
+
+int32_t batch_check_run(const gs_batch* b, void* workspace, size_t bytes, float* images,
+                        float* d_means, float* d_log_scales, float* d_quats,
+                        float* d_opacity_logits, float* d_sh, uint32_t* status_flag) {
+  int32_t r;
+  if (!b) return GS_ERR_INVALID_ARGUMENT;
+  if (b->capacity < 0) return GS_ERR_INVALID_ARGUMENT;  // not planned
+  if (bytes < batch_layout(b, b->capacity).bytes) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace)) || (r = check_dev(images))) return r;
+  if ((r = check_dev(status_flag, false))) return r;
+  if (b->targets && ((r = check_dev(d_means)) || (r = check_dev(d_log_scales)) ||
+                     (r = check_dev(d_quats)) || (r = check_dev(d_opacity_logits)) ||
+                     (r = check_dev(d_sh))))
+    return r;
+  return GS_OK;
+}
+}  // namespace
+
+int32_t gs_batch_create(const gs_batch_desc* d, const gs_settings* set, gs_batch** out) {
+  int32_t r;
+  if (!d || !out) return GS_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if ((r = check_settings(set))) return r;
+  if (d->n_views < 1 || d->n_views > kMaxBatchViews || !d->cams) return GS_ERR_INVALID_ARGUMENT;
+  if ((r = check_inputs(d->n, d->means, d->log_scales, d->quats, d->opacity_logits, d->sh,
+                        d->sh_degree)))
+    return r;
+  if ((r = check_assets(d->n_assets, d->assets, d->n))) return r;
+  if ((r = check_dev(d->targets, false))) return r;
+  if (d->n < 1 || (int64_t)d->n_views * d->n >= kMaxN) return GS_ERR_INVALID_ARGUMENT;
+  auto b = new gs_batch();
+  b->V = d->n_views;
+  b->A = d->n_assets;
+  b->deg = d->sh_degree;
+  b->n = d->n;
+  b->means = d->means; b->log_scales = d->log_scales; b->quats = d->quats;
+  b->logits = d->opacity_logits; b->sh = d->sh; b->targets = d->targets;
+  b->set = *set;
+  b->cams.assign(d->cams, d->cams + d->n_views);
+  b->assets.assign(d->assets, d->assets + d->n_assets);
+  b->models.resize(d->n_assets);
+  // the batch's tile grid: each view a band of tile rows, as wide as the
+  // widest view
+  int row = 0;
+  int64_t pix = 0;
+  for (int v = 0; v < b->V; ++v) {
+    if ((r = check_camera(&b->cams[v], set))) { delete b; return r; }
+    gs::ViewK k{};
+    k.row = row;
+    k.tiles_x = tiles_x_of(&b->cams[v], set);
+    k.tiles_y = tiles_y_of(&b->cams[v], set);
+    k.W = b->cams[v].width;
+    k.H = b->cams[v].height;
+    k.pix = (size_t)pix;
+    b->viewk.push_back(k);
+    row += k.tiles_y;
+    pix += (int64_t)k.W * k.H;
+    b->TX = k.tiles_x > b->TX ? k.tiles_x : b->TX;
+    b->max_pix = k.W * k.H > b->max_pix ? k.W * k.H : b->max_pix;
+  }
+  b->TY = row;
+  b->pixels = pix;
+  if (b->TY > 0xFFFF || (int64_t)b->TX * b->TY >= ((int64_t)1 << 26)) {
+    delete b;
+    return GS_ERR_UNSUPPORTED;
+  }
+  b->pre.n = d->n;
+  b->pre.n_assets = d->n_assets;
+  int blocks = 0;
+  for (int a = 0; a < d->n_assets; ++a) {
+    b->pre.block0[a] = blocks;
+    b->pre.offset[a] = d->assets[a].offset;
+    b->pre.count[a] = (int)d->assets[a].count;
+    blocks += gs::preprocess_blocks(d->assets[a].count);
+    if (d->assets[a].model) {
+      std::memcpy(b->models[a].data(), d->assets[a].model, 12 * sizeof(float));
+      b->assets[a].model = b->models[a].data();
+    }
+  }
+  b->pre.block0[d->n_assets] = blocks;
+  b->camk.resize((size_t)b->V * b->A);
+  for (int v = 0; v < b->V; ++v)
+    for (int a = 0; a < b->A; ++a) {
+      gs::CamK& ck = b->camk[(size_t)v * b->A + a];
+      if ((r = make_camk(&b->cams[v], set, b->assets[a].model, &ck))) { delete b; return r; }
+      ck.tile_row = b->viewk[v].row;
+    }
+  const size_t cb = b->camk.size() * sizeof(gs::CamK), vb = b->viewk.size() * sizeof(gs::ViewK);
+  b->host_camk = 0;
+  b->host_viewk = gs::align_up(cb, 64);
+  b->host_counts = gs::align_up(b->host_viewk + vb, 64);
+  void* hp = nullptr;
+  hipError_t he = hipHostMalloc(&hp, b->host_counts + 16, hipHostMallocDefault);
+  if (he != hipSuccess) {
+    delete b;
+    return hip_fail(he);
+  }
+  b->host = static_cast<unsigned char*>(hp);
+  std::memcpy(b->host + b->host_camk, b->camk.data(), cb);
+  std::memcpy(b->host + b->host_viewk, b->viewk.data(), vb);
+  *out = b;
+  return GS_OK;
+}
+
+void gs_batch_destroy(gs_batch* b) { delete b; }
+
+int64_t gs_batch_pixels(const gs_batch* b) { return b ? b->pixels : -1; }
+
+int64_t gs_batch_pixel_offset(const gs_batch* b, int32_t view) {
+  if (!b || view < 0 || view >= b->V) return -1;
+  return (int64_t)b->viewk[view].pix;
+}
+
+int64_t gs_batch_capacity(const gs_batch* b) { return b ? b->capacity : -1; }
+
+size_t gs_batch_workspace_size(const gs_batch* b, int64_t capacity) {
+  if (!b || capacity < 0 || capacity > kMaxInstances) return 0;
+  return batch_layout(b, capacity).bytes;
+}
+
+int32_t gs_batch_plan(gs_batch* b, float headroom, void* workspace, size_t workspace_bytes,
+                      int64_t* capacity, void* stream) {
+  int32_t r;
+  if (!b || !capacity || !(headroom >= 1.f) || !(headroom <= 4.f)) return GS_ERR_INVALID_ARGUMENT;
+  if (workspace_bytes < batch_layout(b, 0).bytes) return GS_ERR_WORKSPACE;
+  if ((r = check_dev(workspace))) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const int64_t keep = b->capacity;
+  b->capacity = 0;
+  hipError_t e = batch_upload(b, ws, st);
+  if (e == hipSuccess) e = batch_preprocess(b, ws, st);
+  uint32_t* c = reinterpret_cast<uint32_t*>(b->host + b->host_counts);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c, ws + batch_layout(b, 0).counts, 16, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    b->capacity = keep;
+    return hip_fail(e);
+  }
+  // the instance capacity and the depth key bits, with headroom for
+  // parameter updates between plans (a frame that outgrows them raises
+  // bit 0 or bit 1 of the status flag)
+  int64_t cap = (int64_t)std::ceil((double)c[0] * headroom);
+  cap = cap < 256 ? 256 : cap;
+  if (cap > kMaxInstances) return GS_ERR_CAPACITY;
+  int db = 0;
+  if (c[1] > 0) {
+    const uint32_t range = c[3] - c[2];
+    while (db < 32 && ((uint64_t)range >> db) != 0) ++db;
+    db = db + 1 < 32 ? db + 1 : 32;
+  }
+  b->set.depth_bits = db;
+  b->capacity = cap;
+  *capacity = cap;
+  return GS_OK;
+}
+
+int32_t gs_batch_run(gs_batch* b, void* workspace, size_t workspace_bytes, float* images,
+                     float* d_means, float* d_log_scales, float* d_quats, float* d_opacity_logits,
+                     float* d_sh, uint32_t* status_flag, void* stream) {
+  int32_t r;
+  if ((r = batch_check_run(b, workspace, workspace_bytes, images, d_means, d_log_scales, d_quats,
+                           d_opacity_logits, d_sh, status_flag)))
+    return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = batch_upload(b, static_cast<char*>(workspace), st);
+  if (e != hipSuccess) return hip_fail(e);
+  return batch_enqueue(b, static_cast<char*>(workspace), images, d_means, d_log_scales, d_quats,
+                       d_opacity_logits, d_sh, status_flag, st);
+}
+
+int32_t gs_batch_capture(gs_batch* b, void* workspace, size_t workspace_bytes, float* images,
+                         float* d_means, float* d_log_scales, float* d_quats,
+                         float* d_opacity_logits, float* d_sh, uint32_t* status_flag,
+                         void* stream) {
+  int32_t r;
+  if ((r = batch_check_run(b, workspace, workspace_bytes, images, d_means, d_log_scales, d_quats,
+                           d_opacity_logits, d_sh, status_flag)))
+    return r;
+  if (!stream) return GS_ERR_INVALID_ARGUMENT;  // the legacy stream cannot be captured
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  // the tables go to the workspace before the capture (the graph reads
+  // them there)
+  hipError_t e = batch_upload(b, ws, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+  e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e);
+  r = batch_enqueue(b, ws, images, d_means, d_log_scales, d_quats, d_opacity_logits, d_sh,
+                    status_flag, st);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(st, &g);
+  if (r) {
+    if (g) hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return hip_fail(e);
+  }
+  b->graph = g;
+  return GS_OK;
+}
+
+int32_t gs_batch_launch(gs_batch* b, void* stream) {
+  if (!b || !b->exec) return GS_ERR_INVALID_ARGUMENT;
+  const hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GS_OK : hip_fail(e);
+}
+
+int32_t gs_autotune(const gs_batch_desc* desc, const gs_settings* base,
+                    const gs_autotune_space* space, int32_t reps, float headroom, void* workspace,
+                    size_t workspace_bytes, float* images, float* d_means, float* d_log_scales,
+                    float* d_quats, float* d_opacity_logits, float* d_sh, uint32_t* status_flag,
+                    gs_settings* best, float* best_ms, int32_t* evaluated, void* stream) {
+  int32_t r;
+  if (!desc || !base || !space || !best || !best_ms || reps < 1 || reps > 100)
+    return GS_ERR_INVALID_ARGUMENT;
+  if (space->n_tiles < 0 || space->n_tiles > 16 || space->n_bits < 0 || space->n_bits > 8 ||
+      space->n_modes < 0 || space->n_modes > 2 || space->n_orders < 0 || space->n_orders > 2)
+    return GS_ERR_INVALID_ARGUMENT;
+  if ((r = check_settings(base))) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t ev[2];
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) return hip_fail(e);
+  int nev = 0;
+  // time one candidate: plan, one warm batch, then `reps` timed batches
+  auto measure = [&](const gs_settings& s, float* ms) -> int32_t {
+    *ms = INFINITY;
+    if (check_settings(&s)) return GS_OK;  // not a valid candidate
+    gs_batch* b = nullptr;
+    int32_t q = gs_batch_create(desc, &s, &b);
+    if (q) return q == GS_ERR_UNSUPPORTED ? GS_OK : q;
+    int64_t cap = 0;
+    q = gs_batch_plan(b, headroom, workspace, workspace_bytes, &cap, stream);
+    if (q == GS_OK && batch_layout(b, cap).bytes <= workspace_bytes) {
+      q = gs_batch_run(b, workspace, workspace_bytes, images, d_means, d_log_scales, d_quats,
+                       d_opacity_logits, d_sh, status_flag, stream);
+      hipError_t he = hipEventRecord(ev[0], st);
+      for (int k = 0; k < reps && q == GS_OK; ++k)
+        q = batch_enqueue(b, static_cast<char*>(workspace), images, d_means, d_log_scales,
+                          d_quats, d_opacity_logits, d_sh, status_flag, st);
+      if (he == hipSuccess) he = hipEventRecord(ev[1], st);
+      if (he == hipSuccess) he = hipEventSynchronize(ev[1]);
+      float t = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&t, ev[0], ev[1]);
+      if (he != hipSuccess && q == GS_OK) q = hip_fail(he);
+      if (q == GS_OK) {
+        *ms = t / reps;
+        ++nev;
+      }
+    } else if (q == GS_ERR_WORKSPACE || q == GS_OK) {
+      q = GS_OK;  // does not fit the workspace: skipped
+    }
+    gs_batch_destroy(b);
+    return q;
+  };
+  gs_settings cur = *base;
+  float cur_ms = INFINITY;
+  r = measure(cur, &cur_ms);
+  // coordinate search: tile shape, digit width, sort mode, compositing order
+  for (int dim = 0; dim < 4 && r == GS_OK; ++dim) {
+    const int cnt = dim == 0 ? space->n_tiles : dim == 1 ? space->n_bits
+                    : dim == 2 ? space->n_modes : space->n_orders;
+    for (int k = 0; k < cnt && r == GS_OK; ++k) {
+      gs_settings s = cur;
+      if (dim == 0) { s.tile_w = space->tiles[2 * k]; s.tile_h = space->tiles[2 * k + 1]; }
+      else if (dim == 1) s.radix_bits = space->bits[k];
+      else if (dim == 2) s.sort_mode = space->modes[k];
+      else s.raster_order = space->orders[k];
+      if (s.tile_w == cur.tile_w && s.tile_h == cur.tile_h && s.radix_bits == cur.radix_bits &&
+          s.sort_mode == cur.sort_mode && s.raster_order == cur.raster_order)
+        continue;
+      float ms;
+      r = measure(s, &ms);
+      if (r == GS_OK && ms < cur_ms) {
+        cur = s;
+        cur_ms = ms;
+      }
+    }
+  }
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  if (r) return r;
+  *best = cur;
+  best->depth_bits = base->depth_bits;
+  *best_ms = cur_ms;
+  if (evaluated) *evaluated = nev;
+  return std::isfinite(cur_ms) ? GS_OK : GS_ERR_WORKSPACE;
 }
 
 }  // extern "C"

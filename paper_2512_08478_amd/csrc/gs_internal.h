@@ -30,6 +30,7 @@ struct CamK {
   float znear;
   int W, H;
   int has_model;
+  int tile_row;       // first tile row of this view in a batch's tile grid (0: one view)
 };
 
 // Cameras (as seen by one asset) and 2-D gradient records of up to
@@ -41,11 +42,35 @@ struct ViewsK {
   int nv;
 };
 
+// The asset table of a batched preprocess (kernel argument): asset a's
+// Gaussians are [offset[a], offset[a] + count[a]) of each view's n, and its
+// workgroups are blocks [block0[a], block0[a + 1]).
+constexpr int kMaxAssetsK = 64;
+struct BatchPreK {
+  int64_t n;
+  int n_assets;
+  int block0[kMaxAssetsK + 1];
+  int64_t offset[kMaxAssetsK];
+  int count[kMaxAssetsK];
+};
+
+// One view of a batch: its band of tile rows [row, row + tiles_y) in the
+// batch's tile grid (columns 0 .. tiles_x-1 of the grid's width), its size
+// and the offset of its pixels in the batch's per-pixel arrays.
+struct ViewK {
+  int row, tiles_x, tiles_y, W, H, pad;
+  size_t pix;
+};
+
 struct SetK {
   int tile_w, tile_h, tiles_x, tiles_y;
   int raster_order;   // 0: spatial runs over the XCDs; 1: heavy tiles first
   float eps2d, tau, log2_tau, amax, t_eps;
   float bg[3];
+  // a batch of views (n_views > 0): tiles_x/tiles_y are the batch grid's,
+  // views[] (device) maps each band of tile rows to its view
+  const ViewK* views;
+  int n_views;
 };
 
 // Workspace carve-up helpers.
@@ -99,6 +124,15 @@ size_t preprocess_ws_bytes(int64_t n);
 int preprocess_blocks(int64_t n);
 // Projection of n Gaussians; per-block (instances, visible, smallest and
 // largest visible depth key) partials go to partial[0 .. preprocess_blocks(n)).
+// Every view x asset of a batch in one launch (k_preprocess_views); cams
+// (device) holds n_views * n_assets cameras, view-major.  Partials: n_views *
+// B.block0[n_assets] slots.
+hipError_t launch_preprocess_views(const BatchPreK& B, int n_views, const float* means,
+                                   const float* log_scales, const float* quats,
+                                   const float* logits, const float* sh, int degree,
+                                   const CamK* cams, const SetK& set, gs_splat* splats,
+                                   uint32_t* depth_keys, uint32_t* tile_rects, uint4* partial,
+                                   hipStream_t st);
 hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh,
                              int degree, const CamK& cam, const SetK& set,
@@ -193,6 +227,10 @@ hipError_t launch_preprocess_backward_views(int n, const float* means, const flo
                                             float* d_quats, float* d_logits, float* d_sh,
                                             int accumulate, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
+// L1 loss gradient of every view of a batch (views: device table; image and
+// grad 4 floats per pixel, target 3, views concatenated).
+hipError_t launch_l1_grad(const ViewK* views, int n_views, int max_pixels, const float* image,
+                          const float* target, float* grad, hipStream_t st);
 
 // Opt-in kernel tracer: when enabled, trace_mark records a HIP event on the
 // stream; the interval from one mark to the next is attributed to the

@@ -149,16 +149,16 @@ constexpr int kShRows = 32;
 // wave copies the rows of its visible Gaussians into LDS with contiguous
 // 16-byte loads, 32 rows at a time, and each lane reads its row from LDS.
 template <int DEG>
-__global__ __launch_bounds__(kBlock) void k_preprocess(
-    int n, const float* __restrict__ means, const float* __restrict__ log_scales,
+__device__ __forceinline__ void preprocess_block(
+    int blk, int n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float4* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, CamK cam, SetK set, gs_splat* __restrict__ splats,
+    const float* __restrict__ sh, const CamK& cam, const SetK& set, gs_splat* __restrict__ splats,
     uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint4* __restrict__ partial) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr bool STAGED = DEG == 1 || DEG == 3;
   constexpr int F4 = STAGED ? K * 3 / 4 : 1;  // float4 per SH row
   __shared__ float4 s_sh[STAGED ? kBlock / 64 : 1][kShRows * F4];
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blk * kBlock + threadIdx.x;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   uint32_t tiles = 0, dkey = 0xFFFFFFFFu;
   float4 r0, r1, r2;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
   }
   if constexpr (STAGED) {
     const uint64_t need = ballot(tiles > 0);
-    const int i0 = blockIdx.x * kBlock + wave * 64;  // this wave's first Gaussian
+    const int i0 = blk * kBlock + wave * 64;  // this wave's first Gaussian
     const float4* sh4 = reinterpret_cast<const float4*>(sh);
     float4* buf = s_sh[wave];
     // both halves' rows are read from HBM at once (one round trip per
@@ -226,6 +226,39 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
     dst[2] = r2;
   }
   block_counts(tiles, dkey, partial);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_preprocess(
+    int n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, CamK cam, SetK set, gs_splat* __restrict__ splats,
+    uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint4* __restrict__ partial) {
+  preprocess_block<DEG>(blockIdx.x, n, means, log_scales, quats, logits, sh, cam, set, splats,
+                        depth_keys, rects, partial);
+}
+
+// Every view of a batch and every asset in one launch: blockIdx.y is the
+// view, blockIdx.x runs over the assets' blocks (asset a owns blocks
+// [B.block0[a], B.block0[a + 1])).  View v's records, depth keys and tile
+// rects start at v * B.n; workgroup (b, v) writes its partial counts to slot
+// v * B.block0[n_assets] + b.  cams[v * n_assets + a] places asset a in view v.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_preprocess_views(
+    BatchPreK B, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, const CamK* __restrict__ cams, SetK set,
+    gs_splat* __restrict__ splats, uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects,
+    uint4* __restrict__ partial) {
+  constexpr int K3 = (DEG + 1) * (DEG + 1) * 3;
+  const int v = blockIdx.y, b = blockIdx.x;
+  int a = 0;
+  while (a + 1 < B.n_assets && B.block0[a + 1] <= b) ++a;
+  const int64_t o = B.offset[a], vo = (int64_t)v * B.n + o;
+  preprocess_block<DEG>(b - B.block0[a], B.count[a], means + 3 * o, log_scales + 3 * o, quats + o,
+                        logits + o, sh + K3 * o, cams[v * B.n_assets + a], set, splats + vo,
+                        depth_keys + vo, rects + vo,
+                        partial + (size_t)v * B.block0[B.n_assets]);  // slot blockIdx.x
 }
 
 // counts[0] = total instances, counts[1] = visible Gaussians, counts[2] and
@@ -655,6 +688,28 @@ hipError_t launch_preprocess(int n, const float* means, const float* log_scales,
       default: GS_PRE(3); break;
     }
 #undef GS_PRE
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_views(const BatchPreK& B, int n_views, const float* means,
+                                   const float* log_scales, const float* quats,
+                                   const float* logits, const float* sh, int degree,
+                                   const CamK* cams, const SetK& set, gs_splat* splats,
+                                   uint32_t* depth_keys, uint32_t* tile_rects, uint4* partial,
+                                   hipStream_t st) {
+  const int blocks = B.block0[B.n_assets];
+  if (blocks > 0 && n_views > 0) {
+    trace_mark(st, "preprocess_views");
+    const float4* q4 = reinterpret_cast<const float4*>(quats);
+#define GS_PREV(D) hipLaunchKernelGGL(k_preprocess_views<D>, dim3(blocks, n_views), dim3(kBlock), 0, st, B, means, log_scales, q4, logits, sh, cams, set, splats, depth_keys, reinterpret_cast<uint2*>(tile_rects), partial)
+    switch (degree) {
+      case 0: GS_PREV(0); break;
+      case 1: GS_PREV(1); break;
+      case 2: GS_PREV(2); break;
+      default: GS_PREV(3); break;
+    }
+#undef GS_PREV
   }
   return hipGetLastError();
 }

@@ -150,6 +150,27 @@ __device__ __forceinline__ void walk_pairs(F&& f, std::integer_sequence<int, K..
   (void)(f(std::integral_constant<int, 2 * K>{}) && ...);
 }
 
+// A batch of views (set.n_views > 0): the view whose band of tile rows holds
+// grid tile row `trow` (binary search over the bands' first rows); its
+// tile row within the view, size and pixel offset.  Returns false for a
+// tile right of the view's last tile column (the grid is as wide as the
+// widest view; such tiles never hold splats).
+__device__ __forceinline__ bool view_of_tile(const SetK& set, int trow, int tcol, int& vrow,
+                                             int& W, int& H, size_t& pix) {
+  int lo = 0, hi = set.n_views - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (set.views[mid].row <= trow) lo = mid;
+    else hi = mid - 1;
+  }
+  const ViewK& v = set.views[lo];
+  vrow = trow - v.row;
+  W = v.W;
+  H = v.H;
+  pix = v.pix;
+  return tcol < v.tiles_x && vrow < v.tiles_y;
+}
+
 // The fields of a splat record the compositing kernels read.
 struct SplatRec {
   float4 a;  // mx, my, qa, qb
@@ -251,8 +272,17 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   __shared__ StageT<MESH> S;
   int tile, q;
   if (!pick_unit<NQ>(blockIdx.x, set, ranges, tile, q)) return;
+  int trow = tile / set.tiles_x;
+  if (set.n_views > 0) {  // a batch: this tile's view, its pixels
+    size_t pix;
+    if (!view_of_tile(set, trow, tile % set.tiles_x, trow, W, H, pix)) return;
+    image += 4 * pix;
+    T_final += pix;
+    last += pix;
+    if (COUNT) n_blend += pix;
+  }
   const int tx0 = (tile % set.tiles_x) * TW + 8 * (q % QX);
-  const int ty0 = (tile / set.tiles_x) * TH + 8 * (q / QX);
+  const int ty0 = trow * TH + 8 * (q / QX);
   if (tx0 >= W || ty0 >= H) return;  // quadrant wholly outside the image
   const int lane = threadIdx.x;
   const int lx = lane & 7, row = lane >> 3;
@@ -413,8 +443,17 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
   __shared__ float s_red[8][12];  // per 8-lane group (pixel row): its 9 gradient sums
   int tile, q;
   if (!pick_unit<NQ>(blockIdx.x, set, ranges, tile, q)) return;
+  int trow = tile / set.tiles_x;
+  if (set.n_views > 0) {  // a batch: this tile's view, its pixels
+    size_t pix;
+    if (!view_of_tile(set, trow, tile % set.tiles_x, trow, W, H, pix)) return;
+    if (bg_rgb) bg_rgb += 3 * pix;
+    T_final += pix;
+    last += pix;
+    dL_dimage += 4 * pix;
+  }
   const int tx0 = (tile % set.tiles_x) * TW + 8 * (q % QX);
-  const int ty0 = (tile / set.tiles_x) * TH + 8 * (q / QX);
+  const int ty0 = trow * TH + 8 * (q / QX);
   if (tx0 >= W || ty0 >= H) return;  // quadrant wholly outside the image
   const int lane = threadIdx.x;
   const int lx = lane & 7, row = lane >> 3;
@@ -549,7 +588,38 @@ void raster_bwd(const gs_splat* splats, const uint32_t* values, const uint32_t* 
                      splats, values, ranges, set, W, H, bg_rgb, T_final, last, dL_dimage, grad2d);
 }
 
+// The L1 loss gradient of every view of a batch (blockIdx.y = view):
+// dL/dRGBA of L_v = mean over (H, W, 3) of |RGB - target| is
+// sign(RGB - target) / (3 H W) for the colour channels and 0 for alpha.
+// image and grad hold 4 floats per pixel, target 3, views concatenated.
+__global__ __launch_bounds__(kBlock) void k_l1_grad(const ViewK* __restrict__ views,
+                                                    const float4* __restrict__ image,
+                                                    const float* __restrict__ target,
+                                                    float4* __restrict__ grad) {
+  const ViewK v = views[blockIdx.y];
+  const size_t n = (size_t)v.W * v.H;
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  const float d = (float)(3 * n);
+  const size_t q = v.pix + p;
+  const float4 c = image[q];
+  const float* t = target + 3 * q;
+  auto sgn = [](float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); };
+  grad[q] = make_float4(__fdiv_rn(sgn(c.x - t[0]), d), __fdiv_rn(sgn(c.y - t[1]), d),
+                        __fdiv_rn(sgn(c.z - t[2]), d), 0.f);
+}
+
 }  // namespace
+
+hipError_t launch_l1_grad(const ViewK* views, int n_views, int max_pixels, const float* image,
+                          const float* target, float* grad, hipStream_t st) {
+  if (n_views <= 0 || max_pixels <= 0) return hipSuccess;
+  trace_mark(st, "l1_grad");
+  hipLaunchKernelGGL(k_l1_grad, dim3((max_pixels + kBlock - 1) / kBlock, n_views), dim3(kBlock), 0,
+                     st, views, reinterpret_cast<const float4*>(image), target,
+                     reinterpret_cast<float4*>(grad));
+  return hipGetLastError();
+}
 
 bool tile_shape_supported(int tw, int th) {
   return (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 16 && th == 16) ||

@@ -1,9 +1,12 @@
-"""GPU tests of the multi-asset entry points and the batched graph path.
+"""GPU tests of the multi-asset entry points and the batch path.
 
 Multi-asset frames are checked against the FP64 oracle (records, pixels
-and gradients); the graph-captured batch against the plain view-by-view
-path: images bitwise equal on every replay, gradients equal up to the
-order of float atomics; the autotuner's choice leaves images unchanged.
+and gradients).  The batch (gs_batch_*: every view in one preprocess
+launch, one global sort, one compositing launch, captured into one HIP
+graph) against the plain view-by-view path: images bitwise equal on every
+replay, gradients equal up to the order of float atomics; the full batched
+workload (4.5M Gaussians, 32 views) also against the oracle; the
+autotuner's choice leaves images unchanged.
 """
 import numpy as np
 import pytest
@@ -114,15 +117,14 @@ def _rel_max(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
 
 
-@pytest.mark.parametrize("streams", [1, 3])
-def test_graph_batch_matches_plain_views_on_every_replay(R, streams):
-    print_case(f"graph-captured batch on {streams} stream(s) vs plain views, 3 replays")
+def test_graph_batch_matches_plain_views_on_every_replay(R):
+    print_case("graph-captured batch vs plain views, 3 replays")
     from paper_2512_08478_amd.batch import BatchRenderer, plain_views
     assets, cams = small_batch(n_views=4)
     p = concat_params(assets)
     tg = targets_for(cams)
     imgs_ref, grads_ref = plain_views(p, cams, tg)
-    br = BatchRenderer(p, cams, tg, streams=streams)
+    br = BatchRenderer(p, cams, tg)
     br.capture()
     noise = torch.randn(512, 512, device="cuda")
     for rep in range(3):
@@ -135,39 +137,106 @@ def test_graph_batch_matches_plain_views_on_every_replay(R, streams):
         # the program's own eager work between replays
         noise = (noise @ noise.T).tanh_()
         torch.cuda.synchronize()
-    print(f"{len(cams)} views, {p.n} Gaussians, capacities {br.capacity}")
+    # the eager run gives the same images
+    again = [im.clone() for im in br.run_eager()]
+    for v in range(len(cams)):
+        assert torch.equal(again[v], imgs_ref[v])
+    print(f"{len(cams)} views, {p.n} Gaussians, capacity {br.capacity}")
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8, 0, 1), (32, 16, 6, 1, 0), (64, 32, 7, 0, 1)])
+def test_batch_settings_forward_only(R, shape):
+    """A forward-only batch (no targets) in several tile shapes, digit
+    widths, sort modes and orders: images bitwise equal to plain views."""
+    tw, th, bits, mode, order = shape
+    print_case(f"forward-only batch, tiles {tw}x{th}, {bits}-bit, mode {mode}, order {order}")
+    from paper_2512_08478_amd.batch import BatchRenderer, plain_views
+    from paper_2512_08478_amd.render import Renderer
+    st = dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=mode, raster_order=order)
+    assets, cams = small_batch(n_views=5, seed=9)
+    p = concat_params(assets)
+    imgs_ref, _ = plain_views(p, cams, None, renderer=Renderer(st))
+    br = BatchRenderer(p, cams, None, st)
+    br.capture()
+    imgs = br.replay()
+    for v in range(len(cams)):
+        assert torch.equal(imgs[v], imgs_ref[v]), v
 
 
 def test_batch_capacity_overflow_is_reported(R):
+    """Parameters updated after planning so that the batch needs more
+    instances than planned: the status flag reports it."""
     print_case("batched capacity overflow flag")
     from paper_2512_08478_amd.batch import BatchRenderer
     assets, cams = small_batch(n_views=2)
     p = concat_params(assets)
-    br = BatchRenderer(p, cams, targets_for(cams))
+    br = BatchRenderer(p, cams, targets_for(cams), headroom=1.0)
     br.plan()
-    br.capacity = [64 for _ in cams]
+    br.run_eager()
+    torch.cuda.synchronize()
+    br._check_flags()
+    with torch.no_grad():
+        p.log_scales.add_(1.5)     # every footprint grows: more tiles per Gaussian
     br.run_eager()
     torch.cuda.synchronize()
     with pytest.raises(RuntimeError, match="capacity"):
         br._check_flags()
+    br.plan()                      # planned again: fits
+    br.run_eager()
+    torch.cuda.synchronize()
+    br._check_flags()
 
 
 def test_autotuned_settings_leave_images_unchanged(R):
-    print_case("autotune: tile shape / digit width / sort mode choice keeps images")
+    print_case("gs_autotune: tile shape / digit width / sort mode / order choice keeps images")
     from paper_2512_08478_amd.batch import BatchRenderer, autotune
     assets, cams = small_batch(n_views=2)
     p = concat_params(assets)
     tg = targets_for(cams)
-    best, table = autotune(p, cams, tg, reps=1, tiles=((16, 16), (8, 8), (32, 8)), bits=(8, 6),
-                           modes=(0, 1), streams=(1, 2))
-    assert len(table) == 3 + 1 + 1 + 1 + 1
+    best, ms, nev = autotune(p, cams, tg, reps=1, tiles=((16, 16), (8, 8), (32, 8)), bits=(8, 6),
+                             modes=(0, 1), orders=(1, 0))
+    assert nev == 1 + 2 + 1 + 1 + 1 and ms > 0
     ref = BatchRenderer(p, cams, tg)
     ref_imgs = [im.clone() for im in ref.run_eager()]
     tuned = BatchRenderer(p, cams, tg, best)
     imgs = tuned.run_eager()
     for a, b in zip(imgs, ref_imgs):
         assert torch.equal(a, b)
-    print(f"autotune picked {best}")
+    print(f"autotune picked {best} at {ms:.3f} ms per batch")
+
+
+def test_full_batched_workload(R, orc):
+    """The batched workload itself (2M scene + 8 placed assets, 4.5M
+    Gaussians; 32 views of uneven size): the graph-captured batch equals
+    the plain view-by-view path (images bitwise, gradients up to the order
+    of float atomics), and two views against the tiled FP64 oracle, every
+    pixel."""
+    print_case("full batch: 4.5M Gaussians x 32 views, graph vs plain views and oracle")
+    from paper_2512_08478_amd.batch import BatchRenderer, plain_views
+    from paper_2512_08478_amd.render import Renderer
+    assets, cams = S.batched_scenes()
+    p = concat_params(assets)
+    tg = targets_for(cams)
+    st = dict(tile_w=16, tile_h=16, radix_bits=8)
+    br = BatchRenderer(p, cams, tg, st)
+    br.capture()
+    imgs = [im.clone() for im in br.replay()]
+    grads = [g.clone() for g in br.grads]
+    imgs_ref, grads_ref = plain_views(p, cams, tg, renderer=Renderer(st))
+    for v in range(len(cams)):
+        assert torch.equal(imgs[v], imgs_ref[v]), v
+    for k, nm in enumerate(NAMES):
+        d = _rel_max(grads[k], grads_ref[k])
+        print(f"{nm}: max |batch - plain| / max |plain| = {d:.2e}")
+        assert d <= 1e-5, (nm, d)
+    for v in (0, 17):
+        cam = cams[v]
+        ref = orc.render_pixels(orc.preprocess_many(assets, cam), cam, orc.all_pixels(cam),
+                                tiled=True)
+        e, nflag, nloose = image_check(imgs[v].cpu().numpy().reshape(-1, 4), ref)
+        print(f"view {v} {cam.width}x{cam.height}: max err {e:.2e}, flagged {nflag}, "
+              f"jump above 1e-4 {nloose}")
+    print(f"{len(cams)} views, {p.n} Gaussians, {br.pixels} pixels, capacity {br.capacity}")
 
 
 def test_multi_view_backward_matches_per_view_backward(R):
