@@ -222,7 +222,8 @@ def main():
                                    "mesh"}))
         sys.exit(2)
     if args.workload == "batched":
-        return run_batched(args)
+        print(json.dumps(run_batched(args)), flush=True)
+        return
     if args.workload == "sort32":
         return run_sort32(args)
     out = run_view(args, full=True)
@@ -242,6 +243,17 @@ def main():
             extra[w]["stages"] = {k: {kk: vv for kk, vv in v.items()
                                       if kk in ("ms_per_frame", "gbs", "hbm_frac", "tflops", "alu_frac")}
                                   for k, v in e["stages"].items()}
+        # the batched views (32 views x 4.5M Gaussians, forward + backward, one
+        # graph launch per step)
+        a2 = copy.copy(args)
+        a2.workload = "batched"
+        a2.steps, a2.warmup = min(args.steps, 10), min(args.warmup, 2)
+        e = run_batched(a2, full=False)
+        extra["batched"] = {k: e[k] for k in ("value", "unit", "ms_per_step", "plain_frames_per_s",
+                                              "graph_speedup_vs_plain",
+                                              "images_bitwise_equal_to_plain",
+                                              "launches_per_batch", "roofline")}
+        extra["batched"]["config"] = e["config"]
         out["extra_workloads"] = extra
     print(json.dumps(out), flush=True)
 
@@ -522,9 +534,10 @@ def run_sort32(args):
     print(json.dumps(out), flush=True)
 
 
-def run_batched(args):
-    """All views' forward + backward as one HIP graph launch per step."""
-    import numpy as np
+def run_batched(args, full=True):
+    """All views' forward + backward (L1) as one HIP graph launch per step
+    (the library's gs_batch_capture / gs_batch_launch); returns the result
+    dict (with the CPU baseline when `full`)."""
     import torch
     from paper_2512_08478_amd import _lib as L
     from paper_2512_08478_amd import scenes as S
@@ -536,9 +549,9 @@ def run_batched(args):
     targets = [torch.from_numpy(S.random_target(100 + v, c.height, c.width)).cuda()
                for v, c in enumerate(cams)]
     log = (lambda m: print(m, file=sys.stderr, flush=True))
-    best, table = autotune(p, cams, targets, reps=2, log=log)
+    best, tune_ms, tune_n = autotune(p, cams, targets, reps=2, log=log)
     br = BatchRenderer(p, cams, targets, best)
-    caps = br.plan()
+    cap = br.plan()
     br.capture()
     for _ in range(args.warmup):
         br.replay(check=False)
@@ -550,28 +563,26 @@ def run_batched(args):
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
     br._check_flags()
     imgs = [im.clone() for im in br.images]
+    grads = [g.clone() for g in br.grads]
 
     # the plain path: view by view, one count readback per view
-    R = Renderer({k: v for k, v in best.items() if k != "streams"})
+    R = Renderer(best)
     plain_views(p, cams, targets, renderer=R)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = 2
     for _ in range(reps):
-        pimgs, _ = plain_views(p, cams, targets, renderer=R)
+        pimgs, pgrads = plain_views(p, cams, targets, renderer=R)
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - t0) * 1e3 / reps
     equal = all(torch.equal(a, b) for a, b in zip(imgs, pimgs))
+    grad_rel = max(float((a - b).norm() / b.norm().clamp_min(1e-30)) for a, b in zip(grads, pgrads))
 
-    # per-kernel times of one eager batch on one stream (HIP events on the
-    # library's stream)
-    br1 = BatchRenderer(p, cams, targets, dict(best, streams=1))
-    br1.capacity = br.capacity
-    br1.depth_bits = br.depth_bits
-    br1.run_eager()
+    # per-kernel times of one eager batch (HIP events on the library's stream)
+    br.run_eager()
     torch.cuda.synchronize()
     L.trace_enable(True)
-    br1.run_eager()
+    br.run_eager()
     tr = L.trace_read(4096)
     L.trace_enable(False)
     kern_ms, kern_n = {}, {}
@@ -610,19 +621,21 @@ def run_batched(args):
         "config": {"workload": WORKLOADS["batched"], "n_gaussians": p.n,
                    "asset_sizes": [a.n for a in assets], "n_views": n_views,
                    "pixels": int(sum(c.width * c.height for c in cams)),
-                   "instances_per_view": caps, "autotuned": best},
+                   "instances_planned": cap, "autotuned": best},
         "plain_frames_per_s": round(n_views * 1000.0 / plain_ms, 2),
         "graph_speedup_vs_plain": round(plain_ms / ms_per_step, 3),
         "images_bitwise_equal_to_plain": bool(equal),
-        "autotune": [[t[0], round(t[1] * 1e3, 3)] for t in table],
+        "grads_rel_l2_vs_plain": grad_rel,
+        "autotune": {"best_ms_per_batch": round(tune_ms, 4), "candidates_timed": tune_n},
+        "launches_per_batch": sum(kern_n.values()),
         "stages": stages,
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
+    if full and not args.no_cpu_baseline:
         cb = cpu_baseline(assets, cams[0], dict(tile_w=16, tile_h=16))
         cb["sample"] = "view 0 of the batch (all assets): " + cb["sample"]
         out["cpu_baseline"] = cb
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def cpu_model():
