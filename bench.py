@@ -57,18 +57,33 @@ WORKLOADS = {
 }
 
 
+# Launch configuration per workload (tile shape, digit width, compositing
+# order), as the autotuner (--tile auto) picked them on MI355X.  Fixed by
+# default so that the counter measurements of the timed kernels
+# (profiles/pmc_traffic.json) belong to the configuration the bench times.
+TUNED = {
+    "tiny": ("16x16", 8, 1),
+    "medium": ("32x16", 8, 1),
+    "large": ("8x8", 8, 0),
+    "diff": ("32x16", 7, 1),
+    "avatar": ("32x16", 8, 1),
+    "mesh": ("32x16", 8, 1),
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", default="auto",
-                    help="WxH, or auto: the autotuner picks tile shape and digit width")
-    ap.add_argument("--radix-bits", type=int, default=8)
+    ap.add_argument("--tile", default=None,
+                    help="WxH; auto: the autotuner picks tile shape, digit width and "
+                         "compositing order; default: the workload's tuned configuration")
+    ap.add_argument("--radix-bits", type=int, default=None)
     ap.add_argument("--sort-mode", type=int, default=0)
-    ap.add_argument("--raster-order", type=int, default=1,
-                    help="with a fixed --tile: 1 = longest tile lists first, 0 = spatial runs")
+    ap.add_argument("--raster-order", type=int, default=None,
+                    help="1 = longest tile lists first, 0 = spatial runs")
     ap.add_argument("--packed", action="store_true",
                     help="forward from the FP16 pre-packed inputs (pre-packed once, untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -172,6 +187,21 @@ def measured_traffic(workload, kernel, cfg):
     if h.hexdigest()[:16] != rec["source_sha256_16"]:
         return None
     return int(rec["bytes_per_launch"])
+
+
+def evaluated_pairs(np, last, T_final, ranges, W, H, tw, th, t_eps):
+    """(pixel, Gaussian) pairs Eq. 3 evaluates: each pixel walks its tile's
+    list front to back up to the splat after which T fell below t_eps (`last`
+    holds one past that splat's rank in the list), or to the list's end."""
+    last = last.reshape(-1).view(np.uint32).astype(np.int64)
+    T = T_final.reshape(-1)
+    r = ranges.reshape(-1).view(np.uint32).astype(np.int64)
+    tx = (W + tw - 1) // tw
+    py, px = np.divmod(np.arange(W * H), W)
+    tile = (py // th) * tx + px // tw
+    length = r[2 * tile + 1] - r[2 * tile]
+    walk = np.where(T < t_eps, last, length)
+    return int(walk.sum())
 
 
 def frame_percentiles(torch, step, n, flush):
@@ -305,10 +335,10 @@ def run_view(args, full):
         tuned = [[f"{t[0]['tile_w']}x{t[0]['tile_h']}/{t[0]['radix_bits']}b/o{t[0]['raster_order']}",
                   round(t[1] * 1e3, 4)] for t in table]
     else:
-        tw, th = map(int, args.tile.split("x"))
-        bits = args.radix_bits
-        order = args.raster_order
-    args.radix_bits = bits
+        tile, bits, order = TUNED[args.workload]
+        tw, th = map(int, (args.tile or tile).split("x"))
+        bits = args.radix_bits if args.radix_bits is not None else bits
+        order = args.raster_order if args.raster_order is not None else order
     R = Renderer(dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=args.sort_mode,
                       raster_order=order))
 
@@ -361,11 +391,15 @@ def run_view(args, full):
     cold_ms, cold_avg = traced_stages(L, step, reps, flush)
     del flush
 
-    # composited (pixel, Gaussian) pairs of this frame, for the compositing roofline
+    # composited (pixel, Gaussian) pairs of this frame, for the compositing
+    # roofline, and the pairs Eq. 3 evaluates (each pixel walks its tile's
+    # list up to its stop)
     nbl = torch.empty((H, W), dtype=torch.int32, device="cuda")
     R.rasterize(f.splats, f.values, f.ranges, cam, n_blend=nbl, mesh=f.mesh)
     blends = int(nbl.sum(dtype=torch.int64).item())
     del nbl
+    evals = evaluated_pairs(np, f.last.cpu().numpy(), f.T_final.cpu().numpy(),
+                            f.ranges.cpu().numpy(), W, H, tw, th, R.settings.t_eps)
 
     rec = f.splats[: sc.n * 48].cpu().numpy().view(np.uint16).reshape(sc.n, 24)
     n_vis = int(np.count_nonzero(rec[:, 22] >= rec[:, 20]))
@@ -376,8 +410,8 @@ def run_view(args, full):
     if depth_bits > 0 and args.sort_mode == 0:
         depth_passes = -(-depth_bits // 9)
     else:
-        depth_passes = -(-(depth_bits or 32) // args.radix_bits)
-    passes = [depth_passes, -(-(key_bits - 32) // args.radix_bits)]
+        depth_passes = -(-(depth_bits or 32) // bits)
+    passes = [depth_passes, -(-(key_bits - 32) // bits)]
     ab = algorithmic_bytes(sc.n, n_vis, inst, K, W, H, tiles, depth_passes=passes[0])
     stages = {}
     for k, v in kern_avg.items():
@@ -394,7 +428,9 @@ def run_view(args, full):
         if k in stages:
             tf = flops[k] / (kern_avg[k] * 1e-3) / 1e12
             stages[k].update(algo_flops=int(flops[k]), tflops=round(tf, 3),
-                             alu_frac=round(tf / FP32_VECTOR_PEAK_TFLOPS, 4))
+                             alu_frac=round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
+                             evaluated_pairs=evals,
+                             gevals_per_s=round(evals / (kern_avg[k] * 1e-3) / 1e9, 2))
     stages_cold = {}
     for k, v in cold_avg.items():
         e = {"ms_per_launch": round(v, 5)}
@@ -410,7 +446,8 @@ def run_view(args, full):
         roofline = {"kernel": dom, "bound": "alu", "achieved": round(tf, 3),
                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                    "algo_flops_per_launch": int(flops[dom]), "blended_pairs": blends}
+                    "algo_flops_per_launch": int(flops[dom]), "blended_pairs": blends,
+                    "evaluated_pairs": evals}
     else:
         dom_gbs = ab[dom] / (kern_avg[dom] * 1e-3) / 1e9
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dom_gbs, 1),
@@ -418,7 +455,7 @@ def run_view(args, full):
                     "traffic": None, "algo_bytes_per_launch": int(ab[dom])}
     roofline["ms_per_launch"] = round(kern_avg[dom], 5)
     roofline["traffic"] = measured_traffic(args.workload, dom, dict(
-        tile_w=tw, tile_h=th, radix_bits=args.radix_bits, sort_mode=args.sort_mode,
+        tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=args.sort_mode,
         raster_order=order))
 
     out = {
@@ -438,7 +475,7 @@ def run_view(args, full):
                        ", FP16 pre-packed inputs" if args.packed and args.workload != "avatar"
                        else ""),
                    "n_gaussians": sc.n, "width": W, "raster_order": order,
-                   "height": H, "tile": f"{tw}x{th}", "radix_bits": args.radix_bits,
+                   "height": H, "tile": f"{tw}x{th}", "radix_bits": bits,
                    "visible": n_vis, "instances": inst, "key_bits": key_bits,
                    "depth_bits": depth_bits, "depth_passes": passes[0], "tile_passes": passes[1],
                    "first_tile_pass_fused_with_keygen": args.sort_mode == 0},
@@ -469,7 +506,8 @@ def run_sort32(args):
     from paper_2512_08478_amd.render import GaussianParams, Renderer
 
     sc, cam = S.large_scene(n=max(PAPER_SORT_MS))
-    R = Renderer(dict(radix_bits=args.radix_bits, sort_mode=args.sort_mode))
+    bits = args.radix_bits or 8
+    R = Renderer(dict(radix_bits=bits, sort_mode=args.sort_mode))
     p = GaussianParams.from_scene(sc)
     _, dkeys, _, _ = R.preprocess(p, cam, reuse=False)
     torch.cuda.synchronize()
@@ -513,7 +551,7 @@ def run_sort32(args):
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS["sort32"], "n_keys": n, "radix_bits": args.radix_bits,
+        "config": {"workload": WORKLOADS["sort32"], "n_keys": n, "radix_bits": bits,
                    "passes": passes},
         "sweep": rows,
         "roofline": {"kernel": "sort32_pass", "bound": "hbm", "achieved": round(gbs, 1),

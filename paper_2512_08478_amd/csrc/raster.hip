@@ -111,17 +111,18 @@ inline int raster_grid(const SetK& set, int tw, int th) {
 // (consecutive threads on consecutive rows) and the wave's reads (its 8
 // rows of one splat) both touch consecutive words.
 constexpr int kBatch = 64;  // splats per batch: one per lane
-template <bool DEPTH>
+// The forward stages no backward terms: its smaller LDS footprint lets more
+// of its one-wave workgroups share a CU.
+template <bool DEPTH, bool BWD>
 struct StageT {
   float4 hdr[kBatch];      // qa', r, g, b
-  float4 aux[kBatch];      // qb, qc', dy at the quadrant's first row, 1 / opacity
   float2 rows[kBatch][8];  // per quadrant row: log2(o) - qc' dy^2, and dx - qb dy at the
                            // quadrant's first column
-  uint32_t gid[kBatch];    // Gaussian index
   uint32_t pos[kBatch];    // the splat's position in the tile's list (as the kernel counts it)
   float dep[DEPTH ? kBatch : 1];  // camera-space depth (mesh depth test only)
+  float4 aux[BWD ? kBatch : 1];   // qb, qc', dy at the quadrant's first row, 1 / opacity
+  uint32_t gid[BWD ? kBatch : 1];  // Gaussian index
 };
-using Stage = StageT<false>;
 
 // The LDS operands of staged splats k and k + 1 at one pixel row: the row
 // terms (log2 weight offset, dx - qb dy at the first column) and headers.
@@ -131,7 +132,7 @@ struct PairOps {
   float d0, d1;  // depths (mesh depth test only)
 };
 template <bool DEPTH, int K>
-__device__ __forceinline__ void read_pair(const StageT<DEPTH>& S, std::integral_constant<int, K>,
+__device__ __forceinline__ void read_pair(const StageT<DEPTH, false>& S, std::integral_constant<int, K>,
                                           int row, PairOps& o) {
   o.q0 = S.rows[K][row];
   o.q1 = S.rows[K + 1][row];
@@ -205,7 +206,7 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
 // nothing), so the forward walk can take the splats in pairs without a
 // test.  Returns the number of hits.
 template <bool DEPTH, bool BWD>
-__device__ __forceinline__ int stage_batch(StageT<DEPTH>& S, bool valid, const SplatRec& r,
+__device__ __forceinline__ int stage_batch(StageT<DEPTH, BWD>& S, bool valid, const SplatRec& r,
                                            uint32_t g, uint32_t pos, int qx0, int qy0,
                                            int lane) {
   const float4 a = r.a, b = r.b;
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
                                                uint32_t* __restrict__ last,
                                                uint32_t* __restrict__ n_blend) {
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
-  __shared__ StageT<MESH> S;
+  __shared__ StageT<MESH, false> S;
   int tile, q;
   if (!pick_unit<NQ>(blockIdx.x, set, ranges, tile, q)) return;
   int trow = tile / set.tiles_x;
@@ -335,6 +336,9 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     // below alpha_min, or the pixel already stopped) gets alpha = 0, which
     // leaves C and T bitwise unchanged; only wave-uniform branches remain
     // (no lane blends this splat; every pixel of the wave has stopped).
+    // Testing a splat costs 4 vector instructions per pair (u, u^2, the
+    // log2 weight, the compare).  Predicated blends beat exec-masked ones
+    // here: the mask changes lengthen the walk of a wave that runs alone.
     thr = done ? kStopped : log2_tau;
     int lastk = -1;  // rank of this batch's last splat blended into the pixel
     // `tested`: the caller has already found a lane that may take the
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       C0 = fmaf(w, cr, C0);
       C1 = fmaf(w, cg, C1);
       C2 = fmaf(w, cb, C2);
-      T = T * (1.f - alpha);
+      T = T - w;  // T (1 - alpha), one instruction fewer
       lastk = take ? k : lastk;
       if constexpr (COUNT) nb += take ? 1u : 0u;
       thr = T < t_eps ? kStopped : thr;
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
       // both headers whole in registers here: otherwise the colour reads
       // sink into the blend and wait for LDS a second time
       float r0 = o.h0.y, g0 = o.h0.z, b0 = o.h0.w;
-      asm volatile("" : "+v"(r0), "+v"(g0), "+v"(b0));
+      asm volatile("" ::"v"(r0), "v"(g0), "v"(b0));
       const float u0 = o.q0.y + lxf, u1 = o.q1.y + lxf;
       const float e0 = fmaf(-o.h0.x, u0 * u0, o.q0.x);
       const float e1 = fmaf(-o.h1.x, u1 * u1, o.q1.x);
@@ -439,7 +443,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
                                                    const float* __restrict__ dL_dimage,
                                                    float* __restrict__ grad2d) {
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
-  __shared__ Stage S;
+  __shared__ StageT<false, true> S;
   __shared__ float s_red[8][12];  // per 8-lane group (pixel row): its 9 gradient sums
   int tile, q;
   if (!pick_unit<NQ>(blockIdx.x, set, ranges, tile, q)) return;
