@@ -363,10 +363,13 @@ int32_t gs_preprocess_packed(int32_t n_assets, const gs_asset* assets, int64_t n
  * first counts[0] entries are meaningful.
  *
  * Counts are read on the device; there is no host sync.  When counts[0] >
- * capacity, only the first `capacity` instances in depth order are kept,
- * `status_flag[0]` (device u32, may be NULL) gets bit 0 set, and the caller
- * retries with a larger capacity after checking the flag.  Bit 1 reports a
- * depth key range wider than settings.depth_bits (see gs_settings).
+ * capacity, `status_flag[0]` (device u32, may be NULL) gets bit 0 set and
+ * the output is not a valid instance list: some `capacity` instances are
+ * kept (sort_mode 1: the first ones in depth order; sort_mode 0: those the
+ * first tile-digit pass places below `capacity`, i.e. whole groups of
+ * tiles), and the caller retries with a larger capacity after checking the
+ * flag (or uses gs_sort_checked).  Bit 1 reports a depth key range wider
+ * than settings.depth_bits (see gs_settings).
  * Workspace: gs_workspace_size(GS_STAGE_SORT, n, capacity, cam, set).
  */
 int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
@@ -375,6 +378,21 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
                 uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
                 uint32_t* status_flag, void* workspace, size_t workspace_bytes,
                 void* stream);
+
+/*
+ * gs_sort_checked -- gs_sort for callers that size the instance buffers per
+ * frame (Algorithm 1 reads the instance count before sorting): waits for
+ * `stream`, reads counts[0] back, stores it in *required (host, may be
+ * NULL), and returns GS_ERR_CAPACITY without sorting when it exceeds
+ * `capacity`; otherwise runs gs_sort with the same arguments (same
+ * validation and errors).  One host sync per call.
+ */
+int32_t gs_sort_checked(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
+                        const uint32_t* tile_rects, const uint32_t* counts,
+                        const gs_camera* cam, const gs_settings* set, int64_t capacity,
+                        uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
+                        uint32_t* status_flag, void* workspace, size_t workspace_bytes,
+                        int64_t* required, void* stream);
 
 /*
  * gs_sort_plan -- host-only description of the radix passes gs_sort makes

@@ -28,7 +28,7 @@ SPLAT_BYTES = 48
 
 EXPORTED = (
     "gs_version", "gs_status_string", "gs_last_hip_error", "gs_default_settings",
-    "gs_workspace_size", "gs_sort_key_bits", "gs_preprocess", "gs_sort", "gs_sort_pairs",
+    "gs_workspace_size", "gs_sort_key_bits", "gs_preprocess", "gs_sort", "gs_sort_checked", "gs_sort_pairs",
     "gs_rasterize", "gs_rasterize_backward", "gs_trace_enable", "gs_trace_read",
     "gs_preprocess_assets", "gs_rasterize_backward_assets", "gs_rasterize_backward_2d",
     "gs_preprocess_backward_views", "gs_sort_pairs32", "gs_packed_sh_stride", "gs_prepack",
@@ -171,6 +171,9 @@ def load():
     lib.gs_preprocess_noalloc_max_n.argtypes = []
     lib.gs_sort.restype = I32
     lib.gs_sort.argtypes = [I64, P, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ, P]
+    lib.gs_sort_checked.restype = I32
+    lib.gs_sort_checked.argtypes = [I64, P, P, P, P, CAM, SET, I64, P, P, P, P, P, SZ,
+                                    ctypes.POINTER(I64), P]
     lib.gs_sort_pairs.restype = I32
     lib.gs_sort_pairs.argtypes = [I64, P, P, I32, P, P, SET, P, SZ, P]
     lib.gs_sort_pairs32.restype = I32

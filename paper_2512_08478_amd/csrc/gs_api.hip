@@ -635,11 +635,13 @@ int32_t sort_impl(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
 }
 }  // namespace
 
-int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
-                const uint32_t* tile_rects, const uint32_t* counts, const gs_camera* cam,
-                const gs_settings* set,
-                int64_t capacity, uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
-                uint32_t* status_flag, void* workspace, size_t workspace_bytes, void* stream) {
+namespace {
+// gs_sort's argument checks (no HIP call)
+int32_t sort_validate(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
+                      const uint32_t* tile_rects, const uint32_t* counts, const gs_camera* cam,
+                      const gs_settings* set, int64_t capacity, uint64_t* keys,
+                      uint32_t* values, uint32_t* tile_ranges, uint32_t* status_flag,
+                      void* workspace, size_t workspace_bytes) {
   int32_t r;
   if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
   if (n < 0 || n >= kMaxN || capacity < 0 || capacity > kMaxInstances) return GS_ERR_INVALID_ARGUMENT;
@@ -651,9 +653,46 @@ int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   if ((r = check_dev(keys, false)) || (r = check_dev(status_flag, false))) return r;
   const int tx = tiles_x_of(cam, set), ty = tiles_y_of(cam, set);
   if (workspace_bytes < gs::sort_layout(n, capacity, tx * ty).bytes) return GS_ERR_WORKSPACE;
-  if ((r = check_dev(workspace))) return r;
-  return sort_impl(n, splats, depth_keys, tile_rects, counts, tx, ty, set, capacity, keys, values,
-                   tile_ranges, status_flag, workspace, stream);
+  return check_dev(workspace);
+}
+}  // namespace
+
+int32_t gs_sort(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
+                const uint32_t* tile_rects, const uint32_t* counts, const gs_camera* cam,
+                const gs_settings* set,
+                int64_t capacity, uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
+                uint32_t* status_flag, void* workspace, size_t workspace_bytes, void* stream) {
+  int32_t r;
+  if ((r = sort_validate(n, splats, depth_keys, tile_rects, counts, cam, set, capacity, keys,
+                         values, tile_ranges, status_flag, workspace, workspace_bytes)))
+    return r;
+  return sort_impl(n, splats, depth_keys, tile_rects, counts, tiles_x_of(cam, set),
+                   tiles_y_of(cam, set), set, capacity, keys, values, tile_ranges, status_flag,
+                   workspace, stream);
+}
+
+int32_t gs_sort_checked(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
+                        const uint32_t* tile_rects, const uint32_t* counts, const gs_camera* cam,
+                        const gs_settings* set, int64_t capacity, uint64_t* keys,
+                        uint32_t* values, uint32_t* tile_ranges, uint32_t* status_flag,
+                        void* workspace, size_t workspace_bytes, int64_t* required,
+                        void* stream) {
+  int32_t r;
+  if ((r = sort_validate(n, splats, depth_keys, tile_rects, counts, cam, set, capacity, keys,
+                         values, tile_ranges, status_flag, workspace, workspace_bytes)))
+    return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the count the preprocess wrote on this stream, once it is there
+  uint32_t c0 = 0;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&c0, counts, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  if (required) *required = (int64_t)c0;
+  if ((int64_t)c0 > capacity) return GS_ERR_CAPACITY;
+  return sort_impl(n, splats, depth_keys, tile_rects, counts, tiles_x_of(cam, set),
+                   tiles_y_of(cam, set), set, capacity, keys, values, tile_ranges, status_flag,
+                   workspace, stream);
 }
 
 int32_t gs_sort_pairs(int64_t n, const uint64_t* keys_in, const uint32_t* values_in,

@@ -145,6 +145,18 @@ def test_sort_argument_validation(lib):
     assert srt(flag=ctypes.c_void_p(FAKE + 4)) == L.GS_ERR_MISALIGNED
     assert srt(ws=16) == L.GS_ERR_WORKSPACE
 
+    # gs_sort_checked validates the same way before its host sync
+    req = ctypes.c_int64(-7)
+
+    def chk(cap=16, values=F, ws=1 << 30, counts=F):
+        return lib.gs_sort_checked(4, F, F, F, counts, ctypes.byref(c), ctypes.byref(s), cap, None,
+                                   values, F, None, F, ws, ctypes.byref(req), None)
+    assert chk(cap=-1) == L.GS_ERR_INVALID_ARGUMENT
+    assert chk(values=None) == L.GS_ERR_INVALID_ARGUMENT
+    assert chk(counts=None) == L.GS_ERR_INVALID_ARGUMENT
+    assert chk(ws=16) == L.GS_ERR_WORKSPACE
+    assert req.value == -7  # untouched when the arguments are rejected
+
     def sp(n=8, kb=64, kin=F, kout=ctypes.c_void_p(FAKE + 4096), ws=1 << 30):
         return lib.gs_sort_pairs(n, kin, F, kb, kout, ctypes.c_void_p(FAKE + 8192), ctypes.byref(s),
                                  F, ws, None)

@@ -473,21 +473,101 @@ def test_shuffle_and_repeat_invariance(R):
     np.testing.assert_array_equal(a, c)
 
 
-def test_capacity_overflow_flag(R):
-    print_case("capacity overflow sets the flag")
+def generation_order(dkeys, rects, tiles_x):
+    """(tile, Gaussian) instances in the order key generation emits them:
+    visible Gaussians by depth key (index order among equal keys), each
+    Gaussian's tiles row-major."""
+    vis = np.nonzero(dkeys != 0xFFFFFFFF)[0]
+    vis = vis[np.argsort(dkeys[vis], kind="stable")]
+    r = rects.reshape(-1, 2)
+    out = []
+    for g in vis:
+        tx0, ty0 = int(r[g, 0] & 0xFFFF), int(r[g, 0] >> 16)
+        tx1, ty1 = int(r[g, 1] & 0xFFFF), int(r[g, 1] >> 16)
+        for ty in range(ty0, ty1 + 1):
+            for tx in range(tx0, tx1 + 1):
+                out.append((ty * tiles_x + tx, g))
+    return np.array(out, dtype=np.int64).reshape(-1, 2)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_capacity_overflow_keeps_the_documented_instances(mode):
+    """A too-small capacity raises bit 0 of the flag and keeps exactly the
+    instances gs_sort documents: sort mode 1 the first `capacity` in
+    generation (depth) order, sort mode 0 those the first tile-digit pass
+    places below `capacity`; each tile's list holds its kept instances in
+    depth order.  The full capacity clears the flag."""
+    from paper_2512_08478_amd.render import Renderer
+    print_case(f"capacity overflow, sort mode {mode}")
+    bits = 6
+    Rm = Renderer(dict(sort_mode=mode, radix_bits=bits))
+    sc, cam = S.tiny_scene()
+    p = gp(sc)
+    pre = Rm.preprocess(p, cam)
+    tot = int(u32(pre[3])[0])
+    tiles = Rm.tiles(cam)
+    tx = (cam.width + 15) // 16
+    gen = generation_order(u32(pre[1]), u32(pre[2]), tx)
+    assert len(gen) == tot
+    cap = tot // 2
+    if mode == 1:
+        kept = gen[:cap]
+    else:
+        kept = gen[np.argsort(gen[:, 0] & ((1 << bits) - 1), kind="stable")][:cap]
+    _, values, ranges, flag, _ = Rm.sort(sc.n, *pre, cam, capacity=cap)
+    torch.cuda.synchronize()
+    assert int(u32(flag)[0]) & 1 == 1
+    rng = u32(ranges)[:2 * tiles].reshape(-1, 2).astype(np.int64)
+    vals = u32(values)
+    assert rng[:, 1].max() <= cap
+    order = np.argsort(kept[:, 0], kind="stable")   # kept instances by tile, generation order within
+    kt = kept[order]
+    for t in range(tiles):
+        want = kt[kt[:, 0] == t, 1]
+        got = vals[rng[t, 0]:rng[t, 1]] if rng[t, 1] > rng[t, 0] else np.zeros(0, np.uint32)
+        np.testing.assert_array_equal(got, want, err_msg=f"tile {t}")
+    _, values, ranges, flag, _ = Rm.sort(sc.n, *pre, cam, capacity=tot)
+    torch.cuda.synchronize()
+    assert int(u32(flag)[0]) == 0
+
+
+def test_sort_checked_reports_the_required_capacity(R):
+    """gs_sort_checked returns GS_ERR_CAPACITY with the instance count when
+    the capacity is short, and otherwise sorts exactly as gs_sort."""
+    import ctypes
+    from paper_2512_08478_amd import _lib as L
+    print_case("gs_sort_checked")
+    lib = L.load()
     sc, cam = S.tiny_scene()
     p = gp(sc)
     pre = R.preprocess(p, cam)
-    tot = int(u32(pre[3])[0])  # counts[0]: instances
-    keys, values, ranges, flag, cap = R.sort(sc.n, *pre, cam, capacity=tot // 2)
     torch.cuda.synchronize()
-    assert int(u32(flag)[0]) & 1 == 1
-    # the kept half is the front of the depth order: every range lies inside it
-    rng = u32(ranges)[:2 * R.tiles(cam)].reshape(-1, 2)
-    assert rng[:, 1].max() <= tot // 2
-    keys, values, ranges, flag, cap = R.sort(sc.n, *pre, cam, capacity=tot)
-    torch.cuda.synchronize()
-    assert int(u32(flag)[0]) == 0
+    tot = int(u32(pre[3])[0])
+    _, v_ref, r_ref, _, _ = R.sort(sc.n, *pre, cam, capacity=tot)
+    v_ref, r_ref = u32(v_ref).copy(), u32(r_ref).copy()
+    c, s = L.make_camera(cam), R.settings
+    tiles = R.tiles(cam)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for cap, want in ((tot - 1, L.GS_ERR_CAPACITY), (tot, L.GS_OK), (tot + 100, L.GS_OK)):
+        values = torch.zeros(max(cap, 1), dtype=torch.int32, device="cuda")
+        ranges = torch.zeros(3 * tiles, dtype=torch.int32, device="cuda")
+        flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+        wsb = lib.gs_workspace_size(L.GS_STAGE_SORT, sc.n, cap, ctypes.byref(c), ctypes.byref(s))
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        req = ctypes.c_int64(-1)
+        st = lib.gs_sort_checked(sc.n, *[ptr(t) for t in pre], ctypes.byref(c), ctypes.byref(s),
+                                 cap, None, ptr(values), ptr(ranges), ptr(flag), ptr(ws), ws.numel(),
+                                 ctypes.byref(req), stream)
+        torch.cuda.synchronize()
+        assert st == want, (cap, st)
+        assert req.value == tot
+        if want == L.GS_OK:
+            assert int(u32(flag)[0]) == 0
+            np.testing.assert_array_equal(u32(ranges)[:2 * tiles], r_ref[:2 * tiles])
+            np.testing.assert_array_equal(u32(values)[:tot], v_ref[:tot])
+        else:
+            assert int(u32(values).max()) == 0  # nothing sorted
 
 
 @pytest.mark.parametrize("bits", [6, 8])
