@@ -7,6 +7,14 @@
 #include "gs_device.h"
 #include "gs_internal.h"
 
+// No implicit fusion of a multiply and an add into an FMA in the projection
+// (the FMAs it wants are written out): which products the compiler would
+// fuse depends on the code around the inlined functions (a loop over views
+// hoists the view-independent products out of the loop body, where they
+// cannot fuse), and a record must not depend on the kernel that computed it.
+#pragma float_control(push)
+#pragma clang fp contract(off)
+
 namespace gs {
 
 // Real SH normalisation constants (degree <= 3), with the sign of the
@@ -166,3 +174,5 @@ __device__ __forceinline__ void block_counts(uint32_t tiles, uint32_t dkey, uint
 }
 
 }  // namespace gs
+
+#pragma float_control(pop)

@@ -10,6 +10,11 @@
 #include "gs_internal.h"
 #include "gs_project.h"
 
+// The forward projection takes no implicit FMAs either (see gs_project.h):
+// the one-view and the batch kernels must write bitwise-equal records.
+#pragma float_control(push)
+#pragma clang fp contract(off)
+
 namespace gs {
 namespace {
 
@@ -238,28 +243,40 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
                         depth_keys, rects, partial);
 }
 
-// Every view of a batch and every asset in one launch: blockIdx.y is the
-// view, blockIdx.x runs over the assets' blocks (asset a owns blocks
-// [B.block0[a], B.block0[a + 1])).  View v's records, depth keys and tile
-// rects start at v * B.n; workgroup (b, v) writes its partial counts to slot
-// v * B.block0[n_assets] + b.  cams[v * n_assets + a] places asset a in view v.
+// Every view of a batch and every asset in one launch: blockIdx.x runs over
+// the assets' blocks (asset a owns blocks [B.block0[a], B.block0[a + 1])),
+// blockIdx.y over chunks of kViewsPerBlock views, which the workgroup
+// projects one after the other: its Gaussians' inputs come from HBM for the
+// first view and from the cache for the others, instead of once per view.
+// View v's records, depth keys and tile rects start at v * B.n; view v's
+// partial counts of workgroup b go to slot v * B.block0[n_assets] + b.
+// cams[v * n_assets + a] places asset a in view v.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_preprocess_views(
-    BatchPreK B, const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float4* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, const CamK* __restrict__ cams, SetK set,
-    gs_splat* __restrict__ splats, uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects,
-    uint4* __restrict__ partial) {
+    BatchPreK B, int n_views, const float* __restrict__ means,
+    const float* __restrict__ log_scales, const float4* __restrict__ quats,
+    const float* __restrict__ logits, const float* __restrict__ sh,
+    const CamK* __restrict__ cams, SetK set, gs_splat* __restrict__ splats,
+    uint32_t* __restrict__ depth_keys, uint2* __restrict__ rects, uint4* __restrict__ partial) {
   constexpr int K3 = (DEG + 1) * (DEG + 1) * 3;
-  const int v = blockIdx.y, b = blockIdx.x;
+  const int b = blockIdx.x;
   int a = 0;
   while (a + 1 < B.n_assets && B.block0[a + 1] <= b) ++a;
-  const int64_t o = B.offset[a], vo = (int64_t)v * B.n + o;
-  preprocess_block<DEG>(b - B.block0[a], B.count[a], means + 3 * o, log_scales + 3 * o, quats + o,
-                        logits + o, sh + K3 * o, cams[v * B.n_assets + a], set, splats + vo,
-                        depth_keys + vo, rects + vo,
-                        partial + (size_t)v * B.block0[B.n_assets]);  // slot blockIdx.x
+  const int64_t o = B.offset[a];
+  const int v0 = blockIdx.y * kViewsPerBlock;
+  const int v1 = min(n_views, v0 + kViewsPerBlock);
+  for (int v = v0; v < v1; ++v) {
+    const int64_t vo = (int64_t)v * B.n + o;
+    preprocess_block<DEG>(b - B.block0[a], B.count[a], means + 3 * o, log_scales + 3 * o,
+                          quats + o, logits + o, sh + K3 * o, cams[v * B.n_assets + a], set,
+                          splats + vo, depth_keys + vo, rects + vo,
+                          partial + (size_t)v * B.block0[B.n_assets]);  // slot blockIdx.x
+    __syncthreads();  // the next view reuses the LDS of this one
+  }
 }
+
+#pragma float_control(pop)
+#pragma float_control(push)
 
 // counts[0] = total instances, counts[1] = visible Gaussians, counts[2] and
 // counts[3] = the smallest and largest depth key of a visible Gaussian
@@ -702,7 +719,8 @@ hipError_t launch_preprocess_views(const BatchPreK& B, int n_views, const float*
   if (blocks > 0 && n_views > 0) {
     trace_mark(st, "preprocess_views");
     const float4* q4 = reinterpret_cast<const float4*>(quats);
-#define GS_PREV(D) hipLaunchKernelGGL(k_preprocess_views<D>, dim3(blocks, n_views), dim3(kBlock), 0, st, B, means, log_scales, q4, logits, sh, cams, set, splats, depth_keys, reinterpret_cast<uint2*>(tile_rects), partial)
+    const int chunks = (n_views + kViewsPerBlock - 1) / kViewsPerBlock;
+#define GS_PREV(D) hipLaunchKernelGGL(k_preprocess_views<D>, dim3(blocks, chunks), dim3(kBlock), 0, st, B, n_views, means, log_scales, q4, logits, sh, cams, set, splats, depth_keys, reinterpret_cast<uint2*>(tile_rects), partial)
     switch (degree) {
       case 0: GS_PREV(0); break;
       case 1: GS_PREV(1); break;
@@ -765,3 +783,5 @@ hipError_t launch_preprocess_backward_views(int n, const float* means, const flo
 }
 
 }  // namespace gs
+
+#pragma float_control(pop)
