@@ -154,6 +154,12 @@ class BatchRenderer:
         self.captured = True
 
     def replay(self, check=True):
+        """One launch of the captured batch.  With check=True it waits for
+        the stream and raises if the batch outgrew the planned instance
+        capacity or depth key bits (parameters changed since plan(); plan()
+        again).  With check=False nothing waits: when that happens the
+        images and gradients of that step are wrong, and the status flag
+        (self.flag, bits 0 and 1) says so."""
         if not self.captured:
             raise RuntimeError("capture() first")
         self.stream.wait_stream(torch.cuda.current_stream())
