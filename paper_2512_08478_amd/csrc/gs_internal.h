@@ -9,7 +9,7 @@
 namespace gs {
 
 constexpr int kBlock = 256;          // threads per block for streaming kernels
-constexpr int kViewsPerBlock = 8;    // views a batch preprocess workgroup projects in turn
+constexpr int kViewsPerBlock = 16;   // views a batch preprocess workgroup projects in turn
 constexpr int kSortItems = 16;       // keys per thread in a radix pass
 constexpr int kSortPart = kBlock * kSortItems;  // keys per partition (4096)
 constexpr int kMaxPassTotal = 32;    // radix passes per call (depth + tile, or 64-bit)
