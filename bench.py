@@ -496,6 +496,11 @@ def run_view(args, full):
     return out
 
 
+# Table 1's Sort column (ms; an RTX 4090 in WebGPU), at its four Gaussian
+# counts: context for the depth-only sort, not a target.
+PAPER_SORT_MS = {758_000: 0.20, 1_515_000: 0.22, 3_031_000: 0.32, 6_062_000: 0.58}
+
+
 def run_sort32(args):
     """Depth-only 32-bit key sort (the sort the paper times in Table 1) over
     the Table-1-shaped sweep of Gaussian counts."""
