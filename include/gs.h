@@ -638,12 +638,13 @@ typedef struct gs_batch_desc {
 } gs_batch_desc;
 
 /* Validates the description (the gs_preprocess_assets checks for every
- * camera; at most 256 views) and makes the batch: host memory, plus one
- * small pinned host block (hipHostMalloc) holding the camera and view
- * tables that every run copies into the workspace, so that the copy is
- * ordered on the stream.  No device memory.  GS_ERR_UNSUPPORTED when the
- * stacked tile grid exceeds 65535 tile rows or 2^26 tiles; GS_ERR_HIP when
- * the pinned block cannot be allocated. */
+ * camera; at most 256 views) and makes the batch in host memory (no HIP
+ * call).  The first gs_batch_plan / gs_batch_run / gs_batch_capture also
+ * allocates one small pinned host block (hipHostMalloc) for the camera and
+ * view tables that every run copies into the workspace, so that the copy
+ * is ordered on the stream (GS_ERR_HIP if that fails).
+ * GS_ERR_UNSUPPORTED when the stacked tile grid exceeds 65535 tile rows or
+ * 2^26 tiles. */
 int32_t gs_batch_create(const gs_batch_desc* desc, const gs_settings* set, gs_batch** batch);
 /* Frees the batch and its graph; call it once no work of the batch is
  * pending on any stream. */
@@ -658,8 +659,9 @@ size_t gs_batch_workspace_size(const gs_batch* batch, int64_t capacity);
 /* Counting pass: preprocesses every view into the workspace, waits for the
  * stream, and sets the capacity to ceil(instances * headroom) (at least
  * 256; headroom in [1, 4]) and the depth key bits to the visible range's
- * bit length plus one.  *capacity receives the capacity.
- * GS_ERR_CAPACITY when it would exceed 2^30 - 1 instances. */
+ * bit length plus one.  *capacity receives the capacity.  A graph captured
+ * before is dropped (capture again).  GS_ERR_CAPACITY when it would exceed
+ * 2^30 - 1 instances. */
 int32_t gs_batch_plan(gs_batch* batch, float headroom, void* workspace, size_t workspace_bytes,
                       int64_t* capacity, void* stream);
 /* The batch, eagerly: images[pixels * 4] and, with targets, the parameter
@@ -673,7 +675,8 @@ int32_t gs_batch_capture(gs_batch* batch, void* workspace, size_t workspace_byte
                          float* d_means, float* d_log_scales, float* d_quats,
                          float* d_opacity_logits, float* d_sh, uint32_t* status_flag,
                          void* stream);
-/* One launch of the captured graph on `stream`. */
+/* One launch of the captured graph on `stream` (GS_ERR_INVALID_ARGUMENT
+ * when there is none: not captured, or planned since). */
 int32_t gs_batch_launch(gs_batch* batch, void* stream);
 
 /*

@@ -1049,6 +1049,33 @@ BatchLayout batch_layout(const gs_batch* b, int64_t capacity) {
   return L;
 }
 
+// The pinned host copy of the camera and view tables and the count
+// read-back slot, made on the first call that uses the device.
+int32_t batch_host(gs_batch* b) {
+  if (b->host) return GS_OK;
+  const size_t cb = b->camk.size() * sizeof(gs::CamK), vb = b->viewk.size() * sizeof(gs::ViewK);
+  b->host_camk = 0;
+  b->host_viewk = gs::align_up(cb, 64);
+  b->host_counts = gs::align_up(b->host_viewk + vb, 64);
+  void* hp = nullptr;
+  const hipError_t e = hipHostMalloc(&hp, b->host_counts + 16, hipHostMallocDefault);
+  if (e != hipSuccess) return hip_fail(e);
+  b->host = static_cast<unsigned char*>(hp);
+  std::memcpy(b->host + b->host_camk, b->camk.data(), cb);
+  std::memcpy(b->host + b->host_viewk, b->viewk.data(), vb);
+  return GS_OK;
+}
+
+// A captured graph holds the capacity, depth bits and workspace it was
+// recorded with; a new plan drops it (gs_batch_launch then fails until the
+// next capture).
+void batch_drop_graph(gs_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
 // the tables the kernels read, copied into the workspace (stream-ordered)
 hipError_t batch_upload(const gs_batch* b, char* ws, hipStream_t st) {
   const BatchLayout L = batch_layout(b, b->capacity);
@@ -1232,19 +1259,6 @@ int32_t gs_batch_create(const gs_batch_desc* d, const gs_settings* set, gs_batch
       if ((r = make_camk(&b->cams[v], set, b->assets[a].model, &ck))) { delete b; return r; }
       ck.tile_row = b->viewk[v].row;
     }
-  const size_t cb = b->camk.size() * sizeof(gs::CamK), vb = b->viewk.size() * sizeof(gs::ViewK);
-  b->host_camk = 0;
-  b->host_viewk = gs::align_up(cb, 64);
-  b->host_counts = gs::align_up(b->host_viewk + vb, 64);
-  void* hp = nullptr;
-  hipError_t he = hipHostMalloc(&hp, b->host_counts + 16, hipHostMallocDefault);
-  if (he != hipSuccess) {
-    delete b;
-    return hip_fail(he);
-  }
-  b->host = static_cast<unsigned char*>(hp);
-  std::memcpy(b->host + b->host_camk, b->camk.data(), cb);
-  std::memcpy(b->host + b->host_viewk, b->viewk.data(), vb);
   *out = b;
   return GS_OK;
 }
@@ -1271,6 +1285,8 @@ int32_t gs_batch_plan(gs_batch* b, float headroom, void* workspace, size_t works
   if (!b || !capacity || !(headroom >= 1.f) || !(headroom <= 4.f)) return GS_ERR_INVALID_ARGUMENT;
   if (workspace_bytes < batch_layout(b, 0).bytes) return GS_ERR_WORKSPACE;
   if ((r = check_dev(workspace))) return r;
+  if ((r = batch_host(b))) return r;
+  batch_drop_graph(b);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   const int64_t keep = b->capacity;
@@ -1310,6 +1326,7 @@ int32_t gs_batch_run(gs_batch* b, void* workspace, size_t workspace_bytes, float
   if ((r = batch_check_run(b, workspace, workspace_bytes, images, d_means, d_log_scales, d_quats,
                            d_opacity_logits, d_sh, status_flag)))
     return r;
+  if ((r = batch_host(b))) return r;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = batch_upload(b, static_cast<char*>(workspace), st);
   if (e != hipSuccess) return hip_fail(e);
@@ -1326,6 +1343,7 @@ int32_t gs_batch_capture(gs_batch* b, void* workspace, size_t workspace_bytes, f
                            d_opacity_logits, d_sh, status_flag)))
     return r;
   if (!stream) return GS_ERR_INVALID_ARGUMENT;  // the legacy stream cannot be captured
+  if ((r = batch_host(b))) return r;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   // the tables go to the workspace before the capture (the graph reads
@@ -1333,8 +1351,7 @@ int32_t gs_batch_capture(gs_batch* b, void* workspace, size_t workspace_bytes, f
   hipError_t e = batch_upload(b, ws, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e);
-  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+  batch_drop_graph(b);
   e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e);
   r = batch_enqueue(b, ws, images, d_means, d_log_scales, d_quats, d_opacity_logits, d_sh,

@@ -340,3 +340,101 @@ def test_preprocess_noalloc_limits(lib):
     assert lib.gs_preprocess_noalloc(m + 1, *args) == L.GS_ERR_WORKSPACE
     assert lib.gs_preprocess_noalloc(-1, *args) == L.GS_ERR_INVALID_ARGUMENT
     assert lib.gs_preprocess_noalloc(2**31, *args) == L.GS_ERR_INVALID_ARGUMENT
+
+
+def batch_desc(n_views=3, n=100, tables=None, means=FAKE, cams=None, targets=None):
+    cams = cams or [cam_1080() for _ in range(n_views)]
+    arr_c = (L.GsCamera * max(1, len(cams)))(*cams)
+    tab, keep = L.asset_table(tables or [(0, n, None)])
+    d = L.GsBatchDesc()
+    d.n_views = n_views
+    d.cams = ctypes.cast(arr_c, ctypes.c_void_p)
+    d.n_assets = len(tables or [0])
+    d.assets = ctypes.cast(tab, ctypes.c_void_p)
+    d.n = n
+    d.means = means
+    d.log_scales = d.quats = d.opacity_logits = d.sh = FAKE
+    d.sh_degree = 0
+    d.targets = targets
+    return d, (arr_c, tab, keep)
+
+
+def test_batch_api_validation(lib):
+    """gs_batch_create makes a batch without any HIP call; the batch calls
+    reject bad arguments and calls out of order before touching the device."""
+    s = L.default_settings()
+    h = ctypes.c_void_p()
+
+    def create(d, st=s):
+        return lib.gs_batch_create(ctypes.byref(d), ctypes.byref(st), ctypes.byref(h))
+    assert lib.gs_batch_create(None, ctypes.byref(s), ctypes.byref(h)) == L.GS_ERR_INVALID_ARGUMENT
+    d, keep = batch_desc(n_views=0)
+    assert create(d) == L.GS_ERR_INVALID_ARGUMENT
+    d, keep = batch_desc(n_views=257, cams=[cam_1080()] * 257)
+    assert create(d) == L.GS_ERR_INVALID_ARGUMENT
+    d, keep = batch_desc(means=FAKE + 4)
+    assert create(d) == L.GS_ERR_MISALIGNED
+    d, keep = batch_desc(tables=[(0, 40, None), (50, 50, None)])       # a gap
+    assert create(d) == L.GS_ERR_INVALID_ARGUMENT
+    d, keep = batch_desc(targets=FAKE + 8)
+    assert create(d) == L.GS_ERR_MISALIGNED
+    d, keep = batch_desc()
+    assert create(d, L.default_settings(tile_w=7, tile_h=7)) == L.GS_ERR_UNSUPPORTED
+    tall = L.make_camera(S.pinhole_camera(S.look_at((0, 0, -8)), 512, 4096))
+    d, keep = batch_desc(n_views=200, cams=[tall] * 200)              # 51200 tile rows x 2 > 65535
+    assert create(d, L.default_settings(tile_w=16, tile_h=8)) == L.GS_ERR_UNSUPPORTED
+
+    # a valid batch of three 1080p views
+    d, keep = batch_desc()
+    assert create(d) == L.GS_OK and h.value
+    b = h
+    try:
+        assert lib.gs_batch_pixels(b) == 3 * 1920 * 1080
+        assert [lib.gs_batch_pixel_offset(b, v) for v in (0, 1, 2, 3, -1)] == \
+            [0, 1920 * 1080, 2 * 1920 * 1080, -1, -1]
+        assert lib.gs_batch_capacity(b) == -1                     # not planned
+        assert lib.gs_batch_workspace_size(b, 0) > 0
+        assert lib.gs_batch_workspace_size(b, -1) == 0
+        assert lib.gs_batch_workspace_size(b, 1 << 30) == 0
+        F = ctypes.c_void_p(FAKE)
+        cap = ctypes.c_int64(0)
+        need = lib.gs_batch_workspace_size(b, 0)
+        plan = lambda hr=1.1, ws=F, nb=need, c=ctypes.byref(cap): lib.gs_batch_plan(
+            b, ctypes.c_float(hr), ws, nb, c, None)
+        assert plan(hr=0.5) == L.GS_ERR_INVALID_ARGUMENT
+        assert plan(hr=5.0) == L.GS_ERR_INVALID_ARGUMENT
+        assert plan(hr=float("nan")) == L.GS_ERR_INVALID_ARGUMENT
+        assert plan(c=None) == L.GS_ERR_INVALID_ARGUMENT
+        assert plan(nb=need - 1) == L.GS_ERR_WORKSPACE
+        assert plan(ws=ctypes.c_void_p(FAKE + 4)) == L.GS_ERR_MISALIGNED
+        outs = [F] * 6 + [None]
+        # run and capture need a plan first; launch needs a capture
+        assert lib.gs_batch_run(b, F, 1 << 40, *outs, None) == L.GS_ERR_INVALID_ARGUMENT
+        assert lib.gs_batch_capture(b, F, 1 << 40, *outs, F) == L.GS_ERR_INVALID_ARGUMENT
+        assert lib.gs_batch_launch(b, None) == L.GS_ERR_INVALID_ARGUMENT
+        assert lib.gs_batch_launch(None, None) == L.GS_ERR_INVALID_ARGUMENT
+        assert lib.gs_batch_plan(None, ctypes.c_float(1.1), F, need, ctypes.byref(cap), None) == \
+            L.GS_ERR_INVALID_ARGUMENT
+    finally:
+        lib.gs_batch_destroy(b)
+    lib.gs_batch_destroy(None)
+    assert lib.gs_batch_pixels(None) == -1 and lib.gs_batch_workspace_size(None, 0) == 0
+
+    # gs_autotune rejects a malformed search space or repetition count
+    d, keep = batch_desc()
+    sp = L.GsAutotuneSpace()
+    best, ms, nev = L.GsSettings(), ctypes.c_float(0), ctypes.c_int32(0)
+    F = ctypes.c_void_p(FAKE)
+
+    def tune(space=sp, reps=2):
+        return lib.gs_autotune(ctypes.byref(d), ctypes.byref(s), ctypes.byref(space), reps,
+                               ctypes.c_float(1.1), F, 1 << 40, *([F] * 6), None,
+                               ctypes.byref(best), ctypes.byref(ms), ctypes.byref(nev), None)
+    assert tune(reps=0) == L.GS_ERR_INVALID_ARGUMENT
+    assert tune(reps=101) == L.GS_ERR_INVALID_ARGUMENT
+    bad = L.GsAutotuneSpace()
+    bad.n_tiles = 17
+    assert tune(space=bad) == L.GS_ERR_INVALID_ARGUMENT
+    bad = L.GsAutotuneSpace()
+    bad.n_modes = 3
+    assert tune(space=bad) == L.GS_ERR_INVALID_ARGUMENT
