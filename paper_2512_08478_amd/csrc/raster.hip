@@ -67,21 +67,24 @@ __device__ __forceinline__ int xcd_tile(int b, int run) {
 
 // The tile and quadrant of workgroup b.  raster_order 0: block-cyclic runs
 // (xcd_tile).  raster_order 1: the tiles in the heavy-first order that the
-// sort wrote after the ranges, one tile's quadrants on one XCD, tiles dealt
-// to the XCDs in turn, so that the longest lists start first and spread
-// over the chip.  False for padding workgroups (and for an order entry out
-// of range, which only a caller mixing raster_order values can produce).
+// sort wrote after the ranges, one tile's quadrants on one XCD, runs of
+// kRunTiles consecutive ranks dealt to the XCDs in turn: the longest lists
+// start first and spread over the chip, and since the order keeps each
+// wave's tiles of a class in row-major order, a run is mostly neighbouring
+// tiles, which share splats in that XCD's L2.
+// False for padding workgroups (and for an order entry out of range, which
+// only a caller mixing raster_order values can produce).
 template <int NQ>
 __device__ __forceinline__ bool pick_unit(int b, const SetK& set,
                                           const uint32_t* __restrict__ ranges, int& tile,
                                           int& q) {
   const int tiles = set.tiles_x * set.tiles_y;
   if (set.raster_order == 1) {
-    const int x = b % kXcds, i = b / kXcds;
-    const int rank = (i / NQ) * kXcds + x;
+    const int x = b % kXcds, j = (b / kXcds) / NQ;  // this XCD's j-th tile
+    const int rank = ((j / kRunTiles) * kXcds + x) * kRunTiles + j % kRunTiles;
     if (rank >= tiles) return false;
     tile = (int)ranges[2 * tiles + rank];
-    q = i % NQ;
+    q = (b / kXcds) % NQ;
     return tile < tiles;
   }
   const int unit = xcd_tile(b, kRunTiles * NQ);
@@ -98,7 +101,6 @@ inline int xcd_grid(int units, int run) {
 
 inline int raster_grid(const SetK& set, int tw, int th) {
   const int tiles = set.tiles_x * set.tiles_y, nq = (tw / 8) * (th / 8);
-  if (set.raster_order == 1) return (tiles + kXcds - 1) / kXcds * kXcds * nq;
   return xcd_grid(tiles * nq, kRunTiles * nq);
 }
 
