@@ -384,6 +384,28 @@ def run_view(args, full):
     frame_dist = {"warm": frame_percentiles(torch, step, args.steps, None),
                   "cold": frame_percentiles(torch, step, args.steps, flush)}
 
+    # The same frames sized per frame, as for a scene that changes: the
+    # instance count and depth key range are read back (one host sync) before
+    # each sort, instead of the plan taken once from the first frame.
+    def step_sized():
+        if skin is not None:
+            R.lbs_deform(canon, *skin, out=p)
+        f = R.forward(p, cam, mesh=mesh)
+        if backward:
+            G = torch.zeros((H, W, 4), device="cuda")
+            G[..., :3] = torch.sign(f.image[..., :3] - target) / (3.0 * H * W)
+            R.backward(p, cam, f, G)
+        return f
+
+    for _ in range(args.warmup):
+        step_sized()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_sized()
+    torch.cuda.synchronize()
+    ms_sized = (time.perf_counter() - t0) * 1e3 / args.steps
+
     # per-kernel durations, measured with HIP events recorded by libgs on the
     # stream its kernels run on
     reps = max(5, min(20, args.steps))
@@ -483,6 +505,8 @@ def run_view(args, full):
         "sort_ms": round(sort_ms, 4),
         "stages": stages,
         "frame_ms": frame_dist,
+        "ms_per_step_sized_per_frame": round(ms_sized, 4),
+        "frames_per_s_sized_per_frame": round(1000.0 / ms_sized, 2),
         "stages_cold": stages_cold,
         "roofline": roofline,
     }
