@@ -64,7 +64,7 @@ WORKLOADS = {
 TUNED = {
     "tiny": ("16x16", 8, 1),
     "medium": ("32x16", 8, 1),
-    "large": ("8x8", 8, 0),
+    "large": ("8x8", 8, 5),
     "diff": ("32x16", 7, 1),
     "avatar": ("32x16", 8, 1),
     "mesh": ("32x16", 8, 1),
@@ -83,7 +83,8 @@ def parse():
     ap.add_argument("--radix-bits", type=int, default=None)
     ap.add_argument("--sort-mode", type=int, default=0)
     ap.add_argument("--raster-order", type=int, default=None,
-                    help="1 = longest tile lists first, 0 = spatial runs")
+                    help="bit 0: longest tile lists first (else spatial runs); "
+                         "order >> 1 = s: forward quadrants in 2^s row bands")
     ap.add_argument("--packed", action="store_true",
                     help="forward from the FP16 pre-packed inputs (pre-packed once, untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -79,12 +79,16 @@ typedef struct gs_camera {
  *                    kernels; no workgroup waits on another); 1: onesweep
  *                    passes with decoupled look-back between workgroups.
  *                    Both give the same (unique) stable result.
- *   raster_order 1   order in which the compositing kernels take the tiles:
- *                    0: runs of neighbouring tiles dealt to the GPU's XCDs
- *                    in turn; 1: tiles with the longest splat lists first
- *                    (gs_sort then also writes that order).  gs_sort and
- *                    the compositing calls of a frame must use the same
- *                    value.  Images do not depend on it.
+ *   raster_order 1   how the compositing kernels take the tiles (0..5).
+ *                    Bit 0 clear: runs of neighbouring tiles dealt to the
+ *                    GPU's XCDs in turn; set: tiles with the longest splat
+ *                    lists first (gs_sort then also writes that order).
+ *                    raster_order >> 1 = s (0, 1 or 2; forward compositing
+ *                    only): each 8x8 pixel quadrant is taken as 2^s bands
+ *                    of 8 / 2^s rows, each by its own wave, which shortens
+ *                    the frame's tail when a few tiles hold very long
+ *                    lists.  gs_sort and the compositing calls of a frame
+ *                    must use the same value.  Images do not depend on it.
  *   depth_bits 0     how many bits of the depth keys gs_sort orders.  0:
  *                    all 32 bits, in radix_bits-wide passes.  1..32: the
  *                    keys relative to the smallest visible key (counts[2]
@@ -356,7 +360,7 @@ int32_t gs_preprocess_packed(int32_t n_assets, const gs_asset* assets, int64_t n
  * gs_preprocess).  Writes values[capacity] (u32 Gaussian index per sorted
  * instance), tile_ranges[3*tiles] (u32: first the [start, end) of each
  * tile in the sorted list, tiles = ceil(W/tile_w) * ceil(H/tile_h),
- * row-major; then, with raster_order 1, the tiles in the order the
+ * row-major; then, with raster_order 1 or 3, the tiles in the order the
  * compositing kernels take them: by decreasing floor(log2(list length + 1)),
  * in an unspecified order within a class) and, if
  * `keys` is not NULL, keys[capacity] (the sorted u64 keys above).  Only the
@@ -698,7 +702,7 @@ typedef struct gs_autotune_space {
   int32_t n_modes;
   int32_t modes[2];         /* sort modes */
   int32_t n_orders;
-  int32_t orders[2];        /* compositing orders */
+  int32_t orders[6];        /* compositing orders */
 } gs_autotune_space;
 int32_t gs_autotune(const gs_batch_desc* desc, const gs_settings* base,
                     const gs_autotune_space* space, int32_t reps, float headroom, void* workspace,

@@ -77,7 +77,7 @@ class GsAutotuneSpace(ctypes.Structure):
     _fields_ = [("n_tiles", ctypes.c_int32), ("tiles", ctypes.c_int32 * 32),
                 ("n_bits", ctypes.c_int32), ("bits", ctypes.c_int32 * 8),
                 ("n_modes", ctypes.c_int32), ("modes", ctypes.c_int32 * 2),
-                ("n_orders", ctypes.c_int32), ("orders", ctypes.c_int32 * 2)]
+                ("n_orders", ctypes.c_int32), ("orders", ctypes.c_int32 * 6)]
 
 
 class GsCamera(ctypes.Structure):

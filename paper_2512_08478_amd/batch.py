@@ -31,7 +31,7 @@ from .render import GaussianParams, Renderer
 TILE_SHAPES = ((16, 16), (16, 8), (32, 8), (8, 8), (32, 16), (32, 32), (64, 16), (64, 32))
 RADIX_BITS = (8, 7, 6)
 SORT_MODES = (0, 1)
-RASTER_ORDERS = (1, 0)
+RASTER_ORDERS = (1, 0, 3, 5, 2, 4)
 
 
 def l1_grad(image, target):

@@ -59,7 +59,7 @@ int32_t check_settings(const gs_settings* s) {
   if (!gs::tile_shape_supported(s->tile_w, s->tile_h)) return GS_ERR_UNSUPPORTED;
   if (s->radix_bits < 6 || s->radix_bits > 8) return GS_ERR_UNSUPPORTED;
   if (s->sort_mode != 0 && s->sort_mode != 1) return GS_ERR_UNSUPPORTED;
-  if (s->raster_order != 0 && s->raster_order != 1) return GS_ERR_UNSUPPORTED;
+  if (s->raster_order < 0 || s->raster_order > 5) return GS_ERR_UNSUPPORTED;  // bands 1, 2, 4
   if (s->depth_bits < 0 || s->depth_bits > 32) return GS_ERR_INVALID_ARGUMENT;
   if (!(s->eps2d >= 0.f) || !std::isfinite(s->eps2d)) return GS_ERR_INVALID_ARGUMENT;
   if (!(s->alpha_min > 0.f) || !(s->alpha_max > s->alpha_min) || !(s->alpha_max < 1.f))
@@ -543,7 +543,7 @@ int32_t sort_impl(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   const int tiles = tiles_x * tiles_y;
   const gs::SortLayout L = gs::sort_layout(n, capacity, tiles);
   const int bits = set->radix_bits, mode = set->sort_mode;
-  const bool heavy_first = set->raster_order == 1;
+  const bool heavy_first = (set->raster_order & 1) != 0;
   const int db = set->depth_bits;
   const SortPlan plan = plan_sort(tiles, set);
   const int* widths = plan.widths;
@@ -1387,7 +1387,7 @@ int32_t gs_autotune(const gs_batch_desc* desc, const gs_settings* base,
   if (!desc || !base || !space || !best || !best_ms || reps < 1 || reps > 100)
     return GS_ERR_INVALID_ARGUMENT;
   if (space->n_tiles < 0 || space->n_tiles > 16 || space->n_bits < 0 || space->n_bits > 8 ||
-      space->n_modes < 0 || space->n_modes > 2 || space->n_orders < 0 || space->n_orders > 2)
+      space->n_modes < 0 || space->n_modes > 2 || space->n_orders < 0 || space->n_orders > 6)
     return GS_ERR_INVALID_ARGUMENT;
   if ((r = check_settings(base))) return r;
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -65,32 +65,44 @@ __device__ __forceinline__ int xcd_tile(int b, int run) {
   return ((i / run) * kXcds + x) * run + i % run;
 }
 
-// The tile and quadrant of workgroup b.  raster_order 0: block-cyclic runs
-// (xcd_tile).  raster_order 1: the tiles in the heavy-first order that the
-// sort wrote after the ranges, one tile's quadrants on one XCD, runs of
-// kRunTiles consecutive ranks dealt to the XCDs in turn: the longest lists
-// start first and spread over the chip, and since the order keeps each
-// wave's tiles of a class in row-major order, a run is mostly neighbouring
-// tiles, which share splats in that XCD's L2.
+// The tile, quadrant and row band of workgroup b.  raster_order bit 0 clear:
+// block-cyclic runs (xcd_tile).  Bit 0 set: the tiles in the heavy-first
+// order that the sort wrote after the ranges, one tile's units on one XCD,
+// runs of kRunTiles consecutive ranks dealt to the XCDs in turn: the
+// longest lists start first and spread over the chip, and since the order
+// keeps each wave's tiles of a class in row-major order, a run is mostly
+// neighbouring tiles, which share splats in that XCD's L2.
+// raster_order >> 1 = ls (forward only, SPLIT): each quadrant is 2^ls
+// units of 8 >> ls pixel rows (bands), each staging only the splats that
+// reach its rows.  A dense tile's walk is then split over 2^ls waves,
+// which shortens the tail of a frame whose time goes to a few long lists,
+// at the price of idle lanes and of staging a splat once per band it
+// reaches.  band is in [0, 2^ls).
 // False for padding workgroups (and for an order entry out of range, which
 // only a caller mixing raster_order values can produce).
-template <int NQ>
+template <int NQ, bool SPLIT>
 __device__ __forceinline__ bool pick_unit(int b, const SetK& set,
                                           const uint32_t* __restrict__ ranges, int& tile,
-                                          int& q) {
+                                          int& q, int& band) {
   const int tiles = set.tiles_x * set.tiles_y;
-  if (set.raster_order == 1) {
-    const int x = b % kXcds, j = (b / kXcds) / NQ;  // this XCD's j-th tile
+  const int ls = SPLIT ? (set.raster_order >> 1) : 0;  // log2 bands per quadrant
+  const int U = NQ << ls;  // units per tile
+  int u;
+  if (set.raster_order & 1) {
+    const int x = b % kXcds, i = b / kXcds, j = i / U;  // this XCD's j-th tile
     const int rank = ((j / kRunTiles) * kXcds + x) * kRunTiles + j % kRunTiles;
     if (rank >= tiles) return false;
     tile = (int)ranges[2 * tiles + rank];
-    q = (b / kXcds) % NQ;
-    return tile < tiles;
+    u = i % U;
+    if (tile >= tiles) return false;
+  } else {
+    const int unit = xcd_tile(b, kRunTiles * U);
+    if (unit >= tiles * U) return false;
+    tile = unit / U;
+    u = unit % U;
   }
-  const int unit = xcd_tile(b, kRunTiles * NQ);
-  if (unit >= tiles * NQ) return false;
-  tile = unit / NQ;
-  q = unit % NQ;
+  q = u >> ls;
+  band = u & ((1 << ls) - 1);
   return true;
 }
 
@@ -99,9 +111,10 @@ inline int xcd_grid(int units, int run) {
   return (units + per - 1) / per * per;
 }
 
-inline int raster_grid(const SetK& set, int tw, int th) {
-  const int tiles = set.tiles_x * set.tiles_y, nq = (tw / 8) * (th / 8);
-  return xcd_grid(tiles * nq, kRunTiles * nq);
+inline int raster_grid(const SetK& set, int tw, int th, bool split) {
+  const int tiles = set.tiles_x * set.tiles_y;
+  const int u = ((tw / 8) * (th / 8)) << (split ? set.raster_order >> 1 : 0);
+  return xcd_grid(tiles * u, kRunTiles * u);
 }
 
 
@@ -198,7 +211,8 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
 
 // Staging of one batch, called by every lane of the wave (lane j holds the
 // batch's j-th splat when `valid`): whether the splat's footprint reaches
-// the quadrant whose top-left pixel is (qx0, qy0), and if so its
+// pixel rows hy0..hy1 of the quadrant whose top-left pixel is (qx0, qy0)
+// (all 8 rows, or the band the wave composites), and if so its
 // parameters, list position `pos` and per-row weight terms (with BWD also
 // the backward's terms and the Gaussian index g), written
 // at its rank among the batch's hits.  The reach test uses the record's
@@ -210,7 +224,7 @@ __device__ __forceinline__ SplatRec load_splat(const gs_splat* __restrict__ spla
 template <bool DEPTH, bool BWD>
 __device__ __forceinline__ int stage_batch(StageT<DEPTH, BWD>& S, bool valid, const SplatRec& r,
                                            uint32_t g, uint32_t pos, int qx0, int qy0,
-                                           int lane) {
+                                           int lane, int hy0, int hy1) {
   const float4 a = r.a, b = r.b;
   const float c = r.c;
   const float mx = a.x, my = a.y, qb = a.w;  // mean relative to the bbox corner (px0, py0)
@@ -218,7 +232,7 @@ __device__ __forceinline__ int stage_batch(StageT<DEPTH, BWD>& S, bool valid, co
   const float lo = log2f(b.y);
   const int px0 = (int)(r.lo & 0xFFFFu), py0 = (int)(r.lo >> 16);
   const int px1 = (int)(r.hi & 0xFFFFu), py1 = (int)(r.hi >> 16);
-  const bool hit = valid && px0 <= qx0 + 7 && px1 >= qx0 && py0 <= qy0 + 7 && py1 >= qy0;
+  const bool hit = valid && px0 <= qx0 + 7 && px1 >= qx0 && py0 <= hy1 && py1 >= hy0;
   const uint64_t hits = ballot(hit);
   const int nh = __builtin_popcountll(hits);
   if (hit) {
@@ -273,8 +287,8 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
                                                uint32_t* __restrict__ n_blend) {
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ StageT<MESH, false> S;
-  int tile, q;
-  if (!pick_unit<NQ>(blockIdx.x, set, ranges, tile, q)) return;
+  int tile, q, band;
+  if (!pick_unit<NQ, true>(blockIdx.x, set, ranges, tile, q, band)) return;
   int trow = tile / set.tiles_x;
   if (set.n_views > 0) {  // a batch: this tile's view, its pixels
     size_t pix;
@@ -290,7 +304,10 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
   const int lane = threadIdx.x;
   const int lx = lane & 7, row = lane >> 3;
   const int px = tx0 + lx, py = ty0 + row;
-  const bool inside = px < W && py < H;
+  // a band unit takes the pixels of its rows; the other lanes stay idle
+  const int ls = set.raster_order >> 1, prow = 8 >> ls;  // pixel rows per unit
+  const bool inside = px < W && py < H && (row >> (3 - ls)) == band;
+  const int hy0 = ty0 + prow * band, hy1 = hy0 + prow - 1;
   const float lxf = (float)lx;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
   const float log2_tau = set.log2_tau, t_eps = set.t_eps;
@@ -327,7 +344,7 @@ __global__ __launch_bounds__(64) void k_raster(const gs_splat* __restrict__ spla
     const int cnt = (int)min((uint32_t)kBatch, end - bs);
     __syncthreads();  // the previous batch's reads of S are done
     int nh = stage_batch<MESH, false>(S, lane < cnt, r_cur, g_cur, bs - start + lane + 1, tx0,
-                                      ty0, lane);
+                                      ty0, lane, hy0, hy1);
     // an opaque 32-bit scalar, so that the walk's end tests stay one
     // scalar compare (the compiler otherwise compares the 64-bit mask)
     asm volatile("" : "+s"(nh));
@@ -447,8 +464,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ StageT<false, true> S;
   __shared__ float s_red[8][12];  // per 8-lane group (pixel row): its 9 gradient sums
-  int tile, q;
-  if (!pick_unit<NQ>(blockIdx.x, set, ranges, tile, q)) return;
+  int tile, q, band;
+  if (!pick_unit<NQ, false>(blockIdx.x, set, ranges, tile, q, band)) return;
   int trow = tile / set.tiles_x;
   if (set.n_views > 0) {  // a batch: this tile's view, its pixels
     size_t pix;
@@ -504,7 +521,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       g = values[start + bs + lane];
       rec = load_splat(splats, g);
     }
-    const int nh = stage_batch<false, true>(S, lane < cnt, rec, g, bs + lane, tx0, ty0, lane);
+    const int nh = stage_batch<false, true>(S, lane < cnt, rec, g, bs + lane, tx0, ty0, lane,
+                                            ty0, ty0 + 7);
     __syncthreads();
     // Lanes never branch apart: a pair a lane must not revisit (position at
     // or past its `last`, or weight below alpha_min) gets alpha = 0, which
@@ -577,7 +595,7 @@ template <int TW, int TH>
 void raster_fwd(const gs_splat* splats, const uint32_t* values, const uint32_t* ranges,
                 const SetK& set, int W, int H, const float* mesh_depth, const float* mesh_rgb,
                 float* image, float* T_final, uint32_t* last, uint32_t* n_blend, hipStream_t st) {
-#define GS_K(M, C) hipLaunchKernelGGL((k_raster<TW, TH, M, C>), dim3(raster_grid(set, TW, TH)), dim3(64), 0, st, splats, values, ranges, set, W, H, mesh_depth, mesh_rgb, image, T_final, last, n_blend)
+#define GS_K(M, C) hipLaunchKernelGGL((k_raster<TW, TH, M, C>), dim3(raster_grid(set, TW, TH, true)), dim3(64), 0, st, splats, values, ranges, set, W, H, mesh_depth, mesh_rgb, image, T_final, last, n_blend)
   if (mesh_depth) {
     if (n_blend) GS_K(true, true); else GS_K(true, false);
   } else {
@@ -590,7 +608,7 @@ template <int TW, int TH>
 void raster_bwd(const gs_splat* splats, const uint32_t* values, const uint32_t* ranges,
                 const SetK& set, int W, int H, const float* bg_rgb, const float* T_final,
                 const uint32_t* last, const float* dL_dimage, float* grad2d, hipStream_t st) {
-  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(raster_grid(set, TW, TH)), dim3(64), 0, st,
+  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(raster_grid(set, TW, TH, false)), dim3(64), 0, st,
                      splats, values, ranges, set, W, H, bg_rgb, T_final, last, dL_dimage, grad2d);
 }
 

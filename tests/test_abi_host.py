@@ -321,7 +321,7 @@ def test_lbs_validation(lib):
 
 def test_raster_order_validation_and_sort_workspace(lib):
     c = cam_1080()
-    bad = L.default_settings(raster_order=2)
+    bad = L.default_settings(raster_order=6)
     assert lib.gs_sort_key_bits(ctypes.byref(c), ctypes.byref(bad)) == -1
     s = L.default_settings()
     # the sort workspace holds 16 tile-class segments of `tiles` entries
@@ -437,4 +437,7 @@ def test_batch_api_validation(lib):
     assert tune(space=bad) == L.GS_ERR_INVALID_ARGUMENT
     bad = L.GsAutotuneSpace()
     bad.n_modes = 3
+    assert tune(space=bad) == L.GS_ERR_INVALID_ARGUMENT
+    bad = L.GsAutotuneSpace()
+    bad.n_orders = 7
     assert tune(space=bad) == L.GS_ERR_INVALID_ARGUMENT

@@ -144,7 +144,8 @@ def test_graph_batch_matches_plain_views_on_every_replay(R):
     print(f"{len(cams)} views, {p.n} Gaussians, capacity {br.capacity}")
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8, 0, 1), (32, 16, 6, 1, 0), (64, 32, 7, 0, 1)])
+@pytest.mark.parametrize("shape", [(8, 8, 8, 0, 1), (32, 16, 6, 1, 0), (64, 32, 7, 0, 1),
+                                   (16, 8, 8, 0, 3), (32, 16, 7, 1, 2)])
 def test_batch_settings_forward_only(R, shape):
     """A forward-only batch (no targets) in several tile shapes, digit
     widths, sort modes and orders: images bitwise equal to plain views."""
