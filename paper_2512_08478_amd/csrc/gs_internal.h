@@ -94,6 +94,9 @@ SortLayout sort_layout(int64_t n, int64_t capacity, int tiles);
 // tiles with floor(log2(list length + 1)) = kTileClasses - 1 - k (the last
 // class also every shorter list).
 constexpr int kTileClasses = 16;
+// Up to this many tiles, one workgroup writes the heavy-first order (one
+// launch instead of the class and order kernels).
+constexpr int kFusedOrderTiles = 8192;
 SortLayout pairs_layout(int64_t n);  // gs_sort_pairs: dk[0]/dv[0] are the u64/u32 alternates
 
 // One stable LSD radix sort of (key, value) pairs.

@@ -933,6 +933,63 @@ __global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restric
   }
 }
 
+// The heavy-first tile order of at most kFusedOrderTiles tiles, computed
+// by one workgroup from the finished ranges: each tile's class (by the
+// length of its list), the class sizes counted with one LDS atomic per
+// class and wave, their exclusive scan, then each tile written at its
+// class's next free rank.  Order within a class is unspecified.
+constexpr int kFoBlock = 1024;                        // threads of the one workgroup
+constexpr int kFoPer = kFusedOrderTiles / kFoBlock;  // tiles per thread
+constexpr int kFoChunk = 4;                           // range loads in flight per thread
+__device__ void order_tiles_block(const uint32_t* ranges, int tiles, uint32_t* order) {
+  __shared__ uint32_t s_cnt[kTileClasses];
+  __shared__ uint8_t s_cls[kFusedOrderTiles];
+  const int t = threadIdx.x, lane = lane_id();
+  if (tiles <= 0) return;
+  if (t < kTileClasses) s_cnt[t] = 0;
+  __syncthreads();
+  // thread t takes tiles t, t + kFoBlock, ...: classes into LDS, counted
+  for (int j0 = 0; j0 < kFoPer && j0 * kFoBlock < tiles; j0 += kFoChunk) {
+    // branch-free loads (past the last tile: the last tile, not used)
+    uint2 r[kFoChunk];
+#pragma unroll
+    for (int j = 0; j < kFoChunk; ++j)
+      r[j] = *reinterpret_cast<const uint2*>(ranges + 2 * min((j0 + j) * kFoBlock + t, tiles - 1));
+#pragma unroll
+    for (int j = 0; j < kFoChunk; ++j) {
+      const int tile = (j0 + j) * kFoBlock + t;
+      const bool ok = tile < tiles;
+      const int lg = 31 - __builtin_clz(r[j].y - r[j].x + 1u);  // floor(log2(len + 1))
+      const uint32_t k = (uint32_t)(kTileClasses - 1 - min(lg, kTileClasses - 1));
+      if (ok) s_cls[tile] = (uint8_t)k;
+      const uint64_t same = match_digit<4>(k, ballot(ok));
+      if (ok && lane == __builtin_ctzll(same))
+        atomicAdd(&s_cnt[k], (uint32_t)__builtin_popcountll(same));
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < kTileClasses; ++k) {
+      const uint32_t c = s_cnt[k];
+      s_cnt[k] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < kFoPer && j * kFoBlock < tiles; ++j) {
+    const int tile = j * kFoBlock + t;
+    const bool ok = tile < tiles;
+    const uint32_t k = ok ? s_cls[tile] : 0u;
+    const uint64_t same = match_digit<4>(k, ballot(ok));
+    const int leader = same ? __builtin_ctzll(same) : 0;
+    uint32_t base = 0;
+    if (ok && lane == leader) base = atomicAdd(&s_cnt[k], (uint32_t)__builtin_popcountll(same));
+    base = shfl_u32(base, leader);
+    if (ok) order[base + (uint32_t)__builtin_popcountll(same & lanemask_lt())] = (uint32_t)tile;
+  }
+}
+
 // Tile ranges of the sorted tile keys.  Each thread takes 4 consecutive
 // keys with one 16-byte load plus the keys on either side.  The key buffer
 // is padded to a multiple of 64 keys, so the vector load of the last group
@@ -956,6 +1013,14 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint32_t* __restri
       }
     }
   }
+}
+
+// The heavy-first order of at most kFusedOrderTiles tiles in one
+// workgroup (one launch instead of the class and order kernels).
+__global__ __launch_bounds__(kFoBlock) void k_tile_order_one(const uint32_t* __restrict__ ranges,
+                                                           int tiles,
+                                                           uint32_t* __restrict__ order) {
+  order_tiles_block(ranges, tiles, order);
 }
 
 // Heavy-first tile order, step 1: each tile joins its class (by the
@@ -1305,14 +1370,19 @@ hipError_t launch_keygen_fused(int64_t n, int bits, const uint32_t* sorted_idx,
 hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
                               uint32_t* ranges, hipStream_t st) {
   if (capacity == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_ranges, dim3(stream_grid((capacity + 3) / 4, 4096)), dim3(kBlock), 0, st, count,
-                     tkeys, ranges);
+  hipLaunchKernelGGL(k_tile_ranges, dim3(stream_grid((capacity + 3) / 4, 4096)), dim3(kBlock), 0,
+                     st, count, tkeys, ranges);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_order(uint32_t* ranges, int tiles, uint32_t* cls_count, uint32_t* seg,
                              hipStream_t st) {
   if (tiles <= 0) return hipSuccess;
+  if (tiles <= kFusedOrderTiles) {
+    hipLaunchKernelGGL(k_tile_order_one, dim3(1), dim3(kFoBlock), 0, st, ranges, tiles,
+                       ranges + 2 * (size_t)tiles);
+    return hipGetLastError();
+  }
   const int grid = (tiles + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_tile_classes, dim3(grid), dim3(kBlock), 0, st, ranges, tiles, cls_count,
                      seg);

@@ -444,11 +444,14 @@ def test_tile_shape_and_digit_width_invariance(R):
                                       err_msg=f"{tw}x{th} bits {bits} mode {mode} order {order}")
 
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3, 4, 5])
-def test_tile_order_is_a_permutation(R, order):
-    print_case(f"tile order written by the sort (raster_order {order})")
+@pytest.mark.parametrize("order,tile", [(0, 8), (1, 8), (2, 8), (3, 8), (4, 8), (5, 8),
+                                        (1, 32), (3, 32)])
+def test_tile_order_is_a_permutation(R, order, tile):
+    """8x8 tiles at 1080p (32,400 tiles): the order comes from the class and
+    order kernels; 32x16 (4,080 tiles): from the one-workgroup kernel."""
+    print_case(f"tile order written by the sort (raster_order {order}, {tile}x{tile // 2 if tile > 8 else 8} tiles)")
     from paper_2512_08478_amd.render import Renderer
-    Rs = Renderer(dict(tile_w=8, tile_h=8, raster_order=order))
+    Rs = Renderer(dict(tile_w=tile, tile_h=tile // 2 if tile > 8 else 8, raster_order=order))
     sc, cam = S.medium_scene(n=200_000)
     fr = Rs.forward(gp(sc), cam)
     tiles = Rs.tiles(cam)
@@ -467,7 +470,8 @@ def test_tile_order_is_a_permutation(R, order):
         # the whole-quadrant walk's bitwise (the backward reads T_final and
         # the last splat index), and the gradients agree up to the order of
         # the backward's float atomics (which differs from run to run)
-        R0 = Renderer(dict(tile_w=8, tile_h=8, raster_order=order & 1))
+        R0 = Renderer(dict(tile_w=Rs.settings.tile_w, tile_h=Rs.settings.tile_h,
+                           raster_order=order & 1))
         f0 = R0.forward(gp(sc), cam)
         for name in ("image", "T_final", "last"):
             assert torch.equal(getattr(f0, name), getattr(fr, name)), name
@@ -479,6 +483,27 @@ def test_tile_order_is_a_permutation(R, order):
         g0 = R0.backward(gp(sc), cam, f0, torch.ones_like(f0.image))
         for a, b in zip(g0, g):
             assert float((b - a).norm()) <= 1e-5 * float(a.norm())
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (32, 16)])
+def test_tile_order_with_no_instances(R, tile):
+    """A capacity given but no instance in the frame: every tile is empty,
+    and the heavy-first order is still a permutation of all tiles (1080p:
+    32,400 tiles at 8x8, ordered by the class and order kernels; 4,080 at
+    32x16, by the one-workgroup kernel)."""
+    print_case(f"tile order of an empty frame, {tile[0]}x{tile[1]} tiles")
+    from paper_2512_08478_amd.render import Renderer
+    sc, _ = S.tiny_scene()
+    cam = S.pinhole_camera(S.look_at((0.0, 0.0, -3.0)), 1920, 1080, 60.0)
+    sc = sc.subset(np.arange(16))
+    sc.means[:, 2] = -10.0  # all behind the camera
+    Rs = Renderer(dict(tile_w=tile[0], tile_h=tile[1], raster_order=1))
+    fr = Rs.forward(gp(sc), cam, capacity=1024)
+    tiles = Rs.tiles(cam)
+    rg = u32(fr.ranges)
+    assert np.all(rg[:2 * tiles] == 0)
+    assert sorted(rg[2 * tiles:3 * tiles].tolist()) == list(range(tiles))
+    assert np.all(fr.image.cpu().numpy()[..., 3] == 0)
 
 
 def test_shuffle_and_repeat_invariance(R):
