@@ -408,6 +408,32 @@ def run_view(args, full):
     torch.cuda.synchronize()
     ms_sized = (time.perf_counter() - t0) * 1e3 / args.steps
 
+    # The 1M scene's whole 8-view orbit (the same launch configuration; each
+    # view planned once from its first frame, like view 0 above)
+    orbit = None
+    if args.workload == "medium" and not args.packed:
+        from paper_2512_08478_amd import scenes as S
+        per_view = []
+        for v in range(8):
+            cv = S.orbit_camera(v, 8, 8.0, W, H)
+            fv = R.forward(p, cv)
+            torch.cuda.synchronize()
+            cap_v, db_v = fv.capacity, fv.depth_bits
+            for _ in range(args.warmup):
+                R.forward(p, cv, capacity=cap_v, depth_bits=db_v)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fv = R.forward(p, cv, capacity=cap_v, depth_bits=db_v)
+            torch.cuda.synchronize()
+            ms_v = (time.perf_counter() - t0) * 1e3 / args.steps
+            if int(fv.flag[0].item()) & 3:
+                raise RuntimeError(f"orbit view {v}: plan exceeded during the timed steps")
+            per_view.append((round(ms_v, 4), int(cap_v)))
+        orbit = {"ms_per_view": [m for m, _ in per_view],
+                 "instances_per_view": [c for _, c in per_view],
+                 "frames_per_s": round(8000.0 / sum(m for m, _ in per_view), 2)}
+
     # per-kernel durations, measured with HIP events recorded by libgs on the
     # stream its kernels run on
     reps = max(5, min(20, args.steps))
@@ -509,6 +535,7 @@ def run_view(args, full):
         "frame_ms": frame_dist,
         "ms_per_step_sized_per_frame": round(ms_sized, 4),
         "frames_per_s_sized_per_frame": round(1000.0 / ms_sized, 2),
+        "orbit_8_views": orbit,
         "stages_cold": stages_cold,
         "roofline": roofline,
     }

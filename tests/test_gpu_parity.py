@@ -383,13 +383,17 @@ def test_render_medium_1080p_whole_image(R, orc, view, shape):
           f"instances {fr.capacity}")
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (16, 16, 8)])
+@pytest.mark.parametrize("shape", [(8, 8, 8, 5), (8, 8, 8, 1), (16, 16, 8, 1)])
 def test_render_large_6m_whole_image(R, orc, shape):
     """Every pixel of the 6M frame (eye inside the cloud; its densest 8x8
-    tiles hold tens of thousands of splats) against the tiled oracle."""
-    print_case(f"render 6M 1920x1080 whole image, tiles {shape[0]}x{shape[1]}")
+    tiles hold tens of thousands of splats) against the tiled oracle, in the
+    benchmark's launch configuration (8x8 tiles, heavy tiles first, each
+    quadrant in 4 bands of 2 rows) and with whole quadrants."""
+    print_case(f"render 6M 1920x1080 whole image, tiles {shape[0]}x{shape[1]}, "
+               f"raster_order {shape[3]}")
     from paper_2512_08478_amd.render import Renderer
-    Rs = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2]))
+    Rs = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2],
+                       raster_order=shape[3]))
     sc, cam = scene_cached("large")
     fr = Rs.forward(gp(sc), cam)
     img = fr.image.cpu().numpy().reshape(-1, 4)
