@@ -548,25 +548,28 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       T = Ti;
       // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
       // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y;
-      // no gradient flows through alpha where the alpha_max clamp binds
-      const float dy = x.z + rowf;
+      // no gradient flows through alpha where the alpha_max clamp binds.
+      // Per pixel, with dQ = dL/dQ':
+      //   mean x: -2 dQ qa' u      mean y: 2 dQ (qa' u qb - qc' dy)
+      //   qa': c dQ u^2            qb: -2 dQ qa' u dy
+      //   qc': c dQ dy^2           opacity: dal 2^e / o = -dQ / (ln2 o)
+      // (c = log2(e) / 2).  dy is the same for the 8 pixels of a row, so
+      // the row's 9 sums follow from the sums of dQ, dQ qa' u and dQ u^2.
       const float dal = take && gw < set.amax ? dalpha : 0.f;
-      const float gop = dal * gw * x.w;
-      const float dQ = -kLn2 * gw * dal;  // dL/dQ'
-      const float qau = h.x * u;
-      const float gqa = dQ * kHalfLog2e * (u * u);
-      const float gqb = -2.f * dQ * qau * dy;
-      const float gqc = dQ * kHalfLog2e * (dy * dy);
-      const float gmx = -2.f * dQ * qau;
-      const float gmy = 2.f * dQ * (qau * x.x - x.y * dy);
-      const float rs[9] = {oct_sum_dpp(gmx), oct_sum_dpp(gmy), oct_sum_dpp(gqa),
-                           oct_sum_dpp(gqb), oct_sum_dpp(gqc), oct_sum_dpp(gop),
-                           oct_sum_dpp(gr),  oct_sum_dpp(gg),  oct_sum_dpp(gb)};
+      const float dQ = -kLn2 * gw * dal;
+      const float dQau = dQ * (h.x * u);
+      const float dQuu = dQ * (u * u);
+      const float sQ = oct_sum_dpp(dQ), sA = oct_sum_dpp(dQau), sU = oct_sum_dpp(dQuu);
+      const float sr = oct_sum_dpp(gr), sg = oct_sum_dpp(gg), sb = oct_sum_dpp(gb);
       if ((lane & 7) == 7) {
+        const float dy = x.z + rowf;
         float* dst = s_red[lane >> 3];
-        *reinterpret_cast<float4*>(dst) = make_float4(rs[0], rs[1], rs[2], rs[3]);
-        *reinterpret_cast<float4*>(dst + 4) = make_float4(rs[4], rs[5], rs[6], rs[7]);
-        dst[8] = rs[8];
+        *reinterpret_cast<float4*>(dst) =
+            make_float4(-2.f * sA, 2.f * (sA * x.x - (x.y * dy) * sQ), kHalfLog2e * sU,
+                        -2.f * dy * sA);
+        *reinterpret_cast<float4*>(dst + 4) =
+            make_float4(kHalfLog2e * (dy * dy) * sQ, -sQ * x.w * (1.f / kLn2), sr, sg);
+        dst[8] = sb;
       }
       // lane k adds value k: one atomic instruction over 9 consecutive words
       if (lane < 9) {
