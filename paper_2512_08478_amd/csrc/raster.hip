@@ -463,7 +463,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
                                                    float* __restrict__ grad2d) {
   constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8);
   __shared__ StageT<false, true> S;
-  __shared__ float s_red[8][12];  // per 8-lane group (pixel row): its 9 gradient sums
+  // per 8-lane group (pixel row): the 9 gradient sums of up to two splats
+  __shared__ __attribute__((aligned(16))) float s_red[8][24];
   int tile, q, band;
   if (!pick_unit<NQ, false>(blockIdx.x, set, ranges, tile, q, band)) return;
   int trow = tile / set.tiles_x;
@@ -527,10 +528,15 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
     // Lanes never branch apart: a pair a lane must not revisit (position at
     // or past its `last`, or weight below alpha_min) gets alpha = 0, which
     // leaves T, S and B bitwise unchanged and yields zero gradients.
-    auto visit = [&](int k, float u, float e, const float4& h) {
+    // One splat's visit: the back-to-front state update and this lane's
+    // gradient terms (zero where the lane does not take the splat).  False
+    // when no lane takes it (nothing changes).
+    struct Terms {
+      float q, a, uu, r, g, b;  // dQ, dQ qa' u, dQ u^2, dL/d(r, g, b) of the pixel
+    };
+    auto visit = [&](int k, float u, float e, const float4& h, Terms& t) -> bool {
       const bool take = S.pos[k] < mylast && e >= log2_tau;
-      if (!ballot(take)) return;
-      const float4 x = S.aux[k];  // qb, qc', dy at the quadrant's first row, 1 / opacity
+      if (!ballot(take)) return false;
       const float gw = take ? hw_exp2(e) : 0.f;
       const float alpha = __builtin_amdgcn_fmed3f(gw, 0.f, set.amax);  // as the forward
       const float om = 1.f - alpha;
@@ -538,7 +544,6 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       const float Ti = take ? T * __builtin_amdgcn_rcpf(om) : T;
       const float cr = h.y, cg = h.z, cb = h.w;
       const float w = alpha * Ti;
-      const float gr = dC0 * w, gg = dC1 * w, gb = dC2 * w;
       const float dalpha = Ti * (dC0 * (cr - S0) + dC1 * (cg - S1) + dC2 * (cb - S2) -
                                  B * bgdot + dA * B);
       S0 = fmaf(alpha, cr - S0, S0);
@@ -548,22 +553,30 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       T = Ti;
       // weight 2^e, e = log2(o) - Q', Q' = qa' u^2 + qc' dy^2,
       // u = dx - qb dy, dx = px + 1/2 - mean_x, dy = py + 1/2 - mean_y;
-      // no gradient flows through alpha where the alpha_max clamp binds.
-      // Per pixel, with dQ = dL/dQ':
-      //   mean x: -2 dQ qa' u      mean y: 2 dQ (qa' u qb - qc' dy)
-      //   qa': c dQ u^2            qb: -2 dQ qa' u dy
-      //   qc': c dQ dy^2           opacity: dal 2^e / o = -dQ / (ln2 o)
-      // (c = log2(e) / 2).  dy is the same for the 8 pixels of a row, so
-      // the row's 9 sums follow from the sums of dQ, dQ qa' u and dQ u^2.
+      // no gradient flows through alpha where the alpha_max clamp binds
       const float dal = take && gw < set.amax ? dalpha : 0.f;
-      const float dQ = -kLn2 * gw * dal;
-      const float dQau = dQ * (h.x * u);
-      const float dQuu = dQ * (u * u);
-      const float sQ = oct_sum_dpp(dQ), sA = oct_sum_dpp(dQau), sU = oct_sum_dpp(dQuu);
-      const float sr = oct_sum_dpp(gr), sg = oct_sum_dpp(gg), sb = oct_sum_dpp(gb);
+      t.q = -kLn2 * gw * dal;  // dL/dQ'
+      t.a = t.q * (h.x * u);
+      t.uu = t.q * (u * u);
+      t.r = dC0 * w;
+      t.g = dC1 * w;
+      t.b = dC2 * w;
+      return true;
+    };
+    // The 9 gradient sums of splat k over this lane's pixel row, written
+    // by the row's last lane to dst[0..8].  Per pixel, with dQ = dL/dQ':
+    //   mean x: -2 dQ qa' u      mean y: 2 dQ (qa' u qb - qc' dy)
+    //   qa': c dQ u^2            qb: -2 dQ qa' u dy
+    //   qc': c dQ dy^2           opacity: dal 2^e / o = -dQ / (ln2 o)
+    // (c = log2(e) / 2).  dy is the same for the 8 pixels of a row, so the
+    // row's 9 sums follow from the row sums of dQ, dQ qa' u and dQ u^2 and
+    // the 3 colour terms.
+    auto row_sums = [&](int k, const Terms& t, float* dst) {
+      const float sQ = oct_sum_dpp(t.q), sA = oct_sum_dpp(t.a), sU = oct_sum_dpp(t.uu);
+      const float sr = oct_sum_dpp(t.r), sg = oct_sum_dpp(t.g), sb = oct_sum_dpp(t.b);
       if ((lane & 7) == 7) {
+        const float4 x = S.aux[k];  // qb, qc', dy at the quadrant's first row, 1 / opacity
         const float dy = x.z + rowf;
-        float* dst = s_red[lane >> 3];
         *reinterpret_cast<float4*>(dst) =
             make_float4(-2.f * sA, 2.f * (sA * x.x - (x.y * dy) * sQ), kHalfLog2e * sU,
                         -2.f * dy * sA);
@@ -571,15 +584,22 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
             make_float4(kHalfLog2e * (dy * dy) * sQ, -sQ * x.w * (1.f / kLn2), sr, sg);
         dst[8] = sb;
       }
-      // lane k adds value k: one atomic instruction over 9 consecutive words
-      if (lane < 9) {
+    };
+    // The 8 rows' sums added up and sent with one float-atomic instruction:
+    // lane j < 9 adds value j of splat k0, lane 12 + j value j of splat k1
+    // (when `both`).
+    auto send = [&](int k0, int k1, bool both) {
+      const int j = lane % 12;
+      if (lane < (both ? 24 : 12) && j < 9) {
         const float v = ((s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane])) +
                         ((s_red[4][lane] + s_red[5][lane]) + (s_red[6][lane] + s_red[7][lane]));
-        atomicAdd(grad2d + (size_t)S.gid[k] * kGrad2dStride + lane, v);
+        const uint32_t gid = S.gid[lane < 12 ? k0 : k1];
+        atomicAdd(grad2d + (size_t)gid * kGrad2dStride + j, v);
       }
     };
     // two staged splats per step, back to front: both LDS reads are in
-    // flight before the first one is visited
+    // flight before the first one is visited; the two visits' gradients go
+    // through one LDS exchange and one atomic instruction
     for (int k0 = nh - 1; k0 >= 0; k0 -= 2) {
       const bool two = k0 > 0;
       const int k1 = two ? k0 - 1 : k0;
@@ -588,8 +608,18 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const gs_splat* __restrict__ 
       const float u0 = q0.y + lxf, u1 = q1.y + lxf;
       const float e0 = fmaf(-h0.x, u0 * u0, q0.x);
       const float e1 = fmaf(-h1.x, u1 * u1, q1.x);
-      visit(k0, u0, e0, h0);
-      if (two) visit(k1, u1, e1, h1);
+      Terms t0, t1;
+      const bool v0 = visit(k0, u0, e0, h0, t0);
+      const bool v1 = two && visit(k1, u1, e1, h1, t1);
+      if (v0 && v1) {
+        row_sums(k0, t0, s_red[row]);
+        row_sums(k1, t1, s_red[row] + 12);
+        send(k0, k1, true);
+      } else if (v0 || v1) {
+        const int k = v0 ? k0 : k1;
+        row_sums(k, v0 ? t0 : t1, s_red[row]);
+        send(k, k, false);
+      }
     }
   }
 }
