@@ -552,10 +552,16 @@ int32_t sort_impl(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   hipStream_t st = static_cast<hipStream_t>(stream);
   auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
   uint32_t* count = U(L.count);
-  gs::trace_mark(st, "sort_init");
-  hipError_t e = gs::launch_sort_init(L, ws, mode, tile_ranges, tiles, status_flag, counts,
-                                      capacity, st, heavy_first ? U(L.tcls) : nullptr, db);
-  if (e != hipSuccess) return hip_fail(e);
+  // sort mode 0 with work to do: the first depth pass's count kernel does
+  // the set-up; otherwise a launch of its own
+  const bool fold_init = mode == 0 && n > 0 && capacity > 0;
+  hipError_t e = hipSuccess;
+  if (!fold_init) {
+    gs::trace_mark(st, "sort_init");
+    e = gs::launch_sort_init(L, ws, mode, tile_ranges, tiles, status_flag, counts, capacity, st,
+                             heavy_first ? U(L.tcls) : nullptr, db);
+    if (e != hipSuccess) return hip_fail(e);
+  }
   if (n == 0 || capacity == 0) {
     if (heavy_first) {
       gs::trace_mark(st, "tile_order");
@@ -580,6 +586,9 @@ int32_t sort_impl(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   d.table = U(L.table); d.totals = U(L.totals);
   d.hist = U(L.hist); d.tickets = U(L.tickets); d.lookback = U(L.lookback); d.lb_parts = L.parts;
   d.kbase = db > 0 ? counts + 2 : nullptr;
+  if (fold_init)
+    d.init = gs::sort_init_args(L, ws, tile_ranges, tiles, status_flag, counts, capacity,
+                                heavy_first ? U(L.tcls) : nullptr, db);
   if (mode == 0)
     e = gs::launch_radix_sort_widths(d, widths, pd, false, "depth_pass", st);
   else
@@ -590,6 +599,7 @@ int32_t sort_impl(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   uint2* drect = reinterpret_cast<uint2*>(ws + L.drect);
   const uint2* rects = reinterpret_cast<const uint2*>(tile_rects);
   gs::RadixArgs<uint32_t> t = d;
+  t.init.active = 0;
   t.n_grid = capacity;
   t.count = count;
   t.drop_first = 0;

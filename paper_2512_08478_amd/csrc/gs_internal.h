@@ -100,6 +100,25 @@ constexpr int kFusedOrderTiles = 8192;
 SortLayout pairs_layout(int64_t n);  // gs_sort_pairs: dk[0]/dv[0] are the u64/u32 alternates
 
 // One stable LSD radix sort of (key, value) pairs.
+// The sort's set-up: tile ranges, tickets and class counts cleared, and
+// the instance count (counts[0] capped at the capacity) and status flag
+// written.  Done by k_sort_init, or in sort mode 0 by the first depth
+// pass's count kernel (`active`), which saves a launch.
+struct SortInitK {
+  uint32_t* ranges;
+  int ranges_len;
+  uint32_t* tickets;
+  int ntickets;
+  uint32_t* cls_count;
+  uint32_t* count;
+  const uint32_t* total_src;
+  uint32_t host_total;
+  int64_t capacity;
+  uint32_t* status_flag;
+  int depth_bits;
+  int active;
+};
+
 template <typename KeyT>
 struct RadixArgs {
   int mode;                 // 0 reduce-then-scan, 1 onesweep (decoupled look-back)
@@ -120,6 +139,7 @@ struct RadixArgs {
   uint32_t* tickets;        // mode 1: one per pass
   uint32_t* lookback;       // mode 1: two buffers of lb_parts x 256 words
   int lb_parts;
+  SortInitK init;           // mode 0: the set-up, done by the first pass's count kernel
 };
 
 // Launchers (enqueue only; return the first launch error).
@@ -170,6 +190,10 @@ hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* t
                             int tiles, uint32_t* status_flag, const uint32_t* total_src,
                             int64_t capacity, hipStream_t st, uint32_t* cls_count = nullptr,
                             int depth_bits = 0);
+// The same set-up (sort mode 0) as arguments for the first depth pass.
+SortInitK sort_init_args(const SortLayout& L, char* ws, uint32_t* tile_ranges, int tiles,
+                         uint32_t* status_flag, const uint32_t* total_src, int64_t capacity,
+                         uint32_t* cls_count, int depth_bits);
 // Passes first_pass .. passes-1 (digit p at shift p * bits); the pass that
 // would have come before first_pass has left its output in kin/vin.
 template <typename KeyT>

@@ -41,31 +41,30 @@ constexpr int kKgItems = 4;        // sorted Gaussians per thread in the keygen
 constexpr int kKgPart = kBlock * kKgItems;
 constexpr int kRsMinParts = 384;   // reduce-then-scan passes aim for at least this many partitions
 
-__global__ __launch_bounds__(kBlock) void k_sort_init(uint32_t* hist, int hist_len,
-                                                      uint32_t* tickets, int ntickets,
-                                                      uint32_t* lookback, int lb_len,
-                                                      uint32_t* ranges, int ranges_len,
-                                                      uint32_t* count, const uint32_t* total_src,
-                                                      uint32_t host_total, int64_t capacity,
-                                                      uint32_t* status_flag, uint32_t* cls_count,
-                                                      int depth_bits) {
-  const int stride = gridDim.x * kBlock;
-  const int i0 = blockIdx.x * kBlock + threadIdx.x;
-  if (cls_count && i0 < kTileClasses) cls_count[i0] = 0;
-  for (int i = i0; i < lb_len; i += stride) lookback[i] = 0;
-  for (int i = i0; i < ranges_len; i += stride) ranges[i] = 0;
-  for (int i = i0; i < hist_len; i += stride) hist[i] = 0;
-  if (i0 < ntickets) tickets[i0] = 0;
+// Thread i0 of `stride` threads takes its share of the set-up.
+__device__ __forceinline__ void sort_init_body(const SortInitK& I, int i0, int stride) {
+  if (I.cls_count && i0 < kTileClasses) I.cls_count[i0] = 0;
+  for (int i = i0; i < I.ranges_len; i += stride) I.ranges[i] = 0;
+  if (i0 < I.ntickets) I.tickets[i0] = 0;
   if (i0 == 0) {
-    const uint32_t tot = total_src ? *total_src : host_total;
-    const bool over = (int64_t)tot > capacity;
-    *count = over ? (uint32_t)capacity : tot;
+    const uint32_t tot = I.total_src ? *I.total_src : I.host_total;
+    const bool over = (int64_t)tot > I.capacity;
+    *I.count = over ? (uint32_t)I.capacity : tot;
     // total_src = counts: counts[1] visible, counts[2..3] their depth key range
     bool range_over = false;
-    if (total_src && depth_bits > 0 && depth_bits < 32 && total_src[1] > 0)
-      range_over = ((total_src[3] - total_src[2]) >> depth_bits) != 0u;
-    if (status_flag) *status_flag = (over ? 1u : 0u) | (range_over ? 2u : 0u);
+    if (I.total_src && I.depth_bits > 0 && I.depth_bits < 32 && I.total_src[1] > 0)
+      range_over = ((I.total_src[3] - I.total_src[2]) >> I.depth_bits) != 0u;
+    if (I.status_flag) *I.status_flag = (over ? 1u : 0u) | (range_over ? 2u : 0u);
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_init(SortInitK I, uint32_t* hist, int hist_len,
+                                                      uint32_t* lookback, int lb_len) {
+  const int stride = gridDim.x * kBlock;
+  const int i0 = blockIdx.x * kBlock + threadIdx.x;
+  for (int i = i0; i < lb_len; i += stride) lookback[i] = 0;
+  for (int i = i0; i < hist_len; i += stride) hist[i] = 0;
+  sort_init_body(I, i0, stride);
 }
 
 template <typename KeyT, int BITS>
@@ -128,12 +127,14 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const KeyT* __restrict__ 
                                                        const uint32_t* __restrict__ count,
                                                        int64_t n_host, int drop,
                                                        const uint32_t* __restrict__ kbase,
-                                                       int shift, uint32_t* __restrict__ table) {
+                                                       int shift, uint32_t* __restrict__ table,
+                                                       SortInitK init) {
   constexpr int NB = 1 << BITS;
   constexpr int NS = kBlock / 16;  // sub-histograms
   constexpr int PART = kBlock * ITEMS;
   __shared__ uint32_t s_h[NS][NB + 1];
   const int t = threadIdx.x, lane = lane_id();
+  if (init.active) sort_init_body(init, blockIdx.x * kBlock + t, gridDim.x * kBlock);
   const uint32_t n = read_n(count, n_host);
   const uint32_t base = blockIdx.x * PART;
   if (base >= n) return;
@@ -1115,12 +1116,12 @@ void launch_pass(int grid, bool write_keys, const KeyT* ki, const uint32_t* vi, 
 template <typename KeyT, int BITS, int ITEMS>
 void rs_pass(const RadixArgs<KeyT>& a, int shift, const uint32_t* cnt, int drop,
              const uint32_t* kbase, const KeyT* ki, const uint32_t* vi, KeyT* kd, uint32_t* vd,
-             bool write_keys, hipStream_t st) {
+             bool write_keys, const SortInitK& init, hipStream_t st) {
   constexpr int PART = kBlock * ITEMS;
   constexpr int NB = 1 << BITS;
   const int parts = (int)((a.n_grid + PART - 1) / PART);
   hipLaunchKernelGGL((k_rs_upsweep<KeyT, BITS, ITEMS>), dim3(parts), dim3(kBlock), 0, st, ki, cnt,
-                     a.n_grid, drop, kbase, shift, a.table);
+                     a.n_grid, drop, kbase, shift, a.table, init);
   hipLaunchKernelGGL((k_col_scan<NB, PART>), dim3(NB / 4), dim3(kBlock), 0, st, a.table, cnt,
                      a.n_grid, a.totals);
   launch_pass<KeyT, BITS, ITEMS, false>(parts, write_keys, ki, vi, kd, vd, cnt, a.n_grid, drop,
@@ -1137,10 +1138,12 @@ void rs_pass_items(const RadixArgs<KeyT>& a, int p, int shift, const KeyT* ki, c
   const int drop = first && a.drop_first ? 1 : 0;
   const uint32_t* kbase = first ? a.kbase : nullptr;
   const uint32_t* cnt = (!first && a.drop_first) ? a.count_rest : a.count;
+  SortInitK init = a.init;
+  init.active = first && a.init.active;  // the set-up runs once, with the first pass
   switch (rs_items(a.n_grid)) {
-    case 16: rs_pass<KeyT, BITS, 16>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, st); break;
-    case 8: rs_pass<KeyT, BITS, 8>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, st); break;
-    default: rs_pass<KeyT, BITS, 4>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, st); break;
+    case 16: rs_pass<KeyT, BITS, 16>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, init, st); break;
+    case 8: rs_pass<KeyT, BITS, 8>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, init, st); break;
+    default: rs_pass<KeyT, BITS, 4>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, init, st); break;
   }
 }
 
@@ -1232,19 +1235,36 @@ SortLayout pairs_layout(int64_t n) {
   return L;
 }
 
+SortInitK sort_init_args(const SortLayout& L, char* ws, uint32_t* tile_ranges, int tiles,
+                         uint32_t* status_flag, const uint32_t* total_src, int64_t capacity,
+                         uint32_t* cls_count, int depth_bits) {
+  SortInitK I{};
+  I.ranges = tile_ranges;
+  I.ranges_len = tile_ranges ? 2 * tiles : 0;
+  I.tickets = reinterpret_cast<uint32_t*>(ws + L.tickets);
+  I.ntickets = kMaxPassTotal;
+  I.cls_count = cls_count;
+  I.count = reinterpret_cast<uint32_t*>(ws + L.count);
+  I.total_src = total_src;
+  I.host_total = (uint32_t)capacity;
+  I.capacity = capacity;
+  I.status_flag = status_flag;
+  I.depth_bits = depth_bits;
+  I.active = 1;
+  return I;
+}
+
 hipError_t launch_sort_init(const SortLayout& L, char* ws, int mode, uint32_t* tile_ranges,
                             int tiles, uint32_t* status_flag, const uint32_t* total_src,
                             int64_t capacity, hipStream_t st, uint32_t* cls_count,
                             int depth_bits) {
   const int lb_len = mode == 1 ? 2 * L.parts * 256 : 0;
-  const int ranges_len = tile_ranges ? 2 * tiles : 0;
-  const int64_t most = lb_len > ranges_len ? lb_len : ranges_len;
-  hipLaunchKernelGGL(k_sort_init, dim3(stream_grid(most, 1024)), dim3(kBlock), 0, st,
+  const SortInitK I = sort_init_args(L, ws, tile_ranges, tiles, status_flag, total_src, capacity,
+                                     cls_count, depth_bits);
+  const int64_t most = lb_len > I.ranges_len ? lb_len : I.ranges_len;
+  hipLaunchKernelGGL(k_sort_init, dim3(stream_grid(most, 1024)), dim3(kBlock), 0, st, I,
                      reinterpret_cast<uint32_t*>(ws + L.hist), mode == 1 ? kMaxPassTotal * 256 : 0,
-                     reinterpret_cast<uint32_t*>(ws + L.tickets), kMaxPassTotal,
-                     reinterpret_cast<uint32_t*>(ws + L.lookback), lb_len, tile_ranges, ranges_len,
-                     reinterpret_cast<uint32_t*>(ws + L.count), total_src, (uint32_t)capacity,
-                     capacity, status_flag, cls_count, depth_bits);
+                     reinterpret_cast<uint32_t*>(ws + L.lookback), lb_len);
   return hipGetLastError();
 }
 
