@@ -86,7 +86,9 @@ __device__ __forceinline__ uint32_t read_n(const uint32_t* count, int64_t n_host
   return count ? *count : (uint32_t)n_host;
 }
 
-// Block-wide exclusive scan of one u32 per thread (256 threads).
+// Block-wide exclusive scan of one u32 per thread (NT threads; s_tmp holds
+// NT / 64 words).
+template <int NT = kBlock>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const uint32_t incl = wave_incl_scan(v);
@@ -94,7 +96,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp,
   __syncthreads();
   uint32_t off = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) {
+  for (int w = 0; w < NT / 64; ++w) {
     off += w < wave ? s_tmp[w] : 0u;
     tot += s_tmp[w];
   }
@@ -574,8 +576,9 @@ __global__ __launch_bounds__(kBlock) void k_kg_count(uint32_t n, const uint32_t*
   if (threadIdx.x == 0) kg_counts[blockIdx.x] = tot;
 }
 
-// Block-wide exclusive max-scan of one u32 per thread (256 threads): the
+// Block-wide exclusive max-scan of one u32 per thread (NT threads): the
 // largest value held by any lower thread, 0 for thread 0.
+template <int NT = kBlock>
 __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* s_tmp) {
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const uint32_t incl = wave_incl_max_dpp(v);
@@ -583,7 +586,7 @@ __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* s_tmp) 
   if (lane == 63) s_tmp[wave] = incl;
   __syncthreads();
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w)
+  for (int w = 0; w < NT / 64; ++w)
     if (w < wave) excl = max(excl, s_tmp[w]);
   __syncthreads();
   return excl;
@@ -591,6 +594,17 @@ __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* s_tmp) 
 
 constexpr int kKgWin = 2048;              // instances expanded per window
 constexpr int kKgWinItems = kKgWin / kBlock;
+// The fused keygen scatter: threads per workgroup and instances per window.
+// A slice's windows run one after another.  Up to kKgWideMaxN Gaussians
+// the slices fit on the GPU at once, and the kernel takes as long as its
+// heaviest slice (the nearest, largest Gaussians): 512 threads expand its
+// windows faster (1M frame 35.7 -> 29.4 us).  Beyond that the slices come
+// in several rounds, and 256-thread workgroups, more of which fit at once,
+// are faster (6M frame 82.9 -> 79.1 us).
+constexpr int kKgScatThreads = 256;
+constexpr int kKgScatWideThreads = 512;
+constexpr int kKgScatWin = 2048;
+constexpr int64_t kKgWideMaxN = 2000000;
 
 // Instances in depth order: slice p of the depth-sorted visible list starts
 // at kg_prefix[p] (scanned slice counts) and writes (tile id, Gaussian
@@ -766,8 +780,8 @@ __global__ __launch_bounds__(kBlock) void k_kg_hist(uint32_t n, const uint32_t* 
 // no key list written and read back in between.  Positions at or past
 // `cap` are skipped (capacity overflow); every position below it still
 // receives exactly one pair.
-template <int BITS>
-__global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restrict__ sorted_idx,
+template <int BITS, int NT, int WIN>
+__global__ __launch_bounds__(NT) void k_kg_scatter(const uint32_t* __restrict__ sorted_idx,
                                                        const uint32_t* __restrict__ vis_count,
                                                        const uint2* __restrict__ sorted_rects,
                                                        int tiles_x,
@@ -777,12 +791,14 @@ __global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restric
                                                        uint32_t* __restrict__ tkeys,
                                                        uint32_t* __restrict__ tvals) {
   constexpr int NB = 1 << BITS;
-  constexpr int NW = kBlock / 64;
-  constexpr int IT = kKgWinItems;
+  constexpr int NW = NT / 64;
+  constexpr int IT = WIN / NT;       // window positions per thread
+  constexpr int KI = kKgPart / NT;   // slice Gaussians per thread
+  static_assert(NT >= (1 << BITS) && kKgPart % NT == 0 && WIN % NT == 0, "shape");
   __shared__ uint32_t s_off[kKgPart];
   __shared__ uint32_t s_lo[kKgPart], s_hi[kKgPart], s_g[kKgPart];
-  __shared__ uint32_t s_own[kKgWin];  // window owners, then the staged keys
-  __shared__ uint32_t s_val[kKgWin];
+  __shared__ uint32_t s_own[WIN];  // window owners, then the staged keys
+  __shared__ uint32_t s_val[WIN];
   __shared__ uint32_t s_whist[NW][NB];
   __shared__ uint32_t s_local[NB], s_scat[NB];
   __shared__ uint32_t s_tmp[NW], s_sc[NW];
@@ -796,18 +812,18 @@ __global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restric
   // (branch-free: positions past the end read the last Gaussian)
   const uint32_t gcount = t < NB ? totals[t] : 0u;
   const uint32_t tprefix = t < NB ? table[(size_t)slice * NB + t] : 0u;
-  uint32_t gi[kKgItems];
-  uint2 rr[kKgItems];
+  uint32_t gi[KI];
+  uint2 rr[KI];
 #pragma unroll
-  for (int j = 0; j < kKgItems; ++j) {
-    const uint32_t pc = min(base + t * kKgItems + j, nvis - 1);
+  for (int j = 0; j < KI; ++j) {
+    const uint32_t pc = min(base + t * KI + j, nvis - 1);
     gi[j] = sorted_idx[pc];
     rr[j] = sorted_rects[pc];
   }
-  uint32_t cnt[kKgItems], off[kKgItems], sum = 0;
+  uint32_t cnt[KI], off[KI], sum = 0;
 #pragma unroll
-  for (int j = 0; j < kKgItems; ++j) {
-    const int li = t * kKgItems + j;
+  for (int j = 0; j < KI; ++j) {
+    const int li = t * KI + j;
     const bool ok = base + li < nvis;
     const uint32_t c = ok ? rect_tiles(rr[j].x, rr[j].y) : 0u;
     s_g[li] = gi[j];
@@ -817,11 +833,11 @@ __global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restric
     sum += c;
   }
   uint32_t btot;
-  uint32_t run = block_excl_scan(sum, s_tmp, &btot);
+  uint32_t run = block_excl_scan<NT>(sum, s_tmp, &btot);
 #pragma unroll
-  for (int j = 0; j < kKgItems; ++j) {
+  for (int j = 0; j < KI; ++j) {
     off[j] = run;
-    s_off[t * kKgItems + j] = run;
+    s_off[t * KI + j] = run;
     run += cnt[j];
   }
   // running write base of digit t: its global start plus its count in the
@@ -829,19 +845,19 @@ __global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restric
   uint32_t gb = 0;
   {
     uint32_t all;
-    const uint32_t gstart = block_excl_scan(gcount, s_sc, &all);
+    const uint32_t gstart = block_excl_scan<NT>(gcount, s_sc, &all);
     if (t < NB) gb = gstart + tprefix;
   }
   const uint64_t lt = lanemask_lt();
-  for (uint32_t w0 = 0; w0 < btot; w0 += kKgWin) {
+  for (uint32_t w0 = 0; w0 < btot; w0 += WIN) {
 #pragma unroll
     for (int k = 0; k < IT; ++k) s_own[t * IT + k] = 0;
-    for (int b = t; b < NW * NB; b += kBlock) (&s_whist[0][0])[b] = 0;
+    for (int b = t; b < NW * NB; b += NT) (&s_whist[0][0])[b] = 0;
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kKgItems; ++j) {
-      if (cnt[j] && off[j] < w0 + kKgWin && off[j] + cnt[j] > w0)
-        s_own[(off[j] > w0 ? off[j] : w0) - w0] = (uint32_t)(t * kKgItems + j) + 1;
+    for (int j = 0; j < KI; ++j) {
+      if (cnt[j] && off[j] < w0 + WIN && off[j] + cnt[j] > w0)
+        s_own[(off[j] > w0 ? off[j] : w0) - w0] = (uint32_t)(t * KI + j) + 1;
     }
     __syncthreads();
     {
@@ -851,7 +867,7 @@ __global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restric
         v[k] = s_own[t * IT + k];
         m = max(m, v[k]);
       }
-      uint32_t carry = block_excl_max(m, s_tmp);
+      uint32_t carry = block_excl_max<NT>(m, s_tmp);
 #pragma unroll
       for (int k = 0; k < IT; ++k) {
         carry = max(carry, v[k]);
@@ -901,7 +917,7 @@ __global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restric
       }
     }
     uint32_t nwin;
-    const uint32_t lstart = block_excl_scan(tot, s_sc, &nwin);
+    const uint32_t lstart = block_excl_scan<NT>(tot, s_sc, &nwin);
     if (t < NB) {
       s_local[t] = lstart;
       s_scat[t] = gb - lstart;
@@ -920,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void k_kg_scatter(const uint32_t* __restric
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-      const uint32_t j = (uint32_t)(i * kBlock + t);
+      const uint32_t j = (uint32_t)(i * NT + t);
       if (j < nwin) {
         const uint32_t k = s_own[j];
         const uint32_t g = s_scat[k & (NB - 1)] + j;
@@ -1364,8 +1380,14 @@ void kg_fused_t(int64_t n, int parts, const uint32_t* sorted_idx, const uint32_t
   hipLaunchKernelGGL((k_col_scan<NB, kKgPart>), dim3(NB / 4), dim3(kBlock), 0, st, table,
                      vis_count, (int64_t)0, totals);
   trace_mark(st, "keygen");
-  hipLaunchKernelGGL(k_kg_scatter<BITS>, dim3(parts), dim3(kBlock), 0, st, sorted_idx, vis_count,
-                     sorted_rects, tiles_x, inst_count, table, totals, tkeys, tvals);
+  if (n <= kKgWideMaxN)
+    hipLaunchKernelGGL((k_kg_scatter<BITS, kKgScatWideThreads, kKgScatWin>), dim3(parts),
+                       dim3(kKgScatWideThreads), 0, st, sorted_idx, vis_count, sorted_rects,
+                       tiles_x, inst_count, table, totals, tkeys, tvals);
+  else
+    hipLaunchKernelGGL((k_kg_scatter<BITS, kKgScatThreads, kKgScatWin>), dim3(parts),
+                       dim3(kKgScatThreads), 0, st, sorted_idx, vis_count, sorted_rects,
+                       tiles_x, inst_count, table, totals, tkeys, tvals);
 }
 }  // namespace
 
