@@ -600,6 +600,7 @@ int32_t sort_impl(int64_t n, const gs_splat* splats, const uint32_t* depth_keys,
   const uint2* rects = reinterpret_cast<const uint2*>(tile_rects);
   gs::RadixArgs<uint32_t> t = d;
   t.init.active = 0;
+  t.min_parts = gs::kTilePassMinParts;
   t.n_grid = capacity;
   t.count = count;
   t.drop_first = 0;

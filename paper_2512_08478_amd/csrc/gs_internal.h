@@ -140,7 +140,13 @@ struct RadixArgs {
   uint32_t* lookback;       // mode 1: two buffers of lb_parts x 256 words
   int lb_parts;
   SortInitK init;           // mode 0: the set-up, done by the first pass's count kernel
+  int min_parts;            // mode 0: partitions each pass aims for (0: the default)
 };
+// The tile passes (after key generation) aim for more partitions than the
+// depth passes: on the 1M frame 8 keys per thread instead of 16 (1,685
+// partitions) made the tile pass 4 us faster, while 4 instead of 8 made
+// the depth passes 5 us slower.
+constexpr int kTilePassMinParts = 1024;
 
 // Launchers (enqueue only; return the first launch error).
 constexpr int kMaxAssets = 64;       // assets per preprocess / backward call

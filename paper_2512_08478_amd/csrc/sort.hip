@@ -1107,9 +1107,10 @@ int stream_grid(int64_t items, int cap = 2048) {
 
 // Keys per thread of a reduce-then-scan pass: enough partitions to give
 // every CU a few workgroups (small passes are latency-bound), else 16.
-inline int rs_items(int64_t n) {
-  if ((n + kBlock * 16 - 1) / (kBlock * 16) >= kRsMinParts) return 16;
-  if ((n + kBlock * 8 - 1) / (kBlock * 8) >= kRsMinParts) return 8;
+inline int rs_items(int64_t n, int min_parts) {
+  const int64_t m = min_parts > 0 ? min_parts : kRsMinParts;
+  if ((n + kBlock * 16 - 1) / (kBlock * 16) >= m) return 16;
+  if ((n + kBlock * 8 - 1) / (kBlock * 8) >= m) return 8;
   return 4;
 }
 
@@ -1156,7 +1157,7 @@ void rs_pass_items(const RadixArgs<KeyT>& a, int p, int shift, const KeyT* ki, c
   const uint32_t* cnt = (!first && a.drop_first) ? a.count_rest : a.count;
   SortInitK init = a.init;
   init.active = first && a.init.active;  // the set-up runs once, with the first pass
-  switch (rs_items(a.n_grid)) {
+  switch (rs_items(a.n_grid, a.min_parts)) {
     case 16: rs_pass<KeyT, BITS, 16>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, init, st); break;
     case 8: rs_pass<KeyT, BITS, 8>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, init, st); break;
     default: rs_pass<KeyT, BITS, 4>(a, shift, cnt, drop, kbase, ki, vi, kd, vd, write_keys, init, st); break;
