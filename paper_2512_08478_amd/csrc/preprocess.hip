@@ -252,7 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(
 // partial counts of workgroup b go to slot v * B.block0[n_assets] + b.
 // cams[v * n_assets + a] places asset a in view v.
 template <int DEG>
-__global__ __launch_bounds__(kBlock) void k_preprocess_views(
+// 4 waves per SIMD (124 VGPRs, no spill once the inputs are not kept live
+// across the views; 194 VGPRs and 2 waves otherwise): 5.7 -> 5.4 ms per
+// batch of 32 views x 4.5 M Gaussians.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_preprocess_views(
     BatchPreK B, int n_views, const float* __restrict__ means,
     const float* __restrict__ log_scales, const float4* __restrict__ quats,
     const float* __restrict__ logits, const float* __restrict__ sh,
@@ -267,8 +270,16 @@ __global__ __launch_bounds__(kBlock) void k_preprocess_views(
   const int v1 = min(n_views, v0 + kViewsPerBlock);
   for (int v = v0; v < v1; ++v) {
     const int64_t vo = (int64_t)v * B.n + o;
-    preprocess_block<DEG>(b - B.block0[a], B.count[a], means + 3 * o, log_scales + 3 * o,
-                          quats + o, logits + o, sh + K3 * o, cams[v * B.n_assets + a], set,
+    // opaque input pointers: each view reads its inputs again (from the
+    // cache) instead of the compiler keeping them, and all that derives
+    // from them, live across the views
+    const float* m = means + 3 * o;
+    const float* ls = log_scales + 3 * o;
+    const float4* qt = quats + o;
+    const float* lg = logits + o;
+    asm volatile("" : "+s"(m), "+s"(ls), "+s"(qt), "+s"(lg));
+    preprocess_block<DEG>(b - B.block0[a], B.count[a], m, ls, qt, lg, sh + K3 * o,
+                          cams[v * B.n_assets + a], set,
                           splats + vo, depth_keys + vo, rects + vo,
                           partial + (size_t)v * B.block0[B.n_assets]);  // slot blockIdx.x
     __syncthreads();  // the next view reuses the LDS of this one
