@@ -108,6 +108,10 @@ gs::SetK make_setk(const gs_camera* c, const gs_settings* s) {
   gs::SetK k;
   k.tile_w = s->tile_w;
   k.tile_h = s->tile_h;
+  k.tile_w_shift = 0;
+  while ((1 << k.tile_w_shift) < s->tile_w) ++k.tile_w_shift;
+  k.tile_h_shift = 0;
+  while ((1 << k.tile_h_shift) < s->tile_h) ++k.tile_h_shift;
   k.tiles_x = tiles_x_of(c, s);
   k.tiles_y = tiles_y_of(c, s);
   k.raster_order = s->raster_order;

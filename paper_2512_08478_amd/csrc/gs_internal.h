@@ -65,6 +65,7 @@ struct ViewK {
 
 struct SetK {
   int tile_w, tile_h, tiles_x, tiles_y;
+  int tile_w_shift, tile_h_shift;  // log2 of the tile shape (every supported one is a power of 2)
   int raster_order;   // 0: spatial runs over the XCDs; 1: heavy tiles first
   float eps2d, tau, log2_tau, amax, t_eps;
   float bg[3];

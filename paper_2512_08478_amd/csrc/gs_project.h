@@ -96,8 +96,11 @@ __device__ __forceinline__ uint32_t footprint(const double* t, float iz, float w
   fx1 = fmin(fx1, (double)(cam.W - 1)); fy1 = fmin(fy1, (double)(cam.H - 1));
   if (!(fx0 <= fx1 && fy0 <= fy1)) return 0;
   const int px0 = (int)fx0, px1 = (int)fx1, py0 = (int)fy0, py1 = (int)fy1;
-  const int tx0 = px0 / set.tile_w, tx1 = px1 / set.tile_w;
-  const int ty0 = py0 / set.tile_h + cam.tile_row, ty1 = py1 / set.tile_h + cam.tile_row;
+  // tile of a pixel: the tile sides are powers of 2 and the pixel bbox is
+  // clamped to the image, so a shift is the division
+  const int tx0 = px0 >> set.tile_w_shift, tx1 = px1 >> set.tile_w_shift;
+  const int ty0 = (py0 >> set.tile_h_shift) + cam.tile_row;
+  const int ty1 = (py1 >> set.tile_h_shift) + cam.tile_row;
   rect_lo = (uint32_t)px0 | ((uint32_t)py0 << 16);
   rect_hi = (uint32_t)px1 | ((uint32_t)py1 << 16);
   trect = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
