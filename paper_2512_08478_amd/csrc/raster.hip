@@ -249,16 +249,24 @@ __device__ __forceinline__ int stage_batch(StageT<DEPTH, BWD>& S, bool valid, co
     if constexpr (DEPTH) S.dep[k] = r.depth;
     // log2(o) - qc' dy^2 and dx - qb dy at the first column, per row
     const float ux = (float)(qx0 - px0) + 0.5f - mx;
-    float2 t[8];
-#pragma unroll
-    for (int rr = 0; rr < 8; ++rr) {
-      const float dy = uy + (float)rr;
-      t[rr] = make_float2(fmaf(-qc_, dy * dy, lo), fmaf(-qb, dy, ux));
-    }
     float4* dst = reinterpret_cast<float4*>(S.rows[k]);
+    if (hy1 - hy0 == 7) {  // the whole quadrant
+      float2 t[8];
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-      dst[rr] = make_float4(t[2 * rr].x, t[2 * rr].y, t[2 * rr + 1].x, t[2 * rr + 1].y);
+      for (int rr = 0; rr < 8; ++rr) {
+        const float dy = uy + (float)rr;
+        t[rr] = make_float2(fmaf(-qc_, dy * dy, lo), fmaf(-qb, dy, ux));
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        dst[rr] = make_float4(t[2 * rr].x, t[2 * rr].y, t[2 * rr + 1].x, t[2 * rr + 1].y);
+    } else {  // a band of 2 or 4 rows starting at an even row: only its rows
+      for (int rr = hy0 - qy0; rr <= hy1 - qy0; rr += 2) {
+        const float dy0 = uy + (float)rr, dy1 = uy + (float)(rr + 1);
+        dst[rr >> 1] = make_float4(fmaf(-qc_, dy0 * dy0, lo), fmaf(-qb, dy0, ux),
+                                   fmaf(-qc_, dy1 * dy1, lo), fmaf(-qb, dy1, ux));
+      }
+    }
   }
   if ((nh & 1) && lane < 8) {  // nh is odd, so slot nh < kBatch is free
     S.rows[nh][lane] = make_float2(-__builtin_inff(), 0.f);
