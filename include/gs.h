@@ -434,6 +434,27 @@ int32_t gs_sort_plan(int64_t n, int64_t capacity, const gs_camera* cam, const gs
                      int64_t* lookback_words);
 
 /*
+ * gs_raster_grid / gs_raster_unit -- host-only view of how the compositing
+ * kernels split a frame into workgroups (no HIP call; for tests and tools;
+ * the same function the kernels run).  gs_raster_grid: the workgroups of
+ * the forward (forward != 0) or backward compositing launch for this
+ * camera and these settings, or -1 for invalid arguments.
+ * gs_raster_unit: the work of workgroup `workgroup` of that launch, written
+ * to unit[3] = (tile, quadrant, band): tile row-major in the grid, quadrant
+ * row-major among the tile's 8x8 pixel quadrants, band the row band of the
+ * quadrant (0 unless raster_order >> 1 splits the forward's quadrants;
+ * band j covers rows j * 8 / 2^s .. of the quadrant).  Returns 1, or 0 for
+ * a padding workgroup that takes nothing (unit untouched).  With
+ * raster_order bit 0 set, tile_order (host, tiles entries) is the
+ * heavy-first order gs_sort wrote after the tile ranges.  Negative status
+ * codes for invalid arguments, a workgroup outside the grid, or a missing
+ * tile_order.
+ */
+int64_t gs_raster_grid(const gs_camera* cam, const gs_settings* set, int32_t forward);
+int32_t gs_raster_unit(const gs_camera* cam, const gs_settings* set, int32_t forward,
+                       const uint32_t* tile_order, int64_t workgroup, int32_t* unit);
+
+/*
  * gs_sort_pairs -- the stable LSD radix sort on its own: sorts n
  * (key u64, value u32) pairs by the low `key_bits` bits of the key
  * (1..64; higher bits must be zero).  keys_in/values_in are not modified;

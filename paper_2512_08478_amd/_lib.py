@@ -34,6 +34,7 @@ EXPORTED = (
     "gs_preprocess_backward_views", "gs_sort_pairs32", "gs_packed_sh_stride", "gs_prepack",
     "gs_preprocess_packed", "gs_rasterize_mesh", "gs_rasterize_backward_2d_mesh", "gs_lbs_deform",
     "gs_preprocess_noalloc", "gs_preprocess_noalloc_max_n", "gs_sort_plan",
+    "gs_raster_grid", "gs_raster_unit",
     "gs_batch_create", "gs_batch_destroy", "gs_batch_pixels", "gs_batch_pixel_offset",
     "gs_batch_capacity", "gs_batch_workspace_size", "gs_batch_plan", "gs_batch_run",
     "gs_batch_capture", "gs_batch_launch", "gs_autotune",
@@ -167,6 +168,10 @@ def load():
                                 P, P, P]
     lib.gs_sort_plan.restype = I32
     lib.gs_sort_plan.argtypes = [I64, I64, CAM, SET, I32, P, P, P]
+    lib.gs_raster_grid.restype = I64
+    lib.gs_raster_grid.argtypes = [CAM, SET, I32]
+    lib.gs_raster_unit.restype = I32
+    lib.gs_raster_unit.argtypes = [CAM, SET, I32, P, I64, P]
     lib.gs_preprocess_noalloc_max_n.restype = I64
     lib.gs_preprocess_noalloc_max_n.argtypes = []
     lib.gs_sort.restype = I32

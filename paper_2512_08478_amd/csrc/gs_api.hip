@@ -537,6 +537,28 @@ int32_t gs_sort_plan(int64_t n, int64_t capacity, const gs_camera* cam, const gs
   return GS_OK;
 }
 
+int64_t gs_raster_grid(const gs_camera* cam, const gs_settings* set, int32_t forward) {
+  if (check_settings(set) || check_camera(cam, set)) return -1;
+  return gs::raster_units_grid(make_setk(cam, set), forward != 0);
+}
+
+int32_t gs_raster_unit(const gs_camera* cam, const gs_settings* set, int32_t forward,
+                       const uint32_t* tile_order, int64_t workgroup, int32_t* unit) {
+  int32_t r;
+  if ((r = check_settings(set)) || (r = check_camera(cam, set))) return r;
+  if (!unit || workgroup < 0) return GS_ERR_INVALID_ARGUMENT;
+  if ((set->raster_order & 1) && !tile_order) return GS_ERR_INVALID_ARGUMENT;
+  const gs::SetK sk = make_setk(cam, set);
+  if (workgroup >= gs::raster_units_grid(sk, forward != 0)) return GS_ERR_INVALID_ARGUMENT;
+  int tile = 0, q = 0, band = 0;
+  if (!gs::raster_unit_host(sk, forward != 0, tile_order, (int)workgroup, &tile, &q, &band))
+    return 0;
+  unit[0] = tile;
+  unit[1] = q;
+  unit[2] = band;
+  return 1;
+}
+
 namespace {
 // gs_sort over a tile grid of tiles_x x tiles_y tiles (one view's, or a
 // batch's stacked grid); arguments already checked.

@@ -227,6 +227,13 @@ hipError_t launch_keygen_fused(int64_t n, int bits, const uint32_t* sorted_idx,
                                uint2* sorted_rects, int tiles_x, const uint32_t* inst_count,
                                uint32_t* table, uint32_t* totals, uint32_t* tkeys,
                                uint32_t* tvals, hipStream_t st);
+// Host mirror of the compositing kernels' work split (the same function
+// the kernels run): their grid, and the (tile, quadrant, band) workgroup b
+// takes (false for a padding workgroup); `order` is the heavy-first tile
+// order when raster_order bit 0 is set.
+int64_t raster_units_grid(const SetK& set, bool forward);
+bool raster_unit_host(const SetK& set, bool forward, const uint32_t* order, int b, int* tile,
+                      int* quadrant, int* band);
 hipError_t launch_tile_ranges(int64_t capacity, const uint32_t* count, const uint32_t* tkeys,
                               uint32_t* ranges, hipStream_t st);
 // ranges[2*tiles .. 3*tiles) = the tiles, longest lists first (class

@@ -60,7 +60,7 @@ __device__ __forceinline__ float hw_exp2(float e) { return __builtin_amdgcn_exp2
 // tiles' quadrants, neighbouring tiles of one tile row) go to the XCDs in
 // turn, so every XCD's L2 sees coherent runs while dense image regions are
 // spread over all eight.  Units past the end return at once.
-__device__ __forceinline__ int xcd_tile(int b, int run) {
+__host__ __device__ __forceinline__ int xcd_tile(int b, int run) {
   const int x = b % kXcds, i = b / kXcds;
   return ((i / run) * kXcds + x) * run + i % run;
 }
@@ -80,19 +80,18 @@ __device__ __forceinline__ int xcd_tile(int b, int run) {
 // reaches.  band is in [0, 2^ls).
 // False for padding workgroups (and for an order entry out of range, which
 // only a caller mixing raster_order values can produce).
-template <int NQ, bool SPLIT>
-__device__ __forceinline__ bool pick_unit(int b, const SetK& set,
-                                          const uint32_t* __restrict__ ranges, int& tile,
-                                          int& q, int& band) {
-  const int tiles = set.tiles_x * set.tiles_y;
-  const int ls = SPLIT ? (set.raster_order >> 1) : 0;  // log2 bands per quadrant
-  const int U = NQ << ls;  // units per tile
+// The same on the host (gs_raster_unit, for tests): nq quadrants per
+// tile, ls = log2 bands per quadrant, `order` the heavy-first tile order.
+__host__ __device__ __forceinline__ bool unit_of(int b, int tiles, int nq, int raster_order,
+                                                 int ls, const uint32_t* order, int& tile,
+                                                 int& q, int& band) {
+  const int U = nq << ls;  // units per tile
   int u;
-  if (set.raster_order & 1) {
+  if (raster_order & 1) {
     const int x = b % kXcds, i = b / kXcds, j = i / U;  // this XCD's j-th tile
     const int rank = ((j / kRunTiles) * kXcds + x) * kRunTiles + j % kRunTiles;
     if (rank >= tiles) return false;
-    tile = (int)ranges[2 * tiles + rank];
+    tile = (int)order[rank];
     u = i % U;
     if (tile >= tiles) return false;
   } else {
@@ -104,6 +103,15 @@ __device__ __forceinline__ bool pick_unit(int b, const SetK& set,
   q = u >> ls;
   band = u & ((1 << ls) - 1);
   return true;
+}
+
+template <int NQ, bool SPLIT>
+__device__ __forceinline__ bool pick_unit(int b, const SetK& set,
+                                          const uint32_t* __restrict__ ranges, int& tile,
+                                          int& q, int& band) {
+  const int tiles = set.tiles_x * set.tiles_y;
+  const int ls = SPLIT ? (set.raster_order >> 1) : 0;  // log2 bands per quadrant
+  return unit_of(b, tiles, NQ, set.raster_order, ls, ranges + 2 * tiles, tile, q, band);
 }
 
 inline int xcd_grid(int units, int run) {
@@ -684,6 +692,18 @@ hipError_t launch_l1_grad(const ViewK* views, int n_views, int max_pixels, const
                      st, views, reinterpret_cast<const float4*>(image), target,
                      reinterpret_cast<float4*>(grad));
   return hipGetLastError();
+}
+
+int64_t raster_units_grid(const SetK& set, bool forward) {
+  return raster_grid(set, set.tile_w, set.tile_h, forward);
+}
+
+bool raster_unit_host(const SetK& set, bool forward, const uint32_t* order, int b, int* tile,
+                      int* quadrant, int* band) {
+  const int tiles = set.tiles_x * set.tiles_y;
+  const int nq = (set.tile_w / 8) * (set.tile_h / 8);
+  const int ls = forward ? (set.raster_order >> 1) : 0;
+  return unit_of(b, tiles, nq, set.raster_order, ls, order, *tile, *quadrant, *band);
 }
 
 bool tile_shape_supported(int tw, int th) {
