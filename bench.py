@@ -171,13 +171,12 @@ def traffic_key(workload, kernel, cfg):
             f"/m{cfg['sort_mode']}/o{cfg['raster_order']}")
 
 
-def measured_traffic(workload, kernel, cfg):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3
-    FETCH_SIZE + WRITE_SIZE passes (copy-calibrated), taken in exactly this
-    launch configuration, or None when there are none or the kernel's
-    sources changed since."""
+def profile_record(name, workload, kernel, cfg):
+    """The record of profiles/<name> for `kernel` in exactly this launch
+    configuration, or None when there is none or the kernel's sources
+    changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         rec = json.load(open(path))[traffic_key(workload, kernel, cfg)]
     except (OSError, KeyError, ValueError):
@@ -188,7 +187,28 @@ def measured_traffic(workload, kernel, cfg):
             h.update(fh.read())
     if h.hexdigest()[:16] != rec["source_sha256_16"]:
         return None
-    return int(rec["bytes_per_launch"])
+    return rec
+
+
+def measured_traffic(workload, kernel, cfg):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE + WRITE_SIZE passes (copy-calibrated), taken in exactly this
+    launch configuration, or None when there are none or the kernel's
+    sources changed since."""
+    rec = profile_record("pmc_traffic.json", workload, kernel, cfg)
+    return None if rec is None else int(rec["bytes_per_launch"])
+
+
+def measured_counters(workload, kernel, cfg):
+    """VALU-busy and issue fractions, resident waves per SIMD and vector
+    instructions per wave of `kernel`, from the committed rocprofv3 SQ
+    counter pass in exactly this launch configuration (same conditions as
+    measured_traffic), or None."""
+    rec = profile_record("pmc_counters.json", workload, kernel, cfg)
+    if rec is None:
+        return None
+    return {k: rec[k] for k in ("valu_busy", "valu_issue", "waves_per_simd", "valu_insts_per_wave")
+            if k in rec}
 
 
 def evaluated_pairs(np, last, T_final, ranges, W, H, tw, th, t_eps):
@@ -504,9 +524,13 @@ def run_view(args, full):
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                     "traffic": None, "algo_bytes_per_launch": int(ab[dom])}
     roofline["ms_per_launch"] = round(kern_avg[dom], 5)
-    roofline["traffic"] = measured_traffic(args.workload, dom, dict(
-        tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=args.sort_mode,
-        raster_order=order))
+    dom_cfg = dict(tile_w=tw, tile_h=th, radix_bits=bits, sort_mode=args.sort_mode,
+                   raster_order=order)
+    roofline["traffic"] = measured_traffic(args.workload, dom, dom_cfg)
+    if roofline["bound"] == "alu":
+        # what the SQ counters say of the same kernel (an ALU fraction on
+        # blended pairs' flops alone understates an issue-bound kernel)
+        roofline["counters"] = measured_counters(args.workload, dom, dom_cfg)
 
     out = {
         "metric": METRIC,

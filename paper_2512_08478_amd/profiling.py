@@ -12,10 +12,13 @@ per-launch HBM bytes that bench.py reports as roofline.traffic):
       by what the same counters read for the M MiB device copy the run
       starts with; the average bytes per launch of the kernels matching
       REGEX go into PATH under KEY, with a hash of their sources.
-  counters DIR [DIR ...] --kernel REGEX [--title T --command C]
+  counters DIR [DIR ...] --kernel REGEX [--key KEY --json PATH --sources f1,...]
+           [--title T --command C]
       the SQ counters of the matching kernels (one or more --pmc passes),
       averaged per dispatch, with VALU-busy % and LDS bank conflicts per
-      LDS instruction.
+      LDS instruction; with --json, the VALU-busy and issue fractions,
+      resident waves and instructions per wave go into PATH under KEY, with
+      a hash of the kernel's sources.
 
 rocprofv3 writes its CSVs under DIR/<host>/<pid>_*.csv (or directly under
 DIR); every `*_kernel_stats.csv`, `*_kernel_trace.csv` and
@@ -210,6 +213,26 @@ def cmd_counters(a):
                          f"{avg['SQ_LDS_BANK_CONFLICT'] / avg['SQ_INSTS_LDS']:.3f}")
         if "SQ_INSTS_VALU" in avg and "SQ_WAVES" in avg and avg["SQ_WAVES"] > 0:
             lines.append(f"  VALU instructions per wave: {avg['SQ_INSTS_VALU'] / avg['SQ_WAVES']:.1f}")
+        if a.json and a.key and "GRBM_GUI_ACTIVE" in avg and avg["GRBM_GUI_ACTIVE"] > 0:
+            cyc = avg["GRBM_GUI_ACTIVE"] / a.xcds
+            rec = {"kernel": name, "dispatches": len(next(iter(cs.values()))),
+                   "sources": a.sources.split(","), "source_sha256_16": source_hash(a.sources.split(","))}
+            if "SQ_ACTIVE_INST_VALU" in avg:
+                rec["valu_busy"] = round(avg["SQ_ACTIVE_INST_VALU"] * 4 / a.simds / cyc, 4)
+            if "SQ_INSTS_VALU" in avg:
+                rec["valu_issue"] = round(avg["SQ_INSTS_VALU"] * 4 / a.simds / cyc, 4)
+            if "SQ_WAVE_CYCLES" in avg:
+                rec["waves_per_simd"] = round(avg["SQ_WAVE_CYCLES"] * 4 / a.simds / cyc, 3)
+            if "SQ_INSTS_VALU" in avg and avg.get("SQ_WAVES", 0) > 0:
+                rec["valu_insts_per_wave"] = round(avg["SQ_INSTS_VALU"] / avg["SQ_WAVES"], 1)
+            try:
+                db = json.load(open(a.json))
+            except (OSError, ValueError):
+                db = {}
+            db[a.key] = rec
+            with open(a.json, "w") as fh:
+                json.dump(db, fh, indent=1, sort_keys=True)
+                fh.write("\n")
     print("\n".join(lines))
 
 
@@ -231,6 +254,9 @@ def main(argv=None):
     c.add_argument("--kernel", required=True)
     c.add_argument("--simds", type=int, default=1024)
     c.add_argument("--xcds", type=int, default=8)
+    c.add_argument("--key")
+    c.add_argument("--json")
+    c.add_argument("--sources", default="raster.hip,gs_device.h,gs_internal.h")
     for p in (s, t, c):
         p.add_argument("--title", default="")
         p.add_argument("--command", default="")
