@@ -713,7 +713,10 @@ int32_t gs_batch_launch(gs_batch* batch, void* stream);
  * Candidates whose workspace exceeds workspace_bytes are skipped.  Syncs
  * the stream once per candidate.  *best, *best_ms and *evaluated
  * (candidates timed; may be NULL) receive the result; GS_ERR_WORKSPACE when
- * no candidate fits.
+ * no candidate fits.  GS_ERR_INVALID_ARGUMENT for reps outside 1..100 or
+ * a space with more than 16 tile shapes, 8 digit widths, 2 sort modes or
+ * 6 compositing orders (or a negative count); listed values that
+ * gs_settings does not support are skipped.
  */
 typedef struct gs_autotune_space {
   int32_t n_tiles;
