@@ -76,7 +76,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", default=None,
                     help="WxH; auto: the autotuner picks tile shape, digit width and "
@@ -224,6 +224,11 @@ def evaluated_pairs(np, last, T_final, ranges, W, H, tw, th, t_eps):
     length = r[2 * tile + 1] - r[2 * tile]
     walk = np.where(T < t_eps, last, length)
     return int(walk.sum())
+
+
+# Frames timed one by one for the warm and cold medians and percentiles
+# (at least this many, whatever --steps is).
+PERCENTILE_FRAMES = 200
 
 
 def frame_percentiles(torch, step, n, flush):
@@ -403,8 +408,8 @@ def run_view(args, full):
     # A read leaves clean lines behind: a written flush buffer would make
     # the frame pay for writing the cache's dirty lines back.
     flush = torch.ones(2**28, dtype=torch.float32, device="cuda")
-    frame_dist = {"warm": frame_percentiles(torch, step, args.steps, None),
-                  "cold": frame_percentiles(torch, step, args.steps, flush)}
+    frame_dist = {"warm": frame_percentiles(torch, step, max(args.steps, PERCENTILE_FRAMES), None),
+                  "cold": frame_percentiles(torch, step, max(args.steps, PERCENTILE_FRAMES), flush)}
 
     # The same frames sized per frame, as for a scene that changes: the
     # instance count and depth key range are read back (one host sync) before
