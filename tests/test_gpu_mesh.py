@@ -92,6 +92,30 @@ def test_mesh_1m_1080p_whole_image(R, orc, shape):
           f"blended pairs {int(nb.sum())}")
 
 
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+def test_mesh_row_bands_bitwise(R, orc, order):
+    """Mesh composition with each 8x8 quadrant taken in row bands: image,
+    T_final, last and blend counts bitwise those of whole quadrants (the
+    mesh depth hides splats per pixel, so a band must read its own rows'
+    depths)."""
+    print_case(f"mesh composition in row bands (raster_order {order}) == whole quadrants")
+    from paper_2512_08478_amd.render import Renderer
+    sc, _ = S.medium_scene(n=200_000)
+    cam = S.orbit_camera(2, 8, 8.0, 1920, 1080)
+    rec = orc.preprocess(sc, cam)
+    mesh = wall(cam, rec.d[rec.visible, orc.D_DEPTH], normal=(0.1, 0.3, 1.0), seed=8)
+    out = []
+    for o in (order & 1, order):
+        Rs = Renderer(dict(tile_w=8, tile_h=8, raster_order=o))
+        fr = Rs.forward(gp(sc), cam, mesh=mesh)
+        nb = torch.zeros((cam.height, cam.width), dtype=torch.int32, device="cuda")
+        Rs.rasterize(fr.splats, fr.values, fr.ranges, cam, n_blend=nb, mesh=fr.mesh)
+        out.append((fr.image, fr.T_final, fr.last, nb))
+    for a, b, name in zip(out[0], out[1], ("image", "T_final", "last", "n_blend")):
+        assert torch.equal(a, b), name
+    assert int(out[0][3].sum()) > 0
+
+
 def test_mesh_backward_vs_oracle(R, orc):
     print_case("mesh composition backward vs autograd oracle")
     from oracle import grad as og
