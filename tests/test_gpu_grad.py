@@ -70,13 +70,21 @@ def test_backward_diff_scene_sampled(R, orc):
         assert e <= 1e-3, (nm, e)
 
 
-def test_backward_dense_upstream(R, orc):
+@pytest.mark.parametrize("shape", [(16, 16, 8, 1), (32, 16, 6, 1), (8, 8, 8, 0)])
+def test_backward_dense_upstream(orc, shape):
     """Every pixel of a 256x256 frame of 50k Gaussians carries an upstream
     gradient (except the few whose decisions are near a threshold, where
     the gradient is not defined): many pixels accumulate into each Gaussian
     through the backward's atomics.  Against the per-tile FP64 autograd
-    oracle (equal to autograd of the whole image)."""
-    print_case("backward 50k 256x256, dense upstream gradient")
+    oracle (equal to autograd of the whole image), with the default launch
+    configuration, the fwd+bwd benchmark's (32x16 tiles, 6-bit digits) and
+    8x8 tiles in spatial order."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_08478_amd.render import Renderer
+    R = Renderer(dict(tile_w=shape[0], tile_h=shape[1], radix_bits=shape[2],
+                      raster_order=shape[3]))
+    print_case(f"backward 50k 256x256, dense upstream gradient, tiles {shape[0]}x{shape[1]}")
     from oracle import grad as og
     sc, cam = S.diff_scene(n=50_000, size=256)
     ref = orc.render_image(orc.preprocess(sc, cam), cam, tiled=True)
